@@ -1,0 +1,310 @@
+"""FP64 CPU oracle for the 1D3V electrostatic PIC-MCC step (ctypes binding).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, ``__graft_entry__.smoke()``
+and the CPU-baseline leg of ``bench.py``.  The GPU library never imports it.
+
+The arithmetic lives in ``pic_oracle.c`` (plain C, FP64, -ffp-contract=off);
+this module only marshals numpy arrays.  Every function there cites the part
+of the paper (arXiv 2404.10270, Sec. 2 phase list and the moveb listing of
+Sec. 6) or the published method it follows.
+
+Parity unpinned (no closed form or published value exists; only the
+invariants listed in the tests constrain them): the warm-plasma Langmuir
+dispersion beyond the cold limit, and the long-time sheath evolution of the
+bounded workloads.  The cross-section values are configuration inputs, not
+physics claims.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import time
+from typing import List, Optional
+
+import numpy as np
+
+import pic_inputs as pin
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "pic_oracle.c")
+LIB = os.path.join(HERE, "libpic_oracle.so")
+
+MAXSP = 4
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (FP64, no contraction of multiply-adds)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fno-fast-math",
+               "-fPIC", "-shared", "-Wall", "-o", tmp, SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class Config(C.Structure):
+    _fields_ = [("nc", C.c_int32), ("bc", C.c_int32), ("nsp", C.c_int32), ("mcc_on", C.c_int32),
+                ("source_on", C.c_int32), ("inst", C.c_int32), ("seed", C.c_uint64),
+                ("dx", C.c_double), ("dt", C.c_double), ("eps0", C.c_double),
+                ("B0", C.c_double), ("theta", C.c_double),
+                ("q", C.c_double * MAXSP), ("m", C.c_double * MAXSP), ("w", C.c_double * MAXSP),
+                ("kind", C.c_int32 * MAXSP),
+                ("v_cap", C.c_double * MAXSP), ("T_src", C.c_double * MAXSP),
+                ("n_n", C.c_double), ("T_n", C.c_double), ("sig_el", C.c_double),
+                ("sig_iz", C.c_double), ("E_iz", C.c_double), ("sig_cx", C.c_double)]
+
+
+class Particles(C.Structure):
+    _fields_ = [("n", C.c_int64), ("cap", C.c_int64),
+                ("x", C.POINTER(C.c_double)), ("vx", C.POINTER(C.c_double)),
+                ("vy", C.POINTER(C.c_double)), ("vz", C.POINTER(C.c_double)),
+                ("id", C.POINTER(C.c_uint64))]
+
+
+class Counters(C.Structure):
+    _fields_ = [("step", C.c_int64), ("next_id", C.c_uint64), ("status", C.c_uint32),
+                ("_pad", C.c_uint32),
+                ("absorbed", (C.c_int64 * 2) * MAXSP),
+                ("absorbed_total", (C.c_int64 * 2) * MAXSP),
+                ("created_total", C.c_int64 * MAXSP),
+                ("n_candidates", C.c_int64), ("n_elastic", C.c_int64), ("n_ionize", C.c_int64),
+                ("n_cx", C.c_int64), ("n_over_cap", C.c_int64), ("n_source", C.c_int64),
+                ("particle_steps", C.c_int64)]
+
+
+class Sim(C.Structure):
+    _fields_ = [("cfg", Config), ("sp", Particles * MAXSP), ("cnt", Counters),
+                ("S", C.POINTER(C.c_uint64) * MAXSP),
+                ("rho", C.POINTER(C.c_double)), ("phi", C.POINTER(C.c_double)),
+                ("E", C.POINTER(C.c_double)),
+                ("acc", C.POINTER(C.c_double) * MAXSP)]
+
+
+class Diag(C.Structure):
+    _fields_ = [("n", C.c_int64 * MAXSP), ("ke", C.c_double * MAXSP),
+                ("mom", (C.c_double * 3) * MAXSP), ("field_energy", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build(force=False)
+        L = C.CDLL(LIB)
+        dp = C.POINTER(C.c_double)
+        up = C.POINTER(C.c_uint64)
+        L.orc_philox4x32_10.argtypes = [C.POINTER(C.c_uint32)] * 3
+        L.orc_deposit_species.argtypes = [C.c_int64, dp, C.c_int32, up]
+        L.orc_deposit_cic64.argtypes = [C.c_int64, dp, C.c_int32, dp]
+        L.orc_thomas.argtypes = [C.c_int64, dp, dp, dp, dp, dp]
+        L.orc_thomas.restype = C.c_int
+        for name in ("orc_deposit", "orc_push", "orc_walls"):
+            getattr(L, name).argtypes = [C.POINTER(Sim)]
+            getattr(L, name).restype = None
+        for name in ("orc_field", "orc_mcc", "orc_source", "orc_step"):
+            getattr(L, name).argtypes = [C.POINTER(Sim)]
+            getattr(L, name).restype = C.c_int
+        L.orc_run.argtypes = [C.POINTER(Sim), C.c_int64]
+        L.orc_run.restype = C.c_int
+        L.orc_diagnostics.argtypes = [C.POINTER(Sim), C.POINTER(Diag)]
+        L.orc_candidate_threshold.argtypes = [C.POINTER(Config), C.c_int]
+        L.orc_candidate_threshold.restype = C.c_uint64
+        for name, T in (("orc_sizeof_sim", Sim), ("orc_sizeof_config", Config),
+                        ("orc_sizeof_counters", Counters), ("orc_sizeof_diag", Diag)):
+            f = getattr(L, name)
+            f.restype = C.c_int
+            if f() != C.sizeof(T):
+                raise RuntimeError(f"oracle struct layout mismatch for {T.__name__}")
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _up(a):
+    return a.ctypes.data_as(C.POINTER(C.c_uint64))
+
+
+# ---------------------------------------------------------------------------
+# small entry points used by the pins
+# ---------------------------------------------------------------------------
+
+def philox4x32_10(ctr, key) -> np.ndarray:
+    c = (C.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    k = (C.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    o = (C.c_uint32 * 4)()
+    lib().orc_philox4x32_10(c, k, o)
+    return np.array(list(o), dtype=np.uint32)
+
+
+def deposit_fixed(x: np.ndarray, nc: int) -> np.ndarray:
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    S = np.zeros(nc + 1, dtype=np.uint64)
+    lib().orc_deposit_species(x.shape[0], _dp(x), nc, _up(S))
+    return S
+
+
+def deposit_cic64(x: np.ndarray, nc: int) -> np.ndarray:
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.zeros(nc + 1, dtype=np.float64)
+    lib().orc_deposit_cic64(x.shape[0], _dp(x), nc, _dp(out))
+    return out
+
+
+def thomas(a, b, c, d) -> np.ndarray:
+    a, b, c, d = (np.ascontiguousarray(v, dtype=np.float64) for v in (a, b, c, d))
+    x = np.zeros_like(d)
+    rc = lib().orc_thomas(d.shape[0], _dp(a), _dp(b), _dp(c), _dp(d), _dp(x))
+    if rc:
+        raise MemoryError("orc_thomas")
+    return x
+
+
+# ---------------------------------------------------------------------------
+# the simulation object
+# ---------------------------------------------------------------------------
+
+def make_config(wl: pin.Workload, inst: int = 0) -> Config:
+    c = Config()
+    c.nc = wl.nc
+    c.bc = wl.bc
+    c.nsp = len(wl.species)
+    c.mcc_on = 1 if wl.mcc is not None else 0
+    c.source_on = 1 if wl.source else 0
+    c.inst = inst
+    c.seed = wl.seed
+    c.dx, c.dt, c.eps0, c.B0, c.theta = wl.dx, wl.dt, wl.eps0, wl.B0, wl.theta
+    for k, s in enumerate(wl.species):
+        c.q[k], c.m[k], c.w[k] = s.q, s.m, s.w
+        c.kind[k] = s.kind
+        c.v_cap[k] = s.v_cap
+        c.T_src[k] = s.T_src
+    if wl.mcc is not None:
+        mc = wl.mcc
+        c.n_n, c.T_n, c.sig_el, c.sig_iz, c.E_iz, c.sig_cx = (mc.n_n, mc.T_n, mc.sig_el,
+                                                               mc.sig_iz, mc.E_iz, mc.sig_cx)
+    return c
+
+
+class OracleSim:
+    """Owns numpy buffers and a ``Sim`` struct pointing into them."""
+
+    def __init__(self, wl: pin.Workload, state: List[pin.SpeciesState],
+                 caps: Optional[List[int]] = None, inst: int = 0):
+        self.wl = wl
+        nsp = len(wl.species)
+        if nsp > MAXSP:
+            raise ValueError("too many species")
+        if caps is None:
+            caps = pin.capacities(wl, state)
+        self.sim = Sim()
+        self.sim.cfg = make_config(wl, inst)
+        self.arrays = []
+        nc = wl.nc
+        self.x, self.vx, self.vy, self.vz, self.id = [], [], [], [], []
+        for k in range(nsp):
+            st = state[k]
+            cap = max(int(caps[k]), st.n, 1)
+            x = np.zeros(cap); vx = np.zeros(cap); vy = np.zeros(cap); vz = np.zeros(cap)
+            ids = np.zeros(cap, dtype=np.uint64)
+            x[:st.n] = st.x; vx[:st.n] = st.vx; vy[:st.n] = st.vy; vz[:st.n] = st.vz
+            ids[:st.n] = st.id
+            P = self.sim.sp[k]
+            P.n, P.cap = st.n, cap
+            P.x, P.vx, P.vy, P.vz, P.id = _dp(x), _dp(vx), _dp(vy), _dp(vz), _up(ids)
+            self.x.append(x); self.vx.append(vx); self.vy.append(vy); self.vz.append(vz)
+            self.id.append(ids)
+        self.S = [np.zeros(nc + 1, dtype=np.uint64) for _ in range(nsp)]
+        self.acc = [np.zeros(nc + 1) for _ in range(nsp)]
+        self.rho = np.zeros(nc + 1)
+        self.phi = np.zeros(nc + 1)
+        self.E = np.zeros(nc + 1)
+        for k in range(nsp):
+            self.sim.S[k] = _up(self.S[k])
+            self.sim.acc[k] = _dp(self.acc[k])
+        self.sim.rho, self.sim.phi, self.sim.E = _dp(self.rho), _dp(self.phi), _dp(self.E)
+        self.sim.cnt.next_id = int(sum(st.n for st in state))
+        self.sim.cnt.step = 0
+
+    # -- phases ------------------------------------------------------------
+    def deposit(self):
+        lib().orc_deposit(C.byref(self.sim))
+
+    def field(self):
+        if lib().orc_field(C.byref(self.sim)):
+            raise MemoryError("orc_field")
+
+    def push(self):
+        lib().orc_push(C.byref(self.sim))
+
+    def walls(self):
+        lib().orc_walls(C.byref(self.sim))
+
+    def mcc(self):
+        if lib().orc_mcc(C.byref(self.sim)):
+            raise RuntimeError("orc_mcc")
+
+    def source(self):
+        if lib().orc_source(C.byref(self.sim)):
+            raise RuntimeError("orc_source")
+
+    def step(self, n: int = 1):
+        if lib().orc_run(C.byref(self.sim), int(n)):
+            raise RuntimeError("orc_run")
+
+    # -- state ---------------------------------------------------------------
+    @property
+    def step_index(self) -> int:
+        return int(self.sim.cnt.step)
+
+    @property
+    def counters(self) -> Counters:
+        return self.sim.cnt
+
+    def n(self, k: int) -> int:
+        return int(self.sim.sp[k].n)
+
+    def state(self, k: int) -> pin.SpeciesState:
+        n = self.n(k)
+        return pin.SpeciesState(x=self.x[k][:n].copy(), vx=self.vx[k][:n].copy(),
+                                vy=self.vy[k][:n].copy(), vz=self.vz[k][:n].copy(),
+                                id=self.id[k][:n].copy())
+
+    def diagnostics(self) -> Diag:
+        d = Diag()
+        lib().orc_diagnostics(C.byref(self.sim), C.byref(d))
+        return d
+
+    def candidate_threshold(self, k: int) -> int:
+        return int(lib().orc_candidate_threshold(C.byref(self.sim.cfg), k))
+
+    def snapshot(self):
+        """Copy of everything that defines the future of the run."""
+        return {"state": [self.state(k) for k in range(len(self.wl.species))],
+                "step": self.step_index, "next_id": int(self.sim.cnt.next_id)}
+
+    @classmethod
+    def from_snapshot(cls, wl, snap, caps=None, inst=0):
+        o = cls(wl, snap["state"], caps=caps, inst=inst)
+        o.sim.cnt.step = snap["step"]
+        o.sim.cnt.next_id = snap["next_id"]
+        return o
+
+
+def time_steps(wl: pin.Workload, state, n_steps: int, caps=None):
+    """Wall-clock the oracle as it stands (single thread) for n_steps.
+
+    Returns (particle_steps, seconds)."""
+    o = OracleSim(wl, state, caps=caps)
+    ps0 = int(o.sim.cnt.particle_steps)
+    t0 = time.perf_counter()
+    o.step(n_steps)
+    dt = time.perf_counter() - t0
+    return int(o.sim.cnt.particle_steps) - ps0, dt

@@ -1,0 +1,680 @@
+/*
+ * pic_oracle.c -- plain, slow, FP64 CPU oracle for one time step of a 1D3V
+ * electrostatic Particle-in-Cell Monte Carlo (PIC-MC) code.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the
+ * benchmark's CPU-baseline leg load this file.  It shares no code with the
+ * GPU library: no header, helper, table or constant generator.
+ *
+ * What it follows (Williams et al., "Accelerating Particle-in-Cell Monte
+ * Carlo Simulations with MPI, OpenMP/OpenACC and Asynchronous Multi-GPU
+ * Programming", arXiv 2404.10270):
+ *   - Sec. 2, the five-phase explicit PIC cycle: charge deposition with
+ *     interpolation functions, (smoother), Poisson solve with a tridiagonal
+ *     matrix and E = -grad(phi), Monte Carlo collisions and plasma-wall
+ *     interaction, and the mover dv/dt = (q/m) E, dx/dt = v;
+ *   - Sec. 6, the moveb listing: linear gather a[j] + x (a[j+1] - a[j]) with
+ *     the in-cell coordinate x, velocity kick, position advance x += nstep*vx;
+ *   - Sec. 2, "natural sorting" (particles grouped by cell): the oracle never
+ *     needs it, every result here is independent of particle order.
+ * Where the paper is silent (magnetised Boris rotation, the null-collision
+ * Monte Carlo, Philox draws keyed by particle id and step, fixed-point
+ * deposition, wall-node closure, the pair source and ids of created
+ * particles) each function states the reading it implements.
+ *
+ * Units: positions in cells, velocities in cells per step; the physical
+ * inputs (SI or plasma units) are converted here, independently of the GPU
+ * library.  Everything is FP64; build with -ffp-contract=off so that no
+ * multiply-add is fused unless fma() is written out.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_MAXSP 4
+#define ORC_FRAC_BITS 32            /* fixed-point fraction bits of the deposit */
+#define ORC_KIND_ELECTRON 0
+#define ORC_KIND_ION 1
+#define ORC_BC_PERIODIC 0
+#define ORC_BC_ABSORB 1
+
+#define ORC_ST_CAPACITY 1u          /* an append did not fit: the particle was dropped */
+#define ORC_ST_CFL 2u               /* |vx| >= 1 cell per step */
+
+typedef struct {
+    int32_t nc, bc, nsp, mcc_on, source_on, inst;
+    uint64_t seed;
+    double dx, dt, eps0, B0, theta;
+    double q[ORC_MAXSP], m[ORC_MAXSP], w[ORC_MAXSP];
+    int32_t kind[ORC_MAXSP];
+    double v_cap[ORC_MAXSP];        /* m/s */
+    double T_src[ORC_MAXSP];        /* J */
+    double n_n, T_n, sig_el, sig_iz, E_iz, sig_cx;
+} orc_config;
+
+typedef struct {
+    int64_t n, cap;
+    double *x, *vx, *vy, *vz;
+    uint64_t *id;
+} orc_particles;
+
+typedef struct {
+    int64_t step;
+    uint64_t next_id;
+    uint32_t status, _pad;
+    int64_t absorbed[ORC_MAXSP][2];        /* this step, [left, right] wall */
+    int64_t absorbed_total[ORC_MAXSP][2];
+    int64_t created_total[ORC_MAXSP];
+    int64_t n_candidates, n_elastic, n_ionize, n_cx, n_over_cap, n_source;  /* totals */
+    int64_t particle_steps;
+} orc_counters;
+
+typedef struct {
+    orc_config cfg;
+    orc_particles sp[ORC_MAXSP];
+    orc_counters cnt;
+    uint64_t *S[ORC_MAXSP];     /* nc+1 fixed-point deposit per species */
+    double *rho, *phi, *E;      /* nc+1 */
+    double *acc[ORC_MAXSP];     /* nc+1, cells / step^2 */
+} orc_sim;
+
+typedef struct {
+    int64_t n[ORC_MAXSP];
+    double ke[ORC_MAXSP];          /* sum 1/2 m w |V|^2  [J / m^2] */
+    double mom[ORC_MAXSP][3];      /* sum m w V          [kg / (m s)] */
+    double field_energy;           /* 1/2 eps0 sum E_j^2 V_j [J / m^2] */
+} orc_diag;
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as   */
+/* easy as 1, 2, 3", SC'11).  Each round multiplies counter words 0 and 2 by */
+/* fixed odd constants, takes the high and low halves of the 64-bit products */
+/* and mixes them with words 1, 3 and the key; the key is bumped by the two  */
+/* Weyl constants between rounds.                                             */
+/* ------------------------------------------------------------------------ */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* uniform on (0,1): (u + 1/2) 2^-32, exact in FP64 */
+static double u01(uint32_t u) { return ((double)u + 0.5) * 0x1p-32; }
+
+static void draw_block(const orc_config *c, uint64_t id, int64_t step, uint32_t block,
+                       uint32_t out[4])
+{
+    uint32_t ctr[4] = {(uint32_t)id, (uint32_t)(id >> 32), (uint32_t)step, block};
+    uint32_t key[2] = {(uint32_t)c->seed, (uint32_t)(c->seed >> 32) ^ (uint32_t)c->inst};
+    orc_philox4x32_10(ctr, key, out);
+}
+
+/* source pair k draws: counter word 1 = 0xFFFFFFFF, which no particle id
+ * (all ids are below 2^63) ever has */
+static void draw_block_source(const orc_config *c, uint64_t k, int64_t step, uint32_t block,
+                              uint32_t out[4])
+{
+    uint32_t ctr[4] = {(uint32_t)k, 0xFFFFFFFFu, (uint32_t)step, block};
+    uint32_t key[2] = {(uint32_t)c->seed, (uint32_t)(c->seed >> 32) ^ (uint32_t)c->inst};
+    orc_philox4x32_10(ctr, key, out);
+}
+
+/* Box-Muller: two uniforms -> two standard normals */
+static void box_muller(uint32_t a, uint32_t b, double *n0, double *n1)
+{
+    double r = sqrt(-2.0 * log(u01(a)));
+    double t = 2.0 * M_PI * u01(b);
+    *n0 = r * cos(t);
+    *n1 = r * sin(t);
+}
+
+/* isotropic unit vector from two uniforms: cos(chi) = 1 - 2 U, phi = 2 pi U' */
+static void iso_dir(uint32_t a, uint32_t b, double d[3])
+{
+    double cc = 1.0 - 2.0 * u01(a);
+    double ss = sqrt(fmax(0.0, 1.0 - cc * cc));
+    double ph = 2.0 * M_PI * u01(b);
+    d[0] = cc;
+    d[1] = ss * cos(ph);
+    d[2] = ss * sin(ph);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Phase 1: charge deposition (Sec. 2, "plasma density calculation").        */
+/* Linear (cloud-in-cell) weights, the same interpolation the moveb gather   */
+/* uses.  Fixed point with F = 32 fraction bits: the right node receives     */
+/* W1 = rint(f 2^32) and the left node 2^32 - W1, so every particle adds     */
+/* exactly 2^32 and the sum is independent of order.                          */
+/* ------------------------------------------------------------------------ */
+void orc_deposit_species(int64_t n, const double *x, int32_t nc, uint64_t *S)
+{
+    memset(S, 0, sizeof(uint64_t) * (size_t)(nc + 1));
+    for (int64_t p = 0; p < n; ++p) {
+        double jd = floor(x[p]);
+        double f = x[p] - jd;
+        int64_t j = (int64_t)jd;
+        uint64_t w1 = (uint64_t)rint(ldexp(f, ORC_FRAC_BITS));
+        S[j] += ((uint64_t)1 << ORC_FRAC_BITS) - w1;
+        S[j + 1] += w1;
+    }
+}
+
+/* the same linear weights in plain FP64 (used to bound the fixed-point error) */
+void orc_deposit_cic64(int64_t n, const double *x, int32_t nc, double *out)
+{
+    memset(out, 0, sizeof(double) * (size_t)(nc + 1));
+    for (int64_t p = 0; p < n; ++p) {
+        double jd = floor(x[p]);
+        double f = x[p] - jd;
+        int64_t j = (int64_t)jd;
+        out[j] += 1.0 - f;
+        out[j + 1] += f;
+    }
+}
+
+void orc_deposit(orc_sim *s)
+{
+    for (int k = 0; k < s->cfg.nsp; ++k)
+        orc_deposit_species(s->sp[k].n, s->sp[k].x, s->cfg.nc, s->S[k]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Phase 3: field solve (Sec. 2).  Textbook Thomas algorithm for            */
+/* a_i x_{i-1} + b_i x_i + c_i x_{i+1} = d_i, i = 0..n-1 (a_0 and c_{n-1}     */
+/* unused).                                                                   */
+/* ------------------------------------------------------------------------ */
+int orc_thomas(int64_t n, const double *a, const double *b, const double *c, const double *d,
+               double *x)
+{
+    if (n <= 0) return 0;
+    double *cp = (double *)malloc(sizeof(double) * (size_t)n);
+    double *dp = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!cp || !dp) { free(cp); free(dp); return -1; }
+    cp[0] = c[0] / b[0];
+    dp[0] = d[0] / b[0];
+    for (int64_t i = 1; i < n; ++i) {
+        double den = b[i] - a[i] * cp[i - 1];
+        cp[i] = c[i] / den;
+        dp[i] = (d[i] - a[i] * dp[i - 1]) / den;
+    }
+    x[n - 1] = dp[n - 1];
+    for (int64_t i = n - 2; i >= 0; --i) x[i] = dp[i] - cp[i] * x[i + 1];
+    free(cp);
+    free(dp);
+    return 0;
+}
+
+/*
+ * rho from the fixed-point deposits, Poisson  phi_{j-1} - 2 phi_j + phi_{j+1}
+ * = -rho_j dx^2 / eps0 by Thomas, E = -grad(phi), and the per-species grid
+ * acceleration acc_s = (q_s/m_s) E dt^2 / dx (cells per step^2).
+ *
+ * Absorbing walls (grounded, phi_0 = phi_nc = 0): the wall nodes own half a
+ * cell (V = dx/2), interior E is the central difference, and the wall E
+ * closes Gauss's law over the half cell: E_0 = -(phi_1 - phi_0)/dx -
+ * rho_0 dx/(2 eps0), E_nc = -(phi_nc - phi_{nc-1})/dx + rho_nc dx/(2 eps0).
+ *
+ * Periodic: node nc is node 0 (its deposit is folded onto node 0), an
+ * immobile uniform background rho_bg = -sum_s q_s w_s N_s / (nc dx) makes
+ * the system neutral, and the gauge phi_0 = 0 leaves the same tridiagonal
+ * system on nodes 1..nc-1.
+ */
+int orc_field(orc_sim *s)
+{
+    const orc_config *c = &s->cfg;
+    const int32_t nc = c->nc;
+    const double dx = c->dx;
+    double *rho = s->rho, *phi = s->phi, *E = s->E;
+    const double two_m32 = 0x1p-32;
+
+    double rho_bg = 0.0;
+    if (c->bc == ORC_BC_PERIODIC) {
+        double qn = 0.0;
+        for (int k = 0; k < c->nsp; ++k) qn += (c->q[k] * c->w[k]) * (double)s->sp[k].n;
+        rho_bg = -qn / ((double)nc * dx);
+    }
+    for (int32_t j = 0; j <= nc; ++j) {
+        double acc = 0.0;
+        for (int k = 0; k < c->nsp; ++k) {
+            uint64_t Sj = s->S[k][j];
+            if (c->bc == ORC_BC_PERIODIC) {
+                if (j == 0) Sj += s->S[k][nc];
+                if (j == nc) Sj = s->S[k][0] + s->S[k][nc];
+            }
+            acc += (c->q[k] * c->w[k]) * ((double)Sj * two_m32);
+        }
+        double V = dx;
+        if (c->bc == ORC_BC_ABSORB && (j == 0 || j == nc)) V = 0.5 * dx;
+        rho[j] = acc / V + rho_bg;
+    }
+
+    /* unknowns phi_1 .. phi_{nc-1} */
+    const int64_t n = nc - 1;
+    const double K = dx * dx / c->eps0;
+    phi[0] = 0.0;
+    phi[nc] = 0.0;
+    if (n > 0) {
+        double *a = (double *)malloc(sizeof(double) * (size_t)n);
+        double *b = (double *)malloc(sizeof(double) * (size_t)n);
+        double *cc = (double *)malloc(sizeof(double) * (size_t)n);
+        double *d = (double *)malloc(sizeof(double) * (size_t)n);
+        if (!a || !b || !cc || !d) { free(a); free(b); free(cc); free(d); return -1; }
+        for (int64_t i = 0; i < n; ++i) {
+            a[i] = 1.0;
+            b[i] = -2.0;
+            cc[i] = 1.0;
+            d[i] = -(rho[i + 1] * K);
+        }
+        int rc = orc_thomas(n, a, b, cc, d, phi + 1);
+        free(a); free(b); free(cc); free(d);
+        if (rc) return rc;
+    }
+
+    for (int32_t j = 1; j < nc; ++j) E[j] = (phi[j - 1] - phi[j + 1]) / (2.0 * dx);
+    if (c->bc == ORC_BC_ABSORB) {
+        E[0] = -(phi[1] - phi[0]) / dx - rho[0] * dx / (2.0 * c->eps0);
+        E[nc] = -(phi[nc] - phi[nc - 1]) / dx + rho[nc] * dx / (2.0 * c->eps0);
+    } else {
+        E[0] = (phi[nc - 1] - phi[1]) / (2.0 * dx);
+        E[nc] = E[0];
+    }
+    for (int k = 0; k < c->nsp; ++k) {
+        const double C = (c->q[k] / c->m[k]) * (c->dt * c->dt / dx);
+        for (int32_t j = 0; j <= nc; ++j) s->acc[k][j] = C * E[j];
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Phase 5: mover (Sec. 2 and the moveb listing of Sec. 6).                   */
+/* Gather a = a[j] + f (a[j+1] - a[j]) with in-cell f (written as one fma),   */
+/* then a Boris step for the magnetised 1D3V case: half electric kick,        */
+/* rotation about B with t = (q/m) B dt/2 and s = 2t/(1+|t|^2), second half   */
+/* kick; then the advance x += vx (nstep = 1).  B = B0 (cos th, sin th, 0),   */
+/* th measured from the wall normal x.                                        */
+/* ------------------------------------------------------------------------ */
+static void species_rotation(const orc_config *c, int k, double t[2], double sv[2])
+{
+    const double tm = (c->q[k] / c->m[k]) * c->B0 * (0.5 * c->dt);
+    t[0] = tm * cos(c->theta);
+    t[1] = tm * sin(c->theta);
+    const double den = 1.0 + (t[0] * t[0] + t[1] * t[1]);
+    sv[0] = 2.0 * t[0] / den;
+    sv[1] = 2.0 * t[1] / den;
+}
+
+void orc_push_species(const orc_config *c, int k, const double *acc, int64_t n, double *x,
+                      double *vx, double *vy, double *vz)
+{
+    double t[2], sv[2];
+    species_rotation(c, k, t, sv);
+    const double tx = t[0], ty = t[1], sx = sv[0], sy = sv[1];
+    for (int64_t p = 0; p < n; ++p) {
+        double jd = floor(x[p]);
+        double f = x[p] - jd;
+        int64_t j = (int64_t)jd;
+        double a = fma(f, acc[j + 1] - acc[j], acc[j]);
+        double h = 0.5 * a;
+        double mx = vx[p] + h, my = vy[p], mz = vz[p];
+        /* v' = v- + v- x t,  t = (tx, ty, 0) */
+        double px = mx - mz * ty;
+        double py = my + mz * tx;
+        double pz = mz + (mx * ty - my * tx);
+        /* v+ = v- + v' x s,  s = (sx, sy, 0) */
+        double qx = mx - pz * sy;
+        double qy = my + pz * sx;
+        double qz = mz + (px * sy - py * sx);
+        vx[p] = qx + h;
+        vy[p] = qy;
+        vz[p] = qz;
+        x[p] = x[p] + vx[p];
+    }
+}
+
+void orc_push(orc_sim *s)
+{
+    for (int k = 0; k < s->cfg.nsp; ++k) {
+        orc_particles *P = &s->sp[k];
+        orc_push_species(&s->cfg, k, s->acc[k], P->n, P->x, P->vx, P->vy, P->vz);
+        for (int64_t p = 0; p < P->n; ++p)
+            if (fabs(P->vx[p]) >= 1.0) s->cnt.status |= ORC_ST_CFL;
+        s->cnt.particle_steps += P->n;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Plasma-wall interaction (Sec. 2, phase 4): grounded absorbing walls at     */
+/* x = 0 and x = nc (a particle at x < 0 or x >= nc is removed and counted    */
+/* per wall), or periodic re-entry with the same velocity (Table 1).          */
+/* ------------------------------------------------------------------------ */
+void orc_walls(orc_sim *s)
+{
+    const orc_config *c = &s->cfg;
+    const double L = (double)c->nc;
+    for (int k = 0; k < c->nsp; ++k) {
+        orc_particles *P = &s->sp[k];
+        s->cnt.absorbed[k][0] = s->cnt.absorbed[k][1] = 0;
+        if (c->bc == ORC_BC_PERIODIC) {
+            for (int64_t p = 0; p < P->n; ++p) {
+                double x = P->x[p];
+                if (x < 0.0) x += L;
+                else if (x >= L) x -= L;
+                if (x >= L) x -= L;
+                P->x[p] = x;
+            }
+            continue;
+        }
+        int64_t keep = 0;
+        for (int64_t p = 0; p < P->n; ++p) {
+            double x = P->x[p];
+            if (x < 0.0) { s->cnt.absorbed[k][0]++; continue; }
+            if (x >= L) { s->cnt.absorbed[k][1]++; continue; }
+            P->x[keep] = x;
+            P->vx[keep] = P->vx[p];
+            P->vy[keep] = P->vy[p];
+            P->vz[keep] = P->vz[p];
+            P->id[keep] = P->id[p];
+            keep++;
+        }
+        P->n = keep;
+        s->cnt.absorbed_total[k][0] += s->cnt.absorbed[k][0];
+        s->cnt.absorbed_total[k][1] += s->cnt.absorbed[k][1];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Collisions (Sec. 2, phase 4: Monte Carlo collisions and ionisation).       */
+/* Null-collision method (Vahedi & Surendra, CPC 87, 1995) against a uniform  */
+/* cold-rate neutral gas of density n_n: per species the collision frequency  */
+/* is bounded by nu_max = n_n sum_k sigma_k v_cap, a particle is a candidate  */
+/* with probability P = 1 - exp(-nu_max dt), tested as u0 < floor(P 2^32),    */
+/* and a candidate undergoes process k iff r = U(u1) nu_max falls below the   */
+/* cumulative n_n sigma |v| (ionisation only above its threshold energy).     */
+/* All rates in cells and steps: nu dt = n_n sigma dx |v_hat|.                */
+/* Draw block b of a particle is Philox(ctr = (id_lo, id_hi, step, b),        */
+/* key = (seed_lo, seed_hi ^ instance)).                                      */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    uint64_t parent;
+    double x;
+    double ve[3], vi[3];
+} orc_iz_event;
+
+static int cmp_event(const void *a, const void *b)
+{
+    uint64_t pa = ((const orc_iz_event *)a)->parent, pb = ((const orc_iz_event *)b)->parent;
+    return (pa > pb) - (pa < pb);
+}
+
+static int append(orc_sim *s, int k, double x, const double v[3], uint64_t id)
+{
+    orc_particles *P = &s->sp[k];
+    if (P->n >= P->cap) { s->cnt.status |= ORC_ST_CAPACITY; return 0; }
+    P->x[P->n] = x;
+    P->vx[P->n] = v[0];
+    P->vy[P->n] = v[1];
+    P->vz[P->n] = v[2];
+    P->id[P->n] = id;
+    P->n++;
+    s->cnt.created_total[k]++;
+    return 1;
+}
+
+/* the electron and ion species of a two-species plasma */
+static int find_kind(const orc_config *c, int kind)
+{
+    for (int k = 0; k < c->nsp; ++k) if (c->kind[k] == kind) return k;
+    return -1;
+}
+
+/* threshold T = floor(P 2^32) of the candidate test, 0 <= T <= 2^32 */
+uint64_t orc_candidate_threshold(const orc_config *c, int k)
+{
+    const double dx = c->dx, dt = c->dt;
+    double sig = 0.0;
+    if (c->kind[k] == ORC_KIND_ELECTRON) sig = c->sig_el + c->sig_iz;
+    else sig = c->sig_cx;
+    double vcap_hat = c->v_cap[k] * (dt / dx);
+    double nu_max = c->n_n * sig * dx * vcap_hat;       /* per step */
+    double P = -expm1(-nu_max);
+    double T = floor(ldexp(P, 32));
+    if (T > 4294967296.0) T = 4294967296.0;
+    return (uint64_t)T;
+}
+
+int orc_mcc(orc_sim *s)
+{
+    const orc_config *c = &s->cfg;
+    if (!c->mcc_on) return 0;
+    const double dx = c->dx, dt = c->dt;
+    const int ke = find_kind(c, ORC_KIND_ELECTRON), ki = find_kind(c, ORC_KIND_ION);
+    if (ke < 0 || ki < 0) return -1;
+    const double M = c->m[ki];                    /* neutral mass = ion mass */
+    const int64_t step = s->cnt.step;
+
+    orc_iz_event *ev = NULL;
+    int64_t n_ev = 0;
+    if (s->sp[ke].n > 0) {
+        ev = (orc_iz_event *)malloc(sizeof(orc_iz_event) * (size_t)s->sp[ke].n);
+        if (!ev) return -1;
+    }
+
+    for (int k = 0; k < c->nsp; ++k) {
+        orc_particles *P = &s->sp[k];
+        const int is_e = (c->kind[k] == ORC_KIND_ELECTRON);
+        const uint64_t T = orc_candidate_threshold(c, k);
+        const double vcap_hat = c->v_cap[k] * (dt / dx);
+        double c0, c1;                      /* cumulative n_n sigma dx */
+        if (is_e) {
+            c0 = c->n_n * c->sig_el * dx;
+            c1 = c->n_n * (c->sig_el + c->sig_iz) * dx;
+        } else {
+            c0 = c->n_n * c->sig_cx * dx;
+            c1 = c0;
+        }
+        const double nu_max = c1 * vcap_hat;
+        const double C0 = c0 * c0, C1 = c1 * c1;
+        const double vcap2 = vcap_hat * vcap_hat;
+        /* ionisation threshold speed^2 in (cells/step)^2: 2 E_iz / m_e (dt/dx)^2 */
+        const double v2_iz = (2.0 * c->E_iz / c->m[k]) * ((dt / dx) * (dt / dx));
+        const double eps_iz = 0.5 * v2_iz;
+        /* neutral thermal speed (cells/step) for Maxwellian products */
+        const double sig_n = sqrt(c->T_n / M) * (dt / dx);
+        const double am = c->m[k] / (c->m[k] + M), bm = M / (c->m[k] + M);
+        for (int64_t p = 0; p < P->n; ++p) {
+            uint32_t u[4];
+            draw_block(c, P->id[p], step, 0, u);
+            if ((uint64_t)u[0] >= T) continue;
+            s->cnt.n_candidates++;
+            const double vx = P->vx[p], vy = P->vy[p], vz = P->vz[p];
+            const double v2 = (vx * vx + vy * vy) + vz * vz;
+            if (v2 > vcap2) s->cnt.n_over_cap++;
+            const double r = u01(u[1]) * nu_max;
+            const double r2 = r * r;
+            if (is_e) {
+                if (r2 < C0 * v2) {
+                    /* elastic, cold neutral target, isotropic in the centre of mass */
+                    double d[3];
+                    iso_dir(u[2], u[3], d);
+                    const double g = sqrt(v2);
+                    P->vx[p] = am * vx + bm * g * d[0];
+                    P->vy[p] = am * vy + bm * g * d[1];
+                    P->vz[p] = am * vz + bm * g * d[2];
+                    s->cnt.n_elastic++;
+                } else if (v2 >= v2_iz && r2 < C1 * v2) {
+                    /* ionisation: the energy above threshold is split U : 1-U
+                     * between the two electrons, both isotropic; the new ion
+                     * takes a neutral's Maxwellian velocity */
+                    uint32_t u1[4], u2[4];
+                    draw_block(c, P->id[p], step, 1, u1);
+                    draw_block(c, P->id[p], step, 2, u2);
+                    const double e_tot = 0.5 * v2 - eps_iz;
+                    const double e1 = u01(u[2]) * e_tot;
+                    const double e2 = e_tot - e1;
+                    const double g1 = sqrt(2.0 * e1), g2 = sqrt(2.0 * e2);
+                    double d1[3], d2[3];
+                    iso_dir(u1[0], u1[1], d1);
+                    iso_dir(u1[2], u1[3], d2);
+                    P->vx[p] = g1 * d1[0];
+                    P->vy[p] = g1 * d1[1];
+                    P->vz[p] = g1 * d1[2];
+                    orc_iz_event *e = &ev[n_ev++];
+                    e->parent = P->id[p];
+                    e->x = P->x[p];
+                    e->ve[0] = g2 * d2[0];
+                    e->ve[1] = g2 * d2[1];
+                    e->ve[2] = g2 * d2[2];
+                    double n0, n1, n2, n3;
+                    box_muller(u2[0], u2[1], &n0, &n1);
+                    box_muller(u2[2], u2[3], &n2, &n3);
+                    const double sig_i = sqrt(c->T_n / c->m[ki]) * (dt / dx);
+                    e->vi[0] = sig_i * n0;
+                    e->vi[1] = sig_i * n1;
+                    e->vi[2] = sig_i * n2;
+                    s->cnt.n_ionize++;
+                }
+            } else {
+                if (r2 < C0 * v2) {
+                    /* charge exchange: the ion takes a neutral's velocity */
+                    uint32_t u1[4];
+                    draw_block(c, P->id[p], step, 1, u1);
+                    double n0, n1, n2, n3;
+                    box_muller(u[2], u[3], &n0, &n1);
+                    box_muller(u1[0], u1[1], &n2, &n3);
+                    P->vx[p] = sig_n * n0;
+                    P->vy[p] = sig_n * n1;
+                    P->vz[p] = sig_n * n2;
+                    s->cnt.n_cx++;
+                }
+            }
+        }
+    }
+
+    /* ids of created particles: events ordered by parent id; event r gives
+     * the electron next_id + 2r and the ion next_id + 2r + 1 */
+    if (n_ev > 1) qsort(ev, (size_t)n_ev, sizeof(orc_iz_event), cmp_event);
+    for (int64_t r = 0; r < n_ev; ++r) {
+        append(s, ke, ev[r].x, ev[r].ve, s->cnt.next_id + 2 * (uint64_t)r);
+        append(s, ki, ev[r].x, ev[r].vi, s->cnt.next_id + 2 * (uint64_t)r + 1);
+    }
+    s->cnt.next_id += 2 * (uint64_t)n_ev;
+    free(ev);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Volumetric pair source: as many electron-ion pairs as ions were absorbed   */
+/* by the walls this step, each pair at one uniform position, velocities      */
+/* Maxwellian at the species' source temperature.  Pair k takes the ids       */
+/* next_id + 2k (electron) and next_id + 2k + 1 (ion).                        */
+/* ------------------------------------------------------------------------ */
+int orc_source(orc_sim *s)
+{
+    const orc_config *c = &s->cfg;
+    if (!c->source_on) return 0;
+    const int ke = find_kind(c, ORC_KIND_ELECTRON), ki = find_kind(c, ORC_KIND_ION);
+    if (ke < 0 || ki < 0) return -1;
+    const int64_t n_pairs = s->cnt.absorbed[ki][0] + s->cnt.absorbed[ki][1];
+    const double dx = c->dx, dt = c->dt;
+    const double se = sqrt(c->T_src[ke] / c->m[ke]) * (dt / dx);
+    const double si = sqrt(c->T_src[ki] / c->m[ki]) * (dt / dx);
+    const int64_t step = s->cnt.step;
+    for (int64_t k = 0; k < n_pairs; ++k) {
+        uint32_t b0[4], b1[4], b2[4];
+        draw_block_source(c, (uint64_t)k, step, 0, b0);
+        draw_block_source(c, (uint64_t)k, step, 1, b1);
+        draw_block_source(c, (uint64_t)k, step, 2, b2);
+        const double x = u01(b0[0]) * (double)c->nc;
+        double e0, e1, e2, e3, i0, i1, i2, i3;
+        box_muller(b0[1], b0[2], &e0, &e1);
+        box_muller(b1[0], b1[1], &e2, &e3);
+        box_muller(b1[2], b1[3], &i0, &i1);
+        box_muller(b2[0], b2[1], &i2, &i3);
+        double ve[3] = {se * e0, se * e1, se * e2};
+        double vi[3] = {si * i0, si * i1, si * i2};
+        append(s, ke, x, ve, s->cnt.next_id + 2 * (uint64_t)k);
+        append(s, ki, x, vi, s->cnt.next_id + 2 * (uint64_t)k + 1);
+    }
+    s->cnt.next_id += 2 * (uint64_t)n_pairs;
+    s->cnt.n_source += n_pairs;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One step: deposit(x^s) -> field -> push -> walls -> collisions -> source.  */
+/* This is a rotation of the paper's cycle (density, smoother, field,         */
+/* collisions/PWI, mover) with the smoother off; the collisions act on        */
+/* v^{s+1/2} at x^{s+1} and use the step index s in their draws.              */
+/* ------------------------------------------------------------------------ */
+int orc_step(orc_sim *s)
+{
+    orc_deposit(s);
+    if (orc_field(s)) return -1;
+    orc_push(s);
+    orc_walls(s);
+    if (orc_mcc(s)) return -1;
+    if (orc_source(s)) return -1;
+    s->cnt.step++;
+    return 0;
+}
+
+int orc_run(orc_sim *s, int64_t n_steps)
+{
+    for (int64_t i = 0; i < n_steps; ++i)
+        if (orc_step(s)) return -1;
+    return 0;
+}
+
+/* Diagnostics: per-species count, kinetic energy and momentum (SI, per unit
+ * area), and the field energy of the last solve. */
+void orc_diagnostics(const orc_sim *s, orc_diag *out)
+{
+    const orc_config *c = &s->cfg;
+    memset(out, 0, sizeof(*out));
+    const double vs = c->dx / c->dt;
+    for (int k = 0; k < c->nsp; ++k) {
+        const orc_particles *P = &s->sp[k];
+        double s2 = 0.0, px = 0.0, py = 0.0, pz = 0.0;
+        for (int64_t p = 0; p < P->n; ++p) {
+            s2 += (P->vx[p] * P->vx[p] + P->vy[p] * P->vy[p]) + P->vz[p] * P->vz[p];
+            px += P->vx[p];
+            py += P->vy[p];
+            pz += P->vz[p];
+        }
+        out->n[k] = P->n;
+        out->ke[k] = 0.5 * c->m[k] * c->w[k] * (vs * vs) * s2;
+        out->mom[k][0] = c->m[k] * c->w[k] * vs * px;
+        out->mom[k][1] = c->m[k] * c->w[k] * vs * py;
+        out->mom[k][2] = c->m[k] * c->w[k] * vs * pz;
+    }
+    double fe = 0.0;
+    const int32_t nc = c->nc;
+    if (c->bc == ORC_BC_PERIODIC) {
+        for (int32_t j = 0; j < nc; ++j) fe += s->E[j] * s->E[j] * c->dx;
+    } else {
+        for (int32_t j = 0; j <= nc; ++j) {
+            double V = (j == 0 || j == nc) ? 0.5 * c->dx : c->dx;
+            fe += s->E[j] * s->E[j] * V;
+        }
+    }
+    out->field_energy = 0.5 * c->eps0 * fe;
+}
+
+int orc_sizeof_sim(void) { return (int)sizeof(orc_sim); }
+int orc_sizeof_config(void) { return (int)sizeof(orc_config); }
+int orc_sizeof_counters(void) { return (int)sizeof(orc_counters); }
+int orc_sizeof_diag(void) { return (int)sizeof(orc_diag); }
