@@ -1,0 +1,258 @@
+/*
+ * pic.h -- C ABI of libpic, the MI355X (gfx950) hot path of a 1D3V
+ * electrostatic Particle-in-Cell Monte Carlo (PIC-MC) time step.
+ *
+ * The operations follow the explicit PIC cycle of Williams et al., arXiv
+ * 2404.10270, Sec. 2 (five phases: plasma density calculation, density
+ * smoother, field solver, collisions and plasma-wall interaction, particle
+ * mover) and the mover statements of its moveb listing (Sec. 6).  The
+ * smoother is not part of this library.
+ *
+ * Units.  Particle positions are in cells (domain [0, nc)), velocities in
+ * cells per step; the configuration carries SI (or plasma-unit) physical
+ * inputs and libpic converts them once in pic_init.
+ *
+ * Ownership.  Every device buffer is allocated by the caller (typically as
+ * PyTorch tensors) with the sizes pic_query_sizes reports, stays owned by the
+ * caller, and must outlive the context.  libpic never allocates or frees
+ * device memory; a context holds host metadata only.
+ *
+ * Streams.  All calls except pic_query_sizes, pic_region, pic_diagnostics,
+ * pic_destroy and pic_strerror enqueue work on the HIP stream given to
+ * pic_init and return without synchronising.  A context is not thread-safe;
+ * use one context per stream.
+ *
+ * Errors.  Host-detectable errors (bad arguments or configuration) return a
+ * negative pic_status before any device work is enqueued.  Conditions found
+ * on the device (capacity overflow, |vx| >= 1 cell/step, non-finite values)
+ * set bits of a device status word, reported by the next pic_diagnostics.
+ * No exception or abort crosses the ABI.
+ */
+#ifndef PIC_H
+#define PIC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PIC_MAX_SPECIES 4
+#define PIC_FRAC_BITS 32          /* fixed-point fraction bits of the deposit */
+
+typedef enum {
+    PIC_OK = 0,
+    PIC_E_ARG = -1,        /* null pointer, bad count, misaligned buffer */
+    PIC_E_CONFIG = -2,     /* invalid physical or numerical configuration */
+    PIC_E_DEVICE = -3,     /* a HIP call failed */
+    PIC_E_CAPACITY = -4,   /* device status: a created/uploaded particle did not fit */
+    PIC_E_CFL = -5,        /* device status: |vx| >= 1 cell per step */
+    PIC_E_NONFINITE = -6,  /* device status: non-finite velocity or field */
+    PIC_E_STATE = -7       /* call out of order (e.g. a phase before pic_init) */
+} pic_status;
+
+/* device status word bits (pic_diag.status) */
+#define PIC_ST_CAPACITY   0x1u
+#define PIC_ST_CFL        0x2u
+#define PIC_ST_NONFINITE  0x4u
+#define PIC_ST_CANDIDATES 0x8u   /* the collision candidate or event list overflowed */
+#define PIC_ST_INTERNAL   0x10u  /* a device-side consistency check failed */
+#define PIC_ST_BAD_INIT   0x20u  /* an uploaded particle was out of range and was dropped */
+
+typedef enum { PIC_BC_PERIODIC = 0, PIC_BC_ABSORB = 1 } pic_bc;
+typedef enum { PIC_KIND_ELECTRON = 0, PIC_KIND_ION = 1 } pic_kind;
+typedef enum {
+    PIC_FP32 = 0,   /* FP32 gather/push, (cell, f32 in-cell offset) positions, fixed-point deposit */
+    PIC_FP64 = 1    /* FP64 gather/push, f64 positions in cells, fixed-point deposit */
+} pic_precision;
+
+typedef struct {
+    double q;           /* charge [C] */
+    double m;           /* mass [kg] */
+    double w;           /* real particles per macro-particle per unit area [m^-2] */
+    int32_t kind;       /* pic_kind: selects the collision processes */
+    int32_t _pad0;
+    int64_t capacity;   /* particle slots reserved for this species */
+    int64_t n_init;     /* particles uploaded into buffer set 0 before pic_init */
+    double v_cap;       /* speed bounding the null-collision frequency [m/s] */
+    double T_src;       /* temperature of source-born particles [J] */
+} pic_species;
+
+typedef struct {
+    int32_t nc;          /* cells; nodes 0..nc */
+    int32_t bc;          /* pic_bc */
+    int32_t nsp;         /* species, 1..PIC_MAX_SPECIES */
+    int32_t precision;   /* pic_precision (must agree across instances) */
+    int32_t mcc_on;      /* null-collision MCC (needs one electron and one ion species) */
+    int32_t source_on;   /* pair source refilling the ions lost to the walls */
+    int32_t _pad0, _pad1;
+    uint64_t seed;       /* key of the Philox draws */
+    double dx, dt, eps0; /* cell size [m], time step [s], permittivity [F/m] */
+    double B0;           /* magnetic field magnitude [T] */
+    double theta;        /* angle of B to the wall normal x, in the x-y plane [rad] */
+    pic_species sp[PIC_MAX_SPECIES];
+    double n_n, T_n;     /* neutral density [m^-3] and temperature [J] */
+    double sig_el, sig_iz, E_iz, sig_cx;  /* cross sections [m^2], threshold [J] */
+    uint64_t next_id;    /* id given to the first created particle */
+    int64_t step0;       /* index of the first step (keys the draws) */
+} pic_config;
+
+typedef struct {
+    int64_t n_slots;     /* particle slots per array of one buffer set */
+    int64_t n_segments;  /* n_inst * nsp */
+    int64_t n_nodes;     /* grid nodes over all instances: sum(nc_i + 1) */
+    uint64_t work_bytes; /* size of the device workspace */
+    int64_t x_elem_bytes;/* 4 (PIC_FP32: float offset) or 8 (PIC_FP64: double position) */
+    int64_t v_elem_bytes;/* 4 or 8 */
+} pic_sizes;
+
+/*
+ * Particle buffers: two sets (b = 0, 1) of structure-of-arrays, each array
+ * n_slots long, 256-byte aligned.  Segment s = inst * nsp + species occupies
+ * slots [seg_base[s], seg_base[s+1]) of every array (seg_base from
+ * pic_query_sizes).  Set 0 holds the initial state: the n_init particles of
+ * a segment are its first n_init slots.  The current set changes when
+ * pic_sort compacts into the other one; pic_diagnostics reports it.
+ *   x   PIC_FP32: float in-cell offset f in [0,1); PIC_FP64: double x in cells
+ *   cell int32 cell index (PIC_FP32 only; NULL for PIC_FP64)
+ *   vx, vy, vz float (PIC_FP32) or double (PIC_FP64), cells per step
+ *   id  uint64 particle id (unique, < 2^63)
+ * An absorbed particle keeps its slot until the next sort, marked by
+ * cell < 0 (PIC_FP32) or x < 0 (PIC_FP64).
+ */
+typedef struct {
+    void *x[2];
+    int32_t *cell[2];
+    void *vx[2], *vy[2], *vz[2];
+    uint64_t *id[2];
+    void *work;          /* device workspace of pic_sizes.work_bytes, 256-byte aligned */
+} pic_buffers;
+
+typedef struct {
+    int64_t step;                 /* index of the next step */
+    uint64_t next_id;
+    uint32_t status;              /* PIC_ST_* bits */
+    int32_t cur_set;              /* buffer set holding the particles */
+    int64_t n_slots_used[PIC_MAX_SPECIES];  /* occupied slots (live + absorbed since last sort) */
+    int64_t n_live[PIC_MAX_SPECIES];
+    double ke[PIC_MAX_SPECIES];             /* sum 1/2 m w |V|^2 [J/m^2] */
+    double mom[PIC_MAX_SPECIES][3];         /* sum m w V [kg/(m s)] */
+    double field_energy;                    /* 1/2 eps0 sum_j E_j^2 V_j [J/m^2] */
+    int64_t absorbed_total[PIC_MAX_SPECIES][2];  /* [left, right] wall */
+    int64_t created_total[PIC_MAX_SPECIES];
+    int64_t n_candidates, n_elastic, n_ionize, n_cx, n_over_cap, n_source;
+    int64_t particle_steps;       /* particles pushed, summed over steps */
+} pic_diag;
+
+/* workspace regions readable by tests and tools (pic_region) */
+typedef enum {
+    PIC_R_DEPOSIT = 0,   /* uint64 [nsp][n_nodes]  fixed-point deposit S (2^32 per particle) */
+    PIC_R_RHO = 1,       /* double [n_nodes]       charge density [C/m^3] */
+    PIC_R_PHI = 2,       /* double [n_nodes]       potential [V] */
+    PIC_R_EFIELD = 3,    /* double [n_nodes]       E_x [V/m] */
+    PIC_R_ACC64 = 4,     /* double [nsp][n_nodes]  (q/m) E dt^2/dx, cells/step^2 */
+    PIC_R_ACC32 = 5,     /* float  [nsp][n_nodes]  the same, rounded to FP32 */
+    PIC_R_CELL_OFFSETS = 6, /* uint32 [nsp][n_nodes] first slot of each cell after the last sort */
+    PIC_R_NODE_BASE = 7  /* int64 [n_inst+1]       first node of each instance */
+} pic_region_id;
+
+typedef struct pic_ctx pic_ctx;
+
+/* init flags */
+#define PIC_INIT_NO_FIELD 0x1u   /* skip the initial deposit + field solve */
+
+/* push flags */
+#define PIC_PUSH_NO_DEPOSIT 0x1u /* do not deposit the new positions */
+
+/*
+ * pic_query_sizes -- host only, pure.  Validates n_inst configurations and
+ * reports the buffer sizes.  seg_base (may be NULL) receives n_inst*nsp+1
+ * slot offsets.  Returns PIC_OK, PIC_E_ARG or PIC_E_CONFIG.
+ */
+int pic_query_sizes(const pic_config *cfgs, int n_inst, pic_sizes *out, int64_t *seg_base);
+
+/*
+ * pic_init -- bind caller-owned buffers, convert the configuration to
+ * cells/steps, write the per-segment tables, and (unless PIC_INIT_NO_FIELD)
+ * deposit the uploaded particles and solve the field so that the first
+ * pic_push sees E at the initial positions.  stream is a hipStream_t (NULL =
+ * the null stream).  Sec. 2: initialisation of grid and particles before the
+ * cycle.  On error *out is NULL.
+ */
+int pic_init(const pic_config *cfgs, int n_inst, const pic_buffers *bufs, void *stream,
+             unsigned flags, pic_ctx **out);
+
+/*
+ * pic_push -- the mover (Sec. 2 phase 5; moveb listing, Sec. 6): linear
+ * gather of the grid acceleration at the in-cell offset, magnetised Boris
+ * velocity update (half kick, rotation about B, half kick), position advance
+ * x += vx, then plasma-wall interaction (absorbing walls, counted per wall,
+ * or periodic re-entry).  Unless PIC_PUSH_NO_DEPOSIT, the new positions are
+ * deposited (phase 1 of the next step) into the fixed-point arrays.  With
+ * MCC on, the particles selected for a collision test this step are listed
+ * for pic_mcc_collide.
+ */
+int pic_push(pic_ctx *ctx, unsigned flags);
+
+/*
+ * pic_deposit -- phase 1 (Sec. 2, plasma density calculation) on its own:
+ * adds every live particle's linear weights (F = 32 fixed point, 2^32 per
+ * particle, order-independent) to PIC_R_DEPOSIT.
+ */
+int pic_deposit(pic_ctx *ctx);
+
+/*
+ * pic_field_solve -- phase 3 (Sec. 2, field solver): rho from the deposit,
+ * the tridiagonal Poisson solve in FP64 (Thomas recurrences), E = -grad(phi)
+ * and the per-species grid acceleration.  Consumes (clears) the deposit.
+ */
+int pic_field_solve(pic_ctx *ctx);
+
+/*
+ * pic_mcc_collide -- phase 4 (Sec. 2, collisions and plasma-wall
+ * interaction): null-collision Monte Carlo for the particles listed by
+ * pic_push (elastic e-n, charge exchange i-n, ionisation with pair creation),
+ * the pair source refilling this step's ion wall loss, ids of the created
+ * particles, and the close of the step (counters, step index).  Must be
+ * called once per step after pic_push, also when MCC and source are off.
+ */
+int pic_mcc_collide(pic_ctx *ctx);
+
+/*
+ * pic_sort -- "natural sorting" (Sec. 2, BIT1 data layout: particles grouped
+ * by cell): counting sort of every segment by cell into the other buffer
+ * set, dropping absorbed particles; writes PIC_R_CELL_OFFSETS.
+ */
+int pic_sort(pic_ctx *ctx);
+
+/*
+ * pic_diagnostics -- per-instance counts, kinetic energy, momentum, field
+ * energy, wall losses, collision counts and the device status word.
+ * Synchronises the stream (the only call that does).  out has n_inst
+ * entries.  Returns PIC_OK, or the negative code of the most severe status
+ * bit that is set (the diagnostics are filled in either way).
+ */
+int pic_diagnostics(pic_ctx *ctx, pic_diag *out, int n_inst);
+
+/*
+ * pic_step -- n_steps whole steps: pic_push, pic_mcc_collide,
+ * pic_field_solve, and pic_sort every sort_every steps (counted from the
+ * step index), enqueued back to back.
+ */
+int pic_step(pic_ctx *ctx, int n_steps, int sort_every);
+
+/* pic_region -- byte offset (into pic_buffers.work) and element count of a
+ * workspace region; host only. */
+int pic_region(const pic_ctx *ctx, int region, uint64_t *byte_offset, int64_t *n_elems);
+
+/* pic_destroy -- free the host context (no device memory is touched). */
+int pic_destroy(pic_ctx *ctx);
+
+/* pic_strerror -- static text for a pic_status code. */
+const char *pic_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PIC_H */

@@ -1,0 +1,571 @@
+// api.cpp -- host side of libpic: validation, buffer sizes, workspace layout,
+// unit conversion into cells and steps, and the per-phase launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "pic.h"
+#include "pic_internal.h"
+
+using namespace picx;
+
+struct pic_ctx {
+    std::vector<pic_config> cfg;
+    int n_inst = 0, nsp = 0, precision = 0;
+    bool mcc_any = false, src_any = false;
+    Layout L{};
+    Dev d{};
+    hipStream_t st = nullptr;
+    int64_t host_steps = 0;   // steps enqueued since init
+    pic_diag *host_diag = nullptr;  // pinned staging for pic_diagnostics
+};
+
+namespace {
+
+constexpr uint64_t kAlign = 256;
+constexpr int kMaxInst = 4096;
+constexpr int64_t kMaxSlots = 0xFFFFFFF0ll;  // slots are addressed with uint32
+
+uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+bool finite_nonneg(double v) { return std::isfinite(v) && v >= 0.0; }
+
+int find_kind(const pic_config &c, int kind)
+{
+    for (int k = 0; k < c.nsp; ++k)
+        if (c.sp[k].kind == kind) return k;
+    return -1;
+}
+
+int validate(const pic_config *cfgs, int n_inst)
+{
+    if (!cfgs || n_inst < 1 || n_inst > kMaxInst) return PIC_E_ARG;
+    const int nsp = cfgs[0].nsp, prec = cfgs[0].precision;
+    if (nsp < 1 || nsp > PIC_MAX_SPECIES) return PIC_E_CONFIG;
+    if (prec != PIC_FP32 && prec != PIC_FP64) return PIC_E_CONFIG;
+    for (int i = 0; i < n_inst; ++i) {
+        const pic_config &c = cfgs[i];
+        if (c.nsp != nsp || c.precision != prec) return PIC_E_CONFIG;
+        if (c.nc < 2 || c.nc > (1 << 26)) return PIC_E_CONFIG;
+        if (c.bc != PIC_BC_PERIODIC && c.bc != PIC_BC_ABSORB) return PIC_E_CONFIG;
+        if (!finite_pos(c.dx) || !finite_pos(c.dt) || !finite_pos(c.eps0)) return PIC_E_CONFIG;
+        if (!finite_nonneg(c.B0) || !std::isfinite(c.theta)) return PIC_E_CONFIG;
+        if (c.next_id >= (1ull << 62) || c.step0 < 0) return PIC_E_CONFIG;
+        for (int k = 0; k < nsp; ++k) {
+            const pic_species &s = c.sp[k];
+            if (!std::isfinite(s.q) || !finite_pos(s.m) || !finite_pos(s.w)) return PIC_E_CONFIG;
+            if (s.kind != PIC_KIND_ELECTRON && s.kind != PIC_KIND_ION) return PIC_E_CONFIG;
+            if (s.capacity < 1 || s.n_init < 0 || s.n_init > s.capacity) return PIC_E_CONFIG;
+            if (s.capacity > kMaxSlots) return PIC_E_CONFIG;
+        }
+        if (c.mcc_on || c.source_on) {
+            if (nsp != 2 || find_kind(c, PIC_KIND_ELECTRON) < 0 || find_kind(c, PIC_KIND_ION) < 0)
+                return PIC_E_CONFIG;
+        }
+        if (c.mcc_on) {
+            if (!finite_nonneg(c.n_n) || !finite_nonneg(c.T_n) || !finite_nonneg(c.sig_el) ||
+                !finite_nonneg(c.sig_iz) || !finite_nonneg(c.E_iz) || !finite_nonneg(c.sig_cx))
+                return PIC_E_CONFIG;
+            for (int k = 0; k < nsp; ++k)
+                if (!finite_pos(c.sp[k].v_cap)) return PIC_E_CONFIG;
+        }
+        if (c.source_on)
+            for (int k = 0; k < nsp; ++k)
+                if (!finite_nonneg(c.sp[k].T_src)) return PIC_E_CONFIG;
+    }
+    return PIC_OK;
+}
+
+// slots of a segment, rounded to a multiple of 64 so that every segment
+// starts on a 256-byte boundary of each array
+int64_t seg_slots(const pic_species &s) { return (int64_t)align_up((uint64_t)s.capacity, 64); }
+
+// candidate-list capacity: mean plus a wide margin of the binomial count
+int64_t cand_capacity(const pic_config *cfgs, int n_inst, const std::vector<double> &P)
+{
+    double tot = 0.0;
+    int q = 0;
+    for (int i = 0; i < n_inst; ++i)
+        for (int k = 0; k < cfgs[i].nsp; ++k, ++q) {
+            const double cap = (double)cfgs[i].sp[k].capacity;
+            const double mu = cap * P[q];
+            tot += std::fmin(cap, mu + 10.0 * std::sqrt(mu + 1.0) + 256.0);
+        }
+    return (int64_t)align_up((uint64_t)tot + 1024, 256);
+}
+
+// Conversion of the configuration into cells and steps (one per segment).
+// The candidate threshold is floor(P 2^32) with P = 1 - exp(-nu_max dt).
+void seg_constants(const pic_config &c, int inst, int k, SegConst &s)
+{
+    const pic_species &sp = c.sp[k];
+    const double dx = c.dx, dt = c.dt;
+    s.inst = inst;
+    s.sp = k;
+    s.kind = sp.kind;
+    s.nc = c.nc;
+    s.bc = c.bc;
+    s.nsp = c.nsp;
+    s.partner = -1;
+    const double tm = (sp.q / sp.m) * c.B0 * (0.5 * dt);
+    s.tx = tm * std::cos(c.theta);
+    s.ty = tm * std::sin(c.theta);
+    const double den = 1.0 + (s.tx * s.tx + s.ty * s.ty);
+    s.sx = 2.0 * s.tx / den;
+    s.sy = 2.0 * s.ty / den;
+    s.txf = (float)s.tx;
+    s.tyf = (float)s.ty;
+    s.sxf = (float)s.sx;
+    s.syf = (float)s.sy;
+    s.qw = sp.q * sp.w;
+    s.accC = (sp.q / sp.m) * (dt * dt / dx);
+    s.mw = sp.m * sp.w;
+    s.vs = dx / dt;
+    s.key0 = (uint32_t)c.seed;
+    s.key1 = (uint32_t)(c.seed >> 32) ^ (uint32_t)inst;
+    s.T = 0;
+    s.nu_max = s.C0 = s.C1 = s.vcap2 = s.v2_iz = s.eps_iz = s.am = s.bm = s.sig_n = 0.0;
+    s.sig_src = 0.0;
+    if (c.source_on) s.sig_src = std::sqrt(sp.T_src / sp.m) * (dt / dx);
+    if (c.mcc_on) {
+        const int ki = find_kind(c, PIC_KIND_ION);
+        const double M = c.sp[ki].m;  // neutral mass = ion mass
+        double sig, c0, c1;
+        if (sp.kind == PIC_KIND_ELECTRON) {
+            sig = c.sig_el + c.sig_iz;
+            c0 = c.n_n * c.sig_el * dx;
+            c1 = c.n_n * (c.sig_el + c.sig_iz) * dx;
+        } else {
+            sig = c.sig_cx;
+            c0 = c.n_n * c.sig_cx * dx;
+            c1 = c0;
+        }
+        const double vcap_hat = sp.v_cap * (dt / dx);
+        const double nu_max_T = c.n_n * sig * dx * vcap_hat;
+        const double P = -std::expm1(-nu_max_T);
+        double T = std::floor(std::ldexp(P, 32));
+        if (T > 4294967296.0) T = 4294967296.0;
+        s.T = (uint64_t)T;
+        s.nu_max = c1 * vcap_hat;
+        s.C0 = c0 * c0;
+        s.C1 = c1 * c1;
+        s.vcap2 = vcap_hat * vcap_hat;
+        s.v2_iz = (2.0 * c.E_iz / sp.m) * ((dt / dx) * (dt / dx));
+        s.eps_iz = 0.5 * s.v2_iz;
+        s.am = sp.m / (sp.m + M);
+        s.bm = M / (sp.m + M);
+        s.sig_n = std::sqrt(c.T_n / sp.m) * (dt / dx);
+    }
+}
+
+double candidate_probability(const pic_config &c, int k)
+{
+    if (!c.mcc_on) return 0.0;
+    SegConst s{};
+    seg_constants(c, 0, k, s);
+    return (double)s.T / 4294967296.0;
+}
+
+struct Plan {
+    int64_t n_slots = 0, n_tiles = 0, G = 0, n_field_tiles = 0, n_sort_tiles = 0;
+    std::vector<int64_t> seg_base, seg_tile0, node_base, inst_ftile0;
+    Layout L{};
+};
+
+int plan(const pic_config *cfgs, int n_inst, Plan &p)
+{
+    const int nsp = cfgs[0].nsp;
+    const int n_seg = n_inst * nsp;
+    p.seg_base.assign(n_seg + 1, 0);
+    p.seg_tile0.assign(n_seg + 1, 0);
+    p.node_base.assign(n_inst + 1, 0);
+    p.inst_ftile0.assign(n_inst + 1, 0);
+    std::vector<double> P(n_seg, 0.0);
+    for (int i = 0; i < n_inst; ++i) {
+        for (int k = 0; k < nsp; ++k) {
+            const int s = i * nsp + k;
+            const int64_t n = seg_slots(cfgs[i].sp[k]);
+            p.seg_base[s + 1] = p.seg_base[s] + n;
+            p.seg_tile0[s + 1] = p.seg_tile0[s] + (n + kTile - 1) / kTile;
+            P[s] = candidate_probability(cfgs[i], k);
+        }
+        const int64_t nodes = (int64_t)cfgs[i].nc + 1;
+        p.node_base[i + 1] = p.node_base[i] + nodes;
+        p.inst_ftile0[i + 1] = p.inst_ftile0[i] + (nodes + kFieldTile - 1) / kFieldTile;
+    }
+    p.n_slots = p.seg_base[n_seg];
+    if (p.n_slots > kMaxSlots) return PIC_E_CONFIG;
+    p.n_tiles = p.seg_tile0[n_seg];
+    p.G = p.node_base[n_inst];
+    p.n_field_tiles = p.inst_ftile0[n_inst];
+    const int64_t nbins = (int64_t)nsp * p.G;
+    p.n_sort_tiles = (nbins + kSortTile - 1) / kSortTile;
+
+    Layout &L = p.L;
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) {
+        const uint64_t o = off;
+        off = align_up(off + (bytes ? bytes : 1), kAlign);
+        return o;
+    };
+    L.segc = take(sizeof(SegConst) * n_seg);
+    L.instc = take(sizeof(InstConst) * n_inst);
+    L.segd = take(sizeof(SegDyn) * n_seg);
+    L.instd = take(sizeof(InstDyn) * n_inst);
+    L.glob = take(sizeof(Globals));
+    L.seg_tile0 = take(sizeof(int64_t) * (n_seg + 1));
+    L.seg_base = take(sizeof(int64_t) * (n_seg + 1));
+    L.inst_ftile0 = take(sizeof(int64_t) * (n_inst + 1));
+    L.node_base = take(sizeof(int64_t) * (n_inst + 1));
+    L.S = take(sizeof(uint64_t) * nbins);
+    L.rho = take(sizeof(double) * p.G);
+    L.phi = take(sizeof(double) * p.G);
+    L.E = take(sizeof(double) * p.G);
+    L.dprime = take(sizeof(double) * p.G);
+    L.acc64 = take(sizeof(double) * nbins);
+    L.acc32 = take(sizeof(float) * nbins);
+    L.hist = take(sizeof(uint32_t) * nbins);
+    L.cursor = take(sizeof(uint32_t) * nbins);
+    L.offsets = take(sizeof(uint32_t) * nbins);
+    L.seg_start = take(sizeof(uint64_t) * n_seg);
+    L.fwd_status = take(sizeof(AffineStatus) * p.n_field_tiles);
+    L.bwd_status = take(sizeof(AffineStatus) * p.n_field_tiles);
+    L.sort_status = take(sizeof(uint64_t) * p.n_sort_tiles);
+    L.fe_part = take(sizeof(double) * p.n_field_tiles);
+    L.cand_cap = cand_capacity(cfgs, n_inst, P);
+    L.ev_cap = L.cand_cap;
+    L.cand = take(sizeof(uint32_t) * L.cand_cap);
+    L.ev = take(sizeof(IzEvent) * L.ev_cap);
+    L.diag_part = take(sizeof(double) * (uint64_t)kDiagBlocks * n_seg * kDiagVals);
+    L.diag_out = take(sizeof(pic_diag) * n_inst);
+    L.total = off;
+    L.n_field_tiles = p.n_field_tiles;
+    L.n_sort_tiles = p.n_sort_tiles;
+    return PIC_OK;
+}
+
+bool aligned(const void *p) { return p && ((uintptr_t)p % kAlign) == 0; }
+
+template <typename T>
+T *at(void *work, uint64_t off)
+{
+    return (T *)((char *)work + off);
+}
+
+int status_code(uint32_t st)
+{
+    if (st & (PIC_ST_NONFINITE)) return PIC_E_NONFINITE;
+    if (st & PIC_ST_CFL) return PIC_E_CFL;
+    if (st & (PIC_ST_CAPACITY | PIC_ST_CANDIDATES | PIC_ST_BAD_INIT)) return PIC_E_CAPACITY;
+    if (st & PIC_ST_INTERNAL) return PIC_E_STATE;
+    return PIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pic_query_sizes(const pic_config *cfgs, int n_inst, pic_sizes *out, int64_t *seg_base)
+{
+    if (!out) return PIC_E_ARG;
+    const int rc = validate(cfgs, n_inst);
+    if (rc) return rc;
+    Plan p;
+    const int rc2 = plan(cfgs, n_inst, p);
+    if (rc2) return rc2;
+    out->n_slots = p.n_slots;
+    out->n_segments = (int64_t)n_inst * cfgs[0].nsp;
+    out->n_nodes = p.G;
+    out->work_bytes = p.L.total;
+    out->x_elem_bytes = cfgs[0].precision == PIC_FP64 ? 8 : 4;
+    out->v_elem_bytes = out->x_elem_bytes;
+    if (seg_base)
+        for (size_t s = 0; s < p.seg_base.size(); ++s) seg_base[s] = p.seg_base[s];
+    return PIC_OK;
+}
+
+int pic_init(const pic_config *cfgs, int n_inst, const pic_buffers *bufs, void *stream,
+             unsigned flags, pic_ctx **out)
+{
+    if (!out) return PIC_E_ARG;
+    *out = nullptr;
+    if (!bufs) return PIC_E_ARG;
+    const int rc = validate(cfgs, n_inst);
+    if (rc) return rc;
+    Plan p;
+    const int rc2 = plan(cfgs, n_inst, p);
+    if (rc2) return rc2;
+    const bool f64 = cfgs[0].precision == PIC_FP64;
+    for (int b = 0; b < 2; ++b) {
+        if (!aligned(bufs->x[b]) || !aligned(bufs->vx[b]) || !aligned(bufs->vy[b]) ||
+            !aligned(bufs->vz[b]) || !aligned(bufs->id[b]))
+            return PIC_E_ARG;
+        if (!f64 && !aligned(bufs->cell[b])) return PIC_E_ARG;
+    }
+    if (!aligned(bufs->work)) return PIC_E_ARG;
+
+    pic_ctx *c = new (std::nothrow) pic_ctx();
+    if (!c) return PIC_E_ARG;
+    c->cfg.assign(cfgs, cfgs + n_inst);
+    c->n_inst = n_inst;
+    c->nsp = cfgs[0].nsp;
+    c->precision = cfgs[0].precision;
+    c->st = (hipStream_t)stream;
+    c->L = p.L;
+    for (int i = 0; i < n_inst; ++i) {
+        c->mcc_any = c->mcc_any || cfgs[i].mcc_on;
+        c->src_any = c->src_any || cfgs[i].source_on;
+    }
+
+    const int nsp = c->nsp, n_seg = n_inst * nsp;
+    std::vector<SegConst> segc(n_seg);
+    std::vector<InstConst> instc(n_inst);
+    std::vector<SegDyn> segd(n_seg);
+    std::vector<InstDyn> instd(n_inst);
+    for (int i = 0; i < n_inst; ++i) {
+        const pic_config &cf = cfgs[i];
+        InstConst &ic = instc[i];
+        std::memset(&ic, 0, sizeof(ic));
+        ic.gnode = p.node_base[i];
+        ic.ftile0 = p.inst_ftile0[i];
+        ic.nc = cf.nc;
+        ic.bc = cf.bc;
+        ic.nsp = nsp;
+        ic.mcc_on = cf.mcc_on;
+        ic.source_on = cf.source_on;
+        ic.seg0 = i * nsp;
+        const int ke = find_kind(cf, PIC_KIND_ELECTRON), ki = find_kind(cf, PIC_KIND_ION);
+        ic.seg_e = (cf.mcc_on || cf.source_on) && ke >= 0 ? i * nsp + ke : -1;
+        ic.seg_i = (cf.mcc_on || cf.source_on) && ki >= 0 ? i * nsp + ki : -1;
+        ic.dx = cf.dx;
+        ic.eps0 = cf.eps0;
+        ic.K = cf.dx * cf.dx / cf.eps0;
+        for (int k = 0; k < nsp; ++k) {
+            const int s = i * nsp + k;
+            SegConst &sc = segc[s];
+            std::memset(&sc, 0, sizeof(sc));
+            seg_constants(cf, i, k, sc);
+            sc.base = p.seg_base[s];
+            sc.tile0 = p.seg_tile0[s];
+            sc.gnode = p.node_base[i];
+            sc.node_stride = p.G;
+            sc.cap = (uint32_t)cf.sp[k].capacity;
+            if (ic.seg_e >= 0 && ic.seg_i >= 0) {
+                if (s == ic.seg_e) sc.partner = ic.seg_i;
+                if (s == ic.seg_i) sc.partner = ic.seg_e;
+            }
+            SegDyn &sd = segd[s];
+            std::memset(&sd, 0, sizeof(sd));
+            sd.count = (uint32_t)cf.sp[k].n_init;
+            sd.live = (uint32_t)cf.sp[k].n_init;
+        }
+        InstDyn &id = instd[i];
+        std::memset(&id, 0, sizeof(id));
+        id.step = cf.step0;
+        id.next_id = cf.next_id;
+    }
+    Globals g;
+    std::memset(&g, 0, sizeof(g));
+    g.cur_set = 0;
+    for (int q = 0; q < 4; ++q) g.scan_gen[q] = 1;
+
+    void *W = bufs->work;
+    Dev &d = c->d;
+    for (int b = 0; b < 2; ++b) {
+        d.x[b] = bufs->x[b];
+        d.cell[b] = bufs->cell[b];
+        d.vx[b] = bufs->vx[b];
+        d.vy[b] = bufs->vy[b];
+        d.vz[b] = bufs->vz[b];
+        d.id[b] = (unsigned long long *)bufs->id[b];
+    }
+    const Layout &L = c->L;
+    d.segc = at<SegConst>(W, L.segc);
+    d.instc = at<InstConst>(W, L.instc);
+    d.segd = at<SegDyn>(W, L.segd);
+    d.instd = at<InstDyn>(W, L.instd);
+    d.glob = at<Globals>(W, L.glob);
+    d.seg_tile0 = at<int64_t>(W, L.seg_tile0);
+    d.seg_base = at<int64_t>(W, L.seg_base);
+    d.inst_ftile0 = at<int64_t>(W, L.inst_ftile0);
+    d.node_base = at<int64_t>(W, L.node_base);
+    d.S = at<unsigned long long>(W, L.S);
+    d.rho = at<double>(W, L.rho);
+    d.phi = at<double>(W, L.phi);
+    d.E = at<double>(W, L.E);
+    d.dprime = at<double>(W, L.dprime);
+    d.acc64 = at<double>(W, L.acc64);
+    d.acc32 = at<float>(W, L.acc32);
+    d.hist = at<uint32_t>(W, L.hist);
+    d.cursor = at<uint32_t>(W, L.cursor);
+    d.offsets = at<uint32_t>(W, L.offsets);
+    d.seg_start = at<unsigned long long>(W, L.seg_start);
+    d.fwd_status = at<AffineStatus>(W, L.fwd_status);
+    d.bwd_status = at<AffineStatus>(W, L.bwd_status);
+    d.sort_status = at<unsigned long long>(W, L.sort_status);
+    d.fe_part = at<double>(W, L.fe_part);
+    d.cand = at<uint32_t>(W, L.cand);
+    d.ev = at<IzEvent>(W, L.ev);
+    d.diag_part = at<double>(W, L.diag_part);
+    d.diag_out = at<pic_diag>(W, L.diag_out);
+    d.n_slots = p.n_slots;
+    d.n_tiles = p.n_tiles;
+    d.G = p.G;
+    d.cand_cap = L.cand_cap;
+    d.ev_cap = L.ev_cap;
+    d.n_field_tiles = p.n_field_tiles;
+    d.n_sort_tiles = p.n_sort_tiles;
+    d.n_seg = n_seg;
+    d.n_inst = n_inst;
+    d.nsp = nsp;
+    d.precision = c->precision;
+
+    hipStream_t st = c->st;
+    bool ok = hipMemsetAsync(W, 0, L.total, st) == hipSuccess;
+    ok = ok && hipMemcpyAsync((void *)d.segc, segc.data(), sizeof(SegConst) * n_seg,
+                              hipMemcpyHostToDevice, st) == hipSuccess;
+    ok = ok && hipMemcpyAsync((void *)d.instc, instc.data(), sizeof(InstConst) * n_inst,
+                              hipMemcpyHostToDevice, st) == hipSuccess;
+    ok = ok && hipMemcpyAsync(d.segd, segd.data(), sizeof(SegDyn) * n_seg, hipMemcpyHostToDevice,
+                              st) == hipSuccess;
+    ok = ok && hipMemcpyAsync(d.instd, instd.data(), sizeof(InstDyn) * n_inst,
+                              hipMemcpyHostToDevice, st) == hipSuccess;
+    ok = ok && hipMemcpyAsync(d.glob, &g, sizeof(Globals), hipMemcpyHostToDevice, st) == hipSuccess;
+    ok = ok && hipMemcpyAsync((void *)d.seg_tile0, p.seg_tile0.data(), sizeof(int64_t) * (n_seg + 1),
+                              hipMemcpyHostToDevice, st) == hipSuccess;
+    ok = ok && hipMemcpyAsync((void *)d.seg_base, p.seg_base.data(), sizeof(int64_t) * (n_seg + 1),
+                              hipMemcpyHostToDevice, st) == hipSuccess;
+    ok = ok && hipMemcpyAsync((void *)d.inst_ftile0, p.inst_ftile0.data(),
+                              sizeof(int64_t) * (n_inst + 1), hipMemcpyHostToDevice, st) == hipSuccess;
+    ok = ok && hipMemcpyAsync((void *)d.node_base, p.node_base.data(), sizeof(int64_t) * (n_inst + 1),
+                              hipMemcpyHostToDevice, st) == hipSuccess;
+    // the host vectors above must stay alive until the copies are done
+    ok = ok && hipStreamSynchronize(st) == hipSuccess;
+    ok = ok && launch_init_state(d, st, nullptr) == hipSuccess;
+    if (ok && !(flags & PIC_INIT_NO_FIELD)) {
+        ok = launch_deposit(d, st) == hipSuccess;
+        ok = ok && launch_field(d, st) == hipSuccess;
+    }
+    ok = ok && hipHostMalloc((void **)&c->host_diag, sizeof(pic_diag) * n_inst,
+                             hipHostMallocDefault) == hipSuccess;
+    if (!ok) {
+        if (c->host_diag) (void)hipHostFree(c->host_diag);
+        delete c;
+        return PIC_E_DEVICE;
+    }
+    *out = c;
+    return PIC_OK;
+}
+
+int pic_push(pic_ctx *c, unsigned flags)
+{
+    if (!c) return PIC_E_STATE;
+    const bool dep = !(flags & PIC_PUSH_NO_DEPOSIT);
+    return launch_push(c->d, c->st, dep, c->mcc_any) == hipSuccess ? PIC_OK : PIC_E_DEVICE;
+}
+
+int pic_deposit(pic_ctx *c)
+{
+    if (!c) return PIC_E_STATE;
+    return launch_deposit(c->d, c->st) == hipSuccess ? PIC_OK : PIC_E_DEVICE;
+}
+
+int pic_field_solve(pic_ctx *c)
+{
+    if (!c) return PIC_E_STATE;
+    return launch_field(c->d, c->st) == hipSuccess ? PIC_OK : PIC_E_DEVICE;
+}
+
+int pic_mcc_collide(pic_ctx *c)
+{
+    if (!c) return PIC_E_STATE;
+    if (c->mcc_any && launch_collide(c->d, c->st) != hipSuccess) return PIC_E_DEVICE;
+    if (launch_emit(c->d, c->st) != hipSuccess) return PIC_E_DEVICE;
+    c->host_steps += 1;
+    return PIC_OK;
+}
+
+int pic_sort(pic_ctx *c)
+{
+    if (!c) return PIC_E_STATE;
+    return launch_sort(c->d, c->st) == hipSuccess ? PIC_OK : PIC_E_DEVICE;
+}
+
+int pic_step(pic_ctx *c, int n_steps, int sort_every)
+{
+    if (!c) return PIC_E_STATE;
+    if (n_steps < 0 || sort_every < 0) return PIC_E_ARG;
+    for (int s = 0; s < n_steps; ++s) {
+        int rc = pic_push(c, 0);
+        if (!rc) rc = pic_mcc_collide(c);
+        if (!rc) rc = pic_field_solve(c);
+        if (!rc && sort_every > 0 && ((c->cfg[0].step0 + c->host_steps) % sort_every) == 0)
+            rc = pic_sort(c);
+        if (rc) return rc;
+    }
+    return PIC_OK;
+}
+
+int pic_diagnostics(pic_ctx *c, pic_diag *out, int n_inst)
+{
+    if (!c) return PIC_E_STATE;
+    if (!out || n_inst != c->n_inst) return PIC_E_ARG;
+    if (launch_diag(c->d, c->st) != hipSuccess) return PIC_E_DEVICE;
+    if (hipMemcpyAsync(c->host_diag, c->d.diag_out, sizeof(pic_diag) * n_inst,
+                       hipMemcpyDeviceToHost, c->st) != hipSuccess)
+        return PIC_E_DEVICE;
+    if (hipStreamSynchronize(c->st) != hipSuccess) return PIC_E_DEVICE;
+    std::memcpy(out, c->host_diag, sizeof(pic_diag) * n_inst);
+    uint32_t st = 0;
+    for (int i = 0; i < n_inst; ++i) st |= out[i].status;
+    return status_code(st);
+}
+
+int pic_region(const pic_ctx *c, int region, uint64_t *byte_offset, int64_t *n_elems)
+{
+    if (!c || !byte_offset || !n_elems) return PIC_E_ARG;
+    const Layout &L = c->L;
+    const int64_t G = c->d.G, nb = (int64_t)c->nsp * G;
+    switch (region) {
+    case PIC_R_DEPOSIT: *byte_offset = L.S; *n_elems = nb; break;
+    case PIC_R_RHO: *byte_offset = L.rho; *n_elems = G; break;
+    case PIC_R_PHI: *byte_offset = L.phi; *n_elems = G; break;
+    case PIC_R_EFIELD: *byte_offset = L.E; *n_elems = G; break;
+    case PIC_R_ACC64: *byte_offset = L.acc64; *n_elems = nb; break;
+    case PIC_R_ACC32: *byte_offset = L.acc32; *n_elems = nb; break;
+    case PIC_R_CELL_OFFSETS: *byte_offset = L.offsets; *n_elems = nb; break;
+    case PIC_R_NODE_BASE: *byte_offset = L.node_base; *n_elems = c->n_inst + 1; break;
+    default: return PIC_E_ARG;
+    }
+    return PIC_OK;
+}
+
+int pic_destroy(pic_ctx *c)
+{
+    if (!c) return PIC_E_ARG;
+    if (c->host_diag) (void)hipHostFree(c->host_diag);
+    delete c;
+    return PIC_OK;
+}
+
+const char *pic_strerror(int code)
+{
+    switch (code) {
+    case PIC_OK: return "ok";
+    case PIC_E_ARG: return "invalid argument";
+    case PIC_E_CONFIG: return "invalid configuration";
+    case PIC_E_DEVICE: return "HIP runtime error";
+    case PIC_E_CAPACITY: return "particle capacity exceeded";
+    case PIC_E_CFL: return "|vx| reached one cell per step";
+    case PIC_E_NONFINITE: return "non-finite particle velocity";
+    case PIC_E_STATE: return "call out of order or inconsistent device state";
+    default: return "unknown error";
+    }
+}
+
+}  // extern "C"

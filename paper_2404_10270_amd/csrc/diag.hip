@@ -1,0 +1,178 @@
+// diag.hip -- diagnostics (FP64 moments per species and instance) and the
+// validation of an uploaded initial state (gfx950).
+#include "device_common.h"
+
+namespace picx {
+
+// per-block partial sums: [block][segment][kDiagVals]; the block processes a
+// fixed set of tiles, so the partials depend only on the particle order
+__global__ __launch_bounds__(kBlock) void diag_partial_kernel(Dev d)
+{
+    extern __shared__ double s_acc[];  // [n_seg][kDiagVals]
+    __shared__ double s_red[kDiagVals][kBlock];
+    const int cur = d.glob->cur_set;
+    const bool f64 = (d.precision == PIC_FP64);
+    for (int q = threadIdx.x; q < d.n_seg * kDiagVals; q += kBlock) s_acc[q] = 0.0;
+    __syncthreads();
+    const int lane = lane_id();
+    const int wave = threadIdx.x >> 6;
+    for (int64_t t = blockIdx.x; t < d.n_tiles; t += gridDim.x) {
+        const int seg = seg_of_tile(d.seg_tile0, d.n_seg, t);
+        const SegConst &sc = d.segc[seg];
+        const int64_t count = d.segd[seg].count;
+        const int64_t t0 = (t - sc.tile0) * (int64_t)kTile;
+        if (t0 >= count) continue;
+        double a[kDiagVals] = {0, 0, 0, 0, 0, 0};
+        for (int k = 0; k < kPer; ++k) {
+            const int64_t i = t0 + (int64_t)(wave * kPer + k) * 64 + lane;
+            if (i >= count) continue;
+            const int64_t g = sc.base + i;
+            bool live;
+            double vx, vy, vz;
+            if (f64) {
+                live = ((const double *)d.x[cur])[g] >= 0.0;
+                vx = ((const double *)d.vx[cur])[g];
+                vy = ((const double *)d.vy[cur])[g];
+                vz = ((const double *)d.vz[cur])[g];
+            } else {
+                live = d.cell[cur][g] >= 0;
+                vx = ((const float *)d.vx[cur])[g];
+                vy = ((const float *)d.vy[cur])[g];
+                vz = ((const float *)d.vz[cur])[g];
+            }
+            if (!live) continue;
+            a[0] += 1.0;
+            a[1] += (vx * vx + vy * vy) + vz * vz;
+            a[2] += vx;
+            a[3] += vy;
+            a[4] += vz;
+        }
+        for (int v = 0; v < kDiagVals; ++v) s_red[v][threadIdx.x] = a[v];
+        __syncthreads();
+        for (int s = kBlock / 2; s > 0; s >>= 1) {
+            if (threadIdx.x < s)
+                for (int v = 0; v < kDiagVals; ++v) s_red[v][threadIdx.x] += s_red[v][threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x < kDiagVals) s_acc[seg * kDiagVals + threadIdx.x] += s_red[threadIdx.x][0];
+        __syncthreads();
+    }
+    double *out = d.diag_part + (int64_t)blockIdx.x * d.n_seg * kDiagVals;
+    for (int q = threadIdx.x; q < d.n_seg * kDiagVals; q += kBlock) out[q] = s_acc[q];
+}
+
+__global__ __launch_bounds__(kBlock) void diag_final_kernel(Dev d, int n_blocks)
+{
+    for (int i = threadIdx.x; i < d.n_inst; i += kBlock) {
+        const InstConst &ic = d.instc[i];
+        const InstDyn &idn = d.instd[i];
+        pic_diag o;
+        memset(&o, 0, sizeof(o));
+        o.step = idn.step;
+        o.next_id = idn.next_id;
+        o.status = idn.status;
+        o.cur_set = d.glob->cur_set;
+        for (int k = 0; k < ic.nsp; ++k) {
+            const int s = ic.seg0 + k;
+            const SegConst &sc = d.segc[s];
+            const SegDyn &sd = d.segd[s];
+            double a[kDiagVals] = {0, 0, 0, 0, 0, 0};
+            for (int b = 0; b < n_blocks; ++b)
+                for (int v = 0; v < kDiagVals; ++v)
+                    a[v] += d.diag_part[((int64_t)b * d.n_seg + s) * kDiagVals + v];
+            o.n_slots_used[k] = sd.count;
+            o.n_live[k] = (int64_t)a[0];
+            o.ke[k] = 0.5 * sc.mw * (sc.vs * sc.vs) * a[1];
+            o.mom[k][0] = sc.mw * sc.vs * a[2];
+            o.mom[k][1] = sc.mw * sc.vs * a[3];
+            o.mom[k][2] = sc.mw * sc.vs * a[4];
+            o.absorbed_total[k][0] = (int64_t)sd.absorbed_total[0];
+            o.absorbed_total[k][1] = (int64_t)sd.absorbed_total[1];
+            o.created_total[k] = (int64_t)sd.created_total;
+        }
+        double fe = 0.0;
+        for (int64_t t = ic.ftile0; t < d.inst_ftile0[i + 1]; ++t) fe += d.fe_part[t];
+        o.field_energy = 0.5 * ic.eps0 * fe;
+        o.n_candidates = (int64_t)idn.n_candidates;
+        o.n_elastic = (int64_t)idn.n_elastic;
+        o.n_ionize = (int64_t)idn.n_ionize;
+        o.n_cx = (int64_t)idn.n_cx;
+        o.n_over_cap = (int64_t)idn.n_over_cap;
+        o.n_source = (int64_t)idn.n_source;
+        o.particle_steps = (int64_t)idn.particle_steps;
+        d.diag_out[i] = o;
+    }
+}
+
+int diag_blocks(const Dev &d)
+{
+    int64_t g = d.n_tiles;
+    if (g > kDiagBlocks) g = kDiagBlocks;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+hipError_t launch_diag(const Dev &d, hipStream_t st)
+{
+    const int nb = diag_blocks(d);
+    const size_t lds = (size_t)d.n_seg * kDiagVals * sizeof(double);
+    hipLaunchKernelGGL(diag_partial_kernel, dim3(nb), dim3(kBlock), lds, st, d);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(kBlock), 0, st, d, nb);
+    return hipGetLastError();
+}
+
+// uploaded state: a particle outside [0, nc), with a position offset outside
+// [0, 1) or a non-finite velocity is dropped (marked absorbed) and flagged
+__global__ __launch_bounds__(kBlock) void init_check_kernel(Dev d)
+{
+    const bool f64 = (d.precision == PIC_FP64);
+    const int lane = lane_id();
+    const int wave = threadIdx.x >> 6;
+    for (int64_t t = blockIdx.x; t < d.n_tiles; t += gridDim.x) {
+        const int seg = seg_of_tile(d.seg_tile0, d.n_seg, t);
+        const SegConst &sc = d.segc[seg];
+        const int64_t count = d.segd[seg].count;
+        const int64_t t0 = (t - sc.tile0) * (int64_t)kTile;
+        if (t0 >= count) continue;
+        for (int k = 0; k < kPer; ++k) {
+            const int64_t i = t0 + (int64_t)(wave * kPer + k) * 64 + lane;
+            bool drop = false;
+            if (i < count) {
+                const int64_t g = sc.base + i;
+                if (f64) {
+                    const double x = ((const double *)d.x[0])[g];
+                    const double vx = ((const double *)d.vx[0])[g];
+                    const double vy = ((const double *)d.vy[0])[g];
+                    const double vz = ((const double *)d.vz[0])[g];
+                    drop = !(x >= 0.0 && x < (double)sc.nc) || !isfinite(vx) || !isfinite(vy) ||
+                           !isfinite(vz);
+                    if (drop) ((double *)d.x[0])[g] = kDeadX;
+                } else {
+                    const int32_t c = d.cell[0][g];
+                    const float f = ((const float *)d.x[0])[g];
+                    const float vx = ((const float *)d.vx[0])[g];
+                    const float vy = ((const float *)d.vy[0])[g];
+                    const float vz = ((const float *)d.vz[0])[g];
+                    drop = !(c >= 0 && c < sc.nc) || !(f >= 0.0f && f < 1.0f) || !isfinite(vx) ||
+                           !isfinite(vy) || !isfinite(vz);
+                    if (drop) d.cell[0][g] = kDeadCell;
+                }
+            }
+            const unsigned long long m = ballot(drop);
+            if (m && lane == (__ffsll((long long)m) - 1)) {
+                atomicSub(&d.segd[seg].live, (uint32_t)__popcll(m));
+                atomicOr(&d.instd[sc.inst].status, PIC_ST_BAD_INIT);
+            }
+        }
+    }
+}
+
+hipError_t launch_init_state(const Dev &d, hipStream_t st, const uint32_t *)
+{
+    hipLaunchKernelGGL(init_check_kernel, dim3(push_grid(d)), dim3(kBlock), 0, st, d);
+    return hipGetLastError();
+}
+
+}  // namespace picx

@@ -1,0 +1,185 @@
+// pic_internal.h -- device-side tables, workspace layout and launcher
+// declarations of libpic.  Internal to the library (host code and kernels).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pic.h"
+
+namespace picx {
+
+// ---------------------------------------------------------------------------
+// launch geometry
+// ---------------------------------------------------------------------------
+constexpr int kBlock = 256;                 // threads per block of the particle kernels
+constexpr int kWaves = kBlock / 64;         // wave64 per block
+constexpr int kPer = 4;                     // 64-particle chunks per wave per tile
+constexpr int kTile = kBlock * kPer;        // particles per tile (contiguous)
+constexpr int kFieldR = 8;                  // nodes per thread in the field scans
+constexpr int kFieldTile = kBlock * kFieldR;
+constexpr int kSortR = 8;                   // bins per thread in the sort scan
+constexpr int kSortTile = kBlock * kSortR;
+constexpr int kDiagBlocks = 1024;           // blocks of the diagnostics reduction
+constexpr int kEmitBlocks = 64;             // blocks of the emit/close-of-step kernel
+constexpr int kCollideBlocks = 1024;        // grid of the collide kernel (grid-stride)
+constexpr int kDiagVals = 6;                // live, sum v2, sum vx, vy, vz, (pad)
+
+constexpr int32_t kDeadCell = -1;           // FP32 form: cell of an absorbed particle
+constexpr double kDeadX = -1.0;             // FP64 form: position of an absorbed particle
+
+// ---------------------------------------------------------------------------
+// static per-segment constants (segment = instance x species)
+// ---------------------------------------------------------------------------
+struct SegConst {
+    int64_t base;       // first slot
+    int64_t tile0;      // first virtual particle tile of the segment
+    int64_t gnode;      // first grid node of the instance
+    int64_t node_stride;// G: distance between species rows of the [nsp][G] grid arrays
+    uint32_t cap;       // slots
+    int32_t inst, sp, kind;
+    int32_t nc, bc, nsp, partner;   // partner: the other species' segment (MCC / source)
+    // Boris rotation t = (q/m) B dt/2 (cos th, sin th, 0), s = 2t/(1+|t|^2)
+    double tx, ty, sx, sy;
+    float txf, tyf, sxf, syf;
+    // null-collision MCC (rates per step, speeds in cells/step)
+    uint64_t T;         // candidate threshold floor(P 2^32), 0..2^32
+    double nu_max, C0, C1;          // nu_max = c1 vcap; C0 = c0^2, C1 = c1^2
+    double vcap2, v2_iz, eps_iz;
+    double am, bm;      // m/(m+M), M/(m+M) (elastic, cold neutral of mass M)
+    double sig_n;       // neutral Maxwellian sqrt(T_n/m_s) in cells/step (CX, new ions)
+    double sig_src;     // source Maxwellian sqrt(T_src/m_s) in cells/step
+    uint32_t key0, key1;
+    // field / diagnostics
+    double qw;          // q w
+    double accC;        // (q/m) dt^2 / dx
+    double mw, vs;      // m w, dx/dt
+};
+
+struct InstConst {
+    int64_t gnode;      // first node
+    int64_t ftile0;     // first field tile
+    int32_t nc, bc, nsp, mcc_on, source_on, seg0, seg_e, seg_i;
+    double dx, eps0, K; // K = dx^2 / eps0
+};
+
+// dynamic per-segment counters
+struct SegDyn {
+    uint32_t count;          // occupied slots (live + absorbed since the last sort)
+    uint32_t live;
+    uint32_t absorbed_step[2];
+    uint32_t created_step;   // particles placed this step
+    uint32_t _pad;
+    unsigned long long absorbed_total[2];
+    unsigned long long created_total;
+};
+
+// dynamic per-instance counters
+struct InstDyn {
+    long long step;
+    unsigned long long next_id;
+    uint32_t status;
+    uint32_t n_iz_step;      // ionisation events this step
+    unsigned long long n_candidates, n_elastic, n_ionize, n_cx, n_over_cap, n_source;
+    unsigned long long particle_steps;
+};
+
+struct Globals {
+    int32_t cur_set;
+    uint32_t cand_count;
+    uint32_t ev_count;
+    uint32_t emit_done;
+    uint32_t scatter_done;
+    uint32_t pad[3];
+    // self-resetting single-pass scans: ticket counter, finish counter, generation
+    uint32_t scan_ticket[4];
+    uint32_t scan_finish[4];
+    unsigned long long scan_gen[4];
+};
+
+enum ScanId { kScanFwd = 0, kScanBwd = 1, kScanSort = 2 };
+
+// ionisation event recorded by the collide kernel for the emit kernel
+struct IzEvent {
+    unsigned long long parent_id;
+    uint32_t slot;          // parent slot (global)
+    int32_t seg;            // parent segment
+    double g2;              // speed of the secondary electron, cells/step
+};
+
+// look-back status of one tile of an affine (Thomas) scan
+struct AffineStatus {
+    unsigned long long flag;   // gen * 4 + {0: none, 1: aggregate, 2: inclusive}
+    double A, B;               // aggregate map y -> A y + B (never overwritten in a launch)
+    double V;                  // inclusive value, valid once the flag says inclusive
+};
+
+// ---------------------------------------------------------------------------
+// workspace layout (byte offsets into pic_buffers.work)
+// ---------------------------------------------------------------------------
+struct Layout {
+    uint64_t segc, instc, segd, instd, glob;
+    uint64_t seg_tile0, seg_base, inst_ftile0, node_base;
+    uint64_t S, rho, phi, E, dprime, acc64, acc32;
+    uint64_t hist, cursor, offsets, seg_start;
+    uint64_t fwd_status, bwd_status, sort_status;
+    uint64_t fe_part;
+    uint64_t cand, ev;
+    uint64_t diag_part, diag_out;
+    uint64_t total;
+    int64_t cand_cap, ev_cap;
+    int64_t n_field_tiles, n_sort_tiles;
+};
+
+// every device pointer a kernel may need, passed by value
+struct Dev {
+    // particle sets
+    void *x[2];
+    int32_t *cell[2];
+    void *vx[2], *vy[2], *vz[2];
+    unsigned long long *id[2];
+    // tables
+    const SegConst *segc;
+    const InstConst *instc;
+    SegDyn *segd;
+    InstDyn *instd;
+    Globals *glob;
+    const int64_t *seg_tile0;   // [n_seg+1]
+    const int64_t *seg_base;    // [n_seg+1]
+    const int64_t *inst_ftile0; // [n_inst+1]
+    const int64_t *node_base;   // [n_inst+1]
+    // grid
+    unsigned long long *S;      // [nsp][G]
+    double *rho, *phi, *E, *dprime;  // [G]
+    double *acc64;              // [nsp][G]
+    float *acc32;               // [nsp][G]
+    uint32_t *hist, *cursor, *offsets;  // [nsp][G]
+    unsigned long long *seg_start;      // [n_seg] first raw sort position of each segment
+    AffineStatus *fwd_status, *bwd_status;
+    unsigned long long *sort_status;
+    double *fe_part;
+    uint32_t *cand;
+    IzEvent *ev;
+    double *diag_part;
+    pic_diag *diag_out;
+    // sizes
+    int64_t n_slots, n_tiles, G, cand_cap, ev_cap;
+    int64_t n_field_tiles, n_sort_tiles;
+    int32_t n_seg, n_inst, nsp, precision;
+};
+
+// ---------------------------------------------------------------------------
+// launchers (each enqueues on `st`; return hipError_t)
+// ---------------------------------------------------------------------------
+hipError_t launch_init_state(const Dev &d, hipStream_t st, const uint32_t *n_init_dev);
+hipError_t launch_push(const Dev &d, hipStream_t st, bool deposit, bool mcc);
+hipError_t launch_deposit(const Dev &d, hipStream_t st);
+hipError_t launch_field(const Dev &d, hipStream_t st);
+hipError_t launch_collide(const Dev &d, hipStream_t st);
+hipError_t launch_emit(const Dev &d, hipStream_t st);
+hipError_t launch_sort(const Dev &d, hipStream_t st);
+hipError_t launch_diag(const Dev &d, hipStream_t st);
+
+int push_grid(const Dev &d);
+
+}  // namespace picx

@@ -146,7 +146,7 @@ def bounded(nc: int = 8192, ppc: float = 200, seed: int = 2, n_steps: int = 1000
     """Bounded 1D3V plasma between two grounded absorbing walls."""
     Te = Te_eV * EV
     lam_d, w_pe = _bounded_plasma_scales(n0, Te)
-    dx = 0.5 * lam_d
+    dx = lam_d / 0.5  # lambda_De = 0.5 dx
     dt = wpe_dt / w_pe
     m_i = mass_ratio * M_ELECTRON
     w = n0 * dx / ppc

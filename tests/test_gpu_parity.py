@@ -1,0 +1,246 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on
+the same seeded inputs.
+
+Bars (stated per test):
+  * deposition: bit-exact (integer fixed point) on the same positions;
+  * charge density rho: bit-exact (same integer inputs, same FP64 formula);
+  * field solve: |phi_gpu - phi_orc| <= 8 nc eps64 max|phi| (the GPU evaluates
+    the Thomas recurrences as parallel scans, the oracle sequentially; both
+    are within ~nc eps64 of the exact solution);
+  * FP64 push on the oracle's grid acceleration: bit-exact;
+  * FP32 push: position error <= 1e-5 cells, velocity error <= 1e-5 max(|v64|, v_th)
+    per component (the single-step per-particle tolerance of the FP32 form).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import pic_inputs as pin
+from gpu_common import FP32, FP64, P, build_pair, by_id, flush, gpu_state, oracle_state
+
+pytestmark = pytest.mark.gpu
+
+EPS64 = 2.0 ** -52
+
+WORKLOADS = {
+    "langmuir": lambda: pin.langmuir(),                               # 512 cells, 51,200 e
+    "bounded_ragged": lambda: pin.bounded(nc=300, ppc=37.3, seed=7),  # 2 species, ragged counts
+    "bounded_mcc": lambda: pin.bounded_mcc(nc=700, ppc=50, seed=8),
+}
+
+
+def _deposit_ref(orc_state, nc):
+    return [oracle.deposit_fixed(s.x, nc) for s in orc_state]
+
+
+@pytest.mark.parametrize("prec", [FP32, FP64], ids=["fp32", "fp64"])
+@pytest.mark.parametrize("name", list(WORKLOADS))
+def test_deposit_bit_exact(name, prec):
+    wl = WORKLOADS[name]()
+    flush(f"deposit {name} prec={prec}")
+    sim, orc, ost = build_pair(wl, prec, flags=P.PIC_INIT_NO_FIELD)
+    sim.deposit()
+    S = sim.grid(P.PIC_R_DEPOSIT)
+    ref = _deposit_ref(ost, wl.nc)
+    for k in range(len(wl.species)):
+        assert np.array_equal(S[k], ref[k]), f"species {k}: max diff {np.max(np.abs(S[k].astype(np.int64) - ref[k].astype(np.int64)))}"
+        assert int(S[k].sum(dtype=np.uint64)) == ost[k].n * 2 ** 32
+    sim.close()
+
+
+@pytest.mark.parametrize("prec", [FP32, FP64], ids=["fp32", "fp64"])
+@pytest.mark.parametrize("name", list(WORKLOADS))
+def test_field_solve(name, prec):
+    wl = WORKLOADS[name]()
+    flush(f"field {name} prec={prec}")
+    sim, orc, ost = build_pair(wl, prec, flags=P.PIC_INIT_NO_FIELD)
+    sim.deposit()
+    sim.field_solve()
+    orc.deposit()
+    orc.field()
+    rho = sim.grid(P.PIC_R_RHO)
+    assert np.array_equal(rho, orc.rho), f"rho max diff {np.max(np.abs(rho - orc.rho))}"
+    phi = sim.grid(P.PIC_R_PHI)
+    E = sim.grid(P.PIC_R_EFIELD)
+    tol_phi = 8 * wl.nc * EPS64 * np.max(np.abs(orc.phi))
+    assert np.max(np.abs(phi - orc.phi)) <= tol_phi
+    tol_E = 2 * tol_phi / wl.dx + 8 * EPS64 * np.max(np.abs(orc.E))
+    assert np.max(np.abs(E - orc.E)) <= tol_E
+    a64 = sim.grid(P.PIC_R_ACC64)
+    a32 = sim.grid(P.PIC_R_ACC32)
+    for k, s in enumerate(wl.species):
+        C = (s.q / s.m) * (wl.dt * wl.dt / wl.dx)
+        assert np.max(np.abs(a64[k] - orc.acc[k])) <= abs(C) * tol_E * 1.01
+        assert np.max(np.abs(a32[k] - orc.acc[k])) <= abs(C) * tol_E + 2 ** -23 * np.max(np.abs(orc.acc[k]))
+    # the deposit is consumed
+    assert int(sim.grid(P.PIC_R_DEPOSIT).sum()) == 0
+    sim.close()
+
+
+def _oracle_one_push(orc):
+    orc.deposit()
+    orc.field()
+    acc = [a.copy() for a in orc.acc]
+    orc.push()
+    orc.walls()
+    return acc
+
+
+@pytest.mark.parametrize("name", list(WORKLOADS))
+def test_push_fp64_bit_exact_on_oracle_field(name):
+    """Given the oracle's grid acceleration, one FP64 push reproduces the oracle bit for bit,
+    and so does the fused deposit of the new positions."""
+    wl = WORKLOADS[name]()
+    flush(f"push fp64 {name}")
+    sim, orc, ost = build_pair(wl, FP64, flags=P.PIC_INIT_NO_FIELD)
+    acc = _oracle_one_push(orc)
+    sim.set_acc(acc)
+    sim.push()
+    for k in range(len(wl.species)):
+        g, o = gpu_state(sim, k), oracle_state(orc, k)
+        assert np.array_equal(g["id"], o["id"])
+        for f in ("x", "vx", "vy", "vz"):
+            assert np.array_equal(g[f], o[f]), f"{f}: max diff {np.max(np.abs(g[f] - o[f]))}"
+    S = sim.grid(P.PIC_R_DEPOSIT)
+    orc.deposit()
+    for k in range(len(wl.species)):
+        assert np.array_equal(S[k], orc.S[k])
+    sim.close()
+
+
+@pytest.mark.parametrize("name", list(WORKLOADS))
+def test_push_fp32_tolerance(name):
+    wl = WORKLOADS[name]()
+    flush(f"push fp32 {name}")
+    sim, orc, ost = build_pair(wl, FP32, flags=P.PIC_INIT_NO_FIELD)
+    acc = _oracle_one_push(orc)
+    sim.set_acc(acc)
+    sim.push()
+    for k, s in enumerate(wl.species):
+        g, o = gpu_state(sim, k), oracle_state(orc, k)
+        # absorption decisions can differ only for particles within rounding of a wall
+        common, gi, oi = np.intersect1d(g["id"], o["id"], return_indices=True)
+        only = np.setxor1d(g["id"], o["id"])
+        if only.size:
+            ox = np.concatenate([ost[k].x[np.isin(ost[k].id, only)]])
+            assert only.size <= 2, f"{only.size} particles absorbed on one side only"
+        vth = max(wl.vth_hat(s), 1e-30)
+        dx_ = np.abs(g["x"][gi] - o["x"][oi])
+        assert np.max(dx_) <= 1e-5, f"position error {np.max(dx_)}"
+        for f in ("vx", "vy", "vz"):
+            err = np.abs(g[f][gi] - o[f][oi]) / np.maximum(np.abs(o[f][oi]), vth)
+            assert np.max(err) <= 1e-5, f"{f} relative error {np.max(err)}"
+    # fused deposit: every live particle contributes exactly 2^32
+    S = sim.grid(P.PIC_R_DEPOSIT)
+    d, _ = sim.diagnostics()
+    for k in range(len(wl.species)):
+        assert int(S[k].sum(dtype=np.uint64)) == int(np.sum(gpu_state(sim, k)["id"].size)) * 2 ** 32
+    sim.close()
+
+
+@pytest.mark.parametrize("prec", [FP32, FP64], ids=["fp32", "fp64"])
+def test_mcc_one_step(prec):
+    """Push + collisions + ionisation pairs + source for one step, on the oracle's field."""
+    wl = pin.bounded_mcc(nc=400, ppc=80, seed=11)
+    # a denser gas so that every process fires many times in one step
+    wl.mcc.n_n *= 20
+    flush(f"mcc one step prec={prec}")
+    sim, orc, ost = build_pair(wl, prec, flags=P.PIC_INIT_NO_FIELD)
+    orc.deposit()
+    orc.field()
+    acc = [a.copy() for a in orc.acc]
+    orc.push()
+    orc.walls()
+    orc.mcc()
+    orc.source()
+    sim.set_acc(acc)
+    sim.push()
+    sim.mcc_collide()
+    d, rc = sim.diagnostics()
+    d = d[0]
+    c = orc.counters
+    assert rc == 0 and d.status == 0
+    if prec == FP64:
+        assert d.n_candidates == c.n_candidates
+        assert d.n_elastic == c.n_elastic and d.n_ionize == c.n_ionize and d.n_cx == c.n_cx
+        assert d.n_source == c.n_source
+    else:
+        assert abs(d.n_candidates - c.n_candidates) <= 2
+        for a, b in ((d.n_elastic, c.n_elastic), (d.n_ionize, c.n_ionize), (d.n_cx, c.n_cx)):
+            assert abs(a - b) <= 2
+    assert c.n_elastic > 100 and c.n_ionize > 5 and c.n_cx > 20
+    assert d.next_id == c.next_id if prec == FP64 else abs(int(d.next_id) - int(c.next_id)) <= 8
+    tol = 1e-12 if prec == FP64 else 2e-5
+    for k, s in enumerate(wl.species):
+        g, o = gpu_state(sim, k), oracle_state(orc, k)
+        if prec == FP64:
+            assert np.array_equal(g["id"], o["id"])
+            gi = oi = np.arange(g["id"].size)
+        else:
+            _, gi, oi = np.intersect1d(g["id"], o["id"], return_indices=True)
+            assert g["id"].size - gi.size <= 8 and o["id"].size - oi.size <= 8
+        vth = wl.vth_hat(s)
+        assert np.max(np.abs(g["x"][gi] - o["x"][oi])) <= (0 if prec == FP64 else 1e-5)
+        for f in ("vx", "vy", "vz"):
+            err = np.abs(g[f][gi] - o[f][oi]) / np.maximum(np.abs(o[f][oi]), vth)
+            assert np.max(err) <= tol, f"species {k} {f}: {np.max(err)}"
+    sim.close()
+
+
+def test_langmuir_fp64_200_steps():
+    """Whole steps (push, close of step, field solve) for the plain-method workload."""
+    wl = pin.langmuir()
+    flush("langmuir fp64 200 steps")
+    sim, orc, ost = build_pair(wl, FP64)
+    sim.step(200)
+    orc.step(200)
+    # the GPU solves the field at x^200 at the end of step 199; bring the oracle's field there
+    orc.deposit()
+    orc.field()
+    d, rc = sim.diagnostics()
+    od = orc.diagnostics()
+    assert rc == 0 and d[0].step == 200 and d[0].n_live[0] == 51200
+    g, o = gpu_state(sim, 0), oracle_state(orc, 0)
+    assert np.array_equal(g["id"], o["id"])
+    # trajectories start identical and drift apart only through rounding of the field solve
+    assert np.max(np.abs(g["x"] - o["x"])) <= 1e-8
+    assert np.max(np.abs(g["vx"] - o["vx"])) <= 1e-10
+    assert abs(d[0].ke[0] / od.ke[0] - 1) <= 1e-10
+    assert abs(d[0].field_energy / od.field_energy - 1) <= 1e-6
+    assert d[0].particle_steps == 200 * 51200
+    sim.close()
+
+
+@pytest.mark.parametrize("prec", [FP32, FP64], ids=["fp32", "fp64"])
+def test_bounded_mcc_steps_with_sort(prec):
+    """60 whole steps with walls, collisions, source and a sort every 20 steps."""
+    wl = pin.bounded_mcc(nc=256, ppc=40, seed=12)
+    flush(f"bounded mcc 60 steps prec={prec}")
+    sim, orc, ost = build_pair(wl, prec)
+    sim.step(60, sort_every=20)
+    orc.step(60)
+    d, rc = sim.diagnostics()
+    d = d[0]
+    c = orc.counters
+    od = orc.diagnostics()
+    assert rc == 0 and d.status == 0 and d.step == 60
+    for k in range(2):
+        ids = gpu_state(sim, k)["id"]
+        assert np.unique(ids).size == ids.size
+        if prec == FP64:
+            assert d.n_live[k] == od.n[k]
+            assert np.array_equal(ids, oracle_state(orc, k)["id"])
+        else:
+            assert abs(d.n_live[k] - od.n[k]) <= max(3, 0.002 * od.n[k])
+    if prec == FP64:
+        assert d.n_ionize == c.n_ionize and d.n_source == c.n_source
+        for k in range(2):
+            g, o = gpu_state(sim, k), oracle_state(orc, k)
+            assert np.max(np.abs(g["x"] - o["x"])) <= 1e-7
+            assert abs(d.ke[k] / od.ke[k] - 1) <= 1e-9
+    else:
+        for k in range(2):
+            assert abs(d.ke[k] / od.ke[k] - 1) <= 5e-3
+    sim.close()
