@@ -1,0 +1,230 @@
+#!/usr/bin/env python3
+"""Throughput of the 1D3V PIC-MCC hot path on one MI355X.
+
+Workload: the collisional bounded plasma -- 100,000 cells between two
+grounded absorbing walls, electrons and ions (m_i/m_e = 1836, 20 eV),
+100 particles per cell per species (2e7 particles), B at 45 degrees with
+omega_ce dt = 0.2, null-collision MCC against a neutral gas (elastic,
+charge exchange, ionisation), pair source, cell sort every 20 steps.  FP32
+push with 64-bit fixed-point deposition (the FP64 form is timed beside it).
+Inputs are seeded and synthetic (pic_inputs) and resident in HBM before the
+timed region.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Prints one JSON line.  `value` = particles pushed per second over the K timed
+steps (every step runs push+deposit+candidate test, collisions, pairs and
+source, field solve, and a sort every 20 steps).  `roofline` is for the
+dominant kernel (the fused mover), timed with HIP events on its stream.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per particle and push: read cell, f, vx, vy, vz (4 B each)
+# and the 8 B id; write cell, f, vx, vy, vz
+PUSH_BYTES_FP32 = 5 * 4 + 8 + 5 * 4
+# FP64 form: read x, vx, vy, vz (8 B each) and id; write x, vx, vy, vz
+PUSH_BYTES_FP64 = 4 * 8 + 8 + 4 * 8
+SORT_EVERY = 20
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "push_f32_bounded_mcc_traffic.json")
+PUSH_SOURCES = ["paper_2404_10270_amd/csrc/push.hip", "paper_2404_10270_amd/csrc/device_common.h"]
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def source_hash(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def workload(args):
+    import pic_inputs as pin
+    return pin.bounded_mcc(nc=args.nc, ppc=args.ppc, seed=3, sort_every=SORT_EVERY,
+                           cap_factor=1.25)
+
+
+def make_sim(wl, st64, precision):
+    import pic_inputs as pin
+    from paper_2404_10270_amd import pic as P
+    caps = pin.capacities(wl, st64)
+    state = pin.to_fp32_form(st64, wl.nc) if precision == P.PIC_FP32 else st64
+    return P.PicSim(wl, state, precision, capacities=caps, flags=P.PIC_INIT_SORT)
+
+
+def run_form(torch, sim, steps, warmup):
+    """Time `steps` whole steps after `warmup`; returns (p-steps/s, ms/step, p-steps)."""
+    sim.step(warmup, SORT_EVERY)
+    d0, _ = sim.diagnostics()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps, SORT_EVERY)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    d1, rc = sim.diagnostics()
+    if rc != 0:
+        raise RuntimeError(f"device status {d1[0].status:#x} during the timed region")
+    ps = int(d1[0].particle_steps - d0[0].particle_steps)
+    dt = t1 - t0
+    return ps / dt, 1e3 * dt / steps, ps
+
+
+def time_push(torch, sim, n_steps):
+    """Average duration of the fused mover launch, HIP events on its stream."""
+    from paper_2404_10270_amd import pic as P
+    d0, _ = sim.diagnostics()
+    evs = []
+    step = int(d0[0].step)
+    for _ in range(n_steps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(sim.stream)
+        sim.push()
+        e1.record(sim.stream)
+        sim.mcc_collide()
+        sim.field_solve()
+        step += 1
+        if step % SORT_EVERY == 0:
+            sim.sort()
+        evs.append((e0, e1))
+    torch.cuda.synchronize()
+    d1, _ = sim.diagnostics()
+    ms = [a.elapsed_time(b) for a, b in evs]
+    per_launch = (d1[0].particle_steps - d0[0].particle_steps) / n_steps
+    return sum(ms) / len(ms), per_launch
+
+
+def traffic_from_profile():
+    """HBM bytes per mover launch from the committed rocprofv3 counter summary,
+    or None when the mover's source changed since the counters were taken."""
+    try:
+        with open(PROFILE_TRAFFIC) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != source_hash(PUSH_SOURCES):
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(args):
+    """The oracle as it stands, single thread, on a bounded sample of the workload."""
+    import oracle
+    import pic_inputs as pin
+    wl = workload(args)
+    st = pin.initial_state(wl)
+    st32 = pin.to_fp32_form(st, wl.nc)
+    st_o = [s.as_f64() for s in st32]
+    ps, dt = oracle.time_steps(wl, st_o, args.cpu_steps, caps=pin.capacities(wl, st_o))
+    return {"value": ps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{wl.nc} cells, {sum(s.n for s in st_o)} particles, {args.cpu_steps} whole "
+                      f"steps from the seeded start ({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--nc", type=int, default=100_000)
+    ap.add_argument("--ppc", type=float, default=100)
+    ap.add_argument("--push-steps", type=int, default=40)
+    ap.add_argument("--cpu-steps", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np  # noqa: F401
+    import torch
+    import pic_inputs as pin
+    from paper_2404_10270_amd import pic as P
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    wl = workload(args)
+    log(f"generating {wl.n_particles} particles on {wl.nc} cells")
+    st = pin.initial_state(wl)
+
+    log("FP32 form: init")
+    sim = make_sim(wl, st, P.PIC_FP32)
+    log(f"FP32 form: {args.warmup} warm-up + {args.steps} timed steps")
+    rate, ms_step, ps = run_form(torch, sim, args.steps, args.warmup)
+    log(f"FP32 form: {rate:.4e} p-steps/s, {ms_step:.4f} ms/step")
+    push_ms, per_launch = time_push(torch, sim, args.push_steps)
+    log(f"FP32 mover: {push_ms * 1e3:.1f} us/launch, {per_launch:.0f} particles/launch")
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+
+    achieved = PUSH_BYTES_FP32 * per_launch / (push_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile(),
+            "kernel": "push_f32_kernel<true,true>", "bytes_per_particle": PUSH_BYTES_FP32,
+            "particles_per_launch": int(per_launch), "us_per_launch": round(push_ms * 1e3, 2)}
+
+    fp64 = None
+    if not args.no_fp64:
+        log("FP64 form: init")
+        sim64 = make_sim(wl, st, P.PIC_FP64)
+        r64, ms64, _ = run_form(torch, sim64, args.steps, args.warmup)
+        p64_ms, per64 = time_push(torch, sim64, args.push_steps)
+        log(f"FP64 form: {r64:.4e} p-steps/s, mover {p64_ms * 1e3:.1f} us")
+        fp64 = {"value": r64, "ms_per_step": round(ms64, 4),
+                "mover_GBps": round(PUSH_BYTES_FP64 * per64 / (p64_ms * 1e-3) / 1e9, 1),
+                "fp32_over_fp64": round(rate / r64, 3)}
+        sim64.close()
+        del sim64
+        torch.cuda.empty_cache()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"CPU baseline: oracle, {args.cpu_steps} steps")
+        cpu = cpu_baseline(args)
+        log(f"CPU baseline: {cpu['value']:.4e} p-steps/s")
+
+    out = {
+        "metric": "particle-steps/s on 1 MI355X",
+        "value": rate,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "bounded plasma + null-collision MCC, 100,000 cells, "
+                               "100 particles/cell/species",
+                   "cells": wl.nc, "particles": wl.n_particles, "sort_every": SORT_EVERY,
+                   "deposit": "int64 fixed point (F=32)", "field_solve": "f64 Thomas"},
+        "roofline": roof,
+        "fp64_form": fp64,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

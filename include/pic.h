@@ -160,6 +160,7 @@ typedef struct pic_ctx pic_ctx;
 
 /* init flags */
 #define PIC_INIT_NO_FIELD 0x1u   /* skip the initial deposit + field solve */
+#define PIC_INIT_SORT     0x2u   /* sort the uploaded particles by cell first */
 
 /* push flags */
 #define PIC_PUSH_NO_DEPOSIT 0x1u /* do not deposit the new positions */
@@ -173,8 +174,10 @@ int pic_query_sizes(const pic_config *cfgs, int n_inst, pic_sizes *out, int64_t 
 
 /*
  * pic_init -- bind caller-owned buffers, convert the configuration to
- * cells/steps, write the per-segment tables, and (unless PIC_INIT_NO_FIELD)
- * deposit the uploaded particles and solve the field so that the first
+ * cells/steps, write the per-segment tables, drop (and flag) uploaded
+ * particles that are out of range or non-finite, optionally sort them by cell
+ * (PIC_INIT_SORT; the particles then live in buffer set 1), and (unless
+ * PIC_INIT_NO_FIELD) deposit them and solve the field so that the first
  * pic_push sees E at the initial positions.  stream is a hipStream_t (NULL =
  * the null stream).  Sec. 2: initialisation of grid and particles before the
  * cycle.  On error *out is NULL.

@@ -173,6 +173,7 @@ double candidate_probability(const pic_config &c, int k)
 
 struct Plan {
     int64_t n_slots = 0, n_tiles = 0, G = 0, n_field_tiles = 0, n_sort_tiles = 0;
+    int n_push_blocks = 1;
     std::vector<int64_t> seg_base, seg_tile0, node_base, inst_ftile0;
     Layout L{};
 };
@@ -237,10 +238,16 @@ int plan(const pic_config *cfgs, int n_inst, Plan &p)
     L.bwd_status = take(sizeof(AffineStatus) * p.n_field_tiles);
     L.sort_status = take(sizeof(uint64_t) * p.n_sort_tiles);
     L.fe_part = take(sizeof(double) * p.n_field_tiles);
-    L.cand_cap = cand_capacity(cfgs, n_inst, P);
-    L.ev_cap = L.cand_cap;
-    L.cand = take(sizeof(uint32_t) * L.cand_cap);
-    L.ev = take(sizeof(IzEvent) * L.ev_cap);
+    // candidates: one region of kCandQ per push block, then an overflow list
+    // sized for the expected total (mean + 10 sigma)
+    p.n_push_blocks = (int)std::min<int64_t>(std::max<int64_t>(p.n_tiles, 1), kMaxPushBlocks);
+    L.cand_ovf_cap = cand_capacity(cfgs, n_inst, P);
+    L.ev_ovf_cap = L.cand_ovf_cap;
+    L.cand = take(sizeof(uint32_t) * ((uint64_t)p.n_push_blocks * kCandQ + L.cand_ovf_cap));
+    L.cand_n = take(sizeof(uint32_t) * p.n_push_blocks);
+    L.ev = take(sizeof(IzEvent) * ((uint64_t)p.n_push_blocks * kEvQ + L.ev_ovf_cap));
+    L.ev_n = take(sizeof(uint32_t) * p.n_push_blocks);
+    L.cnt_slot = take(sizeof(unsigned long long) * (uint64_t)p.n_push_blocks * kCntSeg * kNCnt);
     L.diag_part = take(sizeof(double) * (uint64_t)kDiagBlocks * n_seg * kDiagVals);
     L.diag_out = take(sizeof(pic_diag) * n_inst);
     L.total = off;
@@ -410,14 +417,18 @@ int pic_init(const pic_config *cfgs, int n_inst, const pic_buffers *bufs, void *
     d.sort_status = at<unsigned long long>(W, L.sort_status);
     d.fe_part = at<double>(W, L.fe_part);
     d.cand = at<uint32_t>(W, L.cand);
+    d.cand_n = at<uint32_t>(W, L.cand_n);
     d.ev = at<IzEvent>(W, L.ev);
+    d.ev_n = at<uint32_t>(W, L.ev_n);
+    d.cnt_slot = at<unsigned long long>(W, L.cnt_slot);
     d.diag_part = at<double>(W, L.diag_part);
     d.diag_out = at<pic_diag>(W, L.diag_out);
     d.n_slots = p.n_slots;
     d.n_tiles = p.n_tiles;
     d.G = p.G;
-    d.cand_cap = L.cand_cap;
-    d.ev_cap = L.ev_cap;
+    d.cand_ovf_cap = L.cand_ovf_cap;
+    d.ev_ovf_cap = L.ev_ovf_cap;
+    d.n_push_blocks = p.n_push_blocks;
     d.n_field_tiles = p.n_field_tiles;
     d.n_sort_tiles = p.n_sort_tiles;
     d.n_seg = n_seg;
@@ -447,6 +458,7 @@ int pic_init(const pic_config *cfgs, int n_inst, const pic_buffers *bufs, void *
     // the host vectors above must stay alive until the copies are done
     ok = ok && hipStreamSynchronize(st) == hipSuccess;
     ok = ok && launch_init_state(d, st, nullptr) == hipSuccess;
+    if (ok && (flags & PIC_INIT_SORT)) ok = launch_sort(d, st) == hipSuccess;
     if (ok && !(flags & PIC_INIT_NO_FIELD)) {
         ok = launch_deposit(d, st) == hipSuccess;
         ok = ok && launch_field(d, st) == hipSuccess;
@@ -485,7 +497,7 @@ int pic_mcc_collide(pic_ctx *c)
 {
     if (!c) return PIC_E_STATE;
     if (c->mcc_any && launch_collide(c->d, c->st) != hipSuccess) return PIC_E_DEVICE;
-    if (launch_emit(c->d, c->st) != hipSuccess) return PIC_E_DEVICE;
+    if (launch_emit(c->d, c->st, c->mcc_any || c->src_any, c->mcc_any) != hipSuccess) return PIC_E_DEVICE;
     c->host_steps += 1;
     return PIC_OK;
 }

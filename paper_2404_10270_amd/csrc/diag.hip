@@ -61,47 +61,82 @@ __global__ __launch_bounds__(kBlock) void diag_partial_kernel(Dev d)
     for (int q = threadIdx.x; q < d.n_seg * kDiagVals; q += kBlock) out[q] = s_acc[q];
 }
 
+// block-wide sum in a fixed order (deterministic)
+__device__ double block_sum(double v, double *s_red)
+{
+    s_red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) s_red[threadIdx.x] += s_red[threadIdx.x + s];
+        __syncthreads();
+    }
+    const double r = s_red[0];
+    __syncthreads();
+    return r;
+}
+
+// one block per instance: sums of the per-block partials, the process-count
+// slots and the field-energy tiles
 __global__ __launch_bounds__(kBlock) void diag_final_kernel(Dev d, int n_blocks)
 {
-    for (int i = threadIdx.x; i < d.n_inst; i += kBlock) {
-        const InstConst &ic = d.instc[i];
-        const InstDyn &idn = d.instd[i];
-        pic_diag o;
-        memset(&o, 0, sizeof(o));
-        o.step = idn.step;
-        o.next_id = idn.next_id;
-        o.status = idn.status;
-        o.cur_set = d.glob->cur_set;
-        for (int k = 0; k < ic.nsp; ++k) {
-            const int s = ic.seg0 + k;
-            const SegConst &sc = d.segc[s];
-            const SegDyn &sd = d.segd[s];
-            double a[kDiagVals] = {0, 0, 0, 0, 0, 0};
-            for (int b = 0; b < n_blocks; ++b)
-                for (int v = 0; v < kDiagVals; ++v)
-                    a[v] += d.diag_part[((int64_t)b * d.n_seg + s) * kDiagVals + v];
-            o.n_slots_used[k] = sd.count;
-            o.n_live[k] = (int64_t)a[0];
-            o.ke[k] = 0.5 * sc.mw * (sc.vs * sc.vs) * a[1];
-            o.mom[k][0] = sc.mw * sc.vs * a[2];
-            o.mom[k][1] = sc.mw * sc.vs * a[3];
-            o.mom[k][2] = sc.mw * sc.vs * a[4];
-            o.absorbed_total[k][0] = (int64_t)sd.absorbed_total[0];
-            o.absorbed_total[k][1] = (int64_t)sd.absorbed_total[1];
-            o.created_total[k] = (int64_t)sd.created_total;
+    __shared__ double s_red[kBlock];
+    const int i = blockIdx.x;
+    const InstConst &ic = d.instc[i];
+    const InstDyn &idn = d.instd[i];
+    double mom[PIC_MAX_SPECIES][kDiagVals];
+    for (int k = 0; k < ic.nsp; ++k) {
+        const int s = ic.seg0 + k;
+        for (int v = 0; v < kDiagVals; ++v) {
+            double a = 0.0;
+            for (int b = threadIdx.x; b < n_blocks; b += kBlock)
+                a += d.diag_part[((int64_t)b * d.n_seg + s) * kDiagVals + v];
+            mom[k][v] = block_sum(a, s_red);
         }
-        double fe = 0.0;
-        for (int64_t t = ic.ftile0; t < d.inst_ftile0[i + 1]; ++t) fe += d.fe_part[t];
-        o.field_energy = 0.5 * ic.eps0 * fe;
-        o.n_candidates = (int64_t)idn.n_candidates;
-        o.n_elastic = (int64_t)idn.n_elastic;
-        o.n_ionize = (int64_t)idn.n_ionize;
-        o.n_cx = (int64_t)idn.n_cx;
-        o.n_over_cap = (int64_t)idn.n_over_cap;
-        o.n_source = (int64_t)idn.n_source;
-        o.particle_steps = (int64_t)idn.particle_steps;
-        d.diag_out[i] = o;
     }
+    unsigned long long pc[kNCnt] = {idn.n_candidates, idn.n_elastic, idn.n_ionize, idn.n_cx,
+                                    idn.n_over_cap};
+    if (d.n_seg <= kCntSeg) {
+        for (int q = 0; q < kNCnt; ++q) {
+            double a = 0.0;  // exact: counts stay far below 2^53
+            for (int b = threadIdx.x; b < d.n_push_blocks; b += kBlock)
+                for (int k = 0; k < ic.nsp; ++k)
+                    a += (double)d.cnt_slot[((int64_t)b * kCntSeg + ic.seg0 + k) * kNCnt + q];
+            pc[q] += (unsigned long long)block_sum(a, s_red);
+        }
+    }
+    double fe = 0.0;
+    for (int64_t t = ic.ftile0 + threadIdx.x; t < d.inst_ftile0[i + 1]; t += kBlock) fe += d.fe_part[t];
+    fe = block_sum(fe, s_red);
+    if (threadIdx.x != 0) return;
+    pic_diag o;
+    memset(&o, 0, sizeof(o));
+    o.step = idn.step;
+    o.next_id = idn.next_id;
+    o.status = idn.status;
+    o.cur_set = d.glob->cur_set;
+    for (int k = 0; k < ic.nsp; ++k) {
+        const int s = ic.seg0 + k;
+        const SegConst &sc = d.segc[s];
+        const SegDyn &sd = d.segd[s];
+        o.n_slots_used[k] = sd.count;
+        o.n_live[k] = (int64_t)mom[k][0];
+        o.ke[k] = 0.5 * sc.mw * (sc.vs * sc.vs) * mom[k][1];
+        o.mom[k][0] = sc.mw * sc.vs * mom[k][2];
+        o.mom[k][1] = sc.mw * sc.vs * mom[k][3];
+        o.mom[k][2] = sc.mw * sc.vs * mom[k][4];
+        o.absorbed_total[k][0] = (int64_t)sd.absorbed_total[0];
+        o.absorbed_total[k][1] = (int64_t)sd.absorbed_total[1];
+        o.created_total[k] = (int64_t)sd.created_total;
+    }
+    o.field_energy = 0.5 * ic.eps0 * fe;
+    o.n_candidates = (int64_t)pc[0];
+    o.n_elastic = (int64_t)pc[1];
+    o.n_ionize = (int64_t)pc[2];
+    o.n_cx = (int64_t)pc[3];
+    o.n_over_cap = (int64_t)pc[4];
+    o.n_source = (int64_t)idn.n_source;
+    o.particle_steps = (int64_t)idn.particle_steps;
+    d.diag_out[i] = o;
 }
 
 int diag_blocks(const Dev &d)
@@ -119,7 +154,7 @@ hipError_t launch_diag(const Dev &d, hipStream_t st)
     hipLaunchKernelGGL(diag_partial_kernel, dim3(nb), dim3(kBlock), lds, st, d);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(kBlock), 0, st, d, nb);
+    hipLaunchKernelGGL(diag_final_kernel, dim3(d.n_inst), dim3(kBlock), 0, st, d, nb);
     return hipGetLastError();
 }
 

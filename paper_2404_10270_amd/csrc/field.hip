@@ -12,7 +12,8 @@
 //   backward  phi_u = (u/(u+1)) phi_{u+1} + d'_u,
 // so each sweep is evaluated as a scan over affine maps y -> A y + B: every
 // thread composes kFieldR consecutive maps, the block scans the thread maps,
-// and tiles chain through a single-pass decoupled look-back.  Same recurrences
+// and tiles chain through a single-pass decoupled look-back in which one wave
+// inspects 64 predecessor tiles per round.  Same recurrences
 // as the sequential sweep, regrouped; only the rounding order differs.
 #include "device_common.h"
 
@@ -68,45 +69,75 @@ __device__ Aff block_exclusive_scan(Aff m, Aff *agg)
     return compose(excl, wpre);
 }
 
-__device__ __forceinline__ unsigned long long ld_acquire(const unsigned long long *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 __device__ __forceinline__ void st_release(unsigned long long *p, unsigned long long v)
 {
     __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Look-back over the tiles before `vt` (same instance, tiles local index > 0):
-// returns the value entering tile vt, publishes the tile's inclusive value.
-// Executed by one thread.
+// Look-back over the tiles before `vt` of the same instance, by the 64 lanes
+// of one wave: each round inspects 64 predecessors at once and composes the
+// aggregates up to the nearest inclusive one.  Publishes this tile's
+// aggregate first and its inclusive value last; returns the value entering
+// the tile (in every lane).
 __device__ double affine_lookback(AffineStatus *st, int64_t vt, int64_t lt, Aff agg,
                                   unsigned long long gen)
 {
-    double y_in = 0.0;
+    const int lane = lane_id();
     if (lt == 0) {
-        st[vt].V = agg.B;  // applied to the boundary value 0
-        st_release(&st[vt].flag, (gen << 2) | 2ull);
+        if (lane == 0) {
+            st[vt].V = agg.B;  // applied to the boundary value 0
+            st_release(&st[vt].flag, (gen << 2) | 2ull);
+        }
         return 0.0;
     }
-    st[vt].A = agg.A;
-    st[vt].B = agg.B;
-    st_release(&st[vt].flag, (gen << 2) | 1ull);
-    Aff R = {1.0, 0.0};
-    for (int64_t p = vt - 1;; --p) {
-        unsigned long long f;
-        do {
-            f = ld_acquire(&st[p].flag);
-        } while ((f >> 2) != gen);
-        if ((f & 3ull) == 2ull) {
-            y_in = R.A * st[p].V + R.B;
+    if (lane == 0) {
+        st[vt].A = agg.A;
+        st[vt].B = agg.B;
+        st_release(&st[vt].flag, (gen << 2) | 1ull);
+    }
+    const int64_t p_first = vt - lt;  // tile 0 of the instance: always inclusive
+    Aff R = {1.0, 0.0};               // maps of the closer tiles, applied last
+    double y_in = 0.0;
+    for (int64_t p_hi = vt - 1;; p_hi -= 64) {
+        const int64_t p = p_hi - lane;
+        const bool inr = p >= p_first;
+        unsigned long long f = 0;
+        if (inr) {
+            // poll without acquire (an acquire invalidates the L2 on every poll)
+            do {
+                f = __hip_atomic_load(&st[p].flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } while ((f >> 2) != gen);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const bool incl = inr && ((f & 3ull) == 2ull);
+        const unsigned long long mb = ballot(incl);
+        const int k = mb ? (__ffsll((long long)mb) - 1) : 64;
+        Aff m = {1.0, 0.0};
+        if (inr && lane < k) m = Aff{st[p].A, st[p].B};
+        // m_0 o m_1 o ... o m_{k-1} (lane 0 is the closest tile)
+#pragma unroll
+        for (int dd = 1; dd < 64; dd <<= 1) {
+            Aff o;
+            o.A = __shfl_down(m.A, dd, 64);
+            o.B = __shfl_down(m.B, dd, 64);
+            if (lane + dd < 64) m = compose(m, o);
+        }
+        Aff c;
+        c.A = __shfl(m.A, 0, 64);
+        c.B = __shfl(m.B, 0, 64);
+        R = compose(R, c);
+        if (mb) {
+            double V = 0.0;
+            if (lane == k) V = st[p].V;
+            V = __shfl(V, k, 64);
+            y_in = R.A * V + R.B;
             break;
         }
-        R = compose(R, Aff{st[p].A, st[p].B});
     }
-    st[vt].V = agg.A * y_in + agg.B;
-    st_release(&st[vt].flag, (gen << 2) | 2ull);
+    if (lane == 0) {
+        st[vt].V = agg.A * y_in + agg.B;
+        st_release(&st[vt].flag, (gen << 2) | 2ull);
+    }
     return y_in;
 }
 
@@ -200,7 +231,10 @@ __global__ __launch_bounds__(kBlock) void field_fwd_kernel(Dev d)
     Aff agg;
     const Aff excl = block_exclusive_scan(m, &agg);
     __shared__ double s_in;
-    if (threadIdx.x == 0) s_in = affine_lookback(d.fwd_status, vt, lt, agg, gen);
+    if (threadIdx.x < 64) {
+        const double y = affine_lookback(d.fwd_status, vt, lt, agg, gen);
+        if (threadIdx.x == 0) s_in = y;
+    }
     __syncthreads();
     double y = excl.A * s_in + excl.B;
 #pragma unroll
@@ -255,7 +289,10 @@ __global__ __launch_bounds__(kBlock) void field_bwd_kernel(Dev d)
     Aff agg;
     const Aff excl = block_exclusive_scan(m, &agg);
     __shared__ double s_in;
-    if (threadIdx.x == 0) s_in = affine_lookback(d.bwd_status, vt_r, lt_r, agg, gen);
+    if (threadIdx.x < 64) {
+        const double y = affine_lookback(d.bwd_status, vt_r, lt_r, agg, gen);
+        if (threadIdx.x == 0) s_in = y;
+    }
     __syncthreads();
     const double phi_above = s_in;  // phi at the node just above this tile (0 at the top)
 

@@ -11,8 +11,13 @@
 //   ionisation    energy above threshold split U : 1-U between two isotropic
 //                 electrons, the new ion Maxwellian at T_n, pair at the parent.
 // The emit kernel then creates the ionisation pairs (ids ranked by parent id)
-// and the source pairs (as many as ions reached the walls this step), deposits
-// them, and its last block closes the step: counts, ids, step index.
+// and the source pairs (as many as ions reached the walls this step) and
+// deposits them; a one-block kernel closes the step (counts, ids, step index).
+//
+// Same-address device atomics from many blocks serialise, so: collide block b
+// reads the candidates push block b wrote, writes its ionisation events to its
+// own region and keeps its process counts in its own slot.  Readers of the
+// events index the regions through a prefix sum built in LDS.
 #include "device_common.h"
 
 #pragma clang fp contract(off)
@@ -30,112 +35,209 @@ __device__ __forceinline__ void st_v(void *p, int64_t g, double v, bool f64)
     else ((float *)p)[g] = (float)v;
 }
 
+enum { kCCand = 0, kCEl = 1, kCIz = 2, kCCx = 3, kCOver = 4 };
+
+// collide one candidate at slot g; returns its segment, fills the counts and
+// the ionisation event
+__device__ __forceinline__ int collide_one(const Dev &d, int cur, bool f64, int64_t g,
+                                           uint32_t (&cnt)[kNCnt], bool &iz, IzEvent &ev)
+{
+    const int seg = seg_of_slot(d.seg_base, d.n_seg, g);
+    const SegConst &sc = d.segc[seg];
+    const long long step = d.instd[sc.inst].step;
+    const unsigned long long pid = d.id[cur][g];
+    const double vx = ld_v(d.vx[cur], g, f64);
+    const double vy = ld_v(d.vy[cur], g, f64);
+    const double vz = ld_v(d.vz[cur], g, f64);
+    const uint4 u = draw(pid, step, 0, sc.key0, sc.key1);
+    const double v2 = (vx * vx + vy * vy) + vz * vz;
+    cnt[kCCand] = 1;
+    if (v2 > sc.vcap2) cnt[kCOver] = 1;
+    const double r = u01(u.y) * sc.nu_max;
+    const double r2 = r * r;
+    if (sc.kind == PIC_KIND_ELECTRON) {
+        if (r2 < sc.C0 * v2) {
+            double d0, d1, d2;
+            iso_dir(u.z, u.w, d0, d1, d2);
+            const double gg = sqrt(v2);
+            st_v(d.vx[cur], g, sc.am * vx + sc.bm * gg * d0, f64);
+            st_v(d.vy[cur], g, sc.am * vy + sc.bm * gg * d1, f64);
+            st_v(d.vz[cur], g, sc.am * vz + sc.bm * gg * d2, f64);
+            cnt[kCEl] = 1;
+        } else if (v2 >= sc.v2_iz && r2 < sc.C1 * v2) {
+            const uint4 u1 = draw(pid, step, 1, sc.key0, sc.key1);
+            const double e_tot = 0.5 * v2 - sc.eps_iz;
+            const double e1 = u01(u.z) * e_tot;
+            const double e2 = e_tot - e1;
+            const double g1 = sqrt(2.0 * e1);
+            double d0, d1, d2;
+            iso_dir(u1.x, u1.y, d0, d1, d2);
+            st_v(d.vx[cur], g, g1 * d0, f64);
+            st_v(d.vy[cur], g, g1 * d1, f64);
+            st_v(d.vz[cur], g, g1 * d2, f64);
+            iz = true;
+            ev.parent_id = pid;
+            ev.slot = (uint32_t)g;
+            ev.seg = seg;
+            ev.inst = sc.inst;
+            ev.g2 = sqrt(2.0 * e2);
+            cnt[kCIz] = 1;
+        }
+    } else {
+        if (r2 < sc.C0 * v2) {
+            const uint4 u1 = draw(pid, step, 1, sc.key0, sc.key1);
+            double n0, n1, n2, n3;
+            box_muller(u.z, u.w, n0, n1);
+            box_muller(u1.x, u1.y, n2, n3);
+            st_v(d.vx[cur], g, sc.sig_n * n0, f64);
+            st_v(d.vy[cur], g, sc.sig_n * n1, f64);
+            st_v(d.vz[cur], g, sc.sig_n * n2, f64);
+            cnt[kCCx] = 1;
+        }
+    }
+    return seg;
+}
+
+__device__ __forceinline__ void add_counts(InstDyn *idn, const uint32_t (&c)[kNCnt])
+{
+    if (c[kCCand]) atomicAdd(&idn->n_candidates, (unsigned long long)c[kCCand]);
+    if (c[kCEl]) atomicAdd(&idn->n_elastic, (unsigned long long)c[kCEl]);
+    if (c[kCIz]) atomicAdd(&idn->n_ionize, (unsigned long long)c[kCIz]);
+    if (c[kCCx]) atomicAdd(&idn->n_cx, (unsigned long long)c[kCCx]);
+    if (c[kCOver]) atomicAdd(&idn->n_over_cap, (unsigned long long)c[kCOver]);
+}
+
 __global__ __launch_bounds__(kBlock) void collide_kernel(Dev d)
 {
+    __shared__ uint32_t s_cnt[kCntSeg][kNCnt];
+    __shared__ IzEvent s_ev[kEvQ];
+    __shared__ uint32_t s_en;
+    const bool lds_cnt = d.n_seg <= kCntSeg;
+    for (int q = threadIdx.x; q < kCntSeg * kNCnt; q += kBlock) (&s_cnt[0][0])[q] = 0u;
+    if (threadIdx.x == 0) s_en = 0u;
+    __syncthreads();
+
     const int cur = d.glob->cur_set;
     const bool f64 = (d.precision == PIC_FP64);
-    uint32_t n = d.glob->cand_count;
-    if (n > (uint32_t)d.cand_cap) n = (uint32_t)d.cand_cap;
-    const uint32_t stride = gridDim.x * kBlock;
-    // uniform trip count so that whole waves take part in the aggregations
-    const uint32_t n_round = ((n + stride - 1) / stride) * stride;
-    for (uint32_t c = blockIdx.x * kBlock + threadIdx.x; c < n_round; c += stride) {
-        const bool own = c < n;
-        int inst = -1;
-        unsigned long long cnt = 0;  // packed counts: cand | el<<12 | iz<<24 | cx<<36 | over<<48
+    // this block's region of the candidate list, then a share of the overflow list
+    const uint32_t nr = d.cand_n[blockIdx.x];
+    uint32_t novf = d.glob->cand_ovf;
+    if (novf > (uint32_t)d.cand_ovf_cap) novf = (uint32_t)d.cand_ovf_cap;
+    const uint32_t per_block = (novf + gridDim.x - 1) / gridDim.x;
+    const uint32_t o_lo = min(novf, blockIdx.x * per_block);
+    const uint32_t o_hi = min(novf, o_lo + per_block);
+    const uint32_t n_items = nr + (o_hi - o_lo);
+    for (uint32_t q = threadIdx.x; q < n_items; q += kBlock) {
+        uint32_t cnt[kNCnt] = {0, 0, 0, 0, 0};
         bool iz = false;
-        IzEvent ev;
-        if (own) {
-            const int64_t g = d.cand[c];
-            const int seg = seg_of_slot(d.seg_base, d.n_seg, g);
-            const SegConst &sc = d.segc[seg];
-            inst = sc.inst;
-            const long long step = d.instd[inst].step;
-            const unsigned long long pid = d.id[cur][g];
-            const double vx = ld_v(d.vx[cur], g, f64);
-            const double vy = ld_v(d.vy[cur], g, f64);
-            const double vz = ld_v(d.vz[cur], g, f64);
-            const uint4 u = draw(pid, step, 0, sc.key0, sc.key1);
-            const double v2 = (vx * vx + vy * vy) + vz * vz;
-            cnt = 1ull;
-            if (v2 > sc.vcap2) cnt += 1ull << 48;
-            const double r = u01(u.y) * sc.nu_max;
-            const double r2 = r * r;
-            if (sc.kind == PIC_KIND_ELECTRON) {
-                if (r2 < sc.C0 * v2) {
-                    double d0, d1, d2;
-                    iso_dir(u.z, u.w, d0, d1, d2);
-                    const double gg = sqrt(v2);
-                    st_v(d.vx[cur], g, sc.am * vx + sc.bm * gg * d0, f64);
-                    st_v(d.vy[cur], g, sc.am * vy + sc.bm * gg * d1, f64);
-                    st_v(d.vz[cur], g, sc.am * vz + sc.bm * gg * d2, f64);
-                    cnt += 1ull << 12;
-                } else if (v2 >= sc.v2_iz && r2 < sc.C1 * v2) {
-                    const uint4 u1 = draw(pid, step, 1, sc.key0, sc.key1);
-                    const double e_tot = 0.5 * v2 - sc.eps_iz;
-                    const double e1 = u01(u.z) * e_tot;
-                    const double e2 = e_tot - e1;
-                    const double g1 = sqrt(2.0 * e1);
-                    double d0, d1, d2;
-                    iso_dir(u1.x, u1.y, d0, d1, d2);
-                    st_v(d.vx[cur], g, g1 * d0, f64);
-                    st_v(d.vy[cur], g, g1 * d1, f64);
-                    st_v(d.vz[cur], g, g1 * d2, f64);
-                    iz = true;
-                    ev.parent_id = pid;
-                    ev.slot = (uint32_t)g;
-                    ev.seg = seg;
-                    ev.g2 = sqrt(2.0 * e2);
-                    cnt += 1ull << 24;
-                }
-            } else {
-                if (r2 < sc.C0 * v2) {
-                    const uint4 u1 = draw(pid, step, 1, sc.key0, sc.key1);
-                    double n0, n1, n2, n3;
-                    box_muller(u.z, u.w, n0, n1);
-                    box_muller(u1.x, u1.y, n2, n3);
-                    st_v(d.vx[cur], g, sc.sig_n * n0, f64);
-                    st_v(d.vy[cur], g, sc.sig_n * n1, f64);
-                    st_v(d.vz[cur], g, sc.sig_n * n2, f64);
-                    cnt += 1ull << 36;
-                }
-            }
-        }
-        // ionisation events
-        const uint32_t idx = wave_append(&d.glob->ev_count, iz);
+        IzEvent ev = {};
+        const int64_t idx = q < nr ? (int64_t)blockIdx.x * kCandQ + q
+                                   : (int64_t)d.n_push_blocks * kCandQ + o_lo + (q - nr);
+        const int seg = collide_one(d, cur, f64, (int64_t)d.cand[idx], cnt, iz, ev);
         if (iz) {
-            if (idx < (uint32_t)d.ev_cap) {
-                d.ev[idx] = ev;
-                atomicAdd(&d.instd[inst].n_iz_step, 1u);
+            // LDS queue of this block; the rare excess goes to the overflow list
+            const uint32_t e = atomicAdd(&s_en, 1u);
+            if (e < (uint32_t)kEvQ) {
+                s_ev[e] = ev;
             } else {
-                atomicOr(&d.instd[inst].status, PIC_ST_CANDIDATES);
+                const uint32_t o = atomicAdd(&d.glob->ev_ovf, 1u);
+                if (o < (uint32_t)d.ev_ovf_cap) d.ev[(int64_t)d.n_push_blocks * kEvQ + o] = ev;
+                else atomicOr(&d.instd[ev.inst].status, PIC_ST_CANDIDATES);
             }
         }
-        // per-instance process counters, summed over runs of equal instance
-        bool tail;
-        const unsigned long long t = run_sum(inst, cnt, tail);
-        if (tail && inst >= 0) {
-            InstDyn *idn = d.instd + inst;
-            const unsigned long long m12 = 0xFFFull;
-            if (t & m12) atomicAdd(&idn->n_candidates, t & m12);
-            if ((t >> 12) & m12) atomicAdd(&idn->n_elastic, (t >> 12) & m12);
-            if ((t >> 24) & m12) atomicAdd(&idn->n_ionize, (t >> 24) & m12);
-            if ((t >> 36) & m12) atomicAdd(&idn->n_cx, (t >> 36) & m12);
-            if ((t >> 48) & m12) atomicAdd(&idn->n_over_cap, (t >> 48) & m12);
+        if (lds_cnt) {
+#pragma unroll
+            for (int c = 0; c < kNCnt; ++c)
+                if (cnt[c]) atomicAdd(&s_cnt[seg][c], cnt[c]);
+        } else {
+            add_counts(d.instd + d.segc[seg].inst, cnt);
+        }
+    }
+    __syncthreads();
+    const uint32_t ne = min(s_en, (uint32_t)kEvQ);
+    for (uint32_t e = threadIdx.x; e < ne; e += kBlock) d.ev[(int64_t)blockIdx.x * kEvQ + e] = s_ev[e];
+    if (threadIdx.x == 0) d.ev_n[blockIdx.x] = ne;
+    if (lds_cnt) {
+        // this block's own slot: plain read-modify-write, no other block touches it
+        unsigned long long *slot = d.cnt_slot + (int64_t)blockIdx.x * kCntSeg * kNCnt;
+        for (int q = threadIdx.x; q < d.n_seg * kNCnt; q += kBlock) {
+            const uint32_t v = (&s_cnt[0][0])[q];
+            if (v) slot[q] += v;
         }
     }
 }
 
-// write one created particle into segment `seg`, in-segment index `i`;
-// returns false if it did not fit
-__device__ __forceinline__ bool place(const Dev &d, int cur, bool f64, int seg, int64_t i,
-                                      unsigned long long id, bool split, int32_t cell, float f,
-                                      double x, double vx, double vy, double vz)
+// ---------------------------------------------------------------------------
+// the event list of this step: per-block regions indexed by an LDS prefix sum
+// ---------------------------------------------------------------------------
+struct EventIndex {
+    uint32_t pre[kMaxPushBlocks + 1];
+    uint32_t in_regions, total;
+};
+
+// builds the prefix over the regions (all threads; barriers inside)
+__device__ void build_event_index(EventIndex &X, const Dev &d)
+{
+    const int nb = d.n_push_blocks;
+    constexpr int kPerT = (kMaxPushBlocks + kBlock - 1) / kBlock;
+    uint32_t v[kPerT];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int r = 0; r < kPerT; ++r) {
+        const int b = threadIdx.x * kPerT + r;
+        v[r] = (b < nb) ? d.ev_n[b] : 0u;
+        sum += v[r];
+    }
+    __shared__ uint32_t s_w[kWaves];
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    uint32_t inc = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += t;
+    }
+    if (lane == 63) s_w[wave] = inc;
+    __syncthreads();
+    uint32_t run = inc - sum;
+    for (int w = 0; w < wave; ++w) run += s_w[w];
+#pragma unroll
+    for (int r = 0; r < kPerT; ++r) {
+        const int b = threadIdx.x * kPerT + r;
+        if (b <= nb) X.pre[b] = run;
+        run += v[r];
+    }
+    if (threadIdx.x == kBlock - 1) {
+        uint32_t ovf = d.glob->ev_ovf;
+        if (ovf > (uint32_t)d.ev_ovf_cap) ovf = (uint32_t)d.ev_ovf_cap;
+        X.in_regions = run;
+        X.total = run + ovf;
+        if (nb == kMaxPushBlocks) X.pre[nb] = run;
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ const IzEvent &event_at(const EventIndex &X, const Dev &d, uint32_t e)
+{
+    if (e >= X.in_regions)
+        return d.ev[(int64_t)d.n_push_blocks * kEvQ + (e - X.in_regions)];
+    int lo = 0, hi = d.n_push_blocks - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (X.pre[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    return d.ev[(int64_t)lo * kEvQ + (e - X.pre[lo])];
+}
+
+// write one created particle into segment `seg`, in-segment index `i`
+// (ignored, and flagged, when the segment is full)
+__device__ __forceinline__ void place(const Dev &d, int cur, bool f64, int seg, int64_t i,
+                                      unsigned long long id, int32_t cell, float f, double x,
+                                      double vx, double vy, double vz)
 {
     const SegConst &sc = d.segc[seg];
     if (i >= (int64_t)sc.cap) {
         atomicOr(&d.instd[sc.inst].status, PIC_ST_CAPACITY);
-        return false;
+        return;
     }
     const int64_t g = sc.base + i;
     unsigned long long *S = d.S + sc.sp * d.G + sc.gnode;
@@ -147,7 +249,6 @@ __device__ __forceinline__ bool place(const Dev &d, int cur, bool f64, int seg, 
         j = (int)jn;
         w1 = (unsigned long long)rint(ldexp(x - jn, PIC_FRAC_BITS));
     } else {
-        (void)split;
         ((float *)d.x[cur])[g] = f;
         d.cell[cur][g] = cell;
         j = cell;
@@ -157,20 +258,39 @@ __device__ __forceinline__ bool place(const Dev &d, int cur, bool f64, int seg, 
     st_v(d.vy[cur], g, vy, f64);
     st_v(d.vz[cur], g, vz, f64);
     d.id[cur][g] = id;
-    atomicAdd(S + j, (1ull << PIC_FRAC_BITS) - w1);
-    atomicAdd(S + j + 1, w1);
-    atomicAdd(&d.segd[seg].created_step, 1u);
-    return true;
+    if ((1ull << PIC_FRAC_BITS) - w1) atomicAdd(S + j, (1ull << PIC_FRAC_BITS) - w1);
+    if (w1) atomicAdd(S + j + 1, w1);
 }
 
 constexpr int kMaxInstLds = 4096;
 
+// per-instance ionisation counts of this step (into LDS)
+__device__ void count_events(const EventIndex &X, const Dev &d, uint32_t *s_m, int n_inst)
+{
+    for (int i = threadIdx.x; i < n_inst; i += kBlock) s_m[i] = 0u;
+    __syncthreads();
+    for (uint32_t e = threadIdx.x; e < X.total; e += kBlock) {
+        const int inst = event_at(X, d, e).inst;
+        if (inst < n_inst) atomicAdd(&s_m[inst], 1u);
+    }
+    __syncthreads();
+}
+
+// ions lost to the walls this step = source pairs of the instance
+__device__ __forceinline__ uint32_t source_pairs(const Dev &d, int i)
+{
+    const InstConst &ic = d.instc[i];
+    if (!ic.source_on || ic.seg_i < 0) return 0u;
+    return d.segd[ic.seg_i].absorbed_step[0] + d.segd[ic.seg_i].absorbed_step[1];
+}
+
 __global__ __launch_bounds__(kBlock) void emit_kernel(Dev d)
 {
+    __shared__ EventIndex X;
+    build_event_index(X, d);
     const int cur = d.glob->cur_set;
     const bool f64 = (d.precision == PIC_FP64);
-    uint32_t m_all = d.glob->ev_count;
-    if (m_all > (uint32_t)d.ev_cap) m_all = (uint32_t)d.ev_cap;
+    const uint32_t m_all = X.total;
     const uint32_t stride = gridDim.x * kBlock;
 
     // ---- ionisation pairs: rank each event among its instance's events by parent id
@@ -180,35 +300,32 @@ __global__ __launch_bounds__(kBlock) void emit_kernel(Dev d)
         const uint32_t e = base + threadIdx.x;
         const bool own = e < m_all;
         IzEvent ev = {};
-        int my_inst = -1;
-        if (own) {
-            ev = d.ev[e];
-            my_inst = d.segc[ev.seg].inst;
-        }
+        if (own) ev = event_at(X, d, e);
         uint32_t rank = 0;
         for (uint32_t cb = 0; cb < m_all; cb += kBlock) {
             __syncthreads();
             const uint32_t k = cb + threadIdx.x;
             if (k < m_all) {
-                const IzEvent o = d.ev[k];
+                const IzEvent &o = event_at(X, d, k);
                 s_pid[threadIdx.x] = o.parent_id;
-                s_inst[threadIdx.x] = d.segc[o.seg].inst;
+                s_inst[threadIdx.x] = o.inst;
             } else {
                 s_pid[threadIdx.x] = ~0ull;
                 s_inst[threadIdx.x] = -2;
             }
             __syncthreads();
             if (own) {
-                const int lim = (m_all - cb < (uint32_t)kBlock) ? (int)(m_all - cb) : kBlock;
-                for (int q = 0; q < lim; ++q)
-                    rank += (s_inst[q] == my_inst && s_pid[q] < ev.parent_id) ? 1u : 0u;
+                // unrolled so that many LDS reads are in flight at once
+#pragma unroll 32
+                for (int q = 0; q < kBlock; ++q)
+                    rank += (s_inst[q] == ev.inst && s_pid[q] < ev.parent_id) ? 1u : 0u;
             }
         }
         if (own) {
             const SegConst &se = d.segc[ev.seg];
             const int seg_i = se.partner;
             const SegConst &si = d.segc[seg_i];
-            const InstDyn &idn = d.instd[se.inst];
+            const InstDyn &idn = d.instd[ev.inst];
             const long long step = idn.step;
             const unsigned long long nid = idn.next_id + 2ull * rank;
             const uint4 u1 = draw(ev.parent_id, step, 1, se.key0, se.key1);
@@ -227,24 +344,24 @@ __global__ __launch_bounds__(kBlock) void emit_kernel(Dev d)
                 cell = d.cell[cur][ev.slot];
                 f = ((const float *)d.x[cur])[ev.slot];
             }
-            place(d, cur, f64, ev.seg, (int64_t)d.segd[ev.seg].count + rank, nid, false, cell, f, x,
+            place(d, cur, f64, ev.seg, (int64_t)d.segd[ev.seg].count + rank, nid, cell, f, x,
                   ev.g2 * d0, ev.g2 * d1, ev.g2 * d2);
-            place(d, cur, f64, seg_i, (int64_t)d.segd[seg_i].count + rank, nid + 1ull, false, cell,
-                  f, x, si.sig_n * n0, si.sig_n * n1, si.sig_n * n2);
+            place(d, cur, f64, seg_i, (int64_t)d.segd[seg_i].count + rank, nid + 1ull, cell, f, x,
+                  si.sig_n * n0, si.sig_n * n1, si.sig_n * n2);
         }
     }
 
     // ---- source pairs: instance i creates as many pairs as ions it lost this step
     __shared__ uint32_t s_pre[kMaxInstLds + 1];
+    __shared__ uint32_t s_m[kMaxInstLds];
     const int n_inst = d.n_inst < kMaxInstLds ? d.n_inst : kMaxInstLds;
     __syncthreads();
+    count_events(X, d, s_m, n_inst);
     if (threadIdx.x == 0) {
         uint32_t acc = 0;
         for (int i = 0; i < n_inst; ++i) {
             s_pre[i] = acc;
-            const InstConst &ic = d.instc[i];
-            if (ic.source_on && ic.seg_i >= 0)
-                acc += d.segd[ic.seg_i].absorbed_step[0] + d.segd[ic.seg_i].absorbed_step[1];
+            acc += source_pairs(d, i);
         }
         s_pre[n_inst] = acc;
     }
@@ -263,7 +380,7 @@ __global__ __launch_bounds__(kBlock) void emit_kernel(Dev d)
         const SegConst &se = d.segc[ic.seg_e];
         const SegConst &si = d.segc[ic.seg_i];
         const long long step = idn.step;
-        const uint32_t m_i = idn.n_iz_step;
+        const uint32_t m_i = s_m[i];
         const uint4 b0 = draw_source(k, step, 0, se.key0, se.key1);
         const uint4 b1 = draw_source(k, step, 1, se.key0, se.key1);
         const uint4 b2 = draw_source(k, step, 2, se.key0, se.key1);
@@ -277,27 +394,31 @@ __global__ __launch_bounds__(kBlock) void emit_kernel(Dev d)
         float f = 0.f;
         if (!f64) split_position(x, ic.nc, cell, f);
         const unsigned long long nid = idn.next_id + 2ull * (m_i + k);
-        place(d, cur, f64, ic.seg_e, (int64_t)d.segd[ic.seg_e].count + m_i + k, nid, true, cell, f,
-              x, se.sig_src * e0, se.sig_src * e1, se.sig_src * e2);
-        place(d, cur, f64, ic.seg_i, (int64_t)d.segd[ic.seg_i].count + m_i + k, nid + 1ull, true,
-              cell, f, x, si.sig_src * i0, si.sig_src * i1, si.sig_src * i2);
+        place(d, cur, f64, ic.seg_e, (int64_t)d.segd[ic.seg_e].count + m_i + k, nid, cell, f, x,
+              se.sig_src * e0, se.sig_src * e1, se.sig_src * e2);
+        place(d, cur, f64, ic.seg_i, (int64_t)d.segd[ic.seg_i].count + m_i + k, nid + 1ull, cell,
+              f, x, si.sig_src * i0, si.sig_src * i1, si.sig_src * i2);
     }
+}
 
-    // ---- close of the step, by the last block to finish
-    __shared__ bool s_last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) s_last = (atomicAdd(&d.glob->emit_done, 1u) == gridDim.x - 1);
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
+// close of the step (one block): counts, ids, wall-loss totals, step index
+__global__ __launch_bounds__(kBlock) void close_step_kernel(Dev d, int with_events)
+{
+    __shared__ EventIndex X;
+    __shared__ uint32_t s_m[kMaxInstLds];
+    const int n_inst = d.n_inst < kMaxInstLds ? d.n_inst : kMaxInstLds;
+    if (with_events) {
+        build_event_index(X, d);
+        count_events(X, d, s_m, n_inst);
+    } else {
+        for (int i = threadIdx.x; i < n_inst; i += kBlock) s_m[i] = 0u;
+        __syncthreads();
+    }
     for (int i = threadIdx.x; i < d.n_inst; i += kBlock) {
         const InstConst &ic = d.instc[i];
         InstDyn *idn = d.instd + i;
-        uint32_t n_src = 0;
-        if (ic.source_on && ic.seg_i >= 0)
-            n_src = d.segd[ic.seg_i].absorbed_step[0] + d.segd[ic.seg_i].absorbed_step[1];
-        const uint32_t m_i = idn->n_iz_step;
+        const uint32_t n_src = source_pairs(d, i);
+        const uint32_t m_i = i < n_inst ? s_m[i] : 0u;
         unsigned long long pushed = 0;
         for (int k = 0; k < ic.nsp; ++k) {
             const int s = ic.seg0 + k;
@@ -306,41 +427,48 @@ __global__ __launch_bounds__(kBlock) void emit_kernel(Dev d)
             pushed += sd->live;
             uint32_t requested = 0;
             if (s == ic.seg_e || s == ic.seg_i) requested = m_i + n_src;
-            uint64_t nc_ = (uint64_t)sd->count + requested;
-            if (nc_ > sc.cap) nc_ = sc.cap;
-            const uint32_t created = sd->created_step;
+            uint64_t n_new = (uint64_t)sd->count + requested;
+            if (n_new > sc.cap) n_new = sc.cap;
+            // created = the slots below capacity that were filled
+            const uint32_t created = (uint32_t)(n_new - sd->count);
             const uint32_t lost = sd->absorbed_step[0] + sd->absorbed_step[1];
-            sd->count = (uint32_t)nc_;
+            sd->count = (uint32_t)n_new;
             sd->live = sd->live - lost + created;
             sd->absorbed_total[0] += sd->absorbed_step[0];
             sd->absorbed_total[1] += sd->absorbed_step[1];
             sd->created_total += created;
             sd->absorbed_step[0] = 0;
             sd->absorbed_step[1] = 0;
-            sd->created_step = 0;
         }
         idn->particle_steps += pushed;
         idn->next_id += 2ull * (unsigned long long)(m_i + n_src);
         idn->n_source += n_src;
-        idn->n_iz_step = 0;
         idn->step += 1;
     }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        d.glob->cand_count = 0;
-        d.glob->ev_count = 0;
-        d.glob->emit_done = 0;
+        d.glob->cand_ovf = 0;
+        d.glob->ev_ovf = 0;
     }
+    // empty event regions for a step without collisions
+    if (!with_events)
+        for (int b = threadIdx.x; b < d.n_push_blocks; b += kBlock) d.ev_n[b] = 0u;
 }
 
 hipError_t launch_collide(const Dev &d, hipStream_t st)
 {
-    hipLaunchKernelGGL(collide_kernel, dim3(kCollideBlocks), dim3(kBlock), 0, st, d);
+    hipLaunchKernelGGL(collide_kernel, dim3(d.n_push_blocks), dim3(kBlock), 0, st, d);
     return hipGetLastError();
 }
 
-hipError_t launch_emit(const Dev &d, hipStream_t st)
+hipError_t launch_emit(const Dev &d, hipStream_t st, bool pairs, bool events)
 {
-    hipLaunchKernelGGL(emit_kernel, dim3(kEmitBlocks), dim3(kBlock), 0, st, d);
+    if (pairs) {
+        hipLaunchKernelGGL(emit_kernel, dim3(kEmitBlocks), dim3(kBlock), 0, st, d);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(close_step_kernel, dim3(1), dim3(kBlock), 0, st, d, events ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -16,14 +16,18 @@ constexpr int kBlock = 256;                 // threads per block of the particle
 constexpr int kWaves = kBlock / 64;         // wave64 per block
 constexpr int kPer = 4;                     // 64-particle chunks per wave per tile
 constexpr int kTile = kBlock * kPer;        // particles per tile (contiguous)
-constexpr int kFieldR = 8;                  // nodes per thread in the field scans
+constexpr int kFieldR = 16;                 // nodes per thread in the field scans
 constexpr int kFieldTile = kBlock * kFieldR;
 constexpr int kSortR = 8;                   // bins per thread in the sort scan
 constexpr int kSortTile = kBlock * kSortR;
 constexpr int kDiagBlocks = 1024;           // blocks of the diagnostics reduction
 constexpr int kEmitBlocks = 64;             // blocks of the emit/close-of-step kernel
-constexpr int kCollideBlocks = 1024;        // grid of the collide kernel (grid-stride)
 constexpr int kDiagVals = 6;                // live, sum v2, sum vx, vy, vz, (pad)
+constexpr int kMaxPushBlocks = 256 * 8;     // persistent grid of the particle kernels
+constexpr int kCandQ = 2048;                // candidate slots per push block (LDS queue)
+constexpr int kEvQ = 32;                    // ionisation-event slots per collide block
+constexpr int kCntSeg = 64;                 // segments counted per block without atomics
+constexpr int kNCnt = 5;                    // candidates, elastic, ionisation, CX, over v_cap
 
 constexpr int32_t kDeadCell = -1;           // FP32 form: cell of an absorbed particle
 constexpr double kDeadX = -1.0;             // FP64 form: position of an absorbed particle
@@ -79,18 +83,18 @@ struct InstDyn {
     long long step;
     unsigned long long next_id;
     uint32_t status;
-    uint32_t n_iz_step;      // ionisation events this step
-    unsigned long long n_candidates, n_elastic, n_ionize, n_cx, n_over_cap, n_source;
+    uint32_t _pad;
+    // process counts of batches with more than kCntSeg segments (otherwise per-block slots)
+    unsigned long long n_candidates, n_elastic, n_ionize, n_cx, n_over_cap;
+    unsigned long long n_source;
     unsigned long long particle_steps;
 };
 
 struct Globals {
     int32_t cur_set;
-    uint32_t cand_count;
-    uint32_t ev_count;
-    uint32_t emit_done;
-    uint32_t scatter_done;
-    uint32_t pad[3];
+    uint32_t cand_ovf;       // candidates in the overflow list this step
+    uint32_t ev_ovf;         // ionisation events in the overflow list this step
+    uint32_t pad[5];
     // self-resetting single-pass scans: ticket counter, finish counter, generation
     uint32_t scan_ticket[4];
     uint32_t scan_finish[4];
@@ -104,6 +108,8 @@ struct IzEvent {
     unsigned long long parent_id;
     uint32_t slot;          // parent slot (global)
     int32_t seg;            // parent segment
+    int32_t inst;           // parent instance
+    int32_t _pad;
     double g2;              // speed of the secondary electron, cells/step
 };
 
@@ -124,10 +130,10 @@ struct Layout {
     uint64_t hist, cursor, offsets, seg_start;
     uint64_t fwd_status, bwd_status, sort_status;
     uint64_t fe_part;
-    uint64_t cand, ev;
+    uint64_t cand, cand_n, ev, ev_n, cnt_slot;
     uint64_t diag_part, diag_out;
     uint64_t total;
-    int64_t cand_cap, ev_cap;
+    int64_t cand_ovf_cap, ev_ovf_cap;
     int64_t n_field_tiles, n_sort_tiles;
 };
 
@@ -158,14 +164,18 @@ struct Dev {
     AffineStatus *fwd_status, *bwd_status;
     unsigned long long *sort_status;
     double *fe_part;
-    uint32_t *cand;
-    IzEvent *ev;
+    uint32_t *cand;             // [n_push_blocks][kCandQ] per-block regions, then the overflow list
+    uint32_t *cand_n;           // [n_push_blocks] candidates in each region
+    IzEvent *ev;                // [n_push_blocks][kEvQ] per-block regions, then the overflow list
+    uint32_t *ev_n;             // [n_push_blocks] events in each region
+    unsigned long long *cnt_slot;  // [n_push_blocks][kCntSeg][kNCnt] process counts per block
     double *diag_part;
     pic_diag *diag_out;
     // sizes
-    int64_t n_slots, n_tiles, G, cand_cap, ev_cap;
+    int64_t n_slots, n_tiles, G, cand_ovf_cap, ev_ovf_cap;
     int64_t n_field_tiles, n_sort_tiles;
     int32_t n_seg, n_inst, nsp, precision;
+    int32_t n_push_blocks, _pad;
 };
 
 // ---------------------------------------------------------------------------
@@ -176,7 +186,9 @@ hipError_t launch_push(const Dev &d, hipStream_t st, bool deposit, bool mcc);
 hipError_t launch_deposit(const Dev &d, hipStream_t st);
 hipError_t launch_field(const Dev &d, hipStream_t st);
 hipError_t launch_collide(const Dev &d, hipStream_t st);
-hipError_t launch_emit(const Dev &d, hipStream_t st);
+// ionisation and source pairs (when `pairs`), then the close of the step
+// (`events`: collisions ran this step)
+hipError_t launch_emit(const Dev &d, hipStream_t st, bool pairs, bool events);
 hipError_t launch_sort(const Dev &d, hipStream_t st);
 hipError_t launch_diag(const Dev &d, hipStream_t st);
 

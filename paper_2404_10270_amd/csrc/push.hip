@@ -6,35 +6,193 @@
 // absorbing or periodic walls, the null-collision candidate test (one Philox
 // block keyed by id and step), and the deposit of the new position.
 //
-// Layout: structure-of-arrays streamed once.  A block owns a tile of
-// kTile consecutive slots of one segment; each wave takes kPer chunks of 64
-// consecutive slots, so every load and store is a 256-byte (FP32) or
-// 512-byte (FP64) coalesced access.  Cell-sorted neighbours deposit into the
-// same nodes, so each chunk first sums its weights over runs of equal cells
-// (wave-level segmented reduction) and only run tails issue the two 64-bit
-// atomics.
+// Memory plan (HBM-bound):
+//  * structure-of-arrays streamed once; a block owns a tile of kTile
+//    consecutive slots of one segment and every wave issues the loads of all
+//    its kPer 64-slot chunks before computing, so each wave keeps
+//    kPer x (4 + 4 + 12 + 8) bytes x 64 lanes in flight;
+//  * segment tables and counts are staged in LDS once per launch, so no
+//    global load sits on the critical path between tiles;
+//  * the deposit of cell-sorted neighbours is summed first over runs of equal
+//    cells inside each wave, then into an LDS window of nodes, and the window
+//    is flushed with one 64-bit global atomic per touched node per tile;
+//  * collision candidates go to an LDS queue that each block writes to its
+//    own region of the candidate list at the end (no atomics); only a block
+//    with more than kCandQ candidates appends the excess to a shared
+//    overflow list.
 #include "device_common.h"
 
 #pragma clang fp contract(off)
 
 namespace picx {
 
-// deposit a chunk: lanes with key >= 0 add W1 = rint(f 2^32) to node key+1 and
-// 2^32 - W1 to node key (linear weights, every particle adds exactly 2^32)
-__device__ __forceinline__ void deposit_chunk(unsigned long long *__restrict__ S, int key,
-                                              unsigned long long w1)
+constexpr int kDepWin = 1024;     // LDS deposit window, nodes
+constexpr int kSegLds = 256;      // segments whose tables are staged in LDS
+
+struct PushLds {
+    unsigned long long dep[kDepWin];
+    uint32_t cq[kCandQ];
+    int64_t tile0[kSegLds + 1];
+    int64_t base[kSegLds];
+    uint32_t count[kSegLds];
+    uint32_t cn;
+    uint32_t gbase;
+    int red[2][kWaves];
+};
+
+__device__ __forceinline__ void push_lds_init(PushLds &L, const Dev &d)
 {
-    // pack (count, sum W1): W1 <= 2^32 and at most 64 lanes -> sum < 2^39
-    const unsigned long long v = (key >= 0) ? ((1ull << 40) + w1) : 0ull;
-    bool tail;
-    const unsigned long long t = run_sum(key, v, tail);
-    if (tail && key >= 0) {
-        const unsigned long long n = t >> 40;
-        const unsigned long long b = t & ((1ull << 40) - 1ull);
-        const unsigned long long a = (n << PIC_FRAC_BITS) - b;
-        if (a) atomicAdd(S + key, a);
-        if (b) atomicAdd(S + key + 1, b);
+    for (int i = threadIdx.x; i < kDepWin; i += kBlock) L.dep[i] = 0ull;
+    if (d.n_seg <= kSegLds) {
+        for (int s = threadIdx.x; s <= d.n_seg; s += kBlock) {
+            L.tile0[s] = d.seg_tile0[s];
+            if (s < d.n_seg) {
+                L.base[s] = d.seg_base[s];
+                L.count[s] = d.segd[s].count;
+            }
+        }
     }
+    if (threadIdx.x == 0) L.cn = 0;
+    __syncthreads();
+}
+
+// (segment, first slot, occupied slots) of virtual tile t
+__device__ __forceinline__ int tile_seg(const PushLds &L, const Dev &d, int64_t t, int64_t &tile0,
+                                        int64_t &base, int64_t &count)
+{
+    int seg;
+    if (d.n_seg <= kSegLds) {
+        int lo = 0, hi = d.n_seg - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (L.tile0[mid] <= t) lo = mid; else hi = mid - 1;
+        }
+        seg = lo;
+        tile0 = L.tile0[seg];
+        base = L.base[seg];
+        count = L.count[seg];
+    } else {
+        seg = seg_of_tile(d.seg_tile0, d.n_seg, t);
+        tile0 = d.seg_tile0[seg];
+        base = d.seg_base[seg];
+        count = d.segd[seg].count;
+    }
+    return seg;
+}
+
+__device__ __forceinline__ int wave_min(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ int wave_max(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Deposit the kPer chunks of this wave (keys = cells, -1 = none) through the
+// block's LDS window.  Contains two block barriers; every thread must call it.
+template <int NP>
+__device__ __forceinline__ void deposit_tile(PushLds &L, unsigned long long *__restrict__ S,
+                                             const int (&key)[NP], const unsigned long long (&w1)[NP])
+{
+    const int lane = lane_id();
+    const int wave = threadIdx.x >> 6;
+    int kmn = 0x7fffffff, kmx = -1;
+#pragma unroll
+    for (int k = 0; k < NP; ++k)
+        if (key[k] >= 0) {
+            kmn = min(kmn, key[k]);
+            kmx = max(kmx, key[k]);
+        }
+    kmn = wave_min(kmn);
+    kmx = wave_max(kmx);
+    if (lane == 0) {
+        L.red[0][wave] = kmn;
+        L.red[1][wave] = kmx;
+    }
+    __syncthreads();
+    int lo = L.red[0][0], hi = L.red[1][0];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) {
+        lo = min(lo, L.red[0][w]);
+        hi = max(hi, L.red[1][w]);
+    }
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        // pack (count, sum W1): W1 <= 2^32 and at most 64 lanes -> sum < 2^39
+        const unsigned long long v = (key[k] >= 0) ? ((1ull << 40) + w1[k]) : 0ull;
+        bool tail;
+        const unsigned long long t = run_sum(key[k], v, tail);
+        if (tail && key[k] >= 0) {
+            const unsigned long long n = t >> 40;
+            const unsigned long long b = t & ((1ull << 40) - 1ull);
+            const unsigned long long a = (n << PIC_FRAC_BITS) - b;
+            const int rel = key[k] - lo;
+            if (rel + 1 < kDepWin) {
+                atomicAdd(&L.dep[rel], a);
+                atomicAdd(&L.dep[rel + 1], b);
+            } else {
+                atomicAdd(S + key[k], a);
+                atomicAdd(S + key[k] + 1, b);
+            }
+        }
+    }
+    __syncthreads();
+    if (hi >= 0) {
+        const int span = min(hi - lo + 2, kDepWin);
+        for (int i = threadIdx.x; i < span; i += kBlock) {
+            const unsigned long long v = L.dep[i];
+            if (v) {
+                atomicAdd(S + lo + i, v);
+                L.dep[i] = 0ull;
+            }
+        }
+    }
+    // the next use of the window is ordered by the next call's first barrier
+}
+
+// Candidates go to the block's LDS queue while it has room; a wave whose
+// candidates do not fit appends the excess to the shared overflow list.
+__device__ __forceinline__ void queue_candidate(PushLds &L, const Dev &d, bool cand, uint32_t g,
+                                                int inst)
+{
+    const unsigned long long m = ballot(cand);
+    if (!m) return;
+    const int lane = lane_id();
+    const int leader = __ffsll((long long)m) - 1;
+    const uint32_t n = (uint32_t)__popcll(m);
+    const uint32_t rank = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(&L.cn, n);
+    base = __shfl(base, leader, 64);
+    // the first n_lds candidates fill the rest of the queue, the others overflow
+    const uint32_t room = base < (uint32_t)kCandQ ? (uint32_t)kCandQ - base : 0u;
+    const uint32_t n_lds = n < room ? n : room;
+    if (cand && rank < n_lds) L.cq[base + rank] = g;
+    if (n_lds == n) return;
+    uint32_t gb = 0;
+    if (lane == leader) gb = atomicAdd(&d.glob->cand_ovf, n - n_lds);
+    gb = __shfl(gb, leader, 64);
+    if (cand && rank >= n_lds) {
+        const uint32_t idx = gb + (rank - n_lds);
+        if (idx < (uint32_t)d.cand_ovf_cap) d.cand[(int64_t)d.n_push_blocks * kCandQ + idx] = g;
+        else atomicOr(&d.instd[inst].status, PIC_ST_CANDIDATES);
+    }
+}
+
+// write the LDS queue to this block's region of the candidate list
+__device__ __forceinline__ void flush_candidates(PushLds &L, const Dev &d)
+{
+    __syncthreads();
+    const uint32_t n = min(L.cn, (uint32_t)kCandQ);
+    uint32_t *dst = d.cand + (int64_t)blockIdx.x * kCandQ;
+    for (uint32_t i = threadIdx.x; i < n; i += kBlock) dst[i] = L.cq[i];
+    if (threadIdx.x == 0) d.cand_n[blockIdx.x] = n;
 }
 
 // ---------------------------------------------------------------------------
@@ -43,6 +201,8 @@ __device__ __forceinline__ void deposit_chunk(unsigned long long *__restrict__ S
 template <bool DEP, bool MCC>
 __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
 {
+    __shared__ PushLds L;
+    push_lds_init(L, d);
     const int cur = d.glob->cur_set;
     float *__restrict__ X = (float *)d.x[cur];
     int32_t *__restrict__ CELL = d.cell[cur];
@@ -54,113 +214,161 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
     const int wave = threadIdx.x >> 6;
 
     for (int64_t t = blockIdx.x; t < d.n_tiles; t += gridDim.x) {
-        const int seg = seg_of_tile(d.seg_tile0, d.n_seg, t);
-        const SegConst &sc = d.segc[seg];
-        const int64_t count = d.segd[seg].count;
-        const int64_t t0 = (t - sc.tile0) * (int64_t)kTile;
+        int64_t tile0, base, count;
+        const int seg = tile_seg(L, d, t, tile0, base, count);
+        const int64_t t0 = (t - tile0) * (int64_t)kTile;
         if (t0 >= count) continue;
+
+        // ---- loads of all chunks
+        int32_t j[kPer];
+        float f[kPer], vx[kPer], vy[kPer], vz[kPer];
+        unsigned long long pid[kPer];
+        bool lv[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int64_t i = t0 + (int64_t)(wave * kPer + k) * 64 + lane;
+            const int64_t g = base + i;
+            j[k] = kDeadCell;
+            f[k] = vx[k] = vy[k] = vz[k] = 0.f;
+            pid[k] = 0;
+            if (i < count) {
+                j[k] = CELL[g];
+                f[k] = X[g];
+                vx[k] = VX[g];
+                vy[k] = VY[g];
+                vz[k] = VZ[g];
+                if (MCC) pid[k] = ID[g];
+            }
+            lv[k] = j[k] >= 0;
+        }
+        // ---- segment constants
+        const SegConst &sc = d.segc[seg];
         const float *__restrict__ acc = d.acc32 + sc.sp * d.G + sc.gnode;
         unsigned long long *__restrict__ S = d.S + sc.sp * d.G + sc.gnode;
         const int nc = sc.nc;
         const bool periodic = (sc.bc == PIC_BC_PERIODIC);
         const float tx = sc.txf, ty = sc.tyf, sx = sc.sxf, sy = sc.syf;
+        const uint32_t key0 = sc.key0, key1 = sc.key1;
+        const unsigned long long T = sc.T;
+        const int inst = sc.inst;
         long long step = 0;
-        unsigned long long T = 0;
-        if (MCC) {
-            step = d.instd[sc.inst].step;
-            T = sc.T;
+        if (MCC) step = d.instd[inst].step;
+        // ---- gather
+        float a0[kPer], a1[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            a0[k] = a1[k] = 0.f;
+            if (j[k] >= 0) {
+                a0[k] = acc[j[k]];
+                a1[k] = acc[j[k] + 1];
+            }
         }
-        SegDyn *sd = d.segd + seg;
-        InstDyn *idn = d.instd + sc.inst;
-
+        // ---- push, walls, candidate test
+        int key[kPer];
+        unsigned long long w1[kPer];
+        bool cand[kPer];
+        bool left = false, right = false, cfl = false, bad = false;
+        int n_left = 0, n_right = 0;
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            key[k] = -1;
+            w1[k] = 0;
+            cand[k] = false;
+            if (j[k] < 0) continue;
+            const float a = fmaf(f[k], a1[k] - a0[k], a0[k]);
+            const float h = 0.5f * a;
+            const float mx = vx[k] + h, my = vy[k], mz = vz[k];
+            const float px = mx - mz * ty;
+            const float py = my + mz * tx;
+            const float pz = mz + (mx * ty - my * tx);
+            const float qx = mx - pz * sy;
+            const float qy = my + pz * sx;
+            const float qz = mz + (px * sy - py * sx);
+            const float nvx = qx + h, nvy = qy, nvz = qz;
+            // advance in cell-relative coordinates; |fl| is clamped so that a
+            // runaway (flagged) particle still maps to a valid integer cell
+            float fn = f[k] + nvx;
+            const float fl = fminf(fmaxf(floorf(fn), -16777216.0f), 16777216.0f);
+            fn = fn - fl;
+            int32_t jn = j[k] + (int32_t)fl;
+            if (fn >= 1.0f) { fn = 0.0f; jn += 1; }
+            cfl |= !(fabsf(nvx) < 1.0f);
+            const bool bk = !isfinite(nvx) || !isfinite(nvy) || !isfinite(nvz);
+            bad |= bk;
+            if (bk) jn = j[k], fn = f[k];  // keep the slot well-formed; the run is flagged
+            bool l = false, r = false;
+            if (periodic) {
+                if (jn < 0) jn += nc;
+                else if (jn >= nc) jn -= nc;
+                if (jn < 0 || jn >= nc) {
+                    jn %= nc;
+                    if (jn < 0) jn += nc;
+                }
+            } else if (jn < 0) {
+                l = true;
+            } else if (jn >= nc) {
+                r = true;
+            }
+            n_left += l;
+            n_right += r;
+            j[k] = (l || r) ? kDeadCell : jn;
+            f[k] = fn;
+            vx[k] = nvx;
+            vy[k] = nvy;
+            vz[k] = nvz;
+            if (j[k] >= 0) {
+                key[k] = j[k];
+                w1[k] = (unsigned long long)rintf(fn * 4294967296.0f);
+                if (MCC) {
+                    const uint4 u = draw(pid[k], step, 0, key0, key1);
+                    cand[k] = (unsigned long long)u.x < T;
+                }
+            }
+        }
+        // ---- stores (no reads after this point in the tile touch these arrays)
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
             const int64_t i = t0 + (int64_t)(wave * kPer + k) * 64 + lane;
-            const bool valid = i < count;
-            const int64_t g = sc.base + i;
-            int32_t j = kDeadCell;
-            if (valid) j = CELL[g];
-            const bool live = valid && j >= 0;
-            float f = 0.f, vx = 0.f, vy = 0.f, vz = 0.f;
-            unsigned long long pid = 0;
-            if (live) {
-                f = X[g];
-                vx = VX[g];
-                vy = VY[g];
-                vz = VZ[g];
-                if (MCC) pid = ID[g];
+            if (i < count && lv[k]) {
+                const int64_t g = base + i;
+                X[g] = f[k];
+                CELL[g] = j[k];
+                VX[g] = vx[k];
+                VY[g] = vy[k];
+                VZ[g] = vz[k];
             }
-            bool left = false, right = false, bad = false, cfl = false, cand = false;
-            int key = -1;
-            unsigned long long w1 = 0;
-            if (live) {
-                // gather: a = a[j] + f (a[j+1] - a[j])
-                const float a0 = acc[j], a1 = acc[j + 1];
-                const float a = fmaf(f, a1 - a0, a0);
-                const float h = 0.5f * a;
-                const float mx = vx + h, my = vy, mz = vz;
-                const float px = mx - mz * ty;
-                const float py = my + mz * tx;
-                const float pz = mz + (mx * ty - my * tx);
-                const float qx = mx - pz * sy;
-                const float qy = my + pz * sx;
-                const float qz = mz + (px * sy - py * sx);
-                vx = qx + h;
-                vy = qy;
-                vz = qz;
-                // advance in cell-relative coordinates
-                float fn = f + vx;
-                // |fl| is clamped so that a runaway (flagged) particle still maps to a
-                // valid integer cell
-                const float fl = fminf(fmaxf(floorf(fn), -16777216.0f), 16777216.0f);
-                fn = fn - fl;
-                int32_t jn = j + (int32_t)fl;
-                if (fn >= 1.0f) { fn = 0.0f; jn += 1; }
-                cfl = !(fabsf(vx) < 1.0f);
-                bad = !isfinite(vx) || !isfinite(vy) || !isfinite(vz);
-                if (bad) jn = j, fn = f;  // keep the slot well-formed; the run is flagged
-                if (periodic) {
-                    if (jn < 0) jn += nc;
-                    else if (jn >= nc) jn -= nc;
-                    if (jn < 0 || jn >= nc) {
-                        jn %= nc;
-                        if (jn < 0) jn += nc;
-                    }
-                } else if (jn < 0) {
-                    left = true;
-                } else if (jn >= nc) {
-                    right = true;
-                }
-                f = fn;
-                j = (left || right) ? kDeadCell : jn;
-                if (j >= 0) {
-                    key = j;
-                    w1 = (unsigned long long)rintf(f * 4294967296.0f);
-                    if (MCC) {
-                        const uint4 u = draw(pid, step, 0, sc.key0, sc.key1);
-                        cand = (unsigned long long)u.x < T;
-                    }
-                }
-                X[g] = f;
-                CELL[g] = j;
-                VX[g] = vx;
-                VY[g] = vy;
-                VZ[g] = vz;
+        }
+        // ---- rare events: wall losses, flags
+        left = n_left > 0;
+        right = n_right > 0;
+        if (ballot(left) | ballot(right) | ballot(cfl) | ballot(bad)) {
+            SegDyn *sd = d.segd + seg;
+            InstDyn *idn = d.instd + inst;
+            const unsigned long long ml = ballot(left), mr = ballot(right);
+            int sl = n_left, sr = n_right;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                sl += __shfl_xor(sl, o, 64);
+                sr += __shfl_xor(sr, o, 64);
             }
-            wave_count(&sd->absorbed_step[0], left);
-            wave_count(&sd->absorbed_step[1], right);
+            if (lane == 0) {
+                if (ml) atomicAdd(&sd->absorbed_step[0], (uint32_t)sl);
+                if (mr) atomicAdd(&sd->absorbed_step[1], (uint32_t)sr);
+            }
             wave_or(&idn->status, PIC_ST_CFL, cfl);
             wave_or(&idn->status, PIC_ST_NONFINITE, bad);
-            if (MCC) {
-                const uint32_t idx = wave_append(&d.glob->cand_count, cand);
-                if (cand) {
-                    if (idx < (uint32_t)d.cand_cap) d.cand[idx] = (uint32_t)g;
-                    else atomicOr(&idn->status, PIC_ST_CANDIDATES);
-                }
-            }
-            if (DEP) deposit_chunk(S, key, w1);
         }
+        // ---- candidates and deposit through LDS
+        if (MCC) {
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) {
+                const int64_t g = base + t0 + (int64_t)(wave * kPer + k) * 64 + lane;
+                queue_candidate(L, d, cand[k], (uint32_t)g, inst);
+            }
+        }
+        if (DEP) deposit_tile<kPer>(L, S, key, w1);
     }
+    if (MCC) flush_candidates(L, d);
 }
 
 // ---------------------------------------------------------------------------
@@ -170,6 +378,8 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
 template <bool DEP, bool MCC>
 __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
 {
+    __shared__ PushLds L;
+    push_lds_init(L, d);
     const int cur = d.glob->cur_set;
     double *__restrict__ X = (double *)d.x[cur];
     double *__restrict__ VX = (double *)d.vx[cur];
@@ -180,106 +390,147 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
     const int wave = threadIdx.x >> 6;
 
     for (int64_t t = blockIdx.x; t < d.n_tiles; t += gridDim.x) {
-        const int seg = seg_of_tile(d.seg_tile0, d.n_seg, t);
-        const SegConst &sc = d.segc[seg];
-        const int64_t count = d.segd[seg].count;
-        const int64_t t0 = (t - sc.tile0) * (int64_t)kTile;
+        int64_t tile0, base, count;
+        const int seg = tile_seg(L, d, t, tile0, base, count);
+        const int64_t t0 = (t - tile0) * (int64_t)kTile;
         if (t0 >= count) continue;
-        const double *__restrict__ acc = d.acc64 + sc.sp * d.G + sc.gnode;
-        unsigned long long *__restrict__ S = d.S + sc.sp * d.G + sc.gnode;
-        const double L = (double)sc.nc;
-        const bool periodic = (sc.bc == PIC_BC_PERIODIC);
-        const double tx = sc.tx, ty = sc.ty, sx = sc.sx, sy = sc.sy;
-        long long step = 0;
-        unsigned long long T = 0;
-        if (MCC) {
-            step = d.instd[sc.inst].step;
-            T = sc.T;
-        }
-        SegDyn *sd = d.segd + seg;
-        InstDyn *idn = d.instd + sc.inst;
 
+        double x[kPer], vx[kPer], vy[kPer], vz[kPer];
+        unsigned long long pid[kPer];
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
             const int64_t i = t0 + (int64_t)(wave * kPer + k) * 64 + lane;
-            const bool valid = i < count;
-            const int64_t g = sc.base + i;
-            double x = kDeadX;
-            if (valid) x = X[g];
-            const bool live = valid && x >= 0.0;
-            double vx = 0.0, vy = 0.0, vz = 0.0;
-            unsigned long long pid = 0;
-            if (live) {
-                vx = VX[g];
-                vy = VY[g];
-                vz = VZ[g];
-                if (MCC) pid = ID[g];
+            const int64_t g = base + i;
+            x[k] = kDeadX;
+            vx[k] = vy[k] = vz[k] = 0.0;
+            pid[k] = 0;
+            if (i < count) {
+                x[k] = X[g];
+                vx[k] = VX[g];
+                vy[k] = VY[g];
+                vz[k] = VZ[g];
+                if (MCC) pid[k] = ID[g];
             }
-            bool left = false, right = false, bad = false, cfl = false, cand = false;
-            int key = -1;
-            unsigned long long w1 = 0;
-            if (live) {
-                const double jd = floor(x);
-                const double f = x - jd;
-                const int32_t j = (int32_t)jd;
-                const double a = fma(f, acc[j + 1] - acc[j], acc[j]);
-                const double h = 0.5 * a;
-                const double mx = vx + h, my = vy, mz = vz;
-                const double px = mx - mz * ty;
-                const double py = my + mz * tx;
-                const double pz = mz + (mx * ty - my * tx);
-                const double qx = mx - pz * sy;
-                const double qy = my + pz * sx;
-                const double qz = mz + (px * sy - py * sx);
-                vx = qx + h;
-                vy = qy;
-                vz = qz;
-                double xn = x + vx;
-                cfl = !(fabs(vx) < 1.0);
-                bad = !isfinite(vx) || !isfinite(vy) || !isfinite(vz);
-                if (bad) xn = x;
-                if (periodic) {
-                    if (xn < 0.0) xn += L;
-                    else if (xn >= L) xn -= L;
-                    if (xn >= L) xn -= L;
-                    if (!(xn >= 0.0 && xn < L)) {  // displacement beyond one period (flagged)
-                        xn = xn - L * floor(xn / L);
-                        if (!(xn >= 0.0 && xn < L)) xn = 0.0;
-                    }
-                } else if (xn < 0.0) {
-                    left = true;
-                } else if (xn >= L) {
-                    right = true;
-                }
-                x = (left || right) ? kDeadX : xn;
-                if (x >= 0.0) {
-                    const double jn = floor(x);
-                    key = (int)jn;
-                    w1 = (unsigned long long)rint(ldexp(x - jn, PIC_FRAC_BITS));
-                    if (MCC) {
-                        const uint4 u = draw(pid, step, 0, sc.key0, sc.key1);
-                        cand = (unsigned long long)u.x < T;
-                    }
-                }
-                X[g] = x;
-                VX[g] = vx;
-                VY[g] = vy;
-                VZ[g] = vz;
+        }
+        const SegConst &sc = d.segc[seg];
+        const double *__restrict__ acc = d.acc64 + sc.sp * d.G + sc.gnode;
+        unsigned long long *__restrict__ S = d.S + sc.sp * d.G + sc.gnode;
+        const double L_ = (double)sc.nc;
+        const bool periodic = (sc.bc == PIC_BC_PERIODIC);
+        const double tx = sc.tx, ty = sc.ty, sx = sc.sx, sy = sc.sy;
+        const uint32_t key0 = sc.key0, key1 = sc.key1;
+        const unsigned long long T = sc.T;
+        const int inst = sc.inst;
+        long long step = 0;
+        if (MCC) step = d.instd[inst].step;
+        double a0[kPer], a1[kPer], fr[kPer];
+        bool live[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            live[k] = x[k] >= 0.0;
+            a0[k] = a1[k] = fr[k] = 0.0;
+            if (live[k]) {
+                const double jd = floor(x[k]);
+                const int32_t jj = (int32_t)jd;
+                fr[k] = x[k] - jd;
+                a0[k] = acc[jj];
+                a1[k] = acc[jj + 1];
             }
-            wave_count(&sd->absorbed_step[0], left);
-            wave_count(&sd->absorbed_step[1], right);
+        }
+        int key[kPer];
+        unsigned long long w1[kPer];
+        bool cand[kPer];
+        bool cfl = false, bad = false;
+        int n_left = 0, n_right = 0;
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            key[k] = -1;
+            w1[k] = 0;
+            cand[k] = false;
+            if (!live[k]) continue;
+            const double a = fma(fr[k], a1[k] - a0[k], a0[k]);
+            const double h = 0.5 * a;
+            const double mx = vx[k] + h, my = vy[k], mz = vz[k];
+            const double px = mx - mz * ty;
+            const double py = my + mz * tx;
+            const double pz = mz + (mx * ty - my * tx);
+            const double qx = mx - pz * sy;
+            const double qy = my + pz * sx;
+            const double qz = mz + (px * sy - py * sx);
+            vx[k] = qx + h;
+            vy[k] = qy;
+            vz[k] = qz;
+            double xn = x[k] + vx[k];
+            cfl |= !(fabs(vx[k]) < 1.0);
+            const bool bk = !isfinite(vx[k]) || !isfinite(vy[k]) || !isfinite(vz[k]);
+            bad |= bk;
+            if (bk) xn = x[k];
+            bool l = false, r = false;
+            if (periodic) {
+                if (xn < 0.0) xn += L_;
+                else if (xn >= L_) xn -= L_;
+                if (xn >= L_) xn -= L_;
+                if (!(xn >= 0.0 && xn < L_)) {  // displacement beyond one period (flagged)
+                    xn = xn - L_ * floor(xn / L_);
+                    if (!(xn >= 0.0 && xn < L_)) xn = 0.0;
+                }
+            } else if (xn < 0.0) {
+                l = true;
+            } else if (xn >= L_) {
+                r = true;
+            }
+            n_left += l;
+            n_right += r;
+            x[k] = (l || r) ? kDeadX : xn;
+            if (x[k] >= 0.0) {
+                const double jn = floor(x[k]);
+                key[k] = (int)jn;
+                w1[k] = (unsigned long long)rint(ldexp(x[k] - jn, PIC_FRAC_BITS));
+                if (MCC) {
+                    const uint4 u = draw(pid[k], step, 0, key0, key1);
+                    cand[k] = (unsigned long long)u.x < T;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int64_t i = t0 + (int64_t)(wave * kPer + k) * 64 + lane;
+            if (i < count && live[k]) {
+                const int64_t g = base + i;
+                X[g] = x[k];
+                VX[g] = vx[k];
+                VY[g] = vy[k];
+                VZ[g] = vz[k];
+            }
+        }
+        const bool left = n_left > 0, right = n_right > 0;
+        if (ballot(left) | ballot(right) | ballot(cfl) | ballot(bad)) {
+            SegDyn *sd = d.segd + seg;
+            InstDyn *idn = d.instd + inst;
+            const unsigned long long ml = ballot(left), mr = ballot(right);
+            int sl = n_left, sr = n_right;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                sl += __shfl_xor(sl, o, 64);
+                sr += __shfl_xor(sr, o, 64);
+            }
+            if (lane == 0) {
+                if (ml) atomicAdd(&sd->absorbed_step[0], (uint32_t)sl);
+                if (mr) atomicAdd(&sd->absorbed_step[1], (uint32_t)sr);
+            }
             wave_or(&idn->status, PIC_ST_CFL, cfl);
             wave_or(&idn->status, PIC_ST_NONFINITE, bad);
-            if (MCC) {
-                const uint32_t idx = wave_append(&d.glob->cand_count, cand);
-                if (cand) {
-                    if (idx < (uint32_t)d.cand_cap) d.cand[idx] = (uint32_t)g;
-                    else atomicOr(&idn->status, PIC_ST_CANDIDATES);
-                }
-            }
-            if (DEP) deposit_chunk(S, key, w1);
         }
+        if (MCC) {
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) {
+                const int64_t g = base + t0 + (int64_t)(wave * kPer + k) * 64 + lane;
+                queue_candidate(L, d, cand[k], (uint32_t)g, inst);
+            }
+        }
+        if (DEP) deposit_tile<kPer>(L, S, key, w1);
     }
+    if (MCC) flush_candidates(L, d);
 }
 
 // ---------------------------------------------------------------------------
@@ -287,40 +538,46 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void deposit_kernel(Dev d)
 {
+    __shared__ PushLds L;
+    push_lds_init(L, d);
     const int cur = d.glob->cur_set;
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
     const bool f64 = (d.precision == PIC_FP64);
     for (int64_t t = blockIdx.x; t < d.n_tiles; t += gridDim.x) {
-        const int seg = seg_of_tile(d.seg_tile0, d.n_seg, t);
-        const SegConst &sc = d.segc[seg];
-        const int64_t count = d.segd[seg].count;
-        const int64_t t0 = (t - sc.tile0) * (int64_t)kTile;
+        int64_t tile0, base, count;
+        const int seg = tile_seg(L, d, t, tile0, base, count);
+        const int64_t t0 = (t - tile0) * (int64_t)kTile;
         if (t0 >= count) continue;
+        const SegConst &sc = d.segc[seg];
         unsigned long long *__restrict__ S = d.S + sc.sp * d.G + sc.gnode;
+        int key[kPer];
+        unsigned long long w1[kPer];
+#pragma unroll
         for (int k = 0; k < kPer; ++k) {
             const int64_t i = t0 + (int64_t)(wave * kPer + k) * 64 + lane;
-            const int64_t g = sc.base + i;
-            int key = -1;
-            unsigned long long w1 = 0;
+            const int64_t g = base + i;
+            key[k] = -1;
+            w1[k] = 0;
             if (i < count) {
                 if (f64) {
                     const double x = ((const double *)d.x[cur])[g];
                     if (x >= 0.0) {
                         const double jn = floor(x);
-                        key = (int)jn;
-                        w1 = (unsigned long long)rint(ldexp(x - jn, PIC_FRAC_BITS));
+                        key[k] = (int)jn;
+                        w1[k] = (unsigned long long)rint(ldexp(x - jn, PIC_FRAC_BITS));
                     }
                 } else {
-                    const int32_t j = d.cell[cur][g];
-                    if (j >= 0) {
-                        key = j;
-                        w1 = (unsigned long long)rintf(((const float *)d.x[cur])[g] * 4294967296.0f);
+                    const int32_t jj = d.cell[cur][g];
+                    if (jj >= 0) {
+                        key[k] = jj;
+                        w1[k] = (unsigned long long)rintf(((const float *)d.x[cur])[g] *
+                                                          4294967296.0f);
                     }
                 }
             }
-            deposit_chunk(S, key, w1);
         }
+        deposit_tile<kPer>(L, S, key, w1);
     }
 }
 
@@ -329,8 +586,7 @@ int push_grid(const Dev &d)
     // persistent-style grid: enough blocks to fill 256 CUs several times over,
     // never more than there are tiles
     int64_t g = d.n_tiles;
-    const int64_t cap = 256 * 16;
-    if (g > cap) g = cap;
+    if (g > kMaxPushBlocks) g = kMaxPushBlocks;
     if (g < 1) g = 1;
     return (int)g;
 }

@@ -2,63 +2,157 @@
 // the cell they occupy) as a counting sort by cell into the other buffer set,
 // dropping absorbed particles (gfx950).
 //
-//   hist     one bin per (species, node); absorbed particles go to the bin of
-//            node nc, which no live particle uses; atomics pre-summed over
-//            runs of equal cells in each wave
+//   hist     one bin per (species, node) counts the live particles of each
+//            cell; every tile first counts into an LDS window of bins
+//            (wave-level run sums, then LDS atomics) and adds the window to
+//            the global bins with one atomic per touched bin
 //   scan     single-pass exclusive scan of all bins (decoupled look-back);
 //            writes the scatter cursors and the per-segment cell offsets
-//   scatter  every live particle takes cursor[bin]++ (one atomic per run) and
-//            is copied to its segment's region of the other set; the last
-//            block switches the current set and sets the counts
+//   scatter  every tile ranks its particles per bin in LDS, reserves each
+//            bin's share with one global atomic per touched bin, and copies
+//            the particles to the other set
+//   finish   one block switches the current set and sets the counts
+// Segment starts come from the live counts, so absorbed particles need no bin.
 #include "device_common.h"
 
 namespace picx {
 
-__device__ __forceinline__ int bin_of(const Dev &d, int cur, const SegConst &sc, int64_t g,
-                                      bool f64, bool &live)
+constexpr int kSortWin = 1024;  // LDS window of bins per tile
+constexpr int kSegLdsS = 256;
+
+struct SortLds {
+    uint32_t cnt[kSortWin];
+    uint32_t base[kSortWin];
+    int64_t tile0[kSegLdsS + 1];
+    int64_t sbase[kSegLdsS];
+    uint32_t count[kSegLdsS];
+    int red[2][kWaves];
+};
+
+__device__ __forceinline__ void sort_lds_init(SortLds &L, const Dev &d)
 {
-    int n;
+    for (int i = threadIdx.x; i < kSortWin; i += kBlock) L.cnt[i] = 0u;
+    if (d.n_seg <= kSegLdsS) {
+        for (int s = threadIdx.x; s <= d.n_seg; s += kBlock) {
+            L.tile0[s] = d.seg_tile0[s];
+            if (s < d.n_seg) {
+                L.sbase[s] = d.seg_base[s];
+                L.count[s] = d.segd[s].count;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ int sort_tile_seg(const SortLds &L, const Dev &d, int64_t t,
+                                             int64_t &tile0, int64_t &base, int64_t &count)
+{
+    int seg;
+    if (d.n_seg <= kSegLdsS) {
+        int lo = 0, hi = d.n_seg - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (L.tile0[mid] <= t) lo = mid; else hi = mid - 1;
+        }
+        seg = lo;
+        tile0 = L.tile0[seg];
+        base = L.sbase[seg];
+        count = L.count[seg];
+    } else {
+        seg = seg_of_tile(d.seg_tile0, d.n_seg, t);
+        tile0 = d.seg_tile0[seg];
+        base = d.seg_base[seg];
+        count = d.segd[seg].count;
+    }
+    return seg;
+}
+
+// node of a slot, -1 when absorbed
+__device__ __forceinline__ int node_of(const Dev &d, int cur, int64_t g, bool f64)
+{
     if (f64) {
         const double x = ((const double *)d.x[cur])[g];
-        live = x >= 0.0;
-        n = live ? (int)floor(x) : sc.nc;
-    } else {
-        const int32_t c = d.cell[cur][g];
-        live = c >= 0;
-        n = live ? c : sc.nc;
+        return x >= 0.0 ? (int)floor(x) : -1;
     }
-    return (int)(sc.sp * d.G + sc.gnode + n);
+    return d.cell[cur][g];
+}
+
+// block window [lo, hi] over the keys of this tile (barrier inside)
+__device__ __forceinline__ void tile_window(SortLds &L, const int (&key)[kPer], int &lo, int &hi)
+{
+    const int lane = lane_id();
+    const int wave = threadIdx.x >> 6;
+    int kmn = 0x7fffffff, kmx = -1;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k)
+        if (key[k] >= 0) {
+            kmn = min(kmn, key[k]);
+            kmx = max(kmx, key[k]);
+        }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        kmn = min(kmn, __shfl_xor(kmn, o, 64));
+        kmx = max(kmx, __shfl_xor(kmx, o, 64));
+    }
+    if (lane == 0) {
+        L.red[0][wave] = kmn;
+        L.red[1][wave] = kmx;
+    }
+    __syncthreads();
+    lo = L.red[0][0];
+    hi = L.red[1][0];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) {
+        lo = min(lo, L.red[0][w]);
+        hi = max(hi, L.red[1][w]);
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void sort_hist_kernel(Dev d)
 {
+    __shared__ SortLds L;
+    sort_lds_init(L, d);
     const int cur = d.glob->cur_set;
     const bool f64 = (d.precision == PIC_FP64);
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
     for (int64_t t = blockIdx.x; t < d.n_tiles; t += gridDim.x) {
-        const int seg = seg_of_tile(d.seg_tile0, d.n_seg, t);
-        const SegConst &sc = d.segc[seg];
-        const int64_t count = d.segd[seg].count;
-        const int64_t t0 = (t - sc.tile0) * (int64_t)kTile;
+        int64_t tile0, base, count;
+        const int seg = sort_tile_seg(L, d, t, tile0, base, count);
+        const int64_t t0 = (t - tile0) * (int64_t)kTile;
         if (t0 >= count) continue;
+        const SegConst &sc = d.segc[seg];
+        uint32_t *__restrict__ H = d.hist + sc.sp * d.G + sc.gnode;
+        int key[kPer];
+#pragma unroll
         for (int k = 0; k < kPer; ++k) {
             const int64_t i = t0 + (int64_t)(wave * kPer + k) * 64 + lane;
-            int key = -1;
-            if (i < count) {
-                bool live;
-                key = bin_of(d, cur, sc, sc.base + i, f64, live);
-            }
+            key[k] = (i < count) ? node_of(d, cur, base + i, f64) : -1;
+        }
+        int lo, hi;
+        tile_window(L, key, lo, hi);
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
             bool tail;
-            const unsigned long long s = run_sum(key, key >= 0 ? 1ull : 0ull, tail);
-            if (tail && key >= 0) atomicAdd(d.hist + key, (uint32_t)s);
+            const unsigned long long s = run_sum(key[k], key[k] >= 0 ? 1ull : 0ull, tail);
+            if (tail && key[k] >= 0) {
+                const int rel = key[k] - lo;
+                if (rel < kSortWin) atomicAdd(&L.cnt[rel], (uint32_t)s);
+                else atomicAdd(H + key[k], (uint32_t)s);
+            }
+        }
+        __syncthreads();
+        if (hi >= 0) {
+            const int span = min(hi - lo + 1, kSortWin);
+            for (int i = threadIdx.x; i < span; i += kBlock) {
+                const uint32_t v = L.cnt[i];
+                if (v) {
+                    atomicAdd(H + lo + i, v);
+                    L.cnt[i] = 0u;
+                }
+            }
         }
     }
-}
-
-__device__ __forceinline__ unsigned long long ld_acq(const unsigned long long *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ void st_rel(unsigned long long *p, unsigned long long v)
@@ -66,7 +160,7 @@ __device__ __forceinline__ void st_rel(unsigned long long *p, unsigned long long
     __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// raw scan position of the first bin of segment `seg`: all occupied slots of
+// raw scan position of the first bin of segment `seg`: the live particles of
 // the segments whose bins come earlier (bins are species-major, then instance)
 __device__ unsigned long long seg_raw_start(const Dev &d, int seg)
 {
@@ -74,7 +168,7 @@ __device__ unsigned long long seg_raw_start(const Dev &d, int seg)
     unsigned long long s = 0;
     for (int q = 0; q < d.n_seg; ++q) {
         const SegConst &o = d.segc[q];
-        if (o.sp < sc.sp || (o.sp == sc.sp && o.inst < sc.inst)) s += d.segd[q].count;
+        if (o.sp < sc.sp || (o.sp == sc.sp && o.inst < sc.inst)) s += d.segd[q].live;
     }
     return s;
 }
@@ -132,7 +226,7 @@ __global__ __launch_bounds__(kBlock) void sort_scan_kernel(Dev d)
             for (int64_t p = vt - 1;; --p) {
                 unsigned long long f;
                 do {
-                    f = ld_acq(&st[p]);
+                    f = __hip_atomic_load(&st[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 } while ((f >> 34) != gen);
                 in += (uint32_t)f;
                 if (((f >> 32) & 3ull) == 2ull) break;
@@ -177,80 +271,105 @@ __device__ __forceinline__ void mv(void *dst, const void *src, int64_t to, int64
 
 __global__ __launch_bounds__(kBlock) void sort_scatter_kernel(Dev d)
 {
+    __shared__ SortLds L;
+    sort_lds_init(L, d);
     const int cur = d.glob->cur_set;
     const int nxt = cur ^ 1;
     const bool f64 = (d.precision == PIC_FP64);
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
     for (int64_t t = blockIdx.x; t < d.n_tiles; t += gridDim.x) {
-        const int seg = seg_of_tile(d.seg_tile0, d.n_seg, t);
-        const SegConst &sc = d.segc[seg];
-        const int64_t count = d.segd[seg].count;
-        const int64_t t0 = (t - sc.tile0) * (int64_t)kTile;
+        int64_t tile0, base, count;
+        const int seg = sort_tile_seg(L, d, t, tile0, base, count);
+        const int64_t t0 = (t - tile0) * (int64_t)kTile;
         if (t0 >= count) continue;
-        const unsigned long long start = d.seg_start[seg];
+        const SegConst &sc = d.segc[seg];
+        const uint32_t start = (uint32_t)d.seg_start[seg];
+        uint32_t *__restrict__ CUR = d.cursor + sc.sp * d.G + sc.gnode;
+        int key[kPer];
+#pragma unroll
         for (int k = 0; k < kPer; ++k) {
             const int64_t i = t0 + (int64_t)(wave * kPer + k) * 64 + lane;
-            const int64_t g = sc.base + i;
-            int key = -1;
-            if (i < count) {
-                bool live;
-                key = bin_of(d, cur, sc, g, f64, live);
-                if (!live) key = -1;
-            }
+            key[k] = (i < count) ? node_of(d, cur, base + i, f64) : -1;
+        }
+        int lo, hi;
+        tile_window(L, key, lo, hi);
+        // rank of every particle among the tile's particles of its cell
+        uint32_t rank[kPer];
+        bool outside[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
             bool tail;
-            const unsigned long long inc = run_sum(key, key >= 0 ? 1ull : 0ull, tail);
+            const unsigned long long inc = run_sum(key[k], key[k] >= 0 ? 1ull : 0ull, tail);
             const unsigned long long tails = ballot(tail);
-            uint32_t base = 0;
-            if (tail && key >= 0) base = atomicAdd(d.cursor + key, (uint32_t)inc);
-            // every lane fetches the base of its run from the run's tail lane
+            const int rel = key[k] - lo;
+            outside[k] = key[k] >= 0 && rel >= kSortWin;
+            uint32_t rb = 0;
+            if (tail && key[k] >= 0) {
+                // in-window bins: rank within the tile; outside: a direct global reservation
+                if (!outside[k]) rb = atomicAdd(&L.cnt[rel], (uint32_t)inc);
+                else rb = atomicAdd(CUR + key[k], (uint32_t)inc);
+            }
             const unsigned long long above = tails & ~((1ull << lane) - 1ull);
             const int tl = __ffsll((long long)above) - 1;
-            base = __shfl(base, tl, 64);
-            if (key >= 0) {
-                const uint32_t pos = base + (uint32_t)inc - 1u;
-                const uint32_t rel = pos - (uint32_t)start;
-                if (rel >= sc.cap) {  // cannot happen with a consistent histogram
-                    atomicOr(&d.instd[sc.inst].status, PIC_ST_INTERNAL);
-                    continue;
+            rb = __shfl(rb, tl, 64);
+            rank[k] = rb + (uint32_t)inc - 1u;
+        }
+        __syncthreads();
+        // one global reservation per touched bin
+        if (hi >= 0) {
+            const int span = min(hi - lo + 1, kSortWin);
+            for (int i = threadIdx.x; i < span; i += kBlock) {
+                const uint32_t v = L.cnt[i];
+                if (v) {
+                    L.base[i] = atomicAdd(CUR + lo + i, v);
+                    L.cnt[i] = 0u;
                 }
-                const int64_t to = sc.base + (int64_t)rel;
-                if (f64) {
-                    mv<double>(d.x[nxt], d.x[cur], to, g);
-                    mv<double>(d.vx[nxt], d.vx[cur], to, g);
-                    mv<double>(d.vy[nxt], d.vy[cur], to, g);
-                    mv<double>(d.vz[nxt], d.vz[cur], to, g);
-                } else {
-                    mv<float>(d.x[nxt], d.x[cur], to, g);
-                    mv<int32_t>(d.cell[nxt], d.cell[cur], to, g);
-                    mv<float>(d.vx[nxt], d.vx[cur], to, g);
-                    mv<float>(d.vy[nxt], d.vy[cur], to, g);
-                    mv<float>(d.vz[nxt], d.vz[cur], to, g);
-                }
-                mv<unsigned long long>(d.id[nxt], d.id[cur], to, g);
             }
         }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            if (key[k] < 0) continue;
+            const int64_t g = base + t0 + (int64_t)(wave * kPer + k) * 64 + lane;
+            const uint32_t pos = outside[k] ? rank[k] : L.base[key[k] - lo] + rank[k];
+            const uint32_t rel = pos - start;
+            if (rel >= sc.cap) {  // cannot happen with a consistent histogram
+                atomicOr(&d.instd[sc.inst].status, PIC_ST_INTERNAL);
+                continue;
+            }
+            const int64_t to = sc.base + (int64_t)rel;
+            if (f64) {
+                mv<double>(d.x[nxt], d.x[cur], to, g);
+                mv<double>(d.vx[nxt], d.vx[cur], to, g);
+                mv<double>(d.vy[nxt], d.vy[cur], to, g);
+                mv<double>(d.vz[nxt], d.vz[cur], to, g);
+            } else {
+                mv<float>(d.x[nxt], d.x[cur], to, g);
+                mv<int32_t>(d.cell[nxt], d.cell[cur], to, g);
+                mv<float>(d.vx[nxt], d.vx[cur], to, g);
+                mv<float>(d.vy[nxt], d.vy[cur], to, g);
+                mv<float>(d.vz[nxt], d.vz[cur], to, g);
+            }
+            mv<unsigned long long>(d.id[nxt], d.id[cur], to, g);
+        }
+        // the next tile's window barrier orders the reuse of L.base
     }
-    // last block: switch sets and set the counts to the live particles
-    __shared__ bool s_last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) s_last = (atomicAdd(&d.glob->scatter_done, 1u) == gridDim.x - 1);
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    for (int s = threadIdx.x; s < d.n_seg; s += kBlock) {
+}
+
+// after the scatter (one block): switch sets and set the counts to the live particles
+__global__ void sort_finish_kernel(Dev d)
+{
+    for (int s = threadIdx.x; s < d.n_seg; s += blockDim.x) {
         const SegConst &sc = d.segc[s];
-        // offsets[node nc] of the segment = number of live particles
+        // offsets[node nc] of the segment = particles in its cell bins
         const uint32_t n_live = d.offsets[sc.sp * d.G + sc.gnode + sc.nc];
         if (n_live != d.segd[s].live) atomicOr(&d.instd[sc.inst].status, PIC_ST_INTERNAL);
         d.segd[s].count = n_live;
         d.segd[s].live = n_live;
     }
-    if (threadIdx.x == 0) {
-        d.glob->cur_set = nxt;
-        d.glob->scatter_done = 0;
-    }
+    __syncthreads();
+    if (threadIdx.x == 0) d.glob->cur_set ^= 1;
 }
 
 __global__ void sort_start_kernel(Dev d)
@@ -271,6 +390,9 @@ hipError_t launch_sort(const Dev &d, hipStream_t st)
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(sort_scatter_kernel, dim3(grid), dim3(kBlock), 0, st, d);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(sort_finish_kernel, dim3(1), dim3(kBlock), 0, st, d);
     return hipGetLastError();
 }
 

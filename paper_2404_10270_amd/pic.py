@@ -34,6 +34,7 @@ PIC_R_DEPOSIT, PIC_R_RHO, PIC_R_PHI, PIC_R_EFIELD = 0, 1, 2, 3
 PIC_R_ACC64, PIC_R_ACC32, PIC_R_CELL_OFFSETS, PIC_R_NODE_BASE = 4, 5, 6, 7
 
 PIC_INIT_NO_FIELD = 0x1
+PIC_INIT_SORT = 0x2
 PIC_PUSH_NO_DEPOSIT = 0x1
 
 # every entry point declared in include/pic.h

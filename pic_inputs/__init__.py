@@ -94,6 +94,7 @@ class Workload:
     perturb_amp: float = 0.0    # mode-1 density perturbation (Langmuir case)
     perturb_mode: int = 1
     quiet: bool = False         # lattice positions instead of random ones
+    pair_start: bool = False    # every ion starts at an electron's position (neutral start)
 
     def replace(self, **kw) -> "Workload":
         return dataclasses.replace(self, **kw)
@@ -157,7 +158,7 @@ def bounded(nc: int = 8192, ppc: float = 200, seed: int = 2, n_steps: int = 1000
                 cap_factor=cap_factor)
     return Workload(name="bounded", nc=nc, bc=BC_ABSORB, dx=dx, dt=dt, eps0=EPS0_SI,
                     species=[e, i], B0=B0, theta=math.radians(theta_deg), source=source,
-                    seed=seed, sort_every=sort_every, n_steps=n_steps)
+                    seed=seed, sort_every=sort_every, n_steps=n_steps, pair_start=True)
 
 
 def default_mcc(n0: float = 1e21) -> MCC:
@@ -222,6 +223,10 @@ def initial_state(wl: Workload) -> List[SpeciesState]:
     Positions are uniform in [0, nc) (or a lattice for ``quiet``), then, if
     ``perturb_amp`` is set, displaced by (A/k) sin(k x) with k = 2 pi m / nc,
     which gives a density modulation of relative amplitude A in mode m.
+    With ``pair_start`` every species after the first reuses the first
+    species' positions (equal counts), so the initial charge density is zero
+    everywhere: independent uniform positions would leave a random-walk charge
+    imbalance whose 1D field grows with the square root of the number of cells.
     Velocities are Maxwellian with sqrt(T/m) per component.  Ids are
     0..N_0-1 for species 0, then the next block for species 1, and so on.
     """
@@ -229,9 +234,12 @@ def initial_state(wl: Workload) -> List[SpeciesState]:
     out: List[SpeciesState] = []
     next_id = 0
     nc = wl.nc
+    first_x = None
     for s in wl.species:
         n = int(round(s.ppc * nc))
-        if wl.quiet:
+        if wl.pair_start and first_x is not None and first_x.shape[0] == n:
+            x = first_x.copy()
+        elif wl.quiet:
             x = (np.arange(n, dtype=np.float64) + 0.5) * (nc / n)
         else:
             x = rng.random(n, dtype=np.float64) * nc
@@ -243,6 +251,8 @@ def initial_state(wl: Workload) -> List[SpeciesState]:
         # keep every position strictly inside [0, nc)
         x = np.where(x >= nc, np.nextafter(float(nc), 0.0), x)
         x = np.where(x < 0.0, 0.0, x)
+        if first_x is None:
+            first_x = x
         vt = wl.vth_hat(s)
         if vt > 0.0:
             v = rng.standard_normal((3, n)) * vt

@@ -1,0 +1,224 @@
+"""GPU checks of properties that hold at any size, edge cases of the ABI on
+the device, and the full-size bench workload on sampled particles.
+
+* sort: the output is a permutation of the live particles (multiset of
+  (id, state) preserved), cells are non-decreasing in every segment, and the
+  cell offsets equal the scan of the per-cell counts;
+* deposit: every live particle contributes exactly 2^32 after every step;
+* ids stay unique; run-to-run results are identical as sets keyed by id;
+* edge cases: an empty species, ragged counts, a capacity overflow, a
+  particle at |vx| >= 1 cell/step, non-finite or out-of-range uploads;
+* full size (100,000 cells, 2e7 particles, FP32 form): the bit-exact deposit
+  of the whole state and one step of a sample of particles against the
+  oracle.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import pic_inputs as pin
+from gpu_common import FP32, FP64, P, build_pair, by_id, flush, gpu_state, oracle_state
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("prec", [FP32, FP64], ids=["fp32", "fp64"])
+def test_sort_is_a_permutation_by_cell(prec):
+    wl = pin.bounded_mcc(nc=600, ppc=45, seed=31)
+    flush(f"sort invariants prec={prec}")
+    sim, orc, ost = build_pair(wl, prec)
+    sim.step(7)  # particles drift, some are absorbed, pairs are appended
+    before = [gpu_state(sim, k) for k in range(2)]
+    sim.sort()
+    d, rc = sim.diagnostics()
+    assert rc == 0 and d[0].cur_set == 1
+    offs = sim.grid(P.PIC_R_CELL_OFFSETS)
+    for k in range(2):
+        raw = sim.state(k, live_only=False)
+        assert np.all(raw["live"]), "the sort drops absorbed particles"
+        cells = np.floor(raw["x"]).astype(np.int64)
+        assert np.all(np.diff(cells) >= 0), "cells not sorted"
+        after = by_id(raw)
+        for f in ("x", "vx", "vy", "vz", "id"):
+            assert np.array_equal(after[f], before[k][f])
+        counts = np.bincount(cells, minlength=wl.nc)
+        assert np.array_equal(offs[k][:wl.nc + 1].astype(np.int64),
+                              np.concatenate([[0], np.cumsum(counts)]))
+        assert d[0].n_slots_used[k] == d[0].n_live[k] == after["id"].size
+    sim.close()
+
+
+@pytest.mark.parametrize("prec", [FP32, FP64], ids=["fp32", "fp64"])
+def test_charge_identity_every_step_and_unique_ids(prec):
+    wl = pin.bounded_mcc(nc=333, ppc=61, seed=32)
+    flush(f"charge identity prec={prec}")
+    sim, orc, ost = build_pair(wl, prec)
+    for s in range(25):
+        sim.push()
+        sim.mcc_collide()
+        S = sim.grid(P.PIC_R_DEPOSIT)
+        d, rc = sim.diagnostics()
+        assert rc == 0
+        for k in range(2):
+            assert int(S[k].sum(dtype=np.uint64)) == d[0].n_live[k] * 2 ** 32
+        ids = np.concatenate([gpu_state(sim, k)["id"] for k in range(2)])
+        assert np.unique(ids).size == ids.size
+        sim.field_solve()
+        if s % 10 == 9:
+            sim.sort()
+    sim.close()
+
+
+@pytest.mark.parametrize("prec", [FP32, FP64], ids=["fp32", "fp64"])
+def test_run_to_run_identical(prec):
+    wl = pin.bounded_mcc(nc=300, ppc=50, seed=33)
+    flush(f"determinism prec={prec}")
+    outs = []
+    for _ in range(2):
+        sim, orc, ost = build_pair(wl, prec)
+        sim.step(30, sort_every=10)
+        outs.append([gpu_state(sim, k) for k in range(2)])
+        d, rc = sim.diagnostics()
+        assert rc == 0
+        sim.close()
+    for k in range(2):
+        for f in ("x", "vx", "vy", "vz", "id"):
+            assert np.array_equal(outs[0][k][f], outs[1][k][f])
+
+
+def test_empty_species_and_ragged_counts():
+    # periodic electrons (ragged count, 211 particles) plus an ion species with no particles;
+    # the neutralising background keeps the system quiet
+    wl = pin.langmuir(nc=64, ppc=3.3)
+    wl.species.append(pin.Species("i", pin.KIND_ION, q=1.0, m=100.0, w=wl.species[0].w, ppc=0,
+                                  T=0.0))
+    st = pin.initial_state(wl)
+    assert st[0].n == 211 and st[1].n == 0
+    flush("empty species")
+    sim, orc, ost = build_pair(wl, FP64, state=st, caps=[st[0].n + 5, 8])
+    sim.step(5)
+    orc.step(5)
+    d, rc = sim.diagnostics()
+    assert rc == 0 and d[0].n_live[1] == 0
+    g, o = gpu_state(sim, 0), oracle_state(orc, 0)
+    assert np.array_equal(g["id"], o["id"])
+    assert np.max(np.abs(g["x"] - o["x"])) <= 1e-9
+    sim.close()
+
+
+def test_capacity_overflow_is_flagged():
+    """Source pairs that do not fit are dropped and reported, never written out of bounds."""
+    wl = pin.bounded(nc=64, ppc=20, seed=35, source=True)
+    st = pin.initial_state(wl)
+    # ions near the walls and fast towards them: many are absorbed in the first step
+    for s in st:
+        s.vx[:] = np.where(s.x < 32, -0.9, 0.9)
+    caps = [st[0].n, st[1].n]  # no room for the source pairs beyond the slots freed by nothing
+    flush("capacity overflow")
+    sim, _, _ = build_pair(wl, FP32, state=st, caps=caps)
+    sim.step(2)
+    d, rc = sim.diagnostics()
+    assert rc == P.PIC_E_CAPACITY and (d[0].status & P.PIC_ST_CAPACITY)
+    for k in range(2):
+        assert d[0].n_slots_used[k] <= caps[k]
+    sim.close()
+
+
+def test_cfl_breach_is_flagged():
+    wl = pin.bounded(nc=64, ppc=5, seed=36, source=False)
+    st = pin.initial_state(wl)
+    st[0].vx[3] = 1.5  # cells per step
+    flush("cfl")
+    sim, _, _ = build_pair(wl, FP64, state=st)
+    sim.step(1)
+    d, rc = sim.diagnostics()
+    assert rc == P.PIC_E_CFL and (d[0].status & P.PIC_ST_CFL)
+    sim.close()
+
+
+@pytest.mark.parametrize("prec", [FP32, FP64], ids=["fp32", "fp64"])
+def test_bad_upload_is_dropped_and_flagged(prec):
+    wl = pin.bounded(nc=64, ppc=5, seed=37, source=False)
+    st = pin.initial_state(wl)
+    st[0].vx[1] = np.nan
+    st[0].x[2] = 64.5  # outside [0, nc)
+    flush(f"bad upload prec={prec}")
+    sim, _, _ = build_pair(wl, prec, state=st)
+    d, rc = sim.diagnostics()
+    assert d[0].status & P.PIC_ST_BAD_INIT
+    assert d[0].n_live[0] == st[0].n - 2
+    sim.step(2)
+    d, rc = sim.diagnostics()
+    assert np.all(np.isfinite(gpu_state(sim, 0)["vx"]))
+    sim.close()
+
+
+def test_periodic_wrap_fp32_matches_oracle():
+    wl = pin.langmuir(nc=128, ppc=50)
+    st = pin.initial_state(wl)
+    st[0].vx[:] = np.where(np.arange(st[0].n) % 2 == 0, 0.7, -0.7)  # many wall crossings
+    flush("periodic wrap")
+    sim, orc, ost = build_pair(wl, FP32, state=st)
+    sim.step(3)
+    orc.step(3)
+    g, o = gpu_state(sim, 0), oracle_state(orc, 0)
+    assert np.array_equal(g["id"], o["id"])
+    dxw = np.abs(g["x"] - o["x"])
+    dxw = np.minimum(dxw, wl.nc - dxw)  # positions on a ring
+    assert np.max(dxw) <= 1e-5
+    sim.close()
+
+
+@pytest.mark.slow
+def test_full_size_bench_workload_sampled():
+    """100,000 cells, 2e7 particles: bit-exact deposit of the whole uploaded state, then
+    one step of the FP32 form compared with the oracle on a sample of particles."""
+    wl = pin.bounded_mcc(nc=100_000, ppc=100, seed=3, cap_factor=1.25)
+    flush("full size: generate")
+    st = pin.initial_state(wl)
+    st32 = pin.to_fp32_form(st, wl.nc)
+    caps = pin.capacities(wl, st)
+    flush("full size: deposit")
+    sim = P.PicSim(wl, st32, FP32, capacities=caps, flags=P.PIC_INIT_NO_FIELD)
+    sim.deposit()
+    S = sim.grid(P.PIC_R_DEPOSIT)
+    ost = [s.as_f64() for s in st32]
+    for k in range(2):
+        assert np.array_equal(S[k], oracle.deposit_fixed(ost[k].x, wl.nc))
+    sim.close()
+    flush("full size: one step")
+    sim = P.PicSim(wl, st32, FP32, capacities=caps)
+    sim.push(P.PIC_PUSH_NO_DEPOSIT)
+    # oracle: field of the whole state, push of a sample
+    full = oracle.OracleSim(wl, ost, caps=caps)
+    full.deposit()
+    full.field()
+    rng = np.random.default_rng(0)
+    for k, s in enumerate(wl.species):
+        pick = np.sort(rng.choice(ost[k].n, 20000, replace=False))
+        sub = pin.SpeciesState(x=ost[k].x[pick], vx=ost[k].vx[pick], vy=ost[k].vy[pick],
+                               vz=ost[k].vz[pick], id=ost[k].id[pick])
+        sample_states = [sub if q == k else pin.SpeciesState(x=np.zeros(0), vx=np.zeros(0),
+                                                               vy=np.zeros(0), vz=np.zeros(0),
+                                                               id=np.zeros(0, np.uint64))
+                         for q in range(2)]
+        o = oracle.OracleSim(wl, sample_states, caps=[pick.size + 1] * 2)
+        for q in range(2):
+            o.acc[q][:] = full.acc[q]
+        o.push()
+        o.walls()
+        os_ = oracle_state(o, k)
+        g = gpu_state(sim, k)
+        gi = np.searchsorted(g["id"], os_["id"])
+        ok = (gi < g["id"].size)
+        gi = np.minimum(gi, g["id"].size - 1)
+        ok &= g["id"][gi] == os_["id"]
+        assert ok.mean() > 0.999
+        vth = wl.vth_hat(s)
+        assert np.max(np.abs(g["x"][gi[ok]] - os_["x"][ok])) <= 1e-5
+        for f in ("vx", "vy", "vz"):
+            err = np.abs(g[f][gi[ok]] - os_[f][ok]) / np.maximum(np.abs(os_[f][ok]), vth)
+            assert np.max(err) <= 1e-5
+    sim.close()
