@@ -38,7 +38,9 @@ PUSH_BYTES_FP32 = 5 * 4 + 8 + 5 * 4
 PUSH_BYTES_FP64 = 4 * 8 + 8 + 4 * 8
 SORT_EVERY = 20
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "push_f32_bounded_mcc_traffic.json")
-PUSH_SOURCES = ["paper_2404_10270_amd/csrc/push.hip", "paper_2404_10270_amd/csrc/device_common.h"]
+PUSH_SOURCES = ["paper_2404_10270_amd/csrc/push.hip", "paper_2404_10270_amd/csrc/device_common.h",
+                "paper_2404_10270_amd/csrc/pic_internal.h"]
+COPY_BYTES = 1 << 30  # calibration copy: 1 GiB read + 1 GiB written per launch
 
 
 def log(msg):
@@ -94,7 +96,7 @@ def time_push(torch, sim, n_steps):
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(sim.stream)
-        sim.push()
+        sim.push()  # the launch pic_step makes
         e1.record(sim.stream)
         sim.mcc_collide()
         sim.field_solve()
@@ -122,6 +124,63 @@ def traffic_from_profile():
     return t.get("bytes_per_launch")
 
 
+def copy_calibration():
+    """A plain elementwise copy of known size (torch.neg, 1 GiB in, 1 GiB out),
+    launched 5 times, for scaling the HBM byte counters."""
+    import torch
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": COPY_BYTES, "copy_bytes_written": COPY_BYTES,
+                      "launches": 5}), flush=True)
+
+
+def _pmc_rows(d, kernel_sub, counter):
+    """Per-dispatch values of `counter` for kernels whose name contains
+    `kernel_sub`, from a rocprofv3 --pmc CSV directory."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no counter_collection.csv under {d}")
+    vals = {}
+    for fn in files:
+        with open(fn) as f:
+            for r in csv.DictReader(f):
+                if kernel_sub in r["Kernel_Name"] and r["Counter_Name"] == counter:
+                    key = (fn, r["Dispatch_Id"])
+                    vals[key] = vals.get(key, 0.0) + float(r["Counter_Value"])
+    if not vals:
+        raise ValueError(f"no {counter} rows for '{kernel_sub}' under {d}")
+    return list(vals.values())
+
+
+def pmc_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, out):
+    """HBM bytes per mover launch: FETCH_SIZE and WRITE_SIZE of the mover,
+    each scaled by bytes / counter value of the calibration copy."""
+    import statistics
+    mover = "push_f32_kernel"
+    cf = statistics.mean(_pmc_rows(cfetch_dir, "neg_kernel", "FETCH_SIZE"))
+    cw = statistics.mean(_pmc_rows(cwrite_dir, "neg_kernel", "WRITE_SIZE"))
+    f_fetch, f_write = COPY_BYTES / cf, COPY_BYTES / cw
+    mf = _pmc_rows(fetch_dir, mover, "FETCH_SIZE")
+    mw = _pmc_rows(write_dir, mover, "WRITE_SIZE")
+    fetch_b = statistics.mean(mf) * f_fetch
+    write_b = statistics.mean(mw) * f_write
+    res = {"kernel": mover, "source_hash": source_hash(PUSH_SOURCES),
+           "bytes_per_launch": round(fetch_b + write_b),
+           "fetch_bytes_per_launch": round(fetch_b), "write_bytes_per_launch": round(write_b),
+           "launches": [len(mf), len(mw)],
+           "copy_factor": {"FETCH_SIZE": f_fetch, "WRITE_SIZE": f_write},
+           "copy_counter_per_launch": {"FETCH_SIZE": cf, "WRITE_SIZE": cw}}
+    with open(out, "w") as f:
+        json.dump(res, f, indent=1)
+        f.write("\n")
+    print(json.dumps(res))
+
+
 def cpu_baseline(args):
     """The oracle as it stands, single thread, on a bounded sample of the workload."""
     import oracle
@@ -147,7 +206,14 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run the plain copy used to scale the HBM byte counters")
+    ap.add_argument("--pmc-summary", nargs=5, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE", "OUT"),
+                    help="summarise four rocprofv3 --pmc CSV directories into OUT (no GPU)")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary)
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
               file=sys.stderr)
@@ -161,6 +227,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     wl = workload(args)
     log(f"generating {wl.n_particles} particles on {wl.nc} cells")
     st = pin.initial_state(wl)
@@ -179,7 +248,7 @@ def main():
     achieved = PUSH_BYTES_FP32 * per_launch / (push_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile(),
-            "kernel": "push_f32_kernel<true,true>", "bytes_per_particle": PUSH_BYTES_FP32,
+            "kernel": "push_f32_kernel<true,1> (mover + deposit + candidate list)", "bytes_per_particle": PUSH_BYTES_FP32,
             "particles_per_launch": int(per_launch), "us_per_launch": round(push_ms * 1e3, 2)}
 
     fp64 = None

@@ -21,6 +21,7 @@ struct pic_ctx {
     Dev d{};
     hipStream_t st = nullptr;
     int64_t host_steps = 0;   // steps enqueued since init
+    bool collided = false;    // the last pic_push ran this step's collisions
     pic_diag *host_diag = nullptr;  // pinned staging for pic_diagnostics
 };
 
@@ -243,10 +244,11 @@ int plan(const pic_config *cfgs, int n_inst, Plan &p)
     p.n_push_blocks = (int)std::min<int64_t>(std::max<int64_t>(p.n_tiles, 1), kMaxPushBlocks);
     L.cand_ovf_cap = cand_capacity(cfgs, n_inst, P);
     L.ev_ovf_cap = L.cand_ovf_cap;
-    L.cand = take(sizeof(uint32_t) * ((uint64_t)p.n_push_blocks * kCandQ + L.cand_ovf_cap));
+    L.cand = take(sizeof(Cand) * ((uint64_t)p.n_push_blocks * kCandQ + L.cand_ovf_cap));
     L.cand_n = take(sizeof(uint32_t) * p.n_push_blocks);
     L.ev = take(sizeof(IzEvent) * ((uint64_t)p.n_push_blocks * kEvQ + L.ev_ovf_cap));
     L.ev_n = take(sizeof(uint32_t) * p.n_push_blocks);
+    L.ev_rank = take(sizeof(uint32_t) * ((uint64_t)p.n_push_blocks * kEvQ + L.ev_ovf_cap));
     L.cnt_slot = take(sizeof(unsigned long long) * (uint64_t)p.n_push_blocks * kCntSeg * kNCnt);
     L.diag_part = take(sizeof(double) * (uint64_t)kDiagBlocks * n_seg * kDiagVals);
     L.diag_out = take(sizeof(pic_diag) * n_inst);
@@ -416,10 +418,11 @@ int pic_init(const pic_config *cfgs, int n_inst, const pic_buffers *bufs, void *
     d.bwd_status = at<AffineStatus>(W, L.bwd_status);
     d.sort_status = at<unsigned long long>(W, L.sort_status);
     d.fe_part = at<double>(W, L.fe_part);
-    d.cand = at<uint32_t>(W, L.cand);
+    d.cand = at<Cand>(W, L.cand);
     d.cand_n = at<uint32_t>(W, L.cand_n);
     d.ev = at<IzEvent>(W, L.ev);
     d.ev_n = at<uint32_t>(W, L.ev_n);
+    d.ev_rank = at<uint32_t>(W, L.ev_rank);
     d.cnt_slot = at<unsigned long long>(W, L.cnt_slot);
     d.diag_part = at<double>(W, L.diag_part);
     d.diag_out = at<pic_diag>(W, L.diag_out);
@@ -478,7 +481,10 @@ int pic_push(pic_ctx *c, unsigned flags)
 {
     if (!c) return PIC_E_STATE;
     const bool dep = !(flags & PIC_PUSH_NO_DEPOSIT);
-    return launch_push(c->d, c->st, dep, c->mcc_any) == hipSuccess ? PIC_OK : PIC_E_DEVICE;
+    int mcc = 0;
+    if (c->mcc_any) mcc = (flags & PIC_PUSH_COLLIDE) ? 2 : 1;
+    c->collided = (mcc == 2);
+    return launch_push(c->d, c->st, dep, mcc) == hipSuccess ? PIC_OK : PIC_E_DEVICE;
 }
 
 int pic_deposit(pic_ctx *c)
@@ -496,7 +502,8 @@ int pic_field_solve(pic_ctx *c)
 int pic_mcc_collide(pic_ctx *c)
 {
     if (!c) return PIC_E_STATE;
-    if (c->mcc_any && launch_collide(c->d, c->st) != hipSuccess) return PIC_E_DEVICE;
+    if (c->mcc_any && !c->collided && launch_collide(c->d, c->st) != hipSuccess) return PIC_E_DEVICE;
+    c->collided = false;
     if (launch_emit(c->d, c->st, c->mcc_any || c->src_any, c->mcc_any) != hipSuccess) return PIC_E_DEVICE;
     c->host_steps += 1;
     return PIC_OK;

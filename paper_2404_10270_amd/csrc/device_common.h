@@ -161,6 +161,70 @@ __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, double &n0, d
     n1 = r * st;
 }
 
+// ---------------------------------------------------------------------------
+// Null-collision Monte Carlo for one candidate (Vahedi & Surendra, CPC 87,
+// 1995) against a uniform neutral gas.  The candidate's first Philox block
+// (id, step, 0) is redrawn; r = U(u1) nu_max is compared with the cumulative
+// n_n sigma_k |v| in squared form, all in FP64:
+//   electron  elastic (cold neutral of mass M, isotropic in the centre of
+//             mass), else ionisation above threshold (energy above it split
+//             U : 1-U, the first electron isotropic; the second electron's
+//             speed is returned in g2 for the pair creation);
+//   ion       charge exchange (the ion takes a Maxwellian velocity at T_n).
+// (vx, vy, vz) in cells/step are updated in place; cnt gets the process
+// counts (candidate, elastic, ionisation, CX, above v_cap).
+// ---------------------------------------------------------------------------
+enum { kCCand = 0, kCEl = 1, kCIz = 2, kCCx = 3, kCOver = 4 };
+
+__device__ __forceinline__ void collide_vel(const SegConst &sc, long long step,
+                                            unsigned long long pid, double &vx, double &vy,
+                                            double &vz, uint32_t (&cnt)[kNCnt], bool &iz,
+                                            double &g2)
+{
+    const uint4 u = draw(pid, step, 0, sc.key0, sc.key1);
+    const double v2 = (vx * vx + vy * vy) + vz * vz;
+    cnt[kCCand] += 1;
+    if (v2 > sc.vcap2) cnt[kCOver] += 1;
+    const double r = u01(u.y) * sc.nu_max;
+    const double r2 = r * r;
+    if (sc.kind == PIC_KIND_ELECTRON) {
+        if (r2 < sc.C0 * v2) {
+            double d0, d1, d2;
+            iso_dir(u.z, u.w, d0, d1, d2);
+            const double gg = sqrt(v2);
+            vx = sc.am * vx + sc.bm * gg * d0;
+            vy = sc.am * vy + sc.bm * gg * d1;
+            vz = sc.am * vz + sc.bm * gg * d2;
+            cnt[kCEl] += 1;
+        } else if (v2 >= sc.v2_iz && r2 < sc.C1 * v2) {
+            const uint4 u1 = draw(pid, step, 1, sc.key0, sc.key1);
+            const double e_tot = 0.5 * v2 - sc.eps_iz;
+            const double e1 = u01(u.z) * e_tot;
+            const double e2 = e_tot - e1;
+            const double g1 = sqrt(2.0 * e1);
+            double d0, d1, d2;
+            iso_dir(u1.x, u1.y, d0, d1, d2);
+            vx = g1 * d0;
+            vy = g1 * d1;
+            vz = g1 * d2;
+            iz = true;
+            g2 = sqrt(2.0 * e2);
+            cnt[kCIz] += 1;
+        }
+    } else {
+        if (r2 < sc.C0 * v2) {
+            const uint4 u1 = draw(pid, step, 1, sc.key0, sc.key1);
+            double n0, n1, n2, n3;
+            box_muller(u.z, u.w, n0, n1);
+            box_muller(u1.x, u1.y, n2, n3);
+            vx = sc.sig_n * n0;
+            vy = sc.sig_n * n1;
+            vz = sc.sig_n * n2;
+            cnt[kCCx] += 1;
+        }
+    }
+}
+
 // FP32 storage form of a position x in cells, 0 <= x < nc
 __device__ __forceinline__ void split_position(double x, int nc, int32_t &cell, float &f)
 {

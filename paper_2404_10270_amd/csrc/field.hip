@@ -11,10 +11,16 @@
 //                                                             c'_u = g_u = -u/(u+1))
 //   backward  phi_u = (u/(u+1)) phi_{u+1} + d'_u,
 // so each sweep is evaluated as a scan over affine maps y -> A y + B: every
-// thread composes kFieldR consecutive maps, the block scans the thread maps,
-// and tiles chain through a single-pass decoupled look-back in which one wave
-// inspects 64 predecessor tiles per round.  Same recurrences
-// as the sequential sweep, regrouped; only the rounding order differs.
+// thread composes kFieldR consecutive maps and the block scans the thread
+// maps.  Tiles chain through three launches, with no atomics and no waiting
+// between blocks:
+//   1. rho, and the composite of each tile's forward maps;
+//   2. the composites of the tiles below give the value entering the tile;
+//      forward sweep (d'), and the composite of the tile's backward maps;
+//   3. the composites of the tiles above give phi entering the tile from the
+//      top; backward sweep (phi), then E, the accelerations, the field energy.
+// Same recurrences as the sequential sweep, regrouped; only the rounding
+// order differs.
 #include "device_common.h"
 
 #pragma clang fp contract(off)
@@ -69,114 +75,44 @@ __device__ Aff block_exclusive_scan(Aff m, Aff *agg)
     return compose(excl, wpre);
 }
 
-__device__ __forceinline__ void st_release(unsigned long long *p, unsigned long long v)
+// Composite of n maps taken in application order a = 0..n-1, where map a is
+// agg[idx(a)]: every thread composes a contiguous run, then an ordered tree
+// over the block.  Returns the composite in every thread.
+template <class Idx>
+__device__ Aff compose_ordered(const AffineStatus *agg, int64_t n, Idx idx)
 {
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Look-back over the tiles before `vt` of the same instance, by the 64 lanes
-// of one wave: each round inspects 64 predecessors at once and composes the
-// aggregates up to the nearest inclusive one.  Publishes this tile's
-// aggregate first and its inclusive value last; returns the value entering
-// the tile (in every lane).
-__device__ double affine_lookback(AffineStatus *st, int64_t vt, int64_t lt, Aff agg,
-                                  unsigned long long gen)
-{
-    const int lane = lane_id();
-    if (lt == 0) {
-        if (lane == 0) {
-            st[vt].V = agg.B;  // applied to the boundary value 0
-            st_release(&st[vt].flag, (gen << 2) | 2ull);
-        }
-        return 0.0;
+    __shared__ Aff s_m[kBlock];
+    const int64_t per = (n + kBlock - 1) / kBlock;
+    const int64_t a0 = (int64_t)threadIdx.x * per;
+    Aff m = {1.0, 0.0};
+    for (int64_t a = a0; a < a0 + per && a < n; ++a) {
+        const AffineStatus &s = agg[idx(a)];
+        m = compose(Aff{s.A, s.B}, m);
     }
-    if (lane == 0) {
-        st[vt].A = agg.A;
-        st[vt].B = agg.B;
-        st_release(&st[vt].flag, (gen << 2) | 1ull);
-    }
-    const int64_t p_first = vt - lt;  // tile 0 of the instance: always inclusive
-    Aff R = {1.0, 0.0};               // maps of the closer tiles, applied last
-    double y_in = 0.0;
-    for (int64_t p_hi = vt - 1;; p_hi -= 64) {
-        const int64_t p = p_hi - lane;
-        const bool inr = p >= p_first;
-        unsigned long long f = 0;
-        if (inr) {
-            // poll without acquire (an acquire invalidates the L2 on every poll)
-            do {
-                f = __hip_atomic_load(&st[p].flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            } while ((f >> 2) != gen);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        const bool incl = inr && ((f & 3ull) == 2ull);
-        const unsigned long long mb = ballot(incl);
-        const int k = mb ? (__ffsll((long long)mb) - 1) : 64;
-        Aff m = {1.0, 0.0};
-        if (inr && lane < k) m = Aff{st[p].A, st[p].B};
-        // m_0 o m_1 o ... o m_{k-1} (lane 0 is the closest tile)
-#pragma unroll
-        for (int dd = 1; dd < 64; dd <<= 1) {
-            Aff o;
-            o.A = __shfl_down(m.A, dd, 64);
-            o.B = __shfl_down(m.B, dd, 64);
-            if (lane + dd < 64) m = compose(m, o);
-        }
-        Aff c;
-        c.A = __shfl(m.A, 0, 64);
-        c.B = __shfl(m.B, 0, 64);
-        R = compose(R, c);
-        if (mb) {
-            double V = 0.0;
-            if (lane == k) V = st[p].V;
-            V = __shfl(V, k, 64);
-            y_in = R.A * V + R.B;
-            break;
-        }
-    }
-    if (lane == 0) {
-        st[vt].V = agg.A * y_in + agg.B;
-        st_release(&st[vt].flag, (gen << 2) | 2ull);
-    }
-    return y_in;
-}
-
-__device__ __forceinline__ void scan_ticket(Globals *g, int id, int64_t *vt, unsigned long long *gen)
-{
-    __shared__ uint32_t s_t;
-    __shared__ unsigned long long s_g;
-    if (threadIdx.x == 0) {
-        s_g = __hip_atomic_load(&g->scan_gen[id], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s_t = atomicAdd(&g->scan_ticket[id], 1u);
-    }
+    s_m[threadIdx.x] = m;
     __syncthreads();
-    *vt = s_t;
-    *gen = s_g;
-}
-
-// the last tile to finish resets the ticket counter and advances the generation
-__device__ __forceinline__ void scan_finish(Globals *g, int id, int64_t n_tiles)
-{
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const uint32_t prev = atomicAdd(&g->scan_finish[id], 1u);
-        if ((int64_t)prev == n_tiles - 1) {
-            g->scan_ticket[id] = 0;
-            g->scan_finish[id] = 0;
-            g->scan_gen[id] = g->scan_gen[id] + 1ull;
-            __threadfence();
-        }
+    for (int s = 1; s < kBlock; s <<= 1) {
+        if ((threadIdx.x & (2 * s - 1)) == 0) s_m[threadIdx.x] = compose(s_m[threadIdx.x + s], s_m[threadIdx.x]);
+        __syncthreads();
     }
+    const Aff r = s_m[0];
+    __syncthreads();
+    return r;
+}
+
+// -g_u = u/(u+1): the multiplier of both sweeps at node u
+__device__ __forceinline__ double gq_of(int64_t j)
+{
+    const double u = (double)j;
+    return u / (u + 1.0);
 }
 
 // ---------------------------------------------------------------------------
-// forward sweep: rho, d, d'
+// 1. rho and the forward composite of every tile
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void field_fwd_kernel(Dev d)
+__global__ __launch_bounds__(kBlock) void field_rho_kernel(Dev d)
 {
-    int64_t vt;
-    unsigned long long gen;
-    scan_ticket(d.glob, kScanFwd, &vt, &gen);
+    const int64_t vt = blockIdx.x;
     const int inst = seg_of_tile(d.inst_ftile0, d.n_inst, vt);
     const InstConst &ic = d.instc[inst];
     const int64_t lt = vt - ic.ftile0;
@@ -190,12 +126,58 @@ __global__ __launch_bounds__(kBlock) void field_fwd_kernel(Dev d)
     double rho_bg = 0.0;
     if (periodic) {
         double qn = 0.0;
-        for (int k = 0; k < nsp; ++k) {
-            const SegConst &sc = d.segc[ic.seg0 + k];
-            qn += sc.qw * (double)d.segd[ic.seg0 + k].live;
-        }
+        for (int k = 0; k < nsp; ++k) qn += d.segc[ic.seg0 + k].qw * (double)d.segd[ic.seg0 + k].live;
         rho_bg = -qn / ((double)nc * ic.dx);
     }
+
+    const int64_t j0 = lt * kFieldTile + (int64_t)threadIdx.x * kFieldR;
+    Aff m = {1.0, 0.0};
+#pragma unroll
+    for (int r = 0; r < kFieldR; ++r) {
+        const int64_t j = j0 + r;
+        if (j > nc) continue;
+        double acc = 0.0;
+        for (int k = 0; k < nsp; ++k) {
+            const unsigned long long *S = d.S + k * G + ic.gnode;
+            unsigned long long Sj = S[j];
+            if (periodic) {
+                if (j == 0) Sj += S[nc];
+                if (j == nc) Sj = S[0] + S[nc];
+            }
+            acc += d.segc[ic.seg0 + k].qw * ((double)Sj * two_m32);
+        }
+        double V = ic.dx;
+        if (!periodic && (j == 0 || j == nc)) V = 0.5 * ic.dx;
+        const double rho = acc / V + rho_bg;
+        d.rho[ic.gnode + j] = rho;
+        if (j >= 1 && j <= nc - 1) {
+            const double dd = -(rho * ic.K);
+            const double gq = gq_of(j);
+            m = compose(Aff{gq, -(gq * dd)}, m);
+        }
+    }
+    Aff agg;
+    (void)block_exclusive_scan(m, &agg);
+    if (threadIdx.x == 0) {
+        d.fwd_status[vt].A = agg.A;
+        d.fwd_status[vt].B = agg.B;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 2. forward sweep (d') and the backward composite of every tile
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void field_fwd_kernel(Dev d)
+{
+    const int64_t vt = blockIdx.x;
+    const int inst = seg_of_tile(d.inst_ftile0, d.n_inst, vt);
+    const InstConst &ic = d.instc[inst];
+    const int64_t lt = vt - ic.ftile0;
+    const int nc = ic.nc;
+
+    // d' entering the tile: the composites of the tiles below applied to d'_0 = 0
+    const int64_t first = ic.ftile0;
+    const Aff below = compose_ordered(d.fwd_status, lt, [first](int64_t a) { return first + a; });
 
     const int64_t j0 = lt * kFieldTile + (int64_t)threadIdx.x * kFieldR;
     double dv[kFieldR];
@@ -204,71 +186,69 @@ __global__ __launch_bounds__(kBlock) void field_fwd_kernel(Dev d)
     for (int r = 0; r < kFieldR; ++r) {
         const int64_t j = j0 + r;
         dv[r] = 0.0;
-        if (j <= nc) {
-            double acc = 0.0;
-            for (int k = 0; k < nsp; ++k) {
-                const unsigned long long *S = d.S + k * G + ic.gnode;
-                unsigned long long Sj = S[j];
-                if (periodic) {
-                    if (j == 0) Sj += S[nc];
-                    if (j == nc) Sj = S[0] + S[nc];
-                }
-                acc += d.segc[ic.seg0 + k].qw * ((double)Sj * two_m32);
-            }
-            double V = ic.dx;
-            if (!periodic && (j == 0 || j == nc)) V = 0.5 * ic.dx;
-            const double rho = acc / V + rho_bg;
-            d.rho[ic.gnode + j] = rho;
-            if (j >= 1 && j <= nc - 1) {
-                const double dd = -(rho * ic.K);
-                const double u = (double)j;
-                const double gq = u / (u + 1.0);  // -g_u
-                dv[r] = dd;
-                m = compose(Aff{gq, -(gq * dd)}, m);
-            }
+        if (j >= 1 && j <= nc - 1) {
+            dv[r] = -(d.rho[ic.gnode + j] * ic.K);
+            const double gq = gq_of(j);
+            m = compose(Aff{gq, -(gq * dv[r])}, m);
         }
     }
     Aff agg;
     const Aff excl = block_exclusive_scan(m, &agg);
-    __shared__ double s_in;
-    if (threadIdx.x < 64) {
-        const double y = affine_lookback(d.fwd_status, vt, lt, agg, gen);
-        if (threadIdx.x == 0) s_in = y;
-    }
-    __syncthreads();
-    double y = excl.A * s_in + excl.B;
+    double y = excl.A * below.B + excl.B;
+    double dp[kFieldR];
 #pragma unroll
     for (int r = 0; r < kFieldR; ++r) {
         const int64_t j = j0 + r;
+        dp[r] = 0.0;
         if (j >= 1 && j <= nc - 1) {
-            const double u = (double)j;
-            const double gq = u / (u + 1.0);
+            const double gq = gq_of(j);
             y = gq * y + (-(gq * dv[r]));
             d.dprime[ic.gnode + j] = y;
+            dp[r] = y;
         }
     }
-    scan_finish(d.glob, kScanFwd, d.n_field_tiles);
+    // backward maps phi_u = (u/(u+1)) phi_{u+1} + d'_u of the thread's nodes, top first
+    Aff mb = {1.0, 0.0};
+#pragma unroll
+    for (int r = kFieldR - 1; r >= 0; --r) {
+        const int64_t j = j0 + r;
+        if (j >= 1 && j <= nc - 1) mb = compose(Aff{gq_of(j), dp[r]}, mb);
+    }
+    // the block's composite: threads from the top down
+    __shared__ Aff s_b[kBlock];
+    s_b[kBlock - 1 - threadIdx.x] = mb;
+    __syncthreads();
+    for (int s = 1; s < kBlock; s <<= 1) {
+        if ((threadIdx.x & (2 * s - 1)) == 0) s_b[threadIdx.x] = compose(s_b[threadIdx.x + s], s_b[threadIdx.x]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        d.bwd_status[vt].A = s_b[0].A;
+        d.bwd_status[vt].B = s_b[0].B;
+    }
 }
 
 // ---------------------------------------------------------------------------
-// backward sweep: phi, E, acc, field-energy partials; clears the deposit
+// 3. backward sweep: phi, E, acc, field-energy partials; clears the deposit
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void field_bwd_kernel(Dev d)
 {
-    int64_t vt_r;
-    unsigned long long gen;
-    scan_ticket(d.glob, kScanBwd, &vt_r, &gen);
-    // tickets run from the top tile of each instance down
-    const int inst = seg_of_tile(d.inst_ftile0, d.n_inst, vt_r);
+    const int64_t vt = blockIdx.x;
+    const int inst = seg_of_tile(d.inst_ftile0, d.n_inst, vt);
     const InstConst &ic = d.instc[inst];
     const int64_t ntl = d.inst_ftile0[inst + 1] - ic.ftile0;
-    const int64_t lt_r = vt_r - ic.ftile0;        // 0 = top tile
-    const int64_t lt = ntl - 1 - lt_r;            // node tile index
+    const int64_t lt = vt - ic.ftile0;
     const int nc = ic.nc;
     const bool periodic = (ic.bc == PIC_BC_PERIODIC);
     const int64_t G = d.G;
     const int nsp = ic.nsp;
     const double dx = ic.dx;
+
+    // phi at the first node above the tile: the composites of the tiles
+    // above, top first, applied to phi_nc = 0
+    const int64_t last = ic.ftile0 + ntl - 1;
+    const Aff above = compose_ordered(d.bwd_status, ntl - 1 - lt, [last](int64_t a) { return last - a; });
+    const double phi_above = above.B;
 
     // thread t owns the chunk counted from the top of the tile
     const int64_t lo = lt * kFieldTile;
@@ -282,19 +262,11 @@ __global__ __launch_bounds__(kBlock) void field_bwd_kernel(Dev d)
         dp[r] = 0.0;
         if (j >= 1 && j <= nc - 1) {
             dp[r] = d.dprime[ic.gnode + j];
-            const double u = (double)j;
-            m = compose(Aff{u / (u + 1.0), dp[r]}, m);
+            m = compose(Aff{gq_of(j), dp[r]}, m);
         }
     }
     Aff agg;
     const Aff excl = block_exclusive_scan(m, &agg);
-    __shared__ double s_in;
-    if (threadIdx.x < 64) {
-        const double y = affine_lookback(d.bwd_status, vt_r, lt_r, agg, gen);
-        if (threadIdx.x == 0) s_in = y;
-    }
-    __syncthreads();
-    const double phi_above = s_in;  // phi at the node just above this tile (0 at the top)
 
     // phi for the thread's nodes, top down
     double ph[kFieldR];
@@ -303,8 +275,7 @@ __global__ __launch_bounds__(kBlock) void field_bwd_kernel(Dev d)
     for (int r = kFieldR - 1; r >= 0; --r) {
         const int64_t j = j0 + r;
         if (j >= 1 && j <= nc - 1) {
-            const double u = (double)j;
-            y = (u / (u + 1.0)) * y + dp[r];
+            y = gq_of(j) * y + dp[r];
             ph[r] = y;
         } else {
             ph[r] = 0.0;  // nodes 0 and nc (and beyond the grid)
@@ -314,22 +285,13 @@ __global__ __launch_bounds__(kBlock) void field_bwd_kernel(Dev d)
     __shared__ double s_phi[kFieldTile + 2];
 #pragma unroll
     for (int r = 0; r < kFieldR; ++r) s_phi[1 + c * kFieldR + r] = ph[r];
+    __syncthreads();
     if (threadIdx.x == 0) {
         const int64_t hi1 = lo + kFieldTile;  // first node above the tile
         s_phi[kFieldTile + 1] = (hi1 <= nc - 1) ? phi_above : 0.0;
         double below = 0.0;                   // phi at node lo - 1
-        if (lo - 1 >= 1) {
-            const double u = (double)(lo - 1);
-            below = (u / (u + 1.0)) * s_phi[1] + d.dprime[ic.gnode + lo - 1];
-        }
+        if (lo - 1 >= 1) below = gq_of(lo - 1) * s_phi[1] + d.dprime[ic.gnode + lo - 1];
         s_phi[0] = below;
-    }
-    __syncthreads();
-    // s_phi[1 + 0] is written by the thread owning chunk 0 before the barrier;
-    // recompute `below` after it if thread 0 did not own chunk 0
-    if (threadIdx.x == 0 && lo - 1 >= 1) {
-        const double u = (double)(lo - 1);
-        s_phi[0] = (u / (u + 1.0)) * s_phi[1] + d.dprime[ic.gnode + lo - 1];
     }
     __syncthreads();
 
@@ -388,14 +350,16 @@ __global__ __launch_bounds__(kBlock) void field_bwd_kernel(Dev d)
         __syncthreads();
     }
     if (threadIdx.x == 0) d.fe_part[ic.ftile0 + lt] = s_fe[0];
-    scan_finish(d.glob, kScanBwd, d.n_field_tiles);
 }
 
 hipError_t launch_field(const Dev &d, hipStream_t st)
 {
     const dim3 grid((unsigned)d.n_field_tiles), block(kBlock);
-    hipLaunchKernelGGL(field_fwd_kernel, grid, block, 0, st, d);
+    hipLaunchKernelGGL(field_rho_kernel, grid, block, 0, st, d);
     hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(field_fwd_kernel, grid, block, 0, st, d);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(field_bwd_kernel, grid, block, 0, st, d);
     return hipGetLastError();

@@ -3,8 +3,9 @@
 //
 // Null-collision Monte Carlo (Vahedi & Surendra, CPC 87, 1995) against a
 // uniform neutral gas.  The push kernel already tested every particle with
-// one Philox block keyed by (id, step) and listed the candidates; here each
-// candidate redraws that block, picks a process from r = U(u1) nu_max against
+// one Philox block keyed by (id, step) and listed the candidates with their
+// velocities and ids; here each candidate redraws that block (collide_vel),
+// picks a process from r = U(u1) nu_max against
 // the cumulative n_n sigma |v| (squared comparisons, FP64), and applies
 //   elastic e-n   cold neutral of mass M, isotropic in the centre of mass;
 //   charge exch.  the ion takes a neutral's Maxwellian velocity (T_n);
@@ -24,76 +25,35 @@
 
 namespace picx {
 
-__device__ __forceinline__ double ld_v(const void *p, int64_t g, bool f64)
-{
-    return f64 ? ((const double *)p)[g] : (double)((const float *)p)[g];
-}
-
 __device__ __forceinline__ void st_v(void *p, int64_t g, double v, bool f64)
 {
     if (f64) ((double *)p)[g] = v;
     else ((float *)p)[g] = (float)v;
 }
 
-enum { kCCand = 0, kCEl = 1, kCIz = 2, kCCx = 3, kCOver = 4 };
-
-// collide one candidate at slot g; returns its segment, fills the counts and
-// the ionisation event
-__device__ __forceinline__ int collide_one(const Dev &d, int cur, bool f64, int64_t g,
+// collide one listed candidate; returns its segment, fills the counts and
+// the ionisation event, and stores the velocity of a particle that collided
+__device__ __forceinline__ int collide_one(const Dev &d, int cur, bool f64, const Cand &c,
                                            uint32_t (&cnt)[kNCnt], bool &iz, IzEvent &ev)
 {
+    const int64_t g = c.g;
     const int seg = seg_of_slot(d.seg_base, d.n_seg, g);
     const SegConst &sc = d.segc[seg];
     const long long step = d.instd[sc.inst].step;
-    const unsigned long long pid = d.id[cur][g];
-    const double vx = ld_v(d.vx[cur], g, f64);
-    const double vy = ld_v(d.vy[cur], g, f64);
-    const double vz = ld_v(d.vz[cur], g, f64);
-    const uint4 u = draw(pid, step, 0, sc.key0, sc.key1);
-    const double v2 = (vx * vx + vy * vy) + vz * vz;
-    cnt[kCCand] = 1;
-    if (v2 > sc.vcap2) cnt[kCOver] = 1;
-    const double r = u01(u.y) * sc.nu_max;
-    const double r2 = r * r;
-    if (sc.kind == PIC_KIND_ELECTRON) {
-        if (r2 < sc.C0 * v2) {
-            double d0, d1, d2;
-            iso_dir(u.z, u.w, d0, d1, d2);
-            const double gg = sqrt(v2);
-            st_v(d.vx[cur], g, sc.am * vx + sc.bm * gg * d0, f64);
-            st_v(d.vy[cur], g, sc.am * vy + sc.bm * gg * d1, f64);
-            st_v(d.vz[cur], g, sc.am * vz + sc.bm * gg * d2, f64);
-            cnt[kCEl] = 1;
-        } else if (v2 >= sc.v2_iz && r2 < sc.C1 * v2) {
-            const uint4 u1 = draw(pid, step, 1, sc.key0, sc.key1);
-            const double e_tot = 0.5 * v2 - sc.eps_iz;
-            const double e1 = u01(u.z) * e_tot;
-            const double e2 = e_tot - e1;
-            const double g1 = sqrt(2.0 * e1);
-            double d0, d1, d2;
-            iso_dir(u1.x, u1.y, d0, d1, d2);
-            st_v(d.vx[cur], g, g1 * d0, f64);
-            st_v(d.vy[cur], g, g1 * d1, f64);
-            st_v(d.vz[cur], g, g1 * d2, f64);
-            iz = true;
-            ev.parent_id = pid;
-            ev.slot = (uint32_t)g;
-            ev.seg = seg;
-            ev.inst = sc.inst;
-            ev.g2 = sqrt(2.0 * e2);
-            cnt[kCIz] = 1;
-        }
-    } else {
-        if (r2 < sc.C0 * v2) {
-            const uint4 u1 = draw(pid, step, 1, sc.key0, sc.key1);
-            double n0, n1, n2, n3;
-            box_muller(u.z, u.w, n0, n1);
-            box_muller(u1.x, u1.y, n2, n3);
-            st_v(d.vx[cur], g, sc.sig_n * n0, f64);
-            st_v(d.vy[cur], g, sc.sig_n * n1, f64);
-            st_v(d.vz[cur], g, sc.sig_n * n2, f64);
-            cnt[kCCx] = 1;
-        }
+    double vx = c.vx, vy = c.vy, vz = c.vz;
+    double g2 = 0.0;
+    collide_vel(sc, step, c.pid, vx, vy, vz, cnt, iz, g2);
+    if (cnt[kCEl] | cnt[kCIz] | cnt[kCCx]) {
+        st_v(d.vx[cur], g, vx, f64);
+        st_v(d.vy[cur], g, vy, f64);
+        st_v(d.vz[cur], g, vz, f64);
+    }
+    if (iz) {
+        ev.parent_id = c.pid;
+        ev.slot = (uint32_t)g;
+        ev.seg = seg;
+        ev.inst = sc.inst;
+        ev.g2 = g2;
     }
     return seg;
 }
@@ -133,7 +93,7 @@ __global__ __launch_bounds__(kBlock) void collide_kernel(Dev d)
         IzEvent ev = {};
         const int64_t idx = q < nr ? (int64_t)blockIdx.x * kCandQ + q
                                    : (int64_t)d.n_push_blocks * kCandQ + o_lo + (q - nr);
-        const int seg = collide_one(d, cur, f64, (int64_t)d.cand[idx], cnt, iz, ev);
+        const int seg = collide_one(d, cur, f64, d.cand[idx], cnt, iz, ev);
         if (iz) {
             // LDS queue of this block; the rare excess goes to the overflow list
             const uint32_t e = atomicAdd(&s_en, 1u);
@@ -267,6 +227,12 @@ constexpr int kMaxInstLds = 4096;
 // per-instance ionisation counts of this step (into LDS)
 __device__ void count_events(const EventIndex &X, const Dev &d, uint32_t *s_m, int n_inst)
 {
+    if (d.n_inst == 1) {
+        // a single instance owns every event
+        if (threadIdx.x == 0) s_m[0] = X.total;
+        __syncthreads();
+        return;
+    }
     for (int i = threadIdx.x; i < n_inst; i += kBlock) s_m[i] = 0u;
     __syncthreads();
     for (uint32_t e = threadIdx.x; e < X.total; e += kBlock) {
@@ -284,6 +250,48 @@ __device__ __forceinline__ uint32_t source_pairs(const Dev &d, int i)
     return d.segd[ic.seg_i].absorbed_step[0] + d.segd[ic.seg_i].absorbed_step[1];
 }
 
+// Rank of every ionisation event among the events of its instance, ordered
+// by parent id: ev_rank[e] = #{k : inst_k == inst_e, pid_k < pid_e}.  The
+// pairs (event block of kBlock, comparison block of kRankJ) are spread over
+// the grid; each adds its partial count to ev_rank (zero at entry).
+__global__ __launch_bounds__(kBlock) void rank_kernel(Dev d)
+{
+    __shared__ EventIndex X;
+    build_event_index(X, d);
+    const uint64_t m = X.total;
+    const uint64_t ni = (m + kBlock - 1) / kBlock;
+    const uint64_t nj = (m + kRankJ - 1) / kRankJ;
+    __shared__ unsigned long long s_pid[kRankJ];
+    __shared__ int s_inst[kRankJ];
+    for (uint64_t p = blockIdx.x; p < ni * nj; p += gridDim.x) {
+        const uint64_t bi = p / nj, bj = p - bi * nj;
+        __syncthreads();
+        if (threadIdx.x < kRankJ) {
+            const uint64_t k = bj * kRankJ + threadIdx.x;
+            unsigned long long pid = ~0ull;
+            int inst = -2;
+            if (k < m) {
+                const IzEvent &o = event_at(X, d, (uint32_t)k);
+                pid = o.parent_id;
+                inst = o.inst;
+            }
+            s_pid[threadIdx.x] = pid;
+            s_inst[threadIdx.x] = inst;
+        }
+        __syncthreads();
+        const uint64_t e = bi * kBlock + threadIdx.x;
+        if (e < m) {
+            const IzEvent &ev = event_at(X, d, (uint32_t)e);
+            const unsigned long long pid = ev.parent_id;
+            const int inst = ev.inst;
+            uint32_t r = 0;
+#pragma unroll 16
+            for (int q = 0; q < kRankJ; ++q) r += (s_inst[q] == inst && s_pid[q] < pid) ? 1u : 0u;
+            if (r) atomicAdd(&d.ev_rank[e], r);
+        }
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void emit_kernel(Dev d)
 {
     __shared__ EventIndex X;
@@ -293,35 +301,11 @@ __global__ __launch_bounds__(kBlock) void emit_kernel(Dev d)
     const uint32_t m_all = X.total;
     const uint32_t stride = gridDim.x * kBlock;
 
-    // ---- ionisation pairs: rank each event among its instance's events by parent id
-    __shared__ unsigned long long s_pid[kBlock];
-    __shared__ int s_inst[kBlock];
-    for (uint32_t base = blockIdx.x * kBlock; base < m_all; base += stride) {
-        const uint32_t e = base + threadIdx.x;
-        const bool own = e < m_all;
-        IzEvent ev = {};
-        if (own) ev = event_at(X, d, e);
-        uint32_t rank = 0;
-        for (uint32_t cb = 0; cb < m_all; cb += kBlock) {
-            __syncthreads();
-            const uint32_t k = cb + threadIdx.x;
-            if (k < m_all) {
-                const IzEvent &o = event_at(X, d, k);
-                s_pid[threadIdx.x] = o.parent_id;
-                s_inst[threadIdx.x] = o.inst;
-            } else {
-                s_pid[threadIdx.x] = ~0ull;
-                s_inst[threadIdx.x] = -2;
-            }
-            __syncthreads();
-            if (own) {
-                // unrolled so that many LDS reads are in flight at once
-#pragma unroll 32
-                for (int q = 0; q < kBlock; ++q)
-                    rank += (s_inst[q] == ev.inst && s_pid[q] < ev.parent_id) ? 1u : 0u;
-            }
-        }
-        if (own) {
+    // ---- ionisation pairs, at in-segment index count + rank and ids next_id + 2 rank
+    for (uint32_t e = blockIdx.x * kBlock + threadIdx.x; e < m_all; e += stride) {
+        const IzEvent ev = event_at(X, d, e);
+        const uint32_t rank = d.ev_rank[e];
+        {
             const SegConst &se = d.segc[ev.seg];
             const int seg_i = se.partner;
             const SegConst &si = d.segc[seg_i];
@@ -450,6 +434,9 @@ __global__ __launch_bounds__(kBlock) void close_step_kernel(Dev d, int with_even
         d.glob->cand_ovf = 0;
         d.glob->ev_ovf = 0;
     }
+    // ranks back to zero for the next step
+    if (with_events)
+        for (uint32_t e = threadIdx.x; e < X.total; e += kBlock) d.ev_rank[e] = 0u;
     // empty event regions for a step without collisions
     if (!with_events)
         for (int b = threadIdx.x; b < d.n_push_blocks; b += kBlock) d.ev_n[b] = 0u;
@@ -463,6 +450,11 @@ hipError_t launch_collide(const Dev &d, hipStream_t st)
 
 hipError_t launch_emit(const Dev &d, hipStream_t st, bool pairs, bool events)
 {
+    if (events) {
+        hipLaunchKernelGGL(rank_kernel, dim3(kRankBlocks), dim3(kBlock), 0, st, d);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     if (pairs) {
         hipLaunchKernelGGL(emit_kernel, dim3(kEmitBlocks), dim3(kBlock), 0, st, d);
         const hipError_t e = hipGetLastError();

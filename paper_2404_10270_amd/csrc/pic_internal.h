@@ -16,7 +16,7 @@ constexpr int kBlock = 256;                 // threads per block of the particle
 constexpr int kWaves = kBlock / 64;         // wave64 per block
 constexpr int kPer = 4;                     // 64-particle chunks per wave per tile
 constexpr int kTile = kBlock * kPer;        // particles per tile (contiguous)
-constexpr int kFieldR = 16;                 // nodes per thread in the field scans
+constexpr int kFieldR = 4;                  // nodes per thread in the field scans
 constexpr int kFieldTile = kBlock * kFieldR;
 constexpr int kSortR = 8;                   // bins per thread in the sort scan
 constexpr int kSortTile = kBlock * kSortR;
@@ -24,10 +24,12 @@ constexpr int kDiagBlocks = 1024;           // blocks of the diagnostics reducti
 constexpr int kEmitBlocks = 64;             // blocks of the emit/close-of-step kernel
 constexpr int kDiagVals = 6;                // live, sum v2, sum vx, vy, vz, (pad)
 constexpr int kMaxPushBlocks = 256 * 8;     // persistent grid of the particle kernels
-constexpr int kCandQ = 2048;                // candidate slots per push block (LDS queue)
+constexpr int kCandQ = 1024;                // candidate entries per push block region
 constexpr int kEvQ = 32;                    // ionisation-event slots per collide block
 constexpr int kCntSeg = 64;                 // segments counted per block without atomics
 constexpr int kNCnt = 5;                    // candidates, elastic, ionisation, CX, over v_cap
+constexpr int kRankJ = 64;                  // events compared per block pass of the rank kernel
+constexpr int kRankBlocks = 512;            // grid of the rank kernel
 
 constexpr int32_t kDeadCell = -1;           // FP32 form: cell of an absorbed particle
 constexpr double kDeadX = -1.0;             // FP64 form: position of an absorbed particle
@@ -95,13 +97,22 @@ struct Globals {
     uint32_t cand_ovf;       // candidates in the overflow list this step
     uint32_t ev_ovf;         // ionisation events in the overflow list this step
     uint32_t pad[5];
-    // self-resetting single-pass scans: ticket counter, finish counter, generation
+    // self-resetting single-pass scan (the sort): ticket counter, finish counter, generation
     uint32_t scan_ticket[4];
     uint32_t scan_finish[4];
     unsigned long long scan_gen[4];
 };
 
-enum ScanId { kScanFwd = 0, kScanBwd = 1, kScanSort = 2 };
+enum ScanId { kScanSort = 2 };
+
+// collision candidate listed by the mover: its slot, its velocity after the
+// push (cells/step, exact in FP64 for both forms) and its id
+struct Cand {
+    uint32_t g;
+    uint32_t _pad;
+    double vx, vy, vz;
+    unsigned long long pid;
+};
 
 // ionisation event recorded by the collide kernel for the emit kernel
 struct IzEvent {
@@ -113,11 +124,9 @@ struct IzEvent {
     double g2;              // speed of the secondary electron, cells/step
 };
 
-// look-back status of one tile of an affine (Thomas) scan
+// composite y -> A y + B of the maps of one tile of an affine (Thomas) sweep
 struct AffineStatus {
-    unsigned long long flag;   // gen * 4 + {0: none, 1: aggregate, 2: inclusive}
-    double A, B;               // aggregate map y -> A y + B (never overwritten in a launch)
-    double V;                  // inclusive value, valid once the flag says inclusive
+    double A, B;
 };
 
 // ---------------------------------------------------------------------------
@@ -130,7 +139,7 @@ struct Layout {
     uint64_t hist, cursor, offsets, seg_start;
     uint64_t fwd_status, bwd_status, sort_status;
     uint64_t fe_part;
-    uint64_t cand, cand_n, ev, ev_n, cnt_slot;
+    uint64_t cand, cand_n, ev, ev_n, ev_rank, cnt_slot;
     uint64_t diag_part, diag_out;
     uint64_t total;
     int64_t cand_ovf_cap, ev_ovf_cap;
@@ -164,10 +173,11 @@ struct Dev {
     AffineStatus *fwd_status, *bwd_status;
     unsigned long long *sort_status;
     double *fe_part;
-    uint32_t *cand;             // [n_push_blocks][kCandQ] per-block regions, then the overflow list
+    Cand *cand;                 // [n_push_blocks][kCandQ] per-block regions, then the overflow list
     uint32_t *cand_n;           // [n_push_blocks] candidates in each region
     IzEvent *ev;                // [n_push_blocks][kEvQ] per-block regions, then the overflow list
     uint32_t *ev_n;             // [n_push_blocks] events in each region
+    uint32_t *ev_rank;          // [events] rank of each event among its instance's (by parent id)
     unsigned long long *cnt_slot;  // [n_push_blocks][kCntSeg][kNCnt] process counts per block
     double *diag_part;
     pic_diag *diag_out;
@@ -182,7 +192,9 @@ struct Dev {
 // launchers (each enqueues on `st`; return hipError_t)
 // ---------------------------------------------------------------------------
 hipError_t launch_init_state(const Dev &d, hipStream_t st, const uint32_t *n_init_dev);
-hipError_t launch_push(const Dev &d, hipStream_t st, bool deposit, bool mcc);
+// mcc: 0 no collisions, 1 list the candidates (pic_mcc_collide collides them),
+// 2 collide in the mover
+hipError_t launch_push(const Dev &d, hipStream_t st, bool deposit, int mcc);
 hipError_t launch_deposit(const Dev &d, hipStream_t st);
 hipError_t launch_field(const Dev &d, hipStream_t st);
 hipError_t launch_collide(const Dev &d, hipStream_t st);

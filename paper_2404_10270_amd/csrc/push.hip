@@ -4,7 +4,8 @@
 // One pass per particle and step: linear gather of the grid acceleration at
 // the in-cell offset, magnetised Boris velocity update, advance x += vx,
 // absorbing or periodic walls, the null-collision candidate test (one Philox
-// block keyed by id and step), and the deposit of the new position.
+// block keyed by id and step), optionally the collisions themselves (paper
+// Sec. 2, phase 4), and the deposit of the new position.
 //
 // Memory plan (HBM-bound):
 //  * structure-of-arrays streamed once; a block owns a tile of kTile
@@ -16,8 +17,15 @@
 //  * the deposit of cell-sorted neighbours is summed first over runs of equal
 //    cells inside each wave, then into an LDS window of nodes, and the window
 //    is flushed with one 64-bit global atomic per touched node per tile;
-//  * collision candidates go to an LDS queue that each block writes to its
-//    own region of the candidate list at the end (no atomics); only a block
+//  * collisions in the mover (MCC = kMccCollide): the block compacts its
+//    candidates into LDS slots while their velocities are still in
+//    registers, one thread per slot collides, the owners take the new
+//    velocities back, and every particle is stored once; ionisation events
+//    go to the block's own region of the event list, process counts to the
+//    block's own slot;
+//  * otherwise (MCC = kMccList) each candidate, with its velocity and id,
+//    goes to its block's own region of the candidate list (index from an LDS
+//    counter), so the collide kernel reads them contiguously; only a block
 //    with more than kCandQ candidates appends the excess to a shared
 //    overflow list.
 #include "device_common.h"
@@ -28,16 +36,30 @@ namespace picx {
 
 constexpr int kDepWin = 1024;     // LDS deposit window, nodes
 constexpr int kSegLds = 256;      // segments whose tables are staged in LDS
+constexpr int kCollQ = kBlock;    // collision slots per block pass (one per thread)
+
+// collisions in the mover: none, list the candidates, or collide in place
+enum { kMccOff = 0, kMccList = 1, kMccCollide = 2 };
+
+struct CollSlot {
+    double vx, vy, vz;
+    unsigned long long pid;
+    uint32_t g;
+    uint32_t _pad;
+};
 
 struct PushLds {
     unsigned long long dep[kDepWin];
-    uint32_t cq[kCandQ];
+    CollSlot cs[kCollQ];
     int64_t tile0[kSegLds + 1];
     int64_t base[kSegLds];
     uint32_t count[kSegLds];
+    IzEvent ev[kEvQ];
+    uint32_t cnt[kCntSeg][kNCnt];
     uint32_t cn;
-    uint32_t gbase;
+    uint32_t en;
     int red[2][kWaves];
+    int wsum[kWaves];
 };
 
 __device__ __forceinline__ void push_lds_init(PushLds &L, const Dev &d)
@@ -52,7 +74,11 @@ __device__ __forceinline__ void push_lds_init(PushLds &L, const Dev &d)
             }
         }
     }
-    if (threadIdx.x == 0) L.cn = 0;
+    for (int q = threadIdx.x; q < kCntSeg * kNCnt; q += kBlock) (&L.cnt[0][0])[q] = 0u;
+    if (threadIdx.x == 0) {
+        L.cn = 0;
+        L.en = 0;
+    }
     __syncthreads();
 }
 
@@ -156,10 +182,14 @@ __device__ __forceinline__ void deposit_tile(PushLds &L, unsigned long long *__r
     // the next use of the window is ordered by the next call's first barrier
 }
 
-// Candidates go to the block's LDS queue while it has room; a wave whose
-// candidates do not fit appends the excess to the shared overflow list.
+// A candidate is written, with its velocity after the push and its id, to
+// the block's own region of the candidate list (the index comes from an LDS
+// counter); a wave whose candidates do not fit appends the excess to the
+// shared overflow list.
+template <typename V>
 __device__ __forceinline__ void queue_candidate(PushLds &L, const Dev &d, bool cand, uint32_t g,
-                                                int inst)
+                                                int inst, V vx, V vy, V vz,
+                                                unsigned long long pid)
 {
     const unsigned long long m = ballot(cand);
     if (!m) return;
@@ -170,35 +200,173 @@ __device__ __forceinline__ void queue_candidate(PushLds &L, const Dev &d, bool c
     uint32_t base = 0;
     if (lane == leader) base = atomicAdd(&L.cn, n);
     base = __shfl(base, leader, 64);
-    // the first n_lds candidates fill the rest of the queue, the others overflow
+    // the first n_reg candidates fill the rest of the region, the others overflow
     const uint32_t room = base < (uint32_t)kCandQ ? (uint32_t)kCandQ - base : 0u;
-    const uint32_t n_lds = n < room ? n : room;
-    if (cand && rank < n_lds) L.cq[base + rank] = g;
-    if (n_lds == n) return;
+    const uint32_t n_reg = n < room ? n : room;
     uint32_t gb = 0;
-    if (lane == leader) gb = atomicAdd(&d.glob->cand_ovf, n - n_lds);
-    gb = __shfl(gb, leader, 64);
-    if (cand && rank >= n_lds) {
-        const uint32_t idx = gb + (rank - n_lds);
-        if (idx < (uint32_t)d.cand_ovf_cap) d.cand[(int64_t)d.n_push_blocks * kCandQ + idx] = g;
-        else atomicOr(&d.instd[inst].status, PIC_ST_CANDIDATES);
+    if (n_reg != n) {
+        if (lane == leader) gb = atomicAdd(&d.glob->cand_ovf, n - n_reg);
+        gb = __shfl(gb, leader, 64);
     }
+    if (!cand) return;
+    int64_t idx;
+    if (rank < n_reg) {
+        idx = (int64_t)blockIdx.x * kCandQ + base + rank;
+    } else {
+        const uint32_t o = gb + (rank - n_reg);
+        if (o >= (uint32_t)d.cand_ovf_cap) {
+            atomicOr(&d.instd[inst].status, PIC_ST_CANDIDATES);
+            return;
+        }
+        idx = (int64_t)d.n_push_blocks * kCandQ + o;
+    }
+    Cand c;
+    c.g = g;
+    c._pad = 0;
+    c.vx = (double)vx;
+    c.vy = (double)vy;
+    c.vz = (double)vz;
+    c.pid = pid;
+    d.cand[idx] = c;
 }
 
-// write the LDS queue to this block's region of the candidate list
+// the number of entries in this block's region
 __device__ __forceinline__ void flush_candidates(PushLds &L, const Dev &d)
 {
     __syncthreads();
-    const uint32_t n = min(L.cn, (uint32_t)kCandQ);
-    uint32_t *dst = d.cand + (int64_t)blockIdx.x * kCandQ;
-    for (uint32_t i = threadIdx.x; i < n; i += kBlock) dst[i] = L.cq[i];
-    if (threadIdx.x == 0) d.cand_n[blockIdx.x] = n;
+    if (threadIdx.x == 0) d.cand_n[blockIdx.x] = min(L.cn, (uint32_t)kCandQ);
+}
+
+// Collisions of the tile's candidates while the particles are in registers
+// (FP32 or FP64 velocities).  The candidates are ranked over the block,
+// copied kCollQ at a time into LDS slots, collided one per thread, and taken
+// back by their owners.  Barriers inside; every thread must call it, and the
+// number of passes is uniform over the block.  g0 is the slot of chunk 0 of
+// this thread; chunk k is at g0 + 64 k.
+template <typename V>
+__device__ __forceinline__ void collide_tile(PushLds &L, const Dev &d, const SegConst &sc, int seg,
+                                             long long step, const bool (&cand)[kPer],
+                                             const unsigned long long (&pid)[kPer],
+                                             V (&vx)[kPer], V (&vy)[kPer], V (&vz)[kPer],
+                                             int64_t g0)
+{
+    const int lane = lane_id();
+    const int wave = threadIdx.x >> 6;
+    int c = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) c += cand[k] ? 1 : 0;
+    int inc = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += t;
+    }
+    if (lane == 63) L.wsum[wave] = inc;
+    __syncthreads();
+    int pos = inc - c, total = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        if (w < wave) pos += L.wsum[w];
+        total += L.wsum[w];
+    }
+    const bool lds_cnt = d.n_seg <= kCntSeg;
+    for (int r0 = 0; r0 < total; r0 += kCollQ) {
+        int p = pos;
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            if (!cand[k]) continue;
+            if (p >= r0 && p < r0 + kCollQ) {
+                CollSlot &cs = L.cs[p - r0];
+                cs.vx = (double)vx[k];
+                cs.vy = (double)vy[k];
+                cs.vz = (double)vz[k];
+                cs.pid = pid[k];
+                cs.g = (uint32_t)(g0 + 64 * k);
+            }
+            ++p;
+        }
+        __syncthreads();
+        if (threadIdx.x < min(kCollQ, total - r0)) {
+            CollSlot &cs = L.cs[threadIdx.x];
+            uint32_t cnt[kNCnt] = {0, 0, 0, 0, 0};
+            bool iz = false;
+            double g2 = 0.0;
+            double nvx = cs.vx, nvy = cs.vy, nvz = cs.vz;
+            collide_vel(sc, step, cs.pid, nvx, nvy, nvz, cnt, iz, g2);
+            cs.vx = nvx;
+            cs.vy = nvy;
+            cs.vz = nvz;
+            if (lds_cnt) {
+#pragma unroll
+                for (int q = 0; q < kNCnt; ++q)
+                    if (cnt[q]) atomicAdd(&L.cnt[seg][q], cnt[q]);
+            } else {
+                InstDyn *idn = d.instd + sc.inst;
+                atomicAdd(&idn->n_candidates, (unsigned long long)cnt[kCCand]);
+                if (cnt[kCEl]) atomicAdd(&idn->n_elastic, 1ull);
+                if (cnt[kCIz]) atomicAdd(&idn->n_ionize, 1ull);
+                if (cnt[kCCx]) atomicAdd(&idn->n_cx, 1ull);
+                if (cnt[kCOver]) atomicAdd(&idn->n_over_cap, 1ull);
+            }
+            if (iz) {
+                IzEvent ev;
+                ev.parent_id = cs.pid;
+                ev.slot = cs.g;
+                ev.seg = seg;
+                ev.inst = sc.inst;
+                ev._pad = 0;
+                ev.g2 = g2;
+                // the block's LDS queue; the rare excess goes to the overflow list
+                const uint32_t e = atomicAdd(&L.en, 1u);
+                if (e < (uint32_t)kEvQ) {
+                    L.ev[e] = ev;
+                } else {
+                    const uint32_t o = atomicAdd(&d.glob->ev_ovf, 1u);
+                    if (o < (uint32_t)d.ev_ovf_cap) d.ev[(int64_t)d.n_push_blocks * kEvQ + o] = ev;
+                    else atomicOr(&d.instd[sc.inst].status, PIC_ST_CANDIDATES);
+                }
+            }
+        }
+        __syncthreads();
+        p = pos;
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            if (!cand[k]) continue;
+            if (p >= r0 && p < r0 + kCollQ) {
+                const CollSlot &cs = L.cs[p - r0];
+                vx[k] = (V)cs.vx;
+                vy[k] = (V)cs.vy;
+                vz[k] = (V)cs.vz;
+            }
+            ++p;
+        }
+        __syncthreads();
+    }
+    // orders this tile's reads of wsum before the next tile's writes
+    if (total == 0) __syncthreads();
+}
+
+// end of the launch: the block's events to its region, its counts to its slot
+__device__ __forceinline__ void flush_collisions(PushLds &L, const Dev &d)
+{
+    __syncthreads();
+    const uint32_t ne = min(L.en, (uint32_t)kEvQ);
+    for (uint32_t e = threadIdx.x; e < ne; e += kBlock) d.ev[(int64_t)blockIdx.x * kEvQ + e] = L.ev[e];
+    if (threadIdx.x == 0) d.ev_n[blockIdx.x] = ne;
+    if (d.n_seg <= kCntSeg) {
+        // this block's own slot: plain read-modify-write, no other block touches it
+        unsigned long long *slot = d.cnt_slot + (int64_t)blockIdx.x * kCntSeg * kNCnt;
+        for (int q = threadIdx.x; q < d.n_seg * kNCnt; q += kBlock) {
+            const uint32_t v = (&L.cnt[0][0])[q];
+            if (v) slot[q] += v;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
 // FP32 form: (int32 cell, float f in [0,1), float v), FP32 gather and push
 // ---------------------------------------------------------------------------
-template <bool DEP, bool MCC>
+template <bool DEP, int MCC>
 __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
 {
     __shared__ PushLds L;
@@ -237,7 +405,7 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
                 vx[k] = VX[g];
                 vy[k] = VY[g];
                 vz[k] = VZ[g];
-                if (MCC) pid[k] = ID[g];
+                if (MCC != kMccOff) pid[k] = ID[g];
             }
             lv[k] = j[k] >= 0;
         }
@@ -252,7 +420,7 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
         const unsigned long long T = sc.T;
         const int inst = sc.inst;
         long long step = 0;
-        if (MCC) step = d.instd[inst].step;
+        if (MCC != kMccOff) step = d.instd[inst].step;
         // ---- gather
         float a0[kPer], a1[kPer];
 #pragma unroll
@@ -319,13 +487,14 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
             if (j[k] >= 0) {
                 key[k] = j[k];
                 w1[k] = (unsigned long long)rintf(fn * 4294967296.0f);
-                if (MCC) {
+                if (MCC != kMccOff) {
                     const uint4 u = draw(pid[k], step, 0, key0, key1);
                     cand[k] = (unsigned long long)u.x < T;
                 }
             }
         }
-        // ---- stores (no reads after this point in the tile touch these arrays)
+        // ---- stores of the positions, and of the velocities unless they may
+        // still collide (no reads after this point in the tile touch these arrays)
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
             const int64_t i = t0 + (int64_t)(wave * kPer + k) * 64 + lane;
@@ -333,9 +502,11 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
                 const int64_t g = base + i;
                 X[g] = f[k];
                 CELL[g] = j[k];
-                VX[g] = vx[k];
-                VY[g] = vy[k];
-                VZ[g] = vz[k];
+                if (MCC != kMccCollide) {
+                    VX[g] = vx[k];
+                    VY[g] = vy[k];
+                    VZ[g] = vz[k];
+                }
             }
         }
         // ---- rare events: wall losses, flags
@@ -359,23 +530,39 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
             wave_or(&idn->status, PIC_ST_NONFINITE, bad);
         }
         // ---- candidates and deposit through LDS
-        if (MCC) {
+        if (MCC == kMccList) {
 #pragma unroll
             for (int k = 0; k < kPer; ++k) {
                 const int64_t g = base + t0 + (int64_t)(wave * kPer + k) * 64 + lane;
-                queue_candidate(L, d, cand[k], (uint32_t)g, inst);
+                queue_candidate(L, d, cand[k], (uint32_t)g, inst, vx[k], vy[k], vz[k], pid[k]);
             }
         }
         if (DEP) deposit_tile<kPer>(L, S, key, w1);
+        // ---- collisions while the velocities are in registers, then their stores
+        if (MCC == kMccCollide) {
+            collide_tile<float>(L, d, sc, seg, step, cand, pid, vx, vy, vz,
+                                base + t0 + (int64_t)wave * kPer * 64 + lane);
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) {
+                const int64_t i = t0 + (int64_t)(wave * kPer + k) * 64 + lane;
+                if (i < count && lv[k]) {
+                    const int64_t g = base + i;
+                    VX[g] = vx[k];
+                    VY[g] = vy[k];
+                    VZ[g] = vz[k];
+                }
+            }
+        }
     }
-    if (MCC) flush_candidates(L, d);
+    if (MCC == kMccList) flush_candidates(L, d);
+    if (MCC == kMccCollide) flush_collisions(L, d);
 }
 
 // ---------------------------------------------------------------------------
 // FP64 form: double x in cells, double v; the same arithmetic as the FP64
 // reference, operation by operation (no contraction, explicit fma in the gather)
 // ---------------------------------------------------------------------------
-template <bool DEP, bool MCC>
+template <bool DEP, int MCC>
 __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
 {
     __shared__ PushLds L;
@@ -409,7 +596,7 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
                 vx[k] = VX[g];
                 vy[k] = VY[g];
                 vz[k] = VZ[g];
-                if (MCC) pid[k] = ID[g];
+                if (MCC != kMccOff) pid[k] = ID[g];
             }
         }
         const SegConst &sc = d.segc[seg];
@@ -422,7 +609,7 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
         const unsigned long long T = sc.T;
         const int inst = sc.inst;
         long long step = 0;
-        if (MCC) step = d.instd[inst].step;
+        if (MCC != kMccOff) step = d.instd[inst].step;
         double a0[kPer], a1[kPer], fr[kPer];
         bool live[kPer];
 #pragma unroll
@@ -486,7 +673,7 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
                 const double jn = floor(x[k]);
                 key[k] = (int)jn;
                 w1[k] = (unsigned long long)rint(ldexp(x[k] - jn, PIC_FRAC_BITS));
-                if (MCC) {
+                if (MCC != kMccOff) {
                     const uint4 u = draw(pid[k], step, 0, key0, key1);
                     cand[k] = (unsigned long long)u.x < T;
                 }
@@ -498,9 +685,11 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
             if (i < count && live[k]) {
                 const int64_t g = base + i;
                 X[g] = x[k];
-                VX[g] = vx[k];
-                VY[g] = vy[k];
-                VZ[g] = vz[k];
+                if (MCC != kMccCollide) {
+                    VX[g] = vx[k];
+                    VY[g] = vy[k];
+                    VZ[g] = vz[k];
+                }
             }
         }
         const bool left = n_left > 0, right = n_right > 0;
@@ -521,16 +710,31 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
             wave_or(&idn->status, PIC_ST_CFL, cfl);
             wave_or(&idn->status, PIC_ST_NONFINITE, bad);
         }
-        if (MCC) {
+        if (MCC == kMccList) {
 #pragma unroll
             for (int k = 0; k < kPer; ++k) {
                 const int64_t g = base + t0 + (int64_t)(wave * kPer + k) * 64 + lane;
-                queue_candidate(L, d, cand[k], (uint32_t)g, inst);
+                queue_candidate(L, d, cand[k], (uint32_t)g, inst, vx[k], vy[k], vz[k], pid[k]);
             }
         }
         if (DEP) deposit_tile<kPer>(L, S, key, w1);
+        if (MCC == kMccCollide) {
+            collide_tile<double>(L, d, sc, seg, step, cand, pid, vx, vy, vz,
+                                 base + t0 + (int64_t)wave * kPer * 64 + lane);
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) {
+                const int64_t i = t0 + (int64_t)(wave * kPer + k) * 64 + lane;
+                if (i < count && live[k]) {
+                    const int64_t g = base + i;
+                    VX[g] = vx[k];
+                    VY[g] = vy[k];
+                    VZ[g] = vz[k];
+                }
+            }
+        }
     }
-    if (MCC) flush_candidates(L, d);
+    if (MCC == kMccList) flush_candidates(L, d);
+    if (MCC == kMccCollide) flush_collisions(L, d);
 }
 
 // ---------------------------------------------------------------------------
@@ -591,19 +795,24 @@ int push_grid(const Dev &d)
     return (int)g;
 }
 
-hipError_t launch_push(const Dev &d, hipStream_t st, bool dep, bool mcc)
+template <bool DEP, int MCC>
+void launch_push_t(const Dev &d, hipStream_t st, dim3 grid)
 {
-    const dim3 grid(push_grid(d)), block(kBlock);
-    if (d.precision == PIC_FP64) {
-        if (dep && mcc) hipLaunchKernelGGL((push_f64_kernel<true, true>), grid, block, 0, st, d);
-        else if (dep) hipLaunchKernelGGL((push_f64_kernel<true, false>), grid, block, 0, st, d);
-        else if (mcc) hipLaunchKernelGGL((push_f64_kernel<false, true>), grid, block, 0, st, d);
-        else hipLaunchKernelGGL((push_f64_kernel<false, false>), grid, block, 0, st, d);
+    if (d.precision == PIC_FP64) hipLaunchKernelGGL((push_f64_kernel<DEP, MCC>), grid, dim3(kBlock), 0, st, d);
+    else hipLaunchKernelGGL((push_f32_kernel<DEP, MCC>), grid, dim3(kBlock), 0, st, d);
+}
+
+hipError_t launch_push(const Dev &d, hipStream_t st, bool dep, int mcc)
+{
+    const dim3 grid(push_grid(d));
+    if (dep) {
+        if (mcc == kMccCollide) launch_push_t<true, kMccCollide>(d, st, grid);
+        else if (mcc == kMccList) launch_push_t<true, kMccList>(d, st, grid);
+        else launch_push_t<true, kMccOff>(d, st, grid);
     } else {
-        if (dep && mcc) hipLaunchKernelGGL((push_f32_kernel<true, true>), grid, block, 0, st, d);
-        else if (dep) hipLaunchKernelGGL((push_f32_kernel<true, false>), grid, block, 0, st, d);
-        else if (mcc) hipLaunchKernelGGL((push_f32_kernel<false, true>), grid, block, 0, st, d);
-        else hipLaunchKernelGGL((push_f32_kernel<false, false>), grid, block, 0, st, d);
+        if (mcc == kMccCollide) launch_push_t<false, kMccCollide>(d, st, grid);
+        else if (mcc == kMccList) launch_push_t<false, kMccList>(d, st, grid);
+        else launch_push_t<false, kMccOff>(d, st, grid);
     }
     return hipGetLastError();
 }

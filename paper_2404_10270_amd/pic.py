@@ -36,6 +36,7 @@ PIC_R_ACC64, PIC_R_ACC32, PIC_R_CELL_OFFSETS, PIC_R_NODE_BASE = 4, 5, 6, 7
 PIC_INIT_NO_FIELD = 0x1
 PIC_INIT_SORT = 0x2
 PIC_PUSH_NO_DEPOSIT = 0x1
+PIC_PUSH_COLLIDE = 0x2
 
 # every entry point declared in include/pic.h
 ABI_SYMBOLS = ("pic_query_sizes", "pic_init", "pic_push", "pic_deposit", "pic_field_solve",

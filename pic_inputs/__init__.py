@@ -95,6 +95,7 @@ class Workload:
     perturb_mode: int = 1
     quiet: bool = False         # lattice positions instead of random ones
     pair_start: bool = False    # every ion starts at an electron's position (neutral start)
+    state_seed: Optional[int] = None  # seed of the initial-state generator (default: seed)
 
     def replace(self, **kw) -> "Workload":
         return dataclasses.replace(self, **kw)
@@ -179,6 +180,31 @@ def bounded_mcc(nc: int = 100_000, ppc: float = 100, seed: int = 3, n_steps: int
     return wl.replace(name="bounded_mcc", mcc=mcc)
 
 
+def batched(n_inst: int = 256, seed: int = 4, nc_min: int = 256, nc_ratio: float = 64.0,
+            ppc_range=(50.0, 400.0), theta_deg_max: float = 85.0,
+            wpe_dt_range=(0.05, 0.2)) -> List[Workload]:
+    """Independent bounded MCC instances of mixed shape, batched in one context.
+
+    Per instance i: nc = round(nc_min * nc_ratio^U) (log-uniform), total
+    particles per cell ~ U[ppc_range] split evenly between the two species,
+    B at theta ~ U[0, theta_deg_max] degrees, omega_pe dt ~ U[wpe_dt_range].
+    All instances share the generator seed `seed`; the collision generator
+    of instance i is keyed with seed_hi xor i, and its initial state is drawn
+    from its own stream (seed, i).
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for i in range(n_inst):
+        nc = int(round(nc_min * nc_ratio ** rng.random()))
+        ppc_total = ppc_range[0] + (ppc_range[1] - ppc_range[0]) * rng.random()
+        theta = theta_deg_max * rng.random()
+        wpe_dt = wpe_dt_range[0] + (wpe_dt_range[1] - wpe_dt_range[0]) * rng.random()
+        wl = bounded_mcc(nc=nc, ppc=0.5 * ppc_total, seed=seed, theta_deg=theta,
+                         wpe_dt=wpe_dt, sort_every=0)
+        out.append(wl.replace(name=f"batched[{i}]", state_seed=seed * 1_000_003 + i))
+    return out
+
+
 def table1() -> Workload:
     """Shape of the paper's Table 1 test case (periodic, unmagnetised).
 
@@ -230,7 +256,7 @@ def initial_state(wl: Workload) -> List[SpeciesState]:
     Velocities are Maxwellian with sqrt(T/m) per component.  Ids are
     0..N_0-1 for species 0, then the next block for species 1, and so on.
     """
-    rng = np.random.Generator(np.random.PCG64(wl.seed))
+    rng = np.random.Generator(np.random.PCG64(wl.seed if wl.state_seed is None else wl.state_seed))
     out: List[SpeciesState] = []
     next_id = 0
     nc = wl.nc

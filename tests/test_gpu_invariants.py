@@ -6,6 +6,10 @@ the device, and the full-size bench workload on sampled particles.
   cell offsets equal the scan of the per-cell counts;
 * deposit: every live particle contributes exactly 2^32 after every step;
 * ids stay unique; run-to-run results are identical as sets keyed by id;
+* collisions inside the mover give the same state, bit for bit, as the
+  separate collide call;
+* resume: k steps, a dump of the live particles, a new context from the dump
+  and k more steps equal 2k steps in one context, bit for bit;
 * edge cases: an empty species, ragged counts, a capacity overflow, a
   particle at |vx| >= 1 cell/step, non-finite or out-of-range uploads;
 * full size (100,000 cells, 2e7 particles, FP32 form): the bit-exact deposit
@@ -86,6 +90,79 @@ def test_run_to_run_identical(prec):
     for k in range(2):
         for f in ("x", "vx", "vy", "vz", "id"):
             assert np.array_equal(outs[0][k][f], outs[1][k][f])
+
+
+@pytest.mark.parametrize("prec", [FP32, FP64], ids=["fp32", "fp64"])
+def test_collisions_in_the_mover_equal_the_separate_call(prec):
+    wl = pin.bounded_mcc(nc=700, ppc=60, seed=34)
+    wl.mcc.n_n *= 20  # many collisions and ionisation events per step
+    flush(f"fused collisions prec={prec}")
+    a, _, _ = build_pair(wl, prec)
+    b, _, _ = build_pair(wl, prec)
+    for s in range(12):
+        a.push(P.PIC_PUSH_COLLIDE)
+        a.mcc_collide()
+        a.field_solve()
+        b.push()
+        b.mcc_collide()
+        b.field_solve()
+        if s % 5 == 4:
+            a.sort()
+            b.sort()
+    da, rca = a.diagnostics()
+    db, rcb = b.diagnostics()
+    assert rca == 0 and rcb == 0
+    assert da[0].n_ionize > 0 and da[0].n_elastic > 0 and da[0].n_cx > 0
+    for f in ("n_candidates", "n_elastic", "n_ionize", "n_cx", "n_over_cap", "n_source",
+              "next_id", "particle_steps"):
+        assert getattr(da[0], f) == getattr(db[0], f), f
+    for k in range(2):
+        ga, gb = gpu_state(a, k), gpu_state(b, k)
+        for f in ("x", "vx", "vy", "vz", "id"):
+            assert np.array_equal(ga[f], gb[f]), f
+    assert np.array_equal(a.grid(P.PIC_R_ACC64), b.grid(P.PIC_R_ACC64))
+    a.close()
+    b.close()
+
+
+def _dump(sim, k, prec):
+    """Live particles of species k in the storage form of `prec`."""
+    from types import SimpleNamespace
+    st = sim.state(k)
+    if prec == FP32:
+        return SimpleNamespace(cell=st["cell"], f=st["f"], vx=st["vx"].astype(np.float32),
+                               vy=st["vy"].astype(np.float32), vz=st["vz"].astype(np.float32),
+                               id=st["id"])
+    return SimpleNamespace(x=st["x"], vx=st["vx"], vy=st["vy"], vz=st["vz"], id=st["id"])
+
+
+@pytest.mark.parametrize("prec", [FP32, FP64], ids=["fp32", "fp64"])
+def test_resume_from_a_dump_is_bit_identical(prec):
+    wl = pin.bounded_mcc(nc=400, ppc=50, seed=38)
+    wl.mcc.n_n *= 20
+    flush(f"resume prec={prec}")
+    full, _, _ = build_pair(wl, prec)
+    full.step(30, sort_every=10)
+    half, _, _ = build_pair(wl, prec)
+    half.step(15, sort_every=10)
+    d, rc = half.diagnostics()
+    assert rc == 0
+    dump = [_dump(half, k, prec) for k in range(2)]
+    caps = [int(half.cfgs[0].sp[k].capacity) for k in range(2)]
+    half.close()
+    res = P.PicSim(wl, dump, prec, capacities=caps, next_ids=[int(d[0].next_id)],
+                   step0=int(d[0].step))
+    res.step(15, sort_every=10)
+    da, rca = full.diagnostics()
+    db, rcb = res.diagnostics()
+    assert rca == 0 and rcb == 0
+    assert da[0].step == db[0].step and da[0].next_id == db[0].next_id
+    for k in range(2):
+        ga, gb = gpu_state(full, k), gpu_state(res, k)
+        for f in ("x", "vx", "vy", "vz", "id"):
+            assert np.array_equal(ga[f], gb[f]), f
+    full.close()
+    res.close()
 
 
 def test_empty_species_and_ragged_counts():

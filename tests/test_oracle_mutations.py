@@ -1,0 +1,82 @@
+"""Mutation check of the oracle's pins: plant one plausible mistake at a time
+in a private copy of the oracle's C source (a dropped term, a wrong sign or
+index, a swapped operand, a wrong constant), rebuild that copy and run the
+oracle pin tests against it.  Every planted mistake must make at least one
+pin fail.  CPU only; nothing here touches the oracle in the repository."""
+import concurrent.futures as cf
+import os
+import shutil
+import subprocess
+import sys
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+# (what the mistake is, original text, mutated text)
+MUTATIONS = [
+    ("half kick doubled", "double h = 0.5 * a;", "double h = a;"),
+    ("rotation sign in z", "double qz = mz + (px * sy - py * sx);", "double qz = mz + (px * sy + py * sx);"),
+    ("cross product operand order", "double pz = mz + (mx * ty - my * tx);",
+     "double pz = mz + (my * tx - mx * ty);"),
+    ("deposit to the wrong node", "S[j + 1] += w1;", "S[j] += w1;"),
+    ("gradient sign", "E[j] = (phi[j - 1] - phi[j + 1]) / (2.0 * dx);",
+     "E[j] = (phi[j + 1] - phi[j - 1]) / (2.0 * dx);"),
+    ("wall closure term dropped", "E[0] = -(phi[1] - phi[0]) / dx - rho[0] * dx / (2.0 * c->eps0);",
+     "E[0] = -(phi[1] - phi[0]) / dx;"),
+    ("elastic mass ratios swapped", "P->vx[p] = am * vx + bm * g * d[0];",
+     "P->vx[p] = bm * vx + am * g * d[0];"),
+    ("ionisation energy not split", "const double e2 = e_tot - e1;", "const double e2 = e_tot;"),
+    ("Philox key constant", "k0 += 0x9E3779B9u;", "k0 += 0x9E3779B8u;"),
+    ("ionisation threshold ignored", "if (v2 >= v2_iz && r2 < C1 * v2)", "if (r2 < C1 * v2)"),
+    ("source counts one wall", "const int64_t n_pairs = s->cnt.absorbed[ki][0] + s->cnt.absorbed[ki][1];",
+     "const int64_t n_pairs = s->cnt.absorbed[ki][0];"),
+    ("events not ranked by parent id", "if (n_ev > 1) qsort", "if (0) qsort"),
+    ("isotropic cosine range", "double cc = 1.0 - 2.0 * u01(a);", "double cc = 1.0 - u01(a);"),
+    ("periodic background dropped", "rho[j] = acc / V + rho_bg;", "rho[j] = acc / V;"),
+    ("Boris uses dt, not dt/2", "const double tm = (c->q[k] / c->m[k]) * c->B0 * (0.5 * c->dt);",
+     "const double tm = (c->q[k] / c->m[k]) * c->B0 * c->dt;"),
+]
+
+
+def _pin_tests():
+    here = os.path.join(ROOT, "tests")
+    return sorted(f for f in os.listdir(here)
+                  if f.startswith("test_oracle_") and f.endswith(".py")
+                  and f != os.path.basename(__file__))
+
+
+def _run(mut):
+    name, a, b = mut
+    with tempfile.TemporaryDirectory(prefix="orc_mut_") as tmp:
+        shutil.copytree(os.path.join(ROOT, "oracle"), os.path.join(tmp, "oracle"),
+                        ignore=shutil.ignore_patterns("*.so", "__pycache__"))
+        shutil.copytree(os.path.join(ROOT, "pic_inputs"), os.path.join(tmp, "pic_inputs"),
+                        ignore=shutil.ignore_patterns("__pycache__"))
+        tdir = os.path.join(tmp, "tests")
+        os.makedirs(tdir)
+        for f in _pin_tests() + ["conftest.py", "rocrand_philox_kat.cpp"]:
+            shutil.copy(os.path.join(ROOT, "tests", f), tdir)
+        shutil.copytree(os.path.join(ROOT, "tests", "golden"), os.path.join(tdir, "golden"))
+        shutil.copy(os.path.join(ROOT, "pytest.ini"), tmp)
+        src = os.path.join(tmp, "oracle", "pic_oracle.c")
+        with open(src) as f:
+            s = f.read()
+        if a not in s:
+            return name, "not applied"
+        with open(src, "w") as f:
+            f.write(s.replace(a, b))
+        env = dict(os.environ, PYTHONDONTWRITEBYTECODE="1")
+        r = subprocess.run([sys.executable, "-m", "pytest", "tests", "-q", "-x", "-m", "not gpu",
+                            "-p", "no:cacheprovider"], cwd=tmp, env=env, capture_output=True,
+                           text=True, timeout=900)
+        return name, ("caught" if r.returncode != 0 else "survived")
+
+
+@pytest.mark.slow
+def test_every_planted_mistake_fails_a_pin():
+    with cf.ThreadPoolExecutor(max_workers=4) as ex:
+        res = list(ex.map(_run, MUTATIONS))
+    bad = [(n, r) for n, r in res if r != "caught"]
+    assert not bad, bad
