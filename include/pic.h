@@ -73,9 +73,11 @@ typedef struct {
     int32_t kind;       /* pic_kind: selects the collision processes */
     int32_t _pad0;
     int64_t capacity;   /* particle slots reserved for this species */
-    int64_t n_init;     /* particles uploaded into buffer set 0 before pic_init */
+    int64_t n_init;     /* initial particles: uploaded into buffer set 0 before pic_init,
+                           or drawn there by pic_init with PIC_INIT_DEVICE */
     double v_cap;       /* speed bounding the null-collision frequency [m/s] */
     double T_src;       /* temperature of source-born particles [J] */
+    double T_init;      /* temperature of the drawn initial Maxwellian [J] (PIC_INIT_DEVICE) */
 } pic_species;
 
 typedef struct {
@@ -95,7 +97,15 @@ typedef struct {
     double sig_el, sig_iz, E_iz, sig_cx;  /* cross sections [m^2], threshold [J] */
     uint64_t next_id;    /* id given to the first created particle */
     int64_t step0;       /* index of the first step (keys the draws) */
+    /* drawn initial state (PIC_INIT_DEVICE only) */
+    double init_amp;     /* amplitude A of the electron density perturbation */
+    int32_t init_mode;   /* its mode number m */
+    uint32_t init_opts;  /* PIC_INIT_OPT_* */
 } pic_config;
+
+/* options of the drawn initial state */
+#define PIC_INIT_OPT_QUIET 0x1u  /* lattice positions (p + 1/2) nc / n instead of uniform draws */
+#define PIC_INIT_OPT_PAIR  0x2u  /* a species with species 0's count starts at its positions */
 
 typedef struct {
     int64_t n_slots;     /* particle slots per array of one buffer set */
@@ -161,6 +171,7 @@ typedef struct pic_ctx pic_ctx;
 /* init flags */
 #define PIC_INIT_NO_FIELD 0x1u   /* skip the initial deposit + field solve */
 #define PIC_INIT_SORT     0x2u   /* sort the uploaded particles by cell first */
+#define PIC_INIT_DEVICE   0x4u   /* draw the initial particles on the device (see pic_init) */
 
 /* push flags */
 #define PIC_PUSH_NO_DEPOSIT 0x1u /* do not deposit the new positions */
@@ -182,6 +193,22 @@ int pic_query_sizes(const pic_config *cfgs, int n_inst, pic_sizes *out, int64_t 
  * pic_push sees E at the initial positions.  stream is a hipStream_t (NULL =
  * the null stream).  Sec. 2: initialisation of grid and particles before the
  * cycle.  On error *out is NULL.
+ *
+ * PIC_INIT_DEVICE draws the n_init particles of every segment into buffer
+ * set 0 instead of reading an upload.  Particle p of species k of instance i
+ * gets id (n_init of the species before k) + p and two Philox4x32-10 blocks
+ * keyed (seed_lo, seed_hi ^ i) with counter (id_lo, id_hi, 0xFFFFFFFF, b),
+ * b = 0, 1 (step -1, before the first step):
+ *   x = U(u0) nc, or (p + 1/2) nc / n_init with PIC_INIT_OPT_QUIET, or, with
+ *       PIC_INIT_OPT_PAIR and the count of species 0, particle p of species
+ *       0's final position; an electron species not so copied is displaced
+ *       by (A/kk) sin(kk x), kk = 2 pi init_mode / nc, A = init_amp (wrapped
+ *       when periodic); x is kept inside [0, nc).  U(u) = (u + 1/2) 2^-32.
+ *   v = sqrt(T_init/m) dt/dx times standard normals from Box-Muller on
+ *       (u1, u2) -> vx, vy and (u3, u'0) -> vz.
+ * The FP32 form stores cell = floor(x) and f = x - cell rounded to float (an
+ * f that rounds to 1 moves to the next cell, or stays below 1 in the last).
+ * next_id must be at least the sum of n_init (PIC_E_CONFIG otherwise).
  */
 int pic_init(const pic_config *cfgs, int n_inst, const pic_buffers *bufs, void *stream,
              unsigned flags, pic_ctx **out);

@@ -112,6 +112,13 @@ def lib():
         L.orc_run.argtypes = [C.POINTER(Sim), C.c_int64]
         L.orc_run.restype = C.c_int
         L.orc_diagnostics.argtypes = [C.POINTER(Sim), C.POINTER(Diag)]
+        ip = C.POINTER(C.c_int64)
+        L.orc_init_species.argtypes = [C.POINTER(Config), ip, C.c_int, C.c_int, C.c_int,
+                                       C.c_double, C.c_int, dp, C.c_int64, ip, dp, dp, dp, dp, up]
+        L.orc_init_species.restype = None
+        L.orc_init_deposit.argtypes = [C.POINTER(Config), ip, C.c_int, C.c_int, C.c_int,
+                                       C.c_double, C.c_int, C.c_int, up]
+        L.orc_init_deposit.restype = None
         L.orc_candidate_threshold.argtypes = [C.POINTER(Config), C.c_int]
         L.orc_candidate_threshold.restype = C.c_uint64
         for name, T in (("orc_sizeof_sim", Sim), ("orc_sizeof_config", Config),
@@ -191,6 +198,53 @@ def make_config(wl: pin.Workload, inst: int = 0) -> Config:
         c.n_n, c.T_n, c.sig_el, c.sig_iz, c.E_iz, c.sig_cx = (mc.n_n, mc.T_n, mc.sig_el,
                                                                mc.sig_iz, mc.E_iz, mc.sig_cx)
     return c
+
+
+def _init_args(wl: pin.Workload, inst: int):
+    c = make_config(wl, inst)
+    nsp = len(wl.species)
+    n_init = (C.c_int64 * MAXSP)(*([int(round(s.ppc * wl.nc)) for s in wl.species]
+                                   + [0] * (MAXSP - nsp)))
+    T = np.zeros(MAXSP)
+    for k, s in enumerate(wl.species):
+        T[k] = s.T
+    opts = (1 if wl.quiet else 0, 1 if wl.pair_start else 0, float(wl.perturb_amp),
+            int(wl.perturb_mode))
+    return c, n_init, T, opts
+
+
+def init_state(wl: pin.Workload, inst: int = 0, select=None) -> List[pin.SpeciesState]:
+    """The configuration's own initial particles, drawn from the counter-based
+    generator at step -1 (orc_init_species): round(ppc nc) particles per
+    species, ids counting from 0 over the species in order.  `select`, if
+    given, lists per species the particle indices to draw (a sample)."""
+    c, n_init, T, opts = _init_args(wl, inst)
+    out = []
+    for k in range(len(wl.species)):
+        if select is None:
+            m, plist, pp = n_init[k], None, None
+        else:
+            pp = np.ascontiguousarray(select[k], dtype=np.int64)
+            m, plist = pp.shape[0], pp.ctypes.data_as(C.POINTER(C.c_int64))
+        x = np.zeros(m); vx = np.zeros(m); vy = np.zeros(m); vz = np.zeros(m)
+        ids = np.zeros(m, dtype=np.uint64)
+        lib().orc_init_species(C.byref(c), n_init, k, *opts, _dp(T), m, plist, _dp(x), _dp(vx),
+                               _dp(vy), _dp(vz), _up(ids))
+        out.append(pin.SpeciesState(x=x, vx=vx, vy=vy, vz=vz, id=ids))
+    return out
+
+
+def init_deposit(wl: pin.Workload, inst: int = 0, fp32_form: bool = False) -> List[np.ndarray]:
+    """Fixed-point deposit of every drawn initial particle, per species,
+    computed particle by particle (no particle arrays are stored); with
+    fp32_form the positions are first rounded to the FP32 storage form."""
+    c, n_init, T, opts = _init_args(wl, inst)
+    out = []
+    for k in range(len(wl.species)):
+        S = np.zeros(wl.nc + 1, dtype=np.uint64)
+        lib().orc_init_deposit(C.byref(c), n_init, k, *opts, 1 if fp32_form else 0, _up(S))
+        out.append(S)
+    return out
 
 
 class OracleSim:

@@ -160,17 +160,21 @@ static void iso_dir(uint32_t a, uint32_t b, double d[3])
 /* W1 = rint(f 2^32) and the left node 2^32 - W1, so every particle adds     */
 /* exactly 2^32 and the sum is independent of order.                          */
 /* ------------------------------------------------------------------------ */
+/* add one particle at x (cells) to the fixed-point deposit S */
+static void deposit_add(double x, uint64_t *S)
+{
+    double jd = floor(x);
+    double f = x - jd;
+    int64_t j = (int64_t)jd;
+    uint64_t w1 = (uint64_t)rint(ldexp(f, ORC_FRAC_BITS));
+    S[j] += ((uint64_t)1 << ORC_FRAC_BITS) - w1;
+    S[j + 1] += w1;
+}
+
 void orc_deposit_species(int64_t n, const double *x, int32_t nc, uint64_t *S)
 {
     memset(S, 0, sizeof(uint64_t) * (size_t)(nc + 1));
-    for (int64_t p = 0; p < n; ++p) {
-        double jd = floor(x[p]);
-        double f = x[p] - jd;
-        int64_t j = (int64_t)jd;
-        uint64_t w1 = (uint64_t)rint(ldexp(f, ORC_FRAC_BITS));
-        S[j] += ((uint64_t)1 << ORC_FRAC_BITS) - w1;
-        S[j + 1] += w1;
-    }
+    for (int64_t p = 0; p < n; ++p) deposit_add(x[p], S);
 }
 
 /* the same linear weights in plain FP64 (used to bound the fixed-point error) */
@@ -672,6 +676,127 @@ void orc_diagnostics(const orc_sim *s, orc_diag *out)
         }
     }
     out->field_energy = 0.5 * c->eps0 * fe;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Initial particles drawn from the counter-based generator (the            */
+/* configuration's own initial state, before step 0).  Particle p of        */
+/* species k has id = (initial particles of the species before k) + p and   */
+/* draws two Philox blocks at step -1:                                      */
+/*   position  uniform x = U(u0) nc, or the lattice (p + 1/2) nc / n        */
+/*             (quiet); with the pair option a species k > 0 of the same    */
+/*             count as species 0 takes particle p of species 0's final     */
+/*             position.  An electron species not so copied is displaced by */
+/*             (A/kk) sin(kk x), kk = 2 pi m / nc (mode m, amplitude A),    */
+/*             wrapped when periodic; every x is then kept inside [0, nc);  */
+/*   velocity  Maxwellian, sqrt(T/m) dt/dx per component in cells/step:     */
+/*             Box-Muller on (u1, u2) gives vx, vy; on (u3, u'0) gives vz.  */
+/* This is the generator behind the X28 reading of the Langmuir start.      */
+/* ------------------------------------------------------------------------ */
+static double init_position(const orc_config *c, const int64_t *n_init, int k, int64_t p,
+                            int quiet, double amp, int mode, uint64_t id)
+{
+    const int64_t n = n_init[k];
+    const double L = (double)c->nc;
+    double x;
+    if (quiet) {
+        x = ((double)p + 0.5) * L / (double)n;
+    } else {
+        uint32_t u[4];
+        draw_block(c, id, -1, 0, u);
+        x = u01(u[0]) * L;
+    }
+    if (amp != 0.0 && c->kind[k] == ORC_KIND_ELECTRON) {
+        const double kk = 2.0 * M_PI * (double)mode / L;
+        x = x + (amp / kk) * sin(kk * x);
+        if (c->bc == ORC_BC_PERIODIC) x = x - L * floor(x / L);
+    }
+    if (x >= L) x = nextafter(L, 0.0);
+    if (x < 0.0) x = 0.0;
+    return x;
+}
+
+/* particle p of species k of the drawn initial state (see above) */
+static void init_one(const orc_config *c, const int64_t *n_init, int k, int64_t p, int quiet,
+                     int pair, double amp, int mode, double vth, double *x, double v[3],
+                     uint64_t *id)
+{
+    int64_t id0 = 0;
+    for (int q = 0; q < k; ++q) id0 += n_init[q];
+    const uint64_t pid = (uint64_t)(id0 + p);
+    const int copy = pair && k > 0 && n_init[k] == n_init[0];
+    *id = pid;
+    if (copy) *x = init_position(c, n_init, 0, p, quiet, amp, mode, (uint64_t)p);
+    else *x = init_position(c, n_init, k, p, quiet, amp, mode, pid);
+    uint32_t u[4], u1[4];
+    draw_block(c, pid, -1, 0, u);
+    draw_block(c, pid, -1, 1, u1);
+    double n0, n1, n2, n3;
+    box_muller(u[1], u[2], &n0, &n1);
+    box_muller(u[3], u1[0], &n2, &n3);
+    v[0] = vth * n0;
+    v[1] = vth * n1;
+    v[2] = vth * n2;
+}
+
+static double init_vth(const orc_config *c, int k, const double *T_init)
+{
+    return T_init[k] > 0.0 ? sqrt(T_init[k] / c->m[k]) * c->dt / c->dx : 0.0;
+}
+
+/* the particles p_list[0..m-1] of species k (all n_init[k] when p_list is NULL) */
+void orc_init_species(const orc_config *c, const int64_t *n_init, int k, int quiet, int pair,
+                      double amp, int mode, const double *T_init, int64_t m,
+                      const int64_t *p_list, double *x, double *vx, double *vy, double *vz,
+                      uint64_t *id)
+{
+    const double vth = init_vth(c, k, T_init);
+    if (!p_list) m = n_init[k];
+    for (int64_t q = 0; q < m; ++q) {
+        const int64_t p = p_list ? p_list[q] : q;
+        double v[3];
+        init_one(c, n_init, k, p, quiet, pair, amp, mode, vth, &x[q], v, &id[q]);
+        vx[q] = v[0];
+        vy[q] = v[1];
+        vz[q] = v[2];
+    }
+}
+
+/* x as stored in the FP32 form: cell = floor(x), f = x - cell rounded to
+ * float; an f that rounds to 1 moves to offset 0 of the next cell, or, in
+ * the last cell, stays at the largest float below 1 */
+static double fp32_form(double x, int32_t nc)
+{
+    double cell = floor(x);
+    float f = (float)(x - cell);
+    if (f >= 1.0f) {
+        if (cell + 1.0 < (double)nc) {
+            cell += 1.0;
+            f = 0.0f;
+        } else {
+            f = nextafterf(1.0f, 0.0f);
+        }
+    }
+    return cell + (double)f;
+}
+
+/* the fixed-point deposit of all n_init[k] drawn particles of species k,
+ * computed particle by particle without storing them (S is cleared first);
+ * with fp32 != 0 each position is first rounded to the FP32 storage form */
+void orc_init_deposit(const orc_config *c, const int64_t *n_init, int k, int quiet, int pair,
+                      double amp, int mode, int fp32, uint64_t *S)
+{
+    const int64_t n = n_init[k];
+    const int copy = pair && k > 0 && n_init[k] == n_init[0];
+    int64_t id0 = 0;
+    for (int q = 0; q < k; ++q) id0 += n_init[q];
+    memset(S, 0, sizeof(uint64_t) * (size_t)(c->nc + 1));
+    for (int64_t p = 0; p < n; ++p) {
+        double x = copy ? init_position(c, n_init, 0, p, quiet, amp, mode, (uint64_t)p)
+                        : init_position(c, n_init, k, p, quiet, amp, mode, (uint64_t)(id0 + p));
+        if (fp32) x = fp32_form(x, c->nc);
+        deposit_add(x, S);
+    }
 }
 
 int orc_sizeof_sim(void) { return (int)sizeof(orc_sim); }

@@ -82,6 +82,24 @@ int validate(const pic_config *cfgs, int n_inst)
     return PIC_OK;
 }
 
+// the configuration of a drawn initial state (PIC_INIT_DEVICE)
+int validate_device_init(const pic_config *cfgs, int n_inst)
+{
+    for (int i = 0; i < n_inst; ++i) {
+        const pic_config &c = cfgs[i];
+        uint64_t total = 0;
+        for (int k = 0; k < c.nsp; ++k) {
+            if (!finite_nonneg(c.sp[k].T_init)) return PIC_E_CONFIG;
+            total += (uint64_t)c.sp[k].n_init;
+        }
+        if (c.next_id < total) return PIC_E_CONFIG;
+        if (!std::isfinite(c.init_amp)) return PIC_E_CONFIG;
+        if (c.init_amp != 0.0 && c.init_mode == 0) return PIC_E_CONFIG;
+        if (c.init_opts & ~(PIC_INIT_OPT_QUIET | PIC_INIT_OPT_PAIR)) return PIC_E_CONFIG;
+    }
+    return PIC_OK;
+}
+
 // slots of a segment, rounded to a multiple of 64 so that every segment
 // starts on a 256-byte boundary of each array
 int64_t seg_slots(const pic_species &s) { return (int64_t)align_up((uint64_t)s.capacity, 64); }
@@ -306,6 +324,10 @@ int pic_init(const pic_config *cfgs, int n_inst, const pic_buffers *bufs, void *
     if (!bufs) return PIC_E_ARG;
     const int rc = validate(cfgs, n_inst);
     if (rc) return rc;
+    if (flags & PIC_INIT_DEVICE) {
+        const int rc1 = validate_device_init(cfgs, n_inst);
+        if (rc1) return rc1;
+    }
     Plan p;
     const int rc2 = plan(cfgs, n_inst, p);
     if (rc2) return rc2;
@@ -354,6 +376,10 @@ int pic_init(const pic_config *cfgs, int n_inst, const pic_buffers *bufs, void *
         ic.dx = cf.dx;
         ic.eps0 = cf.eps0;
         ic.K = cf.dx * cf.dx / cf.eps0;
+        ic.init_amp = cf.init_amp;
+        ic.init_mode = cf.init_mode;
+        ic.init_opts = (int32_t)cf.init_opts;
+        int64_t id0 = 0;
         for (int k = 0; k < nsp; ++k) {
             const int s = i * nsp + k;
             SegConst &sc = segc[s];
@@ -364,6 +390,11 @@ int pic_init(const pic_config *cfgs, int n_inst, const pic_buffers *bufs, void *
             sc.gnode = p.node_base[i];
             sc.node_stride = p.G;
             sc.cap = (uint32_t)cf.sp[k].capacity;
+            sc.n_init = cf.sp[k].n_init;
+            sc.id0 = (uint64_t)id0;
+            id0 += cf.sp[k].n_init;
+            sc.vth_init = cf.sp[k].T_init > 0.0 ? std::sqrt(cf.sp[k].T_init / cf.sp[k].m) * cf.dt / cf.dx
+                                                : 0.0;
             if (ic.seg_e >= 0 && ic.seg_i >= 0) {
                 if (s == ic.seg_e) sc.partner = ic.seg_i;
                 if (s == ic.seg_i) sc.partner = ic.seg_e;
@@ -460,6 +491,7 @@ int pic_init(const pic_config *cfgs, int n_inst, const pic_buffers *bufs, void *
                               hipMemcpyHostToDevice, st) == hipSuccess;
     // the host vectors above must stay alive until the copies are done
     ok = ok && hipStreamSynchronize(st) == hipSuccess;
+    if (ok && (flags & PIC_INIT_DEVICE)) ok = launch_init_device(d, st) == hipSuccess;
     ok = ok && launch_init_state(d, st, nullptr) == hipSuccess;
     if (ok && (flags & PIC_INIT_SORT)) ok = launch_sort(d, st) == hipSuccess;
     if (ok && !(flags & PIC_INIT_NO_FIELD)) {

@@ -56,6 +56,10 @@ struct SegConst {
     double sig_n;       // neutral Maxwellian sqrt(T_n/m_s) in cells/step (CX, new ions)
     double sig_src;     // source Maxwellian sqrt(T_src/m_s) in cells/step
     uint32_t key0, key1;
+    // drawn initial state: particles, first id, Maxwellian sqrt(T/m) in cells/step
+    int64_t n_init;
+    uint64_t id0;
+    double vth_init;
     // field / diagnostics
     double qw;          // q w
     double accC;        // (q/m) dt^2 / dx
@@ -67,6 +71,8 @@ struct InstConst {
     int64_t ftile0;     // first field tile
     int32_t nc, bc, nsp, mcc_on, source_on, seg0, seg_e, seg_i;
     double dx, eps0, K; // K = dx^2 / eps0
+    double init_amp;    // drawn initial state: perturbation amplitude, mode, PIC_INIT_OPT_*
+    int32_t init_mode, init_opts;
 };
 
 // dynamic per-segment counters
@@ -192,6 +198,8 @@ struct Dev {
 // launchers (each enqueues on `st`; return hipError_t)
 // ---------------------------------------------------------------------------
 hipError_t launch_init_state(const Dev &d, hipStream_t st, const uint32_t *n_init_dev);
+// draws the initial particles of every segment into buffer set 0
+hipError_t launch_init_device(const Dev &d, hipStream_t st);
 // mcc: 0 no collisions, 1 list the candidates (pic_mcc_collide collides them),
 // 2 collide in the mover
 hipError_t launch_push(const Dev &d, hipStream_t st, bool deposit, int mcc);

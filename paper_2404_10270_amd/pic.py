@@ -9,6 +9,7 @@ the calls raise.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 from typing import List, Optional, Sequence
 
@@ -35,6 +36,8 @@ PIC_R_ACC64, PIC_R_ACC32, PIC_R_CELL_OFFSETS, PIC_R_NODE_BASE = 4, 5, 6, 7
 
 PIC_INIT_NO_FIELD = 0x1
 PIC_INIT_SORT = 0x2
+PIC_INIT_DEVICE = 0x4
+PIC_INIT_OPT_QUIET, PIC_INIT_OPT_PAIR = 0x1, 0x2
 PIC_PUSH_NO_DEPOSIT = 0x1
 PIC_PUSH_COLLIDE = 0x2
 
@@ -47,7 +50,7 @@ ABI_SYMBOLS = ("pic_query_sizes", "pic_init", "pic_push", "pic_deposit", "pic_fi
 class pic_species(C.Structure):
     _fields_ = [("q", C.c_double), ("m", C.c_double), ("w", C.c_double), ("kind", C.c_int32),
                 ("_pad0", C.c_int32), ("capacity", C.c_int64), ("n_init", C.c_int64),
-                ("v_cap", C.c_double), ("T_src", C.c_double)]
+                ("v_cap", C.c_double), ("T_src", C.c_double), ("T_init", C.c_double)]
 
 
 class pic_config(C.Structure):
@@ -59,7 +62,8 @@ class pic_config(C.Structure):
                 ("sp", pic_species * PIC_MAX_SPECIES),
                 ("n_n", C.c_double), ("T_n", C.c_double), ("sig_el", C.c_double),
                 ("sig_iz", C.c_double), ("E_iz", C.c_double), ("sig_cx", C.c_double),
-                ("next_id", C.c_uint64), ("step0", C.c_int64)]
+                ("next_id", C.c_uint64), ("step0", C.c_int64),
+                ("init_amp", C.c_double), ("init_mode", C.c_int32), ("init_opts", C.c_uint32)]
 
 
 class pic_sizes(C.Structure):
@@ -230,12 +234,17 @@ def make_config(wl, precision: int, capacities: Sequence[int], n_init: Sequence[
         sp.n_init = int(n_init[k])
         sp.v_cap = getattr(s, "v_cap", 0.0)
         sp.T_src = getattr(s, "T_src", 0.0)
+        sp.T_init = getattr(s, "T", 0.0)
     if c.mcc_on:
         m = wl.mcc
         c.n_n, c.T_n, c.sig_el, c.sig_iz, c.E_iz, c.sig_cx = (m.n_n, m.T_n, m.sig_el, m.sig_iz,
                                                               m.E_iz, m.sig_cx)
     c.next_id = int(next_id)
     c.step0 = int(step0)
+    c.init_amp = float(getattr(wl, "perturb_amp", 0.0))
+    c.init_mode = int(getattr(wl, "perturb_mode", 1))
+    c.init_opts = ((PIC_INIT_OPT_QUIET if getattr(wl, "quiet", False) else 0)
+                   | (PIC_INIT_OPT_PAIR if getattr(wl, "pair_start", False) else 0))
     return c
 
 
@@ -258,17 +267,26 @@ class PicSim:
             workloads, states = [workloads], [states]
             if capacities is not None:
                 capacities = [capacities]
+        drawn = bool(flags & PIC_INIT_DEVICE)
+        if drawn:
+            # the device draws the initial particles: only their counts are needed here
+            states = [None] * len(workloads)
+        elif any(st is None for st in states):
+            raise ValueError("an initial state is needed unless PIC_INIT_DEVICE is set")
         self.n_inst = len(workloads)
         self.precision = precision
         self.workloads = list(workloads)
         self.nsp = len(workloads[0].species)
         cfgs = []
         for i, (wl, st) in enumerate(zip(workloads, states)):
-            caps = capacities[i] if capacities is not None else [max(1, int(s.id.shape[0] * 1.5) + 1024)
-                                                                 for s in st]
-            nid = next_ids[i] if next_ids is not None else int(sum(int(s.id.shape[0]) for s in st))
-            cfgs.append(make_config(wl, precision, caps, [int(s.id.shape[0]) for s in st], nid,
-                                    step0))
+            if drawn:
+                n_init = [int(round(sp.ppc * wl.nc)) for sp in wl.species]
+            else:
+                n_init = [int(s.id.shape[0]) for s in st]
+            caps = capacities[i] if capacities is not None else [
+                max(1, int(math.ceil(n * sp.cap_factor)) + 1024) for n, sp in zip(n_init, wl.species)]
+            nid = next_ids[i] if next_ids is not None else int(sum(n_init))
+            cfgs.append(make_config(wl, precision, caps, n_init, nid, step0))
         self.cfgs = cfgs
         sizes, seg_base = pic_query_sizes(cfgs)
         self.sizes, self.seg_base = sizes, seg_base
@@ -285,6 +303,8 @@ class PicSim:
         self.work = torch.zeros(int(sizes.work_bytes), dtype=torch.uint8, device=dev)
         # upload the initial state into set 0
         for i, st in enumerate(states):
+            if st is None:
+                continue
             for k, s in enumerate(st):
                 b = seg_base[i * self.nsp + k]
                 m = int(s.id.shape[0])

@@ -271,3 +271,156 @@ def test_batched_instances_match_the_oracle_one_by_one():
             assert np.max(np.abs(g["x"] - o["x"])) <= 1e-7
             assert abs(d[i].ke[k] / od.ke[k] - 1) <= 1e-9
     sim.close()
+
+
+# ---------------------------------------------------------------------------
+# the drawn initial state (PIC_INIT_DEVICE) against the oracle's generator
+# ---------------------------------------------------------------------------
+INIT_WORKLOADS = {
+    "bounded_mcc_pair": lambda: pin.bounded_mcc(nc=700, ppc=50, seed=51),
+    "bounded_indep_ragged": lambda: pin.bounded_mcc(nc=300, ppc=37.3, seed=52).replace(pair_start=False),
+    "langmuir_perturbed": lambda: pin.langmuir(perturb_amp=1e-2),
+    "langmuir_quiet_cold": lambda: pin.langmuir(nc=128, ppc=20, quiet=True, perturb_amp=1e-3),
+}
+
+
+def _check_drawn(sim, wl, o, prec, inst=0):
+    exact_x = wl.perturb_amp == 0.0
+    for k, s in enumerate(wl.species):
+        g = sim.state(k, inst=inst)  # slot p holds particle p
+        assert np.array_equal(g["id"], o[k].id)
+        vth = wl.vth_hat(s)
+        if prec == FP64:
+            if exact_x:
+                assert np.array_equal(g["x"], o[k].x)
+            else:
+                assert np.max(np.abs(g["x"] - o[k].x)) <= 1e-12 * wl.nc
+            for f in ("vx", "vy", "vz"):
+                assert np.max(np.abs(g[f] - getattr(o[k], f))) <= 1e-13 * vth
+        else:
+            ref = pin.to_fp32_form([o[k]], wl.nc)[0]
+            if exact_x:
+                assert np.array_equal(g["cell"], ref.cell) and np.array_equal(g["f"], ref.f)
+            else:
+                assert np.max(np.abs(g["x"] - ref.as_f64().x)) <= 1e-6
+            for f in ("vx", "vy", "vz"):
+                r = getattr(ref, f).astype(np.float64)
+                assert np.max(np.abs(g[f] - r)) <= 2.0 ** -23 * np.max(np.abs(r)) + 1e-30
+
+
+@pytest.mark.parametrize("prec", [FP32, FP64], ids=["fp32", "fp64"])
+@pytest.mark.parametrize("name", list(INIT_WORKLOADS))
+def test_drawn_initial_state_matches_the_oracle(name, prec):
+    """Positions bit-exact (no perturbation; else within rounding of sin), velocities
+    within a few ulps (the device's log/sin/cos against the host's), ids exact, and the
+    deposit of the drawn state bit-exact against the oracle's."""
+    wl = INIT_WORKLOADS[name]()
+    flush(f"drawn init {name} prec={prec}")
+    sim = P.PicSim(wl, None, prec, flags=P.PIC_INIT_DEVICE | P.PIC_INIT_NO_FIELD)
+    d, rc = sim.diagnostics()
+    assert rc == 0 and d[0].status == 0
+    o = oracle.init_state(wl)
+    _check_drawn(sim, wl, o, prec)
+    if wl.perturb_amp == 0.0:
+        sim.deposit()
+        S = sim.grid(P.PIC_R_DEPOSIT)
+        ref = oracle.init_deposit(wl, fp32_form=(prec == FP32))
+        for k in range(len(wl.species)):
+            assert np.array_equal(S[k], ref[k])
+    sim.close()
+
+
+def test_drawn_initial_state_of_batched_instances():
+    wls = pin.batched(n_inst=4, seed=53, nc_min=64, nc_ratio=8.0, ppc_range=(40.0, 120.0))
+    flush("drawn init batched")
+    sim = P.PicSim(wls, [None] * len(wls), FP64, flags=P.PIC_INIT_DEVICE | P.PIC_INIT_NO_FIELD)
+    for i, w in enumerate(wls):
+        _check_drawn(sim, w, oracle.init_state(w, inst=i), FP64, inst=i)
+    sim.close()
+
+
+def test_drawn_state_rejects_ids_below_the_initial_count():
+    wl = pin.bounded_mcc(nc=64, ppc=10, seed=54)
+    with pytest.raises(P.PicError):
+        P.PicSim(wl, None, FP32, flags=P.PIC_INIT_DEVICE, next_ids=[10])
+
+
+def _sampled_slots(sim, k, idx):
+    """The FP32-form state of slots seg_base + idx of species k (buffer set 0)."""
+    import torch
+    b = int(sim.seg_base[k])
+    ii = torch.from_numpy(np.asarray(idx, np.int64) + b).to(sim.x[0].device)
+    cell = sim.cell[0][ii].cpu().numpy()
+    f = sim.x[0][ii].cpu().numpy()
+    out = {"x": cell.astype(np.float64) + f.astype(np.float64), "cell": cell}
+    for name in ("vx", "vy", "vz"):
+        out[name] = getattr(sim, name)[0][ii].cpu().numpy().astype(np.float64)
+    out["id"] = sim.id[0][ii].cpu().numpy().view(np.uint64)
+    return out
+
+
+@pytest.mark.slow
+def test_full_size_1e6_cells_drawn_state_sampled():
+    """1,000,000 cells and 200 particles per cell per species (4e8 particles), FP32
+    form, drawn on the device.  Bit-exact: the sampled initial particles and the
+    deposit of all 4e8.  Then rho bit-exact, phi/E within the solve's rounding, and
+    one push of 20,000 sampled particles per species against the oracle's push on the
+    oracle's own field (independent positions, so the field is not zero)."""
+    wl = pin.bounded_mcc(nc=1_000_000, ppc=200, seed=5).replace(pair_start=False)
+    n = int(round(200 * wl.nc))
+    caps = [n + n // 20 + 1024] * 2
+    flush("full size 1e6 cells: draw on the device")
+    sim = P.PicSim(wl, None, FP32, capacities=caps, flags=P.PIC_INIT_DEVICE | P.PIC_INIT_NO_FIELD)
+    d, rc = sim.diagnostics()
+    assert rc == 0 and d[0].n_live[0] == n and d[0].n_live[1] == n
+    rng = np.random.default_rng(5)
+    pick = [np.sort(rng.choice(n, 20000, replace=False)) for _ in range(2)]
+    o = oracle.init_state(wl, select=pick)
+    for k in range(2):
+        g = _sampled_slots(sim, k, pick[k])
+        ref = pin.to_fp32_form([o[k]], wl.nc)[0]
+        assert np.array_equal(g["id"], o[k].id)
+        assert np.array_equal(g["x"], ref.as_f64().x)
+    flush("full size 1e6 cells: deposit (oracle: 4e8 particles on one core)")
+    sim.deposit()
+    S = sim.grid(P.PIC_R_DEPOSIT)
+    S_ref = oracle.init_deposit(wl, fp32_form=True)
+    for k in range(2):
+        assert np.array_equal(S[k], S_ref[k])
+    flush("full size 1e6 cells: field")
+    sim.field_solve()
+    empty = [pin.SpeciesState(x=np.zeros(0), vx=np.zeros(0), vy=np.zeros(0), vz=np.zeros(0),
+                              id=np.zeros(0, np.uint64)) for _ in range(2)]
+    full = oracle.OracleSim(wl, empty, caps=[1, 1])
+    for k in range(2):
+        full.S[k][:] = S_ref[k]
+    full.field()
+    assert np.array_equal(sim.grid(P.PIC_R_RHO), full.rho)
+    tol_phi = 8 * wl.nc * EPS64 * np.max(np.abs(full.phi))
+    assert np.max(np.abs(sim.grid(P.PIC_R_PHI) - full.phi)) <= tol_phi
+    flush("full size 1e6 cells: one push of the sample")
+    sim.push(P.PIC_PUSH_NO_DEPOSIT)
+    for k, s in enumerate(wl.species):
+        sub = pin.SpeciesState(x=pin.to_fp32_form([o[k]], wl.nc)[0].as_f64().x,
+                               vx=o[k].vx.astype(np.float32).astype(np.float64),
+                               vy=o[k].vy.astype(np.float32).astype(np.float64),
+                               vz=o[k].vz.astype(np.float32).astype(np.float64), id=o[k].id)
+        states = [sub if q == k else empty[q] for q in range(2)]
+        one = oracle.OracleSim(wl, states, caps=[pick[k].size + 1] * 2)
+        for q in range(2):
+            one.acc[q][:] = full.acc[q]
+        one.push()
+        one.walls()
+        os_ = oracle_state(one, k)
+        g = _sampled_slots(sim, k, pick[k])
+        live = g["cell"] >= 0
+        # absorption can differ only for a particle within rounding of a wall
+        common, gi, oi = np.intersect1d(g["id"][live], os_["id"], return_indices=True)
+        assert np.setxor1d(g["id"][live], os_["id"]).size <= 2
+        vth = wl.vth_hat(s)
+        gx = g["x"][live][gi]
+        assert np.max(np.abs(gx - os_["x"][oi])) <= 1e-5
+        for f in ("vx", "vy", "vz"):
+            err = np.abs(g[f][live][gi] - os_[f][oi]) / np.maximum(np.abs(os_[f][oi]), vth)
+            assert np.max(err) <= 1e-5
+    sim.close()
