@@ -103,6 +103,8 @@ def lib():
         L.orc_deposit_cic64.argtypes = [C.c_int64, dp, C.c_int32, dp]
         L.orc_thomas.argtypes = [C.c_int64, dp, dp, dp, dp, dp]
         L.orc_thomas.restype = C.c_int
+        L.orc_poisson_dirichlet.argtypes = [C.c_int64, dp, dp]
+        L.orc_poisson_dirichlet.restype = C.c_int
         for name in ("orc_deposit", "orc_push", "orc_walls"):
             getattr(L, name).argtypes = [C.POINTER(Sim)]
             getattr(L, name).restype = None
@@ -171,6 +173,15 @@ def thomas(a, b, c, d) -> np.ndarray:
     rc = lib().orc_thomas(d.shape[0], _dp(a), _dp(b), _dp(c), _dp(d), _dp(x))
     if rc:
         raise MemoryError("orc_thomas")
+    return x
+
+
+def poisson_dirichlet(d) -> np.ndarray:
+    """Solve tridiag(1, -2, 1) x = d (Dirichlet ends) with the closed-form pivots."""
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    x = np.zeros_like(d)
+    if lib().orc_poisson_dirichlet(d.shape[0], _dp(d), _dp(x)):
+        raise MemoryError("orc_poisson_dirichlet")
     return x
 
 

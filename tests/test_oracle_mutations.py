@@ -35,6 +35,8 @@ MUTATIONS = [
     ("events not ranked by parent id", "if (n_ev > 1) qsort", "if (0) qsort"),
     ("isotropic cosine range", "double cc = 1.0 - 2.0 * u01(a);", "double cc = 1.0 - u01(a);"),
     ("periodic background dropped", "rho[j] = acc / V + rho_bg;", "rho[j] = acc / V;"),
+    ("Poisson pivot off by one", "const double den = -(u + 1.0) / u;",
+     "const double den = -(u + 2.0) / u;"),
     ("Boris uses dt, not dt/2", "const double tm = (c->q[k] / c->m[k]) * c->B0 * (0.5 * c->dt);",
      "const double tm = (c->q[k] / c->m[k]) * c->B0 * c->dt;"),
 ]
