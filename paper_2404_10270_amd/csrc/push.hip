@@ -8,7 +8,8 @@
 // Sec. 2, phase 4), and the deposit of the new position.
 //
 // Memory plan (HBM-bound):
-//  * structure-of-arrays streamed once; a block owns a tile of kTile
+//  * structure-of-arrays streamed once, with nontemporal loads and stores;
+//    a block owns a tile of kTile
 //    consecutive slots of one segment and every wave issues the loads of all
 //    its kPer 64-slot chunks before computing, so each wave keeps
 //    kPer x (4 + 4 + 12 + 8) bytes x 64 lanes in flight;
@@ -40,6 +41,21 @@ constexpr int kCollQ = kBlock;    // collision slots per block pass (one per thr
 
 // collisions in the mover: none, list the candidates, or collide in place
 enum { kMccOff = 0, kMccList = 1, kMccCollide = 2 };
+
+// Particle arrays are streamed once per step (the state is far larger than
+// the caches): nontemporal loads and stores keep them from displacing the
+// grid, the deposit window flushes and the candidate regions in L2.
+template <typename T>
+__device__ __forceinline__ T stream_ld(const T *p)
+{
+    return __builtin_nontemporal_load(p);
+}
+
+template <typename T>
+__device__ __forceinline__ void stream_st(T *p, T v)
+{
+    __builtin_nontemporal_store(v, p);
+}
 
 struct CollSlot {
     double vx, vy, vz;
@@ -400,12 +416,12 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
             f[k] = vx[k] = vy[k] = vz[k] = 0.f;
             pid[k] = 0;
             if (i < count) {
-                j[k] = CELL[g];
-                f[k] = X[g];
-                vx[k] = VX[g];
-                vy[k] = VY[g];
-                vz[k] = VZ[g];
-                if (MCC != kMccOff) pid[k] = ID[g];
+                j[k] = stream_ld(&CELL[g]);
+                f[k] = stream_ld(&X[g]);
+                vx[k] = stream_ld(&VX[g]);
+                vy[k] = stream_ld(&VY[g]);
+                vz[k] = stream_ld(&VZ[g]);
+                if (MCC != kMccOff) pid[k] = stream_ld(&ID[g]);
             }
             lv[k] = j[k] >= 0;
         }
@@ -500,12 +516,12 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
             const int64_t i = t0 + (int64_t)(wave * kPer + k) * 64 + lane;
             if (i < count && lv[k]) {
                 const int64_t g = base + i;
-                X[g] = f[k];
-                CELL[g] = j[k];
+                stream_st(&X[g], f[k]);
+                stream_st(&CELL[g], j[k]);
                 if (MCC != kMccCollide) {
-                    VX[g] = vx[k];
-                    VY[g] = vy[k];
-                    VZ[g] = vz[k];
+                    stream_st(&VX[g], vx[k]);
+                    stream_st(&VY[g], vy[k]);
+                    stream_st(&VZ[g], vz[k]);
                 }
             }
         }
@@ -547,9 +563,9 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
                 const int64_t i = t0 + (int64_t)(wave * kPer + k) * 64 + lane;
                 if (i < count && lv[k]) {
                     const int64_t g = base + i;
-                    VX[g] = vx[k];
-                    VY[g] = vy[k];
-                    VZ[g] = vz[k];
+                    stream_st(&VX[g], vx[k]);
+                    stream_st(&VY[g], vy[k]);
+                    stream_st(&VZ[g], vz[k]);
                 }
             }
         }
@@ -592,11 +608,11 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
             vx[k] = vy[k] = vz[k] = 0.0;
             pid[k] = 0;
             if (i < count) {
-                x[k] = X[g];
-                vx[k] = VX[g];
-                vy[k] = VY[g];
-                vz[k] = VZ[g];
-                if (MCC != kMccOff) pid[k] = ID[g];
+                x[k] = stream_ld(&X[g]);
+                vx[k] = stream_ld(&VX[g]);
+                vy[k] = stream_ld(&VY[g]);
+                vz[k] = stream_ld(&VZ[g]);
+                if (MCC != kMccOff) pid[k] = stream_ld(&ID[g]);
             }
         }
         const SegConst &sc = d.segc[seg];
@@ -684,11 +700,11 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
             const int64_t i = t0 + (int64_t)(wave * kPer + k) * 64 + lane;
             if (i < count && live[k]) {
                 const int64_t g = base + i;
-                X[g] = x[k];
+                stream_st(&X[g], x[k]);
                 if (MCC != kMccCollide) {
-                    VX[g] = vx[k];
-                    VY[g] = vy[k];
-                    VZ[g] = vz[k];
+                    stream_st(&VX[g], vx[k]);
+                    stream_st(&VY[g], vy[k]);
+                    stream_st(&VZ[g], vz[k]);
                 }
             }
         }
@@ -726,9 +742,9 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
                 const int64_t i = t0 + (int64_t)(wave * kPer + k) * 64 + lane;
                 if (i < count && live[k]) {
                     const int64_t g = base + i;
-                    VX[g] = vx[k];
-                    VY[g] = vy[k];
-                    VZ[g] = vz[k];
+                    stream_st(&VX[g], vx[k]);
+                    stream_st(&VY[g], vy[k]);
+                    stream_st(&VZ[g], vz[k]);
                 }
             }
         }
