@@ -98,6 +98,15 @@ __device__ __forceinline__ void push_lds_init(PushLds &L, const Dev &d)
     __syncthreads();
 }
 
+// a block-uniform value moved to scalar registers (the compiler cannot see
+// that values read from LDS are the same in every lane)
+__device__ __forceinline__ int64_t uniform_i64(int64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // (segment, first slot, occupied slots) of virtual tile t
 __device__ __forceinline__ int tile_seg(const PushLds &L, const Dev &d, int64_t t, int64_t &tile0,
                                         int64_t &base, int64_t &count)
@@ -119,7 +128,10 @@ __device__ __forceinline__ int tile_seg(const PushLds &L, const Dev &d, int64_t 
         base = d.seg_base[seg];
         count = d.segd[seg].count;
     }
-    return seg;
+    tile0 = uniform_i64(tile0);
+    base = uniform_i64(base);
+    count = uniform_i64(count);
+    return __builtin_amdgcn_readfirstlane(seg);
 }
 
 __device__ __forceinline__ int wave_min(int v)
@@ -408,20 +420,29 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
         float f[kPer], vx[kPer], vy[kPer], vz[kPer];
         unsigned long long pid[kPer];
         bool lv[kPer];
+        // the tile's arrays from scalar base pointers; lanes address them with
+        // a 32-bit offset below kTile
+        const int64_t tb = base + t0;
+        const uint32_t rem = (uint32_t)min(count - t0, (int64_t)kTile);
+        float *__restrict__ Xt = X + tb;
+        int32_t *__restrict__ CELLt = CELL + tb;
+        float *__restrict__ VXt = VX + tb;
+        float *__restrict__ VYt = VY + tb;
+        float *__restrict__ VZt = VZ + tb;
+        const unsigned long long *__restrict__ IDt = ID + tb;
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
-            const int64_t i = t0 + (int64_t)(wave * kPer + k) * 64 + lane;
-            const int64_t g = base + i;
+            const uint32_t o = (uint32_t)((wave * kPer + k) * 64 + lane);
             j[k] = kDeadCell;
             f[k] = vx[k] = vy[k] = vz[k] = 0.f;
             pid[k] = 0;
-            if (i < count) {
-                j[k] = stream_ld(&CELL[g]);
-                f[k] = stream_ld(&X[g]);
-                vx[k] = stream_ld(&VX[g]);
-                vy[k] = stream_ld(&VY[g]);
-                vz[k] = stream_ld(&VZ[g]);
-                if (MCC != kMccOff) pid[k] = stream_ld(&ID[g]);
+            if (o < rem) {
+                j[k] = stream_ld(&CELLt[o]);
+                f[k] = stream_ld(&Xt[o]);
+                vx[k] = stream_ld(&VXt[o]);
+                vy[k] = stream_ld(&VYt[o]);
+                vz[k] = stream_ld(&VZt[o]);
+                if (MCC != kMccOff) pid[k] = stream_ld(&IDt[o]);
             }
             lv[k] = j[k] >= 0;
         }
@@ -513,15 +534,14 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
         // still collide (no reads after this point in the tile touch these arrays)
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
-            const int64_t i = t0 + (int64_t)(wave * kPer + k) * 64 + lane;
-            if (i < count && lv[k]) {
-                const int64_t g = base + i;
-                stream_st(&X[g], f[k]);
-                stream_st(&CELL[g], j[k]);
+            const uint32_t o = (uint32_t)((wave * kPer + k) * 64 + lane);
+            if (o < rem && lv[k]) {
+                stream_st(&Xt[o], f[k]);
+                stream_st(&CELLt[o], j[k]);
                 if (MCC != kMccCollide) {
-                    stream_st(&VX[g], vx[k]);
-                    stream_st(&VY[g], vy[k]);
-                    stream_st(&VZ[g], vz[k]);
+                    stream_st(&VXt[o], vx[k]);
+                    stream_st(&VYt[o], vy[k]);
+                    stream_st(&VZt[o], vz[k]);
                 }
             }
         }
@@ -549,23 +569,22 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
         if (MCC == kMccList) {
 #pragma unroll
             for (int k = 0; k < kPer; ++k) {
-                const int64_t g = base + t0 + (int64_t)(wave * kPer + k) * 64 + lane;
-                queue_candidate(L, d, cand[k], (uint32_t)g, inst, vx[k], vy[k], vz[k], pid[k]);
+                const uint32_t o = (uint32_t)((wave * kPer + k) * 64 + lane);
+                queue_candidate(L, d, cand[k], (uint32_t)(tb + o), inst, vx[k], vy[k], vz[k], pid[k]);
             }
         }
         if (DEP) deposit_tile<kPer>(L, S, key, w1);
         // ---- collisions while the velocities are in registers, then their stores
         if (MCC == kMccCollide) {
             collide_tile<float>(L, d, sc, seg, step, cand, pid, vx, vy, vz,
-                                base + t0 + (int64_t)wave * kPer * 64 + lane);
+                                tb + (int64_t)wave * kPer * 64 + lane);
 #pragma unroll
             for (int k = 0; k < kPer; ++k) {
-                const int64_t i = t0 + (int64_t)(wave * kPer + k) * 64 + lane;
-                if (i < count && lv[k]) {
-                    const int64_t g = base + i;
-                    stream_st(&VX[g], vx[k]);
-                    stream_st(&VY[g], vy[k]);
-                    stream_st(&VZ[g], vz[k]);
+                const uint32_t o = (uint32_t)((wave * kPer + k) * 64 + lane);
+                if (o < rem && lv[k]) {
+                    stream_st(&VXt[o], vx[k]);
+                    stream_st(&VYt[o], vy[k]);
+                    stream_st(&VZt[o], vz[k]);
                 }
             }
         }
@@ -600,19 +619,25 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
 
         double x[kPer], vx[kPer], vy[kPer], vz[kPer];
         unsigned long long pid[kPer];
+        const int64_t tb = base + t0;
+        const uint32_t rem = (uint32_t)min(count - t0, (int64_t)kTile);
+        double *__restrict__ Xt = X + tb;
+        double *__restrict__ VXt = VX + tb;
+        double *__restrict__ VYt = VY + tb;
+        double *__restrict__ VZt = VZ + tb;
+        const unsigned long long *__restrict__ IDt = ID + tb;
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
-            const int64_t i = t0 + (int64_t)(wave * kPer + k) * 64 + lane;
-            const int64_t g = base + i;
+            const uint32_t o = (uint32_t)((wave * kPer + k) * 64 + lane);
             x[k] = kDeadX;
             vx[k] = vy[k] = vz[k] = 0.0;
             pid[k] = 0;
-            if (i < count) {
-                x[k] = stream_ld(&X[g]);
-                vx[k] = stream_ld(&VX[g]);
-                vy[k] = stream_ld(&VY[g]);
-                vz[k] = stream_ld(&VZ[g]);
-                if (MCC != kMccOff) pid[k] = stream_ld(&ID[g]);
+            if (o < rem) {
+                x[k] = stream_ld(&Xt[o]);
+                vx[k] = stream_ld(&VXt[o]);
+                vy[k] = stream_ld(&VYt[o]);
+                vz[k] = stream_ld(&VZt[o]);
+                if (MCC != kMccOff) pid[k] = stream_ld(&IDt[o]);
             }
         }
         const SegConst &sc = d.segc[seg];
@@ -697,14 +722,13 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
         }
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
-            const int64_t i = t0 + (int64_t)(wave * kPer + k) * 64 + lane;
-            if (i < count && live[k]) {
-                const int64_t g = base + i;
-                stream_st(&X[g], x[k]);
+            const uint32_t o = (uint32_t)((wave * kPer + k) * 64 + lane);
+            if (o < rem && live[k]) {
+                stream_st(&Xt[o], x[k]);
                 if (MCC != kMccCollide) {
-                    stream_st(&VX[g], vx[k]);
-                    stream_st(&VY[g], vy[k]);
-                    stream_st(&VZ[g], vz[k]);
+                    stream_st(&VXt[o], vx[k]);
+                    stream_st(&VYt[o], vy[k]);
+                    stream_st(&VZt[o], vz[k]);
                 }
             }
         }
@@ -729,22 +753,21 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
         if (MCC == kMccList) {
 #pragma unroll
             for (int k = 0; k < kPer; ++k) {
-                const int64_t g = base + t0 + (int64_t)(wave * kPer + k) * 64 + lane;
-                queue_candidate(L, d, cand[k], (uint32_t)g, inst, vx[k], vy[k], vz[k], pid[k]);
+                const uint32_t o = (uint32_t)((wave * kPer + k) * 64 + lane);
+                queue_candidate(L, d, cand[k], (uint32_t)(tb + o), inst, vx[k], vy[k], vz[k], pid[k]);
             }
         }
         if (DEP) deposit_tile<kPer>(L, S, key, w1);
         if (MCC == kMccCollide) {
             collide_tile<double>(L, d, sc, seg, step, cand, pid, vx, vy, vz,
-                                 base + t0 + (int64_t)wave * kPer * 64 + lane);
+                                 tb + (int64_t)wave * kPer * 64 + lane);
 #pragma unroll
             for (int k = 0; k < kPer; ++k) {
-                const int64_t i = t0 + (int64_t)(wave * kPer + k) * 64 + lane;
-                if (i < count && live[k]) {
-                    const int64_t g = base + i;
-                    stream_st(&VX[g], vx[k]);
-                    stream_st(&VY[g], vy[k]);
-                    stream_st(&VZ[g], vz[k]);
+                const uint32_t o = (uint32_t)((wave * kPer + k) * 64 + lane);
+                if (o < rem && live[k]) {
+                    stream_st(&VXt[o], vx[k]);
+                    stream_st(&VYt[o], vy[k]);
+                    stream_st(&VZt[o], vz[k]);
                 }
             }
         }
