@@ -175,7 +175,6 @@ typedef struct pic_ctx pic_ctx;
 
 /* push flags */
 #define PIC_PUSH_NO_DEPOSIT 0x1u /* do not deposit the new positions */
-#define PIC_PUSH_COLLIDE    0x2u /* run this step's collisions inside the mover */
 
 /*
  * pic_query_sizes -- host only, pure.  Validates n_inst configurations and
@@ -221,10 +220,7 @@ int pic_init(const pic_config *cfgs, int n_inst, const pic_buffers *bufs, void *
  * or periodic re-entry).  Unless PIC_PUSH_NO_DEPOSIT, the new positions are
  * deposited (phase 1 of the next step) into the fixed-point arrays.  With
  * MCC on, every particle takes the null-collision test; the selected ones
- * are listed for pic_mcc_collide, or, with PIC_PUSH_COLLIDE, collided here
- * while still in registers (the same arithmetic and the same result as the
- * separate call; pic_mcc_collide then only creates the pairs and closes the
- * step).
+ * are listed, with their velocities and ids, for pic_mcc_collide.
  */
 int pic_push(pic_ctx *ctx, unsigned flags);
 
@@ -245,8 +241,7 @@ int pic_field_solve(pic_ctx *ctx);
 /*
  * pic_mcc_collide -- phase 4 (Sec. 2, collisions and plasma-wall
  * interaction): null-collision Monte Carlo for the particles listed by
- * pic_push (elastic e-n, charge exchange i-n, ionisation with pair creation;
- * skipped when pic_push already collided them, PIC_PUSH_COLLIDE),
+ * pic_push (elastic e-n, charge exchange i-n, ionisation with pair creation),
  * the pair source refilling this step's ion wall loss, ids of the created
  * particles, and the close of the step (counters, step index).  Must be
  * called once per step after pic_push, also when MCC and source are off.

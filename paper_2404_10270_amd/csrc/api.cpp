@@ -21,7 +21,6 @@ struct pic_ctx {
     Dev d{};
     hipStream_t st = nullptr;
     int64_t host_steps = 0;   // steps enqueued since init
-    bool collided = false;    // the last pic_push ran this step's collisions
     pic_diag *host_diag = nullptr;  // pinned staging for pic_diagnostics
 };
 
@@ -513,10 +512,7 @@ int pic_push(pic_ctx *c, unsigned flags)
 {
     if (!c) return PIC_E_STATE;
     const bool dep = !(flags & PIC_PUSH_NO_DEPOSIT);
-    int mcc = 0;
-    if (c->mcc_any) mcc = (flags & PIC_PUSH_COLLIDE) ? 2 : 1;
-    c->collided = (mcc == 2);
-    return launch_push(c->d, c->st, dep, mcc) == hipSuccess ? PIC_OK : PIC_E_DEVICE;
+    return launch_push(c->d, c->st, dep, c->mcc_any) == hipSuccess ? PIC_OK : PIC_E_DEVICE;
 }
 
 int pic_deposit(pic_ctx *c)
@@ -534,8 +530,7 @@ int pic_field_solve(pic_ctx *c)
 int pic_mcc_collide(pic_ctx *c)
 {
     if (!c) return PIC_E_STATE;
-    if (c->mcc_any && !c->collided && launch_collide(c->d, c->st) != hipSuccess) return PIC_E_DEVICE;
-    c->collided = false;
+    if (c->mcc_any && launch_collide(c->d, c->st) != hipSuccess) return PIC_E_DEVICE;
     if (launch_emit(c->d, c->st, c->mcc_any || c->src_any, c->mcc_any) != hipSuccess) return PIC_E_DEVICE;
     c->host_steps += 1;
     return PIC_OK;

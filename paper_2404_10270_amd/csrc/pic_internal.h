@@ -200,9 +200,8 @@ struct Dev {
 hipError_t launch_init_state(const Dev &d, hipStream_t st, const uint32_t *n_init_dev);
 // draws the initial particles of every segment into buffer set 0
 hipError_t launch_init_device(const Dev &d, hipStream_t st);
-// mcc: 0 no collisions, 1 list the candidates (pic_mcc_collide collides them),
-// 2 collide in the mover
-hipError_t launch_push(const Dev &d, hipStream_t st, bool deposit, int mcc);
+// mcc: test every particle and list the candidates (pic_mcc_collide collides them)
+hipError_t launch_push(const Dev &d, hipStream_t st, bool deposit, bool mcc);
 hipError_t launch_deposit(const Dev &d, hipStream_t st);
 hipError_t launch_field(const Dev &d, hipStream_t st);
 hipError_t launch_collide(const Dev &d, hipStream_t st);

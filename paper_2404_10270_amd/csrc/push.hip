@@ -4,31 +4,24 @@
 // One pass per particle and step: linear gather of the grid acceleration at
 // the in-cell offset, magnetised Boris velocity update, advance x += vx,
 // absorbing or periodic walls, the null-collision candidate test (one Philox
-// block keyed by id and step), optionally the collisions themselves (paper
-// Sec. 2, phase 4), and the deposit of the new position.
+// block keyed by id and step), and the deposit of the new position.
 //
 // Memory plan (HBM-bound):
 //  * structure-of-arrays streamed once, with nontemporal loads and stores;
-//    a block owns a tile of kTile
-//    consecutive slots of one segment and every wave issues the loads of all
-//    its kPer 64-slot chunks before computing, so each wave keeps
-//    kPer x (4 + 4 + 12 + 8) bytes x 64 lanes in flight;
+//    a block owns a tile of kTile consecutive slots of one segment, and every
+//    wave issues the loads of all its kPer 64-slot chunks before computing,
+//    so each wave keeps kPer x (4 + 4 + 12 + 8) bytes x 64 lanes in flight;
+//  * tile base pointers live in scalar registers; lanes address them with a
+//    32-bit offset below kTile;
 //  * segment tables and counts are staged in LDS once per launch, so no
 //    global load sits on the critical path between tiles;
 //  * the deposit of cell-sorted neighbours is summed first over runs of equal
 //    cells inside each wave, then into an LDS window of nodes, and the window
 //    is flushed with one 64-bit global atomic per touched node per tile;
-//  * collisions in the mover (MCC = kMccCollide): the block compacts its
-//    candidates into LDS slots while their velocities are still in
-//    registers, one thread per slot collides, the owners take the new
-//    velocities back, and every particle is stored once; ionisation events
-//    go to the block's own region of the event list, process counts to the
-//    block's own slot;
-//  * otherwise (MCC = kMccList) each candidate, with its velocity and id,
-//    goes to its block's own region of the candidate list (index from an LDS
-//    counter), so the collide kernel reads them contiguously; only a block
-//    with more than kCandQ candidates appends the excess to a shared
-//    overflow list.
+//  * each candidate, with its velocity after the push and its id, goes to its
+//    block's own region of the candidate list (index from an LDS counter), so
+//    the collide kernel reads them contiguously; only a block with more than
+//    kCandQ candidates appends the excess to a shared overflow list.
 #include "device_common.h"
 
 #pragma clang fp contract(off)
@@ -37,10 +30,6 @@ namespace picx {
 
 constexpr int kDepWin = 1024;     // LDS deposit window, nodes
 constexpr int kSegLds = 256;      // segments whose tables are staged in LDS
-constexpr int kCollQ = kBlock;    // collision slots per block pass (one per thread)
-
-// collisions in the mover: none, list the candidates, or collide in place
-enum { kMccOff = 0, kMccList = 1, kMccCollide = 2 };
 
 // Particle arrays are streamed once per step (the state is far larger than
 // the caches): nontemporal loads and stores keep them from displacing the
@@ -57,25 +46,13 @@ __device__ __forceinline__ void stream_st(T *p, T v)
     __builtin_nontemporal_store(v, p);
 }
 
-struct CollSlot {
-    double vx, vy, vz;
-    unsigned long long pid;
-    uint32_t g;
-    uint32_t _pad;
-};
-
 struct PushLds {
     unsigned long long dep[kDepWin];
-    CollSlot cs[kCollQ];
     int64_t tile0[kSegLds + 1];
     int64_t base[kSegLds];
     uint32_t count[kSegLds];
-    IzEvent ev[kEvQ];
-    uint32_t cnt[kCntSeg][kNCnt];
     uint32_t cn;
-    uint32_t en;
     int red[2][kWaves];
-    int wsum[kWaves];
 };
 
 __device__ __forceinline__ void push_lds_init(PushLds &L, const Dev &d)
@@ -90,11 +67,7 @@ __device__ __forceinline__ void push_lds_init(PushLds &L, const Dev &d)
             }
         }
     }
-    for (int q = threadIdx.x; q < kCntSeg * kNCnt; q += kBlock) (&L.cnt[0][0])[q] = 0u;
-    if (threadIdx.x == 0) {
-        L.cn = 0;
-        L.en = 0;
-    }
+    if (threadIdx.x == 0) L.cn = 0;
     __syncthreads();
 }
 
@@ -265,136 +238,10 @@ __device__ __forceinline__ void flush_candidates(PushLds &L, const Dev &d)
     if (threadIdx.x == 0) d.cand_n[blockIdx.x] = min(L.cn, (uint32_t)kCandQ);
 }
 
-// Collisions of the tile's candidates while the particles are in registers
-// (FP32 or FP64 velocities).  The candidates are ranked over the block,
-// copied kCollQ at a time into LDS slots, collided one per thread, and taken
-// back by their owners.  Barriers inside; every thread must call it, and the
-// number of passes is uniform over the block.  g0 is the slot of chunk 0 of
-// this thread; chunk k is at g0 + 64 k.
-template <typename V>
-__device__ __forceinline__ void collide_tile(PushLds &L, const Dev &d, const SegConst &sc, int seg,
-                                             long long step, const bool (&cand)[kPer],
-                                             const unsigned long long (&pid)[kPer],
-                                             V (&vx)[kPer], V (&vy)[kPer], V (&vz)[kPer],
-                                             int64_t g0)
-{
-    const int lane = lane_id();
-    const int wave = threadIdx.x >> 6;
-    int c = 0;
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) c += cand[k] ? 1 : 0;
-    int inc = c;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int t = __shfl_up(inc, o, 64);
-        if (lane >= o) inc += t;
-    }
-    if (lane == 63) L.wsum[wave] = inc;
-    __syncthreads();
-    int pos = inc - c, total = 0;
-#pragma unroll
-    for (int w = 0; w < kWaves; ++w) {
-        if (w < wave) pos += L.wsum[w];
-        total += L.wsum[w];
-    }
-    const bool lds_cnt = d.n_seg <= kCntSeg;
-    for (int r0 = 0; r0 < total; r0 += kCollQ) {
-        int p = pos;
-#pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            if (!cand[k]) continue;
-            if (p >= r0 && p < r0 + kCollQ) {
-                CollSlot &cs = L.cs[p - r0];
-                cs.vx = (double)vx[k];
-                cs.vy = (double)vy[k];
-                cs.vz = (double)vz[k];
-                cs.pid = pid[k];
-                cs.g = (uint32_t)(g0 + 64 * k);
-            }
-            ++p;
-        }
-        __syncthreads();
-        if (threadIdx.x < min(kCollQ, total - r0)) {
-            CollSlot &cs = L.cs[threadIdx.x];
-            uint32_t cnt[kNCnt] = {0, 0, 0, 0, 0};
-            bool iz = false;
-            double g2 = 0.0;
-            double nvx = cs.vx, nvy = cs.vy, nvz = cs.vz;
-            collide_vel(sc, step, cs.pid, nvx, nvy, nvz, cnt, iz, g2);
-            cs.vx = nvx;
-            cs.vy = nvy;
-            cs.vz = nvz;
-            if (lds_cnt) {
-#pragma unroll
-                for (int q = 0; q < kNCnt; ++q)
-                    if (cnt[q]) atomicAdd(&L.cnt[seg][q], cnt[q]);
-            } else {
-                InstDyn *idn = d.instd + sc.inst;
-                atomicAdd(&idn->n_candidates, (unsigned long long)cnt[kCCand]);
-                if (cnt[kCEl]) atomicAdd(&idn->n_elastic, 1ull);
-                if (cnt[kCIz]) atomicAdd(&idn->n_ionize, 1ull);
-                if (cnt[kCCx]) atomicAdd(&idn->n_cx, 1ull);
-                if (cnt[kCOver]) atomicAdd(&idn->n_over_cap, 1ull);
-            }
-            if (iz) {
-                IzEvent ev;
-                ev.parent_id = cs.pid;
-                ev.slot = cs.g;
-                ev.seg = seg;
-                ev.inst = sc.inst;
-                ev._pad = 0;
-                ev.g2 = g2;
-                // the block's LDS queue; the rare excess goes to the overflow list
-                const uint32_t e = atomicAdd(&L.en, 1u);
-                if (e < (uint32_t)kEvQ) {
-                    L.ev[e] = ev;
-                } else {
-                    const uint32_t o = atomicAdd(&d.glob->ev_ovf, 1u);
-                    if (o < (uint32_t)d.ev_ovf_cap) d.ev[(int64_t)d.n_push_blocks * kEvQ + o] = ev;
-                    else atomicOr(&d.instd[sc.inst].status, PIC_ST_CANDIDATES);
-                }
-            }
-        }
-        __syncthreads();
-        p = pos;
-#pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            if (!cand[k]) continue;
-            if (p >= r0 && p < r0 + kCollQ) {
-                const CollSlot &cs = L.cs[p - r0];
-                vx[k] = (V)cs.vx;
-                vy[k] = (V)cs.vy;
-                vz[k] = (V)cs.vz;
-            }
-            ++p;
-        }
-        __syncthreads();
-    }
-    // orders this tile's reads of wsum before the next tile's writes
-    if (total == 0) __syncthreads();
-}
-
-// end of the launch: the block's events to its region, its counts to its slot
-__device__ __forceinline__ void flush_collisions(PushLds &L, const Dev &d)
-{
-    __syncthreads();
-    const uint32_t ne = min(L.en, (uint32_t)kEvQ);
-    for (uint32_t e = threadIdx.x; e < ne; e += kBlock) d.ev[(int64_t)blockIdx.x * kEvQ + e] = L.ev[e];
-    if (threadIdx.x == 0) d.ev_n[blockIdx.x] = ne;
-    if (d.n_seg <= kCntSeg) {
-        // this block's own slot: plain read-modify-write, no other block touches it
-        unsigned long long *slot = d.cnt_slot + (int64_t)blockIdx.x * kCntSeg * kNCnt;
-        for (int q = threadIdx.x; q < d.n_seg * kNCnt; q += kBlock) {
-            const uint32_t v = (&L.cnt[0][0])[q];
-            if (v) slot[q] += v;
-        }
-    }
-}
-
 // ---------------------------------------------------------------------------
 // FP32 form: (int32 cell, float f in [0,1), float v), FP32 gather and push
 // ---------------------------------------------------------------------------
-template <bool DEP, int MCC>
+template <bool DEP, bool MCC>
 __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
 {
     __shared__ PushLds L;
@@ -442,7 +289,7 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
                 vx[k] = stream_ld(&VXt[o]);
                 vy[k] = stream_ld(&VYt[o]);
                 vz[k] = stream_ld(&VZt[o]);
-                if (MCC != kMccOff) pid[k] = stream_ld(&IDt[o]);
+                if (MCC) pid[k] = stream_ld(&IDt[o]);
             }
             lv[k] = j[k] >= 0;
         }
@@ -457,7 +304,7 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
         const unsigned long long T = sc.T;
         const int inst = sc.inst;
         long long step = 0;
-        if (MCC != kMccOff) step = d.instd[inst].step;
+        if (MCC) step = d.instd[inst].step;
         // ---- gather
         float a0[kPer], a1[kPer];
 #pragma unroll
@@ -524,25 +371,22 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
             if (j[k] >= 0) {
                 key[k] = j[k];
                 w1[k] = (unsigned long long)rintf(fn * 4294967296.0f);
-                if (MCC != kMccOff) {
+                if (MCC) {
                     const uint4 u = draw(pid[k], step, 0, key0, key1);
                     cand[k] = (unsigned long long)u.x < T;
                 }
             }
         }
-        // ---- stores of the positions, and of the velocities unless they may
-        // still collide (no reads after this point in the tile touch these arrays)
+        // ---- stores (no reads after this point in the tile touch these arrays)
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
             const uint32_t o = (uint32_t)((wave * kPer + k) * 64 + lane);
             if (o < rem && lv[k]) {
                 stream_st(&Xt[o], f[k]);
                 stream_st(&CELLt[o], j[k]);
-                if (MCC != kMccCollide) {
-                    stream_st(&VXt[o], vx[k]);
-                    stream_st(&VYt[o], vy[k]);
-                    stream_st(&VZt[o], vz[k]);
-                }
+                stream_st(&VXt[o], vx[k]);
+                stream_st(&VYt[o], vy[k]);
+                stream_st(&VZt[o], vz[k]);
             }
         }
         // ---- rare events: wall losses, flags
@@ -566,7 +410,7 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
             wave_or(&idn->status, PIC_ST_NONFINITE, bad);
         }
         // ---- candidates and deposit through LDS
-        if (MCC == kMccList) {
+        if (MCC) {
 #pragma unroll
             for (int k = 0; k < kPer; ++k) {
                 const uint32_t o = (uint32_t)((wave * kPer + k) * 64 + lane);
@@ -574,30 +418,15 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
             }
         }
         if (DEP) deposit_tile<kPer>(L, S, key, w1);
-        // ---- collisions while the velocities are in registers, then their stores
-        if (MCC == kMccCollide) {
-            collide_tile<float>(L, d, sc, seg, step, cand, pid, vx, vy, vz,
-                                tb + (int64_t)wave * kPer * 64 + lane);
-#pragma unroll
-            for (int k = 0; k < kPer; ++k) {
-                const uint32_t o = (uint32_t)((wave * kPer + k) * 64 + lane);
-                if (o < rem && lv[k]) {
-                    stream_st(&VXt[o], vx[k]);
-                    stream_st(&VYt[o], vy[k]);
-                    stream_st(&VZt[o], vz[k]);
-                }
-            }
-        }
     }
-    if (MCC == kMccList) flush_candidates(L, d);
-    if (MCC == kMccCollide) flush_collisions(L, d);
+    if (MCC) flush_candidates(L, d);
 }
 
 // ---------------------------------------------------------------------------
 // FP64 form: double x in cells, double v; the same arithmetic as the FP64
 // reference, operation by operation (no contraction, explicit fma in the gather)
 // ---------------------------------------------------------------------------
-template <bool DEP, int MCC>
+template <bool DEP, bool MCC>
 __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
 {
     __shared__ PushLds L;
@@ -637,7 +466,7 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
                 vx[k] = stream_ld(&VXt[o]);
                 vy[k] = stream_ld(&VYt[o]);
                 vz[k] = stream_ld(&VZt[o]);
-                if (MCC != kMccOff) pid[k] = stream_ld(&IDt[o]);
+                if (MCC) pid[k] = stream_ld(&IDt[o]);
             }
         }
         const SegConst &sc = d.segc[seg];
@@ -650,7 +479,7 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
         const unsigned long long T = sc.T;
         const int inst = sc.inst;
         long long step = 0;
-        if (MCC != kMccOff) step = d.instd[inst].step;
+        if (MCC) step = d.instd[inst].step;
         double a0[kPer], a1[kPer], fr[kPer];
         bool live[kPer];
 #pragma unroll
@@ -714,7 +543,7 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
                 const double jn = floor(x[k]);
                 key[k] = (int)jn;
                 w1[k] = (unsigned long long)rint(ldexp(x[k] - jn, PIC_FRAC_BITS));
-                if (MCC != kMccOff) {
+                if (MCC) {
                     const uint4 u = draw(pid[k], step, 0, key0, key1);
                     cand[k] = (unsigned long long)u.x < T;
                 }
@@ -725,11 +554,9 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
             const uint32_t o = (uint32_t)((wave * kPer + k) * 64 + lane);
             if (o < rem && live[k]) {
                 stream_st(&Xt[o], x[k]);
-                if (MCC != kMccCollide) {
-                    stream_st(&VXt[o], vx[k]);
-                    stream_st(&VYt[o], vy[k]);
-                    stream_st(&VZt[o], vz[k]);
-                }
+                stream_st(&VXt[o], vx[k]);
+                stream_st(&VYt[o], vy[k]);
+                stream_st(&VZt[o], vz[k]);
             }
         }
         const bool left = n_left > 0, right = n_right > 0;
@@ -750,7 +577,7 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
             wave_or(&idn->status, PIC_ST_CFL, cfl);
             wave_or(&idn->status, PIC_ST_NONFINITE, bad);
         }
-        if (MCC == kMccList) {
+        if (MCC) {
 #pragma unroll
             for (int k = 0; k < kPer; ++k) {
                 const uint32_t o = (uint32_t)((wave * kPer + k) * 64 + lane);
@@ -758,22 +585,8 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
             }
         }
         if (DEP) deposit_tile<kPer>(L, S, key, w1);
-        if (MCC == kMccCollide) {
-            collide_tile<double>(L, d, sc, seg, step, cand, pid, vx, vy, vz,
-                                 tb + (int64_t)wave * kPer * 64 + lane);
-#pragma unroll
-            for (int k = 0; k < kPer; ++k) {
-                const uint32_t o = (uint32_t)((wave * kPer + k) * 64 + lane);
-                if (o < rem && live[k]) {
-                    stream_st(&VXt[o], vx[k]);
-                    stream_st(&VYt[o], vy[k]);
-                    stream_st(&VZt[o], vz[k]);
-                }
-            }
-        }
     }
-    if (MCC == kMccList) flush_candidates(L, d);
-    if (MCC == kMccCollide) flush_collisions(L, d);
+    if (MCC) flush_candidates(L, d);
 }
 
 // ---------------------------------------------------------------------------
@@ -834,25 +647,20 @@ int push_grid(const Dev &d)
     return (int)g;
 }
 
-template <bool DEP, int MCC>
+template <bool DEP, bool MCC>
 void launch_push_t(const Dev &d, hipStream_t st, dim3 grid)
 {
     if (d.precision == PIC_FP64) hipLaunchKernelGGL((push_f64_kernel<DEP, MCC>), grid, dim3(kBlock), 0, st, d);
     else hipLaunchKernelGGL((push_f32_kernel<DEP, MCC>), grid, dim3(kBlock), 0, st, d);
 }
 
-hipError_t launch_push(const Dev &d, hipStream_t st, bool dep, int mcc)
+hipError_t launch_push(const Dev &d, hipStream_t st, bool dep, bool mcc)
 {
     const dim3 grid(push_grid(d));
-    if (dep) {
-        if (mcc == kMccCollide) launch_push_t<true, kMccCollide>(d, st, grid);
-        else if (mcc == kMccList) launch_push_t<true, kMccList>(d, st, grid);
-        else launch_push_t<true, kMccOff>(d, st, grid);
-    } else {
-        if (mcc == kMccCollide) launch_push_t<false, kMccCollide>(d, st, grid);
-        else if (mcc == kMccList) launch_push_t<false, kMccList>(d, st, grid);
-        else launch_push_t<false, kMccOff>(d, st, grid);
-    }
+    if (dep && mcc) launch_push_t<true, true>(d, st, grid);
+    else if (dep) launch_push_t<true, false>(d, st, grid);
+    else if (mcc) launch_push_t<false, true>(d, st, grid);
+    else launch_push_t<false, false>(d, st, grid);
     return hipGetLastError();
 }
 

@@ -39,7 +39,6 @@ PIC_INIT_SORT = 0x2
 PIC_INIT_DEVICE = 0x4
 PIC_INIT_OPT_QUIET, PIC_INIT_OPT_PAIR = 0x1, 0x2
 PIC_PUSH_NO_DEPOSIT = 0x1
-PIC_PUSH_COLLIDE = 0x2
 
 # every entry point declared in include/pic.h
 ABI_SYMBOLS = ("pic_query_sizes", "pic_init", "pic_push", "pic_deposit", "pic_field_solve",

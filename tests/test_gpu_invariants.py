@@ -6,8 +6,6 @@ the device, and the full-size bench workload on sampled particles.
   cell offsets equal the scan of the per-cell counts;
 * deposit: every live particle contributes exactly 2^32 after every step;
 * ids stay unique; run-to-run results are identical as sets keyed by id;
-* collisions inside the mover give the same state, bit for bit, as the
-  separate collide call;
 * resume: k steps, a dump of the live particles, a new context from the dump
   and k more steps equal 2k steps in one context, bit for bit;
 * edge cases: an empty species, ragged counts, a capacity overflow, a
@@ -90,39 +88,6 @@ def test_run_to_run_identical(prec):
     for k in range(2):
         for f in ("x", "vx", "vy", "vz", "id"):
             assert np.array_equal(outs[0][k][f], outs[1][k][f])
-
-
-@pytest.mark.parametrize("prec", [FP32, FP64], ids=["fp32", "fp64"])
-def test_collisions_in_the_mover_equal_the_separate_call(prec):
-    wl = pin.bounded_mcc(nc=700, ppc=60, seed=34)
-    wl.mcc.n_n *= 20  # many collisions and ionisation events per step
-    flush(f"fused collisions prec={prec}")
-    a, _, _ = build_pair(wl, prec)
-    b, _, _ = build_pair(wl, prec)
-    for s in range(12):
-        a.push(P.PIC_PUSH_COLLIDE)
-        a.mcc_collide()
-        a.field_solve()
-        b.push()
-        b.mcc_collide()
-        b.field_solve()
-        if s % 5 == 4:
-            a.sort()
-            b.sort()
-    da, rca = a.diagnostics()
-    db, rcb = b.diagnostics()
-    assert rca == 0 and rcb == 0
-    assert da[0].n_ionize > 0 and da[0].n_elastic > 0 and da[0].n_cx > 0
-    for f in ("n_candidates", "n_elastic", "n_ionize", "n_cx", "n_over_cap", "n_source",
-              "next_id", "particle_steps"):
-        assert getattr(da[0], f) == getattr(db[0], f), f
-    for k in range(2):
-        ga, gb = gpu_state(a, k), gpu_state(b, k)
-        for f in ("x", "vx", "vy", "vz", "id"):
-            assert np.array_equal(ga[f], gb[f]), f
-    assert np.array_equal(a.grid(P.PIC_R_ACC64), b.grid(P.PIC_R_ACC64))
-    a.close()
-    b.close()
 
 
 def _dump(sim, k, prec):
