@@ -271,6 +271,18 @@ int pic_diagnostics(pic_ctx *ctx, pic_diag *out, int n_inst);
  */
 int pic_step(pic_ctx *ctx, int n_steps, int sort_every);
 
+/*
+ * pic_step_graph -- the same n_steps whole steps as pic_step, with the same
+ * results, replayed from a HIP graph: one sort period (sort_every steps and
+ * the sort, or one step when sort_every is 0) is captured on a stream the
+ * context owns, instantiated once (again when sort_every changes) and
+ * launched on the context's stream.  Steps before the next sort, and the
+ * remainder after the last whole period, run as in pic_step.  The captured
+ * work holds no memset and no host synchronisation.  Returns PIC_E_DEVICE
+ * when capture or instantiation fails.
+ */
+int pic_step_graph(pic_ctx *ctx, int n_steps, int sort_every);
+
 /* pic_region -- byte offset (into pic_buffers.work) and element count of a
  * workspace region; host only. */
 int pic_region(const pic_ctx *ctx, int region, uint64_t *byte_offset, int64_t *n_elems);

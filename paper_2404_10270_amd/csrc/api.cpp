@@ -22,6 +22,10 @@ struct pic_ctx {
     hipStream_t st = nullptr;
     int64_t host_steps = 0;   // steps enqueued since init
     pic_diag *host_diag = nullptr;  // pinned staging for pic_diagnostics
+    // pic_step_graph: one sort period captured on a stream of its own
+    hipStream_t cap_st = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int g_period = 0, g_sort = -1;
 };
 
 namespace {
@@ -557,6 +561,92 @@ int pic_step(pic_ctx *c, int n_steps, int sort_every)
     return PIC_OK;
 }
 
+namespace {
+
+// enqueue `n` whole steps on c->st, the sort after the last one when `sort`
+int enqueue_period(pic_ctx *c, int n, bool sort)
+{
+    for (int s = 0; s < n; ++s) {
+        int rc = pic_push(c, 0);
+        if (!rc) rc = pic_mcc_collide(c);
+        if (!rc) rc = pic_field_solve(c);
+        if (rc) return rc;
+    }
+    return sort ? pic_sort(c) : PIC_OK;
+}
+
+void drop_graph(pic_ctx *c)
+{
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+    c->g_period = 0;
+    c->g_sort = -1;
+}
+
+// capture one period (sort_every steps and the sort, or one step when
+// sort_every is 0) into c->gexec
+int capture_period(pic_ctx *c, int sort_every)
+{
+    drop_graph(c);
+    if (!c->cap_st && hipStreamCreateWithFlags(&c->cap_st, hipStreamNonBlocking) != hipSuccess) {
+        c->cap_st = nullptr;
+        return PIC_E_DEVICE;
+    }
+    const int period = sort_every > 0 ? sort_every : 1;
+    hipStream_t user = c->st;
+    const int64_t steps = c->host_steps;
+    if (hipStreamBeginCapture(c->cap_st, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return PIC_E_DEVICE;
+    c->st = c->cap_st;
+    const int rc = enqueue_period(c, period, sort_every > 0);
+    c->st = user;
+    c->host_steps = steps;  // capture enqueues nothing
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->cap_st, &g);
+    if (rc || e != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc ? rc : PIC_E_DEVICE;
+    }
+    const hipError_t ei = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+        c->gexec = nullptr;
+        return PIC_E_DEVICE;
+    }
+    c->g_period = period;
+    c->g_sort = sort_every;
+    return PIC_OK;
+}
+
+}  // namespace
+
+int pic_step_graph(pic_ctx *c, int n_steps, int sort_every)
+{
+    if (!c) return PIC_E_STATE;
+    if (n_steps < 0 || sort_every < 0) return PIC_E_ARG;
+    const int64_t step0 = c->cfg[0].step0;
+    int left = n_steps;
+    // eager steps up to the next sort, so that every replay starts a period
+    if (sort_every > 0) {
+        while (left > 0 && ((step0 + c->host_steps) % sort_every) != 0) {
+            const int rc = pic_step(c, 1, sort_every);
+            if (rc) return rc;
+            --left;
+        }
+    }
+    const int period = sort_every > 0 ? sort_every : 1;
+    if (left >= period && (!c->gexec || c->g_sort != sort_every)) {
+        const int rc = capture_period(c, sort_every);
+        if (rc) return rc;
+    }
+    while (left >= period) {
+        if (hipGraphLaunch(c->gexec, c->st) != hipSuccess) return PIC_E_DEVICE;
+        c->host_steps += period;
+        left -= period;
+    }
+    return left > 0 ? pic_step(c, left, sort_every) : PIC_OK;
+}
+
 int pic_diagnostics(pic_ctx *c, pic_diag *out, int n_inst)
 {
     if (!c) return PIC_E_STATE;
@@ -594,6 +684,8 @@ int pic_region(const pic_ctx *c, int region, uint64_t *byte_offset, int64_t *n_e
 int pic_destroy(pic_ctx *c)
 {
     if (!c) return PIC_E_ARG;
+    drop_graph(c);
+    if (c->cap_st) (void)hipStreamDestroy(c->cap_st);
     if (c->host_diag) (void)hipHostFree(c->host_diag);
     delete c;
     return PIC_OK;

@@ -42,8 +42,8 @@ PIC_PUSH_NO_DEPOSIT = 0x1
 
 # every entry point declared in include/pic.h
 ABI_SYMBOLS = ("pic_query_sizes", "pic_init", "pic_push", "pic_deposit", "pic_field_solve",
-               "pic_mcc_collide", "pic_sort", "pic_diagnostics", "pic_step", "pic_region",
-               "pic_destroy", "pic_strerror")
+               "pic_mcc_collide", "pic_sort", "pic_diagnostics", "pic_step", "pic_step_graph",
+               "pic_region", "pic_destroy", "pic_strerror")
 
 
 class pic_species(C.Structure):
@@ -119,6 +119,7 @@ def lib():
                      "pic_destroy"):
             getattr(L, name).argtypes = [P]
         L.pic_step.argtypes = [P, C.c_int, C.c_int]
+        L.pic_step_graph.argtypes = [P, C.c_int, C.c_int]
         L.pic_diagnostics.argtypes = [P, C.POINTER(pic_diag), C.c_int]
         L.pic_region.argtypes = [P, C.c_int, C.POINTER(C.c_uint64), C.POINTER(C.c_int64)]
         L.pic_strerror.argtypes = [C.c_int]
@@ -190,6 +191,10 @@ def pic_sort(ctx):
 
 def pic_step(ctx, n_steps: int, sort_every: int = 0):
     return _check(lib().pic_step(ctx, int(n_steps), int(sort_every)), "pic_step")
+
+
+def pic_step_graph(ctx, n_steps: int, sort_every: int = 0):
+    return _check(lib().pic_step_graph(ctx, n_steps, sort_every), "pic_step_graph")
 
 
 def pic_diagnostics(ctx, n_inst: int = 1):
@@ -352,6 +357,9 @@ class PicSim:
 
     def step(self, n: int = 1, sort_every: int = 0):
         pic_step(self.ctx, n, sort_every)
+
+    def step_graph(self, n: int = 1, sort_every: int = 0):
+        pic_step_graph(self.ctx, n, sort_every)
 
     def diagnostics(self):
         return pic_diagnostics(self.ctx, self.n_inst)

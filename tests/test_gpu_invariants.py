@@ -6,6 +6,9 @@ the device, and the full-size bench workload on sampled particles.
   cell offsets equal the scan of the per-cell counts;
 * deposit: every live particle contributes exactly 2^32 after every step;
 * ids stay unique; run-to-run results are identical as sets keyed by id;
+* graph replay: steps replayed from a captured HIP graph (with eager work and
+  synchronisation between the replays, and a start that is not aligned with
+  the sort period) equal the same steps enqueued one by one, bit for bit;
 * resume: k steps, a dump of the live particles, a new context from the dump
   and k more steps equal 2k steps in one context, bit for bit;
 * edge cases: an empty species, ragged counts, a capacity overflow, a
@@ -88,6 +91,45 @@ def test_run_to_run_identical(prec):
     for k in range(2):
         for f in ("x", "vx", "vy", "vz", "id"):
             assert np.array_equal(outs[0][k][f], outs[1][k][f])
+
+
+@pytest.mark.parametrize("prec", [FP32, FP64], ids=["fp32", "fp64"])
+def test_graph_replays_equal_eager_steps(prec):
+    wl = pin.bounded_mcc(nc=500, ppc=60, seed=39)
+    wl.mcc.n_n *= 10
+    flush(f"graph replay prec={prec}")
+    a, _, _ = build_pair(wl, prec)
+    b, _, _ = build_pair(wl, prec)
+    a.step(67, sort_every=20)
+    b.step_graph(7, 20)        # eager: the first sort comes after step 20
+    b.step_graph(13, 20)       # eager up to the sort
+    b.step_graph(20, 20)       # one replay
+    d, rc = b.diagnostics()    # eager kernels and a synchronisation between replays
+    assert rc == 0 and d[0].step == 40
+    mid = [gpu_state(b, k) for k in range(2)]
+    b.step_graph(20, 20)       # the same graph again
+    d, rc = b.diagnostics()
+    assert rc == 0 and d[0].step == 60 and mid[0]["id"].size > 0
+    b.step_graph(7, 20)        # remainder, eager
+    da, rca = a.diagnostics()
+    db, rcb = b.diagnostics()
+    assert rca == 0 and rcb == 0 and da[0].step == db[0].step == 67
+    for f in ("n_candidates", "n_elastic", "n_ionize", "n_cx", "n_source", "next_id",
+              "particle_steps"):
+        assert getattr(da[0], f) == getattr(db[0], f), f
+    for k in range(2):
+        ga, gb = gpu_state(a, k), gpu_state(b, k)
+        for f in ("x", "vx", "vy", "vz", "id"):
+            assert np.array_equal(ga[f], gb[f]), f
+    # without sorting: a graph of one step, replayed
+    a.step(9, sort_every=0)
+    b.step_graph(9, 0)
+    for k in range(2):
+        ga, gb = gpu_state(a, k), gpu_state(b, k)
+        for f in ("x", "vx", "vy", "vz", "id"):
+            assert np.array_equal(ga[f], gb[f]), f
+    a.close()
+    b.close()
 
 
 def _dump(sim, k, prec):
