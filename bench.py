@@ -69,13 +69,15 @@ def make_sim(wl, st64, precision):
     return P.PicSim(wl, state, precision, capacities=caps, flags=P.PIC_INIT_SORT)
 
 
-def run_form(torch, sim, steps, warmup):
-    """Time `steps` whole steps after `warmup`; returns (p-steps/s, ms/step, p-steps)."""
-    sim.step(warmup, SORT_EVERY)
+def run_form(torch, sim, steps, warmup, graph=False):
+    """Time `steps` whole steps after `warmup`; returns (p-steps/s, ms/step, p-steps).
+    With `graph` the steps are replayed from a captured HIP graph (pic_step_graph)."""
+    step = sim.step_graph if graph else sim.step
+    step(warmup, SORT_EVERY)
     d0, _ = sim.diagnostics()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sim.step(steps, SORT_EVERY)
+    step(steps, SORT_EVERY)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     d1, rc = sim.diagnostics()
@@ -206,6 +208,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--eager", action="store_true",
+                    help="enqueue the timed steps one by one instead of replaying a HIP graph")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the plain copy used to scale the HBM byte counters")
     ap.add_argument("--pmc-summary", nargs=5, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE", "OUT"),
@@ -237,7 +241,7 @@ def main():
     log("FP32 form: init")
     sim = make_sim(wl, st, P.PIC_FP32)
     log(f"FP32 form: {args.warmup} warm-up + {args.steps} timed steps")
-    rate, ms_step, ps = run_form(torch, sim, args.steps, args.warmup)
+    rate, ms_step, ps = run_form(torch, sim, args.steps, args.warmup, graph=not args.eager)
     log(f"FP32 form: {rate:.4e} p-steps/s, {ms_step:.4f} ms/step")
     push_ms, per_launch = time_push(torch, sim, args.push_steps)
     log(f"FP32 mover: {push_ms * 1e3:.1f} us/launch, {per_launch:.0f} particles/launch")
@@ -255,7 +259,7 @@ def main():
     if not args.no_fp64:
         log("FP64 form: init")
         sim64 = make_sim(wl, st, P.PIC_FP64)
-        r64, ms64, _ = run_form(torch, sim64, args.steps, args.warmup)
+        r64, ms64, _ = run_form(torch, sim64, args.steps, args.warmup, graph=not args.eager)
         p64_ms, per64 = time_push(torch, sim64, args.push_steps)
         log(f"FP64 form: {r64:.4e} p-steps/s, mover {p64_ms * 1e3:.1f} us")
         fp64 = {"value": r64, "ms_per_step": round(ms64, 4),

@@ -101,6 +101,12 @@ typedef struct {
     double init_amp;     /* amplitude A of the electron density perturbation */
     int32_t init_mode;   /* its mode number m */
     uint32_t init_opts;  /* PIC_INIT_OPT_* */
+    /* density smoother (Sec. 2, phase 2): passes of the binomial (1,2,1)/4
+       filter on the node charges rho_j V_j before the field solve; at an
+       absorbing wall the quarter that would leave stays on the wall node
+       (total charge unchanged), a periodic grid wraps.  0 = off, at most 64. */
+    int32_t smooth_passes;
+    int32_t _pad2;
 } pic_config;
 
 /* options of the drawn initial state */
@@ -232,9 +238,10 @@ int pic_push(pic_ctx *ctx, unsigned flags);
 int pic_deposit(pic_ctx *ctx);
 
 /*
- * pic_field_solve -- phase 3 (Sec. 2, field solver): rho from the deposit,
- * the tridiagonal Poisson solve in FP64 (Thomas recurrences), E = -grad(phi)
- * and the per-species grid acceleration.  Consumes (clears) the deposit.
+ * pic_field_solve -- phases 2 and 3 (Sec. 2, density smoother and field
+ * solver): rho from the deposit, smoothed when smooth_passes > 0, the
+ * tridiagonal Poisson solve in FP64 (Thomas recurrences), E = -grad(phi) and
+ * the per-species grid acceleration.  Consumes (clears) the deposit.
  */
 int pic_field_solve(pic_ctx *ctx);
 

@@ -53,7 +53,8 @@ class Config(C.Structure):
                 ("kind", C.c_int32 * MAXSP),
                 ("v_cap", C.c_double * MAXSP), ("T_src", C.c_double * MAXSP),
                 ("n_n", C.c_double), ("T_n", C.c_double), ("sig_el", C.c_double),
-                ("sig_iz", C.c_double), ("E_iz", C.c_double), ("sig_cx", C.c_double)]
+                ("sig_iz", C.c_double), ("E_iz", C.c_double), ("sig_cx", C.c_double),
+                ("smooth_passes", C.c_int32), ("_pad", C.c_int32)]
 
 
 class Particles(C.Structure):
@@ -104,6 +105,8 @@ def lib():
         L.orc_thomas.argtypes = [C.c_int64, dp, dp, dp, dp, dp]
         L.orc_thomas.restype = C.c_int
         L.orc_poisson_dirichlet.argtypes = [C.c_int64, dp, dp]
+        L.orc_smooth.argtypes = [C.c_int32, C.c_int, C.c_int, dp, dp]
+        L.orc_smooth.restype = None
         L.orc_poisson_dirichlet.restype = C.c_int
         for name in ("orc_deposit", "orc_push", "orc_walls"):
             getattr(L, name).argtypes = [C.POINTER(Sim)]
@@ -176,6 +179,14 @@ def thomas(a, b, c, d) -> np.ndarray:
     return x
 
 
+def smooth(rho, V, bc: int, passes: int) -> np.ndarray:
+    """The density smoother applied to a copy of rho (nodes 0..nc, volumes V)."""
+    r = np.array(rho, dtype=np.float64)
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    lib().orc_smooth(r.shape[0] - 1, int(bc), int(passes), _dp(V), _dp(r))
+    return r
+
+
 def poisson_dirichlet(d) -> np.ndarray:
     """Solve tridiag(1, -2, 1) x = d (Dirichlet ends) with the closed-form pivots."""
     d = np.ascontiguousarray(d, dtype=np.float64)
@@ -204,6 +215,7 @@ def make_config(wl: pin.Workload, inst: int = 0) -> Config:
         c.kind[k] = s.kind
         c.v_cap[k] = s.v_cap
         c.T_src[k] = s.T_src
+    c.smooth_passes = int(getattr(wl, "smooth_passes", 0))
     if wl.mcc is not None:
         mc = wl.mcc
         c.n_n, c.T_n, c.sig_el, c.sig_iz, c.E_iz, c.sig_cx = (mc.n_n, mc.T_n, mc.sig_el,

@@ -51,6 +51,7 @@ typedef struct {
     double v_cap[ORC_MAXSP];        /* m/s */
     double T_src[ORC_MAXSP];        /* J */
     double n_n, T_n, sig_el, sig_iz, E_iz, sig_cx;
+    int32_t smooth_passes, _pad;    /* density smoother (0 = off) */
 } orc_config;
 
 typedef struct {
@@ -267,6 +268,40 @@ int orc_poisson_dirichlet(int64_t n, const double *d, double *x)
     return 0;
 }
 
+/* Density smoother (Sec. 2, phase 2).  The paper names the phase but gives
+ * no stencil; one pass here is the binomial (1, 2, 1)/4 filter applied to the
+ * node charges Q_j = rho_j V_j: every node keeps half of its charge and
+ * passes a quarter to each neighbour.  At an absorbing wall the quarter that
+ * would leave the domain stays on the wall node, so the total charge is
+ * unchanged; a periodic grid wraps (node nc is node 0).  rho is read and
+ * written in place, V holds the node volumes. */
+void orc_smooth(int32_t nc, int bc, int passes, const double *V, double *rho)
+{
+    const int32_t n = (bc == ORC_BC_PERIODIC) ? nc : nc + 1;  /* distinct nodes */
+    double *Q = (double *)malloc(sizeof(double) * (size_t)n);
+    double *R = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!Q || !R) { free(Q); free(R); return; }
+    for (int32_t j = 0; j < n; ++j) Q[j] = rho[j] * V[j];
+    for (int p = 0; p < passes; ++p) {
+        for (int32_t j = 0; j < n; ++j) {
+            double left, right;
+            if (bc == ORC_BC_PERIODIC) {
+                left = Q[(j + n - 1) % n];
+                right = Q[(j + 1) % n];
+            } else {
+                left = j > 0 ? Q[j - 1] : Q[j];
+                right = j < n - 1 ? Q[j + 1] : Q[j];
+            }
+            R[j] = (left + 2.0 * Q[j] + right) * 0.25;
+        }
+        double *t = Q; Q = R; R = t;
+    }
+    for (int32_t j = 0; j < n; ++j) rho[j] = Q[j] / V[j];
+    if (bc == ORC_BC_PERIODIC) rho[nc] = rho[0];
+    free(Q);
+    free(R);
+}
+
 int orc_field(orc_sim *s)
 {
     const orc_config *c = &s->cfg;
@@ -294,6 +329,14 @@ int orc_field(orc_sim *s)
         double V = dx;
         if (c->bc == ORC_BC_ABSORB && (j == 0 || j == nc)) V = 0.5 * dx;
         rho[j] = acc / V + rho_bg;
+    }
+    if (c->smooth_passes > 0) {
+        double *Vn = (double *)malloc(sizeof(double) * (size_t)(nc + 1));
+        if (!Vn) return -1;
+        for (int32_t j = 0; j <= nc; ++j)
+            Vn[j] = (c->bc == ORC_BC_ABSORB && (j == 0 || j == nc)) ? 0.5 * dx : dx;
+        orc_smooth(nc, c->bc, c->smooth_passes, Vn, rho);
+        free(Vn);
     }
 
     /* unknowns phi_1 .. phi_{nc-1} */

@@ -17,6 +17,7 @@ struct pic_ctx {
     std::vector<pic_config> cfg;
     int n_inst = 0, nsp = 0, precision = 0;
     bool mcc_any = false, src_any = false;
+    int max_smooth = 0;       // most smoother passes of any instance
     Layout L{};
     Dev d{};
     hipStream_t st = nullptr;
@@ -60,6 +61,7 @@ int validate(const pic_config *cfgs, int n_inst)
         if (!finite_pos(c.dx) || !finite_pos(c.dt) || !finite_pos(c.eps0)) return PIC_E_CONFIG;
         if (!finite_nonneg(c.B0) || !std::isfinite(c.theta)) return PIC_E_CONFIG;
         if (c.next_id >= (1ull << 62) || c.step0 < 0) return PIC_E_CONFIG;
+        if (c.smooth_passes < 0 || c.smooth_passes > 64) return PIC_E_CONFIG;
         for (int k = 0; k < nsp; ++k) {
             const pic_species &s = c.sp[k];
             if (!std::isfinite(s.q) || !finite_pos(s.m) || !finite_pos(s.w)) return PIC_E_CONFIG;
@@ -382,6 +384,8 @@ int pic_init(const pic_config *cfgs, int n_inst, const pic_buffers *bufs, void *
         ic.init_amp = cf.init_amp;
         ic.init_mode = cf.init_mode;
         ic.init_opts = (int32_t)cf.init_opts;
+        ic.smooth_passes = cf.smooth_passes;
+        if (cf.smooth_passes > c->max_smooth) c->max_smooth = cf.smooth_passes;
         int64_t id0 = 0;
         for (int k = 0; k < nsp; ++k) {
             const int s = i * nsp + k;
@@ -499,7 +503,7 @@ int pic_init(const pic_config *cfgs, int n_inst, const pic_buffers *bufs, void *
     if (ok && (flags & PIC_INIT_SORT)) ok = launch_sort(d, st) == hipSuccess;
     if (ok && !(flags & PIC_INIT_NO_FIELD)) {
         ok = launch_deposit(d, st) == hipSuccess;
-        ok = ok && launch_field(d, st) == hipSuccess;
+        ok = ok && launch_field(d, st, c->max_smooth) == hipSuccess;
     }
     ok = ok && hipHostMalloc((void **)&c->host_diag, sizeof(pic_diag) * n_inst,
                              hipHostMallocDefault) == hipSuccess;
@@ -528,7 +532,7 @@ int pic_deposit(pic_ctx *c)
 int pic_field_solve(pic_ctx *c)
 {
     if (!c) return PIC_E_STATE;
-    return launch_field(c->d, c->st) == hipSuccess ? PIC_OK : PIC_E_DEVICE;
+    return launch_field(c->d, c->st, c->max_smooth) == hipSuccess ? PIC_OK : PIC_E_DEVICE;
 }
 
 int pic_mcc_collide(pic_ctx *c)

@@ -110,7 +110,8 @@ __device__ __forceinline__ double gq_of(int64_t j)
 // ---------------------------------------------------------------------------
 // 1. rho and the forward composite of every tile
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void field_rho_kernel(Dev d)
+// from_rho: rho is already in place (smoothed); only the composites are formed
+__global__ __launch_bounds__(kBlock) void field_rho_kernel(Dev d, int from_rho)
 {
     const int64_t vt = blockIdx.x;
     const int inst = seg_of_tile(d.inst_ftile0, d.n_inst, vt);
@@ -136,6 +137,14 @@ __global__ __launch_bounds__(kBlock) void field_rho_kernel(Dev d)
     for (int r = 0; r < kFieldR; ++r) {
         const int64_t j = j0 + r;
         if (j > nc) continue;
+        if (from_rho) {
+            if (j >= 1 && j <= nc - 1) {
+                const double dd = -(d.rho[ic.gnode + j] * ic.K);
+                const double gq = gq_of(j);
+                m = compose(Aff{gq, -(gq * dd)}, m);
+            }
+            continue;
+        }
         double acc = 0.0;
         for (int k = 0; k < nsp; ++k) {
             const unsigned long long *S = d.S + k * G + ic.gnode;
@@ -352,12 +361,74 @@ __global__ __launch_bounds__(kBlock) void field_bwd_kernel(Dev d)
     if (threadIdx.x == 0) d.fe_part[ic.ftile0 + lt] = s_fe[0];
 }
 
-hipError_t launch_field(const Dev &d, hipStream_t st)
+// ---------------------------------------------------------------------------
+// density smoother (Sec. 2, phase 2): one pass of the binomial (1,2,1)/4
+// filter on the node charges Q_j = rho_j V_j of every instance with more
+// than `pass` passes (the others are copied).  The first pass reads rho and
+// forms Q, the last divides by V again, so Q is carried between passes as the
+// oracle carries it.  At an absorbing wall the outgoing quarter stays on the
+// wall node; a periodic grid wraps and node nc repeats node 0.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void field_smooth_kernel(Dev d, const double *in, double *out,
+                                                             int pass, int last_pass)
+{
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (g >= d.G) return;
+    const int inst = seg_of_tile(d.node_base, d.n_inst, g);
+    const InstConst &ic = d.instc[inst];
+    const int64_t j = g - ic.gnode;
+    const int nc = ic.nc;
+    const bool periodic = (ic.bc == PIC_BC_PERIODIC);
+    const int passes = ic.smooth_passes;
+    if (pass >= passes) {  // not smoothed this pass: carry the value through
+        out[g] = in[g];
+        return;
+    }
+    const bool first = (pass == 0), last = (pass == passes - 1) || (pass == last_pass);
+    const double dx = ic.dx;
+    auto vol = [&](int64_t q) { return (!periodic && (q == 0 || q == nc)) ? 0.5 * dx : dx; };
+    auto charge = [&](int64_t q) { return first ? in[ic.gnode + q] * vol(q) : in[ic.gnode + q]; };
+    int64_t jj = j, jl, jr;
+    if (periodic) {
+        if (jj == nc) jj = 0;
+        jl = jj > 0 ? jj - 1 : nc - 1;
+        jr = jj < nc - 1 ? jj + 1 : 0;
+    } else {
+        jl = jj > 0 ? jj - 1 : jj;
+        jr = jj < nc ? jj + 1 : jj;
+    }
+    const double r = (charge(jl) + 2.0 * charge(jj) + charge(jr)) * 0.25;
+    out[g] = last ? r / vol(jj) : r;
+}
+
+hipError_t launch_field(const Dev &d, hipStream_t st, int smooth)
 {
     const dim3 grid((unsigned)d.n_field_tiles), block(kBlock);
-    hipLaunchKernelGGL(field_rho_kernel, grid, block, 0, st, d);
+    hipLaunchKernelGGL(field_rho_kernel, grid, block, 0, st, d, 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (smooth > 0) {
+        // passes alternate between rho and the d' array (free until the forward sweep)
+        const dim3 ng((unsigned)((d.G + kBlock - 1) / kBlock));
+        double *a = d.rho, *b = d.dprime;
+        for (int p = 0; p < smooth; ++p) {
+            hipLaunchKernelGGL(field_smooth_kernel, ng, block, 0, st, d, a, b, p, smooth - 1);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            double *t = a;
+            a = b;
+            b = t;
+        }
+        if (a != d.rho) {  // an odd number of passes: the result is in d'
+            hipLaunchKernelGGL(field_smooth_kernel, ng, block, 0, st, d, (const double *)a, d.rho,
+                               smooth, smooth);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(field_rho_kernel, grid, block, 0, st, d, 1);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(field_fwd_kernel, grid, block, 0, st, d);
     e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -73,6 +73,7 @@ struct InstConst {
     double dx, eps0, K; // K = dx^2 / eps0
     double init_amp;    // drawn initial state: perturbation amplitude, mode, PIC_INIT_OPT_*
     int32_t init_mode, init_opts;
+    int32_t smooth_passes, _pad;
 };
 
 // dynamic per-segment counters
@@ -203,7 +204,8 @@ hipError_t launch_init_device(const Dev &d, hipStream_t st);
 // mcc: test every particle and list the candidates (pic_mcc_collide collides them)
 hipError_t launch_push(const Dev &d, hipStream_t st, bool deposit, bool mcc);
 hipError_t launch_deposit(const Dev &d, hipStream_t st);
-hipError_t launch_field(const Dev &d, hipStream_t st);
+// smooth: the most density-smoother passes of any instance
+hipError_t launch_field(const Dev &d, hipStream_t st, int smooth);
 hipError_t launch_collide(const Dev &d, hipStream_t st);
 // ionisation and source pairs (when `pairs`), then the close of the step
 // (`events`: collisions ran this step)

@@ -62,7 +62,8 @@ class pic_config(C.Structure):
                 ("n_n", C.c_double), ("T_n", C.c_double), ("sig_el", C.c_double),
                 ("sig_iz", C.c_double), ("E_iz", C.c_double), ("sig_cx", C.c_double),
                 ("next_id", C.c_uint64), ("step0", C.c_int64),
-                ("init_amp", C.c_double), ("init_mode", C.c_int32), ("init_opts", C.c_uint32)]
+                ("init_amp", C.c_double), ("init_mode", C.c_int32), ("init_opts", C.c_uint32),
+                ("smooth_passes", C.c_int32), ("_pad2", C.c_int32)]
 
 
 class pic_sizes(C.Structure):
@@ -249,6 +250,7 @@ def make_config(wl, precision: int, capacities: Sequence[int], n_init: Sequence[
     c.init_mode = int(getattr(wl, "perturb_mode", 1))
     c.init_opts = ((PIC_INIT_OPT_QUIET if getattr(wl, "quiet", False) else 0)
                    | (PIC_INIT_OPT_PAIR if getattr(wl, "pair_start", False) else 0))
+    c.smooth_passes = int(getattr(wl, "smooth_passes", 0))
     return c
 
 

@@ -96,6 +96,7 @@ class Workload:
     quiet: bool = False         # lattice positions instead of random ones
     pair_start: bool = False    # every ion starts at an electron's position (neutral start)
     state_seed: Optional[int] = None  # seed of the initial-state generator (default: seed)
+    smooth_passes: int = 0      # binomial density-smoother passes before the field solve
 
     def replace(self, **kw) -> "Workload":
         return dataclasses.replace(self, **kw)

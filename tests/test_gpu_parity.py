@@ -28,6 +28,10 @@ WORKLOADS = {
     "langmuir": lambda: pin.langmuir(),                               # 512 cells, 51,200 e
     "bounded_ragged": lambda: pin.bounded(nc=300, ppc=37.3, seed=7),  # 2 species, ragged counts
     "bounded_mcc": lambda: pin.bounded_mcc(nc=700, ppc=50, seed=8),
+    # density smoother on: three passes with walls, two on a periodic grid
+    "bounded_smooth3": lambda: pin.bounded(nc=300, ppc=37.3, seed=9).replace(pair_start=False,
+                                                                              smooth_passes=3),
+    "langmuir_smooth2": lambda: pin.langmuir(nc=256, ppc=40).replace(smooth_passes=2),
 }
 
 
