@@ -290,6 +290,20 @@ int pic_step(pic_ctx *ctx, int n_steps, int sort_every);
  */
 int pic_step_graph(pic_ctx *ctx, int n_steps, int sort_every);
 
+/*
+ * pic_autotune_sort -- choose the sort cadence by measurement ("natural
+ * sorting", Sec. 2: how often to restore the order by cell).  For each of
+ * the n_cand candidates (a cadence in steps, 0 = never) the particles are
+ * sorted, then trial_steps whole steps run as in pic_step_graph and are
+ * timed with HIP events; *best receives the candidate with the most
+ * particle-steps per second, rates[i] (may be NULL) each candidate's rate.
+ * The trials advance the simulation by n_cand * trial_steps steps, like
+ * warm-up steps; make trial_steps a multiple of every candidate so that each
+ * trial ends with a sort.  Synchronises the stream.
+ */
+int pic_autotune_sort(pic_ctx *ctx, const int *cand, int n_cand, int trial_steps, int *best,
+                      double *rates);
+
 /* pic_region -- byte offset (into pic_buffers.work) and element count of a
  * workspace region; host only. */
 int pic_region(const pic_ctx *ctx, int region, uint64_t *byte_offset, int64_t *n_elems);

@@ -262,17 +262,28 @@ int plan(const pic_config *cfgs, int n_inst, Plan &p)
     L.bwd_status = take(sizeof(AffineStatus) * p.n_field_tiles);
     L.sort_status = take(sizeof(uint64_t) * p.n_sort_tiles);
     L.fe_part = take(sizeof(double) * p.n_field_tiles);
-    // candidates: one region of kCandQ per push block, then an overflow list
-    // sized for the expected total (mean + 10 sigma)
+    // candidates: one region per push block, sized so that a block holds
+    // 1.25 times its share of the candidates of a full capacity (the shared
+    // overflow list, whose appends contend on one counter, stays rare), then
+    // an overflow list sized for the expected total (mean + 10 sigma)
     p.n_push_blocks = (int)std::min<int64_t>(std::max<int64_t>(p.n_tiles, 1), kMaxPushBlocks);
     L.cand_ovf_cap = cand_capacity(cfgs, n_inst, P);
     L.ev_ovf_cap = L.cand_ovf_cap;
-    L.cand = take(sizeof(Cand) * ((uint64_t)p.n_push_blocks * kCandQ + L.cand_ovf_cap));
+    double expect = 0.0;
+    for (int s = 0; s < n_seg; ++s) {
+        const pic_config &cf = cfgs[s / nsp];
+        expect += (double)cf.sp[s % nsp].capacity * P[s];
+    }
+    L.cand_q = std::max<int64_t>(kCandQMin,
+                                 (int64_t)align_up((uint64_t)(1.25 * expect / p.n_push_blocks) + 64, 64));
+    L.ev_q = std::max<int64_t>(kEvQMin, L.cand_q / 16);
+    L.cand = take(sizeof(Cand) * ((uint64_t)p.n_push_blocks * L.cand_q + L.cand_ovf_cap));
     L.cand_n = take(sizeof(uint32_t) * p.n_push_blocks);
-    L.ev = take(sizeof(IzEvent) * ((uint64_t)p.n_push_blocks * kEvQ + L.ev_ovf_cap));
+    L.ev = take(sizeof(IzEvent) * ((uint64_t)p.n_push_blocks * L.ev_q + L.ev_ovf_cap));
     L.ev_n = take(sizeof(uint32_t) * p.n_push_blocks);
-    L.ev_rank = take(sizeof(uint32_t) * ((uint64_t)p.n_push_blocks * kEvQ + L.ev_ovf_cap));
-    L.cnt_slot = take(sizeof(unsigned long long) * (uint64_t)p.n_push_blocks * kCntSeg * kNCnt);
+    L.ev_rank = take(sizeof(uint32_t) * ((uint64_t)p.n_push_blocks * L.ev_q + L.ev_ovf_cap));
+    L.cnt_slot = take(sizeof(unsigned long long) * (uint64_t)p.n_push_blocks *
+                      (n_seg <= kCntSegMax ? n_seg : 0) * kNCnt);
     L.diag_part = take(sizeof(double) * (uint64_t)kDiagBlocks * n_seg * kDiagVals);
     L.diag_out = take(sizeof(pic_diag) * n_inst);
     L.total = off;
@@ -469,6 +480,8 @@ int pic_init(const pic_config *cfgs, int n_inst, const pic_buffers *bufs, void *
     d.G = p.G;
     d.cand_ovf_cap = L.cand_ovf_cap;
     d.ev_ovf_cap = L.ev_ovf_cap;
+    d.cand_q = (int32_t)L.cand_q;
+    d.ev_q = (int32_t)L.ev_q;
     d.n_push_blocks = p.n_push_blocks;
     d.n_field_tiles = p.n_field_tiles;
     d.n_sort_tiles = p.n_sort_tiles;
@@ -649,6 +662,61 @@ int pic_step_graph(pic_ctx *c, int n_steps, int sort_every)
         left -= period;
     }
     return left > 0 ? pic_step(c, left, sort_every) : PIC_OK;
+}
+
+int pic_autotune_sort(pic_ctx *c, const int *cand, int n_cand, int trial_steps, int *best,
+                      double *rates)
+{
+    if (!c) return PIC_E_STATE;
+    if (!cand || n_cand < 1 || trial_steps < 1 || !best) return PIC_E_ARG;
+    for (int i = 0; i < n_cand; ++i)
+        if (cand[i] < 0) return PIC_E_ARG;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return PIC_E_DEVICE;
+    }
+    std::vector<InstDyn> before(c->n_inst), after(c->n_inst);
+    int rc = PIC_OK, pick = 0;
+    double best_rate = -1.0;
+    for (int i = 0; i < n_cand && rc == PIC_OK; ++i) {
+        // every trial starts from freshly sorted particles
+        rc = pic_sort(c);
+        if (rc) break;
+        if (hipMemcpyAsync(before.data(), c->d.instd, sizeof(InstDyn) * c->n_inst,
+                           hipMemcpyDeviceToHost, c->st) != hipSuccess ||
+            hipEventRecord(e0, c->st) != hipSuccess) {
+            rc = PIC_E_DEVICE;
+            break;
+        }
+        rc = pic_step_graph(c, trial_steps, cand[i]);
+        if (rc) break;
+        if (hipEventRecord(e1, c->st) != hipSuccess ||
+            hipMemcpyAsync(after.data(), c->d.instd, sizeof(InstDyn) * c->n_inst,
+                           hipMemcpyDeviceToHost, c->st) != hipSuccess ||
+            hipStreamSynchronize(c->st) != hipSuccess) {
+            rc = PIC_E_DEVICE;
+            break;
+        }
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess || !(ms > 0.f)) {
+            rc = PIC_E_DEVICE;
+            break;
+        }
+        double ps = 0.0;
+        for (int k = 0; k < c->n_inst; ++k)
+            ps += (double)(after[k].particle_steps - before[k].particle_steps);
+        const double rate = ps / (1e-3 * (double)ms);
+        if (rates) rates[i] = rate;
+        if (rate > best_rate) {
+            best_rate = rate;
+            pick = i;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc == PIC_OK) *best = cand[pick];
+    return rc;
 }
 
 int pic_diagnostics(pic_ctx *c, pic_diag *out, int n_inst)

@@ -95,12 +95,12 @@ __global__ __launch_bounds__(kBlock) void diag_final_kernel(Dev d, int n_blocks)
     }
     unsigned long long pc[kNCnt] = {idn.n_candidates, idn.n_elastic, idn.n_ionize, idn.n_cx,
                                     idn.n_over_cap};
-    if (d.n_seg <= kCntSeg) {
+    if (d.n_seg <= kCntSegMax) {
         for (int q = 0; q < kNCnt; ++q) {
             double a = 0.0;  // exact: counts stay far below 2^53
             for (int b = threadIdx.x; b < d.n_push_blocks; b += kBlock)
                 for (int k = 0; k < ic.nsp; ++k)
-                    a += (double)d.cnt_slot[((int64_t)b * kCntSeg + ic.seg0 + k) * kNCnt + q];
+                    a += (double)d.cnt_slot[((int64_t)b * d.n_seg + ic.seg0 + k) * kNCnt + q];
             pc[q] += (unsigned long long)block_sum(a, s_red);
         }
     }

@@ -69,11 +69,11 @@ __device__ __forceinline__ void add_counts(InstDyn *idn, const uint32_t (&c)[kNC
 
 __global__ __launch_bounds__(kBlock) void collide_kernel(Dev d)
 {
-    __shared__ uint32_t s_cnt[kCntSeg][kNCnt];
-    __shared__ IzEvent s_ev[kEvQ];
+    extern __shared__ uint32_t s_cnt[];  // [n_seg][kNCnt] when n_seg <= kCntSegMax
     __shared__ uint32_t s_en;
-    const bool lds_cnt = d.n_seg <= kCntSeg;
-    for (int q = threadIdx.x; q < kCntSeg * kNCnt; q += kBlock) (&s_cnt[0][0])[q] = 0u;
+    const bool lds_cnt = d.n_seg <= kCntSegMax;
+    if (lds_cnt)
+        for (int q = threadIdx.x; q < d.n_seg * kNCnt; q += kBlock) s_cnt[q] = 0u;
     if (threadIdx.x == 0) s_en = 0u;
     __syncthreads();
 
@@ -91,37 +91,35 @@ __global__ __launch_bounds__(kBlock) void collide_kernel(Dev d)
         uint32_t cnt[kNCnt] = {0, 0, 0, 0, 0};
         bool iz = false;
         IzEvent ev = {};
-        const int64_t idx = q < nr ? (int64_t)blockIdx.x * kCandQ + q
-                                   : (int64_t)d.n_push_blocks * kCandQ + o_lo + (q - nr);
+        const int64_t idx = q < nr ? (int64_t)blockIdx.x * d.cand_q + q
+                                   : (int64_t)d.n_push_blocks * d.cand_q + o_lo + (q - nr);
         const int seg = collide_one(d, cur, f64, d.cand[idx], cnt, iz, ev);
         if (iz) {
-            // LDS queue of this block; the rare excess goes to the overflow list
+            // this block's region of the event list; the rare excess goes to the overflow list
             const uint32_t e = atomicAdd(&s_en, 1u);
-            if (e < (uint32_t)kEvQ) {
-                s_ev[e] = ev;
+            if (e < (uint32_t)d.ev_q) {
+                d.ev[(int64_t)blockIdx.x * d.ev_q + e] = ev;
             } else {
                 const uint32_t o = atomicAdd(&d.glob->ev_ovf, 1u);
-                if (o < (uint32_t)d.ev_ovf_cap) d.ev[(int64_t)d.n_push_blocks * kEvQ + o] = ev;
+                if (o < (uint32_t)d.ev_ovf_cap) d.ev[(int64_t)d.n_push_blocks * d.ev_q + o] = ev;
                 else atomicOr(&d.instd[ev.inst].status, PIC_ST_CANDIDATES);
             }
         }
         if (lds_cnt) {
 #pragma unroll
             for (int c = 0; c < kNCnt; ++c)
-                if (cnt[c]) atomicAdd(&s_cnt[seg][c], cnt[c]);
+                if (cnt[c]) atomicAdd(&s_cnt[seg * kNCnt + c], cnt[c]);
         } else {
             add_counts(d.instd + d.segc[seg].inst, cnt);
         }
     }
     __syncthreads();
-    const uint32_t ne = min(s_en, (uint32_t)kEvQ);
-    for (uint32_t e = threadIdx.x; e < ne; e += kBlock) d.ev[(int64_t)blockIdx.x * kEvQ + e] = s_ev[e];
-    if (threadIdx.x == 0) d.ev_n[blockIdx.x] = ne;
+    if (threadIdx.x == 0) d.ev_n[blockIdx.x] = min(s_en, (uint32_t)d.ev_q);
     if (lds_cnt) {
         // this block's own slot: plain read-modify-write, no other block touches it
-        unsigned long long *slot = d.cnt_slot + (int64_t)blockIdx.x * kCntSeg * kNCnt;
+        unsigned long long *slot = d.cnt_slot + (int64_t)blockIdx.x * d.n_seg * kNCnt;
         for (int q = threadIdx.x; q < d.n_seg * kNCnt; q += kBlock) {
-            const uint32_t v = (&s_cnt[0][0])[q];
+            const uint32_t v = s_cnt[q];
             if (v) slot[q] += v;
         }
     }
@@ -179,13 +177,13 @@ __device__ void build_event_index(EventIndex &X, const Dev &d)
 __device__ __forceinline__ const IzEvent &event_at(const EventIndex &X, const Dev &d, uint32_t e)
 {
     if (e >= X.in_regions)
-        return d.ev[(int64_t)d.n_push_blocks * kEvQ + (e - X.in_regions)];
+        return d.ev[(int64_t)d.n_push_blocks * d.ev_q + (e - X.in_regions)];
     int lo = 0, hi = d.n_push_blocks - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (X.pre[mid] <= e) lo = mid; else hi = mid - 1;
     }
-    return d.ev[(int64_t)lo * kEvQ + (e - X.pre[lo])];
+    return d.ev[(int64_t)lo * d.ev_q + (e - X.pre[lo])];
 }
 
 // write one created particle into segment `seg`, in-segment index `i`
@@ -235,8 +233,19 @@ __device__ void count_events(const EventIndex &X, const Dev &d, uint32_t *s_m, i
     }
     for (int i = threadIdx.x; i < n_inst; i += kBlock) s_m[i] = 0u;
     __syncthreads();
-    for (uint32_t e = threadIdx.x; e < X.total; e += kBlock) {
-        const int inst = event_at(X, d, e).inst;
+    // region by region (no index search): thread t takes regions t, t + kBlock, ...
+    for (int b = threadIdx.x; b < d.n_push_blocks; b += kBlock) {
+        const uint32_t n = X.pre[b + 1] - X.pre[b];
+        const IzEvent *r = d.ev + (int64_t)b * d.ev_q;
+        for (uint32_t e = 0; e < n; ++e) {
+            const int inst = r[e].inst;
+            if (inst < n_inst) atomicAdd(&s_m[inst], 1u);
+        }
+    }
+    const uint32_t n_ovf = X.total - X.in_regions;
+    const IzEvent *o = d.ev + (int64_t)d.n_push_blocks * d.ev_q;
+    for (uint32_t e = threadIdx.x; e < n_ovf; e += kBlock) {
+        const int inst = o[e].inst;
         if (inst < n_inst) atomicAdd(&s_m[inst], 1u);
     }
     __syncthreads();
@@ -444,7 +453,8 @@ __global__ __launch_bounds__(kBlock) void close_step_kernel(Dev d, int with_even
 
 hipError_t launch_collide(const Dev &d, hipStream_t st)
 {
-    hipLaunchKernelGGL(collide_kernel, dim3(d.n_push_blocks), dim3(kBlock), 0, st, d);
+    const size_t lds = d.n_seg <= kCntSegMax ? sizeof(uint32_t) * d.n_seg * kNCnt : 0;
+    hipLaunchKernelGGL(collide_kernel, dim3(d.n_push_blocks), dim3(kBlock), lds, st, d);
     return hipGetLastError();
 }
 

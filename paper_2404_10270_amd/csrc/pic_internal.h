@@ -24,9 +24,9 @@ constexpr int kDiagBlocks = 1024;           // blocks of the diagnostics reducti
 constexpr int kEmitBlocks = 64;             // blocks of the emit/close-of-step kernel
 constexpr int kDiagVals = 6;                // live, sum v2, sum vx, vy, vz, (pad)
 constexpr int kMaxPushBlocks = 256 * 8;     // persistent grid of the particle kernels
-constexpr int kCandQ = 1024;                // candidate entries per push block region
-constexpr int kEvQ = 32;                    // ionisation-event slots per collide block
-constexpr int kCntSeg = 64;                 // segments counted per block without atomics
+constexpr int kCandQMin = 1024;             // least candidate entries per push block region
+constexpr int kEvQMin = 32;                 // least ionisation-event slots per collide block
+constexpr int kCntSegMax = 1024;           // segments counted per block in LDS (no atomics)
 constexpr int kNCnt = 5;                    // candidates, elastic, ionisation, CX, over v_cap
 constexpr int kRankJ = 64;                  // events compared per block pass of the rank kernel
 constexpr int kRankBlocks = 512;            // grid of the rank kernel
@@ -93,7 +93,7 @@ struct InstDyn {
     unsigned long long next_id;
     uint32_t status;
     uint32_t _pad;
-    // process counts of batches with more than kCntSeg segments (otherwise per-block slots)
+    // process counts of batches with more than kCntSegMax segments (otherwise per-block slots)
     unsigned long long n_candidates, n_elastic, n_ionize, n_cx, n_over_cap;
     unsigned long long n_source;
     unsigned long long particle_steps;
@@ -150,6 +150,7 @@ struct Layout {
     uint64_t diag_part, diag_out;
     uint64_t total;
     int64_t cand_ovf_cap, ev_ovf_cap;
+    int64_t cand_q, ev_q;
     int64_t n_field_tiles, n_sort_tiles;
 };
 
@@ -180,12 +181,12 @@ struct Dev {
     AffineStatus *fwd_status, *bwd_status;
     unsigned long long *sort_status;
     double *fe_part;
-    Cand *cand;                 // [n_push_blocks][kCandQ] per-block regions, then the overflow list
+    Cand *cand;                 // [n_push_blocks][cand_q] per-block regions, then the overflow list
     uint32_t *cand_n;           // [n_push_blocks] candidates in each region
-    IzEvent *ev;                // [n_push_blocks][kEvQ] per-block regions, then the overflow list
+    IzEvent *ev;                // [n_push_blocks][ev_q] per-block regions, then the overflow list
     uint32_t *ev_n;             // [n_push_blocks] events in each region
     uint32_t *ev_rank;          // [events] rank of each event among its instance's (by parent id)
-    unsigned long long *cnt_slot;  // [n_push_blocks][kCntSeg][kNCnt] process counts per block
+    unsigned long long *cnt_slot;  // [n_push_blocks][n_seg][kNCnt] process counts per block
     double *diag_part;
     pic_diag *diag_out;
     // sizes
@@ -193,6 +194,7 @@ struct Dev {
     int64_t n_field_tiles, n_sort_tiles;
     int32_t n_seg, n_inst, nsp, precision;
     int32_t n_push_blocks, _pad;
+    int32_t cand_q, ev_q;       // entries per block region of the candidate and event lists
 };
 
 // ---------------------------------------------------------------------------

@@ -21,7 +21,8 @@
 //  * each candidate, with its velocity after the push and its id, goes to its
 //    block's own region of the candidate list (index from an LDS counter), so
 //    the collide kernel reads them contiguously; only a block with more than
-//    kCandQ candidates appends the excess to a shared overflow list.
+//    its region's cand_q candidates appends the excess to a shared overflow
+//    list.
 #include "device_common.h"
 
 #pragma clang fp contract(off)
@@ -29,7 +30,7 @@
 namespace picx {
 
 constexpr int kDepWin = 1024;     // LDS deposit window, nodes
-constexpr int kSegLds = 256;      // segments whose tables are staged in LDS
+constexpr int kSegLds = 1024;     // segments whose tables are staged in LDS
 
 // Particle arrays are streamed once per step (the state is far larger than
 // the caches): nontemporal loads and stores keep them from displacing the
@@ -202,7 +203,7 @@ __device__ __forceinline__ void queue_candidate(PushLds &L, const Dev &d, bool c
     if (lane == leader) base = atomicAdd(&L.cn, n);
     base = __shfl(base, leader, 64);
     // the first n_reg candidates fill the rest of the region, the others overflow
-    const uint32_t room = base < (uint32_t)kCandQ ? (uint32_t)kCandQ - base : 0u;
+    const uint32_t room = base < (uint32_t)d.cand_q ? (uint32_t)d.cand_q - base : 0u;
     const uint32_t n_reg = n < room ? n : room;
     uint32_t gb = 0;
     if (n_reg != n) {
@@ -212,14 +213,14 @@ __device__ __forceinline__ void queue_candidate(PushLds &L, const Dev &d, bool c
     if (!cand) return;
     int64_t idx;
     if (rank < n_reg) {
-        idx = (int64_t)blockIdx.x * kCandQ + base + rank;
+        idx = (int64_t)blockIdx.x * d.cand_q + base + rank;
     } else {
         const uint32_t o = gb + (rank - n_reg);
         if (o >= (uint32_t)d.cand_ovf_cap) {
             atomicOr(&d.instd[inst].status, PIC_ST_CANDIDATES);
             return;
         }
-        idx = (int64_t)d.n_push_blocks * kCandQ + o;
+        idx = (int64_t)d.n_push_blocks * d.cand_q + o;
     }
     Cand c;
     c.g = g;
@@ -235,7 +236,7 @@ __device__ __forceinline__ void queue_candidate(PushLds &L, const Dev &d, bool c
 __device__ __forceinline__ void flush_candidates(PushLds &L, const Dev &d)
 {
     __syncthreads();
-    if (threadIdx.x == 0) d.cand_n[blockIdx.x] = min(L.cn, (uint32_t)kCandQ);
+    if (threadIdx.x == 0) d.cand_n[blockIdx.x] = min(L.cn, (uint32_t)d.cand_q);
 }
 
 // ---------------------------------------------------------------------------

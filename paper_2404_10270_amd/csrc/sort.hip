@@ -18,7 +18,7 @@
 namespace picx {
 
 constexpr int kSortWin = 1024;  // LDS window of bins per tile
-constexpr int kSegLdsS = 256;
+constexpr int kSegLdsS = 1024;
 
 struct SortLds {
     uint32_t cnt[kSortWin];

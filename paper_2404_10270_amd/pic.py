@@ -43,7 +43,7 @@ PIC_PUSH_NO_DEPOSIT = 0x1
 # every entry point declared in include/pic.h
 ABI_SYMBOLS = ("pic_query_sizes", "pic_init", "pic_push", "pic_deposit", "pic_field_solve",
                "pic_mcc_collide", "pic_sort", "pic_diagnostics", "pic_step", "pic_step_graph",
-               "pic_region", "pic_destroy", "pic_strerror")
+               "pic_autotune_sort", "pic_region", "pic_destroy", "pic_strerror")
 
 
 class pic_species(C.Structure):
@@ -121,6 +121,8 @@ def lib():
             getattr(L, name).argtypes = [P]
         L.pic_step.argtypes = [P, C.c_int, C.c_int]
         L.pic_step_graph.argtypes = [P, C.c_int, C.c_int]
+        L.pic_autotune_sort.argtypes = [P, C.POINTER(C.c_int), C.c_int, C.c_int,
+                                        C.POINTER(C.c_int), C.POINTER(C.c_double)]
         L.pic_diagnostics.argtypes = [P, C.POINTER(pic_diag), C.c_int]
         L.pic_region.argtypes = [P, C.c_int, C.POINTER(C.c_uint64), C.POINTER(C.c_int64)]
         L.pic_strerror.argtypes = [C.c_int]
@@ -196,6 +198,17 @@ def pic_step(ctx, n_steps: int, sort_every: int = 0):
 
 def pic_step_graph(ctx, n_steps: int, sort_every: int = 0):
     return _check(lib().pic_step_graph(ctx, n_steps, sort_every), "pic_step_graph")
+
+
+def pic_autotune_sort(ctx, candidates: Sequence[int], trial_steps: int):
+    """(best cadence, [rate per candidate])"""
+    n = len(candidates)
+    cand = (C.c_int * n)(*[int(v) for v in candidates])
+    rates = (C.c_double * n)()
+    best = C.c_int()
+    _check(lib().pic_autotune_sort(ctx, cand, n, int(trial_steps), C.byref(best), rates),
+           "pic_autotune_sort")
+    return best.value, list(rates)
 
 
 def pic_diagnostics(ctx, n_inst: int = 1):
@@ -362,6 +375,9 @@ class PicSim:
 
     def step_graph(self, n: int = 1, sort_every: int = 0):
         pic_step_graph(self.ctx, n, sort_every)
+
+    def autotune_sort(self, candidates=(5, 10, 20, 40, 80), trial_steps: int = 80):
+        return pic_autotune_sort(self.ctx, candidates, trial_steps)
 
     def diagnostics(self):
         return pic_diagnostics(self.ctx, self.n_inst)

@@ -140,6 +140,7 @@ def test_init_argument_errors_before_device_work(P):
     assert L.pic_field_solve(None) == P.PIC_E_STATE
     assert L.pic_step(None, 1, 0) == P.PIC_E_STATE
     assert L.pic_step_graph(None, 1, 0) == P.PIC_E_STATE
+    assert L.pic_autotune_sort(None, None, 0, 1, None, None) == P.PIC_E_STATE
     assert L.pic_destroy(None) == P.PIC_E_ARG
 
 

@@ -132,6 +132,24 @@ def test_graph_replays_equal_eager_steps(prec):
     b.close()
 
 
+def test_autotune_sort_picks_a_candidate_and_leaves_a_valid_state():
+    wl = pin.bounded_mcc(nc=2000, ppc=50, seed=42)
+    flush("autotune sort cadence")
+    sim, _, _ = build_pair(wl, FP32)
+    best, rates = sim.autotune_sort((5, 10, 20, 0), 20)
+    assert best in (5, 10, 20, 0)
+    assert len(rates) == 4 and all(r > 0 for r in rates)
+    d, rc = sim.diagnostics()
+    assert rc == 0 and d[0].step == 80  # four trials of 20 steps
+    sim.step(7, best)
+    d, rc = sim.diagnostics()
+    assert rc == 0 and d[0].step == 87
+    for k in range(2):
+        ids = gpu_state(sim, k)["id"]
+        assert np.unique(ids).size == ids.size
+    sim.close()
+
+
 def _dump(sim, k, prec):
     """Live particles of species k in the storage form of `prec`."""
     from types import SimpleNamespace
