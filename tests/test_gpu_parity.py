@@ -428,3 +428,51 @@ def test_full_size_1e6_cells_drawn_state_sampled():
             err = np.abs(g[f][live][gi] - os_[f][oi]) / np.maximum(np.abs(os_[f][oi]), vth)
             assert np.max(err) <= 1e-5
     sim.close()
+
+
+@pytest.mark.slow
+def test_full_size_batched_256_instances_drawn_sampled():
+    """The 256-instance batched workload at full size (2.5e8 particles, FP32 form, drawn
+    on the device, sorted at init), in the configuration the benchmark runs: for three
+    instances, sampled drawn particles exact, the deposit of every particle of the
+    instance bit-exact, rho bit-exact and phi within the solve's rounding; the
+    diagnostics of every instance report all its particles."""
+    import torch
+    wls = pin.batched(n_inst=256, seed=4)
+    flush("batched 256: draw on the device")
+    sim = P.PicSim(wls, [None] * len(wls), FP32, flags=P.PIC_INIT_DEVICE | P.PIC_INIT_NO_FIELD)
+    d, rc = sim.diagnostics()
+    assert rc == 0
+    for i, w in enumerate(wls):
+        for k, s in enumerate(w.species):
+            assert d[i].n_live[k] == int(round(s.ppc * w.nc))
+    sim.deposit()
+    S = [sim.grid(P.PIC_R_DEPOSIT, inst=i) for i in (0, 97, 255)]
+    sim.field_solve()
+    rng = np.random.default_rng(44)
+    for n_i, i in enumerate((0, 97, 255)):
+        w = wls[i]
+        flush(f"batched 256: instance {i} ({w.nc} cells)")
+        n = [int(round(s.ppc * w.nc)) for s in w.species]
+        pick = [np.sort(rng.choice(n[k], min(n[k], 2000), replace=False)) for k in range(2)]
+        o = oracle.init_state(w, inst=i, select=pick)
+        for k in range(2):
+            b = int(sim.seg_base[i * 2 + k])
+            ii = torch.from_numpy(pick[k].astype(np.int64) + b).to(sim.x[0].device)
+            x = sim.cell[0][ii].cpu().numpy().astype(np.float64) + sim.x[0][ii].cpu().numpy().astype(np.float64)
+            ref = pin.to_fp32_form([o[k]], w.nc)[0]
+            assert np.array_equal(x, ref.as_f64().x)
+            assert np.array_equal(sim.id[0][ii].cpu().numpy().view(np.uint64), o[k].id)
+        S_ref = oracle.init_deposit(w, inst=i, fp32_form=True)
+        for k in range(2):
+            assert np.array_equal(S[n_i][k], S_ref[k])
+        empty = [pin.SpeciesState(x=np.zeros(0), vx=np.zeros(0), vy=np.zeros(0), vz=np.zeros(0),
+                                  id=np.zeros(0, np.uint64)) for _ in range(2)]
+        orc = oracle.OracleSim(w, empty, caps=[1, 1], inst=i)
+        for k in range(2):
+            orc.S[k][:] = S_ref[k]
+        orc.field()
+        assert np.array_equal(sim.grid(P.PIC_R_RHO, inst=i), orc.rho)
+        tol = 8 * w.nc * EPS64 * np.max(np.abs(orc.phi)) + 1e-300
+        assert np.max(np.abs(sim.grid(P.PIC_R_PHI, inst=i) - orc.phi)) <= tol
+    sim.close()
