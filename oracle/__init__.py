@@ -50,7 +50,7 @@ class Config(C.Structure):
                 ("dx", C.c_double), ("dt", C.c_double), ("eps0", C.c_double),
                 ("B0", C.c_double), ("theta", C.c_double),
                 ("q", C.c_double * MAXSP), ("m", C.c_double * MAXSP), ("w", C.c_double * MAXSP),
-                ("kind", C.c_int32 * MAXSP),
+                ("kind", C.c_int32 * MAXSP), ("nstep", C.c_int32 * MAXSP),
                 ("v_cap", C.c_double * MAXSP), ("T_src", C.c_double * MAXSP),
                 ("n_n", C.c_double), ("T_n", C.c_double), ("sig_el", C.c_double),
                 ("sig_iz", C.c_double), ("E_iz", C.c_double), ("sig_cx", C.c_double),
@@ -213,6 +213,7 @@ def make_config(wl: pin.Workload, inst: int = 0) -> Config:
     for k, s in enumerate(wl.species):
         c.q[k], c.m[k], c.w[k] = s.q, s.m, s.w
         c.kind[k] = s.kind
+        c.nstep[k] = int(getattr(s, "nstep", 1))
         c.v_cap[k] = s.v_cap
         c.T_src[k] = s.T_src
     c.smooth_passes = int(getattr(wl, "smooth_passes", 0))

@@ -48,6 +48,7 @@ typedef struct {
     double dx, dt, eps0, B0, theta;
     double q[ORC_MAXSP], m[ORC_MAXSP], w[ORC_MAXSP];
     int32_t kind[ORC_MAXSP];
+    int32_t nstep[ORC_MAXSP];       /* push every nstep steps (subcycling); 0 or 1 = every step */
     double v_cap[ORC_MAXSP];        /* m/s */
     double T_src[ORC_MAXSP];        /* J */
     double n_n, T_n, sig_el, sig_iz, E_iz, sig_cx;
@@ -376,9 +377,19 @@ int orc_field(orc_sim *s)
 /* kick; then the advance x += vx (nstep = 1).  B = B0 (cos th, sin th, 0),   */
 /* th measured from the wall normal x.                                        */
 /* ------------------------------------------------------------------------ */
+/* Subcycling (the per-species step multiplier nstep of the moveb listing,
+ * Sec. 6): species k is pushed only on steps s with s mod nstep = 0, over a
+ * time nstep dt -- the kick, the rotation angle and the advance
+ * x += nstep vx all take nstep dt; its particles keep their positions (and
+ * their deposit) on the steps in between, and its collision test runs on
+ * the push steps with the probability of nstep dt. */
+static int sub_of(const orc_config *c, int k) { return c->nstep[k] > 1 ? c->nstep[k] : 1; }
+
+static int pushed_at(const orc_config *c, int k, int64_t step) { return step % sub_of(c, k) == 0; }
+
 static void species_rotation(const orc_config *c, int k, double t[2], double sv[2])
 {
-    const double tm = (c->q[k] / c->m[k]) * c->B0 * (0.5 * c->dt);
+    const double tm = (c->q[k] / c->m[k]) * c->B0 * (0.5 * (c->dt * (double)sub_of(c, k)));
     t[0] = tm * cos(c->theta);
     t[1] = tm * sin(c->theta);
     const double den = 1.0 + (t[0] * t[0] + t[1] * t[1]);
@@ -392,12 +403,14 @@ void orc_push_species(const orc_config *c, int k, const double *acc, int64_t n, 
     double t[2], sv[2];
     species_rotation(c, k, t, sv);
     const double tx = t[0], ty = t[1], sx = sv[0], sy = sv[1];
+    const double ms = (double)sub_of(c, k);
+    const double hk = 0.5 * ms;
     for (int64_t p = 0; p < n; ++p) {
         double jd = floor(x[p]);
         double f = x[p] - jd;
         int64_t j = (int64_t)jd;
         double a = fma(f, acc[j + 1] - acc[j], acc[j]);
-        double h = 0.5 * a;
+        double h = hk * a;
         double mx = vx[p] + h, my = vy[p], mz = vz[p];
         /* v' = v- + v- x t,  t = (tx, ty, 0) */
         double px = mx - mz * ty;
@@ -410,17 +423,19 @@ void orc_push_species(const orc_config *c, int k, const double *acc, int64_t n, 
         vx[p] = qx + h;
         vy[p] = qy;
         vz[p] = qz;
-        x[p] = x[p] + vx[p];
+        x[p] = x[p] + ms * vx[p];
     }
 }
 
 void orc_push(orc_sim *s)
 {
     for (int k = 0; k < s->cfg.nsp; ++k) {
+        if (!pushed_at(&s->cfg, k, s->cnt.step)) continue;
         orc_particles *P = &s->sp[k];
         orc_push_species(&s->cfg, k, s->acc[k], P->n, P->x, P->vx, P->vy, P->vz);
+        const double ms = (double)sub_of(&s->cfg, k);
         for (int64_t p = 0; p < P->n; ++p)
-            if (fabs(P->vx[p]) >= 1.0) s->cnt.status |= ORC_ST_CFL;
+            if (fabs(ms * P->vx[p]) >= 1.0) s->cnt.status |= ORC_ST_CFL;
         s->cnt.particle_steps += P->n;
     }
 }
@@ -519,7 +534,7 @@ uint64_t orc_candidate_threshold(const orc_config *c, int k)
     else sig = c->sig_cx;
     double vcap_hat = c->v_cap[k] * (dt / dx);
     double nu_max = c->n_n * sig * dx * vcap_hat;       /* per step */
-    double P = -expm1(-nu_max);
+    double P = -expm1(-(nu_max * (double)sub_of(c, k)));  /* per push */
     double T = floor(ldexp(P, 32));
     if (T > 4294967296.0) T = 4294967296.0;
     return (uint64_t)T;
@@ -543,6 +558,7 @@ int orc_mcc(orc_sim *s)
     }
 
     for (int k = 0; k < c->nsp; ++k) {
+        if (!pushed_at(c, k, step)) continue;  /* tested on its push steps only */
         orc_particles *P = &s->sp[k];
         const int is_e = (c->kind[k] == ORC_KIND_ELECTRON);
         const uint64_t T = orc_candidate_threshold(c, k);

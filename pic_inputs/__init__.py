@@ -63,6 +63,7 @@ class Species:
     T_src: float = 0.0  # temperature of source-born particles [J]
     v_cap: float = 0.0  # speed bounding the null-collision frequency [m/s]
     cap_factor: float = 1.5  # capacity / initial count
+    nstep: int = 1      # pushed every nstep steps over nstep dt (subcycling)
 
 
 @dataclass

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 # (what the mistake is, original text, mutated text)
 MUTATIONS = [
-    ("half kick doubled", "double h = 0.5 * a;", "double h = a;"),
+    ("half kick doubled", "const double hk = 0.5 * ms;", "const double hk = ms;"),
     ("rotation sign in z", "double qz = mz + (px * sy - py * sx);", "double qz = mz + (px * sy + py * sx);"),
     ("cross product operand order", "double pz = mz + (mx * ty - my * tx);",
      "double pz = mz + (my * tx - mx * ty);"),
@@ -37,8 +37,12 @@ MUTATIONS = [
     ("periodic background dropped", "rho[j] = acc / V + rho_bg;", "rho[j] = acc / V;"),
     ("Poisson pivot off by one", "const double den = -(u + 1.0) / u;",
      "const double den = -(u + 2.0) / u;"),
-    ("Boris uses dt, not dt/2", "const double tm = (c->q[k] / c->m[k]) * c->B0 * (0.5 * c->dt);",
-     "const double tm = (c->q[k] / c->m[k]) * c->B0 * c->dt;"),
+    ("Boris uses dt, not dt/2",
+     "const double tm = (c->q[k] / c->m[k]) * c->B0 * (0.5 * (c->dt * (double)sub_of(c, k)));",
+     "const double tm = (c->q[k] / c->m[k]) * c->B0 * (c->dt * (double)sub_of(c, k));"),
+    ("subcycled advance ignores nstep", "x[p] = x[p] + ms * vx[p];", "x[p] = x[p] + vx[p];"),
+    ("subcycled collision test uses one step", "double P = -expm1(-(nu_max * (double)sub_of(c, k)));",
+     "double P = -expm1(-nu_max);"),
 ]
 
 
