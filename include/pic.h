@@ -71,7 +71,9 @@ typedef struct {
     double m;           /* mass [kg] */
     double w;           /* real particles per macro-particle per unit area [m^-2] */
     int32_t kind;       /* pic_kind: selects the collision processes */
-    int32_t _pad0;
+    int32_t nstep;      /* subcycling (nstep of the moveb listing, Sec. 6): pushed on steps
+                           s with s mod nstep = 0 over nstep dt, deposited every step;
+                           0 or 1 = every step */
     int64_t capacity;   /* particle slots reserved for this species */
     int64_t n_init;     /* initial particles: uploaded into buffer set 0 before pic_init,
                            or drawn there by pic_init with PIC_INIT_DEVICE */

@@ -18,6 +18,7 @@ struct pic_ctx {
     int n_inst = 0, nsp = 0, precision = 0;
     bool mcc_any = false, src_any = false;
     int max_smooth = 0;       // most smoother passes of any instance
+    bool sub_any = false;     // some species is subcycled (nstep > 1)
     Layout L{};
     Dev d{};
     hipStream_t st = nullptr;
@@ -66,6 +67,7 @@ int validate(const pic_config *cfgs, int n_inst)
             const pic_species &s = c.sp[k];
             if (!std::isfinite(s.q) || !finite_pos(s.m) || !finite_pos(s.w)) return PIC_E_CONFIG;
             if (s.kind != PIC_KIND_ELECTRON && s.kind != PIC_KIND_ION) return PIC_E_CONFIG;
+            if (s.nstep < 0 || s.nstep > 1000000) return PIC_E_CONFIG;
             if (s.capacity < 1 || s.n_init < 0 || s.n_init > s.capacity) return PIC_E_CONFIG;
             if (s.capacity > kMaxSlots) return PIC_E_CONFIG;
         }
@@ -132,11 +134,14 @@ void seg_constants(const pic_config &c, int inst, int k, SegConst &s)
     s.inst = inst;
     s.sp = k;
     s.kind = sp.kind;
+    s.nstep = sp.nstep > 1 ? sp.nstep : 1;
+    s.ms = (double)s.nstep;
+    s.msf = (float)s.nstep;
     s.nc = c.nc;
     s.bc = c.bc;
     s.nsp = c.nsp;
     s.partner = -1;
-    const double tm = (sp.q / sp.m) * c.B0 * (0.5 * dt);
+    const double tm = (sp.q / sp.m) * c.B0 * (0.5 * (dt * s.ms));
     s.tx = tm * std::cos(c.theta);
     s.ty = tm * std::sin(c.theta);
     const double den = 1.0 + (s.tx * s.tx + s.ty * s.ty);
@@ -171,7 +176,7 @@ void seg_constants(const pic_config &c, int inst, int k, SegConst &s)
         }
         const double vcap_hat = sp.v_cap * (dt / dx);
         const double nu_max_T = c.n_n * sig * dx * vcap_hat;
-        const double P = -std::expm1(-nu_max_T);
+        const double P = -std::expm1(-(nu_max_T * s.ms));  // per push of nstep steps
         double T = std::floor(std::ldexp(P, 32));
         if (T > 4294967296.0) T = 4294967296.0;
         s.T = (uint64_t)T;
@@ -367,6 +372,7 @@ int pic_init(const pic_config *cfgs, int n_inst, const pic_buffers *bufs, void *
     for (int i = 0; i < n_inst; ++i) {
         c->mcc_any = c->mcc_any || cfgs[i].mcc_on;
         c->src_any = c->src_any || cfgs[i].source_on;
+        for (int k = 0; k < cfgs[i].nsp; ++k) c->sub_any = c->sub_any || cfgs[i].sp[k].nstep > 1;
     }
 
     const int nsp = c->nsp, n_seg = n_inst * nsp;
@@ -533,7 +539,7 @@ int pic_push(pic_ctx *c, unsigned flags)
 {
     if (!c) return PIC_E_STATE;
     const bool dep = !(flags & PIC_PUSH_NO_DEPOSIT);
-    return launch_push(c->d, c->st, dep, c->mcc_any) == hipSuccess ? PIC_OK : PIC_E_DEVICE;
+    return launch_push(c->d, c->st, dep, c->mcc_any, c->sub_any) == hipSuccess ? PIC_OK : PIC_E_DEVICE;
 }
 
 int pic_deposit(pic_ctx *c)

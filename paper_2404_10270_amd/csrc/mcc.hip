@@ -417,7 +417,7 @@ __global__ __launch_bounds__(kBlock) void close_step_kernel(Dev d, int with_even
             const int s = ic.seg0 + k;
             SegDyn *sd = d.segd + s;
             const SegConst &sc = d.segc[s];
-            pushed += sd->live;
+            if (idn->step % sc.nstep == 0) pushed += sd->live;  // a subcycled species moved this step
             uint32_t requested = 0;
             if (s == ic.seg_e || s == ic.seg_i) requested = m_i + n_src;
             uint64_t n_new = (uint64_t)sd->count + requested;

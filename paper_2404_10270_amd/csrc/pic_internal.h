@@ -44,10 +44,13 @@ struct SegConst {
     int64_t node_stride;// G: distance between species rows of the [nsp][G] grid arrays
     uint32_t cap;       // slots
     int32_t inst, sp, kind;
+    int32_t nstep;      // pushed on steps s with s mod nstep = 0, over nstep dt
     int32_t nc, bc, nsp, partner;   // partner: the other species' segment (MCC / source)
     // Boris rotation t = (q/m) B dt/2 (cos th, sin th, 0), s = 2t/(1+|t|^2)
     double tx, ty, sx, sy;
     float txf, tyf, sxf, syf;
+    double ms;          // nstep as a double (kick, advance)
+    float msf;
     // null-collision MCC (rates per step, speeds in cells/step)
     uint64_t T;         // candidate threshold floor(P 2^32), 0..2^32
     double nu_max, C0, C1;          // nu_max = c1 vcap; C0 = c0^2, C1 = c1^2
@@ -204,7 +207,8 @@ hipError_t launch_init_state(const Dev &d, hipStream_t st, const uint32_t *n_ini
 // draws the initial particles of every segment into buffer set 0
 hipError_t launch_init_device(const Dev &d, hipStream_t st);
 // mcc: test every particle and list the candidates (pic_mcc_collide collides them)
-hipError_t launch_push(const Dev &d, hipStream_t st, bool deposit, bool mcc);
+// subcycled: some species has nstep > 1 (its deposit between pushes is launched too)
+hipError_t launch_push(const Dev &d, hipStream_t st, bool deposit, bool mcc, bool subcycled);
 hipError_t launch_deposit(const Dev &d, hipStream_t st);
 // smooth: the most density-smoother passes of any instance
 hipError_t launch_field(const Dev &d, hipStream_t st, int smooth);

@@ -2,7 +2,9 @@
 // the fixed-point charge deposition (Sec. 2, phase 1) for gfx950.
 //
 // One pass per particle and step: linear gather of the grid acceleration at
-// the in-cell offset, magnetised Boris velocity update, advance x += vx,
+// the in-cell offset, magnetised Boris velocity update, advance
+// x += nstep vx (a subcycled species moves every nstep steps over nstep dt
+// and is only deposited in between),
 // absorbing or periodic walls, the null-collision candidate test (one Philox
 // block keyed by id and step), and the deposit of the new position.
 //
@@ -56,7 +58,16 @@ struct PushLds {
     int red[2][kWaves];
 };
 
-__device__ __forceinline__ void push_lds_init(PushLds &L, const Dev &d)
+// a subcycled species between its pushes (block-uniform)
+__device__ __forceinline__ bool still(const Dev &d, int seg)
+{
+    const SegConst &sc = d.segc[seg];
+    return sc.nstep > 1 && d.instd[sc.inst].step % sc.nstep != 0;
+}
+
+// drop_still: a subcycled species between its pushes gets no tiles (its
+// segments read as empty, so the movers pay nothing per tile for the test)
+__device__ __forceinline__ void push_lds_init(PushLds &L, const Dev &d, bool drop_still = false)
 {
     for (int i = threadIdx.x; i < kDepWin; i += kBlock) L.dep[i] = 0ull;
     if (d.n_seg <= kSegLds) {
@@ -64,7 +75,7 @@ __device__ __forceinline__ void push_lds_init(PushLds &L, const Dev &d)
             L.tile0[s] = d.seg_tile0[s];
             if (s < d.n_seg) {
                 L.base[s] = d.seg_base[s];
-                L.count[s] = d.segd[s].count;
+                L.count[s] = drop_still && still(d, s) ? 0 : d.segd[s].count;
             }
         }
     }
@@ -184,6 +195,43 @@ __device__ __forceinline__ void deposit_tile(PushLds &L, unsigned long long *__r
     // the next use of the window is ordered by the next call's first barrier
 }
 
+// The deposit of the current positions of one tile (both forms): the
+// standalone deposit, and a subcycled species between its pushes.
+__device__ __forceinline__ void deposit_positions(PushLds &L, const Dev &d, int cur, const SegConst &sc,
+                                                  int64_t tb, uint32_t rem)
+{
+    unsigned long long *__restrict__ S = d.S + sc.sp * d.G + sc.gnode;
+    const bool f64 = (d.precision == PIC_FP64);
+    const int lane = lane_id();
+    const int wave = threadIdx.x >> 6;
+    int key[kPer];
+    unsigned long long w1[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const uint32_t o = (uint32_t)((wave * kPer + k) * 64 + lane);
+        key[k] = -1;
+        w1[k] = 0;
+        if (o < rem) {
+            if (f64) {
+                const double x = stream_ld(&((const double *)d.x[cur])[tb + o]);
+                if (x >= 0.0) {
+                    const double jn = floor(x);
+                    key[k] = (int)jn;
+                    w1[k] = (unsigned long long)rint(ldexp(x - jn, PIC_FRAC_BITS));
+                }
+            } else {
+                const int32_t jj = stream_ld(&d.cell[cur][tb + o]);
+                if (jj >= 0) {
+                    key[k] = jj;
+                    w1[k] = (unsigned long long)rintf(stream_ld(&((const float *)d.x[cur])[tb + o]) *
+                                                      4294967296.0f);
+                }
+            }
+        }
+    }
+    deposit_tile<kPer>(L, S, key, w1);
+}
+
 // A candidate is written, with its velocity after the push and its id, to
 // the block's own region of the candidate list (the index comes from an LDS
 // counter); a wave whose candidates do not fit appends the excess to the
@@ -246,7 +294,7 @@ template <bool DEP, bool MCC>
 __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
 {
     __shared__ PushLds L;
-    push_lds_init(L, d);
+    push_lds_init(L, d, true);
     const int cur = d.glob->cur_set;
     float *__restrict__ X = (float *)d.x[cur];
     int32_t *__restrict__ CELL = d.cell[cur];
@@ -262,6 +310,9 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
         const int seg = tile_seg(L, d, t, tile0, base, count);
         const int64_t t0 = (t - tile0) * (int64_t)kTile;
         if (t0 >= count) continue;
+        // a subcycled species between its pushes keeps its positions (their
+        // deposit is a launch of its own, deposit_kernel<true>)
+        if (d.n_seg > kSegLds && still(d, seg)) continue;
 
         // ---- loads of all chunks
         int32_t j[kPer];
@@ -301,6 +352,7 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
         const int nc = sc.nc;
         const bool periodic = (sc.bc == PIC_BC_PERIODIC);
         const float tx = sc.txf, ty = sc.tyf, sx = sc.sxf, sy = sc.syf;
+        const float msf = sc.msf, hk = 0.5f * sc.msf;
         const uint32_t key0 = sc.key0, key1 = sc.key1;
         const unsigned long long T = sc.T;
         const int inst = sc.inst;
@@ -329,7 +381,7 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
             cand[k] = false;
             if (j[k] < 0) continue;
             const float a = fmaf(f[k], a1[k] - a0[k], a0[k]);
-            const float h = 0.5f * a;
+            const float h = hk * a;
             const float mx = vx[k] + h, my = vy[k], mz = vz[k];
             const float px = mx - mz * ty;
             const float py = my + mz * tx;
@@ -340,12 +392,12 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
             const float nvx = qx + h, nvy = qy, nvz = qz;
             // advance in cell-relative coordinates; |fl| is clamped so that a
             // runaway (flagged) particle still maps to a valid integer cell
-            float fn = f[k] + nvx;
+            float fn = f[k] + msf * nvx;
             const float fl = fminf(fmaxf(floorf(fn), -16777216.0f), 16777216.0f);
             fn = fn - fl;
             int32_t jn = j[k] + (int32_t)fl;
             if (fn >= 1.0f) { fn = 0.0f; jn += 1; }
-            cfl |= !(fabsf(nvx) < 1.0f);
+            cfl |= !(fabsf(msf * nvx) < 1.0f);
             const bool bk = !isfinite(nvx) || !isfinite(nvy) || !isfinite(nvz);
             bad |= bk;
             if (bk) jn = j[k], fn = f[k];  // keep the slot well-formed; the run is flagged
@@ -431,7 +483,7 @@ template <bool DEP, bool MCC>
 __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
 {
     __shared__ PushLds L;
-    push_lds_init(L, d);
+    push_lds_init(L, d, true);
     const int cur = d.glob->cur_set;
     double *__restrict__ X = (double *)d.x[cur];
     double *__restrict__ VX = (double *)d.vx[cur];
@@ -446,6 +498,9 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
         const int seg = tile_seg(L, d, t, tile0, base, count);
         const int64_t t0 = (t - tile0) * (int64_t)kTile;
         if (t0 >= count) continue;
+        // a subcycled species between its pushes keeps its positions (their
+        // deposit is a launch of its own, deposit_kernel<true>)
+        if (d.n_seg > kSegLds && still(d, seg)) continue;
 
         double x[kPer], vx[kPer], vy[kPer], vz[kPer];
         unsigned long long pid[kPer];
@@ -476,6 +531,7 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
         const double L_ = (double)sc.nc;
         const bool periodic = (sc.bc == PIC_BC_PERIODIC);
         const double tx = sc.tx, ty = sc.ty, sx = sc.sx, sy = sc.sy;
+        const double ms = sc.ms, hk = 0.5 * sc.ms;
         const uint32_t key0 = sc.key0, key1 = sc.key1;
         const unsigned long long T = sc.T;
         const int inst = sc.inst;
@@ -507,7 +563,7 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
             cand[k] = false;
             if (!live[k]) continue;
             const double a = fma(fr[k], a1[k] - a0[k], a0[k]);
-            const double h = 0.5 * a;
+            const double h = hk * a;
             const double mx = vx[k] + h, my = vy[k], mz = vz[k];
             const double px = mx - mz * ty;
             const double py = my + mz * tx;
@@ -518,8 +574,8 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
             vx[k] = qx + h;
             vy[k] = qy;
             vz[k] = qz;
-            double xn = x[k] + vx[k];
-            cfl |= !(fabs(vx[k]) < 1.0);
+            double xn = x[k] + ms * vx[k];
+            cfl |= !(fabs(ms * vx[k]) < 1.0);
             const bool bk = !isfinite(vx[k]) || !isfinite(vy[k]) || !isfinite(vz[k]);
             bad |= bk;
             if (bk) xn = x[k];
@@ -593,48 +649,20 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
 // ---------------------------------------------------------------------------
 // standalone deposit of the current positions (both forms)
 // ---------------------------------------------------------------------------
+// ONLY_STILL: just the tiles of subcycled species between their pushes
+template <bool ONLY_STILL>
 __global__ __launch_bounds__(kBlock) void deposit_kernel(Dev d)
 {
     __shared__ PushLds L;
     push_lds_init(L, d);
     const int cur = d.glob->cur_set;
-    const int lane = lane_id();
-    const int wave = threadIdx.x >> 6;
-    const bool f64 = (d.precision == PIC_FP64);
     for (int64_t t = blockIdx.x; t < d.n_tiles; t += gridDim.x) {
         int64_t tile0, base, count;
         const int seg = tile_seg(L, d, t, tile0, base, count);
         const int64_t t0 = (t - tile0) * (int64_t)kTile;
         if (t0 >= count) continue;
-        const SegConst &sc = d.segc[seg];
-        unsigned long long *__restrict__ S = d.S + sc.sp * d.G + sc.gnode;
-        int key[kPer];
-        unsigned long long w1[kPer];
-#pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            const int64_t i = t0 + (int64_t)(wave * kPer + k) * 64 + lane;
-            const int64_t g = base + i;
-            key[k] = -1;
-            w1[k] = 0;
-            if (i < count) {
-                if (f64) {
-                    const double x = ((const double *)d.x[cur])[g];
-                    if (x >= 0.0) {
-                        const double jn = floor(x);
-                        key[k] = (int)jn;
-                        w1[k] = (unsigned long long)rint(ldexp(x - jn, PIC_FRAC_BITS));
-                    }
-                } else {
-                    const int32_t jj = d.cell[cur][g];
-                    if (jj >= 0) {
-                        key[k] = jj;
-                        w1[k] = (unsigned long long)rintf(((const float *)d.x[cur])[g] *
-                                                          4294967296.0f);
-                    }
-                }
-            }
-        }
-        deposit_tile<kPer>(L, S, key, w1);
+        if (ONLY_STILL && !still(d, seg)) continue;
+        deposit_positions(L, d, cur, d.segc[seg], base + t0, (uint32_t)min(count - t0, (int64_t)kTile));
     }
 }
 
@@ -655,19 +683,20 @@ void launch_push_t(const Dev &d, hipStream_t st, dim3 grid)
     else hipLaunchKernelGGL((push_f32_kernel<DEP, MCC>), grid, dim3(kBlock), 0, st, d);
 }
 
-hipError_t launch_push(const Dev &d, hipStream_t st, bool dep, bool mcc)
+hipError_t launch_push(const Dev &d, hipStream_t st, bool dep, bool mcc, bool subcycled)
 {
     const dim3 grid(push_grid(d));
     if (dep && mcc) launch_push_t<true, true>(d, st, grid);
     else if (dep) launch_push_t<true, false>(d, st, grid);
     else if (mcc) launch_push_t<false, true>(d, st, grid);
     else launch_push_t<false, false>(d, st, grid);
+    if (dep && subcycled) hipLaunchKernelGGL(deposit_kernel<true>, grid, dim3(kBlock), 0, st, d);
     return hipGetLastError();
 }
 
 hipError_t launch_deposit(const Dev &d, hipStream_t st)
 {
-    hipLaunchKernelGGL(deposit_kernel, dim3(push_grid(d)), dim3(kBlock), 0, st, d);
+    hipLaunchKernelGGL(deposit_kernel<false>, dim3(push_grid(d)), dim3(kBlock), 0, st, d);
     return hipGetLastError();
 }
 

@@ -48,7 +48,7 @@ ABI_SYMBOLS = ("pic_query_sizes", "pic_init", "pic_push", "pic_deposit", "pic_fi
 
 class pic_species(C.Structure):
     _fields_ = [("q", C.c_double), ("m", C.c_double), ("w", C.c_double), ("kind", C.c_int32),
-                ("_pad0", C.c_int32), ("capacity", C.c_int64), ("n_init", C.c_int64),
+                ("nstep", C.c_int32), ("capacity", C.c_int64), ("n_init", C.c_int64),
                 ("v_cap", C.c_double), ("T_src", C.c_double), ("T_init", C.c_double)]
 
 
@@ -248,6 +248,7 @@ def make_config(wl, precision: int, capacities: Sequence[int], n_init: Sequence[
     for k, s in enumerate(wl.species):
         sp = c.sp[k]
         sp.q, sp.m, sp.w, sp.kind = s.q, s.m, s.w, s.kind
+        sp.nstep = int(getattr(s, "nstep", 1))
         sp.capacity = int(capacities[k])
         sp.n_init = int(n_init[k])
         sp.v_cap = getattr(s, "v_cap", 0.0)

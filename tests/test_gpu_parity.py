@@ -476,3 +476,34 @@ def test_full_size_batched_256_instances_drawn_sampled():
         tol = 8 * w.nc * EPS64 * np.max(np.abs(orc.phi)) + 1e-300
         assert np.max(np.abs(sim.grid(P.PIC_R_PHI, inst=i) - orc.phi)) <= tol
     sim.close()
+
+
+@pytest.mark.parametrize("prec", [FP32, FP64], ids=["fp32", "fp64"])
+def test_subcycled_ions(prec):
+    """Ions pushed every 4 steps over 4 dt (deposited in between), 41 whole steps with
+    walls, collisions, source and a sort every 20 steps."""
+    wl = pin.bounded_mcc(nc=300, ppc=40, seed=15)
+    wl.species[1].nstep = 4
+    wl.mcc.n_n *= 5
+    flush(f"subcycled ions prec={prec}")
+    sim, orc, ost = build_pair(wl, prec)
+    sim.step(41, sort_every=20)
+    orc.step(41)
+    d, rc = sim.diagnostics()
+    d = d[0]
+    c = orc.counters
+    od = orc.diagnostics()
+    assert rc == 0 and d.step == 41
+    if prec == FP64:
+        assert d.particle_steps == c.particle_steps
+        assert d.n_cx == c.n_cx and d.n_ionize == c.n_ionize and d.n_source == c.n_source
+        for k in range(2):
+            g, o = gpu_state(sim, k), oracle_state(orc, k)
+            assert np.array_equal(g["id"], o["id"])
+            assert np.max(np.abs(g["x"] - o["x"])) <= 1e-7
+            assert abs(d.ke[k] / od.ke[k] - 1) <= 1e-9
+    else:
+        assert abs(d.particle_steps - c.particle_steps) <= 0.001 * c.particle_steps
+        for k in range(2):
+            assert abs(d.ke[k] / od.ke[k] - 1) <= 5e-3
+    sim.close()
