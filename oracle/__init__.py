@@ -31,6 +31,8 @@ SRC = os.path.join(HERE, "pic_oracle.c")
 LIB = os.path.join(HERE, "libpic_oracle.so")
 
 MAXSP = 4
+XS_IZ_RATE = 1          # ionisation with a constant rate coefficient sig_iz v_cap
+ST_CAPACITY, ST_CFL, ST_NN_CAP = 1, 2, 4
 
 
 def build(force: bool = True) -> str:
@@ -54,7 +56,9 @@ class Config(C.Structure):
                 ("v_cap", C.c_double * MAXSP), ("T_src", C.c_double * MAXSP),
                 ("n_n", C.c_double), ("T_n", C.c_double), ("sig_el", C.c_double),
                 ("sig_iz", C.c_double), ("E_iz", C.c_double), ("sig_cx", C.c_double),
-                ("smooth_passes", C.c_int32), ("_pad", C.c_int32)]
+                ("smooth_passes", C.c_int32), ("_pad", C.c_int32),
+                ("sig_ex", C.c_double), ("E_ex", C.c_double), ("field_off", C.c_int32),
+                ("xs_flags", C.c_uint32)]
 
 
 class Particles(C.Structure):
@@ -72,7 +76,9 @@ class Counters(C.Structure):
                 ("created_total", C.c_int64 * MAXSP),
                 ("n_candidates", C.c_int64), ("n_elastic", C.c_int64), ("n_ionize", C.c_int64),
                 ("n_cx", C.c_int64), ("n_over_cap", C.c_int64), ("n_source", C.c_int64),
-                ("particle_steps", C.c_int64)]
+                ("particle_steps", C.c_int64),
+                ("n_excite", C.c_int64), ("n_consumed", C.c_int64),
+                ("n_iz_untargeted", C.c_int64)]
 
 
 class Sim(C.Structure):
@@ -80,7 +86,8 @@ class Sim(C.Structure):
                 ("S", C.POINTER(C.c_uint64) * MAXSP),
                 ("rho", C.POINTER(C.c_double)), ("phi", C.POINTER(C.c_double)),
                 ("E", C.POINTER(C.c_double)),
-                ("acc", C.POINTER(C.c_double) * MAXSP)]
+                ("acc", C.POINTER(C.c_double) * MAXSP),
+                ("nn", C.POINTER(C.c_double))]
 
 
 class Diag(C.Structure):
@@ -126,6 +133,8 @@ def lib():
         L.orc_init_deposit.restype = None
         L.orc_candidate_threshold.argtypes = [C.POINTER(Config), C.c_int]
         L.orc_candidate_threshold.restype = C.c_uint64
+        L.orc_neutral_key.argtypes = [C.POINTER(Config), C.c_uint64, C.c_int64]
+        L.orc_neutral_key.restype = C.c_uint64
         for name, T in (("orc_sizeof_sim", Sim), ("orc_sizeof_config", Config),
                         ("orc_sizeof_counters", Counters), ("orc_sizeof_diag", Diag)):
             f = getattr(L, name)
@@ -217,10 +226,13 @@ def make_config(wl: pin.Workload, inst: int = 0) -> Config:
         c.v_cap[k] = s.v_cap
         c.T_src[k] = s.T_src
     c.smooth_passes = int(getattr(wl, "smooth_passes", 0))
+    c.field_off = 1 if wl.field_off else 0
     if wl.mcc is not None:
         mc = wl.mcc
         c.n_n, c.T_n, c.sig_el, c.sig_iz, c.E_iz, c.sig_cx = (mc.n_n, mc.T_n, mc.sig_el,
                                                                mc.sig_iz, mc.E_iz, mc.sig_cx)
+        c.sig_ex, c.E_ex = mc.sig_ex, mc.E_ex
+        c.xs_flags = XS_IZ_RATE if mc.iz_const_rate else 0
     return c
 
 
@@ -304,6 +316,8 @@ class OracleSim:
         self.rho = np.zeros(nc + 1)
         self.phi = np.zeros(nc + 1)
         self.E = np.zeros(nc + 1)
+        self.nn = np.zeros(nc + 1)
+        self.sim.nn = _dp(self.nn)
         for k in range(nsp):
             self.sim.S[k] = _up(self.S[k])
             self.sim.acc[k] = _dp(self.acc[k])
@@ -362,6 +376,10 @@ class OracleSim:
 
     def candidate_threshold(self, k: int) -> int:
         return int(lib().orc_candidate_threshold(C.byref(self.sim.cfg), k))
+
+    def neutral_key(self, pid: int, step: int) -> int:
+        """Order key of a kinetic neutral for consumption by ionisation at `step`."""
+        return int(lib().orc_neutral_key(C.byref(self.sim.cfg), int(pid), int(step)))
 
     def snapshot(self):
         """Copy of everything that defines the future of the run."""

@@ -36,11 +36,14 @@
 #define ORC_FRAC_BITS 32            /* fixed-point fraction bits of the deposit */
 #define ORC_KIND_ELECTRON 0
 #define ORC_KIND_ION 1
+#define ORC_KIND_NEUTRAL 2          /* kinetic neutral (q = 0): moved ballistically, ionised */
+#define ORC_XS_IZ_RATE 1u           /* ionisation with a constant rate coefficient sig_iz v_cap */
 #define ORC_BC_PERIODIC 0
 #define ORC_BC_ABSORB 1
 
 #define ORC_ST_CAPACITY 1u          /* an append did not fit: the particle was dropped */
 #define ORC_ST_CFL 2u               /* |vx| >= 1 cell per step */
+#define ORC_ST_NN_CAP 4u            /* a local neutral density exceeded the bound n_n */
 
 typedef struct {
     int32_t nc, bc, nsp, mcc_on, source_on, inst;
@@ -53,6 +56,9 @@ typedef struct {
     double T_src[ORC_MAXSP];        /* J */
     double n_n, T_n, sig_el, sig_iz, E_iz, sig_cx;
     int32_t smooth_passes, _pad;    /* density smoother (0 = off) */
+    double sig_ex, E_ex;            /* electron-impact excitation: cross section, threshold */
+    int32_t field_off;              /* no field solve: E = 0 (the paper's Table 1 case) */
+    uint32_t xs_flags;              /* ORC_XS_* */
 } orc_config;
 
 typedef struct {
@@ -70,6 +76,7 @@ typedef struct {
     int64_t created_total[ORC_MAXSP];
     int64_t n_candidates, n_elastic, n_ionize, n_cx, n_over_cap, n_source;  /* totals */
     int64_t particle_steps;
+    int64_t n_excite, n_consumed, n_iz_untargeted;  /* totals (kinetic neutrals) */
 } orc_counters;
 
 typedef struct {
@@ -79,6 +86,7 @@ typedef struct {
     uint64_t *S[ORC_MAXSP];     /* nc+1 fixed-point deposit per species */
     double *rho, *phi, *E;      /* nc+1 */
     double *acc[ORC_MAXSP];     /* nc+1, cells / step^2 */
+    double *nn;                 /* nc+1, density of the kinetic neutral species [m^-3] */
 } orc_sim;
 
 typedef struct {
@@ -116,6 +124,13 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
 
 /* uniform on (0,1): (u + 1/2) 2^-32, exact in FP64 */
 static double u01(uint32_t u) { return ((double)u + 0.5) * 0x1p-32; }
+
+/* the first species of a kind (electron, ion, kinetic neutral), or -1 */
+static int find_kind(const orc_config *c, int kind)
+{
+    for (int k = 0; k < c->nsp; ++k) if (c->kind[k] == kind) return k;
+    return -1;
+}
 
 static void draw_block(const orc_config *c, uint64_t id, int64_t step, uint32_t block,
                        uint32_t out[4])
@@ -331,6 +346,33 @@ int orc_field(orc_sim *s)
         if (c->bc == ORC_BC_ABSORB && (j == 0 || j == nc)) V = 0.5 * dx;
         rho[j] = acc / V + rho_bg;
     }
+    /* density of the kinetic neutral species at the nodes, from its deposit
+     * with the same node volumes: real neutrals per macro-particle per unit
+     * area times the deposited particle count, over the node volume */
+    if (s->nn) {
+        const int kn = find_kind(c, ORC_KIND_NEUTRAL);
+        for (int32_t j = 0; j <= nc; ++j) {
+            double n = 0.0;
+            if (kn >= 0) {
+                uint64_t Sj = s->S[kn][j];
+                if (c->bc == ORC_BC_PERIODIC) {
+                    if (j == 0) Sj += s->S[kn][nc];
+                    if (j == nc) Sj = s->S[kn][0] + s->S[kn][nc];
+                }
+                double V = dx;
+                if (c->bc == ORC_BC_ABSORB && (j == 0 || j == nc)) V = 0.5 * dx;
+                n = (c->w[kn] * ((double)Sj * two_m32)) / V;
+            }
+            s->nn[j] = n;
+        }
+    }
+    /* the paper's Table 1 case runs without the field solver: E = 0 */
+    if (c->field_off) {
+        for (int32_t j = 0; j <= nc; ++j) phi[j] = E[j] = 0.0;
+        for (int k = 0; k < c->nsp; ++k)
+            for (int32_t j = 0; j <= nc; ++j) s->acc[k][j] = 0.0;
+        return 0;
+    }
     if (c->smooth_passes > 0) {
         double *Vn = (double *)malloc(sizeof(double) * (size_t)(nc + 1));
         if (!Vn) return -1;
@@ -494,8 +536,10 @@ void orc_walls(orc_sim *s)
 /* ------------------------------------------------------------------------ */
 typedef struct {
     uint64_t parent;
-    double x;
-    double ve[3], vi[3];
+    double x;              /* parent position (cells) */
+    int64_t cell;          /* parent cell */
+    double ve[3], vi[3];   /* the new electron; the new ion's Maxwellian draw */
+    int64_t target;        /* kinetic neutral consumed by the event, or -1 */
 } orc_iz_event;
 
 static int cmp_event(const void *a, const void *b)
@@ -518,20 +562,17 @@ static int append(orc_sim *s, int k, double x, const double v[3], uint64_t id)
     return 1;
 }
 
-/* the electron and ion species of a two-species plasma */
-static int find_kind(const orc_config *c, int kind)
-{
-    for (int k = 0; k < c->nsp; ++k) if (c->kind[k] == kind) return k;
-    return -1;
-}
-
 /* threshold T = floor(P 2^32) of the candidate test, 0 <= T <= 2^32 */
+/* threshold T = floor(P 2^32) of the candidate test, 0 <= T <= 2^32.  The
+ * electron bound sums elastic, excitation and ionisation; with a constant
+ * ionisation rate coefficient sig_iz v_cap its term is bounded the same way.
+ * A kinetic neutral takes no test. */
 uint64_t orc_candidate_threshold(const orc_config *c, int k)
 {
     const double dx = c->dx, dt = c->dt;
     double sig = 0.0;
-    if (c->kind[k] == ORC_KIND_ELECTRON) sig = c->sig_el + c->sig_iz;
-    else sig = c->sig_cx;
+    if (c->kind[k] == ORC_KIND_ELECTRON) sig = (c->sig_el + c->sig_ex) + c->sig_iz;
+    else if (c->kind[k] == ORC_KIND_ION) sig = c->sig_cx;
     double vcap_hat = c->v_cap[k] * (dt / dx);
     double nu_max = c->n_n * sig * dx * vcap_hat;       /* per step */
     double P = -expm1(-(nu_max * (double)sub_of(c, k)));  /* per push */
@@ -540,14 +581,123 @@ uint64_t orc_candidate_threshold(const orc_config *c, int k)
     return (uint64_t)T;
 }
 
+/* density of the kinetic neutrals at x (cells): the node densities of the
+ * last field pass, gathered with the mover's linear weights */
+static double neutral_density_at(const orc_sim *s, double x)
+{
+    const double jd = floor(x);
+    const double f = x - jd;
+    const int64_t j = (int64_t)jd;
+    return fma(f, s->nn[j + 1] - s->nn[j], s->nn[j]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Kinetic neutrals (the paper's Table 1 case, Sec. 3.4: electron-impact      */
+/* ionisation depletes the gas).  An ionisation event takes its neutral from  */
+/* the parent electron's cell: the events of one cell, in parent-id order,    */
+/* consume that cell's live neutrals (positions after this step's push) in    */
+/* the order of a key drawn for each neutral from block 3 of its own counter, */
+/* (key, id) ascending.  The new ion is the consumed atom: it takes the       */
+/* neutral's position and velocity.  Events beyond the neutrals of their cell */
+/* consume nothing and keep the Maxwellian ion at the parent.                 */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t cell;
+    uint64_t key, id;
+    int64_t idx;
+} orc_nkey;
+
+static int cmp_nkey(const void *a, const void *b)
+{
+    const orc_nkey *p = (const orc_nkey *)a, *q = (const orc_nkey *)b;
+    if (p->cell != q->cell) return (p->cell > q->cell) - (p->cell < q->cell);
+    if (p->key != q->key) return (p->key > q->key) - (p->key < q->key);
+    return (p->id > q->id) - (p->id < q->id);
+}
+
+uint64_t orc_neutral_key(const orc_config *c, uint64_t id, int64_t step)
+{
+    uint32_t u[4];
+    draw_block(c, id, step, 3, u);
+    return ((uint64_t)u[0] << 32) | (uint64_t)u[1];
+}
+
+static int consume_neutrals(orc_sim *s, int kn, orc_iz_event *ev, int64_t n_ev)
+{
+    const orc_config *c = &s->cfg;
+    orc_particles *N = &s->sp[kn];
+    const int32_t nc = c->nc;
+    const int64_t step = s->cnt.step;
+    int64_t *want = (int64_t *)calloc((size_t)nc, sizeof(int64_t));
+    int64_t *gbeg = (int64_t *)malloc(sizeof(int64_t) * (size_t)nc);
+    int64_t *used = (int64_t *)calloc((size_t)nc, sizeof(int64_t));
+    orc_nkey *list = (orc_nkey *)malloc(sizeof(orc_nkey) * (size_t)(N->n > 0 ? N->n : 1));
+    unsigned char *dead = (unsigned char *)calloc((size_t)(N->n > 0 ? N->n : 1), 1);
+    if (!want || !gbeg || !used || !list || !dead) {
+        free(want); free(gbeg); free(used); free(list); free(dead);
+        return -1;
+    }
+    for (int64_t r = 0; r < n_ev; ++r) want[ev[r].cell]++;
+    /* the live neutrals of the cells with events, grouped by cell, keyed */
+    int64_t m = 0;
+    for (int64_t i = 0; i < N->n; ++i) {
+        const int64_t j = (int64_t)floor(N->x[i]);
+        if (want[j] == 0) continue;
+        list[m].cell = j;
+        list[m].key = orc_neutral_key(c, N->id[i], step);
+        list[m].id = N->id[i];
+        list[m].idx = i;
+        m++;
+    }
+    if (m > 1) qsort(list, (size_t)m, sizeof(orc_nkey), cmp_nkey);
+    for (int32_t j = 0; j < nc; ++j) gbeg[j] = -1;
+    for (int64_t q = m - 1; q >= 0; --q) gbeg[list[q].cell] = q;
+    /* events in parent-id order take the neutrals of their cell in key order */
+    for (int64_t r = 0; r < n_ev; ++r) {
+        const int64_t j = ev[r].cell;
+        const int64_t q = used[j]++;
+        ev[r].target = -1;
+        if (gbeg[j] >= 0 && gbeg[j] + q < m && list[gbeg[j] + q].cell == j) {
+            const int64_t i = list[gbeg[j] + q].idx;
+            ev[r].target = i;
+            dead[i] = 1;
+            ev[r].vi[0] = N->vx[i];
+            ev[r].vi[1] = N->vy[i];
+            ev[r].vi[2] = N->vz[i];
+            s->cnt.n_consumed++;
+        } else {
+            s->cnt.n_iz_untargeted++;
+        }
+    }
+    /* positions of the consumed atoms for their ions, then remove them */
+    for (int64_t r = 0; r < n_ev; ++r)
+        if (ev[r].target >= 0) ev[r].x = N->x[ev[r].target];
+    int64_t keep = 0;
+    for (int64_t i = 0; i < N->n; ++i) {
+        if (dead[i]) continue;
+        N->x[keep] = N->x[i];
+        N->vx[keep] = N->vx[i];
+        N->vy[keep] = N->vy[i];
+        N->vz[keep] = N->vz[i];
+        N->id[keep] = N->id[i];
+        keep++;
+    }
+    N->n = keep;
+    free(want); free(gbeg); free(used); free(list); free(dead);
+    return 0;
+}
+
 int orc_mcc(orc_sim *s)
 {
     const orc_config *c = &s->cfg;
     if (!c->mcc_on) return 0;
     const double dx = c->dx, dt = c->dt;
     const int ke = find_kind(c, ORC_KIND_ELECTRON), ki = find_kind(c, ORC_KIND_ION);
+    const int kn = find_kind(c, ORC_KIND_NEUTRAL);
     if (ke < 0 || ki < 0) return -1;
-    const double M = c->m[ki];                    /* neutral mass = ion mass */
+    if (kn >= 0 && (c->sig_cx != 0.0 || !s->nn)) return -1;  /* no ion-neutral processes here */
+    const double M = kn >= 0 ? c->m[kn] : c->m[ki];  /* neutral mass (elastic target) */
+    const int rate_iz = (c->xs_flags & ORC_XS_IZ_RATE) != 0;
     const int64_t step = s->cnt.step;
 
     orc_iz_event *ev = NULL;
@@ -559,23 +709,19 @@ int orc_mcc(orc_sim *s)
 
     for (int k = 0; k < c->nsp; ++k) {
         if (!pushed_at(c, k, step)) continue;  /* tested on its push steps only */
+        if (c->kind[k] == ORC_KIND_NEUTRAL) continue;
         orc_particles *P = &s->sp[k];
         const int is_e = (c->kind[k] == ORC_KIND_ELECTRON);
         const uint64_t T = orc_candidate_threshold(c, k);
         const double vcap_hat = c->v_cap[k] * (dt / dx);
-        double c0, c1;                      /* cumulative n_n sigma dx */
-        if (is_e) {
-            c0 = c->n_n * c->sig_el * dx;
-            c1 = c->n_n * (c->sig_el + c->sig_iz) * dx;
-        } else {
-            c0 = c->n_n * c->sig_cx * dx;
-            c1 = c0;
-        }
-        const double nu_max = c1 * vcap_hat;
-        const double C0 = c0 * c0, C1 = c1 * c1;
+        /* the bound nu_max from n_n (the uniform gas, or the bound of the
+         * local density of kinetic neutrals) */
+        const double sig_tot = is_e ? (c->sig_el + c->sig_ex) + c->sig_iz : c->sig_cx;
+        const double nu_max = ((c->n_n * sig_tot) * dx) * vcap_hat;
         const double vcap2 = vcap_hat * vcap_hat;
-        /* ionisation threshold speed^2 in (cells/step)^2: 2 E_iz / m_e (dt/dx)^2 */
+        /* threshold speeds^2 in (cells/step)^2: 2 E / m_e (dt/dx)^2 */
         const double v2_iz = (2.0 * c->E_iz / c->m[k]) * ((dt / dx) * (dt / dx));
+        const double v2_ex = (2.0 * c->E_ex / c->m[k]) * ((dt / dx) * (dt / dx));
         const double eps_iz = 0.5 * v2_iz;
         /* neutral thermal speed (cells/step) for Maxwellian products */
         const double sig_n = sqrt(c->T_n / M) * (dt / dx);
@@ -588,9 +734,28 @@ int orc_mcc(orc_sim *s)
             const double vx = P->vx[p], vy = P->vy[p], vz = P->vz[p];
             const double v2 = (vx * vx + vy * vy) + vz * vz;
             if (v2 > vcap2) s->cnt.n_over_cap++;
+            /* the neutral density the candidate sees */
+            double nl = c->n_n;
+            if (kn >= 0) {
+                nl = neutral_density_at(s, P->x[p]);
+                if (nl > c->n_n) s->cnt.status |= ORC_ST_NN_CAP;
+            }
+            /* cumulative (density x cross section x dx) of the processes */
+            double c0, c1, c2;
+            if (is_e) {
+                c0 = (nl * c->sig_el) * dx;
+                c1 = (nl * (c->sig_el + c->sig_ex)) * dx;
+                c2 = (nl * ((c->sig_el + c->sig_ex) + c->sig_iz)) * dx;
+            } else {
+                c0 = (nl * c->sig_cx) * dx;
+                c1 = c0;
+                c2 = c0;
+            }
+            const double C0 = c0 * c0, C1 = c1 * c1, C2 = c2 * c2;
             const double r = u01(u[1]) * nu_max;
             const double r2 = r * r;
             if (is_e) {
+                int iz = 0;
                 if (r2 < C0 * v2) {
                     /* elastic, cold neutral target, isotropic in the centre of mass */
                     double d[3];
@@ -600,10 +765,32 @@ int orc_mcc(orc_sim *s)
                     P->vy[p] = am * vy + bm * g * d[1];
                     P->vz[p] = am * vz + bm * g * d[2];
                     s->cnt.n_elastic++;
-                } else if (v2 >= v2_iz && r2 < C1 * v2) {
+                } else if (r2 < C1 * v2) {
+                    /* excitation above its threshold: the electron loses E_ex
+                     * and leaves isotropically (the atom is not followed) */
+                    if (v2 >= v2_ex) {
+                        double d[3];
+                        iso_dir(u[2], u[3], d);
+                        const double g = sqrt(v2 - v2_ex);
+                        P->vx[p] = g * d[0];
+                        P->vy[p] = g * d[1];
+                        P->vz[p] = g * d[2];
+                        s->cnt.n_excite++;
+                    }
+                } else if (v2 >= v2_iz) {
+                    if (rate_iz) {
+                        /* slot width nl sig_iz dx v_cap: r < c1 |v| + that */
+                        const double rr = r - ((nl * c->sig_iz) * dx) * vcap_hat;
+                        iz = rr < 0.0 || rr * rr < C1 * v2;
+                    } else {
+                        iz = r2 < C2 * v2;
+                    }
+                }
+                if (iz) {
                     /* ionisation: the energy above threshold is split U : 1-U
                      * between the two electrons, both isotropic; the new ion
-                     * takes a neutral's Maxwellian velocity */
+                     * takes a neutral's Maxwellian velocity (or, with kinetic
+                     * neutrals, the consumed atom's) */
                     uint32_t u1[4], u2[4];
                     draw_block(c, P->id[p], step, 1, u1);
                     draw_block(c, P->id[p], step, 2, u2);
@@ -620,6 +807,8 @@ int orc_mcc(orc_sim *s)
                     orc_iz_event *e = &ev[n_ev++];
                     e->parent = P->id[p];
                     e->x = P->x[p];
+                    e->cell = (int64_t)floor(P->x[p]);
+                    e->target = -1;
                     e->ve[0] = g2 * d2[0];
                     e->ve[1] = g2 * d2[1];
                     e->ve[2] = g2 * d2[2];
@@ -652,11 +841,25 @@ int orc_mcc(orc_sim *s)
     /* ids of created particles: events ordered by parent id; event r gives
      * the electron next_id + 2r and the ion next_id + 2r + 1 */
     if (n_ev > 1) qsort(ev, (size_t)n_ev, sizeof(orc_iz_event), cmp_event);
+    /* the new electron stays at its parent; keep that position apart from
+     * the ion's, which becomes the consumed atom's */
+    double *xe = NULL;
+    if (n_ev > 0) {
+        xe = (double *)malloc(sizeof(double) * (size_t)n_ev);
+        if (!xe) { free(ev); return -1; }
+        for (int64_t r = 0; r < n_ev; ++r) xe[r] = ev[r].x;
+    }
+    if (kn >= 0 && n_ev > 0 && consume_neutrals(s, kn, ev, n_ev)) {
+        free(xe);
+        free(ev);
+        return -1;
+    }
     for (int64_t r = 0; r < n_ev; ++r) {
-        append(s, ke, ev[r].x, ev[r].ve, s->cnt.next_id + 2 * (uint64_t)r);
+        append(s, ke, xe[r], ev[r].ve, s->cnt.next_id + 2 * (uint64_t)r);
         append(s, ki, ev[r].x, ev[r].vi, s->cnt.next_id + 2 * (uint64_t)r + 1);
     }
     s->cnt.next_id += 2 * (uint64_t)n_ev;
+    free(xe);
     free(ev);
     return 0;
 }

@@ -26,8 +26,9 @@ Workloads (the recipe is restated in the design doc):
   * ``bounded_mcc`` the same plus null-collision MCC against a neutral
                    background (n_n = 1e3 n0, T_n = 1 eV), 100,000 cells x 100
                    particles/cell/species, cell sort every 20 steps.
-  * ``table1``     the paper's Table 1 test-case shape (periodic, unmagnetised,
-                   100,000 cells, 1 m); used for unit checks only.
+  * ``table1``     the paper's Table 1 test case (periodic, unmagnetised, no
+                   field solve, 100,000 cells, 1 m): electrons, D+ ions and
+                   kinetic D neutrals, elastic, excitation and ionisation.
 """
 from __future__ import annotations
 
@@ -46,6 +47,7 @@ EV = E_CHARGE  # 1 eV in joules
 
 KIND_ELECTRON = 0
 KIND_ION = 1
+KIND_NEUTRAL = 2   # kinetic neutral atom (q = 0): moved ballistically, consumed by ionisation
 
 BC_PERIODIC = 0
 BC_ABSORB = 1
@@ -74,6 +76,9 @@ class MCC:
     sig_iz: float       # electron-impact ionisation cross section [m^2]
     E_iz: float         # ionisation threshold [J]
     sig_cx: float       # ion-neutral charge exchange cross section [m^2]
+    sig_ex: float = 0.0  # electron-impact excitation cross section [m^2]
+    E_ex: float = 0.0    # excitation threshold [J]
+    iz_const_rate: bool = False  # ionisation rate coefficient sig_iz v_cap, constant in |v|
 
 
 @dataclass
@@ -98,6 +103,7 @@ class Workload:
     pair_start: bool = False    # every ion starts at an electron's position (neutral start)
     state_seed: Optional[int] = None  # seed of the initial-state generator (default: seed)
     smooth_passes: int = 0      # binomial density-smoother passes before the field solve
+    field_off: bool = False     # no field solve (E = 0), as in the paper's Table 1 case
 
     def replace(self, **kw) -> "Workload":
         return dataclasses.replace(self, **kw)
@@ -207,25 +213,39 @@ def batched(n_inst: int = 256, seed: int = 4, nc_min: int = 256, nc_ratio: float
     return out
 
 
-def table1() -> Workload:
-    """Shape of the paper's Table 1 test case (periodic, unmagnetised).
+def table1(nc: int = 100_000, ppc: float = 100, seed: int = 6, n_steps: int = 200_000,
+           L: float = 1.0, sort_every: int = 20, cap_factor: float = 1.25,
+           mcc: Optional[MCC] = None, v_cap_eV: float = 400.0) -> Workload:
+    """The paper's Table 1 test case (Sec. 3.4): an initially uniform hot
+    plasma (electrons and D+ ions, 1e21 m^-3, 20 eV) in a uniform deuterium
+    gas of kinetic neutral atoms (1e21 m^-3, 1 eV), periodic, unmagnetised,
+    no field solver; electron-neutral elastic, excitation and ionisation
+    collisions; 1 m, 100,000 cells, 100 particles/cell/species, dt = 4e-14 s,
+    200,000 steps.
 
-    1 m, 100,000 cells, 100 particles/cell/species, dt = 4e-14 s, densities
-    1e21 m^-3, 20 eV charged species.  (Neutrals are a kinetic species in the
-    paper; they are not part of this workload builder.)
+    The paper gives no cross sections.  The defaults are constant stand-ins
+    of the right size for deuterium: elastic 1e-19 m^2, excitation 5e-21 m^2
+    above 10.2 eV, ionisation 5e-21 m^2 above 13.6 eV.  n_n is the bound of
+    the local neutral density used by the null-collision test (2 n0).
     """
     n0 = 1e21
-    nc = 100_000
-    L = 1.0
     dx = L / nc
-    ppc = 100
     w = n0 * dx / ppc
     Te = 20.0 * EV
-    e = Species("e", KIND_ELECTRON, q=-E_CHARGE, m=M_ELECTRON, w=w, ppc=ppc, T=Te)
-    i = Species("D+", KIND_ION, q=E_CHARGE, m=2.0 * 1836.15267343 * M_ELECTRON, w=w,
-                ppc=ppc, T=Te)
+    m_d = 2.0 * 1836.15267343 * M_ELECTRON       # deuteron (the D+ ion)
+    e = Species("e", KIND_ELECTRON, q=-E_CHARGE, m=M_ELECTRON, w=w, ppc=ppc, T=Te,
+                cap_factor=cap_factor)
+    i = Species("D+", KIND_ION, q=E_CHARGE, m=m_d, w=w, ppc=ppc, T=Te, cap_factor=cap_factor)
+    n = Species("D", KIND_NEUTRAL, q=0.0, m=m_d + M_ELECTRON, w=w, ppc=ppc, T=1.0 * EV,
+                cap_factor=1.0)
+    for s in (e, i, n):
+        s.v_cap = math.sqrt(2.0 * v_cap_eV * EV / s.m)
+    if mcc is None:
+        mcc = MCC(n_n=2.0 * n0, T_n=1.0 * EV, sig_el=1e-19, sig_iz=5e-21, E_iz=13.6 * EV,
+                  sig_cx=0.0, sig_ex=5e-21, E_ex=10.2 * EV)
     return Workload(name="table1", nc=nc, bc=BC_PERIODIC, dx=dx, dt=4e-14, eps0=EPS0_SI,
-                    species=[e, i], seed=6, n_steps=200_000)
+                    species=[e, i, n], mcc=mcc, seed=seed, n_steps=n_steps,
+                    sort_every=sort_every, field_off=True)
 
 
 # ---------------------------------------------------------------------------

@@ -29,7 +29,7 @@ MUTATIONS = [
      "P->vx[p] = bm * vx + am * g * d[0];"),
     ("ionisation energy not split", "const double e2 = e_tot - e1;", "const double e2 = e_tot;"),
     ("Philox key constant", "k0 += 0x9E3779B9u;", "k0 += 0x9E3779B8u;"),
-    ("ionisation threshold ignored", "if (v2 >= v2_iz && r2 < C1 * v2)", "if (r2 < C1 * v2)"),
+    ("ionisation threshold ignored", "} else if (v2 >= v2_iz) {", "} else if (1) {"),
     ("source counts one wall", "const int64_t n_pairs = s->cnt.absorbed[ki][0] + s->cnt.absorbed[ki][1];",
      "const int64_t n_pairs = s->cnt.absorbed[ki][0];"),
     ("events not ranked by parent id", "if (n_ev > 1) qsort", "if (0) qsort"),
@@ -43,6 +43,20 @@ MUTATIONS = [
     ("subcycled advance ignores nstep", "x[p] = x[p] + ms * vx[p];", "x[p] = x[p] + vx[p];"),
     ("subcycled collision test uses one step", "double P = -expm1(-(nu_max * (double)sub_of(c, k)));",
      "double P = -expm1(-nu_max);"),
+    ("atoms consumed largest key first", "if (p->key != q->key) return (p->key > q->key) - (p->key < q->key);",
+     "if (p->key != q->key) return (p->key < q->key) - (p->key > q->key);"),
+    ("ion left at the parent, not the atom", "if (ev[r].target >= 0) ev[r].x = N->x[ev[r].target];",
+     "if (0) ev[r].x = N->x[ev[r].target];"),
+    ("excitation loses no energy", "const double g = sqrt(v2 - v2_ex);", "const double g = sqrt(v2);"),
+    ("constant rate taken at |v|", "const double rr = r - ((nl * c->sig_iz) * dx) * vcap_hat;",
+     "const double rr = r - ((nl * c->sig_iz) * dx) * sqrt(v2);"),
+    ("neutral density without the node volume", "n = (c->w[kn] * ((double)Sj * two_m32)) / V;",
+     "n = (c->w[kn] * ((double)Sj * two_m32)) / dx;"),
+    ("mean instead of local neutral density", "nl = neutral_density_at(s, P->x[p]);",
+     "nl = 0.5 * (s->nn[0] + s->nn[c->nc / 2]);"),
+    ("field left on without the solver", "    if (c->field_off) {", "    if (0) {"),
+    ("new electrons not counted in n_e", "append(s, ke, xe[r], ev[r].ve, s->cnt.next_id + 2 * (uint64_t)r);",
+     "(void)xe;"),
 ]
 
 
