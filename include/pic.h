@@ -5,8 +5,9 @@
  * The operations follow the explicit PIC cycle of Williams et al., arXiv
  * 2404.10270, Sec. 2 (five phases: plasma density calculation, density
  * smoother, field solver, collisions and plasma-wall interaction, particle
- * mover) and the mover statements of its moveb listing (Sec. 6).  The
- * smoother is not part of this library.
+ * mover), the mover statements of its moveb listing (Sec. 6), and its Table 1
+ * test case (Sec. 3.4: electrons, ions and kinetic neutral atoms, no field
+ * solver, ionisation depleting the gas).
  *
  * Units.  Particle positions are in cells (domain [0, nc)), velocities in
  * cells per step; the configuration carries SI (or plasma-unit) physical
@@ -58,9 +59,12 @@ typedef enum {
 #define PIC_ST_CANDIDATES 0x8u   /* the collision candidate or event list overflowed */
 #define PIC_ST_INTERNAL   0x10u  /* a device-side consistency check failed */
 #define PIC_ST_BAD_INIT   0x20u  /* an uploaded particle was out of range and was dropped */
+#define PIC_ST_NN_CAP     0x40u  /* a local kinetic-neutral density exceeded the bound n_n */
 
 typedef enum { PIC_BC_PERIODIC = 0, PIC_BC_ABSORB = 1 } pic_bc;
-typedef enum { PIC_KIND_ELECTRON = 0, PIC_KIND_ION = 1 } pic_kind;
+/* PIC_KIND_NEUTRAL: kinetic neutral atoms (q = 0), moved ballistically and
+ * consumed by electron-impact ionisation (at most one such species) */
+typedef enum { PIC_KIND_ELECTRON = 0, PIC_KIND_ION = 1, PIC_KIND_NEUTRAL = 2 } pic_kind;
 typedef enum {
     PIC_FP32 = 0,   /* FP32 gather/push, (cell, f32 in-cell offset) positions, fixed-point deposit */
     PIC_FP64 = 1    /* FP64 gather/push, f64 positions in cells, fixed-point deposit */
@@ -87,7 +91,8 @@ typedef struct {
     int32_t bc;          /* pic_bc */
     int32_t nsp;         /* species, 1..PIC_MAX_SPECIES */
     int32_t precision;   /* pic_precision (must agree across instances) */
-    int32_t mcc_on;      /* null-collision MCC (needs one electron and one ion species) */
+    int32_t mcc_on;      /* null-collision MCC (needs one electron and one ion species;
+                            with a neutral species its atoms are the collision targets) */
     int32_t source_on;   /* pair source refilling the ions lost to the walls */
     int32_t _pad0, _pad1;
     uint64_t seed;       /* key of the Philox draws */
@@ -95,7 +100,9 @@ typedef struct {
     double B0;           /* magnetic field magnitude [T] */
     double theta;        /* angle of B to the wall normal x, in the x-y plane [rad] */
     pic_species sp[PIC_MAX_SPECIES];
-    double n_n, T_n;     /* neutral density [m^-3] and temperature [J] */
+    double n_n, T_n;     /* neutral density [m^-3] (with a kinetic neutral species: the
+                            bound of its local density in the null-collision test)
+                            and temperature [J] */
     double sig_el, sig_iz, E_iz, sig_cx;  /* cross sections [m^2], threshold [J] */
     uint64_t next_id;    /* id given to the first created particle */
     int64_t step0;       /* index of the first step (keys the draws) */
@@ -109,7 +116,18 @@ typedef struct {
        (total charge unchanged), a periodic grid wraps.  0 = off, at most 64. */
     int32_t smooth_passes;
     int32_t _pad2;
+    /* electron-impact excitation: cross section [m^2] and threshold [J]
+       (the electron loses E_ex and leaves isotropically) */
+    double sig_ex, E_ex;
+    /* no field solve (E = 0), as in the Table 1 case: the deposit, rho and
+       the neutral density are still formed */
+    int32_t field_off;
+    uint32_t xs_flags;   /* PIC_XS_* */
 } pic_config;
+
+/* ionisation with a constant rate coefficient sig_iz * v_cap (frequency
+   n sig_iz v_cap whatever the speed) instead of a constant cross section */
+#define PIC_XS_IZ_RATE 0x1u
 
 /* options of the drawn initial state */
 #define PIC_INIT_OPT_QUIET 0x1u  /* lattice positions (p + 1/2) nc / n instead of uniform draws */
@@ -160,6 +178,9 @@ typedef struct {
     int64_t created_total[PIC_MAX_SPECIES];
     int64_t n_candidates, n_elastic, n_ionize, n_cx, n_over_cap, n_source;
     int64_t particle_steps;       /* particles pushed, summed over steps */
+    int64_t n_excite;             /* excitation collisions */
+    int64_t n_consumed;           /* neutral atoms consumed by ionisation */
+    int64_t n_iz_untargeted;      /* ionisations whose cell had no atom left */
 } pic_diag;
 
 /* workspace regions readable by tests and tools (pic_region) */
@@ -171,7 +192,8 @@ typedef enum {
     PIC_R_ACC64 = 4,     /* double [nsp][n_nodes]  (q/m) E dt^2/dx, cells/step^2 */
     PIC_R_ACC32 = 5,     /* float  [nsp][n_nodes]  the same, rounded to FP32 */
     PIC_R_CELL_OFFSETS = 6, /* uint32 [nsp][n_nodes] first slot of each cell after the last sort */
-    PIC_R_NODE_BASE = 7  /* int64 [n_inst+1]       first node of each instance */
+    PIC_R_NODE_BASE = 7, /* int64 [n_inst+1]       first node of each instance */
+    PIC_R_NEUTRAL_DENSITY = 8 /* double [n_nodes] density of the kinetic neutrals [m^-3] */
 } pic_region_id;
 
 typedef struct pic_ctx pic_ctx;
@@ -227,8 +249,10 @@ int pic_init(const pic_config *cfgs, int n_inst, const pic_buffers *bufs, void *
  * x += vx, then plasma-wall interaction (absorbing walls, counted per wall,
  * or periodic re-entry).  Unless PIC_PUSH_NO_DEPOSIT, the new positions are
  * deposited (phase 1 of the next step) into the fixed-point arrays.  With
- * MCC on, every particle takes the null-collision test; the selected ones
- * are listed, with their velocities and ids, for pic_mcc_collide.
+ * MCC on, every particle of a species with a collision process takes the
+ * null-collision test; the selected ones are listed, with their velocities
+ * and ids, for pic_mcc_collide.  Kinetic neutrals (q = 0) and every species
+ * of a field-off instance move ballistically.
  */
 int pic_push(pic_ctx *ctx, unsigned flags);
 
@@ -243,17 +267,32 @@ int pic_deposit(pic_ctx *ctx);
  * pic_field_solve -- phases 2 and 3 (Sec. 2, density smoother and field
  * solver): rho from the deposit, smoothed when smooth_passes > 0, the
  * tridiagonal Poisson solve in FP64 (Thomas recurrences), E = -grad(phi) and
- * the per-species grid acceleration.  Consumes (clears) the deposit.
+ * the per-species grid acceleration; also the node density of a kinetic
+ * neutral species (its deposit times its macro weight over the node volume).
+ * A field-off instance gets E = phi = 0.  Consumes (clears) the deposit.
  */
 int pic_field_solve(pic_ctx *ctx);
 
 /*
  * pic_mcc_collide -- phase 4 (Sec. 2, collisions and plasma-wall
  * interaction): null-collision Monte Carlo for the particles listed by
- * pic_push (elastic e-n, charge exchange i-n, ionisation with pair creation),
- * the pair source refilling this step's ion wall loss, ids of the created
- * particles, and the close of the step (counters, step index).  Must be
- * called once per step after pic_push, also when MCC and source are off.
+ * pic_push (elastic e-n, excitation, charge exchange i-n, ionisation with
+ * pair creation), the pair source refilling this step's ion wall loss, ids
+ * of the created particles, and the close of the step (counters, step
+ * index).  Must be called once per step after pic_push, also when MCC and
+ * source are off.
+ *
+ * With a kinetic neutral species (the Table 1 case, Sec. 3.4) the electron
+ * rates use the local atom density of the last field pass, gathered at the
+ * electron with the mover's linear weights, and each ionisation consumes an
+ * atom of its parent's cell: the events of a cell, in parent-id order, take
+ * the live atoms of the cell (after this step's push) in the order of the
+ * key (w0 << 32 | w1) of Philox block (id, step, 3) of the atom, ties by id;
+ * the new ion is that atom (its position and velocity).  An event whose cell
+ * has no atom left creates its ion at the parent with a Maxwellian draw at
+ * T_n.  The atoms of a cell are found through the cell offsets of the last
+ * pic_sort (a window of cells wide enough for the fastest atom since then),
+ * or by a scan of the species when no sort has run.
  */
 int pic_mcc_collide(pic_ctx *ctx);
 

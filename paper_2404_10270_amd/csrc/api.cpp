@@ -48,6 +48,13 @@ int find_kind(const pic_config &c, int kind)
     return -1;
 }
 
+int count_kind(const pic_config &c, int kind)
+{
+    int n = 0;
+    for (int k = 0; k < c.nsp; ++k) n += c.sp[k].kind == kind;
+    return n;
+}
+
 int validate(const pic_config *cfgs, int n_inst)
 {
     if (!cfgs || n_inst < 1 || n_inst > kMaxInst) return PIC_E_ARG;
@@ -63,24 +70,36 @@ int validate(const pic_config *cfgs, int n_inst)
         if (!finite_nonneg(c.B0) || !std::isfinite(c.theta)) return PIC_E_CONFIG;
         if (c.next_id >= (1ull << 62) || c.step0 < 0) return PIC_E_CONFIG;
         if (c.smooth_passes < 0 || c.smooth_passes > 64) return PIC_E_CONFIG;
+        if (c.field_off != 0 && c.field_off != 1) return PIC_E_CONFIG;
+        if (c.xs_flags & ~PIC_XS_IZ_RATE) return PIC_E_CONFIG;
+        if (count_kind(c, PIC_KIND_NEUTRAL) > 1) return PIC_E_CONFIG;
         for (int k = 0; k < nsp; ++k) {
             const pic_species &s = c.sp[k];
             if (!std::isfinite(s.q) || !finite_pos(s.m) || !finite_pos(s.w)) return PIC_E_CONFIG;
-            if (s.kind != PIC_KIND_ELECTRON && s.kind != PIC_KIND_ION) return PIC_E_CONFIG;
+            if (s.kind != PIC_KIND_ELECTRON && s.kind != PIC_KIND_ION && s.kind != PIC_KIND_NEUTRAL)
+                return PIC_E_CONFIG;
+            if (s.kind == PIC_KIND_NEUTRAL && s.q != 0.0) return PIC_E_CONFIG;
             if (s.nstep < 0 || s.nstep > 1000000) return PIC_E_CONFIG;
             if (s.capacity < 1 || s.n_init < 0 || s.n_init > s.capacity) return PIC_E_CONFIG;
             if (s.capacity > kMaxSlots) return PIC_E_CONFIG;
         }
+        // collisions and the source: one electron and one ion species, and
+        // at most one kinetic neutral species besides
         if (c.mcc_on || c.source_on) {
-            if (nsp != 2 || find_kind(c, PIC_KIND_ELECTRON) < 0 || find_kind(c, PIC_KIND_ION) < 0)
+            const int nn = count_kind(c, PIC_KIND_NEUTRAL);
+            if (count_kind(c, PIC_KIND_ELECTRON) != 1 || count_kind(c, PIC_KIND_ION) != 1 ||
+                nsp != 2 + nn)
                 return PIC_E_CONFIG;
         }
         if (c.mcc_on) {
             if (!finite_nonneg(c.n_n) || !finite_nonneg(c.T_n) || !finite_nonneg(c.sig_el) ||
-                !finite_nonneg(c.sig_iz) || !finite_nonneg(c.E_iz) || !finite_nonneg(c.sig_cx))
+                !finite_nonneg(c.sig_iz) || !finite_nonneg(c.E_iz) || !finite_nonneg(c.sig_cx) ||
+                !finite_nonneg(c.sig_ex) || !finite_nonneg(c.E_ex))
                 return PIC_E_CONFIG;
+            // no ion-neutral process with kinetic neutrals (the atom would have to change too)
+            if (find_kind(c, PIC_KIND_NEUTRAL) >= 0 && c.sig_cx != 0.0) return PIC_E_CONFIG;
             for (int k = 0; k < nsp; ++k)
-                if (!finite_pos(c.sp[k].v_cap)) return PIC_E_CONFIG;
+                if (c.sp[k].kind != PIC_KIND_NEUTRAL && !finite_pos(c.sp[k].v_cap)) return PIC_E_CONFIG;
         }
         if (c.source_on)
             for (int k = 0; k < nsp; ++k)
@@ -157,22 +176,31 @@ void seg_constants(const pic_config &c, int inst, int k, SegConst &s)
     s.vs = dx / dt;
     s.key0 = (uint32_t)c.seed;
     s.key1 = (uint32_t)(c.seed >> 32) ^ (uint32_t)inst;
+    s.w = sp.w;
+    s.force = (sp.q != 0.0 && !c.field_off) ? 1 : 0;  // else no gather: the acceleration is 0
     s.T = 0;
-    s.nu_max = s.C0 = s.C1 = s.vcap2 = s.v2_iz = s.eps_iz = s.am = s.bm = s.sig_n = 0.0;
+    s.nu_max = s.C0 = s.C1 = s.C2 = s.crate = 0.0;
+    s.vcap2 = s.v2_iz = s.eps_iz = s.v2_ex = s.vcap_hat = s.am = s.bm = s.sig_n = 0.0;
+    s.sig_el = s.sig_ex = s.sig_iz = 0.0;
+    s.dxm = dx;
+    s.n_bound = c.n_n;
+    s.kinetic = s.rate_iz = 0;
     s.sig_src = 0.0;
     if (c.source_on) s.sig_src = std::sqrt(sp.T_src / sp.m) * (dt / dx);
     if (c.mcc_on) {
-        const int ki = find_kind(c, PIC_KIND_ION);
-        const double M = c.sp[ki].m;  // neutral mass = ion mass
-        double sig, c0, c1;
+        const int ki = find_kind(c, PIC_KIND_ION), kn = find_kind(c, PIC_KIND_NEUTRAL);
+        const double M = kn >= 0 ? c.sp[kn].m : c.sp[ki].m;  // neutral (elastic target) mass
+        // cumulative (n sigma) dx of the processes, in the bound's density n_n
+        double sig = 0.0, c0 = 0.0, c1 = 0.0, c2 = 0.0;
         if (sp.kind == PIC_KIND_ELECTRON) {
-            sig = c.sig_el + c.sig_iz;
-            c0 = c.n_n * c.sig_el * dx;
-            c1 = c.n_n * (c.sig_el + c.sig_iz) * dx;
-        } else {
+            sig = (c.sig_el + c.sig_ex) + c.sig_iz;
+            c0 = (c.n_n * c.sig_el) * dx;
+            c1 = (c.n_n * (c.sig_el + c.sig_ex)) * dx;
+            c2 = (c.n_n * ((c.sig_el + c.sig_ex) + c.sig_iz)) * dx;
+        } else if (sp.kind == PIC_KIND_ION) {
             sig = c.sig_cx;
-            c0 = c.n_n * c.sig_cx * dx;
-            c1 = c0;
+            c0 = (c.n_n * c.sig_cx) * dx;
+            c1 = c2 = c0;
         }
         const double vcap_hat = sp.v_cap * (dt / dx);
         const double nu_max_T = c.n_n * sig * dx * vcap_hat;
@@ -180,15 +208,24 @@ void seg_constants(const pic_config &c, int inst, int k, SegConst &s)
         double T = std::floor(std::ldexp(P, 32));
         if (T > 4294967296.0) T = 4294967296.0;
         s.T = (uint64_t)T;
-        s.nu_max = c1 * vcap_hat;
+        s.nu_max = nu_max_T;
         s.C0 = c0 * c0;
         s.C1 = c1 * c1;
+        s.C2 = c2 * c2;
+        s.crate = ((c.n_n * c.sig_iz) * dx) * vcap_hat;
         s.vcap2 = vcap_hat * vcap_hat;
+        s.vcap_hat = vcap_hat;
         s.v2_iz = (2.0 * c.E_iz / sp.m) * ((dt / dx) * (dt / dx));
         s.eps_iz = 0.5 * s.v2_iz;
+        s.v2_ex = (2.0 * c.E_ex / sp.m) * ((dt / dx) * (dt / dx));
         s.am = sp.m / (sp.m + M);
         s.bm = M / (sp.m + M);
         s.sig_n = std::sqrt(c.T_n / sp.m) * (dt / dx);
+        s.sig_el = c.sig_el;
+        s.sig_ex = c.sig_ex;
+        s.sig_iz = c.sig_iz;
+        s.kinetic = (kn >= 0 && sp.kind == PIC_KIND_ELECTRON) ? 1 : 0;
+        s.rate_iz = (c.xs_flags & PIC_XS_IZ_RATE) ? 1 : 0;
     }
 }
 
@@ -287,6 +324,9 @@ int plan(const pic_config *cfgs, int n_inst, Plan &p)
     L.ev = take(sizeof(IzEvent) * ((uint64_t)p.n_push_blocks * L.ev_q + L.ev_ovf_cap));
     L.ev_n = take(sizeof(uint32_t) * p.n_push_blocks);
     L.ev_rank = take(sizeof(uint32_t) * ((uint64_t)p.n_push_blocks * L.ev_q + L.ev_ovf_cap));
+    L.ev_crank = take(sizeof(uint32_t) * ((uint64_t)p.n_push_blocks * L.ev_q + L.ev_ovf_cap));
+    L.ev_target = take(sizeof(long long) * ((uint64_t)p.n_push_blocks * L.ev_q + L.ev_ovf_cap));
+    L.nn = take(sizeof(double) * p.G);
     L.cnt_slot = take(sizeof(unsigned long long) * (uint64_t)p.n_push_blocks *
                       (n_seg <= kCntSegMax ? n_seg : 0) * kNCnt);
     L.diag_part = take(sizeof(double) * (uint64_t)kDiagBlocks * n_seg * kDiagVals);
@@ -402,7 +442,10 @@ int pic_init(const pic_config *cfgs, int n_inst, const pic_buffers *bufs, void *
         ic.init_mode = cf.init_mode;
         ic.init_opts = (int32_t)cf.init_opts;
         ic.smooth_passes = cf.smooth_passes;
-        if (cf.smooth_passes > c->max_smooth) c->max_smooth = cf.smooth_passes;
+        ic.field_off = cf.field_off;
+        const int kn = find_kind(cf, PIC_KIND_NEUTRAL);
+        ic.seg_n = kn >= 0 ? i * nsp + kn : -1;
+        if (!cf.field_off && cf.smooth_passes > c->max_smooth) c->max_smooth = cf.smooth_passes;
         int64_t id0 = 0;
         for (int k = 0; k < nsp; ++k) {
             const int s = i * nsp + k;
@@ -436,6 +479,7 @@ int pic_init(const pic_config *cfgs, int n_inst, const pic_buffers *bufs, void *
     Globals g;
     std::memset(&g, 0, sizeof(g));
     g.cur_set = 0;
+    g.since_sort = kNoIndex;  // no cell offsets yet
     for (int q = 0; q < 4; ++q) g.scan_gen[q] = 1;
 
     void *W = bufs->work;
@@ -478,6 +522,9 @@ int pic_init(const pic_config *cfgs, int n_inst, const pic_buffers *bufs, void *
     d.ev = at<IzEvent>(W, L.ev);
     d.ev_n = at<uint32_t>(W, L.ev_n);
     d.ev_rank = at<uint32_t>(W, L.ev_rank);
+    d.ev_crank = at<uint32_t>(W, L.ev_crank);
+    d.ev_target = at<long long>(W, L.ev_target);
+    d.nn = at<double>(W, L.nn);
     d.cnt_slot = at<unsigned long long>(W, L.cnt_slot);
     d.diag_part = at<double>(W, L.diag_part);
     d.diag_out = at<pic_diag>(W, L.diag_out);
@@ -495,6 +542,12 @@ int pic_init(const pic_config *cfgs, int n_inst, const pic_buffers *bufs, void *
     d.n_inst = n_inst;
     d.nsp = nsp;
     d.precision = c->precision;
+    d.kinetic_any = 0;
+    d.field_all_off = 1;
+    for (int i = 0; i < n_inst; ++i) {
+        if (find_kind(cfgs[i], PIC_KIND_NEUTRAL) >= 0) d.kinetic_any = 1;
+        if (!cfgs[i].field_off) d.field_all_off = 0;
+    }
 
     hipStream_t st = c->st;
     bool ok = hipMemsetAsync(W, 0, L.total, st) == hipSuccess;
@@ -754,6 +807,7 @@ int pic_region(const pic_ctx *c, int region, uint64_t *byte_offset, int64_t *n_e
     case PIC_R_ACC32: *byte_offset = L.acc32; *n_elems = nb; break;
     case PIC_R_CELL_OFFSETS: *byte_offset = L.offsets; *n_elems = nb; break;
     case PIC_R_NODE_BASE: *byte_offset = L.node_base; *n_elems = c->n_inst + 1; break;
+    case PIC_R_NEUTRAL_DENSITY: *byte_offset = L.nn; *n_elems = G; break;
     default: return PIC_E_ARG;
     }
     return PIC_OK;

@@ -163,20 +163,41 @@ __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, double &n0, d
 
 // ---------------------------------------------------------------------------
 // Null-collision Monte Carlo for one candidate (Vahedi & Surendra, CPC 87,
-// 1995) against a uniform neutral gas.  The candidate's first Philox block
-// (id, step, 0) is redrawn; r = U(u1) nu_max is compared with the cumulative
-// n_n sigma_k |v| in squared form, all in FP64:
+// 1995).  The candidate's first Philox block (id, step, 0) is redrawn;
+// r = U(u1) nu_max is compared, in FP64 and squared form, with the cumulative
+// (n sigma_k dx) |v| of the processes in a fixed order:
 //   electron  elastic (cold neutral of mass M, isotropic in the centre of
-//             mass), else ionisation above threshold (energy above it split
-//             U : 1-U, the first electron isotropic; the second electron's
-//             speed is returned in g2 for the pair creation);
+//             mass); excitation above its threshold (loses E_ex, isotropic);
+//             ionisation above its threshold (energy above it split U : 1-U,
+//             the first electron isotropic; the second electron's speed is
+//             returned in g2 for the pair creation), its slot n sig_iz dx
+//             |v|, or n sig_iz dx v_cap with a constant rate coefficient;
 //   ion       charge exchange (the ion takes a Maxwellian velocity at T_n).
-// (vx, vy, vz) in cells/step are updated in place; cnt gets the process
-// counts (candidate, elastic, ionisation, CX, above v_cap).
+// n is the uniform gas density, or the local density of kinetic neutrals.
+// (vx, vy, vz) in cells/step are updated in place; cnt gets the counts.
 // ---------------------------------------------------------------------------
-enum { kCCand = 0, kCEl = 1, kCIz = 2, kCCx = 3, kCOver = 4 };
+enum { kCCand = 0, kCEl = 1, kCIz = 2, kCCx = 3, kCOver = 4, kCEx = 5 };
 
-__device__ __forceinline__ void collide_vel(const SegConst &sc, long long step,
+// squares of the cumulative (n sigma) dx, and the constant-rate ionisation slot
+struct Rates {
+    double C0, C1, C2, crate;
+};
+
+__device__ __forceinline__ Rates uniform_rates(const SegConst &sc)
+{
+    return Rates{sc.C0, sc.C1, sc.C2, sc.crate};
+}
+
+// an electron's rates at the local neutral density nl [m^-3]
+__device__ __forceinline__ Rates local_rates(const SegConst &sc, double nl)
+{
+    const double c0 = (nl * sc.sig_el) * sc.dxm;
+    const double c1 = (nl * (sc.sig_el + sc.sig_ex)) * sc.dxm;
+    const double c2 = (nl * ((sc.sig_el + sc.sig_ex) + sc.sig_iz)) * sc.dxm;
+    return Rates{c0 * c0, c1 * c1, c2 * c2, ((nl * sc.sig_iz) * sc.dxm) * sc.vcap_hat};
+}
+
+__device__ __forceinline__ void collide_vel(const SegConst &sc, const Rates &R, long long step,
                                             unsigned long long pid, double &vx, double &vy,
                                             double &vz, uint32_t (&cnt)[kNCnt], bool &iz,
                                             double &g2)
@@ -188,7 +209,8 @@ __device__ __forceinline__ void collide_vel(const SegConst &sc, long long step,
     const double r = u01(u.y) * sc.nu_max;
     const double r2 = r * r;
     if (sc.kind == PIC_KIND_ELECTRON) {
-        if (r2 < sc.C0 * v2) {
+        bool hit = false;
+        if (r2 < R.C0 * v2) {
             double d0, d1, d2;
             iso_dir(u.z, u.w, d0, d1, d2);
             const double gg = sqrt(v2);
@@ -196,7 +218,25 @@ __device__ __forceinline__ void collide_vel(const SegConst &sc, long long step,
             vy = sc.am * vy + sc.bm * gg * d1;
             vz = sc.am * vz + sc.bm * gg * d2;
             cnt[kCEl] += 1;
-        } else if (v2 >= sc.v2_iz && r2 < sc.C1 * v2) {
+        } else if (r2 < R.C1 * v2) {
+            if (v2 >= sc.v2_ex) {
+                double d0, d1, d2;
+                iso_dir(u.z, u.w, d0, d1, d2);
+                const double gg = sqrt(v2 - sc.v2_ex);
+                vx = gg * d0;
+                vy = gg * d1;
+                vz = gg * d2;
+                cnt[kCEx] += 1;
+            }
+        } else if (v2 >= sc.v2_iz) {
+            if (sc.rate_iz) {
+                const double rr = r - R.crate;
+                hit = rr < 0.0 || rr * rr < R.C1 * v2;
+            } else {
+                hit = r2 < R.C2 * v2;
+            }
+        }
+        if (hit) {
             const uint4 u1 = draw(pid, step, 1, sc.key0, sc.key1);
             const double e_tot = 0.5 * v2 - sc.eps_iz;
             const double e1 = u01(u.z) * e_tot;
@@ -212,7 +252,7 @@ __device__ __forceinline__ void collide_vel(const SegConst &sc, long long step,
             cnt[kCIz] += 1;
         }
     } else {
-        if (r2 < sc.C0 * v2) {
+        if (r2 < R.C0 * v2) {
             const uint4 u1 = draw(pid, step, 1, sc.key0, sc.key1);
             double n0, n1, n2, n3;
             box_muller(u.z, u.w, n0, n1);

@@ -94,7 +94,7 @@ __global__ __launch_bounds__(kBlock) void diag_final_kernel(Dev d, int n_blocks)
         }
     }
     unsigned long long pc[kNCnt] = {idn.n_candidates, idn.n_elastic, idn.n_ionize, idn.n_cx,
-                                    idn.n_over_cap};
+                                    idn.n_over_cap, idn.n_excite};
     if (d.n_seg <= kCntSegMax) {
         for (int q = 0; q < kNCnt; ++q) {
             double a = 0.0;  // exact: counts stay far below 2^53
@@ -134,6 +134,9 @@ __global__ __launch_bounds__(kBlock) void diag_final_kernel(Dev d, int n_blocks)
     o.n_ionize = (int64_t)pc[2];
     o.n_cx = (int64_t)pc[3];
     o.n_over_cap = (int64_t)pc[4];
+    o.n_excite = (int64_t)pc[5];
+    o.n_consumed = (int64_t)idn.n_consumed;
+    o.n_iz_untargeted = (int64_t)idn.n_iz_untargeted;
     o.n_source = (int64_t)idn.n_source;
     o.particle_steps = (int64_t)idn.particle_steps;
     d.diag_out[i] = o;

@@ -21,6 +21,13 @@
 //      top; backward sweep (phi), then E, the accelerations, the field energy.
 // Same recurrences as the sequential sweep, regrouped; only the rounding
 // order differs.
+//
+// The first launch also forms the node density of a kinetic neutral species,
+//   n_j = w_n S_n[j] 2^-32 / V_j,
+// which the collisions gather at the electrons.  An instance without a field
+// solve (the paper's Table 1 case) gets E = phi = 0; when no instance solves
+// the field, the first launch alone runs (rho, the neutral density, the
+// deposit cleared).
 #include "device_common.h"
 
 #pragma clang fp contract(off)
@@ -110,9 +117,15 @@ __device__ __forceinline__ double gq_of(int64_t j)
 // ---------------------------------------------------------------------------
 // 1. rho and the forward composite of every tile
 // ---------------------------------------------------------------------------
-// from_rho: rho is already in place (smoothed); only the composites are formed
-__global__ __launch_bounds__(kBlock) void field_rho_kernel(Dev d, int from_rho)
+enum { kRhoSolve = 0, kRhoFromRho = 1, kRhoNoSolve = 2 };
+
+// mode kRhoSolve: rho (and the neutral density) from the deposit, and the
+// composites; kRhoFromRho: rho is already in place (smoothed), only the
+// composites; kRhoNoSolve: rho and the neutral density, the deposit cleared,
+// no composites (no instance solves the field)
+__global__ __launch_bounds__(kBlock) void field_rho_kernel(Dev d, int mode)
 {
+    const bool from_rho = (mode == kRhoFromRho);
     const int64_t vt = blockIdx.x;
     const int inst = seg_of_tile(d.inst_ftile0, d.n_inst, vt);
     const InstConst &ic = d.instc[inst];
@@ -145,6 +158,10 @@ __global__ __launch_bounds__(kBlock) void field_rho_kernel(Dev d, int from_rho)
             }
             continue;
         }
+        // without a solve the deposit is cleared in this launch: on a periodic
+        // grid node 0's thread also writes node nc (the same node) and no
+        // thread reads node nc's deposit after it is cleared
+        if (mode == kRhoNoSolve && periodic && j == nc) continue;
         double acc = 0.0;
         for (int k = 0; k < nsp; ++k) {
             const unsigned long long *S = d.S + k * G + ic.gnode;
@@ -159,11 +176,44 @@ __global__ __launch_bounds__(kBlock) void field_rho_kernel(Dev d, int from_rho)
         if (!periodic && (j == 0 || j == nc)) V = 0.5 * ic.dx;
         const double rho = acc / V + rho_bg;
         d.rho[ic.gnode + j] = rho;
+        if (mode == kRhoNoSolve && periodic && j == 0) d.rho[ic.gnode + nc] = rho;
+        if (d.kinetic_any) {
+            double n = 0.0;
+            if (ic.seg_n >= 0) {
+                const SegConst &sn = d.segc[ic.seg_n];
+                const unsigned long long *S = d.S + (int64_t)sn.sp * G + ic.gnode;
+                unsigned long long Sj = S[j];
+                if (periodic) {
+                    if (j == 0) Sj += S[nc];
+                    if (j == nc) Sj = S[0] + S[nc];
+                }
+                n = (sn.w * ((double)Sj * two_m32)) / V;
+            }
+            d.nn[ic.gnode + j] = n;
+            if (mode == kRhoNoSolve && periodic && j == 0) d.nn[ic.gnode + nc] = n;
+        }
+        if (mode == kRhoNoSolve) continue;
         if (j >= 1 && j <= nc - 1) {
             const double dd = -(rho * ic.K);
             const double gq = gq_of(j);
             m = compose(Aff{gq, -(gq * dd)}, m);
         }
+    }
+    if (mode == kRhoNoSolve) {
+        // the deposit is consumed; E, phi and the accelerations stay zero
+        // (cleared at set-up, never written in this mode)
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kFieldR; ++r) {
+            const int64_t j = j0 + r;
+            if (j > nc || (periodic && j == nc)) continue;
+            for (int k = 0; k < nsp; ++k) {
+                d.S[k * G + ic.gnode + j] = 0ull;
+                if (periodic && j == 0) d.S[k * G + ic.gnode + nc] = 0ull;
+            }
+        }
+        if (threadIdx.x == 0) d.fe_part[vt] = 0.0;
+        return;
     }
     Aff agg;
     (void)block_exclusive_scan(m, &agg);
@@ -333,7 +383,8 @@ __global__ __launch_bounds__(kBlock) void field_bwd_kernel(Dev d)
             E = -(pc - pl) / dx + d.rho[ic.gnode + nc] * dx / (2.0 * ic.eps0);
             V = 0.5 * dx;
         }
-        d.phi[ic.gnode + j] = pc;
+        if (ic.field_off) E = 0.0;  // no field solve in this instance
+        d.phi[ic.gnode + j] = ic.field_off ? 0.0 : pc;
         if (!(periodic && j == nc)) {
             d.E[ic.gnode + j] = E;
             fe += E * E * V;
@@ -379,7 +430,7 @@ __global__ __launch_bounds__(kBlock) void field_smooth_kernel(Dev d, const doubl
     const int64_t j = g - ic.gnode;
     const int nc = ic.nc;
     const bool periodic = (ic.bc == PIC_BC_PERIODIC);
-    const int passes = ic.smooth_passes;
+    const int passes = ic.field_off ? 0 : ic.smooth_passes;
     if (pass >= passes) {  // not smoothed this pass: carry the value through
         out[g] = in[g];
         return;
@@ -404,7 +455,11 @@ __global__ __launch_bounds__(kBlock) void field_smooth_kernel(Dev d, const doubl
 hipError_t launch_field(const Dev &d, hipStream_t st, int smooth)
 {
     const dim3 grid((unsigned)d.n_field_tiles), block(kBlock);
-    hipLaunchKernelGGL(field_rho_kernel, grid, block, 0, st, d, 0);
+    if (d.field_all_off) {
+        hipLaunchKernelGGL(field_rho_kernel, grid, block, 0, st, d, (int)kRhoNoSolve);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(field_rho_kernel, grid, block, 0, st, d, (int)kRhoSolve);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (smooth > 0) {
@@ -425,7 +480,7 @@ hipError_t launch_field(const Dev &d, hipStream_t st, int smooth)
             e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
-        hipLaunchKernelGGL(field_rho_kernel, grid, block, 0, st, d, 1);
+        hipLaunchKernelGGL(field_rho_kernel, grid, block, 0, st, d, (int)kRhoFromRho);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -2,15 +2,20 @@
 // Monte Carlo collisions and ionisation, plasma-wall interaction) on gfx950.
 //
 // Null-collision Monte Carlo (Vahedi & Surendra, CPC 87, 1995) against a
-// uniform neutral gas.  The push kernel already tested every particle with
-// one Philox block keyed by (id, step) and listed the candidates with their
+// uniform neutral gas, or against kinetic neutral atoms (the paper's Table 1
+// case, Sec. 3.4).  The push kernel already tested every particle with one
+// Philox block keyed by (id, step) and listed the candidates with their
 // velocities and ids; here each candidate redraws that block (collide_vel),
-// picks a process from r = U(u1) nu_max against
-// the cumulative n_n sigma |v| (squared comparisons, FP64), and applies
+// picks a process from r = U(u1) nu_max against the cumulative n sigma |v|
+// (squared comparisons, FP64; n is the gas density or the atom density
+// gathered at the electron), and applies
 //   elastic e-n   cold neutral of mass M, isotropic in the centre of mass;
+//   excitation    the electron loses E_ex and leaves isotropically;
 //   charge exch.  the ion takes a neutral's Maxwellian velocity (T_n);
 //   ionisation    energy above threshold split U : 1-U between two isotropic
-//                 electrons, the new ion Maxwellian at T_n, pair at the parent.
+//                 electrons; the new ion is Maxwellian at T_n at the parent,
+//                 or, with kinetic neutrals, a consumed atom of the parent's
+//                 cell (the target kernel picks it).
 // The emit kernel then creates the ionisation pairs (ids ranked by parent id)
 // and the source pairs (as many as ions reached the walls this step) and
 // deposits them; a one-block kernel closes the step (counts, ids, step index).
@@ -42,8 +47,30 @@ __device__ __forceinline__ int collide_one(const Dev &d, int cur, bool f64, cons
     const long long step = d.instd[sc.inst].step;
     double vx = c.vx, vy = c.vy, vz = c.vz;
     double g2 = 0.0;
-    collide_vel(sc, step, c.pid, vx, vy, vz, cnt, iz, g2);
-    if (cnt[kCEl] | cnt[kCIz] | cnt[kCCx]) {
+    // with kinetic neutrals: the atom density at the electron (the mover's
+    // linear weights on the node densities of the last field pass)
+    int32_t cell = 0;
+    Rates R;
+    if (sc.kinetic) {
+        double f;
+        if (f64) {
+            const double x = ((const double *)d.x[cur])[g];
+            const double jd = floor(x);
+            cell = (int32_t)jd;
+            f = x - jd;
+        } else {
+            cell = d.cell[cur][g];
+            f = (double)((const float *)d.x[cur])[g];
+        }
+        const double *nn = d.nn + sc.gnode;
+        const double nl = fma(f, nn[cell + 1] - nn[cell], nn[cell]);
+        if (nl > sc.n_bound) atomicOr(&d.instd[sc.inst].status, PIC_ST_NN_CAP);
+        R = local_rates(sc, nl);
+    } else {
+        R = uniform_rates(sc);
+    }
+    collide_vel(sc, R, step, c.pid, vx, vy, vz, cnt, iz, g2);
+    if (cnt[kCEl] | cnt[kCIz] | cnt[kCCx] | cnt[kCEx]) {
         st_v(d.vx[cur], g, vx, f64);
         st_v(d.vy[cur], g, vy, f64);
         st_v(d.vz[cur], g, vz, f64);
@@ -53,6 +80,7 @@ __device__ __forceinline__ int collide_one(const Dev &d, int cur, bool f64, cons
         ev.slot = (uint32_t)g;
         ev.seg = seg;
         ev.inst = sc.inst;
+        ev.cell = cell;
         ev.g2 = g2;
     }
     return seg;
@@ -65,6 +93,7 @@ __device__ __forceinline__ void add_counts(InstDyn *idn, const uint32_t (&c)[kNC
     if (c[kCIz]) atomicAdd(&idn->n_ionize, (unsigned long long)c[kCIz]);
     if (c[kCCx]) atomicAdd(&idn->n_cx, (unsigned long long)c[kCCx]);
     if (c[kCOver]) atomicAdd(&idn->n_over_cap, (unsigned long long)c[kCOver]);
+    if (c[kCEx]) atomicAdd(&idn->n_excite, (unsigned long long)c[kCEx]);
 }
 
 __global__ __launch_bounds__(kBlock) void collide_kernel(Dev d)
@@ -88,7 +117,7 @@ __global__ __launch_bounds__(kBlock) void collide_kernel(Dev d)
     const uint32_t o_hi = min(novf, o_lo + per_block);
     const uint32_t n_items = nr + (o_hi - o_lo);
     for (uint32_t q = threadIdx.x; q < n_items; q += kBlock) {
-        uint32_t cnt[kNCnt] = {0, 0, 0, 0, 0};
+        uint32_t cnt[kNCnt] = {0, 0, 0, 0, 0, 0};
         bool iz = false;
         IzEvent ev = {};
         const int64_t idx = q < nr ? (int64_t)blockIdx.x * d.cand_q + q
@@ -260,9 +289,10 @@ __device__ __forceinline__ uint32_t source_pairs(const Dev &d, int i)
 }
 
 // Rank of every ionisation event among the events of its instance, ordered
-// by parent id: ev_rank[e] = #{k : inst_k == inst_e, pid_k < pid_e}.  The
-// pairs (event block of kBlock, comparison block of kRankJ) are spread over
-// the grid; each adds its partial count to ev_rank (zero at entry).
+// by parent id: ev_rank[e] = #{k : inst_k == inst_e, pid_k < pid_e}, and,
+// with kinetic neutrals, among those of its cell too (ev_crank).  The pairs
+// (event block of kBlock, comparison block of kRankJ) are spread over the
+// grid; each adds its partial counts to ev_rank / ev_crank (zero at entry).
 __global__ __launch_bounds__(kBlock) void rank_kernel(Dev d)
 {
     __shared__ EventIndex X;
@@ -272,20 +302,24 @@ __global__ __launch_bounds__(kBlock) void rank_kernel(Dev d)
     const uint64_t nj = (m + kRankJ - 1) / kRankJ;
     __shared__ unsigned long long s_pid[kRankJ];
     __shared__ int s_inst[kRankJ];
+    __shared__ int s_cell[kRankJ];
+    const bool cells = d.kinetic_any != 0;
     for (uint64_t p = blockIdx.x; p < ni * nj; p += gridDim.x) {
         const uint64_t bi = p / nj, bj = p - bi * nj;
         __syncthreads();
         if (threadIdx.x < kRankJ) {
             const uint64_t k = bj * kRankJ + threadIdx.x;
             unsigned long long pid = ~0ull;
-            int inst = -2;
+            int inst = -2, cell = -1;
             if (k < m) {
                 const IzEvent &o = event_at(X, d, (uint32_t)k);
                 pid = o.parent_id;
                 inst = o.inst;
+                cell = o.cell;
             }
             s_pid[threadIdx.x] = pid;
             s_inst[threadIdx.x] = inst;
+            s_cell[threadIdx.x] = cell;
         }
         __syncthreads();
         const uint64_t e = bi * kBlock + threadIdx.x;
@@ -297,8 +331,161 @@ __global__ __launch_bounds__(kBlock) void rank_kernel(Dev d)
 #pragma unroll 16
             for (int q = 0; q < kRankJ; ++q) r += (s_inst[q] == inst && s_pid[q] < pid) ? 1u : 0u;
             if (r) atomicAdd(&d.ev_rank[e], r);
+            if (cells) {
+                const int cell = ev.cell;
+                uint32_t rc = 0;
+                for (int q = 0; q < kRankJ; ++q)
+                    rc += (s_inst[q] == inst && s_cell[q] == cell && s_pid[q] < pid) ? 1u : 0u;
+                if (rc) atomicAdd(&d.ev_crank[e], rc);
+            }
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Kinetic neutrals: the atom each ionisation event consumes.  Event e of
+// instance i in cell j, with rank q among the events of (i, j), takes the
+// (q+1)-th smallest (key, id) among the live atoms in cell j, where key is
+// (w0 << 32 | w1) of the atom's Philox block (id, step, 3).  One wave per
+// event.  The atoms of cell j are looked up through the cell offsets of the
+// last sort over the cells within reach of j: an atom's velocity does not
+// change between sorts, so none has moved farther than vmax (steps since the
+// sort + nstep) cells.  With no sort yet, or a reach of half the grid, the
+// whole species is searched.
+// ---------------------------------------------------------------------------
+struct KeyId {
+    unsigned long long key, id;
+    long long slot;
+};
+
+__device__ __forceinline__ bool key_less(const KeyId &a, const KeyId &b)
+{
+    return a.key < b.key || (a.key == b.key && a.id < b.id);
+}
+
+__device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v, int o)
+{
+    const uint32_t lo = __shfl_xor((uint32_t)v, o, 64);
+    const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), o, 64);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ KeyId wave_min_key(KeyId v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        KeyId w;
+        w.key = shfl_xor_u64(v.key, o);
+        w.id = shfl_xor_u64(v.id, o);
+        w.slot = (long long)shfl_xor_u64((unsigned long long)v.slot, o);
+        if (key_less(w, v)) v = w;
+    }
+    return v;
+}
+
+__global__ __launch_bounds__(kBlock) void target_kernel(Dev d)
+{
+    __shared__ EventIndex X;
+    build_event_index(X, d);
+    const int cur = d.glob->cur_set;
+    const bool f64 = (d.precision == PIC_FP64);
+    const uint32_t since = d.glob->since_sort;
+    const int lane = lane_id();
+    const uint32_t n_waves = gridDim.x * kWaves;
+    for (uint32_t e = blockIdx.x * kWaves + (threadIdx.x >> 6); e < X.total; e += n_waves) {
+        const IzEvent &ev = event_at(X, d, e);
+        const InstConst &ic = d.instc[ev.inst];
+        long long target = -1;
+        if (ic.seg_n >= 0) {
+            const SegConst &sn = d.segc[ic.seg_n];
+            const long long step = d.instd[ev.inst].step;
+            const int64_t nc = ic.nc;
+            const int64_t j = ev.cell;
+            const uint32_t q = d.ev_crank[e];
+            // in-segment slot ranges [a0, b0) and [a1, b1) to search
+            int64_t a0 = 0, b0 = d.segd[ic.seg_n].count, a1 = 0, b1 = 0;
+            if (since != kNoIndex) {
+                const double vmax = __longlong_as_double((long long)d.segd[ic.seg_n].vmax_bits);
+                const double reach = vmax * ((double)since + sn.ms);
+                if (reach < 0.25 * (double)nc) {
+                    const int64_t W = (int64_t)floor(reach) + 1;
+                    const uint32_t *off = d.offsets + (int64_t)sn.sp * d.G + sn.gnode;
+                    int64_t lo = j - W, hi = j + W;  // cells, inclusive
+                    if (ic.bc == PIC_BC_PERIODIC) {
+                        if (lo < 0) {
+                            a0 = off[lo + nc]; b0 = off[nc]; a1 = 0; b1 = off[hi + 1];
+                        } else if (hi >= nc) {
+                            a0 = off[lo]; b0 = off[nc]; a1 = 0; b1 = off[hi + 1 - nc];
+                        } else {
+                            a0 = off[lo]; b0 = off[hi + 1];
+                        }
+                    } else {
+                        lo = lo < 0 ? 0 : lo;
+                        hi = hi > nc - 1 ? nc - 1 : hi;
+                        a0 = off[lo]; b0 = off[hi + 1];
+                    }
+                }
+            }
+            KeyId prev = {0ull, 0ull, -1};
+            for (uint32_t r = 0; r <= q; ++r) {
+                KeyId best = {~0ull, ~0ull, -1};
+                for (int part = 0; part < 2; ++part) {
+                    const int64_t a = part ? a1 : a0, b = part ? b1 : b0;
+                    for (int64_t i = a + lane; i < b; i += 64) {
+                        const int64_t g = sn.base + i;
+                        int64_t cj;
+                        if (f64) {
+                            const double x = ((const double *)d.x[cur])[g];
+                            cj = x >= 0.0 ? (int64_t)x : -1;
+                        } else {
+                            cj = d.cell[cur][g];
+                        }
+                        if (cj != j) continue;
+                        const unsigned long long id = d.id[cur][g];
+                        const uint4 u = draw(id, step, 3, sn.key0, sn.key1);
+                        const KeyId k = {((unsigned long long)u.x << 32) | u.y, id, (long long)g};
+                        if ((r == 0 || key_less(prev, k)) && key_less(k, best)) best = k;
+                    }
+                }
+                best = wave_min_key(best);
+                if (best.slot < 0) {
+                    target = -1;
+                    break;
+                }
+                prev = best;
+                target = best.slot;
+            }
+        }
+        if (lane == 0) d.ev_target[e] = target;
+    }
+}
+
+// the consumed atom at slot t leaves its segment: marked absorbed, its share
+// of the deposit taken back (it was deposited by this step's push)
+__device__ __forceinline__ void consume_atom(const Dev &d, int cur, bool f64, int seg_n, int64_t t)
+{
+    const SegConst &sn = d.segc[seg_n];
+    unsigned long long *S = d.S + (int64_t)sn.sp * d.G + sn.gnode;
+    int j;
+    unsigned long long w1;
+    if (f64) {
+        double *X = (double *)d.x[cur];
+        const double x = X[t];
+        const double jn = floor(x);
+        j = (int)jn;
+        w1 = (unsigned long long)rint(ldexp(x - jn, PIC_FRAC_BITS));
+        X[t] = kDeadX;
+    } else {
+        const float f = ((const float *)d.x[cur])[t];
+        j = d.cell[cur][t];
+        w1 = (unsigned long long)rintf(f * 4294967296.0f);
+        d.cell[cur][t] = kDeadCell;
+    }
+    const unsigned long long w0 = (1ull << PIC_FRAC_BITS) - w1;
+    if (w0) atomicAdd(S + j, 0ull - w0);
+    if (w1) atomicAdd(S + j + 1, 0ull - w1);
+    atomicAdd(&d.segd[seg_n].consumed_step, 1u);
+    atomicAdd(&d.instd[sn.inst].n_consumed, 1ull);
 }
 
 __global__ __launch_bounds__(kBlock) void emit_kernel(Dev d)
@@ -339,8 +526,31 @@ __global__ __launch_bounds__(kBlock) void emit_kernel(Dev d)
             }
             place(d, cur, f64, ev.seg, (int64_t)d.segd[ev.seg].count + rank, nid, cell, f, x,
                   ev.g2 * d0, ev.g2 * d1, ev.g2 * d2);
+            // the ion: Maxwellian at the parent, or the consumed atom itself
+            double ivx = si.sig_n * n0, ivy = si.sig_n * n1, ivz = si.sig_n * n2;
+            const int seg_n = d.instc[ev.inst].seg_n;
+            if (seg_n >= 0) {
+                const long long t = d.ev_target[e];
+                if (t >= 0) {
+                    if (f64) {
+                        x = ((const double *)d.x[cur])[t];
+                        ivx = ((const double *)d.vx[cur])[t];
+                        ivy = ((const double *)d.vy[cur])[t];
+                        ivz = ((const double *)d.vz[cur])[t];
+                    } else {
+                        cell = d.cell[cur][t];
+                        f = ((const float *)d.x[cur])[t];
+                        ivx = (double)((const float *)d.vx[cur])[t];
+                        ivy = (double)((const float *)d.vy[cur])[t];
+                        ivz = (double)((const float *)d.vz[cur])[t];
+                    }
+                    consume_atom(d, cur, f64, seg_n, t);
+                } else {
+                    atomicAdd(&d.instd[ev.inst].n_iz_untargeted, 1ull);
+                }
+            }
             place(d, cur, f64, seg_i, (int64_t)d.segd[seg_i].count + rank, nid + 1ull, cell, f, x,
-                  si.sig_n * n0, si.sig_n * n1, si.sig_n * n2);
+                  ivx, ivy, ivz);
         }
     }
 
@@ -424,9 +634,10 @@ __global__ __launch_bounds__(kBlock) void close_step_kernel(Dev d, int with_even
             if (n_new > sc.cap) n_new = sc.cap;
             // created = the slots below capacity that were filled
             const uint32_t created = (uint32_t)(n_new - sd->count);
-            const uint32_t lost = sd->absorbed_step[0] + sd->absorbed_step[1];
+            const uint32_t lost = sd->absorbed_step[0] + sd->absorbed_step[1] + sd->consumed_step;
             sd->count = (uint32_t)n_new;
             sd->live = sd->live - lost + created;
+            sd->consumed_step = 0;
             sd->absorbed_total[0] += sd->absorbed_step[0];
             sd->absorbed_total[1] += sd->absorbed_step[1];
             sd->created_total += created;
@@ -442,10 +653,15 @@ __global__ __launch_bounds__(kBlock) void close_step_kernel(Dev d, int with_even
     if (threadIdx.x == 0) {
         d.glob->cand_ovf = 0;
         d.glob->ev_ovf = 0;
+        const uint32_t s = d.glob->since_sort;
+        if (s != kNoIndex && s < kNoIndex - 1u) d.glob->since_sort = s + 1u;
     }
     // ranks back to zero for the next step
     if (with_events)
-        for (uint32_t e = threadIdx.x; e < X.total; e += kBlock) d.ev_rank[e] = 0u;
+        for (uint32_t e = threadIdx.x; e < X.total; e += kBlock) {
+            d.ev_rank[e] = 0u;
+            d.ev_crank[e] = 0u;
+        }
     // empty event regions for a step without collisions
     if (!with_events)
         for (int b = threadIdx.x; b < d.n_push_blocks; b += kBlock) d.ev_n[b] = 0u;
@@ -462,8 +678,13 @@ hipError_t launch_emit(const Dev &d, hipStream_t st, bool pairs, bool events)
 {
     if (events) {
         hipLaunchKernelGGL(rank_kernel, dim3(kRankBlocks), dim3(kBlock), 0, st, d);
-        const hipError_t e = hipGetLastError();
+        hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
+        if (d.kinetic_any) {
+            hipLaunchKernelGGL(target_kernel, dim3(kTargetBlocks), dim3(kBlock), 0, st, d);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
     }
     if (pairs) {
         hipLaunchKernelGGL(emit_kernel, dim3(kEmitBlocks), dim3(kBlock), 0, st, d);

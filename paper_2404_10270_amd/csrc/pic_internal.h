@@ -27,9 +27,11 @@ constexpr int kMaxPushBlocks = 256 * 8;     // persistent grid of the particle k
 constexpr int kCandQMin = 1024;             // least candidate entries per push block region
 constexpr int kEvQMin = 32;                 // least ionisation-event slots per collide block
 constexpr int kCntSegMax = 1024;           // segments counted per block in LDS (no atomics)
-constexpr int kNCnt = 5;                    // candidates, elastic, ionisation, CX, over v_cap
+constexpr int kNCnt = 6;                    // candidates, elastic, ionisation, CX, over v_cap, excitation
 constexpr int kRankJ = 64;                  // events compared per block pass of the rank kernel
 constexpr int kRankBlocks = 512;            // grid of the rank kernel
+constexpr int kTargetBlocks = 64;           // grid of the neutral-target kernel (a wave per event)
+constexpr uint32_t kNoIndex = 0xFFFFFFFFu;  // steps since the last sort: no sort yet
 
 constexpr int32_t kDeadCell = -1;           // FP32 form: cell of an absorbed particle
 constexpr double kDeadX = -1.0;             // FP64 form: position of an absorbed particle
@@ -53,8 +55,18 @@ struct SegConst {
     float msf;
     // null-collision MCC (rates per step, speeds in cells/step)
     uint64_t T;         // candidate threshold floor(P 2^32), 0..2^32
-    double nu_max, C0, C1;          // nu_max = c1 vcap; C0 = c0^2, C1 = c1^2
-    double vcap2, v2_iz, eps_iz;
+    double nu_max;      // (n_n sig_all) dx vcap
+    double C0, C1, C2;  // squares of the cumulative (n sig) dx: elastic, +excitation, +ionisation
+    double crate;       // (n_n sig_iz) dx vcap: the constant-rate ionisation slot
+    double vcap2, v2_iz, eps_iz, v2_ex;
+    double vcap_hat;
+    // kinetic neutrals: cross sections and dx (m) for the rates at the local density
+    double sig_el, sig_ex, sig_iz, dxm, n_bound;
+    int32_t kinetic;    // the instance has a kinetic neutral species (electron rates are local)
+    int32_t rate_iz;    // PIC_XS_IZ_RATE
+    int32_t force;      // 0: no field acts (q = 0 or the instance's field is off): no gather
+    int32_t _pad1;
+    double w;           // macro weight (real particles per macro-particle per unit area)
     double am, bm;      // m/(m+M), M/(m+M) (elastic, cold neutral of mass M)
     double sig_n;       // neutral Maxwellian sqrt(T_n/m_s) in cells/step (CX, new ions)
     double sig_src;     // source Maxwellian sqrt(T_src/m_s) in cells/step
@@ -76,7 +88,10 @@ struct InstConst {
     double dx, eps0, K; // K = dx^2 / eps0
     double init_amp;    // drawn initial state: perturbation amplitude, mode, PIC_INIT_OPT_*
     int32_t init_mode, init_opts;
-    int32_t smooth_passes, _pad;
+    int32_t smooth_passes;
+    int32_t field_off;  // no field solve (E = 0)
+    int32_t seg_n;      // segment of the kinetic neutral species, or -1
+    int32_t _pad;
 };
 
 // dynamic per-segment counters
@@ -85,9 +100,10 @@ struct SegDyn {
     uint32_t live;
     uint32_t absorbed_step[2];
     uint32_t created_step;   // particles placed this step
-    uint32_t _pad;
+    uint32_t consumed_step;  // kinetic neutrals consumed by ionisation this step
     unsigned long long absorbed_total[2];
     unsigned long long created_total;
+    unsigned long long vmax_bits;  // kinetic neutrals: bits of max |vx| (double) at the last sort
 };
 
 // dynamic per-instance counters
@@ -100,13 +116,15 @@ struct InstDyn {
     unsigned long long n_candidates, n_elastic, n_ionize, n_cx, n_over_cap;
     unsigned long long n_source;
     unsigned long long particle_steps;
+    unsigned long long n_consumed, n_iz_untargeted, n_excite;
 };
 
 struct Globals {
     int32_t cur_set;
     uint32_t cand_ovf;       // candidates in the overflow list this step
     uint32_t ev_ovf;         // ionisation events in the overflow list this step
-    uint32_t pad[5];
+    uint32_t since_sort;     // steps closed since the last sort (kNoIndex: none yet)
+    uint32_t pad[4];
     // self-resetting single-pass scan (the sort): ticket counter, finish counter, generation
     uint32_t scan_ticket[4];
     uint32_t scan_finish[4];
@@ -130,7 +148,7 @@ struct IzEvent {
     uint32_t slot;          // parent slot (global)
     int32_t seg;            // parent segment
     int32_t inst;           // parent instance
-    int32_t _pad;
+    int32_t cell;           // parent cell (in-instance)
     double g2;              // speed of the secondary electron, cells/step
 };
 
@@ -150,6 +168,7 @@ struct Layout {
     uint64_t fwd_status, bwd_status, sort_status;
     uint64_t fe_part;
     uint64_t cand, cand_n, ev, ev_n, ev_rank, cnt_slot;
+    uint64_t nn, ev_crank, ev_target;
     uint64_t diag_part, diag_out;
     uint64_t total;
     int64_t cand_ovf_cap, ev_ovf_cap;
@@ -189,6 +208,9 @@ struct Dev {
     IzEvent *ev;                // [n_push_blocks][ev_q] per-block regions, then the overflow list
     uint32_t *ev_n;             // [n_push_blocks] events in each region
     uint32_t *ev_rank;          // [events] rank of each event among its instance's (by parent id)
+    uint32_t *ev_crank;         // [events] rank among the events of its instance and cell
+    long long *ev_target;       // [events] slot of the atom an event consumes, or -1
+    double *nn;                 // [G] density of the kinetic neutrals [m^-3]
     unsigned long long *cnt_slot;  // [n_push_blocks][n_seg][kNCnt] process counts per block
     double *diag_part;
     pic_diag *diag_out;
@@ -196,8 +218,11 @@ struct Dev {
     int64_t n_slots, n_tiles, G, cand_ovf_cap, ev_ovf_cap;
     int64_t n_field_tiles, n_sort_tiles;
     int32_t n_seg, n_inst, nsp, precision;
-    int32_t n_push_blocks, _pad;
+    int32_t n_push_blocks;
+    int32_t kinetic_any;        // some instance has a kinetic neutral species (with MCC on)
     int32_t cand_q, ev_q;       // entries per block region of the candidate and event lists
+    int32_t field_all_off;      // no instance solves the field
+    int32_t _pad;
 };
 
 // ---------------------------------------------------------------------------

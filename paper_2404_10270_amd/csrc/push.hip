@@ -314,6 +314,10 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
         // deposit is a launch of its own, deposit_kernel<true>)
         if (d.n_seg > kSegLds && still(d, seg)) continue;
 
+        // a species with no collision process takes no test (no id read, no
+        // draw); a species on which no field acts takes no gather
+        const bool test = MCC && d.segc[seg].T != 0ull;
+        const bool force = d.segc[seg].force != 0;
         // ---- loads of all chunks
         int32_t j[kPer];
         float f[kPer], vx[kPer], vy[kPer], vz[kPer];
@@ -341,7 +345,7 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
                 vx[k] = stream_ld(&VXt[o]);
                 vy[k] = stream_ld(&VYt[o]);
                 vz[k] = stream_ld(&VZt[o]);
-                if (MCC) pid[k] = stream_ld(&IDt[o]);
+                if (test) pid[k] = stream_ld(&IDt[o]);
             }
             lv[k] = j[k] >= 0;
         }
@@ -363,7 +367,7 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
             a0[k] = a1[k] = 0.f;
-            if (j[k] >= 0) {
+            if (force && j[k] >= 0) {
                 a0[k] = acc[j[k]];
                 a1[k] = acc[j[k] + 1];
             }
@@ -424,7 +428,7 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
             if (j[k] >= 0) {
                 key[k] = j[k];
                 w1[k] = (unsigned long long)rintf(fn * 4294967296.0f);
-                if (MCC) {
+                if (test) {
                     const uint4 u = draw(pid[k], step, 0, key0, key1);
                     cand[k] = (unsigned long long)u.x < T;
                 }
@@ -501,6 +505,8 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
         // a subcycled species between its pushes keeps its positions (their
         // deposit is a launch of its own, deposit_kernel<true>)
         if (d.n_seg > kSegLds && still(d, seg)) continue;
+        const bool test = MCC && d.segc[seg].T != 0ull;
+        const bool force = d.segc[seg].force != 0;
 
         double x[kPer], vx[kPer], vy[kPer], vz[kPer];
         unsigned long long pid[kPer];
@@ -522,7 +528,7 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
                 vx[k] = stream_ld(&VXt[o]);
                 vy[k] = stream_ld(&VYt[o]);
                 vz[k] = stream_ld(&VZt[o]);
-                if (MCC) pid[k] = stream_ld(&IDt[o]);
+                if (test) pid[k] = stream_ld(&IDt[o]);
             }
         }
         const SegConst &sc = d.segc[seg];
@@ -547,8 +553,10 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
                 const double jd = floor(x[k]);
                 const int32_t jj = (int32_t)jd;
                 fr[k] = x[k] - jd;
-                a0[k] = acc[jj];
-                a1[k] = acc[jj + 1];
+                if (force) {
+                    a0[k] = acc[jj];
+                    a1[k] = acc[jj + 1];
+                }
             }
         }
         int key[kPer];
@@ -600,7 +608,7 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
                 const double jn = floor(x[k]);
                 key[k] = (int)jn;
                 w1[k] = (unsigned long long)rint(ldexp(x[k] - jn, PIC_FRAC_BITS));
-                if (MCC) {
+                if (test) {
                     const uint4 u = draw(pid[k], step, 0, key0, key1);
                     cand[k] = (unsigned long long)u.x < T;
                 }

@@ -12,6 +12,9 @@
 //            bin's share with one global atomic per touched bin, and copies
 //            the particles to the other set
 //   finish   one block switches the current set and sets the counts
+// The scatter also records the largest |vx| of a kinetic neutral species:
+// atoms keep their velocity until the next sort, so it bounds how far any
+// of them can move from the cell the offsets list it in.
 // Segment starts come from the live counts, so absorbed particles need no bin.
 #include "device_common.h"
 
@@ -353,6 +356,26 @@ __global__ __launch_bounds__(kBlock) void sort_scatter_kernel(Dev d)
             }
             mv<unsigned long long>(d.id[nxt], d.id[cur], to, g);
         }
+        if (sc.kind == PIC_KIND_NEUTRAL) {
+            unsigned long long vb = 0ull;
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) {
+                if (key[k] < 0) continue;
+                const int64_t g = base + t0 + (int64_t)(wave * kPer + k) * 64 + lane;
+                const double v = f64 ? fabs(((const double *)d.vx[cur])[g])
+                                     : fabs((double)((const float *)d.vx[cur])[g]);
+                const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+                vb = b > vb ? b : vb;
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                const uint32_t lo = __shfl_xor((uint32_t)vb, o, 64);
+                const uint32_t hi = __shfl_xor((uint32_t)(vb >> 32), o, 64);
+                const unsigned long long w = ((unsigned long long)hi << 32) | lo;
+                vb = w > vb ? w : vb;
+            }
+            if (lane == 0 && vb) atomicMax(&d.segd[seg].vmax_bits, vb);
+        }
         // the next tile's window barrier orders the reuse of L.base
     }
 }
@@ -369,12 +392,18 @@ __global__ void sort_finish_kernel(Dev d)
         d.segd[s].live = n_live;
     }
     __syncthreads();
-    if (threadIdx.x == 0) d.glob->cur_set ^= 1;
+    if (threadIdx.x == 0) {
+        d.glob->cur_set ^= 1;
+        d.glob->since_sort = 0u;  // the cell offsets are current
+    }
 }
 
 __global__ void sort_start_kernel(Dev d)
 {
-    for (int s = threadIdx.x; s < d.n_seg; s += blockDim.x) d.seg_start[s] = seg_raw_start(d, s);
+    for (int s = threadIdx.x; s < d.n_seg; s += blockDim.x) {
+        d.seg_start[s] = seg_raw_start(d, s);
+        d.segd[s].vmax_bits = 0ull;
+    }
 }
 
 hipError_t launch_sort(const Dev &d, hipStream_t st)

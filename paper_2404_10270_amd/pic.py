@@ -26,13 +26,16 @@ PIC_E_CAPACITY, PIC_E_CFL, PIC_E_NONFINITE, PIC_E_STATE = -4, -5, -6, -7
 
 PIC_ST_CAPACITY, PIC_ST_CFL, PIC_ST_NONFINITE = 0x1, 0x2, 0x4
 PIC_ST_CANDIDATES, PIC_ST_INTERNAL, PIC_ST_BAD_INIT = 0x8, 0x10, 0x20
+PIC_ST_NN_CAP = 0x40
+PIC_XS_IZ_RATE = 0x1
 
 PIC_BC_PERIODIC, PIC_BC_ABSORB = 0, 1
-PIC_KIND_ELECTRON, PIC_KIND_ION = 0, 1
+PIC_KIND_ELECTRON, PIC_KIND_ION, PIC_KIND_NEUTRAL = 0, 1, 2
 PIC_FP32, PIC_FP64 = 0, 1
 
 PIC_R_DEPOSIT, PIC_R_RHO, PIC_R_PHI, PIC_R_EFIELD = 0, 1, 2, 3
 PIC_R_ACC64, PIC_R_ACC32, PIC_R_CELL_OFFSETS, PIC_R_NODE_BASE = 4, 5, 6, 7
+PIC_R_NEUTRAL_DENSITY = 8
 
 PIC_INIT_NO_FIELD = 0x1
 PIC_INIT_SORT = 0x2
@@ -63,7 +66,9 @@ class pic_config(C.Structure):
                 ("sig_iz", C.c_double), ("E_iz", C.c_double), ("sig_cx", C.c_double),
                 ("next_id", C.c_uint64), ("step0", C.c_int64),
                 ("init_amp", C.c_double), ("init_mode", C.c_int32), ("init_opts", C.c_uint32),
-                ("smooth_passes", C.c_int32), ("_pad2", C.c_int32)]
+                ("smooth_passes", C.c_int32), ("_pad2", C.c_int32),
+                ("sig_ex", C.c_double), ("E_ex", C.c_double), ("field_off", C.c_int32),
+                ("xs_flags", C.c_uint32)]
 
 
 class pic_sizes(C.Structure):
@@ -90,7 +95,8 @@ class pic_diag(C.Structure):
                 ("created_total", C.c_int64 * PIC_MAX_SPECIES),
                 ("n_candidates", C.c_int64), ("n_elastic", C.c_int64), ("n_ionize", C.c_int64),
                 ("n_cx", C.c_int64), ("n_over_cap", C.c_int64), ("n_source", C.c_int64),
-                ("particle_steps", C.c_int64)]
+                ("particle_steps", C.c_int64), ("n_excite", C.c_int64),
+                ("n_consumed", C.c_int64), ("n_iz_untargeted", C.c_int64)]
 
 
 class PicError(RuntimeError):
@@ -258,6 +264,8 @@ def make_config(wl, precision: int, capacities: Sequence[int], n_init: Sequence[
         m = wl.mcc
         c.n_n, c.T_n, c.sig_el, c.sig_iz, c.E_iz, c.sig_cx = (m.n_n, m.T_n, m.sig_el, m.sig_iz,
                                                               m.E_iz, m.sig_cx)
+        c.sig_ex, c.E_ex = getattr(m, "sig_ex", 0.0), getattr(m, "E_ex", 0.0)
+        c.xs_flags = PIC_XS_IZ_RATE if getattr(m, "iz_const_rate", False) else 0
     c.next_id = int(next_id)
     c.step0 = int(step0)
     c.init_amp = float(getattr(wl, "perturb_amp", 0.0))
@@ -265,6 +273,7 @@ def make_config(wl, precision: int, capacities: Sequence[int], n_init: Sequence[
     c.init_opts = ((PIC_INIT_OPT_QUIET if getattr(wl, "quiet", False) else 0)
                    | (PIC_INIT_OPT_PAIR if getattr(wl, "pair_start", False) else 0))
     c.smooth_passes = int(getattr(wl, "smooth_passes", 0))
+    c.field_off = 1 if getattr(wl, "field_off", False) else 0
     return c
 
 
@@ -407,7 +416,8 @@ class PicSim:
         torch = self.torch
         dt = {PIC_R_DEPOSIT: torch.int64, PIC_R_RHO: torch.float64, PIC_R_PHI: torch.float64,
               PIC_R_EFIELD: torch.float64, PIC_R_ACC64: torch.float64,
-              PIC_R_ACC32: torch.float32, PIC_R_CELL_OFFSETS: torch.int32}[region]
+              PIC_R_ACC32: torch.float32, PIC_R_CELL_OFFSETS: torch.int32,
+              PIC_R_NEUTRAL_DENSITY: torch.float64}[region]
         torch.cuda.synchronize()
         a = self.region(region, dt).cpu().numpy()
         if region == PIC_R_DEPOSIT:
