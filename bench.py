@@ -16,6 +16,8 @@ Prints one JSON line.  `value` = particles pushed per second over the K timed
 steps (every step runs push+deposit+candidate test, collisions, pairs and
 source, field solve, and a sort every 20 steps).  `roofline` is for the
 dominant kernel (the fused mover), timed with HIP events on its stream.
+Beside it: the FP64 form, 256 batched instances, and the paper's own Table 1
+test case (electrons, D+ ions and kinetic D atoms, no field solve).
 """
 from __future__ import annotations
 
@@ -216,6 +218,40 @@ def batched(torch, args):
     return out
 
 
+def table1_run(torch, args):
+    """The paper's Table 1 test case at full size (Sec. 3.4): electrons, D+ ions
+    and kinetic D atoms, 100,000 cells x 100 particles per cell per species (3e7
+    particles), 1 m, dt = 4e-14 s, periodic, no field solve; elastic, excitation
+    and ionisation against the atoms (stand-in cross sections); FP32 form, drawn
+    on the device and sorted, steps from a HIP graph with a sort every 20 steps.
+    The mover moves 48 B per electron (its id is read for the collision test)
+    and 40 B per ion or atom (no process, no id read)."""
+    import pic_inputs as pin
+    from paper_2404_10270_amd import pic as P
+    wl = pin.table1()
+    n = wl.n_particles
+    log(f"table1: {n} particles on {wl.nc} cells, drawn on the device")
+    sim = P.PicSim(wl, None, P.PIC_FP32, flags=P.PIC_INIT_DEVICE | P.PIC_INIT_SORT)
+    rate, ms_step, _ = run_form(torch, sim, args.table1_steps, args.warmup, graph=True)
+    d0, _ = sim.diagnostics()
+    push_ms, per_launch = time_push(torch, sim, args.push_steps)
+    d1, rc = sim.diagnostics()
+    if rc != 0:
+        raise RuntimeError(f"device status during the table1 run: {rc}")
+    live = [int(d1[0].n_live[k]) for k in range(3)]
+    bytes_launch = PUSH_BYTES_FP32 * live[0] + (PUSH_BYTES_FP32 - 8) * (live[1] + live[2])
+    gbs = bytes_launch / (push_ms * 1e-3) / 1e9
+    sim.close()
+    out = {"value": rate, "unit": "particle-steps/s", "particles": n, "cells": wl.nc,
+           "steps": args.table1_steps, "ms_per_step": round(ms_step, 4), "sort_every": SORT_EVERY,
+           "field_solve": "off", "mover_us": round(push_ms * 1e3, 2),
+           "mover_GBps": round(gbs, 1), "mover_frac": round(gbs / HBM_PEAK_GBS, 4),
+           "ionisations": int(d1[0].n_ionize), "atoms_consumed": int(d1[0].n_consumed)}
+    log(f"table1: {rate:.4e} p-steps/s, {ms_step:.4f} ms/step, mover {push_ms * 1e3:.1f} us "
+        f"({gbs:.0f} GB/s)")
+    return out
+
+
 def cpu_baseline(args):
     """The oracle as it stands, single thread, on a bounded sample of the workload."""
     import oracle
@@ -244,6 +280,10 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-instances", type=int, default=256)
     ap.add_argument("--batched-steps", type=int, default=60)
+    ap.add_argument("--no-table1", action="store_true")
+    ap.add_argument("--table1-steps", type=int, default=200)
+    ap.add_argument("--only-table1", action="store_true",
+                    help="run only the Table 1 workload and print its JSON object (profiling)")
     ap.add_argument("--eager", action="store_true",
                     help="enqueue the timed steps one by one instead of replaying a HIP graph")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -270,6 +310,9 @@ def main():
     if args.copy_calibration:
         copy_calibration()
         return
+    if args.only_table1:
+        print(json.dumps(table1_run(torch, args)), flush=True)
+        return
     wl = workload(args)
     log(f"generating {wl.n_particles} particles on {wl.nc} cells")
     st = pin.initial_state(wl)
@@ -288,7 +331,8 @@ def main():
     achieved = PUSH_BYTES_FP32 * per_launch / (push_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile(),
-            "kernel": "push_f32_kernel<true,1> (mover + deposit + candidate list)", "bytes_per_particle": PUSH_BYTES_FP32,
+            "kernel": "push_f32_kernel<true,true> (mover + deposit + candidate list)",
+            "bytes_per_particle": PUSH_BYTES_FP32,
             "particles_per_launch": int(per_launch), "us_per_launch": round(push_ms * 1e3, 2)}
 
     fp64 = None
@@ -308,6 +352,11 @@ def main():
     bat = None
     if not args.no_batched:
         bat = batched(torch, args)
+        torch.cuda.empty_cache()
+
+    t1 = None
+    if not args.no_table1:
+        t1 = table1_run(torch, args)
         torch.cuda.empty_cache()
 
     cpu = None
@@ -337,6 +386,7 @@ def main():
         "roofline": roof,
         "fp64_form": fp64,
         "batched_256": bat,
+        "table1": t1,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -203,6 +203,30 @@ __device__ void build_event_index(EventIndex &X, const Dev &d)
     __syncthreads();
 }
 
+// one block, once per step after the collisions: the prefix over the regions
+// and the totals, for every kernel after it
+__global__ __launch_bounds__(kBlock) void index_kernel(Dev d)
+{
+    __shared__ EventIndex X;
+    build_event_index(X, d);
+    for (int b = threadIdx.x; b <= d.n_push_blocks; b += kBlock) d.ev_pre[b] = X.pre[b];
+    if (threadIdx.x == 0) {
+        d.glob->ev_total = X.total;
+        d.glob->ev_in_regions = X.in_regions;
+    }
+}
+
+// the index index_kernel wrote, into LDS (all threads; a barrier inside)
+__device__ void load_event_index(EventIndex &X, const Dev &d)
+{
+    for (int b = threadIdx.x; b <= d.n_push_blocks; b += kBlock) X.pre[b] = d.ev_pre[b];
+    if (threadIdx.x == 0) {
+        X.total = d.glob->ev_total;
+        X.in_regions = d.glob->ev_in_regions;
+    }
+    __syncthreads();
+}
+
 __device__ __forceinline__ const IzEvent &event_at(const EventIndex &X, const Dev &d, uint32_t e)
 {
     if (e >= X.in_regions)
@@ -295,8 +319,14 @@ __device__ __forceinline__ uint32_t source_pairs(const Dev &d, int i)
 // grid; each adds its partial counts to ev_rank / ev_crank (zero at entry).
 __global__ __launch_bounds__(kBlock) void rank_kernel(Dev d)
 {
+    {
+        // blocks beyond the pairs of this step's events leave at once
+        const uint64_t m0 = d.glob->ev_total;
+        const uint64_t pairs = ((m0 + kBlock - 1) / kBlock) * ((m0 + kRankJ - 1) / kRankJ);
+        if (blockIdx.x >= pairs) return;
+    }
     __shared__ EventIndex X;
-    build_event_index(X, d);
+    load_event_index(X, d);
     const uint64_t m = X.total;
     const uint64_t ni = (m + kBlock - 1) / kBlock;
     const uint64_t nj = (m + kRankJ - 1) / kRankJ;
@@ -385,8 +415,9 @@ __device__ __forceinline__ KeyId wave_min_key(KeyId v)
 
 __global__ __launch_bounds__(kBlock) void target_kernel(Dev d)
 {
+    if ((uint64_t)blockIdx.x * kWaves >= d.glob->ev_total) return;  // no event for this block
     __shared__ EventIndex X;
-    build_event_index(X, d);
+    load_event_index(X, d);
     const int cur = d.glob->cur_set;
     const bool f64 = (d.precision == PIC_FP64);
     const uint32_t since = d.glob->since_sort;
@@ -491,7 +522,7 @@ __device__ __forceinline__ void consume_atom(const Dev &d, int cur, bool f64, in
 __global__ __launch_bounds__(kBlock) void emit_kernel(Dev d)
 {
     __shared__ EventIndex X;
-    build_event_index(X, d);
+    load_event_index(X, d);
     const int cur = d.glob->cur_set;
     const bool f64 = (d.precision == PIC_FP64);
     const uint32_t m_all = X.total;
@@ -611,7 +642,7 @@ __global__ __launch_bounds__(kBlock) void close_step_kernel(Dev d, int with_even
     __shared__ uint32_t s_m[kMaxInstLds];
     const int n_inst = d.n_inst < kMaxInstLds ? d.n_inst : kMaxInstLds;
     if (with_events) {
-        build_event_index(X, d);
+        load_event_index(X, d);
         count_events(X, d, s_m, n_inst);
     } else {
         for (int i = threadIdx.x; i < n_inst; i += kBlock) s_m[i] = 0u;
@@ -676,6 +707,11 @@ hipError_t launch_collide(const Dev &d, hipStream_t st)
 
 hipError_t launch_emit(const Dev &d, hipStream_t st, bool pairs, bool events)
 {
+    if (events || pairs) {
+        hipLaunchKernelGGL(index_kernel, dim3(1), dim3(kBlock), 0, st, d);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     if (events) {
         hipLaunchKernelGGL(rank_kernel, dim3(kRankBlocks), dim3(kBlock), 0, st, d);
         hipError_t e = hipGetLastError();

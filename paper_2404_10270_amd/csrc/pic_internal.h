@@ -124,7 +124,9 @@ struct Globals {
     uint32_t cand_ovf;       // candidates in the overflow list this step
     uint32_t ev_ovf;         // ionisation events in the overflow list this step
     uint32_t since_sort;     // steps closed since the last sort (kNoIndex: none yet)
-    uint32_t pad[4];
+    uint32_t ev_total;       // ionisation events this step (regions + overflow), from index_kernel
+    uint32_t ev_in_regions;  // of which in the per-block regions
+    uint32_t pad[2];
     // self-resetting single-pass scan (the sort): ticket counter, finish counter, generation
     uint32_t scan_ticket[4];
     uint32_t scan_finish[4];
@@ -168,7 +170,7 @@ struct Layout {
     uint64_t fwd_status, bwd_status, sort_status;
     uint64_t fe_part;
     uint64_t cand, cand_n, ev, ev_n, ev_rank, cnt_slot;
-    uint64_t nn, ev_crank, ev_target;
+    uint64_t nn, ev_crank, ev_target, ev_pre;
     uint64_t diag_part, diag_out;
     uint64_t total;
     int64_t cand_ovf_cap, ev_ovf_cap;
@@ -211,6 +213,7 @@ struct Dev {
     uint32_t *ev_crank;         // [events] rank among the events of its instance and cell
     long long *ev_target;       // [events] slot of the atom an event consumes, or -1
     double *nn;                 // [G] density of the kinetic neutrals [m^-3]
+    uint32_t *ev_pre;           // [n_push_blocks+1] first event of each region (index_kernel)
     unsigned long long *cnt_slot;  // [n_push_blocks][n_seg][kNCnt] process counts per block
     double *diag_part;
     pic_diag *diag_out;

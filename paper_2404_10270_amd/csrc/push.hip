@@ -54,9 +54,20 @@ struct PushLds {
     int64_t tile0[kSegLds + 1];
     int64_t base[kSegLds];
     uint32_t count[kSegLds];
+    uint8_t flg[kSegLds];   // kFlgTest | kFlgForce of each segment
     uint32_t cn;
     int red[2][kWaves];
 };
+
+// per-segment flags of the movers: a collision process (the candidate test
+// reads ids and draws), a field that acts (the gather)
+constexpr uint32_t kFlgTest = 1u, kFlgForce = 2u;
+
+__device__ __forceinline__ uint32_t seg_flags(const Dev &d, int s)
+{
+    const SegConst &sc = d.segc[s];
+    return (sc.T != 0ull ? kFlgTest : 0u) | (sc.force ? kFlgForce : 0u);
+}
 
 // a subcycled species between its pushes (block-uniform)
 __device__ __forceinline__ bool still(const Dev &d, int seg)
@@ -76,6 +87,7 @@ __device__ __forceinline__ void push_lds_init(PushLds &L, const Dev &d, bool dro
             if (s < d.n_seg) {
                 L.base[s] = d.seg_base[s];
                 L.count[s] = drop_still && still(d, s) ? 0 : d.segd[s].count;
+                L.flg[s] = (uint8_t)seg_flags(d, s);
             }
         }
     }
@@ -92,9 +104,9 @@ __device__ __forceinline__ int64_t uniform_i64(int64_t v)
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-// (segment, first slot, occupied slots) of virtual tile t
+// (segment, first slot, occupied slots, flags) of virtual tile t
 __device__ __forceinline__ int tile_seg(const PushLds &L, const Dev &d, int64_t t, int64_t &tile0,
-                                        int64_t &base, int64_t &count)
+                                        int64_t &base, int64_t &count, uint32_t &flags)
 {
     int seg;
     if (d.n_seg <= kSegLds) {
@@ -107,15 +119,18 @@ __device__ __forceinline__ int tile_seg(const PushLds &L, const Dev &d, int64_t 
         tile0 = L.tile0[seg];
         base = L.base[seg];
         count = L.count[seg];
+        flags = L.flg[seg];
     } else {
         seg = seg_of_tile(d.seg_tile0, d.n_seg, t);
         tile0 = d.seg_tile0[seg];
         base = d.seg_base[seg];
         count = d.segd[seg].count;
+        flags = seg_flags(d, seg);
     }
     tile0 = uniform_i64(tile0);
     base = uniform_i64(base);
     count = uniform_i64(count);
+    flags = (uint32_t)__builtin_amdgcn_readfirstlane((int)flags);
     return __builtin_amdgcn_readfirstlane(seg);
 }
 
@@ -307,7 +322,8 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
 
     for (int64_t t = blockIdx.x; t < d.n_tiles; t += gridDim.x) {
         int64_t tile0, base, count;
-        const int seg = tile_seg(L, d, t, tile0, base, count);
+        uint32_t flg;
+        const int seg = tile_seg(L, d, t, tile0, base, count, flg);
         const int64_t t0 = (t - tile0) * (int64_t)kTile;
         if (t0 >= count) continue;
         // a subcycled species between its pushes keeps its positions (their
@@ -316,8 +332,8 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
 
         // a species with no collision process takes no test (no id read, no
         // draw); a species on which no field acts takes no gather
-        const bool test = MCC && d.segc[seg].T != 0ull;
-        const bool force = d.segc[seg].force != 0;
+        const bool test = MCC && (flg & kFlgTest);
+        const bool force = (flg & kFlgForce) != 0;
         // ---- loads of all chunks
         int32_t j[kPer];
         float f[kPer], vx[kPer], vy[kPer], vz[kPer];
@@ -499,14 +515,15 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
 
     for (int64_t t = blockIdx.x; t < d.n_tiles; t += gridDim.x) {
         int64_t tile0, base, count;
-        const int seg = tile_seg(L, d, t, tile0, base, count);
+        uint32_t flg;
+        const int seg = tile_seg(L, d, t, tile0, base, count, flg);
         const int64_t t0 = (t - tile0) * (int64_t)kTile;
         if (t0 >= count) continue;
         // a subcycled species between its pushes keeps its positions (their
         // deposit is a launch of its own, deposit_kernel<true>)
         if (d.n_seg > kSegLds && still(d, seg)) continue;
-        const bool test = MCC && d.segc[seg].T != 0ull;
-        const bool force = d.segc[seg].force != 0;
+        const bool test = MCC && (flg & kFlgTest);
+        const bool force = (flg & kFlgForce) != 0;
 
         double x[kPer], vx[kPer], vy[kPer], vz[kPer];
         unsigned long long pid[kPer];
@@ -666,7 +683,8 @@ __global__ __launch_bounds__(kBlock) void deposit_kernel(Dev d)
     const int cur = d.glob->cur_set;
     for (int64_t t = blockIdx.x; t < d.n_tiles; t += gridDim.x) {
         int64_t tile0, base, count;
-        const int seg = tile_seg(L, d, t, tile0, base, count);
+        uint32_t flg;
+        const int seg = tile_seg(L, d, t, tile0, base, count, flg);
         const int64_t t0 = (t - tile0) * (int64_t)kTile;
         if (t0 >= count) continue;
         if (ONLY_STILL && !still(d, seg)) continue;

@@ -374,7 +374,11 @@ __global__ __launch_bounds__(kBlock) void sort_scatter_kernel(Dev d)
                 const unsigned long long w = ((unsigned long long)hi << 32) | lo;
                 vb = w > vb ? w : vb;
             }
-            if (lane == 0 && vb) atomicMax(&d.segd[seg].vmax_bits, vb);
+            // same-address atomics serialise: only a wave that raises the
+            // maximum it can see issues one
+            unsigned long long *vm = &d.segd[seg].vmax_bits;
+            if (lane == 0 && vb > __hip_atomic_load(vm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                atomicMax(vm, vb);
         }
         // the next tile's window barrier orders the reuse of L.base
     }
