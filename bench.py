@@ -41,7 +41,7 @@ PUSH_BYTES_FP64 = 4 * 8 + 8 + 4 * 8
 SORT_EVERY = 20
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "push_f32_bounded_mcc_traffic.json")
 PUSH_SOURCES = ["paper_2404_10270_amd/csrc/push.hip", "paper_2404_10270_amd/csrc/device_common.h",
-                "paper_2404_10270_amd/csrc/pic_internal.h"]
+                "paper_2404_10270_amd/csrc/pic_internal.h", "paper_2404_10270_amd/csrc/mover_common.h"]
 COPY_BYTES = 1 << 30  # calibration copy: 1 GiB read + 1 GiB written per launch
 
 
@@ -252,6 +252,72 @@ def table1_run(torch, args):
     return out
 
 
+def layout_study(torch, args):
+    """The mover pass in four particle layouts (libpic_layout): structure of
+    arrays (libpic's), array of 32-byte structs, 64-particle blocks of arrays,
+    and per-cell slots with slack regrouped every pass (natural sorting).  One
+    magnetised species of 2e7 particles on 100,000 periodic cells (200 per
+    cell, B at 45 degrees with |t| = 0.1, v_th = 0.05 cells/step, 4.6%
+    candidates), drawn on the device in cell order; each layout is timed with
+    HIP events over `passes` passes after 5 warm-up passes."""
+    from paper_2404_10270_amd import layout as Lb
+    nc, ppc, passes = 100_000, 200, args.layout_passes
+    n = nc * ppc
+    dev = torch.device("cuda")
+    g = torch.Generator(device=dev)
+    g.manual_seed(7)
+    x = torch.sort(torch.rand(n, generator=g, device=dev, dtype=torch.float64) * nc).values
+    cell = torch.floor(x).to(torch.int32)
+    f = (x - cell.to(torch.float64)).to(torch.float32)
+    f = torch.where(f >= 1.0, torch.full_like(f, 0.99999994), f)
+    del x
+    v = torch.randn(3, n, generator=g, device=dev, dtype=torch.float32) * 0.05
+    soa = {"cell": cell, "f": f, "vx": v[0].contiguous(), "vy": v[1].contiguous(),
+           "vz": v[2].contiguous(), "id": torch.arange(n, dtype=torch.int64, device=dev)}
+    del v
+    acc = (1e-4 * torch.sin(2 * math.pi * torch.arange(nc + 1, device=dev, dtype=torch.float64) / nc)
+           ).to(torch.float32)
+    S = torch.zeros(nc + 1, dtype=torch.int64, device=dev)
+    per_cell = int(torch.bincount(cell, minlength=nc).max())
+    slack = int(math.ceil(per_cell * 1.5 / 64.0) * 64)
+    tm = 0.1
+    tx = ty = tm * math.cos(math.pi / 4)
+    den = 1.0 + (tx * tx + ty * ty)
+    p = Lb.pls_params()
+    p.nc, p.slack = nc, slack
+    p.tx, p.ty, p.sx, p.sy = tx, ty, 2 * tx / den, 2 * ty / den
+    p.key0, p.key1 = 3, 0
+    p.T = int(math.floor(-math.expm1(-0.047) * 2 ** 32))
+    p.acc, p.S = acc.data_ptr(), S.data_ptr()
+    out = {"particles": n, "cells": nc, "passes": passes, "slack": slack,
+           "bytes_per_particle": 48}
+    for name, lay in Lb.LAYOUTS.items():
+        log(f"layout study: {name}")
+        r = Lb.LayoutRun(lay, soa, nc, slack)
+        for s in range(5):
+            r.step(p, s)
+        st = r.stream
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for s in range(passes):
+            r.step(p, 5 + s)
+        e1.record(st)
+        torch.cuda.synchronize()
+        us = 1e3 * e0.elapsed_time(e1) / passes
+        _, n_cand = r.store()
+        foot = (r.work.numel() - 256) / n
+        out[name] = {"us_per_pass": round(us, 1), "particle_steps_per_s": n / (us * 1e-6),
+                     "GBps": round(48 * n / (us * 1e-6) / 1e9, 1),
+                     "frac": round(48 * n / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                     "bytes_stored_per_particle": round(foot, 1), "candidates": n_cand}
+        log(f"layout study: {name} {us:.1f} us/pass, {out[name]['GBps']} GB/s, "
+            f"{foot:.1f} B stored per particle")
+        del r
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(args):
     """The oracle as it stands, single thread, on a bounded sample of the workload."""
     import oracle
@@ -282,6 +348,9 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=60)
     ap.add_argument("--no-table1", action="store_true")
     ap.add_argument("--table1-steps", type=int, default=200)
+    ap.add_argument("--layout-study", action="store_true",
+                    help="run only the particle-layout study of the mover and print its JSON object")
+    ap.add_argument("--layout-passes", type=int, default=40)
     ap.add_argument("--only-table1", action="store_true",
                     help="run only the Table 1 workload and print its JSON object (profiling)")
     ap.add_argument("--eager", action="store_true",
@@ -309,6 +378,9 @@ def main():
         sys.exit(1)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.layout_study:
+        print(json.dumps({"layout_study": layout_study(torch, args)}), flush=True)
         return
     if args.only_table1:
         print(json.dumps(table1_run(torch, args)), flush=True)

@@ -1,9 +1,10 @@
-"""Build libpic.so (HIP, gfx950) in-tree.
+"""Build libpic.so and libpic_layout.so (HIP, gfx950) in-tree.
 
     python -m paper_2404_10270_amd.build
 
 Every source under csrc/ is compiled with hipcc for gfx950 and linked into
-paper_2404_10270_amd/libpic.so next to this file.
+paper_2404_10270_amd/libpic.so next to this file; study/layout.hip (the
+particle-layout study of the mover) is linked into libpic_layout.so.
 """
 from __future__ import annotations
 
@@ -19,6 +20,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpic.so")
+LAYOUT_LIB = os.path.join(HERE, "libpic_layout.so")
+STUDY = os.path.join(HERE, "study")
 OBJ = os.path.join(ROOT, "_build", "libpic")
 
 ARCH = "gfx950"
@@ -48,20 +51,27 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(OBJ, exist_ok=True)
-    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip"))) + [os.path.join(CSRC, "api.cpp")]
-    jobs = min(len(srcs), int(os.environ.get("MAX_JOBS", "8")), 16)
-    with cf.ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = LIB + ".tmp%d" % os.getpid()
+def _link(objs, lib: str) -> None:
+    tmp = lib + ".tmp%d" % os.getpid()
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(OBJ, exist_ok=True)
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip"))) + [os.path.join(CSRC, "api.cpp")]
+    study = [os.path.join(STUDY, "layout.hip")]
+    jobs = min(len(srcs) + len(study), int(os.environ.get("MAX_JOBS", "8")), 16)
+    with cf.ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
+        objs = list(ex.map(_compile, srcs + study))
+    _link(objs[:len(srcs)], LIB)
+    _link(objs[len(srcs):], LAYOUT_LIB)
     if verbose:
         print("built", LIB)
+        print("built", LAYOUT_LIB)
     return LIB
 
 

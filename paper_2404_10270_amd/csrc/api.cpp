@@ -320,7 +320,7 @@ int plan(const pic_config *cfgs, int n_inst, Plan &p)
                                  (int64_t)align_up((uint64_t)(1.25 * expect / p.n_push_blocks) + 64, 64));
     L.ev_q = std::max<int64_t>(kEvQMin, L.cand_q / 16);
     L.cand = take(sizeof(Cand) * ((uint64_t)p.n_push_blocks * L.cand_q + L.cand_ovf_cap));
-    L.cand_n = take(sizeof(uint32_t) * p.n_push_blocks);
+    L.cand_n = take(sizeof(uint32_t) * p.n_push_blocks * kWaves);
     L.ev = take(sizeof(IzEvent) * ((uint64_t)p.n_push_blocks * L.ev_q + L.ev_ovf_cap));
     L.ev_n = take(sizeof(uint32_t) * p.n_push_blocks);
     L.ev_rank = take(sizeof(uint32_t) * ((uint64_t)p.n_push_blocks * L.ev_q + L.ev_ovf_cap));

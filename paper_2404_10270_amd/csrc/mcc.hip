@@ -108,8 +108,14 @@ __global__ __launch_bounds__(kBlock) void collide_kernel(Dev d)
 
     const int cur = d.glob->cur_set;
     const bool f64 = (d.precision == PIC_FP64);
-    // this block's region of the candidate list, then a share of the overflow list
-    const uint32_t nr = d.cand_n[blockIdx.x];
+    // this block's region of the candidate list (one part per mover wave),
+    // then a share of the overflow list
+    const uint32_t qw = (uint32_t)d.cand_q / kWaves;
+    uint32_t pre[kWaves + 1];
+    pre[0] = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) pre[w + 1] = pre[w] + d.cand_n[blockIdx.x * kWaves + w];
+    const uint32_t nr = pre[kWaves];
     uint32_t novf = d.glob->cand_ovf;
     if (novf > (uint32_t)d.cand_ovf_cap) novf = (uint32_t)d.cand_ovf_cap;
     const uint32_t per_block = (novf + gridDim.x - 1) / gridDim.x;
@@ -120,8 +126,15 @@ __global__ __launch_bounds__(kBlock) void collide_kernel(Dev d)
         uint32_t cnt[kNCnt] = {0, 0, 0, 0, 0, 0};
         bool iz = false;
         IzEvent ev = {};
-        const int64_t idx = q < nr ? (int64_t)blockIdx.x * d.cand_q + q
-                                   : (int64_t)d.n_push_blocks * d.cand_q + o_lo + (q - nr);
+        int64_t idx;
+        if (q < nr) {
+            int w = 0;
+#pragma unroll
+            for (int v = 1; v < kWaves; ++v) w += (q >= pre[v]) ? 1 : 0;
+            idx = (int64_t)blockIdx.x * d.cand_q + (int64_t)w * qw + (q - pre[w]);
+        } else {
+            idx = (int64_t)d.n_push_blocks * d.cand_q + o_lo + (q - nr);
+        }
         const int seg = collide_one(d, cur, f64, d.cand[idx], cnt, iz, ev);
         if (iz) {
             // this block's region of the event list; the rare excess goes to the overflow list

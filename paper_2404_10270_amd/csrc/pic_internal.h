@@ -206,7 +206,7 @@ struct Dev {
     unsigned long long *sort_status;
     double *fe_part;
     Cand *cand;                 // [n_push_blocks][cand_q] per-block regions, then the overflow list
-    uint32_t *cand_n;           // [n_push_blocks] candidates in each region
+    uint32_t *cand_n;           // [n_push_blocks][kWaves] candidates in each wave's part of a region
     IzEvent *ev;                // [n_push_blocks][ev_q] per-block regions, then the overflow list
     uint32_t *ev_n;             // [n_push_blocks] events in each region
     uint32_t *ev_rank;          // [events] rank of each event among its instance's (by parent id)

@@ -25,29 +25,13 @@
 //    the collide kernel reads them contiguously; only a block with more than
 //    its region's cand_q candidates appends the excess to a shared overflow
 //    list.
-#include "device_common.h"
+#include "mover_common.h"
 
 #pragma clang fp contract(off)
 
 namespace picx {
 
-constexpr int kDepWin = 1024;     // LDS deposit window, nodes
 constexpr int kSegLds = 1024;     // segments whose tables are staged in LDS
-
-// Particle arrays are streamed once per step (the state is far larger than
-// the caches): nontemporal loads and stores keep them from displacing the
-// grid, the deposit window flushes and the candidate regions in L2.
-template <typename T>
-__device__ __forceinline__ T stream_ld(const T *p)
-{
-    return __builtin_nontemporal_load(p);
-}
-
-template <typename T>
-__device__ __forceinline__ void stream_st(T *p, T v)
-{
-    __builtin_nontemporal_store(v, p);
-}
 
 struct PushLds {
     unsigned long long dep[kDepWin];
@@ -55,7 +39,6 @@ struct PushLds {
     int64_t base[kSegLds];
     uint32_t count[kSegLds];
     uint8_t flg[kSegLds];   // kFlgTest | kFlgForce of each segment
-    uint32_t cn;
     int red[2][kWaves];
 };
 
@@ -91,7 +74,6 @@ __device__ __forceinline__ void push_lds_init(PushLds &L, const Dev &d, bool dro
             }
         }
     }
-    if (threadIdx.x == 0) L.cn = 0;
     __syncthreads();
 }
 
@@ -134,80 +116,12 @@ __device__ __forceinline__ int tile_seg(const PushLds &L, const Dev &d, int64_t 
     return __builtin_amdgcn_readfirstlane(seg);
 }
 
-__device__ __forceinline__ int wave_min(int v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
-__device__ __forceinline__ int wave_max(int v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
-// Deposit the kPer chunks of this wave (keys = cells, -1 = none) through the
-// block's LDS window.  Contains two block barriers; every thread must call it.
+// Deposit the kPer chunks of this wave through the block's LDS window.
 template <int NP>
 __device__ __forceinline__ void deposit_tile(PushLds &L, unsigned long long *__restrict__ S,
                                              const int (&key)[NP], const unsigned long long (&w1)[NP])
 {
-    const int lane = lane_id();
-    const int wave = threadIdx.x >> 6;
-    int kmn = 0x7fffffff, kmx = -1;
-#pragma unroll
-    for (int k = 0; k < NP; ++k)
-        if (key[k] >= 0) {
-            kmn = min(kmn, key[k]);
-            kmx = max(kmx, key[k]);
-        }
-    kmn = wave_min(kmn);
-    kmx = wave_max(kmx);
-    if (lane == 0) {
-        L.red[0][wave] = kmn;
-        L.red[1][wave] = kmx;
-    }
-    __syncthreads();
-    int lo = L.red[0][0], hi = L.red[1][0];
-#pragma unroll
-    for (int w = 1; w < kWaves; ++w) {
-        lo = min(lo, L.red[0][w]);
-        hi = max(hi, L.red[1][w]);
-    }
-#pragma unroll
-    for (int k = 0; k < NP; ++k) {
-        // pack (count, sum W1): W1 <= 2^32 and at most 64 lanes -> sum < 2^39
-        const unsigned long long v = (key[k] >= 0) ? ((1ull << 40) + w1[k]) : 0ull;
-        bool tail;
-        const unsigned long long t = run_sum(key[k], v, tail);
-        if (tail && key[k] >= 0) {
-            const unsigned long long n = t >> 40;
-            const unsigned long long b = t & ((1ull << 40) - 1ull);
-            const unsigned long long a = (n << PIC_FRAC_BITS) - b;
-            const int rel = key[k] - lo;
-            if (rel + 1 < kDepWin) {
-                atomicAdd(&L.dep[rel], a);
-                atomicAdd(&L.dep[rel + 1], b);
-            } else {
-                atomicAdd(S + key[k], a);
-                atomicAdd(S + key[k] + 1, b);
-            }
-        }
-    }
-    __syncthreads();
-    if (hi >= 0) {
-        const int span = min(hi - lo + 2, kDepWin);
-        for (int i = threadIdx.x; i < span; i += kBlock) {
-            const unsigned long long v = L.dep[i];
-            if (v) {
-                atomicAdd(S + lo + i, v);
-                L.dep[i] = 0ull;
-            }
-        }
-    }
-    // the next use of the window is ordered by the next call's first barrier
+    deposit_window<NP>(L.dep, L.red, S, key, w1);
 }
 
 // The deposit of the current positions of one tile (both forms): the
@@ -248,35 +162,35 @@ __device__ __forceinline__ void deposit_positions(PushLds &L, const Dev &d, int 
 }
 
 // A candidate is written, with its velocity after the push and its id, to
-// the block's own region of the candidate list (the index comes from an LDS
-// counter); a wave whose candidates do not fit appends the excess to the
-// shared overflow list.
+// its wave's own part of the block's region of the candidate list: the
+// wave's running count wn is block-uniform per wave (a scalar), so no LDS or
+// global atomic is needed; a wave whose part is full appends the excess to
+// the shared overflow list.
 template <typename V>
-__device__ __forceinline__ void queue_candidate(PushLds &L, const Dev &d, bool cand, uint32_t g,
-                                                int inst, V vx, V vy, V vz,
-                                                unsigned long long pid)
+__device__ __forceinline__ void queue_candidate(const Dev &d, bool cand, uint32_t g, int inst, V vx,
+                                                V vy, V vz, unsigned long long pid, uint32_t &wn)
 {
     const unsigned long long m = ballot(cand);
     if (!m) return;
     const int lane = lane_id();
-    const int leader = __ffsll((long long)m) - 1;
     const uint32_t n = (uint32_t)__popcll(m);
     const uint32_t rank = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(&L.cn, n);
-    base = __shfl(base, leader, 64);
-    // the first n_reg candidates fill the rest of the region, the others overflow
-    const uint32_t room = base < (uint32_t)d.cand_q ? (uint32_t)d.cand_q - base : 0u;
+    const uint32_t base = wn;
+    wn = base + n;
+    const uint32_t qw = (uint32_t)d.cand_q / kWaves;
+    // the first n_reg candidates fill the rest of the wave's part, the others overflow
+    const uint32_t room = base < qw ? qw - base : 0u;
     const uint32_t n_reg = n < room ? n : room;
     uint32_t gb = 0;
     if (n_reg != n) {
+        const int leader = __ffsll((long long)m) - 1;
         if (lane == leader) gb = atomicAdd(&d.glob->cand_ovf, n - n_reg);
         gb = __shfl(gb, leader, 64);
     }
     if (!cand) return;
     int64_t idx;
     if (rank < n_reg) {
-        idx = (int64_t)blockIdx.x * d.cand_q + base + rank;
+        idx = (int64_t)blockIdx.x * d.cand_q + (int64_t)(threadIdx.x >> 6) * qw + base + rank;
     } else {
         const uint32_t o = gb + (rank - n_reg);
         if (o >= (uint32_t)d.cand_ovf_cap) {
@@ -295,11 +209,11 @@ __device__ __forceinline__ void queue_candidate(PushLds &L, const Dev &d, bool c
     d.cand[idx] = c;
 }
 
-// the number of entries in this block's region
-__device__ __forceinline__ void flush_candidates(PushLds &L, const Dev &d)
+// the number of entries in this wave's part of the region
+__device__ __forceinline__ void flush_candidates(const Dev &d, uint32_t wn)
 {
-    __syncthreads();
-    if (threadIdx.x == 0) d.cand_n[blockIdx.x] = min(L.cn, (uint32_t)d.cand_q);
+    const uint32_t qw = (uint32_t)d.cand_q / kWaves;
+    if (lane_id() == 0) d.cand_n[blockIdx.x * kWaves + (threadIdx.x >> 6)] = min(wn, qw);
 }
 
 // ---------------------------------------------------------------------------
@@ -319,6 +233,7 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
     const unsigned long long *__restrict__ ID = d.id[cur];
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
+    uint32_t wn = 0;  // this wave's candidates so far (uniform)
 
     for (int64_t t = blockIdx.x; t < d.n_tiles; t += gridDim.x) {
         int64_t tile0, base, count;
@@ -487,12 +402,12 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
 #pragma unroll
             for (int k = 0; k < kPer; ++k) {
                 const uint32_t o = (uint32_t)((wave * kPer + k) * 64 + lane);
-                queue_candidate(L, d, cand[k], (uint32_t)(tb + o), inst, vx[k], vy[k], vz[k], pid[k]);
+                queue_candidate(d, cand[k], (uint32_t)(tb + o), inst, vx[k], vy[k], vz[k], pid[k], wn);
             }
         }
         if (DEP) deposit_tile<kPer>(L, S, key, w1);
     }
-    if (MCC) flush_candidates(L, d);
+    if (MCC) flush_candidates(d, wn);
 }
 
 // ---------------------------------------------------------------------------
@@ -512,6 +427,7 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
     const unsigned long long *__restrict__ ID = d.id[cur];
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
+    uint32_t wn = 0;  // this wave's candidates so far (uniform)
 
     for (int64_t t = blockIdx.x; t < d.n_tiles; t += gridDim.x) {
         int64_t tile0, base, count;
@@ -663,12 +579,12 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
 #pragma unroll
             for (int k = 0; k < kPer; ++k) {
                 const uint32_t o = (uint32_t)((wave * kPer + k) * 64 + lane);
-                queue_candidate(L, d, cand[k], (uint32_t)(tb + o), inst, vx[k], vy[k], vz[k], pid[k]);
+                queue_candidate(d, cand[k], (uint32_t)(tb + o), inst, vx[k], vy[k], vz[k], pid[k], wn);
             }
         }
         if (DEP) deposit_tile<kPer>(L, S, key, w1);
     }
-    if (MCC) flush_candidates(L, d);
+    if (MCC) flush_candidates(d, wn);
 }
 
 // ---------------------------------------------------------------------------

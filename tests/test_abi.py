@@ -148,3 +148,40 @@ def test_strerror(P):
     for code in (0, -1, -2, -3, -4, -5, -6, -7, -99):
         s = P.pic_strerror(code)
         assert isinstance(s, str) and s
+
+
+def test_layout_study_library_exports_and_layout(P, tmp_path):
+    """libpic_layout (the mover in four particle layouts): every entry point
+    include/pic_layout.h declares is exported, the ctypes mirrors have the C
+    layout, and bad arguments are refused without device work."""
+    from paper_2404_10270_amd import layout as Lb
+    src = open(os.path.join(ROOT, "include", "pic_layout.h")).read()
+    names = sorted(set(re.findall(r"^\s*int\s+(pls_\w+)\s*\(", src, re.M)))
+    assert set(names) == set(Lb.ABI_SYMBOLS)
+    out = subprocess.run(["nm", "-D", "--defined-only", Lb.LIB], capture_output=True, text=True,
+                         check=True).stdout
+    for n in names:
+        assert re.search(rf" T {n}$", out, re.M), n
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pic_layout.h"', 'int main(void){']
+    for name, T in {"pls_soa": Lb.pls_soa, "pls_params": Lb.pls_params}.items():
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for f, _ in T._fields_:
+            lines.append(f'printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    lines.append("return 0;}")
+    c = tmp_path / "pls.c"
+    c.write_text("\n".join(lines))
+    exe = tmp_path / "pls"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)])
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                 check=True).stdout.split("\n") if l.strip())
+    for name, T in {"pls_soa": Lb.pls_soa, "pls_params": Lb.pls_params}.items():
+        assert int(got[name]) == C.sizeof(T), name
+        for f, _ in T._fields_:
+            assert int(got[f"{name}.{f}"]) == getattr(T, f).offset, f"{name}.{f}"
+    L = Lb.lib()
+    nb = C.c_uint64()
+    assert L.pls_work_bytes(Lb.PLS_SOA, 1000, 100, 0, C.byref(nb)) == 0 and nb.value > 24000
+    assert L.pls_work_bytes(7, 1000, 100, 0, C.byref(nb)) == -1          # no such layout
+    assert L.pls_work_bytes(Lb.PLS_CELLPAD, 1000, 100, 100, C.byref(nb)) == -1  # slack not a multiple of 64
+    assert L.pls_work_bytes(Lb.PLS_SOA, 1000, 1, 0, C.byref(nb)) == -1   # too few cells
+    assert L.pls_step(Lb.PLS_SOA, None, 10, 0, 0, None, None) == -1
