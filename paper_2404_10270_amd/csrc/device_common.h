@@ -174,7 +174,8 @@ __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, double &n0, d
 //             |v|, or n sig_iz dx v_cap with a constant rate coefficient;
 //   ion       charge exchange (the ion takes a Maxwellian velocity at T_n).
 // n is the uniform gas density, or the local density of kinetic neutrals.
-// (vx, vy, vz) in cells/step are updated in place; cnt gets the counts.
+// (vx, vy, vz) in cells/step are updated in place; ev gets one bit per
+// process that happened (1 << kC...; a candidate sets each bit at most once).
 // ---------------------------------------------------------------------------
 enum { kCCand = 0, kCEl = 1, kCIz = 2, kCCx = 3, kCOver = 4, kCEx = 5 };
 
@@ -199,13 +200,12 @@ __device__ __forceinline__ Rates local_rates(const SegConst &sc, double nl)
 
 __device__ __forceinline__ void collide_vel(const SegConst &sc, const Rates &R, long long step,
                                             unsigned long long pid, double &vx, double &vy,
-                                            double &vz, uint32_t (&cnt)[kNCnt], bool &iz,
-                                            double &g2)
+                                            double &vz, uint32_t &ev, bool &iz, double &g2)
 {
     const uint4 u = draw(pid, step, 0, sc.key0, sc.key1);
     const double v2 = (vx * vx + vy * vy) + vz * vz;
-    cnt[kCCand] += 1;
-    if (v2 > sc.vcap2) cnt[kCOver] += 1;
+    ev |= 1u << kCCand;
+    if (v2 > sc.vcap2) ev |= 1u << kCOver;
     const double r = u01(u.y) * sc.nu_max;
     const double r2 = r * r;
     if (sc.kind == PIC_KIND_ELECTRON) {
@@ -217,7 +217,7 @@ __device__ __forceinline__ void collide_vel(const SegConst &sc, const Rates &R, 
             vx = sc.am * vx + sc.bm * gg * d0;
             vy = sc.am * vy + sc.bm * gg * d1;
             vz = sc.am * vz + sc.bm * gg * d2;
-            cnt[kCEl] += 1;
+            ev |= 1u << kCEl;
         } else if (r2 < R.C1 * v2) {
             if (v2 >= sc.v2_ex) {
                 double d0, d1, d2;
@@ -226,7 +226,7 @@ __device__ __forceinline__ void collide_vel(const SegConst &sc, const Rates &R, 
                 vx = gg * d0;
                 vy = gg * d1;
                 vz = gg * d2;
-                cnt[kCEx] += 1;
+                ev |= 1u << kCEx;
             }
         } else if (v2 >= sc.v2_iz) {
             if (sc.rate_iz) {
@@ -249,7 +249,7 @@ __device__ __forceinline__ void collide_vel(const SegConst &sc, const Rates &R, 
             vz = g1 * d2;
             iz = true;
             g2 = sqrt(2.0 * e2);
-            cnt[kCIz] += 1;
+            ev |= 1u << kCIz;
         }
     } else {
         if (r2 < R.C0 * v2) {
@@ -260,7 +260,7 @@ __device__ __forceinline__ void collide_vel(const SegConst &sc, const Rates &R, 
             vx = sc.sig_n * n0;
             vy = sc.sig_n * n1;
             vz = sc.sig_n * n2;
-            cnt[kCCx] += 1;
+            ev |= 1u << kCCx;
         }
     }
 }

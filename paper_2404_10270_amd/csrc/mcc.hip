@@ -39,7 +39,7 @@ __device__ __forceinline__ void st_v(void *p, int64_t g, double v, bool f64)
 // collide one listed candidate; returns its segment, fills the counts and
 // the ionisation event, and stores the velocity of a particle that collided
 __device__ __forceinline__ int collide_one(const Dev &d, int cur, bool f64, const Cand &c,
-                                           uint32_t (&cnt)[kNCnt], bool &iz, IzEvent &ev)
+                                           uint32_t &cnt, bool &iz, IzEvent &ev)
 {
     const int64_t g = c.g;
     const int seg = seg_of_slot(d.seg_base, d.n_seg, g);
@@ -70,7 +70,7 @@ __device__ __forceinline__ int collide_one(const Dev &d, int cur, bool f64, cons
         R = uniform_rates(sc);
     }
     collide_vel(sc, R, step, c.pid, vx, vy, vz, cnt, iz, g2);
-    if (cnt[kCEl] | cnt[kCIz] | cnt[kCCx] | cnt[kCEx]) {
+    if (cnt & ((1u << kCEl) | (1u << kCIz) | (1u << kCCx) | (1u << kCEx))) {
         st_v(d.vx[cur], g, vx, f64);
         st_v(d.vy[cur], g, vy, f64);
         st_v(d.vz[cur], g, vz, f64);
@@ -86,85 +86,14 @@ __device__ __forceinline__ int collide_one(const Dev &d, int cur, bool f64, cons
     return seg;
 }
 
-__device__ __forceinline__ void add_counts(InstDyn *idn, const uint32_t (&c)[kNCnt])
+__device__ __forceinline__ void add_counts(InstDyn *idn, uint32_t c)
 {
-    if (c[kCCand]) atomicAdd(&idn->n_candidates, (unsigned long long)c[kCCand]);
-    if (c[kCEl]) atomicAdd(&idn->n_elastic, (unsigned long long)c[kCEl]);
-    if (c[kCIz]) atomicAdd(&idn->n_ionize, (unsigned long long)c[kCIz]);
-    if (c[kCCx]) atomicAdd(&idn->n_cx, (unsigned long long)c[kCCx]);
-    if (c[kCOver]) atomicAdd(&idn->n_over_cap, (unsigned long long)c[kCOver]);
-    if (c[kCEx]) atomicAdd(&idn->n_excite, (unsigned long long)c[kCEx]);
-}
-
-__global__ __launch_bounds__(kBlock) void collide_kernel(Dev d)
-{
-    extern __shared__ uint32_t s_cnt[];  // [n_seg][kNCnt] when n_seg <= kCntSegMax
-    __shared__ uint32_t s_en;
-    const bool lds_cnt = d.n_seg <= kCntSegMax;
-    if (lds_cnt)
-        for (int q = threadIdx.x; q < d.n_seg * kNCnt; q += kBlock) s_cnt[q] = 0u;
-    if (threadIdx.x == 0) s_en = 0u;
-    __syncthreads();
-
-    const int cur = d.glob->cur_set;
-    const bool f64 = (d.precision == PIC_FP64);
-    // this block's region of the candidate list (one part per mover wave),
-    // then a share of the overflow list
-    const uint32_t qw = (uint32_t)d.cand_q / kWaves;
-    uint32_t pre[kWaves + 1];
-    pre[0] = 0;
-#pragma unroll
-    for (int w = 0; w < kWaves; ++w) pre[w + 1] = pre[w] + d.cand_n[blockIdx.x * kWaves + w];
-    const uint32_t nr = pre[kWaves];
-    uint32_t novf = d.glob->cand_ovf;
-    if (novf > (uint32_t)d.cand_ovf_cap) novf = (uint32_t)d.cand_ovf_cap;
-    const uint32_t per_block = (novf + gridDim.x - 1) / gridDim.x;
-    const uint32_t o_lo = min(novf, blockIdx.x * per_block);
-    const uint32_t o_hi = min(novf, o_lo + per_block);
-    const uint32_t n_items = nr + (o_hi - o_lo);
-    for (uint32_t q = threadIdx.x; q < n_items; q += kBlock) {
-        uint32_t cnt[kNCnt] = {0, 0, 0, 0, 0, 0};
-        bool iz = false;
-        IzEvent ev = {};
-        int64_t idx;
-        if (q < nr) {
-            int w = 0;
-#pragma unroll
-            for (int v = 1; v < kWaves; ++v) w += (q >= pre[v]) ? 1 : 0;
-            idx = (int64_t)blockIdx.x * d.cand_q + (int64_t)w * qw + (q - pre[w]);
-        } else {
-            idx = (int64_t)d.n_push_blocks * d.cand_q + o_lo + (q - nr);
-        }
-        const int seg = collide_one(d, cur, f64, d.cand[idx], cnt, iz, ev);
-        if (iz) {
-            // this block's region of the event list; the rare excess goes to the overflow list
-            const uint32_t e = atomicAdd(&s_en, 1u);
-            if (e < (uint32_t)d.ev_q) {
-                d.ev[(int64_t)blockIdx.x * d.ev_q + e] = ev;
-            } else {
-                const uint32_t o = atomicAdd(&d.glob->ev_ovf, 1u);
-                if (o < (uint32_t)d.ev_ovf_cap) d.ev[(int64_t)d.n_push_blocks * d.ev_q + o] = ev;
-                else atomicOr(&d.instd[ev.inst].status, PIC_ST_CANDIDATES);
-            }
-        }
-        if (lds_cnt) {
-#pragma unroll
-            for (int c = 0; c < kNCnt; ++c)
-                if (cnt[c]) atomicAdd(&s_cnt[seg * kNCnt + c], cnt[c]);
-        } else {
-            add_counts(d.instd + d.segc[seg].inst, cnt);
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) d.ev_n[blockIdx.x] = min(s_en, (uint32_t)d.ev_q);
-    if (lds_cnt) {
-        // this block's own slot: plain read-modify-write, no other block touches it
-        unsigned long long *slot = d.cnt_slot + (int64_t)blockIdx.x * d.n_seg * kNCnt;
-        for (int q = threadIdx.x; q < d.n_seg * kNCnt; q += kBlock) {
-            const uint32_t v = s_cnt[q];
-            if (v) slot[q] += v;
-        }
-    }
+    if (c & (1u << kCCand)) atomicAdd(&idn->n_candidates, 1ull);
+    if (c & (1u << kCEl)) atomicAdd(&idn->n_elastic, 1ull);
+    if (c & (1u << kCIz)) atomicAdd(&idn->n_ionize, 1ull);
+    if (c & (1u << kCCx)) atomicAdd(&idn->n_cx, 1ull);
+    if (c & (1u << kCOver)) atomicAdd(&idn->n_over_cap, 1ull);
+    if (c & (1u << kCEx)) atomicAdd(&idn->n_excite, 1ull);
 }
 
 // ---------------------------------------------------------------------------
@@ -217,7 +146,9 @@ __device__ void build_event_index(EventIndex &X, const Dev &d)
 }
 
 // one block, once per step after the collisions: the prefix over the regions
-// and the totals, for every kernel after it
+// and the totals, for every kernel after it.  (A kernel of its own: folding
+// it into the collide kernel's last block costs a device-scope fence in every
+// block, which writes back L2 and is far slower than the launch.)
 __global__ __launch_bounds__(kBlock) void index_kernel(Dev d)
 {
     __shared__ EventIndex X;
@@ -250,6 +181,77 @@ __device__ __forceinline__ const IzEvent &event_at(const EventIndex &X, const De
         if (X.pre[mid] <= e) lo = mid; else hi = mid - 1;
     }
     return d.ev[(int64_t)lo * d.ev_q + (e - X.pre[lo])];
+}
+
+__global__ __launch_bounds__(kBlock) void collide_kernel(Dev d)
+{
+    extern __shared__ uint32_t s_cnt[];  // [n_seg][kNCnt] when n_seg <= kCntSegMax
+    __shared__ uint32_t s_en;
+    const bool lds_cnt = d.n_seg <= kCntSegMax;
+    if (lds_cnt)
+        for (int q = threadIdx.x; q < d.n_seg * kNCnt; q += kBlock) s_cnt[q] = 0u;
+    if (threadIdx.x == 0) s_en = 0u;
+    __syncthreads();
+
+    const int cur = d.glob->cur_set;
+    const bool f64 = (d.precision == PIC_FP64);
+    // this block's region of the candidate list (one part per mover wave),
+    // then a share of the overflow list
+    const uint32_t qw = (uint32_t)d.cand_q / kWaves;
+    uint32_t pre[kWaves + 1];
+    pre[0] = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) pre[w + 1] = pre[w] + d.cand_n[blockIdx.x * kWaves + w];
+    const uint32_t nr = pre[kWaves];
+    uint32_t novf = d.glob->cand_ovf;
+    if (novf > (uint32_t)d.cand_ovf_cap) novf = (uint32_t)d.cand_ovf_cap;
+    const uint32_t per_block = (novf + gridDim.x - 1) / gridDim.x;
+    const uint32_t o_lo = min(novf, blockIdx.x * per_block);
+    const uint32_t o_hi = min(novf, o_lo + per_block);
+    const uint32_t n_items = nr + (o_hi - o_lo);
+    for (uint32_t q = threadIdx.x; q < n_items; q += kBlock) {
+        uint32_t cnt = 0;  // one bit per process (1 << kC...)
+        bool iz = false;
+        IzEvent ev = {};
+        int64_t idx;
+        if (q < nr) {
+            int w = 0;
+#pragma unroll
+            for (int v = 1; v < kWaves; ++v) w += (q >= pre[v]) ? 1 : 0;
+            idx = (int64_t)blockIdx.x * d.cand_q + (int64_t)w * qw + (q - pre[w]);
+        } else {
+            idx = (int64_t)d.n_push_blocks * d.cand_q + o_lo + (q - nr);
+        }
+        const int seg = collide_one(d, cur, f64, d.cand[idx], cnt, iz, ev);
+        if (iz) {
+            // this block's region of the event list; the rare excess goes to the overflow list
+            const uint32_t e = atomicAdd(&s_en, 1u);
+            if (e < (uint32_t)d.ev_q) {
+                d.ev[(int64_t)blockIdx.x * d.ev_q + e] = ev;
+            } else {
+                const uint32_t o = atomicAdd(&d.glob->ev_ovf, 1u);
+                if (o < (uint32_t)d.ev_ovf_cap) d.ev[(int64_t)d.n_push_blocks * d.ev_q + o] = ev;
+                else atomicOr(&d.instd[ev.inst].status, PIC_ST_CANDIDATES);
+            }
+        }
+        if (lds_cnt) {
+#pragma unroll
+            for (int c = 0; c < kNCnt; ++c)
+                if (cnt & (1u << c)) atomicAdd(&s_cnt[seg * kNCnt + c], 1u);
+        } else {
+            add_counts(d.instd + d.segc[seg].inst, cnt);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) d.ev_n[blockIdx.x] = min(s_en, (uint32_t)d.ev_q);
+    if (lds_cnt) {
+        // this block's own slot: plain read-modify-write, no other block touches it
+        unsigned long long *slot = d.cnt_slot + (int64_t)blockIdx.x * d.n_seg * kNCnt;
+        for (int q = threadIdx.x; q < d.n_seg * kNCnt; q += kBlock) {
+            const uint32_t v = s_cnt[q];
+            if (v) slot[q] += v;
+        }
+    }
 }
 
 // write one created particle into segment `seg`, in-segment index `i`
@@ -648,19 +650,11 @@ __global__ __launch_bounds__(kBlock) void emit_kernel(Dev d)
     }
 }
 
-// close of the step (one block): counts, ids, wall-loss totals, step index
-__global__ __launch_bounds__(kBlock) void close_step_kernel(Dev d, int with_events)
+// close of the step (one block, all threads): counts, ids, wall-loss
+// totals, step index, and the per-step lists cleared
+__device__ void close_body(const Dev &d, const EventIndex &X, const uint32_t *s_m, int n_inst,
+                           bool with_events)
 {
-    __shared__ EventIndex X;
-    __shared__ uint32_t s_m[kMaxInstLds];
-    const int n_inst = d.n_inst < kMaxInstLds ? d.n_inst : kMaxInstLds;
-    if (with_events) {
-        load_event_index(X, d);
-        count_events(X, d, s_m, n_inst);
-    } else {
-        for (int i = threadIdx.x; i < n_inst; i += kBlock) s_m[i] = 0u;
-        __syncthreads();
-    }
     for (int i = threadIdx.x; i < d.n_inst; i += kBlock) {
         const InstConst &ic = d.instc[i];
         InstDyn *idn = d.instd + i;
@@ -711,6 +705,22 @@ __global__ __launch_bounds__(kBlock) void close_step_kernel(Dev d, int with_even
         for (int b = threadIdx.x; b < d.n_push_blocks; b += kBlock) d.ev_n[b] = 0u;
 }
 
+__global__ __launch_bounds__(kBlock) void close_step_kernel(Dev d, int with_events)
+{
+    __shared__ EventIndex X;
+    __shared__ uint32_t s_m[kMaxInstLds];
+    const int n_inst = d.n_inst < kMaxInstLds ? d.n_inst : kMaxInstLds;
+    if (with_events) {
+        load_event_index(X, d);
+        count_events(X, d, s_m, n_inst);
+    } else {
+        if (threadIdx.x == 0) X.total = 0u;
+        for (int i = threadIdx.x; i < n_inst; i += kBlock) s_m[i] = 0u;
+        __syncthreads();
+    }
+    close_body(d, X, s_m, n_inst, with_events != 0);
+}
+
 hipError_t launch_collide(const Dev &d, hipStream_t st)
 {
     const size_t lds = d.n_seg <= kCntSegMax ? sizeof(uint32_t) * d.n_seg * kNCnt : 0;
@@ -720,7 +730,7 @@ hipError_t launch_collide(const Dev &d, hipStream_t st)
 
 hipError_t launch_emit(const Dev &d, hipStream_t st, bool pairs, bool events)
 {
-    if (events || pairs) {
+    if (events) {
         hipLaunchKernelGGL(index_kernel, dim3(1), dim3(kBlock), 0, st, d);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
