@@ -197,3 +197,26 @@ def test_full_size_table1_decay_law_fp32():
         assert d.n_live[0] == Ne0 + (N0 - N) and d.n_live[1] == n + (N0 - N)
     assert N0 - N > 0.1 * N0
     sim.close()
+
+
+@pytest.mark.parametrize("case", ["walls_field_on", "subcycled_atoms"])
+def test_table1_variants_fp64(case):
+    """Kinetic atoms between absorbing walls with the field solved (particles
+    lost to the walls), and atoms pushed every 4 steps
+    (the reach of the cell-offset search takes the subcycle into account)."""
+    if case == "walls_field_on":
+        wl = table1_small(nc=180, seed=47, field_off=False).replace(bc=pin.BC_ABSORB)
+    else:
+        wl = table1_small(nc=160, seed=48)
+        wl.species[2].nstep = 4
+    st = pin.initial_state(wl)
+    flush(f"table1 variant {case} fp64")
+    sim, orc, ost = build_pair(wl, FP64, caps=caps_for(wl, st), flags=P.PIC_INIT_SORT, state=st)
+    sim.step(25, sort_every=10)
+    orc.step(25)
+    c = orc.counters
+    assert c.n_consumed > 20
+    if case == "walls_field_on":
+        assert sum(c.absorbed_total[0][w] for w in range(2)) > 0  # electrons reached the walls
+    _compare_fp64(sim, orc, wl)
+    sim.close()
