@@ -220,3 +220,27 @@ def test_table1_variants_fp64(case):
         assert sum(c.absorbed_total[0][w] for w in range(2)) > 0  # electrons reached the walls
     _compare_fp64(sim, orc, wl)
     sim.close()
+
+
+def test_many_kinetic_instances_fp64():
+    """350 small Table 1 instances (1050 segments, beyond the LDS tables):
+    every instance's counts against its own oracle, ids for a sample."""
+    wls = [table1_small(nc=30 + (i % 9) * 4, ppc=24, ppc_n=24, seed=100 + i) for i in range(350)]
+    states = [pin.initial_state(w) for w in wls]
+    caps = [caps_for(w, s) for w, s in zip(wls, states)]
+    flush("350 kinetic instances, 1050 segments")
+    sim = P.PicSim(wls, states, FP64, capacities=caps, flags=P.PIC_INIT_SORT)
+    sim.step(10, sort_every=5)
+    d, rc = sim.diagnostics()
+    assert rc == 0
+    consumed = 0
+    for i, (w, s) in enumerate(zip(wls, states)):
+        orc = oracle.OracleSim(w, s, caps=caps[i], inst=i)
+        orc.step(10)
+        if i % 25 == 0:
+            _compare_fp64(sim, orc, w, inst=i, d=d)
+        else:
+            assert _counts(d[i]) == _orc_counts(orc.counters), i
+        consumed += orc.counters.n_consumed
+    assert consumed > 100
+    sim.close()

@@ -507,3 +507,36 @@ def test_subcycled_ions(prec):
         for k in range(2):
             assert abs(d.ke[k] / od.ke[k] - 1) <= 5e-3
     sim.close()
+
+
+def test_more_segments_than_the_lds_tables_fp64():
+    """600 small instances (1200 segments): more segments than the movers, the
+    sort and the collide kernel stage in LDS (1024), so their global-memory
+    paths run.  Every instance against its own oracle: identical ids and
+    process counts."""
+    wls = pin.batched(n_inst=600, seed=61, nc_min=32, nc_ratio=2.0, ppc_range=(20.0, 40.0))
+    for w in wls:
+        w.mcc.n_n *= 20  # collisions in every instance
+    states = [pin.initial_state(w) for w in wls]
+    caps = [pin.capacities(w, s) for w, s in zip(wls, states)]
+    flush("600 instances, 1200 segments")
+    sim = P.PicSim(wls, states, FP64, capacities=caps, flags=P.PIC_INIT_SORT)
+    sim.step(12, sort_every=6)
+    d, rc = sim.diagnostics()
+    assert rc == 0
+    tot = 0
+    for i, (w, s) in enumerate(zip(wls, states)):
+        orc = oracle.OracleSim(w, s, caps=caps[i], inst=i)
+        orc.step(12)
+        c = orc.counters
+        assert (d[i].n_candidates, d[i].n_elastic, d[i].n_ionize, d[i].n_cx) == \
+            (c.n_candidates, c.n_elastic, c.n_ionize, c.n_cx), i
+        tot += c.n_elastic
+        if i % 37 == 0:
+            for k in range(2):
+                g = by_id(sim.state(k, inst=i))
+                o = oracle_state(orc, k)
+                assert np.array_equal(g["id"], o["id"]), (i, k)
+                assert np.max(np.abs(g["x"] - o["x"]), initial=0.0) <= 1e-7
+    assert tot > 1000
+    sim.close()
