@@ -266,10 +266,40 @@ __global__ __launch_bounds__(kBlock) void sort_scan_kernel(Dev d)
     }
 }
 
-template <typename T>
-__device__ __forceinline__ void mv(void *dst, const void *src, int64_t to, int64_t from)
+// copy the fields of a wave's kPer chunks (slot g0 + 64 k) to slots to[k]
+// (-1: none) of the other set: all loads, then all stores
+template <typename V, bool CELL>
+__device__ __forceinline__ void move_fields(const Dev &d, int cur, int nxt, int64_t g0,
+                                            const int64_t (&to)[kPer])
 {
-    ((T *)dst)[to] = ((const T *)src)[from];
+    V x[kPer], vx[kPer], vy[kPer], vz[kPer];
+    int32_t c[kPer];
+    unsigned long long id[kPer];
+    const V *X = (const V *)d.x[cur], *VX = (const V *)d.vx[cur], *VY = (const V *)d.vy[cur],
+            *VZ = (const V *)d.vz[cur];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        if (to[k] < 0) continue;
+        const int64_t g = g0 + (int64_t)k * 64;
+        x[k] = X[g];
+        vx[k] = VX[g];
+        vy[k] = VY[g];
+        vz[k] = VZ[g];
+        if (CELL) c[k] = d.cell[cur][g];
+        id[k] = d.id[cur][g];
+    }
+    V *Xn = (V *)d.x[nxt], *VXn = (V *)d.vx[nxt], *VYn = (V *)d.vy[nxt], *VZn = (V *)d.vz[nxt];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        if (to[k] < 0) continue;
+        const int64_t t = to[k];
+        Xn[t] = x[k];
+        VXn[t] = vx[k];
+        VYn[t] = vy[k];
+        VZn[t] = vz[k];
+        if (CELL) d.cell[nxt][t] = c[k];
+        d.id[nxt][t] = id[k];
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void sort_scatter_kernel(Dev d)
@@ -331,30 +361,28 @@ __global__ __launch_bounds__(kBlock) void sort_scatter_kernel(Dev d)
             }
         }
         __syncthreads();
+        // destinations; then every field of the tile's particles is loaded
+        // before any is stored (a store to the other set could alias a later
+        // load in the compiler's view, which would otherwise keep each load
+        // waiting behind the previous store)
+        int64_t to[kPer];
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
+            to[k] = -1;
             if (key[k] < 0) continue;
-            const int64_t g = base + t0 + (int64_t)(wave * kPer + k) * 64 + lane;
             const uint32_t pos = outside[k] ? rank[k] : L.base[key[k] - lo] + rank[k];
             const uint32_t rel = pos - start;
             if (rel >= sc.cap) {  // cannot happen with a consistent histogram
                 atomicOr(&d.instd[sc.inst].status, PIC_ST_INTERNAL);
                 continue;
             }
-            const int64_t to = sc.base + (int64_t)rel;
-            if (f64) {
-                mv<double>(d.x[nxt], d.x[cur], to, g);
-                mv<double>(d.vx[nxt], d.vx[cur], to, g);
-                mv<double>(d.vy[nxt], d.vy[cur], to, g);
-                mv<double>(d.vz[nxt], d.vz[cur], to, g);
-            } else {
-                mv<float>(d.x[nxt], d.x[cur], to, g);
-                mv<int32_t>(d.cell[nxt], d.cell[cur], to, g);
-                mv<float>(d.vx[nxt], d.vx[cur], to, g);
-                mv<float>(d.vy[nxt], d.vy[cur], to, g);
-                mv<float>(d.vz[nxt], d.vz[cur], to, g);
-            }
-            mv<unsigned long long>(d.id[nxt], d.id[cur], to, g);
+            to[k] = sc.base + (int64_t)rel;
+        }
+        const int64_t g0 = base + t0 + (int64_t)(wave * kPer) * 64 + lane;
+        if (f64) {
+            move_fields<double, false>(d, cur, nxt, g0, to);
+        } else {
+            move_fields<float, true>(d, cur, nxt, g0, to);
         }
         if (sc.kind == PIC_KIND_NEUTRAL) {
             unsigned long long vb = 0ull;
