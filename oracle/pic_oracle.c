@@ -16,7 +16,10 @@
  *   - Sec. 6, the moveb listing: linear gather a[j] + x (a[j+1] - a[j]) with
  *     the in-cell coordinate x, velocity kick, position advance x += nstep*vx;
  *   - Sec. 2, "natural sorting" (particles grouped by cell): the oracle never
- *     needs it, every result here is independent of particle order.
+ *     needs it, every result here is independent of particle order;
+ *   - Sec. 3.4 (Table 1 and the text after it), the test case: electrons,
+ *     D+ ions and kinetic D atoms, no field solver, electron-atom elastic,
+ *     excitation and ionisation, the gas depleting by dn/dt = -n n_e R.
  * Where the paper is silent (magnetised Boris rotation, the null-collision
  * Monte Carlo, Philox draws keyed by particle id and step, fixed-point
  * deposition, wall-node closure, the pair source and ids of created
