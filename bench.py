@@ -340,7 +340,7 @@ def main():
     ap.add_argument("--nc", type=int, default=100_000)
     ap.add_argument("--ppc", type=float, default=100)
     ap.add_argument("--push-steps", type=int, default=40)
-    ap.add_argument("--cpu-steps", type=int, default=5)
+    ap.add_argument("--cpu-steps", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
