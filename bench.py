@@ -141,6 +141,27 @@ def copy_calibration():
                       "launches": 5}), flush=True)
 
 
+def copy_rate(torch):
+    """HBM bandwidth a plain copy reaches (torch.neg, 1 GiB in and 1 GiB out),
+    timed with HIP events over 5 launches after one warm-up: what a streaming
+    kernel attains on this GPU, beside the 8 TB/s peak."""
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.neg(src, out=dst)
+    st = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(5):
+        torch.neg(src, out=dst)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 5
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * COPY_BYTES / (ms * 1e-3) / 1e9
+
+
 def _pmc_rows(d, kernel_sub, counter):
     """Per-dispatch values of `counter` for kernels whose name contains
     `kernel_sub`, from a rocprofv3 --pmc CSV directory."""
@@ -401,11 +422,14 @@ def main():
     torch.cuda.empty_cache()
 
     achieved = PUSH_BYTES_FP32 * per_launch / (push_ms * 1e-3) / 1e9
+    copy_gbs = copy_rate(torch)
+    log(f"plain copy: {copy_gbs:.0f} GB/s (mover at {achieved / copy_gbs:.2f} of it)")
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile(),
             "kernel": "push_f32_kernel<true,true> (mover + deposit + candidate list)",
             "bytes_per_particle": PUSH_BYTES_FP32,
-            "particles_per_launch": int(per_launch), "us_per_launch": round(push_ms * 1e3, 2)}
+            "particles_per_launch": int(per_launch), "us_per_launch": round(push_ms * 1e3, 2),
+            "copy_GBps": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
 
     fp64 = None
     if not args.no_fp64:
