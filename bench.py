@@ -372,6 +372,8 @@ def main():
     ap.add_argument("--layout-study", action="store_true",
                     help="run only the particle-layout study of the mover and print its JSON object")
     ap.add_argument("--layout-passes", type=int, default=40)
+    ap.add_argument("--only-batched", action="store_true",
+                    help="run only the batched workload and print its JSON object (profiling)")
     ap.add_argument("--only-table1", action="store_true",
                     help="run only the Table 1 workload and print its JSON object (profiling)")
     ap.add_argument("--eager", action="store_true",
@@ -402,6 +404,9 @@ def main():
         return
     if args.layout_study:
         print(json.dumps({"layout_study": layout_study(torch, args)}), flush=True)
+        return
+    if args.only_batched:
+        print(json.dumps(batched(torch, args)), flush=True)
         return
     if args.only_table1:
         print(json.dumps(table1_run(torch, args)), flush=True)

@@ -328,6 +328,10 @@ int plan(const pic_config *cfgs, int n_inst, Plan &p)
     L.ev_target = take(sizeof(long long) * ((uint64_t)p.n_push_blocks * L.ev_q + L.ev_ovf_cap));
     L.nn = take(sizeof(double) * p.G);
     L.ev_pre = take(sizeof(uint32_t) * ((uint64_t)p.n_push_blocks + 1));
+    L.inst_ev = take(sizeof(uint32_t) * n_inst);
+    L.inst_fill = take(sizeof(uint32_t) * n_inst);
+    L.inst_start = take(sizeof(uint32_t) * (n_inst + 1));
+    L.rank_bucket = take(sizeof(RankEntry) * ((uint64_t)p.n_push_blocks * L.ev_q + L.ev_ovf_cap));
     L.cnt_slot = take(sizeof(unsigned long long) * (uint64_t)p.n_push_blocks *
                       (n_seg <= kCntSegMax ? n_seg : 0) * kNCnt);
     L.diag_part = take(sizeof(double) * (uint64_t)kDiagBlocks * n_seg * kDiagVals);
@@ -527,6 +531,10 @@ int pic_init(const pic_config *cfgs, int n_inst, const pic_buffers *bufs, void *
     d.ev_target = at<long long>(W, L.ev_target);
     d.nn = at<double>(W, L.nn);
     d.ev_pre = at<uint32_t>(W, L.ev_pre);
+    d.inst_ev = at<uint32_t>(W, L.inst_ev);
+    d.inst_fill = at<uint32_t>(W, L.inst_fill);
+    d.inst_start = at<uint32_t>(W, L.inst_start);
+    d.rank_bucket = at<RankEntry>(W, L.rank_bucket);
     d.cnt_slot = at<unsigned long long>(W, L.cnt_slot);
     d.diag_part = at<double>(W, L.diag_part);
     d.diag_out = at<pic_diag>(W, L.diag_out);

@@ -388,6 +388,99 @@ __global__ __launch_bounds__(kBlock) void rank_kernel(Dev d)
 }
 
 // ---------------------------------------------------------------------------
+// The same ranks for a batch of instances, where events of different
+// instances are never compared: the events are counted per instance, the
+// counts scanned, each event's (parent id, cell, index) placed in its
+// instance's bucket, and every event ranked against its own bucket only
+// (sum of m_i^2 comparisons instead of m^2).  Launched when n_inst > 1.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void bucket_count_kernel(Dev d)
+{
+    if ((uint64_t)blockIdx.x * kBlock >= d.glob->ev_total) return;
+    __shared__ EventIndex X;
+    load_event_index(X, d);
+    for (uint32_t e = blockIdx.x * kBlock + threadIdx.x; e < X.total; e += gridDim.x * kBlock)
+        atomicAdd(&d.inst_ev[event_at(X, d, e).inst], 1u);
+}
+
+// one block: inst_start = exclusive prefix of the per-instance counts (which
+// are cleared for the next step, as are the fill counters)
+__global__ __launch_bounds__(kBlock) void bucket_scan_kernel(Dev d)
+{
+    __shared__ uint32_t s_w[kWaves];
+    __shared__ uint32_t s_carry;
+    if (threadIdx.x == 0) s_carry = 0u;
+    __syncthreads();
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    for (int base = 0; base < d.n_inst; base += kBlock) {
+        const int i = base + threadIdx.x;
+        const uint32_t v = i < d.n_inst ? d.inst_ev[i] : 0u;
+        uint32_t inc = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t t = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += t;
+        }
+        if (lane == 63) s_w[wave] = inc;
+        __syncthreads();
+        uint32_t run = s_carry + inc - v;
+        for (int w = 0; w < wave; ++w) run += s_w[w];
+        if (i < d.n_inst) {
+            d.inst_start[i] = run;
+            d.inst_ev[i] = 0u;
+            d.inst_fill[i] = 0u;
+        }
+        __syncthreads();
+        if (threadIdx.x == kBlock - 1) s_carry = run + v;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) d.inst_start[d.n_inst] = s_carry;
+}
+
+__global__ __launch_bounds__(kBlock) void bucket_fill_kernel(Dev d)
+{
+    if ((uint64_t)blockIdx.x * kBlock >= d.glob->ev_total) return;
+    __shared__ EventIndex X;
+    load_event_index(X, d);
+    for (uint32_t e = blockIdx.x * kBlock + threadIdx.x; e < X.total; e += gridDim.x * kBlock) {
+        const IzEvent &ev = event_at(X, d, e);
+        const uint32_t q = d.inst_start[ev.inst] + atomicAdd(&d.inst_fill[ev.inst], 1u);
+        RankEntry r;
+        r.pid = ev.parent_id;
+        r.cell = ev.cell;
+        r.e = e;
+        d.rank_bucket[q] = r;
+    }
+}
+
+// every event against the entries of its instance's bucket
+__global__ __launch_bounds__(kBlock) void bucket_rank_kernel(Dev d)
+{
+    if ((uint64_t)blockIdx.x * kBlock >= d.glob->ev_total) return;
+    const uint32_t m = d.glob->ev_total;
+    const bool cells = d.kinetic_any != 0;
+    for (uint32_t q = blockIdx.x * kBlock + threadIdx.x; q < m; q += gridDim.x * kBlock) {
+        const RankEntry me = d.rank_bucket[q];
+        // the instance owning bucket entry q
+        int lo = 0, hi = d.n_inst - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (d.inst_start[mid] <= q) lo = mid; else hi = mid - 1;
+        }
+        const uint32_t b0 = d.inst_start[lo], b1 = d.inst_start[lo + 1];
+        uint32_t r = 0, rc = 0;
+        for (uint32_t k = b0; k < b1; ++k) {
+            const RankEntry o = d.rank_bucket[k];
+            const bool less = o.pid < me.pid;
+            r += less ? 1u : 0u;
+            rc += (less && o.cell == me.cell) ? 1u : 0u;
+        }
+        d.ev_rank[me.e] = r;
+        if (cells) d.ev_crank[me.e] = rc;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Kinetic neutrals: the atom each ionisation event consumes.  Event e of
 // instance i in cell j, with rank q among the events of (i, j), takes the
 // (q+1)-th smallest (key, id) among the live atoms in cell j, where key is
@@ -736,8 +829,16 @@ hipError_t launch_emit(const Dev &d, hipStream_t st, bool pairs, bool events)
         if (e != hipSuccess) return e;
     }
     if (events) {
-        hipLaunchKernelGGL(rank_kernel, dim3(kRankBlocks), dim3(kBlock), 0, st, d);
-        hipError_t e = hipGetLastError();
+        hipError_t e;
+        if (d.n_inst > 1) {
+            hipLaunchKernelGGL(bucket_count_kernel, dim3(kRankBlocks), dim3(kBlock), 0, st, d);
+            hipLaunchKernelGGL(bucket_scan_kernel, dim3(1), dim3(kBlock), 0, st, d);
+            hipLaunchKernelGGL(bucket_fill_kernel, dim3(kRankBlocks), dim3(kBlock), 0, st, d);
+            hipLaunchKernelGGL(bucket_rank_kernel, dim3(kRankBlocks), dim3(kBlock), 0, st, d);
+        } else {
+            hipLaunchKernelGGL(rank_kernel, dim3(kRankBlocks), dim3(kBlock), 0, st, d);
+        }
+        e = hipGetLastError();
         if (e != hipSuccess) return e;
         if (d.kinetic_any) {
             hipLaunchKernelGGL(target_kernel, dim3(kTargetBlocks), dim3(kBlock), 0, st, d);

@@ -154,6 +154,13 @@ struct IzEvent {
     double g2;              // speed of the secondary electron, cells/step
 };
 
+// an ionisation event in its instance's bucket (ranks of a batch)
+struct RankEntry {
+    unsigned long long pid;
+    int32_t cell;
+    uint32_t e;             // the event's index in the step's event list
+};
+
 // composite y -> A y + B of the maps of one tile of an affine (Thomas) sweep
 struct AffineStatus {
     double A, B;
@@ -171,6 +178,7 @@ struct Layout {
     uint64_t fe_part;
     uint64_t cand, cand_n, ev, ev_n, ev_rank, cnt_slot;
     uint64_t nn, ev_crank, ev_target, ev_pre;
+    uint64_t inst_ev, inst_fill, inst_start, rank_bucket;
     uint64_t diag_part, diag_out;
     uint64_t total;
     int64_t cand_ovf_cap, ev_ovf_cap;
@@ -214,6 +222,9 @@ struct Dev {
     long long *ev_target;       // [events] slot of the atom an event consumes, or -1
     double *nn;                 // [G] density of the kinetic neutrals [m^-3]
     uint32_t *ev_pre;           // [n_push_blocks+1] first event of each region (index_kernel)
+    // ranks of a batch: events per instance, fill counters, bucket starts, buckets
+    uint32_t *inst_ev, *inst_fill, *inst_start;   // [n_inst], [n_inst], [n_inst+1]
+    RankEntry *rank_bucket;                        // [events]
     unsigned long long *cnt_slot;  // [n_push_blocks][n_seg][kNCnt] process counts per block
     double *diag_part;
     pic_diag *diag_out;
