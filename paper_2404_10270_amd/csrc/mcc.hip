@@ -42,7 +42,7 @@ __device__ __forceinline__ int collide_one(const Dev &d, int cur, bool f64, cons
                                            uint32_t &cnt, bool &iz, IzEvent &ev)
 {
     const int64_t g = c.g;
-    const int seg = seg_of_slot(d.seg_base, d.n_seg, g);
+    const int seg = c.seg;  // the mover's segment of the candidate
     const SegConst &sc = d.segc[seg];
     const long long step = d.instd[sc.inst].step;
     double vx = c.vx, vy = c.vy, vz = c.vz;

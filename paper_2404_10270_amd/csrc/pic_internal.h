@@ -139,7 +139,7 @@ enum ScanId { kScanSort = 2 };
 // push (cells/step, exact in FP64 for both forms) and its id
 struct Cand {
     uint32_t g;
-    uint32_t _pad;
+    int32_t seg;            // its segment
     double vx, vy, vz;
     unsigned long long pid;
 };

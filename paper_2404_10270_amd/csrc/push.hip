@@ -167,8 +167,8 @@ __device__ __forceinline__ void deposit_positions(PushLds &L, const Dev &d, int 
 // global atomic is needed; a wave whose part is full appends the excess to
 // the shared overflow list.
 template <typename V>
-__device__ __forceinline__ void queue_candidate(const Dev &d, bool cand, uint32_t g, int inst, V vx,
-                                                V vy, V vz, unsigned long long pid, uint32_t &wn)
+__device__ __forceinline__ void queue_candidate(const Dev &d, bool cand, uint32_t g, int seg, int inst,
+                                                V vx, V vy, V vz, unsigned long long pid, uint32_t &wn)
 {
     const unsigned long long m = ballot(cand);
     if (!m) return;
@@ -201,7 +201,7 @@ __device__ __forceinline__ void queue_candidate(const Dev &d, bool cand, uint32_
     }
     Cand c;
     c.g = g;
-    c._pad = 0;
+    c.seg = seg;
     c.vx = (double)vx;
     c.vy = (double)vy;
     c.vz = (double)vz;
@@ -402,7 +402,7 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
 #pragma unroll
             for (int k = 0; k < kPer; ++k) {
                 const uint32_t o = (uint32_t)((wave * kPer + k) * 64 + lane);
-                queue_candidate(d, cand[k], (uint32_t)(tb + o), inst, vx[k], vy[k], vz[k], pid[k], wn);
+                queue_candidate(d, cand[k], (uint32_t)(tb + o), seg, inst, vx[k], vy[k], vz[k], pid[k], wn);
             }
         }
         if (DEP) deposit_tile<kPer>(L, S, key, w1);
@@ -579,7 +579,7 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
 #pragma unroll
             for (int k = 0; k < kPer; ++k) {
                 const uint32_t o = (uint32_t)((wave * kPer + k) * 64 + lane);
-                queue_candidate(d, cand[k], (uint32_t)(tb + o), inst, vx[k], vy[k], vz[k], pid[k], wn);
+                queue_candidate(d, cand[k], (uint32_t)(tb + o), seg, inst, vx[k], vy[k], vz[k], pid[k], wn);
             }
         }
         if (DEP) deposit_tile<kPer>(L, S, key, w1);

@@ -163,19 +163,6 @@ __device__ __forceinline__ void st_rel(unsigned long long *p, unsigned long long
     __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// raw scan position of the first bin of segment `seg`: the live particles of
-// the segments whose bins come earlier (bins are species-major, then instance)
-__device__ unsigned long long seg_raw_start(const Dev &d, int seg)
-{
-    const SegConst &sc = d.segc[seg];
-    unsigned long long s = 0;
-    for (int q = 0; q < d.n_seg; ++q) {
-        const SegConst &o = d.segc[q];
-        if (o.sp < sc.sp || (o.sp == sc.sp && o.inst < sc.inst)) s += d.segd[q].live;
-    }
-    return s;
-}
-
 __global__ __launch_bounds__(kBlock) void sort_scan_kernel(Dev d)
 {
     __shared__ uint32_t s_t;
@@ -430,11 +417,41 @@ __global__ void sort_finish_kernel(Dev d)
     }
 }
 
-__global__ void sort_start_kernel(Dev d)
+// one block: the raw scan position of every segment, an exclusive prefix of
+// the live counts in bin order (species-major, then instance)
+__global__ __launch_bounds__(kBlock) void sort_start_kernel(Dev d)
 {
-    for (int s = threadIdx.x; s < d.n_seg; s += blockDim.x) {
-        d.seg_start[s] = seg_raw_start(d, s);
-        d.segd[s].vmax_bits = 0ull;
+    __shared__ unsigned long long s_w[kWaves];
+    __shared__ unsigned long long s_carry;
+    if (threadIdx.x == 0) s_carry = 0ull;
+    __syncthreads();
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    for (int base = 0; base < d.n_seg; base += kBlock) {
+        const int q = base + threadIdx.x;  // position in bin order: q = sp * n_inst + inst
+        int s = -1;
+        unsigned long long v = 0ull;
+        if (q < d.n_seg) {
+            const int sp = q / d.n_inst, inst = q - sp * d.n_inst;
+            s = inst * d.nsp + sp;
+            v = d.segd[s].live;
+        }
+        unsigned long long inc = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned long long t = shfl_up_u64(inc, o);
+            if (lane >= o) inc += t;
+        }
+        if (lane == 63) s_w[wave] = inc;
+        __syncthreads();
+        unsigned long long run = s_carry + inc - v;
+        for (int w = 0; w < wave; ++w) run += s_w[w];
+        if (s >= 0) {
+            d.seg_start[s] = run;
+            d.segd[s].vmax_bits = 0ull;
+        }
+        __syncthreads();
+        if (threadIdx.x == kBlock - 1) s_carry = run + v;
+        __syncthreads();
     }
 }
 
