@@ -299,23 +299,10 @@ __device__ void count_events(const EventIndex &X, const Dev &d, uint32_t *s_m, i
         __syncthreads();
         return;
     }
-    for (int i = threadIdx.x; i < n_inst; i += kBlock) s_m[i] = 0u;
-    __syncthreads();
-    // region by region (no index search): thread t takes regions t, t + kBlock, ...
-    for (int b = threadIdx.x; b < d.n_push_blocks; b += kBlock) {
-        const uint32_t n = X.pre[b + 1] - X.pre[b];
-        const IzEvent *r = d.ev + (int64_t)b * d.ev_q;
-        for (uint32_t e = 0; e < n; ++e) {
-            const int inst = r[e].inst;
-            if (inst < n_inst) atomicAdd(&s_m[inst], 1u);
-        }
-    }
-    const uint32_t n_ovf = X.total - X.in_regions;
-    const IzEvent *o = d.ev + (int64_t)d.n_push_blocks * d.ev_q;
-    for (uint32_t e = threadIdx.x; e < n_ovf; e += kBlock) {
-        const int inst = o[e].inst;
-        if (inst < n_inst) atomicAdd(&s_m[inst], 1u);
-    }
+    // a batch: the bucket scan of this step holds the counts (it runs
+    // whenever there are events and more than one instance)
+    for (int i = threadIdx.x; i < n_inst; i += kBlock)
+        s_m[i] = X.total ? d.inst_start[i + 1] - d.inst_start[i] : 0u;
     __syncthreads();
 }
 
@@ -699,15 +686,34 @@ __global__ __launch_bounds__(kBlock) void emit_kernel(Dev d)
     const int n_inst = d.n_inst < kMaxInstLds ? d.n_inst : kMaxInstLds;
     __syncthreads();
     count_events(X, d, s_m, n_inst);
-    if (threadIdx.x == 0) {
-        uint32_t acc = 0;
-        for (int i = 0; i < n_inst; ++i) {
-            s_pre[i] = acc;
-            acc += source_pairs(d, i);
+    {
+        // s_pre = exclusive prefix of the instances' source pairs (block scan)
+        __shared__ uint32_t s_w[kWaves];
+        __shared__ uint32_t s_carry;
+        if (threadIdx.x == 0) s_carry = 0u;
+        __syncthreads();
+        const int lane = lane_id(), wave = threadIdx.x >> 6;
+        for (int base = 0; base < n_inst; base += kBlock) {
+            const int i = base + threadIdx.x;
+            const uint32_t v = i < n_inst ? source_pairs(d, i) : 0u;
+            uint32_t inc = v;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t t = __shfl_up(inc, o, 64);
+                if (lane >= o) inc += t;
+            }
+            if (lane == 63) s_w[wave] = inc;
+            __syncthreads();
+            uint32_t run = s_carry + inc - v;
+            for (int w = 0; w < wave; ++w) run += s_w[w];
+            if (i < n_inst) s_pre[i] = run;
+            __syncthreads();
+            if (threadIdx.x == kBlock - 1) s_carry = run + v;
+            __syncthreads();
         }
-        s_pre[n_inst] = acc;
+        if (threadIdx.x == 0) s_pre[n_inst] = s_carry;
+        __syncthreads();
     }
-    __syncthreads();
     const uint32_t n_src_all = s_pre[n_inst];
     for (uint32_t q = blockIdx.x * kBlock + threadIdx.x; q < n_src_all; q += stride) {
         int lo = 0, hi = n_inst - 1;
