@@ -86,18 +86,29 @@ __device__ __forceinline__ int64_t uniform_i64(int64_t v)
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-// (segment, first slot, occupied slots, flags) of virtual tile t
+// (segment, first slot, occupied slots, flags) of virtual tile t.  hint:
+// the segment of the block's previous tile (tiles only increase), so a few
+// steps forward usually find it; otherwise a binary search.
 __device__ __forceinline__ int tile_seg(const PushLds &L, const Dev &d, int64_t t, int64_t &tile0,
-                                        int64_t &base, int64_t &count, uint32_t &flags)
+                                        int64_t &base, int64_t &count, uint32_t &flags, int &hint)
 {
     int seg;
     if (d.n_seg <= kSegLds) {
-        int lo = 0, hi = d.n_seg - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (L.tile0[mid] <= t) lo = mid; else hi = mid - 1;
+        int s = hint, steps = 0;
+        while (s + 1 < d.n_seg && L.tile0[s + 1] <= t && steps < 8) {
+            ++s;
+            ++steps;
         }
-        seg = lo;
+        if (s + 1 < d.n_seg && L.tile0[s + 1] <= t) {
+            int lo = s, hi = d.n_seg - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (L.tile0[mid] <= t) lo = mid; else hi = mid - 1;
+            }
+            s = lo;
+        }
+        seg = __builtin_amdgcn_readfirstlane(s);
+        hint = seg;
         tile0 = L.tile0[seg];
         base = L.base[seg];
         count = L.count[seg];
@@ -235,10 +246,11 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
     const int wave = threadIdx.x >> 6;
     uint32_t wn = 0;  // this wave's candidates so far (uniform)
 
+    int hint = 0;  // segment of the previous tile
     for (int64_t t = blockIdx.x; t < d.n_tiles; t += gridDim.x) {
         int64_t tile0, base, count;
         uint32_t flg;
-        const int seg = tile_seg(L, d, t, tile0, base, count, flg);
+        const int seg = tile_seg(L, d, t, tile0, base, count, flg, hint);
         const int64_t t0 = (t - tile0) * (int64_t)kTile;
         if (t0 >= count) continue;
         // a subcycled species between its pushes keeps its positions (their
@@ -429,10 +441,11 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
     const int wave = threadIdx.x >> 6;
     uint32_t wn = 0;  // this wave's candidates so far (uniform)
 
+    int hint = 0;  // segment of the previous tile
     for (int64_t t = blockIdx.x; t < d.n_tiles; t += gridDim.x) {
         int64_t tile0, base, count;
         uint32_t flg;
-        const int seg = tile_seg(L, d, t, tile0, base, count, flg);
+        const int seg = tile_seg(L, d, t, tile0, base, count, flg, hint);
         const int64_t t0 = (t - tile0) * (int64_t)kTile;
         if (t0 >= count) continue;
         // a subcycled species between its pushes keeps its positions (their
@@ -597,10 +610,11 @@ __global__ __launch_bounds__(kBlock) void deposit_kernel(Dev d)
     __shared__ PushLds L;
     push_lds_init(L, d);
     const int cur = d.glob->cur_set;
+    int hint = 0;  // segment of the previous tile
     for (int64_t t = blockIdx.x; t < d.n_tiles; t += gridDim.x) {
         int64_t tile0, base, count;
         uint32_t flg;
-        const int seg = tile_seg(L, d, t, tile0, base, count, flg);
+        const int seg = tile_seg(L, d, t, tile0, base, count, flg, hint);
         const int64_t t0 = (t - tile0) * (int64_t)kTile;
         if (t0 >= count) continue;
         if (ONLY_STILL && !still(d, seg)) continue;

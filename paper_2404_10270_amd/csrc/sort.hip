@@ -47,17 +47,28 @@ __device__ __forceinline__ void sort_lds_init(SortLds &L, const Dev &d)
     __syncthreads();
 }
 
+// hint: the segment of the block's previous tile (tiles only increase)
 __device__ __forceinline__ int sort_tile_seg(const SortLds &L, const Dev &d, int64_t t,
-                                             int64_t &tile0, int64_t &base, int64_t &count)
+                                             int64_t &tile0, int64_t &base, int64_t &count,
+                                             int &hint)
 {
     int seg;
     if (d.n_seg <= kSegLdsS) {
-        int lo = 0, hi = d.n_seg - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (L.tile0[mid] <= t) lo = mid; else hi = mid - 1;
+        int s = hint, steps = 0;
+        while (s + 1 < d.n_seg && L.tile0[s + 1] <= t && steps < 8) {
+            ++s;
+            ++steps;
         }
-        seg = lo;
+        if (s + 1 < d.n_seg && L.tile0[s + 1] <= t) {
+            int lo = s, hi = d.n_seg - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (L.tile0[mid] <= t) lo = mid; else hi = mid - 1;
+            }
+            s = lo;
+        }
+        seg = __builtin_amdgcn_readfirstlane(s);
+        hint = seg;
         tile0 = L.tile0[seg];
         base = L.sbase[seg];
         count = L.count[seg];
@@ -119,9 +130,10 @@ __global__ __launch_bounds__(kBlock) void sort_hist_kernel(Dev d)
     const bool f64 = (d.precision == PIC_FP64);
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
+    int hint = 0;  // segment of the previous tile
     for (int64_t t = blockIdx.x; t < d.n_tiles; t += gridDim.x) {
         int64_t tile0, base, count;
-        const int seg = sort_tile_seg(L, d, t, tile0, base, count);
+        const int seg = sort_tile_seg(L, d, t, tile0, base, count, hint);
         const int64_t t0 = (t - tile0) * (int64_t)kTile;
         if (t0 >= count) continue;
         const SegConst &sc = d.segc[seg];
@@ -298,9 +310,10 @@ __global__ __launch_bounds__(kBlock) void sort_scatter_kernel(Dev d)
     const bool f64 = (d.precision == PIC_FP64);
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
+    int hint = 0;  // segment of the previous tile
     for (int64_t t = blockIdx.x; t < d.n_tiles; t += gridDim.x) {
         int64_t tile0, base, count;
-        const int seg = sort_tile_seg(L, d, t, tile0, base, count);
+        const int seg = sort_tile_seg(L, d, t, tile0, base, count, hint);
         const int64_t t0 = (t - tile0) * (int64_t)kTile;
         if (t0 >= count) continue;
         const SegConst &sc = d.segc[seg];
