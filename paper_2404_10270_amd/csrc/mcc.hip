@@ -145,8 +145,8 @@ __device__ void build_event_index(EventIndex &X, const Dev &d)
     __syncthreads();
 }
 
-// one block, once per step after the collisions: the prefix over the regions
-// and the totals, for every kernel after it.  (A kernel of its own: folding
+// one block, once per step after the collisions of a batch: the prefix over
+// the regions and the totals, for every kernel after it.  (A kernel of its own: folding
 // it into the collide kernel's last block costs a device-scope fence in every
 // block, which writes back L2 and is far slower than the launch.)
 __global__ __launch_bounds__(kBlock) void index_kernel(Dev d)
@@ -169,6 +169,15 @@ __device__ void load_event_index(EventIndex &X, const Dev &d)
         X.in_regions = d.glob->ev_in_regions;
     }
     __syncthreads();
+}
+
+// the step's event index: a batch reads the one index_kernel wrote (its
+// bucket kernels need the total before they start); a single instance builds
+// it in every block (cheaper than a kernel of its own)
+__device__ void get_event_index(EventIndex &X, const Dev &d)
+{
+    if (d.n_inst > 1) load_event_index(X, d);
+    else build_event_index(X, d);
 }
 
 __device__ __forceinline__ const IzEvent &event_at(const EventIndex &X, const Dev &d, uint32_t e)
@@ -321,14 +330,8 @@ __device__ __forceinline__ uint32_t source_pairs(const Dev &d, int i)
 // grid; each adds its partial counts to ev_rank / ev_crank (zero at entry).
 __global__ __launch_bounds__(kBlock) void rank_kernel(Dev d)
 {
-    {
-        // blocks beyond the pairs of this step's events leave at once
-        const uint64_t m0 = d.glob->ev_total;
-        const uint64_t pairs = ((m0 + kBlock - 1) / kBlock) * ((m0 + kRankJ - 1) / kRankJ);
-        if (blockIdx.x >= pairs) return;
-    }
     __shared__ EventIndex X;
-    load_event_index(X, d);
+    get_event_index(X, d);
     const uint64_t m = X.total;
     const uint64_t ni = (m + kBlock - 1) / kBlock;
     const uint64_t nj = (m + kRankJ - 1) / kRankJ;
@@ -510,9 +513,9 @@ __device__ __forceinline__ KeyId wave_min_key(KeyId v)
 
 __global__ __launch_bounds__(kBlock) void target_kernel(Dev d)
 {
-    if ((uint64_t)blockIdx.x * kWaves >= d.glob->ev_total) return;  // no event for this block
     __shared__ EventIndex X;
-    load_event_index(X, d);
+    get_event_index(X, d);
+    if ((uint64_t)blockIdx.x * kWaves >= X.total) return;  // no event for this block
     const int cur = d.glob->cur_set;
     const bool f64 = (d.precision == PIC_FP64);
     const uint32_t since = d.glob->since_sort;
@@ -617,7 +620,7 @@ __device__ __forceinline__ void consume_atom(const Dev &d, int cur, bool f64, in
 __global__ __launch_bounds__(kBlock) void emit_kernel(Dev d)
 {
     __shared__ EventIndex X;
-    load_event_index(X, d);
+    get_event_index(X, d);
     const int cur = d.glob->cur_set;
     const bool f64 = (d.precision == PIC_FP64);
     const uint32_t m_all = X.total;
@@ -810,7 +813,7 @@ __global__ __launch_bounds__(kBlock) void close_step_kernel(Dev d, int with_even
     __shared__ uint32_t s_m[kMaxInstLds];
     const int n_inst = d.n_inst < kMaxInstLds ? d.n_inst : kMaxInstLds;
     if (with_events) {
-        load_event_index(X, d);
+        get_event_index(X, d);
         count_events(X, d, s_m, n_inst);
     } else {
         if (threadIdx.x == 0) X.total = 0u;
@@ -829,7 +832,7 @@ hipError_t launch_collide(const Dev &d, hipStream_t st)
 
 hipError_t launch_emit(const Dev &d, hipStream_t st, bool pairs, bool events)
 {
-    if (events) {
+    if (events && d.n_inst > 1) {  // a single instance builds the index in each kernel
         hipLaunchKernelGGL(index_kernel, dim3(1), dim3(kBlock), 0, st, d);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
