@@ -207,7 +207,7 @@ def pmc_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, out):
 
 
 def batched(torch, args):
-    """256 independent bounded MCC instances of mixed shape (100 to 16,000 cells,
+    """256 independent bounded MCC instances of mixed shape (256 to 16,384 cells,
     25 to 200 particles per cell per species, B at 0 to 85 degrees, omega_pe dt
     0.05 to 0.2) in one context, FP32 form, drawn on the device; the sort
     cadence is chosen by pic_autotune_sort, then steps replay from a HIP graph."""
