@@ -247,6 +247,18 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
     uint32_t wn = 0;  // this wave's candidates so far (uniform)
 
     int hint = 0;  // segment of the previous tile
+    // the constants of the segment of the previous tile, kept across tiles
+    // (loaded again only when the segment changes, so no global load of
+    // them waits behind a tile's particle loads)
+    int cseg = -1;
+    const float *__restrict__ acc = nullptr;
+    unsigned long long *__restrict__ S = nullptr;
+    int nc = 0, inst = 0;
+    bool periodic = false;
+    float tx = 0.f, ty = 0.f, sx = 0.f, sy = 0.f, msf = 0.f, hk = 0.f;
+    uint32_t key0 = 0, key1 = 0;
+    unsigned long long T = 0;
+    long long step = 0;
     for (int64_t t = blockIdx.x; t < d.n_tiles; t += gridDim.x) {
         int64_t tile0, base, count;
         uint32_t flg;
@@ -256,6 +268,20 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
         // a subcycled species between its pushes keeps its positions (their
         // deposit is a launch of its own, deposit_kernel<true>)
         if (d.n_seg > kSegLds && still(d, seg)) continue;
+        if (seg != cseg) {
+            const SegConst &sc = d.segc[seg];
+            acc = d.acc32 + sc.sp * d.G + sc.gnode;
+            S = d.S + sc.sp * d.G + sc.gnode;
+            nc = sc.nc;
+            periodic = (sc.bc == PIC_BC_PERIODIC);
+            tx = sc.txf, ty = sc.tyf, sx = sc.sxf, sy = sc.syf;
+            msf = sc.msf, hk = 0.5f * sc.msf;
+            key0 = sc.key0, key1 = sc.key1;
+            T = sc.T;
+            inst = sc.inst;
+            if (MCC) step = d.instd[inst].step;
+            cseg = seg;
+        }
 
         // a species with no collision process takes no test (no id read, no
         // draw); a species on which no field acts takes no gather
@@ -276,44 +302,65 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
         float *__restrict__ VYt = VY + tb;
         float *__restrict__ VZt = VZ + tb;
         const unsigned long long *__restrict__ IDt = ID + tb;
+        if (rem == (uint32_t)kTile) {
+            // a full tile: every load unconditional, so none is predicated
+            // and the wave issues all of them before its first wait
+            if (test) {
 #pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            const uint32_t o = (uint32_t)((wave * kPer + k) * 64 + lane);
-            j[k] = kDeadCell;
-            f[k] = vx[k] = vy[k] = vz[k] = 0.f;
-            pid[k] = 0;
-            if (o < rem) {
-                j[k] = stream_ld(&CELLt[o]);
-                f[k] = stream_ld(&Xt[o]);
-                vx[k] = stream_ld(&VXt[o]);
-                vy[k] = stream_ld(&VYt[o]);
-                vz[k] = stream_ld(&VZt[o]);
-                if (test) pid[k] = stream_ld(&IDt[o]);
+                for (int k = 0; k < kPer; ++k) {
+                    const uint32_t o = (uint32_t)((wave * kPer + k) * 64 + lane);
+                    j[k] = stream_ld(&CELLt[o]);
+                    f[k] = stream_ld(&Xt[o]);
+                    vx[k] = stream_ld(&VXt[o]);
+                    vy[k] = stream_ld(&VYt[o]);
+                    vz[k] = stream_ld(&VZt[o]);
+                    pid[k] = stream_ld(&IDt[o]);
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < kPer; ++k) {
+                    const uint32_t o = (uint32_t)((wave * kPer + k) * 64 + lane);
+                    j[k] = stream_ld(&CELLt[o]);
+                    f[k] = stream_ld(&Xt[o]);
+                    vx[k] = stream_ld(&VXt[o]);
+                    vy[k] = stream_ld(&VYt[o]);
+                    vz[k] = stream_ld(&VZt[o]);
+                    pid[k] = 0;
+                }
             }
-            lv[k] = j[k] >= 0;
+        } else {
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) {
+                const uint32_t o = (uint32_t)((wave * kPer + k) * 64 + lane);
+                j[k] = kDeadCell;
+                f[k] = vx[k] = vy[k] = vz[k] = 0.f;
+                pid[k] = 0;
+                if (o < rem) {
+                    j[k] = stream_ld(&CELLt[o]);
+                    f[k] = stream_ld(&Xt[o]);
+                    vx[k] = stream_ld(&VXt[o]);
+                    vy[k] = stream_ld(&VYt[o]);
+                    vz[k] = stream_ld(&VZt[o]);
+                    if (test) pid[k] = stream_ld(&IDt[o]);
+                }
+            }
         }
-        // ---- segment constants
-        const SegConst &sc = d.segc[seg];
-        const float *__restrict__ acc = d.acc32 + sc.sp * d.G + sc.gnode;
-        unsigned long long *__restrict__ S = d.S + sc.sp * d.G + sc.gnode;
-        const int nc = sc.nc;
-        const bool periodic = (sc.bc == PIC_BC_PERIODIC);
-        const float tx = sc.txf, ty = sc.tyf, sx = sc.sxf, sy = sc.syf;
-        const float msf = sc.msf, hk = 0.5f * sc.msf;
-        const uint32_t key0 = sc.key0, key1 = sc.key1;
-        const unsigned long long T = sc.T;
-        const int inst = sc.inst;
-        long long step = 0;
-        if (MCC) step = d.instd[inst].step;
-        // ---- gather
-        float a0[kPer], a1[kPer];
 #pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            a0[k] = a1[k] = 0.f;
-            if (force && j[k] >= 0) {
-                a0[k] = acc[j[k]];
-                a1[k] = acc[j[k] + 1];
+        for (int k = 0; k < kPer; ++k) lv[k] = j[k] >= 0;
+        // ---- gather
+        // (unpredicated: an empty slot reads node 0 and ignores it, so the
+        // wave issues the four gathers before one wait, not one wait each)
+        float a0[kPer], a1[kPer];
+        if (force) {
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) {
+                const int jj = j[k] >= 0 ? j[k] : 0;
+                a0[k] = acc[jj];
+                a1[k] = acc[jj + 1];
             }
+        } else {
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) a0[k] = a1[k] = 0.f;
         }
         // ---- push, walls, candidate test
         int key[kPer];
