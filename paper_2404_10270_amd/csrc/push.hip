@@ -489,6 +489,17 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
     uint32_t wn = 0;  // this wave's candidates so far (uniform)
 
     int hint = 0;  // segment of the previous tile
+    // the constants of the segment of the previous tile, kept across tiles
+    int cseg = -1;
+    const double *__restrict__ acc = nullptr;
+    unsigned long long *__restrict__ S = nullptr;
+    double L_ = 0.0;
+    bool periodic = false;
+    double tx = 0.0, ty = 0.0, sx = 0.0, sy = 0.0, ms = 0.0, hk = 0.0;
+    uint32_t key0 = 0, key1 = 0;
+    unsigned long long T = 0;
+    int inst = 0;
+    long long step = 0;
     for (int64_t t = blockIdx.x; t < d.n_tiles; t += gridDim.x) {
         int64_t tile0, base, count;
         uint32_t flg;
@@ -498,6 +509,20 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
         // a subcycled species between its pushes keeps its positions (their
         // deposit is a launch of its own, deposit_kernel<true>)
         if (d.n_seg > kSegLds && still(d, seg)) continue;
+        if (seg != cseg) {
+            const SegConst &sc = d.segc[seg];
+            acc = d.acc64 + sc.sp * d.G + sc.gnode;
+            S = d.S + sc.sp * d.G + sc.gnode;
+            L_ = (double)sc.nc;
+            periodic = (sc.bc == PIC_BC_PERIODIC);
+            tx = sc.tx, ty = sc.ty, sx = sc.sx, sy = sc.sy;
+            ms = sc.ms, hk = 0.5 * sc.ms;
+            key0 = sc.key0, key1 = sc.key1;
+            T = sc.T;
+            inst = sc.inst;
+            if (MCC) step = d.instd[inst].step;
+            cseg = seg;
+        }
         const bool test = MCC && (flg & kFlgTest);
         const bool force = (flg & kFlgForce) != 0;
 
@@ -510,47 +535,65 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
         double *__restrict__ VYt = VY + tb;
         double *__restrict__ VZt = VZ + tb;
         const unsigned long long *__restrict__ IDt = ID + tb;
+        if (rem == (uint32_t)kTile) {
+            // a full tile: every load unconditional (see the FP32 form)
+            if (test) {
 #pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            const uint32_t o = (uint32_t)((wave * kPer + k) * 64 + lane);
-            x[k] = kDeadX;
-            vx[k] = vy[k] = vz[k] = 0.0;
-            pid[k] = 0;
-            if (o < rem) {
-                x[k] = stream_ld(&Xt[o]);
-                vx[k] = stream_ld(&VXt[o]);
-                vy[k] = stream_ld(&VYt[o]);
-                vz[k] = stream_ld(&VZt[o]);
-                if (test) pid[k] = stream_ld(&IDt[o]);
+                for (int k = 0; k < kPer; ++k) {
+                    const uint32_t o = (uint32_t)((wave * kPer + k) * 64 + lane);
+                    x[k] = stream_ld(&Xt[o]);
+                    vx[k] = stream_ld(&VXt[o]);
+                    vy[k] = stream_ld(&VYt[o]);
+                    vz[k] = stream_ld(&VZt[o]);
+                    pid[k] = stream_ld(&IDt[o]);
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < kPer; ++k) {
+                    const uint32_t o = (uint32_t)((wave * kPer + k) * 64 + lane);
+                    x[k] = stream_ld(&Xt[o]);
+                    vx[k] = stream_ld(&VXt[o]);
+                    vy[k] = stream_ld(&VYt[o]);
+                    vz[k] = stream_ld(&VZt[o]);
+                    pid[k] = 0;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) {
+                const uint32_t o = (uint32_t)((wave * kPer + k) * 64 + lane);
+                x[k] = kDeadX;
+                vx[k] = vy[k] = vz[k] = 0.0;
+                pid[k] = 0;
+                if (o < rem) {
+                    x[k] = stream_ld(&Xt[o]);
+                    vx[k] = stream_ld(&VXt[o]);
+                    vy[k] = stream_ld(&VYt[o]);
+                    vz[k] = stream_ld(&VZt[o]);
+                    if (test) pid[k] = stream_ld(&IDt[o]);
+                }
             }
         }
-        const SegConst &sc = d.segc[seg];
-        const double *__restrict__ acc = d.acc64 + sc.sp * d.G + sc.gnode;
-        unsigned long long *__restrict__ S = d.S + sc.sp * d.G + sc.gnode;
-        const double L_ = (double)sc.nc;
-        const bool periodic = (sc.bc == PIC_BC_PERIODIC);
-        const double tx = sc.tx, ty = sc.ty, sx = sc.sx, sy = sc.sy;
-        const double ms = sc.ms, hk = 0.5 * sc.ms;
-        const uint32_t key0 = sc.key0, key1 = sc.key1;
-        const unsigned long long T = sc.T;
-        const int inst = sc.inst;
-        long long step = 0;
-        if (MCC) step = d.instd[inst].step;
+        // the gather unpredicated (an empty slot reads node 0 and ignores it)
         double a0[kPer], a1[kPer], fr[kPer];
         bool live[kPer];
+        int32_t jg[kPer];
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
             live[k] = x[k] >= 0.0;
-            a0[k] = a1[k] = fr[k] = 0.0;
-            if (live[k]) {
-                const double jd = floor(x[k]);
-                const int32_t jj = (int32_t)jd;
-                fr[k] = x[k] - jd;
-                if (force) {
-                    a0[k] = acc[jj];
-                    a1[k] = acc[jj + 1];
-                }
+            const double jd = floor(x[k]);
+            jg[k] = live[k] ? (int32_t)jd : 0;
+            fr[k] = live[k] ? x[k] - jd : 0.0;
+        }
+        if (force) {
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) {
+                a0[k] = acc[jg[k]];
+                a1[k] = acc[jg[k] + 1];
             }
+        } else {
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) a0[k] = a1[k] = 0.0;
         }
         int key[kPer];
         unsigned long long w1[kPer];
