@@ -123,10 +123,9 @@ struct Args {
 };
 
 // one particle's push (libpic's FP32 mover with nstep = 1, periodic)
-__device__ __forceinline__ void move_one(const pls_params &p, int32_t &j, float &f, float &vx,
-                                         float &vy, float &vz)
+__device__ __forceinline__ void move_one(const pls_params &p, float a0, float a1, int32_t &j, float &f,
+                                         float &vx, float &vy, float &vz)
 {
-    const float a0 = p.acc[j], a1 = p.acc[j + 1];
     const float a = fmaf(f, a1 - a0, a0);
     const float h = 0.5f * a;
     const float mx = vx + h, my = vy, mz = vz;
@@ -179,13 +178,8 @@ __global__ __launch_bounds__(kBlock) void move_kernel(Args a)
         int32_t j[kPerL];
         float f[kPerL], vx[kPerL], vy[kPerL], vz[kPerL];
         unsigned long long id[kPerL];
-#pragma unroll
-        for (int k = 0; k < kPerL; ++k) {
-            const int64_t s = t * kTileL + (int64_t)(wave * kPerL + k) * 64 + lane;
-            j[k] = -1;
-            f[k] = vx[k] = vy[k] = vz[k] = 0.f;
-            id[k] = 0;
-            if (s >= v.n_slots) continue;
+        // one chunk of the tile (slot s, lane's part), in the layout
+        auto load_chunk = [&](int k, int64_t s) {
             if (L == PLS_SOA) {
                 j[k] = stream_ld(&v.cell[s]);
                 f[k] = stream_ld(&v.f[s]);
@@ -222,6 +216,31 @@ __global__ __launch_bounds__(kBlock) void move_kernel(Args a)
                     id[k] = stream_ld(&v.cid[rd][s]);
                 }
             }
+        };
+        // the three flat layouts load unpredicated (a lane past the end
+        // reads the last slot again and is marked empty after all loads), so
+        // the wave issues every load before its first wait
+#pragma unroll
+        for (int k = 0; k < kPerL; ++k) {
+            const int64_t s = t * kTileL + (int64_t)(wave * kPerL + k) * 64 + lane;
+            j[k] = -1;
+            f[k] = vx[k] = vy[k] = vz[k] = 0.f;
+            id[k] = 0;
+            if (L != PLS_CELLPAD) load_chunk(k, s < v.n_slots ? s : v.n_slots - 1);
+            else if (s < v.n_slots) load_chunk(k, s);
+        }
+        if (L != PLS_CELLPAD) {
+#pragma unroll
+            for (int k = 0; k < kPerL; ++k)
+                if (t * kTileL + (int64_t)(wave * kPerL + k) * 64 + lane >= v.n_slots) j[k] = -1;
+        }
+        // the gather unpredicated (an empty slot reads node 0 and ignores it)
+        float a0[kPerL], a1[kPerL];
+#pragma unroll
+        for (int k = 0; k < kPerL; ++k) {
+            const int jj = j[k] >= 0 ? j[k] : 0;
+            a0[k] = p.acc[jj];
+            a1[k] = p.acc[jj + 1];
         }
         int key[kPerL];
         unsigned long long w1[kPerL];
@@ -232,7 +251,7 @@ __global__ __launch_bounds__(kBlock) void move_kernel(Args a)
             key[k] = -1;
             w1[k] = 0;
             if (!live[k]) continue;
-            move_one(p, j[k], f[k], vx[k], vy[k], vz[k]);
+            move_one(p, a0[k], a1[k], j[k], f[k], vx[k], vy[k], vz[k]);
             key[k] = j[k];
             w1[k] = (unsigned long long)rintf(f[k] * 4294967296.0f);
             const uint4 u = draw(id[k], a.step, 0, p.key0, p.key1);
