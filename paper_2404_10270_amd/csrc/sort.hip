@@ -91,6 +91,38 @@ __device__ __forceinline__ int node_of(const Dev &d, int cur, int64_t g, bool f6
     return d.cell[cur][g];
 }
 
+// the keys of this wave's kPer chunks of the tile at slot base + t0 (-1 past
+// count or absorbed).  A full tile loads unpredicated, with the precision
+// branch outside the chunk loop, so the wave issues every load before one
+// wait rather than waiting inside each chunk's branch.
+__device__ __forceinline__ void tile_keys(const Dev &d, int cur, int64_t base, int64_t t0, int64_t count,
+                                          bool f64, int (&key)[kPer])
+{
+    const int lane = lane_id();
+    const int wave = threadIdx.x >> 6;
+    if (t0 + kTile <= count) {
+        const int64_t g0 = base + t0 + (int64_t)(wave * kPer) * 64 + lane;
+        if (f64) {
+            const double *X = (const double *)d.x[cur] + g0;
+            double x[kPer];
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) x[k] = X[k * 64];
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) key[k] = x[k] >= 0.0 ? (int)floor(x[k]) : -1;
+        } else {
+            const int32_t *CELL = d.cell[cur] + g0;
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) key[k] = CELL[k * 64];
+        }
+        return;
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int64_t i = t0 + (int64_t)(wave * kPer + k) * 64 + lane;
+        key[k] = (i < count) ? node_of(d, cur, base + i, f64) : -1;
+    }
+}
+
 // block window [lo, hi] over the keys of this tile (barrier inside)
 __device__ __forceinline__ void tile_window(SortLds &L, const int (&key)[kPer], int &lo, int &hi)
 {
@@ -139,11 +171,7 @@ __global__ __launch_bounds__(kBlock) void sort_hist_kernel(Dev d)
         const SegConst &sc = d.segc[seg];
         uint32_t *__restrict__ H = d.hist + sc.sp * d.G + sc.gnode;
         int key[kPer];
-#pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            const int64_t i = t0 + (int64_t)(wave * kPer + k) * 64 + lane;
-            key[k] = (i < count) ? node_of(d, cur, base + i, f64) : -1;
-        }
+        tile_keys(d, cur, base, t0, count, f64, key);
         int lo, hi;
         tile_window(L, key, lo, hi);
 #pragma unroll
@@ -269,16 +297,14 @@ __global__ __launch_bounds__(kBlock) void sort_scan_kernel(Dev d)
 // (-1: none) of the other set: all loads, then all stores
 template <typename V, bool CELL>
 __device__ __forceinline__ void move_fields(const Dev &d, int cur, int nxt, int64_t g0,
-                                            const int64_t (&to)[kPer])
+                                            const int64_t (&to)[kPer], bool full)
 {
     V x[kPer], vx[kPer], vy[kPer], vz[kPer];
     int32_t c[kPer];
     unsigned long long id[kPer];
     const V *X = (const V *)d.x[cur], *VX = (const V *)d.vx[cur], *VY = (const V *)d.vy[cur],
             *VZ = (const V *)d.vz[cur];
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-        if (to[k] < 0) continue;
+    auto load = [&](int k) {
         const int64_t g = g0 + (int64_t)k * 64;
         x[k] = X[g];
         vx[k] = VX[g];
@@ -286,6 +312,16 @@ __device__ __forceinline__ void move_fields(const Dev &d, int cur, int nxt, int6
         vz[k] = VZ[g];
         if (CELL) c[k] = d.cell[cur][g];
         id[k] = d.id[cur][g];
+    };
+    if (full) {
+        // every slot of a full tile exists: its loads go unpredicated (an
+        // absorbed particle's fields are read and not stored)
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) load(k);
+    } else {
+#pragma unroll
+        for (int k = 0; k < kPer; ++k)
+            if (to[k] >= 0) load(k);
     }
     V *Xn = (V *)d.x[nxt], *VXn = (V *)d.vx[nxt], *VYn = (V *)d.vy[nxt], *VZn = (V *)d.vz[nxt];
 #pragma unroll
@@ -320,11 +356,7 @@ __global__ __launch_bounds__(kBlock) void sort_scatter_kernel(Dev d)
         const uint32_t start = (uint32_t)d.seg_start[seg];
         uint32_t *__restrict__ CUR = d.cursor + sc.sp * d.G + sc.gnode;
         int key[kPer];
-#pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            const int64_t i = t0 + (int64_t)(wave * kPer + k) * 64 + lane;
-            key[k] = (i < count) ? node_of(d, cur, base + i, f64) : -1;
-        }
+        tile_keys(d, cur, base, t0, count, f64, key);
         int lo, hi;
         tile_window(L, key, lo, hi);
         // rank of every particle among the tile's particles of its cell
@@ -365,24 +397,31 @@ __global__ __launch_bounds__(kBlock) void sort_scatter_kernel(Dev d)
         // before any is stored (a store to the other set could alias a later
         // load in the compiler's view, which would otherwise keep each load
         // waiting behind the previous store)
+        // (the segment's cap and base read once: the status atomic below would
+        // otherwise make the compiler read them again, with a wait, per chunk)
+        const uint32_t cap = sc.cap;
+        const int64_t sbase = sc.base;
         int64_t to[kPer];
+        bool overflow = false;
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
             to[k] = -1;
             if (key[k] < 0) continue;
             const uint32_t pos = outside[k] ? rank[k] : L.base[key[k] - lo] + rank[k];
             const uint32_t rel = pos - start;
-            if (rel >= sc.cap) {  // cannot happen with a consistent histogram
-                atomicOr(&d.instd[sc.inst].status, PIC_ST_INTERNAL);
+            if (rel >= cap) {  // cannot happen with a consistent histogram
+                overflow = true;
                 continue;
             }
-            to[k] = sc.base + (int64_t)rel;
+            to[k] = sbase + (int64_t)rel;
         }
+        if (overflow) atomicOr(&d.instd[sc.inst].status, PIC_ST_INTERNAL);
         const int64_t g0 = base + t0 + (int64_t)(wave * kPer) * 64 + lane;
+        const bool full = t0 + kTile <= count;
         if (f64) {
-            move_fields<double, false>(d, cur, nxt, g0, to);
+            move_fields<double, false>(d, cur, nxt, g0, to, full);
         } else {
-            move_fields<float, true>(d, cur, nxt, g0, to);
+            move_fields<float, true>(d, cur, nxt, g0, to, full);
         }
         if (sc.kind == PIC_KIND_NEUTRAL) {
             unsigned long long vb = 0ull;
