@@ -273,6 +273,136 @@ def table1_run(torch, args):
     return out
 
 
+PRECISION_GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden",
+                                "precision_subsample_oracle.json")
+
+
+def _gpu_moments(torch, sim, nc, bins):
+    """N, kinetic energy and a `bins`-bin density histogram per species, and
+    the field energy, of instance 0 (histograms from the device arrays)."""
+    from paper_2404_10270_amd import pic as P
+    d, rc = sim.diagnostics()
+    if rc != 0:
+        raise RuntimeError(f"device status {d[0].status:#x}")
+    d = d[0]
+    cur = d.cur_set
+    out = {"step": int(d.step)}
+    for k in range(sim.nsp):
+        b = sim.seg_base[k]
+        m = int(d.n_slots_used[k])
+        if sim.precision == P.PIC_FP32:
+            c = sim.cell[cur][b:b + m]
+            live = c >= 0
+            x = c[live].double() + sim.x[cur][b:b + m][live].double()
+        else:
+            x = sim.x[cur][b:b + m]
+            x = x[x >= 0]
+        idx = torch.clamp(torch.floor(x * (bins / nc)).long(), 0, bins - 1)
+        out[f"N{k}"] = int(d.n_live[k])
+        out[f"KE{k}"] = float(d.ke[k])
+        out[f"h{k}"] = torch.bincount(idx, minlength=bins).cpu().tolist()
+    out["FE"] = float(d.field_energy)
+    return out
+
+
+def _rel_diff(a, b):
+    """Largest relative difference of moments a against b (histograms: over bins)."""
+    import numpy as np
+    r = {}
+    for key in b:
+        if key == "step":
+            continue
+        x, y = np.asarray(a[key], np.float64), np.asarray(b[key], np.float64)
+        r[key] = float(np.max(np.abs(x - y) / np.maximum(np.abs(y), 1e-300)))
+    return r
+
+
+def precision_study(torch, args):
+    """The precision study (FP32/fixed-point form against the FP64 form): the
+    1,000,000-cell bounded MCC instance (200 particles per cell per species,
+    4e8 particles) run for 2,000 steps as the FP64 and as the FP32 GPU form from
+    the same drawn start, and the 10,000-cell instance with the same plasma
+    (the 1% subsample) run as both GPU forms and compared with the oracle's
+    moments at steps 500..2000 (tests/golden/precision_subsample_oracle.json,
+    written by the oracle alone).  Reported: the largest relative difference of
+    N, kinetic energy, field energy and a 64-bin density profile per species,
+    beside the FP64 form's own noise floor (the same run with every drawn
+    position moved by one ulp)."""
+    import numpy as np
+    import pic_inputs as pin
+    from paper_2404_10270_amd import pic as P
+    bins = 64
+    out = {}
+    # ---- the 1% subsample: oracle, FP64 form, FP32 form, one-ulp floor
+    with open(PRECISION_GOLDEN) as f:
+        gold = json.load(f)
+    wl = pin.bounded_mcc(nc=10_000, ppc=200, seed=5)
+    caps = gold["caps"]
+    checks = [r["step"] for r in gold["moments"][1:]]
+    runs = {}
+    for name, prec in (("fp64", P.PIC_FP64), ("fp32", P.PIC_FP32)):
+        log(f"precision: 10,000-cell instance, {name} form")
+        sim = P.PicSim(wl, None, prec, capacities=caps, flags=P.PIC_INIT_DEVICE)
+        rows, last = [], 0
+        for c in checks:
+            sim.step_graph(c - last, SORT_EVERY)
+            last = c
+            rows.append(_gpu_moments(torch, sim, wl.nc, bins))
+        runs[name] = rows
+        sim.close()
+    # the FP64 noise floor: positions of the drawn start moved by one ulp
+    sim = P.PicSim(wl, None, P.PIC_FP64, capacities=caps, flags=P.PIC_INIT_DEVICE)
+    st0 = [sim.state(k) for k in range(2)]
+    n_drawn = sum(int(s["id"].shape[0]) for s in st0)
+    sim.close()
+    pert = []
+    for k in range(2):
+        x = np.nextafter(st0[k]["x"], np.inf)
+        x = np.where(x >= wl.nc, st0[k]["x"], x)
+        pert.append(pin.SpeciesState(x=x, vx=st0[k]["vx"], vy=st0[k]["vy"], vz=st0[k]["vz"],
+                                     id=st0[k]["id"]))
+    log("precision: 10,000-cell instance, FP64 form, positions moved one ulp")
+    sim = P.PicSim(wl, pert, P.PIC_FP64, capacities=caps, next_ids=[n_drawn])
+    rows, last = [], 0
+    for c in checks:
+        sim.step_graph(c - last, SORT_EVERY)
+        last = c
+        rows.append(_gpu_moments(torch, sim, wl.nc, bins))
+    runs["fp64_ulp"] = rows
+    sim.close()
+    sub = []
+    for i, c in enumerate(checks):
+        g = gold["moments"][i + 1]
+        sub.append({"step": c,
+                    "fp64_vs_oracle": _rel_diff(runs["fp64"][i], g),
+                    "fp32_vs_oracle": _rel_diff(runs["fp32"][i], g),
+                    "fp32_vs_fp64": _rel_diff(runs["fp32"][i], runs["fp64"][i]),
+                    "fp64_ulp_vs_fp64": _rel_diff(runs["fp64_ulp"][i], runs["fp64"][i])})
+    out["subsample_10k_cells"] = {"particles": n_drawn, "checkpoints": sub}
+    # ---- the 1,000,000-cell instance: FP32 form against FP64 form on the GPU
+    wl = pin.bounded_mcc(nc=args.precision_cells, ppc=200, seed=5)
+    n = wl.n_particles
+    caps = [int(0.75 * n) + 1024] * 2  # ionisation grows the plasma by about 25% in 2,000 steps
+    big = {}
+    for name, prec in (("fp64", P.PIC_FP64), ("fp32", P.PIC_FP32)):
+        log(f"precision: {wl.nc}-cell instance ({n} particles), {name} form, {args.precision_steps} steps")
+        sim = P.PicSim(wl, None, prec, capacities=caps, flags=P.PIC_INIT_DEVICE | P.PIC_INIT_SORT)
+        rows, last = [], 0
+        t0 = time.perf_counter()
+        for c in range(500, args.precision_steps + 1, 500):
+            sim.step_graph(c - last, SORT_EVERY)
+            last = c
+            rows.append(_gpu_moments(torch, sim, wl.nc, bins))
+            log(f"precision: {name} step {c} ({time.perf_counter() - t0:.1f} s)")
+        big[name] = rows
+        sim.close()
+        torch.cuda.empty_cache()
+    out["large"] = {"cells": wl.nc, "particles": n, "steps": args.precision_steps,
+                    "checkpoints": [{"step": a["step"], "fp32_vs_fp64": _rel_diff(a, b)}
+                                    for a, b in zip(big["fp32"], big["fp64"])]}
+    return out
+
+
 def layout_study(torch, args):
     """The mover pass in four particle layouts (libpic_layout): structure of
     arrays (libpic's), array of 32-byte structs, 64-particle blocks of arrays,
@@ -372,6 +502,10 @@ def main():
     ap.add_argument("--layout-study", action="store_true",
                     help="run only the particle-layout study of the mover and print its JSON object")
     ap.add_argument("--layout-passes", type=int, default=40)
+    ap.add_argument("--precision-study", action="store_true",
+                    help="FP32 form against FP64 form and the oracle (1e6- and 1e4-cell instances); prints its own JSON")
+    ap.add_argument("--precision-cells", type=int, default=1_000_000)
+    ap.add_argument("--precision-steps", type=int, default=2000)
     ap.add_argument("--only-batched", action="store_true",
                     help="run only the batched workload and print its JSON object (profiling)")
     ap.add_argument("--only-table1", action="store_true",
@@ -404,6 +538,9 @@ def main():
         return
     if args.layout_study:
         print(json.dumps({"layout_study": layout_study(torch, args)}), flush=True)
+        return
+    if args.precision_study:
+        print(json.dumps({"precision_study": precision_study(torch, args)}), flush=True)
         return
     if args.only_batched:
         print(json.dumps(batched(torch, args)), flush=True)

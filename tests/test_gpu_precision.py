@@ -67,3 +67,35 @@ def test_fp32_moments_track_fp64_over_1e4_steps():
         err = _rel(m32[key], m64[key])
         flush(f"{key}: fp32-fp64 {err:.3e}, fp64 noise floor {floor:.3e}")
         assert err <= max(1e-4, 3.0 * floor), key
+
+
+def test_fp64_form_tracks_the_oracle_over_2000_steps():
+    """The 10,000-cell precision instance (4e6 particles, MCC and source on),
+    drawn on the device, 2,000 steps of the FP64 form against the oracle's
+    moments at steps 500..2000 (tests/golden/precision_subsample_oracle.json,
+    written by the oracle alone from the same draw).  The two differ only in
+    the rounding of the field solve, which over 2,000 steps moves no particle
+    across a 64-bin boundary and changes no collision or wall outcome: counts
+    and density profiles equal, kinetic energies to summation order, the
+    field energy to the solve's rounding."""
+    import json
+    import os
+    gold_path = os.path.join(os.path.dirname(__file__), "golden", "precision_subsample_oracle.json")
+    with open(gold_path) as f:
+        gold = json.load(f)
+    wl = pin.bounded_mcc(nc=10_000, ppc=200, seed=5)
+    flush("precision: FP64 form against the stored oracle moments, 2,000 steps")
+    sim = P.PicSim(wl, None, FP64, capacities=gold["caps"], flags=P.PIC_INIT_DEVICE)
+    last = 0
+    for g in gold["moments"][1:]:
+        sim.step_graph(g["step"] - last, 20)
+        last = g["step"]
+        d, rc = sim.diagnostics()
+        assert rc == 0 and d[0].step == g["step"]
+        for k in range(2):
+            assert int(d[0].n_live[k]) == g[f"N{k}"], (g["step"], k)
+            h = np.histogram(sim.state(k)["x"], bins=gold["bins"], range=(0, wl.nc))[0]
+            assert np.array_equal(h, np.asarray(g[f"h{k}"])), (g["step"], k)
+            assert abs(d[0].ke[k] / g[f"KE{k}"] - 1) <= 1e-12, (g["step"], k)
+        assert abs(d[0].field_energy / g["FE"] - 1) <= 1e-6, g["step"]
+    sim.close()
