@@ -104,4 +104,68 @@ __device__ __forceinline__ void deposit_window(unsigned long long *dep, int (*re
     // the next use of the window is ordered by the next call's first barrier
 }
 
+// Orders this wave's LDS operations before and after the call (a wave's LDS
+// operations complete in issue order; the fences keep the compiler from
+// moving them across).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr int kWaveWin = 64;      // LDS deposit window of one wave, nodes
+
+// Deposit the NP chunks of this wave through its own LDS window
+// wdep[kWaveWin] (zero between calls), with no block barrier: runs of equal
+// cells are summed across lanes, their two node weights added into the
+// window, and the window flushed with one 64-bit global atomic per touched
+// node.  A run whose nodes fall outside the window adds to S directly.
+template <int NP>
+__device__ __forceinline__ void deposit_wave(unsigned long long *wdep, unsigned long long *__restrict__ S,
+                                             const int (&key)[NP], const unsigned long long (&w1)[NP])
+{
+    const int lane = lane_id();
+    int kmn = 0x7fffffff, kmx = -1;
+#pragma unroll
+    for (int k = 0; k < NP; ++k)
+        if (key[k] >= 0) {
+            kmn = min(kmn, key[k]);
+            kmx = max(kmx, key[k]);
+        }
+    const int lo = __builtin_amdgcn_readfirstlane(wave_min(kmn));
+    const int hi = __builtin_amdgcn_readfirstlane(wave_max(kmx));
+    if (hi < 0) return;  // no live particle in the wave's chunks
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        // pack (count, sum W1): W1 <= 2^32 and at most 64 lanes -> sum < 2^39
+        const unsigned long long v = (key[k] >= 0) ? ((1ull << 40) + w1[k]) : 0ull;
+        bool tail;
+        const unsigned long long t = run_sum(key[k], v, tail);
+        if (tail && key[k] >= 0) {
+            const unsigned long long n = t >> 40;
+            const unsigned long long b = t & ((1ull << 40) - 1ull);
+            const unsigned long long a = (n << PIC_FRAC_BITS) - b;
+            const int rel = key[k] - lo;
+            if (rel + 1 < kWaveWin) {
+                atomicAdd(&wdep[rel], a);
+                atomicAdd(&wdep[rel + 1], b);
+            } else {
+                atomicAdd(S + key[k], a);
+                atomicAdd(S + key[k] + 1, b);
+            }
+        }
+    }
+    wave_lds_sync();
+    const int span = min(hi - lo + 2, kWaveWin);
+    for (int i = lane; i < span; i += 64) {
+        const unsigned long long v = wdep[i];
+        if (v) {
+            atomicAdd(S + lo + i, v);
+            wdep[i] = 0ull;
+        }
+    }
+    wave_lds_sync();
+}
+
 }  // namespace picx

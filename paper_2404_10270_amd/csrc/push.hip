@@ -18,8 +18,9 @@
 //  * segment tables and counts are staged in LDS once per launch, so no
 //    global load sits on the critical path between tiles;
 //  * the deposit of cell-sorted neighbours is summed first over runs of equal
-//    cells inside each wave, then into an LDS window of nodes, and the window
-//    is flushed with one 64-bit global atomic per touched node per tile;
+//    cells inside each wave, then into the wave's own LDS window of nodes
+//    (no block barrier), and the window is flushed with one 64-bit global
+//    atomic per touched node per wave and tile;
 //  * each candidate, with its velocity after the push and its id, goes to its
 //    block's own region of the candidate list (index from an LDS counter), so
 //    the collide kernel reads them contiguously; only a block with more than
@@ -34,12 +35,11 @@ namespace picx {
 constexpr int kSegLds = 1024;     // segments whose tables are staged in LDS
 
 struct PushLds {
-    unsigned long long dep[kDepWin];
+    unsigned long long wdep[kWaves][kWaveWin];  // each wave's deposit window
     int64_t tile0[kSegLds + 1];
     int64_t base[kSegLds];
     uint32_t count[kSegLds];
     uint8_t flg[kSegLds];   // kFlgTest | kFlgForce of each segment
-    int red[2][kWaves];
 };
 
 // per-segment flags of the movers: a collision process (the candidate test
@@ -63,7 +63,7 @@ __device__ __forceinline__ bool still(const Dev &d, int seg)
 // segments read as empty, so the movers pay nothing per tile for the test)
 __device__ __forceinline__ void push_lds_init(PushLds &L, const Dev &d, bool drop_still = false)
 {
-    for (int i = threadIdx.x; i < kDepWin; i += kBlock) L.dep[i] = 0ull;
+    for (int i = threadIdx.x; i < kWaves * kWaveWin; i += kBlock) (&L.wdep[0][0])[i] = 0ull;
     if (d.n_seg <= kSegLds) {
         for (int s = threadIdx.x; s <= d.n_seg; s += kBlock) {
             L.tile0[s] = d.seg_tile0[s];
@@ -127,12 +127,13 @@ __device__ __forceinline__ int tile_seg(const PushLds &L, const Dev &d, int64_t 
     return __builtin_amdgcn_readfirstlane(seg);
 }
 
-// Deposit the kPer chunks of this wave through the block's LDS window.
+// Deposit the kPer chunks of this wave through its own LDS window (no block
+// barrier: the waves of a block run through their tiles independently).
 template <int NP>
 __device__ __forceinline__ void deposit_tile(PushLds &L, unsigned long long *__restrict__ S,
                                              const int (&key)[NP], const unsigned long long (&w1)[NP])
 {
-    deposit_window<NP>(L.dep, L.red, S, key, w1);
+    deposit_wave<NP>(L.wdep[threadIdx.x >> 6], S, key, w1);
 }
 
 // The deposit of the current positions of one tile (both forms): the
