@@ -1,13 +1,11 @@
 // mover_common.h -- pieces of the mover shared by libpic (push.hip) and the
 // layout study (study/layout.hip): streaming loads and stores, wave
-// reductions, and the tile deposit through an LDS window of nodes.
+// reductions, and the deposit through a per-wave LDS window of nodes.
 #pragma once
 
 #include "device_common.h"
 
 namespace picx {
-
-constexpr int kDepWin = 1024;     // LDS deposit window, nodes
 
 // Particle arrays are streamed once per step (the state is far larger than
 // the caches): nontemporal loads and stores keep them from displacing the
@@ -36,72 +34,6 @@ __device__ __forceinline__ int wave_max(int v)
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
     return v;
-}
-
-// Deposit the NP chunks of this wave (keys = cells, -1 = none) through the
-// block's LDS window dep[kDepWin] (zero between calls); red[2][kWaves] holds
-// the per-wave key bounds.  Contains two block barriers; every thread must
-// call it.
-template <int NP>
-__device__ __forceinline__ void deposit_window(unsigned long long *dep, int (*red)[kWaves],
-                                               unsigned long long *__restrict__ S,
-                                               const int (&key)[NP],
-                                               const unsigned long long (&w1)[NP])
-{
-    const int lane = lane_id();
-    const int wave = threadIdx.x >> 6;
-    int kmn = 0x7fffffff, kmx = -1;
-#pragma unroll
-    for (int k = 0; k < NP; ++k)
-        if (key[k] >= 0) {
-            kmn = min(kmn, key[k]);
-            kmx = max(kmx, key[k]);
-        }
-    kmn = wave_min(kmn);
-    kmx = wave_max(kmx);
-    if (lane == 0) {
-        red[0][wave] = kmn;
-        red[1][wave] = kmx;
-    }
-    __syncthreads();
-    int lo = red[0][0], hi = red[1][0];
-#pragma unroll
-    for (int w = 1; w < kWaves; ++w) {
-        lo = min(lo, red[0][w]);
-        hi = max(hi, red[1][w]);
-    }
-#pragma unroll
-    for (int k = 0; k < NP; ++k) {
-        // pack (count, sum W1): W1 <= 2^32 and at most 64 lanes -> sum < 2^39
-        const unsigned long long v = (key[k] >= 0) ? ((1ull << 40) + w1[k]) : 0ull;
-        bool tail;
-        const unsigned long long t = run_sum(key[k], v, tail);
-        if (tail && key[k] >= 0) {
-            const unsigned long long n = t >> 40;
-            const unsigned long long b = t & ((1ull << 40) - 1ull);
-            const unsigned long long a = (n << PIC_FRAC_BITS) - b;
-            const int rel = key[k] - lo;
-            if (rel + 1 < kDepWin) {
-                atomicAdd(&dep[rel], a);
-                atomicAdd(&dep[rel + 1], b);
-            } else {
-                atomicAdd(S + key[k], a);
-                atomicAdd(S + key[k] + 1, b);
-            }
-        }
-    }
-    __syncthreads();
-    if (hi >= 0) {
-        const int span = min(hi - lo + 2, kDepWin);
-        for (int i = threadIdx.x; i < span; i += kBlock) {
-            const unsigned long long v = dep[i];
-            if (v) {
-                atomicAdd(S + lo + i, v);
-                dep[i] = 0ull;
-            }
-        }
-    }
-    // the next use of the window is ordered by the next call's first barrier
 }
 
 // Orders this wave's LDS operations before and after the call (a wave's LDS

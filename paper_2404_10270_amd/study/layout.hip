@@ -161,10 +161,9 @@ __device__ __forceinline__ void move_one(const pls_params &p, float a0, float a1
 template <int L>
 __global__ __launch_bounds__(kBlock) void move_kernel(Args a)
 {
-    __shared__ unsigned long long dep[kDepWin];
-    __shared__ int red[2][kWaves];
+    __shared__ unsigned long long wdep[kWaves][kWaveWin];  // each wave's deposit window
     __shared__ unsigned long long s_cand[kWaves];
-    for (int i = threadIdx.x; i < kDepWin; i += kBlock) dep[i] = 0ull;
+    for (int i = threadIdx.x; i < kWaves * kWaveWin; i += kBlock) (&wdep[0][0])[i] = 0ull;
     __syncthreads();
     const View &v = a.v;
     const pls_params &p = a.p;
@@ -308,7 +307,7 @@ __global__ __launch_bounds__(kBlock) void move_kernel(Args a)
                 stream_st(&b.vz[lane], vz[k]);
             }
         }
-        deposit_window<kPerL>(dep, red, (unsigned long long *)p.S, key, w1);
+        deposit_wave<kPerL>(wdep[wave], (unsigned long long *)p.S, key, w1);
     }
     // this block's candidates into its own slot
     uint32_t c = n_cand;
