@@ -6,7 +6,7 @@
 // Every layout runs the same per-particle arithmetic as libpic's FP32 mover
 // (gather fma(f, a1 - a0, a0), half kick, Boris rotation, half kick,
 // advance, periodic re-entry, the candidate draw of Philox block (id, step,
-// 0)) and the same tile deposit through an LDS window (mover_common.h), on
+// 0)) and the same deposit through per-wave LDS windows (mover_common.h), on
 // the same persistent grid of 1024-slot tiles; only where the particle
 // fields live differs:
 //   SOA      six arrays (libpic);
