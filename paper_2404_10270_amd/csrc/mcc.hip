@@ -718,7 +718,10 @@ __global__ __launch_bounds__(kBlock) void emit_kernel(Dev d)
         __syncthreads();
     }
     const uint32_t n_src_all = s_pre[n_inst];
-    for (uint32_t q = blockIdx.x * kBlock + threadIdx.x; q < n_src_all; q += stride) {
+    // source pairs from the last blocks down, so that they run beside the
+    // ionisation pairs (from the first blocks up), not after them
+    const uint32_t sb = gridDim.x - 1 - blockIdx.x;
+    for (uint32_t q = sb * kBlock + threadIdx.x; q < n_src_all; q += stride) {
         int lo = 0, hi = n_inst - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
