@@ -135,16 +135,49 @@ __global__ __launch_bounds__(kBlock) void field_rho_kernel(Dev d, int mode)
     const int64_t G = d.G;
     const int nsp = ic.nsp;
     const double two_m32 = 0x1p-32;
+    // the instance's constants read once (the stores to rho below would make
+    // the compiler read them again, with a wait, per node)
+    const int64_t gnode = ic.gnode;
+    const double dx = ic.dx, K = ic.K;
 
     // uniform background for periodic systems, from the live counts
     double rho_bg = 0.0;
     if (periodic) {
         double qn = 0.0;
         for (int k = 0; k < nsp; ++k) qn += d.segc[ic.seg0 + k].qw * (double)d.segd[ic.seg0 + k].live;
-        rho_bg = -qn / ((double)nc * ic.dx);
+        rho_bg = -qn / ((double)nc * dx);
     }
 
     const int64_t j0 = lt * kFieldTile + (int64_t)threadIdx.x * kFieldR;
+    // the deposit of the thread's nodes for every species, and of nodes 0 and
+    // nc (the periodic wrap), loaded before the first wait: unpredicated, a
+    // node past nc reads node nc and a species past nsp repeats the last one,
+    // neither used
+    unsigned long long Sv[kFieldR][PIC_MAX_SPECIES], S0[PIC_MAX_SPECIES], Snc[PIC_MAX_SPECIES];
+    double qw[PIC_MAX_SPECIES];  // q w of each species (read once, not per node)
+    if (!from_rho) {
+#pragma unroll
+        for (int k = 0; k < PIC_MAX_SPECIES; ++k) {
+            const int kk = min(k, nsp - 1);
+            const unsigned long long *Sk = d.S + kk * G + gnode;
+#pragma unroll
+            for (int r = 0; r < kFieldR; ++r) Sv[r][k] = Sk[min(j0 + r, (int64_t)nc)];
+            S0[k] = Sk[0];
+            Snc[k] = Sk[nc];
+            qw[k] = d.segc[ic.seg0 + kk].qw;
+        }
+    }
+    const double wn = ic.seg_n >= 0 ? d.segc[ic.seg_n].w : 0.0;  // the atoms' weight
+    const int spn = ic.seg_n >= 0 ? d.segc[ic.seg_n].sp : -1;
+    // the deposit at node j of species k, with the periodic wrap
+    auto dep_at = [&](int r, int k, int64_t j) -> unsigned long long {
+        unsigned long long Sj = Sv[r][k];
+        if (periodic) {
+            if (j == 0) Sj += Snc[k];
+            if (j == nc) Sj = S0[k] + Snc[k];
+        }
+        return Sj;
+    };
     Aff m = {1.0, 0.0};
 #pragma unroll
     for (int r = 0; r < kFieldR; ++r) {
@@ -152,7 +185,7 @@ __global__ __launch_bounds__(kBlock) void field_rho_kernel(Dev d, int mode)
         if (j > nc) continue;
         if (from_rho) {
             if (j >= 1 && j <= nc - 1) {
-                const double dd = -(d.rho[ic.gnode + j] * ic.K);
+                const double dd = -(d.rho[gnode + j] * K);
                 const double gq = gq_of(j);
                 m = compose(Aff{gq, -(gq * dd)}, m);
             }
@@ -163,38 +196,29 @@ __global__ __launch_bounds__(kBlock) void field_rho_kernel(Dev d, int mode)
         // thread reads node nc's deposit after it is cleared
         if (mode == kRhoNoSolve && periodic && j == nc) continue;
         double acc = 0.0;
-        for (int k = 0; k < nsp; ++k) {
-            const unsigned long long *S = d.S + k * G + ic.gnode;
-            unsigned long long Sj = S[j];
-            if (periodic) {
-                if (j == 0) Sj += S[nc];
-                if (j == nc) Sj = S[0] + S[nc];
-            }
-            acc += d.segc[ic.seg0 + k].qw * ((double)Sj * two_m32);
-        }
-        double V = ic.dx;
-        if (!periodic && (j == 0 || j == nc)) V = 0.5 * ic.dx;
+#pragma unroll
+        for (int k = 0; k < PIC_MAX_SPECIES; ++k)
+            if (k < nsp) acc += qw[k] * ((double)dep_at(r, k, j) * two_m32);
+        double V = dx;
+        if (!periodic && (j == 0 || j == nc)) V = 0.5 * dx;
         const double rho = acc / V + rho_bg;
-        d.rho[ic.gnode + j] = rho;
-        if (mode == kRhoNoSolve && periodic && j == 0) d.rho[ic.gnode + nc] = rho;
+        d.rho[gnode + j] = rho;
+        if (mode == kRhoNoSolve && periodic && j == 0) d.rho[gnode + nc] = rho;
         if (d.kinetic_any) {
             double n = 0.0;
             if (ic.seg_n >= 0) {
-                const SegConst &sn = d.segc[ic.seg_n];
-                const unsigned long long *S = d.S + (int64_t)sn.sp * G + ic.gnode;
-                unsigned long long Sj = S[j];
-                if (periodic) {
-                    if (j == 0) Sj += S[nc];
-                    if (j == nc) Sj = S[0] + S[nc];
-                }
-                n = (sn.w * ((double)Sj * two_m32)) / V;
+                unsigned long long Sj = 0;
+#pragma unroll
+                for (int k = 0; k < PIC_MAX_SPECIES; ++k)
+                    if (k == spn) Sj = dep_at(r, k, j);
+                n = (wn * ((double)Sj * two_m32)) / V;
             }
-            d.nn[ic.gnode + j] = n;
-            if (mode == kRhoNoSolve && periodic && j == 0) d.nn[ic.gnode + nc] = n;
+            d.nn[gnode + j] = n;
+            if (mode == kRhoNoSolve && periodic && j == 0) d.nn[gnode + nc] = n;
         }
         if (mode == kRhoNoSolve) continue;
         if (j >= 1 && j <= nc - 1) {
-            const double dd = -(rho * ic.K);
+            const double dd = -(rho * K);
             const double gq = gq_of(j);
             m = compose(Aff{gq, -(gq * dd)}, m);
         }
@@ -208,8 +232,8 @@ __global__ __launch_bounds__(kBlock) void field_rho_kernel(Dev d, int mode)
             const int64_t j = j0 + r;
             if (j > nc || (periodic && j == nc)) continue;
             for (int k = 0; k < nsp; ++k) {
-                d.S[k * G + ic.gnode + j] = 0ull;
-                if (periodic && j == 0) d.S[k * G + ic.gnode + nc] = 0ull;
+                d.S[k * G + gnode + j] = 0ull;
+                if (periodic && j == 0) d.S[k * G + gnode + nc] = 0ull;
             }
         }
         if (threadIdx.x == 0) d.fe_part[vt] = 0.0;
@@ -234,11 +258,17 @@ __global__ __launch_bounds__(kBlock) void field_fwd_kernel(Dev d)
     const int64_t lt = vt - ic.ftile0;
     const int nc = ic.nc;
 
+    // the thread's rho, loaded before the first wait (unpredicated: a node
+    // past nc reads node nc and is not used)
+    const int64_t j0 = lt * kFieldTile + (int64_t)threadIdx.x * kFieldR;
+    double rl[kFieldR];
+#pragma unroll
+    for (int r = 0; r < kFieldR; ++r) rl[r] = d.rho[ic.gnode + min(j0 + r, (int64_t)nc)];
+
     // d' entering the tile: the composites of the tiles below applied to d'_0 = 0
     const int64_t first = ic.ftile0;
     const Aff below = compose_ordered(d.fwd_status, lt, [first](int64_t a) { return first + a; });
 
-    const int64_t j0 = lt * kFieldTile + (int64_t)threadIdx.x * kFieldR;
     double dv[kFieldR];
     Aff m = {1.0, 0.0};
 #pragma unroll
@@ -246,7 +276,7 @@ __global__ __launch_bounds__(kBlock) void field_fwd_kernel(Dev d)
         const int64_t j = j0 + r;
         dv[r] = 0.0;
         if (j >= 1 && j <= nc - 1) {
-            dv[r] = -(d.rho[ic.gnode + j] * ic.K);
+            dv[r] = -(rl[r] * ic.K);
             const double gq = gq_of(j);
             m = compose(Aff{gq, -(gq * dv[r])}, m);
         }
@@ -303,16 +333,22 @@ __global__ __launch_bounds__(kBlock) void field_bwd_kernel(Dev d)
     const int nsp = ic.nsp;
     const double dx = ic.dx;
 
+    // thread t owns the chunk counted from the top of the tile; its d' is
+    // loaded before the first wait (unpredicated: a node past nc reads node
+    // nc and is not used)
+    const int64_t lo = lt * kFieldTile;
+    const int64_t c = kBlock - 1 - threadIdx.x;
+    const int64_t j0 = lo + c * kFieldR;
+    double dl[kFieldR];
+#pragma unroll
+    for (int r = 0; r < kFieldR; ++r) dl[r] = d.dprime[ic.gnode + min(j0 + r, (int64_t)nc)];
+
     // phi at the first node above the tile: the composites of the tiles
     // above, top first, applied to phi_nc = 0
     const int64_t last = ic.ftile0 + ntl - 1;
     const Aff above = compose_ordered(d.bwd_status, ntl - 1 - lt, [last](int64_t a) { return last - a; });
     const double phi_above = above.B;
 
-    // thread t owns the chunk counted from the top of the tile
-    const int64_t lo = lt * kFieldTile;
-    const int64_t c = kBlock - 1 - threadIdx.x;
-    const int64_t j0 = lo + c * kFieldR;
     double dp[kFieldR];
     Aff m = {1.0, 0.0};
 #pragma unroll
@@ -320,7 +356,7 @@ __global__ __launch_bounds__(kBlock) void field_bwd_kernel(Dev d)
         const int64_t j = j0 + r;
         dp[r] = 0.0;
         if (j >= 1 && j <= nc - 1) {
-            dp[r] = d.dprime[ic.gnode + j];
+            dp[r] = dl[r];
             m = compose(Aff{gq_of(j), dp[r]}, m);
         }
     }
