@@ -36,15 +36,23 @@ __device__ __forceinline__ void st_v(void *p, int64_t g, double v, bool f64)
     else ((float *)p)[g] = (float)v;
 }
 
+// segments whose constants the collide kernel stages in LDS (few segments:
+// a single instance or a small batch)
+constexpr int kCollSegLds = 8;
+
 // collide one listed candidate; returns its segment, fills the counts and
-// the ionisation event, and stores the velocity of a particle that collided
+// the ionisation event, and stores the velocity of a particle that collided.
+// SEGLDS: the segment constants and instance steps come from the block's LDS
+// copies s_sc / s_step (staged at block start, beside the first loads).
+template <bool SEGLDS>
 __device__ __forceinline__ int collide_one(const Dev &d, int cur, bool f64, const Cand &c,
+                                           const SegConst *s_sc, const long long *s_step,
                                            uint32_t &cnt, bool &iz, IzEvent &ev)
 {
     const int64_t g = c.g;
     const int seg = c.seg;  // the mover's segment of the candidate
-    const SegConst &sc = d.segc[seg];
-    const long long step = d.instd[sc.inst].step;
+    const SegConst &sc = SEGLDS ? s_sc[seg] : d.segc[seg];
+    const long long step = SEGLDS ? s_step[seg] : d.instd[sc.inst].step;
     double vx = c.vx, vy = c.vy, vz = c.vz;
     double g2 = 0.0;
     // with kinetic neutrals: the atom density at the electron (the mover's
@@ -192,14 +200,26 @@ __device__ __forceinline__ const IzEvent &event_at(const EventIndex &X, const De
     return d.ev[(int64_t)lo * d.ev_q + (e - X.pre[lo])];
 }
 
+template <bool SEGLDS>
 __global__ __launch_bounds__(kBlock) void collide_kernel(Dev d)
 {
     extern __shared__ uint32_t s_cnt[];  // [n_seg][kNCnt] when n_seg <= kCntSegMax
     __shared__ uint32_t s_en;
+    __shared__ SegConst s_sc[SEGLDS ? kCollSegLds : 1];
+    __shared__ long long s_step[SEGLDS ? kCollSegLds : 1];
     const bool lds_cnt = d.n_seg <= kCntSegMax;
     if (lds_cnt)
         for (int q = threadIdx.x; q < d.n_seg * kNCnt; q += kBlock) s_cnt[q] = 0u;
     if (threadIdx.x == 0) s_en = 0u;
+    if (SEGLDS) {
+        // the segments' constants word by word, and each segment's step
+        constexpr int kW = (int)(sizeof(SegConst) / 8);
+        static_assert(sizeof(SegConst) % 8 == 0, "segment constants: whole words");
+        const unsigned long long *src = (const unsigned long long *)d.segc;
+        unsigned long long *dst = (unsigned long long *)s_sc;
+        for (int q = threadIdx.x; q < d.n_seg * kW; q += kBlock) dst[q] = src[q];
+        if (threadIdx.x < d.n_seg) s_step[threadIdx.x] = d.instd[d.segc[threadIdx.x].inst].step;
+    }
     __syncthreads();
 
     const int cur = d.glob->cur_set;
@@ -231,7 +251,7 @@ __global__ __launch_bounds__(kBlock) void collide_kernel(Dev d)
         } else {
             idx = (int64_t)d.n_push_blocks * d.cand_q + o_lo + (q - nr);
         }
-        const int seg = collide_one(d, cur, f64, d.cand[idx], cnt, iz, ev);
+        const int seg = collide_one<SEGLDS>(d, cur, f64, d.cand[idx], s_sc, s_step, cnt, iz, ev);
         if (iz) {
             // this block's region of the event list; the rare excess goes to the overflow list
             const uint32_t e = atomicAdd(&s_en, 1u);
@@ -829,7 +849,10 @@ __global__ __launch_bounds__(kBlock) void close_step_kernel(Dev d, int with_even
 hipError_t launch_collide(const Dev &d, hipStream_t st)
 {
     const size_t lds = d.n_seg <= kCntSegMax ? sizeof(uint32_t) * d.n_seg * kNCnt : 0;
-    hipLaunchKernelGGL(collide_kernel, dim3(d.n_push_blocks), dim3(kBlock), lds, st, d);
+    if (d.n_seg <= kCollSegLds)
+        hipLaunchKernelGGL(collide_kernel<true>, dim3(d.n_push_blocks), dim3(kBlock), lds, st, d);
+    else
+        hipLaunchKernelGGL(collide_kernel<false>, dim3(d.n_push_blocks), dim3(kBlock), lds, st, d);
     return hipGetLastError();
 }
 
