@@ -3,9 +3,10 @@
 // dropping absorbed particles (gfx950).
 //
 //   hist     one bin per (species, node) counts the live particles of each
-//            cell; every tile first counts into an LDS window of bins
-//            (wave-level run sums, then LDS atomics) and adds the window to
-//            the global bins with one atomic per touched bin
+//            cell; every wave first counts its chunks of a tile into its own
+//            LDS window of bins (wave-level run sums, then LDS atomics, no
+//            block barrier) and adds the window to the global bins with one
+//            atomic per touched bin
 //   scan     single-pass exclusive scan of all bins (decoupled look-back);
 //            writes the scatter cursors and the per-segment cell offsets
 //   scatter  every tile ranks its particles per bin in LDS, reserves each
@@ -20,7 +21,18 @@
 
 namespace picx {
 
-constexpr int kSortWin = 1024;  // LDS window of bins per tile
+constexpr int kSortWin = 1024;  // LDS window of bins per tile (scatter)
+constexpr int kHistWaveWin = 64;  // LDS window of bins per wave (histogram)
+
+// orders this wave's LDS operations before and after the call (a wave's LDS
+// operations complete in issue order; the fences keep the compiler from
+// moving them across)
+__device__ __forceinline__ void hist_wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 constexpr int kSegLdsS = 1024;
 
 struct SortLds {
@@ -157,11 +169,14 @@ __device__ __forceinline__ void tile_window(SortLds &L, const int (&key)[kPer], 
 __global__ __launch_bounds__(kBlock) void sort_hist_kernel(Dev d)
 {
     __shared__ SortLds L;
+    __shared__ uint32_t wcnt[kWaves][kHistWaveWin];  // each wave's window of bins
+    for (int i = threadIdx.x; i < kWaves * kHistWaveWin; i += kBlock) (&wcnt[0][0])[i] = 0u;
     sort_lds_init(L, d);
     const int cur = d.glob->cur_set;
     const bool f64 = (d.precision == PIC_FP64);
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
+    uint32_t *W = wcnt[wave];
     int hint = 0;  // segment of the previous tile
     for (int64_t t = blockIdx.x; t < d.n_tiles; t += gridDim.x) {
         int64_t tile0, base, count;
@@ -172,29 +187,43 @@ __global__ __launch_bounds__(kBlock) void sort_hist_kernel(Dev d)
         uint32_t *__restrict__ H = d.hist + sc.sp * d.G + sc.gnode;
         int key[kPer];
         tile_keys(d, cur, base, t0, count, f64, key);
-        int lo, hi;
-        tile_window(L, key, lo, hi);
+        // this wave's bins: run sums of equal keys into its own LDS window (no
+        // block barrier), then one global atomic per touched bin
+        int kmn = 0x7fffffff, kmx = -1;
+#pragma unroll
+        for (int k = 0; k < kPer; ++k)
+            if (key[k] >= 0) {
+                kmn = min(kmn, key[k]);
+                kmx = max(kmx, key[k]);
+            }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            kmn = min(kmn, __shfl_xor(kmn, o, 64));
+            kmx = max(kmx, __shfl_xor(kmx, o, 64));
+        }
+        const int lo = __builtin_amdgcn_readfirstlane(kmn);
+        const int hi = __builtin_amdgcn_readfirstlane(kmx);
+        if (hi < 0) continue;  // no live particle in the wave's chunks
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
             bool tail;
-            const unsigned long long s = run_sum(key[k], key[k] >= 0 ? 1ull : 0ull, tail);
+            const unsigned long long n = run_sum(key[k], key[k] >= 0 ? 1ull : 0ull, tail);
             if (tail && key[k] >= 0) {
                 const int rel = key[k] - lo;
-                if (rel < kSortWin) atomicAdd(&L.cnt[rel], (uint32_t)s);
-                else atomicAdd(H + key[k], (uint32_t)s);
+                if (rel < kHistWaveWin) atomicAdd(&W[rel], (uint32_t)n);
+                else atomicAdd(H + key[k], (uint32_t)n);
             }
         }
-        __syncthreads();
-        if (hi >= 0) {
-            const int span = min(hi - lo + 1, kSortWin);
-            for (int i = threadIdx.x; i < span; i += kBlock) {
-                const uint32_t v = L.cnt[i];
-                if (v) {
-                    atomicAdd(H + lo + i, v);
-                    L.cnt[i] = 0u;
-                }
+        hist_wave_sync();
+        const int span = min(hi - lo + 1, kHistWaveWin);
+        for (int i = lane; i < span; i += 64) {
+            const uint32_t v = W[i];
+            if (v) {
+                atomicAdd(H + lo + i, v);
+                W[i] = 0u;
             }
         }
+        hist_wave_sync();
     }
 }
 
