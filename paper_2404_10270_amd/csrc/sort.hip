@@ -118,13 +118,13 @@ __device__ __forceinline__ void tile_keys(const Dev &d, int cur, int64_t base, i
             const double *X = (const double *)d.x[cur] + g0;
             double x[kPer];
 #pragma unroll
-            for (int k = 0; k < kPer; ++k) x[k] = X[k * 64];
+            for (int k = 0; k < kPer; ++k) x[k] = __builtin_nontemporal_load(&X[k * 64]);
 #pragma unroll
             for (int k = 0; k < kPer; ++k) key[k] = x[k] >= 0.0 ? (int)floor(x[k]) : -1;
         } else {
             const int32_t *CELL = d.cell[cur] + g0;
 #pragma unroll
-            for (int k = 0; k < kPer; ++k) key[k] = CELL[k * 64];
+            for (int k = 0; k < kPer; ++k) key[k] = __builtin_nontemporal_load(&CELL[k * 64]);
         }
         return;
     }
@@ -333,14 +333,18 @@ __device__ __forceinline__ void move_fields(const Dev &d, int cur, int nxt, int6
     unsigned long long id[kPer];
     const V *X = (const V *)d.x[cur], *VX = (const V *)d.vx[cur], *VY = (const V *)d.vy[cur],
             *VZ = (const V *)d.vz[cur];
+    // the source arrays are streamed once per sort: nontemporal loads keep
+    // them from displacing the bins, cursors and the scattered destinations
+    // in L2 (the stores stay cached: a tile's particles go to many bins, and
+    // L2 merges their partial lines)
     auto load = [&](int k) {
         const int64_t g = g0 + (int64_t)k * 64;
-        x[k] = X[g];
-        vx[k] = VX[g];
-        vy[k] = VY[g];
-        vz[k] = VZ[g];
-        if (CELL) c[k] = d.cell[cur][g];
-        id[k] = d.id[cur][g];
+        x[k] = __builtin_nontemporal_load(&X[g]);
+        vx[k] = __builtin_nontemporal_load(&VX[g]);
+        vy[k] = __builtin_nontemporal_load(&VY[g]);
+        vz[k] = __builtin_nontemporal_load(&VZ[g]);
+        if (CELL) c[k] = __builtin_nontemporal_load(&d.cell[cur][g]);
+        id[k] = __builtin_nontemporal_load(&d.id[cur][g]);
     };
     if (full) {
         // every slot of a full tile exists: its loads go unpredicated (an
