@@ -88,7 +88,7 @@ __device__ Aff block_exclusive_scan(Aff m, Aff *agg)
 template <class Idx>
 __device__ Aff compose_ordered(const AffineStatus *agg, int64_t n, Idx idx)
 {
-    __shared__ Aff s_m[kBlock];
+    __shared__ Aff s_m[kWaves];
     const int64_t per = (n + kBlock - 1) / kBlock;
     const int64_t a0 = (int64_t)threadIdx.x * per;
     Aff m = {1.0, 0.0};
@@ -96,13 +96,20 @@ __device__ Aff compose_ordered(const AffineStatus *agg, int64_t n, Idx idx)
         const AffineStatus &s = agg[idx(a)];
         m = compose(Aff{s.A, s.B}, m);
     }
-    s_m[threadIdx.x] = m;
-    __syncthreads();
-    for (int s = 1; s < kBlock; s <<= 1) {
-        if ((threadIdx.x & (2 * s - 1)) == 0) s_m[threadIdx.x] = compose(s_m[threadIdx.x + s], s_m[threadIdx.x]);
-        __syncthreads();
+    // the tree's levels inside a wave through shuffles (the same pairs in the
+    // same order as a tree over LDS, without a barrier per level), then the
+    // four wave composites
+    const int lane = lane_id();
+    const int wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int s = 1; s < 64; s <<= 1) {
+        const Aff o = {__shfl_down(m.A, s, 64), __shfl_down(m.B, s, 64)};
+        if ((lane & (2 * s - 1)) == 0) m = compose(o, m);
     }
-    const Aff r = s_m[0];
+    static_assert(kWaves == 4, "the cross-wave levels below are written for four waves");
+    if (lane == 0) s_m[wave] = m;
+    __syncthreads();
+    const Aff r = compose(compose(s_m[3], s_m[2]), compose(s_m[1], s_m[0]));
     __syncthreads();
     return r;
 }
@@ -438,14 +445,23 @@ __global__ __launch_bounds__(kBlock) void field_bwd_kernel(Dev d)
         for (int k = 0; k < nsp; ++k) d.S[k * G + ic.gnode + j] = 0ull;
     }
     // field-energy partial of the tile (1/2 eps0 applied by the diagnostics)
+    // (a halving tree: the two levels across waves through LDS, the six
+    // inside wave 0 through shuffles, the same sums in the same order)
     __shared__ double s_fe[kBlock];
     s_fe[threadIdx.x] = fe;
     __syncthreads();
-    for (int s = kBlock / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) s_fe[threadIdx.x] += s_fe[threadIdx.x + s];
-        __syncthreads();
+    static_assert(kBlock == 256, "the levels below are written for 256 threads");
+    if (threadIdx.x < 128) s_fe[threadIdx.x] += s_fe[threadIdx.x + 128];
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        double v = s_fe[threadIdx.x] + s_fe[threadIdx.x + 64];
+#pragma unroll
+        for (int s = 32; s > 0; s >>= 1) {
+            const double o = __shfl_down(v, s, 64);
+            if (threadIdx.x < s) v += o;
+        }
+        if (threadIdx.x == 0) d.fe_part[ic.ftile0 + lt] = v;
     }
-    if (threadIdx.x == 0) d.fe_part[ic.ftile0 + lt] = s_fe[0];
 }
 
 // ---------------------------------------------------------------------------
