@@ -310,17 +310,25 @@ __global__ __launch_bounds__(kBlock) void field_fwd_kernel(Dev d)
         const int64_t j = j0 + r;
         if (j >= 1 && j <= nc - 1) mb = compose(Aff{gq_of(j), dp[r]}, mb);
     }
-    // the block's composite: threads from the top down
-    __shared__ Aff s_b[kBlock];
-    s_b[kBlock - 1 - threadIdx.x] = mb;
-    __syncthreads();
-    for (int s = 1; s < kBlock; s <<= 1) {
-        if ((threadIdx.x & (2 * s - 1)) == 0) s_b[threadIdx.x] = compose(s_b[threadIdx.x + s], s_b[threadIdx.x]);
-        __syncthreads();
+    // the block's composite: threads from the top down, i.e. an ordered tree
+    // over i = kBlock - 1 - thread.  Inside a wave index i is lane 63 - l of
+    // group 3 - wave, so each level takes the lane s below (the same pairs in
+    // the same order as the tree over LDS, without a barrier per level).
+    const int lane = lane_id();
+    const int wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int s = 1; s < 64; s <<= 1) {
+        const Aff o = shfl_up_aff(mb, s);
+        if (((63 - lane) & (2 * s - 1)) == 0) mb = compose(o, mb);
     }
+    static_assert(kWaves == 4, "the cross-wave levels below are written for four waves");
+    __shared__ Aff s_b[kWaves];
+    if (lane == 63) s_b[wave] = mb;  // the composite of group 3 - wave
+    __syncthreads();
     if (threadIdx.x == 0) {
-        d.bwd_status[vt].A = s_b[0].A;
-        d.bwd_status[vt].B = s_b[0].B;
+        const Aff r = compose(compose(s_b[0], s_b[1]), compose(s_b[2], s_b[3]));
+        d.bwd_status[vt].A = r.A;
+        d.bwd_status[vt].B = r.B;
     }
 }
 
