@@ -285,17 +285,34 @@ __global__ __launch_bounds__(kBlock) void collide_kernel(Dev d)
 
 // write one created particle into segment `seg`, in-segment index `i`
 // (ignored, and flagged, when the segment is full)
-__device__ __forceinline__ void place(const Dev &d, int cur, bool f64, int seg, int64_t i,
+// what placing a created particle in a segment needs, read in one go (the
+// stores of one placement would otherwise make the compiler read the next
+// segment's values again, each after a wait)
+struct PlaceSeg {
+    int64_t base;                 // first slot
+    unsigned long long *S;        // the species' deposit row of the instance
+    uint32_t cap, count;          // slots, occupied slots before this step's creations
+    int inst;
+};
+
+__device__ __forceinline__ PlaceSeg place_seg(const Dev &d, int seg)
+{
+    const SegConst &sc = d.segc[seg];
+    return PlaceSeg{sc.base, d.S + sc.sp * d.G + sc.gnode, sc.cap, d.segd[seg].count, sc.inst};
+}
+
+// write one created particle into segment ps at in-segment index i
+// (ignored, and flagged, when the segment is full)
+__device__ __forceinline__ void place(const Dev &d, int cur, bool f64, const PlaceSeg &ps, int64_t i,
                                       unsigned long long id, int32_t cell, float f, double x,
                                       double vx, double vy, double vz)
 {
-    const SegConst &sc = d.segc[seg];
-    if (i >= (int64_t)sc.cap) {
-        atomicOr(&d.instd[sc.inst].status, PIC_ST_CAPACITY);
+    if (i >= (int64_t)ps.cap) {
+        atomicOr(&d.instd[ps.inst].status, PIC_ST_CAPACITY);
         return;
     }
-    const int64_t g = sc.base + i;
-    unsigned long long *S = d.S + sc.sp * d.G + sc.gnode;
+    const int64_t g = ps.base + i;
+    unsigned long long *S = ps.S;
     int j;
     unsigned long long w1;
     if (f64) {
@@ -657,13 +674,10 @@ __global__ __launch_bounds__(kBlock) void emit_kernel(Dev d)
             const InstDyn &idn = d.instd[ev.inst];
             const long long step = idn.step;
             const unsigned long long nid = idn.next_id + 2ull * rank;
-            const uint4 u1 = draw(ev.parent_id, step, 1, se.key0, se.key1);
-            const uint4 u2 = draw(ev.parent_id, step, 2, se.key0, se.key1);
-            double d0, d1, d2;
-            iso_dir(u1.z, u1.w, d0, d1, d2);
-            double n0, n1, n2, n3;
-            box_muller(u2.x, u2.y, n0, n1);
-            box_muller(u2.z, u2.w, n2, n3);
+            // everything the placements read, before their first store
+            const PlaceSeg pe = place_seg(d, ev.seg), pi = place_seg(d, seg_i);
+            const double sig_n = si.sig_n;
+            const int seg_n = d.instc[ev.inst].seg_n;
             // position of the parent (unchanged by the collision)
             int32_t cell = 0;
             float f = 0.f;
@@ -673,11 +687,17 @@ __global__ __launch_bounds__(kBlock) void emit_kernel(Dev d)
                 cell = d.cell[cur][ev.slot];
                 f = ((const float *)d.x[cur])[ev.slot];
             }
-            place(d, cur, f64, ev.seg, (int64_t)d.segd[ev.seg].count + rank, nid, cell, f, x,
+            const uint4 u1 = draw(ev.parent_id, step, 1, se.key0, se.key1);
+            const uint4 u2 = draw(ev.parent_id, step, 2, se.key0, se.key1);
+            double d0, d1, d2;
+            iso_dir(u1.z, u1.w, d0, d1, d2);
+            double n0, n1, n2, n3;
+            box_muller(u2.x, u2.y, n0, n1);
+            box_muller(u2.z, u2.w, n2, n3);
+            place(d, cur, f64, pe, (int64_t)pe.count + rank, nid, cell, f, x,
                   ev.g2 * d0, ev.g2 * d1, ev.g2 * d2);
             // the ion: Maxwellian at the parent, or the consumed atom itself
-            double ivx = si.sig_n * n0, ivy = si.sig_n * n1, ivz = si.sig_n * n2;
-            const int seg_n = d.instc[ev.inst].seg_n;
+            double ivx = sig_n * n0, ivy = sig_n * n1, ivz = sig_n * n2;
             if (seg_n >= 0) {
                 const long long t = d.ev_target[e];
                 if (t >= 0) {
@@ -698,8 +718,7 @@ __global__ __launch_bounds__(kBlock) void emit_kernel(Dev d)
                     atomicAdd(&d.instd[ev.inst].n_iz_untargeted, 1ull);
                 }
             }
-            place(d, cur, f64, seg_i, (int64_t)d.segd[seg_i].count + rank, nid + 1ull, cell, f, x,
-                  ivx, ivy, ivz);
+            place(d, cur, f64, pi, (int64_t)pi.count + rank, nid + 1ull, cell, f, x, ivx, ivy, ivz);
         }
     }
 
@@ -768,10 +787,13 @@ __global__ __launch_bounds__(kBlock) void emit_kernel(Dev d)
         float f = 0.f;
         if (!f64) split_position(x, ic.nc, cell, f);
         const unsigned long long nid = idn.next_id + 2ull * (m_i + k);
-        place(d, cur, f64, ic.seg_e, (int64_t)d.segd[ic.seg_e].count + m_i + k, nid, cell, f, x,
-              se.sig_src * e0, se.sig_src * e1, se.sig_src * e2);
-        place(d, cur, f64, ic.seg_i, (int64_t)d.segd[ic.seg_i].count + m_i + k, nid + 1ull, cell,
-              f, x, si.sig_src * i0, si.sig_src * i1, si.sig_src * i2);
+        // everything the placements read, before their first store
+        const PlaceSeg pe = place_seg(d, ic.seg_e), pi = place_seg(d, ic.seg_i);
+        const double se_src = se.sig_src, si_src = si.sig_src;
+        place(d, cur, f64, pe, (int64_t)pe.count + m_i + k, nid, cell, f, x, se_src * e0, se_src * e1,
+              se_src * e2);
+        place(d, cur, f64, pi, (int64_t)pi.count + m_i + k, nid + 1ull, cell, f, x, si_src * i0,
+              si_src * i1, si_src * i2);
     }
 }
 
