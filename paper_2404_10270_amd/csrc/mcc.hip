@@ -378,6 +378,17 @@ __global__ __launch_bounds__(kBlock) void rank_kernel(Dev d)
     const bool cells = d.kinetic_any != 0;
     for (uint64_t p = blockIdx.x; p < ni * nj; p += gridDim.x) {
         const uint64_t bi = p / nj, bj = p - bi * nj;
+        // this thread's own event, read before the barrier (beside the
+        // column events' reads)
+        const uint64_t e = bi * kBlock + threadIdx.x;
+        unsigned long long pid = 0;
+        int inst = -1, cell = -1;
+        if (e < m) {
+            const IzEvent &ev = event_at(X, d, (uint32_t)e);
+            pid = ev.parent_id;
+            inst = ev.inst;
+            cell = ev.cell;
+        }
         __syncthreads();
         if (threadIdx.x < kRankJ) {
             const uint64_t k = bj * kRankJ + threadIdx.x;
@@ -394,17 +405,12 @@ __global__ __launch_bounds__(kBlock) void rank_kernel(Dev d)
             s_cell[threadIdx.x] = cell;
         }
         __syncthreads();
-        const uint64_t e = bi * kBlock + threadIdx.x;
         if (e < m) {
-            const IzEvent &ev = event_at(X, d, (uint32_t)e);
-            const unsigned long long pid = ev.parent_id;
-            const int inst = ev.inst;
             uint32_t r = 0;
 #pragma unroll 16
             for (int q = 0; q < kRankJ; ++q) r += (s_inst[q] == inst && s_pid[q] < pid) ? 1u : 0u;
             if (r) atomicAdd(&d.ev_rank[e], r);
             if (cells) {
-                const int cell = ev.cell;
                 uint32_t rc = 0;
                 for (int q = 0; q < kRankJ; ++q)
                     rc += (s_inst[q] == inst && s_cell[q] == cell && s_pid[q] < pid) ? 1u : 0u;
