@@ -492,16 +492,26 @@ __global__ __launch_bounds__(kBlock) void bucket_rank_kernel(Dev d)
     if ((uint64_t)blockIdx.x * kBlock >= d.glob->ev_total) return;
     const uint32_t m = d.glob->ev_total;
     const bool cells = d.kinetic_any != 0;
+    // the bucket starts in LDS for the search below (up to kStartLds instances)
+    constexpr int kStartLds = 1024;
+    __shared__ uint32_t s_start[kStartLds + 1];
+    const bool lds = d.n_inst <= kStartLds;
+    if (lds)
+        for (int i = threadIdx.x; i <= d.n_inst; i += kBlock) s_start[i] = d.inst_start[i];
+    __syncthreads();
+    const uint32_t *start = lds ? s_start : d.inst_start;
     for (uint32_t q = blockIdx.x * kBlock + threadIdx.x; q < m; q += gridDim.x * kBlock) {
         const RankEntry me = d.rank_bucket[q];
         // the instance owning bucket entry q
         int lo = 0, hi = d.n_inst - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (d.inst_start[mid] <= q) lo = mid; else hi = mid - 1;
+            if (start[mid] <= q) lo = mid; else hi = mid - 1;
         }
-        const uint32_t b0 = d.inst_start[lo], b1 = d.inst_start[lo + 1];
+        const uint32_t b0 = start[lo], b1 = start[lo + 1];
         uint32_t r = 0, rc = 0;
+        // (unrolled: eight independent reads of the bucket per wait)
+#pragma unroll 8
         for (uint32_t k = b0; k < b1; ++k) {
             const RankEntry o = d.rank_bucket[k];
             const bool less = o.pid < me.pid;
