@@ -171,7 +171,18 @@ __global__ __launch_bounds__(kBlock) void index_kernel(Dev d)
 // the index index_kernel wrote, into LDS (all threads; a barrier inside)
 __device__ void load_event_index(EventIndex &X, const Dev &d)
 {
-    for (int b = threadIdx.x; b <= d.n_push_blocks; b += kBlock) X.pre[b] = d.ev_pre[b];
+    // all of a thread's loads before its first LDS store (unpredicated: an
+    // index past the last region reads the last entry again)
+    constexpr int kPerT = (kMaxPushBlocks + 1 + kBlock - 1) / kBlock;
+    const int nb = d.n_push_blocks;
+    uint32_t v[kPerT];
+#pragma unroll
+    for (int r = 0; r < kPerT; ++r) v[r] = d.ev_pre[min(threadIdx.x + r * kBlock, (unsigned)nb)];
+#pragma unroll
+    for (int r = 0; r < kPerT; ++r) {
+        const int b = threadIdx.x + r * kBlock;
+        if (b <= nb) X.pre[b] = v[r];
+    }
     if (threadIdx.x == 0) {
         X.total = d.glob->ev_total;
         X.in_regions = d.glob->ev_in_regions;
