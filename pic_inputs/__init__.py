@@ -12,7 +12,7 @@ Units of the particle state handed to both sides:
 These are the in-cell coordinates and the ``x += nstep*vx`` advance of the
 paper's mover (Sec. 2 and the moveb listing in Sec. 6), with nstep = 1.
 
-Workloads (the recipe is restated in the design doc):
+Workloads:
   * ``langmuir``   periodic electron plasma on a neutralising background,
                    512 cells, 100 particles/cell, plasma units (eps0 = 1,
                    omega_p = 1, q/m = -1), lambda_D = 0.5 dx, omega_p dt = 0.1,
