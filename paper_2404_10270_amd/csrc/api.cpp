@@ -307,8 +307,13 @@ int plan(const pic_config *cfgs, int n_inst, Plan &p)
     // candidates: one region per push block, sized so that a block holds
     // 1.25 times its share of the candidates of a full capacity (the shared
     // overflow list, whose appends contend on one counter, stays rare), then
-    // an overflow list sized for the expected total (mean + 10 sigma)
-    p.n_push_blocks = (int)std::min<int64_t>(std::max<int64_t>(p.n_tiles, 1), kMaxPushBlocks);
+    // an overflow list sized for the expected total (mean + 10 sigma).  The
+    // persistent grid: 1024 blocks for the FP32 form (every block resident at
+    // once; the collide kernel, a block per region, and the event index then
+    // cost less than with 2048, the mover the same), 2048 for the FP64 form
+    // (its mover is 16% slower at 1024)
+    const int max_blocks = cfgs[0].precision == PIC_FP64 ? kMaxPushBlocks : kMaxPushBlocks / 2;
+    p.n_push_blocks = (int)std::min<int64_t>(std::max<int64_t>(p.n_tiles, 1), max_blocks);
     L.cand_ovf_cap = cand_capacity(cfgs, n_inst, P);
     L.ev_ovf_cap = L.cand_ovf_cap;
     double expect = 0.0;

@@ -715,12 +715,9 @@ __global__ __launch_bounds__(kBlock) void deposit_kernel(Dev d)
 
 int push_grid(const Dev &d)
 {
-    // persistent-style grid: enough blocks to fill 256 CUs several times over,
-    // never more than there are tiles
-    int64_t g = d.n_tiles;
-    if (g > kMaxPushBlocks) g = kMaxPushBlocks;
-    if (g < 1) g = 1;
-    return (int)g;
+    // persistent-style grid, never more blocks than tiles: one block per
+    // candidate region (the count the layout planned, at most kMaxPushBlocks)
+    return d.n_push_blocks;
 }
 
 template <bool DEP, bool MCC>
