@@ -308,11 +308,12 @@ int plan(const pic_config *cfgs, int n_inst, Plan &p)
     // 1.25 times its share of the candidates of a full capacity (the shared
     // overflow list, whose appends contend on one counter, stays rare), then
     // an overflow list sized for the expected total (mean + 10 sigma).  The
-    // persistent grid: 1024 blocks for the FP32 form (every block resident at
-    // once; the collide kernel, a block per region, and the event index then
-    // cost less than with 2048, the mover the same), 2048 for the FP64 form
-    // (its mover is 16% slower at 1024)
-    const int max_blocks = cfgs[0].precision == PIC_FP64 ? kMaxPushBlocks : kMaxPushBlocks / 2;
+    // persistent grid is one residency of the mover on 256 CUs: 4 blocks per
+    // CU in the FP32 form, 3 in the FP64 form (their register counts allow 4
+    // and 3 waves per SIMD).  A partial second residency leaves the mover's
+    // last blocks running alone, and fewer regions make the collide kernel (a
+    // block per region) and the event index over the regions cheaper.
+    const int max_blocks = cfgs[0].precision == PIC_FP64 ? 256 * 3 : kMaxPushBlocks;
     p.n_push_blocks = (int)std::min<int64_t>(std::max<int64_t>(p.n_tiles, 1), max_blocks);
     L.cand_ovf_cap = cand_capacity(cfgs, n_inst, P);
     L.ev_ovf_cap = L.cand_ovf_cap;

@@ -23,7 +23,7 @@ constexpr int kSortTile = kBlock * kSortR;
 constexpr int kDiagBlocks = 1024;           // blocks of the diagnostics reduction
 constexpr int kEmitBlocks = 64;             // blocks of the emit/close-of-step kernel
 constexpr int kDiagVals = 6;                // live, sum v2, sum vx, vy, vz, (pad)
-constexpr int kMaxPushBlocks = 256 * 8;     // persistent grid of the particle kernels
+constexpr int kMaxPushBlocks = 256 * 4;     // persistent grid of the particle kernels (at most)
 constexpr int kCandQMin = 1024;             // least candidate entries per push block region
 constexpr int kEvQMin = 32;                 // least ionisation-event slots per collide block
 constexpr int kCntSegMax = 1024;           // segments counted per block in LDS (no atomics)
