@@ -131,6 +131,8 @@ def lib():
         L.orc_init_deposit.argtypes = [C.POINTER(Config), ip, C.c_int, C.c_int, C.c_int,
                                        C.c_double, C.c_int, C.c_int, up]
         L.orc_init_deposit.restype = None
+        L.orc_fp32_form.argtypes = [C.c_double, C.c_int32]
+        L.orc_fp32_form.restype = C.c_double
         L.orc_candidate_threshold.argtypes = [C.POINTER(Config), C.c_int]
         L.orc_candidate_threshold.restype = C.c_uint64
         L.orc_neutral_key.argtypes = [C.POINTER(Config), C.c_uint64, C.c_int64]
@@ -194,6 +196,11 @@ def smooth(rho, V, bc: int, passes: int) -> np.ndarray:
     V = np.ascontiguousarray(V, dtype=np.float64)
     lib().orc_smooth(r.shape[0] - 1, int(bc), int(passes), _dp(V), _dp(r))
     return r
+
+
+def fp32_form(x: float, nc: int) -> float:
+    """The value of position x (cells) as stored in the FP32 form (orc_fp32_form)."""
+    return float(lib().orc_fp32_form(float(x), int(nc)))
 
 
 def poisson_dirichlet(d) -> np.ndarray:

@@ -1052,7 +1052,7 @@ void orc_init_species(const orc_config *c, const int64_t *n_init, int k, int qui
 /* x as stored in the FP32 form: cell = floor(x), f = x - cell rounded to
  * float; an f that rounds to 1 moves to offset 0 of the next cell, or, in
  * the last cell, stays at the largest float below 1 */
-static double fp32_form(double x, int32_t nc)
+double orc_fp32_form(double x, int32_t nc)
 {
     double cell = floor(x);
     float f = (float)(x - cell);
@@ -1081,7 +1081,7 @@ void orc_init_deposit(const orc_config *c, const int64_t *n_init, int k, int qui
     for (int64_t p = 0; p < n; ++p) {
         double x = copy ? init_position(c, n_init, 0, p, quiet, amp, mode, (uint64_t)p)
                         : init_position(c, n_init, k, p, quiet, amp, mode, (uint64_t)(id0 + p));
-        if (fp32) x = fp32_form(x, c->nc);
+        if (fp32) x = orc_fp32_form(x, c->nc);
         deposit_add(x, S);
     }
 }

@@ -57,6 +57,22 @@ MUTATIONS = [
     ("field left on without the solver", "    if (c->field_off) {", "    if (0) {"),
     ("new electrons not counted in n_e", "append(s, ke, xe[r], ev[r].ve, s->cnt.next_id + 2 * (uint64_t)r);",
      "(void)xe;"),
+    ("kinetic energy without the half", "out->ke[k] = 0.5 * c->m[k] * c->w[k] * (vs * vs) * s2;",
+     "out->ke[k] = c->m[k] * c->w[k] * (vs * vs) * s2;"),
+    ("kinetic energy with dx/dt not squared", "c->w[k] * (vs * vs) * s2;", "c->w[k] * vs * s2;"),
+    ("momentum z from vx", "pz += P->vz[p];", "pz += P->vx[p];"),
+    ("field energy with full wall-node volumes", "fe += s->E[j] * s->E[j] * V;",
+     "fe += s->E[j] * s->E[j] * c->dx;"),
+    ("periodic field energy counts node nc twice", "for (int32_t j = 0; j < nc; ++j) fe +=",
+     "for (int32_t j = 0; j <= nc; ++j) fe +="),
+    ("field energy without the half", "out->field_energy = 0.5 * c->eps0 * fe;",
+     "out->field_energy = c->eps0 * fe;"),
+    ("FP32 form leaves the last cell", "if (cell + 1.0 < (double)nc) {", "if (1) {"),
+    ("FP32 form keeps an offset of one", "if (f >= 1.0f) {", "if (f > 1.0f) {"),
+    ("x = nc kept", "if (x >= L) { s->cnt.absorbed[k][1]++; continue; }",
+     "if (x > L) { s->cnt.absorbed[k][1]++; continue; }"),
+    ("x = 0 absorbed", "if (x < 0.0) { s->cnt.absorbed[k][0]++; continue; }",
+     "if (x <= 0.0) { s->cnt.absorbed[k][0]++; continue; }"),
 ]
 
 
