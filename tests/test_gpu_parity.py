@@ -193,6 +193,15 @@ def test_mcc_one_step(prec):
     sim.close()
 
 
+def _check_momentum(d, od, wl, rel):
+    """Momentum per species and component against the oracle's, within rel of
+    the sum of |m w V| (bounded by sqrt(2 m w N KE))."""
+    for k, s in enumerate(wl.species):
+        scale = math.sqrt(2.0 * s.m * s.w * od.n[k] * od.ke[k])
+        for c in range(3):
+            assert abs(d.mom[k][c] - od.mom[k][c]) <= rel * scale, (k, c, d.mom[k][c], od.mom[k][c])
+
+
 def test_langmuir_fp64_200_steps():
     """Whole steps (push, close of step, field solve) for the plain-method workload."""
     wl = pin.langmuir()
@@ -212,6 +221,7 @@ def test_langmuir_fp64_200_steps():
     assert np.max(np.abs(g["x"] - o["x"])) <= 1e-8
     assert np.max(np.abs(g["vx"] - o["vx"])) <= 1e-10
     assert abs(d[0].ke[0] / od.ke[0] - 1) <= 1e-10
+    _check_momentum(d[0], od, wl, 1e-10)
     assert abs(d[0].field_energy / od.field_energy - 1) <= 1e-6
     assert d[0].particle_steps == 200 * 51200
     sim.close()
@@ -244,6 +254,7 @@ def test_bounded_mcc_steps_with_sort(prec):
             g, o = gpu_state(sim, k), oracle_state(orc, k)
             assert np.max(np.abs(g["x"] - o["x"])) <= 1e-7
             assert abs(d.ke[k] / od.ke[k] - 1) <= 1e-9
+        _check_momentum(d, od, wl, 1e-9)
     else:
         for k in range(2):
             assert abs(d.ke[k] / od.ke[k] - 1) <= 5e-3
