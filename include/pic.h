@@ -18,10 +18,14 @@
  * caller, and must outlive the context.  libpic never allocates or frees
  * device memory; a context holds host metadata only.
  *
- * Streams.  All calls except pic_query_sizes, pic_region, pic_diagnostics,
- * pic_destroy and pic_strerror enqueue work on the HIP stream given to
- * pic_init and return without synchronising.  A context is not thread-safe;
- * use one context per stream.
+ * Streams.  pic_init synchronises its stream once, after uploading the
+ * tables (the initial draw, sort, deposit and field solve it enqueues after
+ * that are not waited for); pic_diagnostics and pic_autotune_sort
+ * synchronise too.  Every other phase call enqueues
+ * work on the HIP stream given to pic_init and returns without
+ * synchronising; pic_query_sizes, pic_region, pic_destroy and pic_strerror
+ * do no device work.  A context is not thread-safe; use one context per
+ * stream.
  *
  * Errors.  Host-detectable errors (bad arguments or configuration) return a
  * negative pic_status before any device work is enqueued.  Conditions found
