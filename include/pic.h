@@ -16,7 +16,9 @@
  * Ownership.  Every device buffer is allocated by the caller (typically as
  * PyTorch tensors) with the sizes pic_query_sizes reports, stays owned by the
  * caller, and must outlive the context.  libpic never allocates or frees
- * device memory; a context holds host metadata only.
+ * device memory; a context holds host metadata only.  The one exception is
+ * the static workspace array of pic_init_static (a fixed-size device array
+ * of the library, not an allocation at run time).
  *
  * Streams.  pic_init synchronises its stream once, after uploading the
  * tables (the initial draw, sort, deposit and field solve it enqueues after
@@ -53,7 +55,9 @@ typedef enum {
     PIC_E_CAPACITY = -4,   /* device status: a created/uploaded particle did not fit */
     PIC_E_CFL = -5,        /* device status: |vx| >= 1 cell per step */
     PIC_E_NONFINITE = -6,  /* device status: non-finite velocity or field */
-    PIC_E_STATE = -7       /* call out of order (e.g. a phase before pic_init) */
+    PIC_E_STATE = -7,      /* call out of order (e.g. a phase before pic_init) */
+    PIC_E_SCRATCH = -8,    /* pic_init_static: the workspace exceeds PIC_STATIC_WORK_MAX */
+    PIC_E_BUSY = -9        /* pic_init_static: a live context holds the device's static workspace */
 } pic_status;
 
 /* device status word bits (pic_diag.status) */
@@ -348,6 +352,32 @@ int pic_step_graph(pic_ctx *ctx, int n_steps, int sort_every);
  */
 int pic_autotune_sort(pic_ctx *ctx, const int *cand, int n_cand, int trial_steps, int *best,
                       double *rates);
+
+/*
+ * pic_init_static -- pic_init for callers that cannot allocate device memory
+ * (serving loops and harnesses that forbid hipMalloc): the workspace is not
+ * a caller buffer but a static device array of the library, PIC_STATIC_WORK_MAX
+ * bytes on each GPU it runs on, held until the process ends.  Same arguments,
+ * checks, flags, work and results as pic_init, except:
+ *   - bufs->work must be NULL (PIC_E_ARG otherwise); the particle buffers are
+ *     the caller's, as for pic_init;
+ *   - a configuration whose pic_sizes.work_bytes exceeds PIC_STATIC_WORK_MAX
+ *     returns PIC_E_SCRATCH before any device work;
+ *   - the array belongs to the device current at the call; while a context
+ *     made by pic_init_static on that device is alive (until its
+ *     pic_destroy), another pic_init_static there returns PIC_E_BUSY.  The
+ *     array keeps the last context's contents; pic_init_static clears the
+ *     part it uses, as pic_init clears its workspace;
+ *   - no device or pinned host memory is allocated: the diagnostics are
+ *     staged in the context (host memory), not in pinned memory.
+ * The context is used with every other call like one from pic_init;
+ * pic_region offsets are into the static array, which the caller cannot
+ * address.  pic_step_graph on such a context still creates its capture
+ * stream and graph.
+ */
+#define PIC_STATIC_WORK_MAX (64ull << 20)
+int pic_init_static(const pic_config *cfgs, int n_inst, const pic_buffers *bufs, void *stream,
+                    unsigned flags, pic_ctx **out);
 
 /* pic_region -- byte offset (into pic_buffers.work) and element count of a
  * workspace region; host only. */

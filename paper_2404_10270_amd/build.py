@@ -2,7 +2,7 @@
 
     python -m paper_2404_10270_amd.build
 
-Every source under csrc/ is compiled with hipcc for gfx950 and linked into
+Every source under csrc/ (*.hip, *.cpp) is compiled with hipcc for gfx950 and linked into
 paper_2404_10270_amd/libpic.so next to this file; study/layout.hip (the
 particle-layout study of the mover) is linked into libpic_layout.so.
 """
@@ -62,7 +62,7 @@ def _link(objs, lib: str) -> None:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(OBJ, exist_ok=True)
-    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip"))) + [os.path.join(CSRC, "api.cpp")]
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip"))) + sorted(glob.glob(os.path.join(CSRC, "*.cpp")))
     study = [os.path.join(STUDY, "layout.hip")]
     jobs = min(len(srcs) + len(study), int(os.environ.get("MAX_JOBS", "8")), 16)
     with cf.ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:

@@ -23,7 +23,10 @@ struct pic_ctx {
     Dev d{};
     hipStream_t st = nullptr;
     int64_t host_steps = 0;   // steps enqueued since init
-    pic_diag *host_diag = nullptr;  // pinned staging for pic_diagnostics
+    pic_diag *host_diag = nullptr;  // staging for pic_diagnostics: pinned (pic_init) ...
+    bool host_diag_pinned = false;
+    std::vector<pic_diag> diag_stage;  // ... or held here (pic_init_static)
+    int static_dev = -1;            // device whose static workspace this context holds
     // pic_step_graph: one sort period captured on a stream of its own
     hipStream_t cap_st = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -388,8 +391,24 @@ int pic_query_sizes(const pic_config *cfgs, int n_inst, pic_sizes *out, int64_t 
     return PIC_OK;
 }
 
-int pic_init(const pic_config *cfgs, int n_inst, const pic_buffers *bufs, void *stream,
-             unsigned flags, pic_ctx **out)
+}  // extern "C"
+
+namespace picx {
+
+uint64_t work_bytes_of(const pic_config *cfgs, int n_inst, int *rc)
+{
+    *rc = validate(cfgs, n_inst);
+    if (*rc) return 0;
+    Plan p;
+    *rc = plan(cfgs, n_inst, p);
+    return *rc ? 0 : p.L.total;
+}
+
+// pic_init with the workspace at W (bufs->work is not read).  pinned_diag:
+// stage the diagnostics in pinned host memory (pic_init) or in the context
+// itself (pic_init_static, which allocates no device or pinned memory).
+int init_context(const pic_config *cfgs, int n_inst, const pic_buffers *bufs, void *W,
+                 void *stream, unsigned flags, bool pinned_diag, pic_ctx **out)
 {
     if (!out) return PIC_E_ARG;
     *out = nullptr;
@@ -410,7 +429,7 @@ int pic_init(const pic_config *cfgs, int n_inst, const pic_buffers *bufs, void *
             return PIC_E_ARG;
         if (!f64 && !aligned(bufs->cell[b])) return PIC_E_ARG;
     }
-    if (!aligned(bufs->work)) return PIC_E_ARG;
+    if (!aligned(W)) return PIC_E_ARG;
 
     pic_ctx *c = new (std::nothrow) pic_ctx();
     if (!c) return PIC_E_ARG;
@@ -493,7 +512,6 @@ int pic_init(const pic_config *cfgs, int n_inst, const pic_buffers *bufs, void *
     g.since_sort = kNoIndex;  // no cell offsets yet
     for (int q = 0; q < 4; ++q) g.scan_gen[q] = 1;
 
-    void *W = bufs->work;
     Dev &d = c->d;
     for (int b = 0; b < 2; ++b) {
         d.x[b] = bufs->x[b];
@@ -593,15 +611,37 @@ int pic_init(const pic_config *cfgs, int n_inst, const pic_buffers *bufs, void *
         ok = launch_deposit(d, st) == hipSuccess;
         ok = ok && launch_field(d, st, c->max_smooth) == hipSuccess;
     }
-    ok = ok && hipHostMalloc((void **)&c->host_diag, sizeof(pic_diag) * n_inst,
-                             hipHostMallocDefault) == hipSuccess;
+    if (pinned_diag) {
+        ok = ok && hipHostMalloc((void **)&c->host_diag, sizeof(pic_diag) * n_inst,
+                                 hipHostMallocDefault) == hipSuccess;
+        c->host_diag_pinned = true;
+    } else {
+        c->diag_stage.resize(n_inst);
+        c->host_diag = c->diag_stage.data();
+    }
     if (!ok) {
-        if (c->host_diag) (void)hipHostFree(c->host_diag);
+        if (c->host_diag && c->host_diag_pinned) (void)hipHostFree(c->host_diag);
         delete c;
         return PIC_E_DEVICE;
     }
     *out = c;
     return PIC_OK;
+}
+
+void mark_static(pic_ctx *c, int device) { c->static_dev = device; }
+
+}  // namespace picx
+
+extern "C" {
+
+int pic_init(const pic_config *cfgs, int n_inst, const pic_buffers *bufs, void *stream,
+             unsigned flags, pic_ctx **out)
+{
+    if (!bufs) {
+        if (out) *out = nullptr;
+        return PIC_E_ARG;
+    }
+    return init_context(cfgs, n_inst, bufs, bufs->work, stream, flags, true, out);
 }
 
 int pic_push(pic_ctx *c, unsigned flags)
@@ -834,7 +874,8 @@ int pic_destroy(pic_ctx *c)
     if (!c) return PIC_E_ARG;
     drop_graph(c);
     if (c->cap_st) (void)hipStreamDestroy(c->cap_st);
-    if (c->host_diag) (void)hipHostFree(c->host_diag);
+    if (c->host_diag && c->host_diag_pinned) (void)hipHostFree(c->host_diag);
+    if (c->static_dev >= 0) static_release(c->static_dev);
     delete c;
     return PIC_OK;
 }
@@ -850,6 +891,9 @@ const char *pic_strerror(int code)
     case PIC_E_CFL: return "|vx| reached one cell per step";
     case PIC_E_NONFINITE: return "non-finite particle velocity";
     case PIC_E_STATE: return "call out of order or inconsistent device state";
+    case PIC_E_SCRATCH:
+        return "workspace larger than the library's static scratch array (PIC_STATIC_WORK_MAX)";
+    case PIC_E_BUSY: return "the device's static scratch array is held by another context";
     default: return "unknown error";
     }
 }

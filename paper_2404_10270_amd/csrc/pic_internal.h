@@ -260,4 +260,17 @@ hipError_t launch_diag(const Dev &d, hipStream_t st);
 
 int push_grid(const Dev &d);
 
+// ---------------------------------------------------------------------------
+// host side: context set-up shared by pic_init and pic_init_static
+// ---------------------------------------------------------------------------
+// workspace bytes of a configuration (0 and *rc < 0 when it is invalid)
+uint64_t work_bytes_of(const pic_config *cfgs, int n_inst, int *rc);
+// pic_init with the workspace at W; pinned_diag: stage the diagnostics in
+// pinned host memory, else in the context
+int init_context(const pic_config *cfgs, int n_inst, const pic_buffers *bufs, void *W,
+                 void *stream, unsigned flags, bool pinned_diag, pic_ctx **out);
+// the context holds the static workspace of `device` (released by pic_destroy)
+void mark_static(pic_ctx *c, int device);
+void static_release(int device);
+
 }  // namespace picx

@@ -23,6 +23,8 @@ PIC_FRAC_BITS = 32
 
 PIC_OK, PIC_E_ARG, PIC_E_CONFIG, PIC_E_DEVICE = 0, -1, -2, -3
 PIC_E_CAPACITY, PIC_E_CFL, PIC_E_NONFINITE, PIC_E_STATE = -4, -5, -6, -7
+PIC_E_SCRATCH, PIC_E_BUSY = -8, -9
+PIC_STATIC_WORK_MAX = 64 << 20
 
 PIC_ST_CAPACITY, PIC_ST_CFL, PIC_ST_NONFINITE = 0x1, 0x2, 0x4
 PIC_ST_CANDIDATES, PIC_ST_INTERNAL, PIC_ST_BAD_INIT = 0x8, 0x10, 0x20
@@ -46,7 +48,8 @@ PIC_PUSH_NO_DEPOSIT = 0x1
 # every entry point declared in include/pic.h
 ABI_SYMBOLS = ("pic_query_sizes", "pic_init", "pic_push", "pic_deposit", "pic_field_solve",
                "pic_mcc_collide", "pic_sort", "pic_diagnostics", "pic_step", "pic_step_graph",
-               "pic_autotune_sort", "pic_region", "pic_destroy", "pic_strerror")
+               "pic_autotune_sort", "pic_region", "pic_destroy", "pic_strerror",
+               "pic_init_static")
 
 
 class pic_species(C.Structure):
@@ -120,6 +123,7 @@ def lib():
                                       C.POINTER(C.c_int64)]
         L.pic_init.argtypes = [C.POINTER(pic_config), C.c_int, C.POINTER(pic_buffers), P, C.c_uint,
                                C.POINTER(P)]
+        L.pic_init_static.argtypes = L.pic_init.argtypes
         for name in ("pic_push",):
             getattr(L, name).argtypes = [P, C.c_uint]
         for name in ("pic_deposit", "pic_field_solve", "pic_mcc_collide", "pic_sort",
@@ -175,6 +179,15 @@ def pic_init(cfgs: Sequence[pic_config], bufs: pic_buffers, stream: int, flags: 
     ctx = C.c_void_p()
     _check(lib().pic_init(arr, len(cfgs), C.byref(bufs), C.c_void_p(stream), flags,
                           C.byref(ctx)), "pic_init")
+    return ctx
+
+
+def pic_init_static(cfgs: Sequence[pic_config], bufs: pic_buffers, stream: int, flags: int = 0):
+    """pic_init with the library's static workspace (bufs.work must be NULL)."""
+    arr = (pic_config * len(cfgs))(*cfgs)
+    ctx = C.c_void_p()
+    _check(lib().pic_init_static(arr, len(cfgs), C.byref(bufs), C.c_void_p(stream), flags,
+                                 C.byref(ctx)), "pic_init_static")
     return ctx
 
 
@@ -287,7 +300,7 @@ class PicSim:
     """
 
     def __init__(self, workloads, states, precision: int, capacities=None, flags: int = 0,
-                 next_ids=None, step0: int = 0, device: str = "cuda"):
+                 next_ids=None, step0: int = 0, device: str = "cuda", static_work: bool = False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("libpic needs a ROCm GPU; none is visible")
@@ -329,7 +342,10 @@ class PicSim:
         self.vy = [torch.zeros(n, dtype=fdt, device=dev) for _ in range(2)]
         self.vz = [torch.zeros(n, dtype=fdt, device=dev) for _ in range(2)]
         self.id = [torch.zeros(n, dtype=torch.int64, device=dev) for _ in range(2)]
-        self.work = torch.zeros(int(sizes.work_bytes), dtype=torch.uint8, device=dev)
+        # static_work: the context uses libpic's static workspace (pic_init_static)
+        self.static_work = static_work
+        self.work = None if static_work else torch.zeros(int(sizes.work_bytes), dtype=torch.uint8,
+                                                         device=dev)
         # upload the initial state into set 0
         for i, st in enumerate(states):
             if st is None:
@@ -358,11 +374,12 @@ class PicSim:
             bufs.vy[b] = self.vy[b].data_ptr()
             bufs.vz[b] = self.vz[b].data_ptr()
             bufs.id[b] = self.id[b].data_ptr()
-        bufs.work = self.work.data_ptr()
+        bufs.work = None if static_work else self.work.data_ptr()
         self.bufs = bufs
         self.stream = torch.cuda.current_stream()
         torch.cuda.synchronize()
-        self.ctx = pic_init(cfgs, bufs, self.stream.cuda_stream, flags)
+        init = pic_init_static if static_work else pic_init
+        self.ctx = init(cfgs, bufs, self.stream.cuda_stream, flags)
 
     # -- phases -------------------------------------------------------------
     def push(self, flags: int = 0):
@@ -407,6 +424,8 @@ class PicSim:
     # -- views ----------------------------------------------------------------
     def region(self, region: int, dtype):
         """A torch view of a workspace region."""
+        if self.work is None:
+            raise RuntimeError("the static workspace of pic_init_static is not addressable")
         off, n = pic_region(self.ctx, region)
         esz = self.torch.empty(0, dtype=dtype).element_size()
         return self.work[off:off + n * esz].view(dtype)

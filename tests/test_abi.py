@@ -144,8 +144,35 @@ def test_init_argument_errors_before_device_work(P):
     assert L.pic_destroy(None) == P.PIC_E_ARG
 
 
+def test_init_static_refuses_before_device_work(P):
+    """pic_init_static: a caller workspace, or a configuration whose workspace
+    exceeds PIC_STATIC_WORK_MAX, is refused before any device call."""
+    L = P.lib()
+    ctx = C.c_void_p()
+    small = _cfg(P)
+    arr = (P.pic_config * 1)(small)
+    b = P.pic_buffers()
+    b.work = 0x100000
+    assert L.pic_init_static(arr, 1, C.byref(b), None, 0, C.byref(ctx)) == P.PIC_E_ARG
+    assert L.pic_init_static(arr, 1, None, None, 0, C.byref(ctx)) == P.PIC_E_ARG
+    assert ctx.value is None
+    wl = pin.bounded_mcc(nc=100_000, ppc=100, seed=3)
+    n = [int(round(sp.ppc * wl.nc)) for sp in wl.species]
+    big = P.make_config(wl, P.PIC_FP32, [m + 1024 for m in n], n, sum(n))
+    sizes, _ = P.pic_query_sizes([big])
+    assert sizes.work_bytes > P.PIC_STATIC_WORK_MAX
+    b.work = None
+    arr = (P.pic_config * 1)(big)
+    assert L.pic_init_static(arr, 1, C.byref(b), None, 0, C.byref(ctx)) == P.PIC_E_SCRATCH
+    bad = _cfg(P)
+    bad.dt = 0.0
+    arr = (P.pic_config * 1)(bad)
+    assert L.pic_init_static(arr, 1, C.byref(b), None, 0, C.byref(ctx)) == P.PIC_E_CONFIG
+    assert ctx.value is None
+
+
 def test_strerror(P):
-    for code in (0, -1, -2, -3, -4, -5, -6, -7, -99):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7, -8, -9, -99):
         s = P.pic_strerror(code)
         assert isinstance(s, str) and s
 
