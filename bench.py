@@ -15,9 +15,13 @@ timed region.
 Prints one JSON line.  `value` = particles pushed per second over the K timed
 steps (every step runs push+deposit+candidate test, collisions, pairs and
 source, field solve, and a sort every 20 steps).  `roofline` is for the
-dominant kernel (the fused mover), timed with HIP events on its stream.
-Beside it: the FP64 form, 256 batched instances, and the paper's own Table 1
-test case (electrons, D+ ions and kinetic D atoms, no field solve).
+dominant kernel (the fused mover), timed with HIP events on its stream;
+`windows` gives the median, least and largest rate of five further one-period
+windows.  Beside it: the FP64 form, the 4e8-particle instance on 1,000,000
+cells in both forms, the two small configurations (Langmuir, 8,192-cell
+bounded plasma), 256 batched instances, the paper's own Table 1 test case
+(electrons, D+ ions and kinetic D atoms, no field solve), and the oracle on
+the host's cores.
 """
 from __future__ import annotations
 
@@ -88,6 +92,28 @@ def run_form(torch, sim, steps, warmup, graph=False):
     ps = int(d1[0].particle_steps - d0[0].particle_steps)
     dt = t1 - t0
     return ps / dt, 1e3 * dt / steps, ps
+
+
+def time_windows(torch, sim, n_windows=5, steps=SORT_EVERY, sort_every=SORT_EVERY):
+    """Rate of `n_windows` further windows of `steps` whole steps each (one
+    sort period), replayed from the HIP graph and timed with HIP events on the
+    context's stream: median, least and largest p-steps/s."""
+    import statistics
+    rates = []
+    for _ in range(n_windows):
+        d0, _ = sim.diagnostics()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(sim.stream)
+        sim.step_graph(steps, sort_every)
+        e1.record(sim.stream)
+        d1, rc = sim.diagnostics()
+        if rc != 0:
+            raise RuntimeError(f"device status {d1[0].status:#x} in a timed window")
+        ps = sum(int(d1[i].particle_steps - d0[i].particle_steps) for i in range(len(d1)))
+        rates.append(ps / (e0.elapsed_time(e1) * 1e-3))
+    return {"windows": n_windows, "steps_each": steps, "median": statistics.median(rates),
+            "min": min(rates), "max": max(rates)}
 
 
 def time_push(torch, sim, n_steps):
@@ -317,32 +343,125 @@ def _rel_diff(a, b):
     return r
 
 
-def precision_study(torch, args):
-    """The precision study (FP32/fixed-point form against the FP64 form): the
-    1,000,000-cell bounded MCC instance (200 particles per cell per species,
-    4e8 particles) run for 2,000 steps as the FP64 and as the FP32 GPU form from
-    the same drawn start, and the 10,000-cell instance with the same plasma
-    (the 1% subsample) run as both GPU forms and compared with the oracle's
-    moments at steps 500..2000 (tests/golden/precision_subsample_oracle.json,
-    written by the oracle alone).  Reported: the largest relative difference of
-    N, kinetic energy, field energy and a 64-bin density profile per species,
-    beside the FP64 form's own noise floor (the same run with every drawn
-    position moved by one ulp)."""
+PRECISION_BINS = 64
+
+
+def perturb_one_ulp(torch, sim, nc, seed):
+    """Move every particle position of an FP64-form context (current buffer
+    set) by one ulp, up or down by a fair sign per particle drawn from a
+    device torch.Generator seeded `seed` (species in order); a position that
+    would leave [0, nc) keeps its value.  Then deposit and solve the field, as
+    pic_init does after its draw (the context is made with PIC_INIT_NO_FIELD)."""
+    from paper_2404_10270_amd import pic as P
+    if sim.precision != P.PIC_FP64:
+        raise ValueError("the one-ulp ensemble perturbs the FP64 form")
+    d, _ = sim.diagnostics()
+    cur = d[0].cur_set
+    dev = sim.x[cur].device
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    inf = torch.tensor(float("inf"), dtype=torch.float64, device=dev)
+    for k in range(sim.nsp):
+        b = sim.seg_base[k]
+        m = int(d[0].n_slots_used[k])
+        x = sim.x[cur][b:b + m]
+        up = torch.randint(0, 2, (m,), generator=g, device=dev, dtype=torch.int8) == 1
+        y = torch.where(up, torch.nextafter(x, inf), torch.nextafter(x, -inf))
+        x.copy_(torch.where((y < 0) | (y >= nc), x, y))
+    torch.cuda.synchronize()
+    sim.deposit()
+    sim.field_solve()
+
+
+def _protocol_moments(torch, sim, nc):
+    m = _gpu_moments(torch, sim, nc, PRECISION_BINS)
+    m["E"] = sum(m[f"KE{k}"] for k in range(sim.nsp)) + m["FE"]
+    return m
+
+
+def precision_protocol(torch, wl, caps, steps, K, flags, label=""):
+    """The precision protocol (fixed before it was measured): the FP32/fixed-point
+    form's moments after `steps` steps against the FP64 form R, with the bound
+    per moment max(1e-4, spread of an FP64 ensemble).  The ensemble is R and K
+    FP64 runs whose drawn start has every position moved by one ulp (run i:
+    signs from a device generator seeded 1000 + i).  Moments: live particles
+    N and kinetic energy KE per species, field energy FE, total energy E, and
+    a 64-bin density profile h per species.  spread = (largest - smallest over
+    the K + 1 runs) / |R| (a profile: per bin, then the largest bin); the FP32
+    deviation e = |FP32 - R| / |R| (a profile: the largest bin) passes iff
+    e <= max(1e-4, spread).  All runs are drawn on the device (`flags`)."""
     import numpy as np
+    from paper_2404_10270_amd import pic as P
+
+    def run(prec, seed=None):
+        f = flags | (P.PIC_INIT_NO_FIELD if seed is not None else 0)
+        sim = P.PicSim(wl, None, prec, capacities=caps, flags=f)
+        try:
+            if seed is not None:
+                perturb_one_ulp(torch, sim, wl.nc, seed)
+            t0 = time.perf_counter()
+            sim.step_graph(steps, SORT_EVERY)
+            m = _protocol_moments(torch, sim, wl.nc)
+        finally:
+            sim.close()
+            torch.cuda.empty_cache()
+        name = "FP32" if prec == P.PIC_FP32 else ("FP64" if seed is None else f"FP64 ulp {seed}")
+        log(f"precision{label}: {name} run, {steps} steps in {time.perf_counter() - t0:.1f} s")
+        return m
+
+    ens = [run(P.PIC_FP64)]
+    ens += [run(P.PIC_FP64, 1000 + i) for i in range(1, K + 1)]
+    f32 = run(P.PIC_FP32)
+    ref = ens[0]
+    keys = [f"N{k}" for k in range(len(wl.species))] + [f"KE{k}" for k in range(len(wl.species))]
+    keys += ["FE", "E"] + [f"h{k}" for k in range(len(wl.species))]
+    out = {}
+    for key in keys:
+        vals = np.array([np.asarray(m[key], np.float64) for m in ens])
+        den = np.maximum(np.abs(vals[0]), 1e-300)
+        spread = float(np.max((vals.max(axis=0) - vals.min(axis=0)) / den))
+        dev = float(np.max(np.abs(np.asarray(f32[key], np.float64) - vals[0]) / den))
+        bound = max(1e-4, spread)
+        out[key] = {"fp32_dev": dev, "fp64_spread": spread, "bound": bound,
+                    "binds": "spread" if spread > 1e-4 else "1e-4", "pass": bool(dev <= bound)}
+        log(f"precision{label}: {key} FP32 {dev:.3e}, FP64 spread {spread:.3e}, "
+            f"{'pass' if dev <= bound else 'FAIL'}")
+    return {"steps": steps, "ensemble": K + 1, "moments": out,
+            "fp64_R": {k: ref[k] for k in keys if not k.startswith("h")},
+            "fp32": {k: f32[k] for k in keys if not k.startswith("h")}}
+
+
+def precision_study(torch, args):
+    """The precision study (FP32/fixed-point form against the FP64 form).
+    1. The precision protocol on the 10,000-cell instance (200 particles per
+       cell per species, 4e6 particles, MCC and source) over 10^4 steps, with a
+       16-run FP64 ensemble.
+    2. The same instance (the 1% subsample of the precision configuration)
+       over 2,000 steps as both GPU forms, compared with the oracle's moments
+       at steps 500..2000 (tests/golden/precision_subsample_oracle.json,
+       written by the oracle alone).
+    3. The precision protocol on the 1,000,000-cell instance (4e8 particles)
+       over 2,000 steps, with an 8-run FP64 ensemble.
+    All drawn on the device."""
     import pic_inputs as pin
     from paper_2404_10270_amd import pic as P
-    bins = 64
-    out = {}
-    # ---- the 1% subsample: oracle, FP64 form, FP32 form, one-ulp floor
+    bins = PRECISION_BINS
+    out = {"protocol": "bound per moment max(1e-4, FP64 one-ulp ensemble spread); FP32 passes "
+                       "iff |FP32 - FP64| / |FP64| <= bound"}
+    wl = pin.bounded_mcc(nc=10_000, ppc=200, seed=5)
+    n = int(round(200 * wl.nc))
+    if not args.precision_skip_small:
+        caps = [4 * n + 1024] * 2  # ionisation grows the plasma by ~80% over 10^4 steps
+        out["instance_10k_cells"] = precision_protocol(torch, wl, caps, 10_000, 16, P.PIC_INIT_DEVICE,
+                                                       " (10,000 cells)")
+    # ---- the 1% subsample against the oracle's moments
     with open(PRECISION_GOLDEN) as f:
         gold = json.load(f)
-    wl = pin.bounded_mcc(nc=10_000, ppc=200, seed=5)
-    caps = gold["caps"]
     checks = [r["step"] for r in gold["moments"][1:]]
     runs = {}
     for name, prec in (("fp64", P.PIC_FP64), ("fp32", P.PIC_FP32)):
-        log(f"precision: 10,000-cell instance, {name} form")
-        sim = P.PicSim(wl, None, prec, capacities=caps, flags=P.PIC_INIT_DEVICE)
+        log(f"precision: 10,000-cell instance against the oracle, {name} form")
+        sim = P.PicSim(wl, None, prec, capacities=gold["caps"], flags=P.PIC_INIT_DEVICE)
         rows, last = [], 0
         for c in checks:
             sim.step_graph(c - last, SORT_EVERY)
@@ -350,56 +469,18 @@ def precision_study(torch, args):
             rows.append(_gpu_moments(torch, sim, wl.nc, bins))
         runs[name] = rows
         sim.close()
-    # the FP64 noise floor: positions of the drawn start moved by one ulp
-    sim = P.PicSim(wl, None, P.PIC_FP64, capacities=caps, flags=P.PIC_INIT_DEVICE)
-    st0 = [sim.state(k) for k in range(2)]
-    n_drawn = sum(int(s["id"].shape[0]) for s in st0)
-    sim.close()
-    pert = []
-    for k in range(2):
-        x = np.nextafter(st0[k]["x"], np.inf)
-        x = np.where(x >= wl.nc, st0[k]["x"], x)
-        pert.append(pin.SpeciesState(x=x, vx=st0[k]["vx"], vy=st0[k]["vy"], vz=st0[k]["vz"],
-                                     id=st0[k]["id"]))
-    log("precision: 10,000-cell instance, FP64 form, positions moved one ulp")
-    sim = P.PicSim(wl, pert, P.PIC_FP64, capacities=caps, next_ids=[n_drawn])
-    rows, last = [], 0
-    for c in checks:
-        sim.step_graph(c - last, SORT_EVERY)
-        last = c
-        rows.append(_gpu_moments(torch, sim, wl.nc, bins))
-    runs["fp64_ulp"] = rows
-    sim.close()
-    sub = []
-    for i, c in enumerate(checks):
-        g = gold["moments"][i + 1]
-        sub.append({"step": c,
-                    "fp64_vs_oracle": _rel_diff(runs["fp64"][i], g),
-                    "fp32_vs_oracle": _rel_diff(runs["fp32"][i], g),
-                    "fp32_vs_fp64": _rel_diff(runs["fp32"][i], runs["fp64"][i]),
-                    "fp64_ulp_vs_fp64": _rel_diff(runs["fp64_ulp"][i], runs["fp64"][i])})
-    out["subsample_10k_cells"] = {"particles": n_drawn, "checkpoints": sub}
-    # ---- the 1,000,000-cell instance: FP32 form against FP64 form on the GPU
+    out["subsample_vs_oracle"] = [
+        {"step": c, "fp64_vs_oracle": _rel_diff(runs["fp64"][i], gold["moments"][i + 1]),
+         "fp32_vs_oracle": _rel_diff(runs["fp32"][i], gold["moments"][i + 1])}
+        for i, c in enumerate(checks)]
+    # ---- the precision configuration: 1,000,000 cells, 4e8 particles
     wl = pin.bounded_mcc(nc=args.precision_cells, ppc=200, seed=5)
     n = wl.n_particles
     caps = [int(0.75 * n) + 1024] * 2  # ionisation grows the plasma by about 25% in 2,000 steps
-    big = {}
-    for name, prec in (("fp64", P.PIC_FP64), ("fp32", P.PIC_FP32)):
-        log(f"precision: {wl.nc}-cell instance ({n} particles), {name} form, {args.precision_steps} steps")
-        sim = P.PicSim(wl, None, prec, capacities=caps, flags=P.PIC_INIT_DEVICE | P.PIC_INIT_SORT)
-        rows, last = [], 0
-        t0 = time.perf_counter()
-        for c in range(500, args.precision_steps + 1, 500):
-            sim.step_graph(c - last, SORT_EVERY)
-            last = c
-            rows.append(_gpu_moments(torch, sim, wl.nc, bins))
-            log(f"precision: {name} step {c} ({time.perf_counter() - t0:.1f} s)")
-        big[name] = rows
-        sim.close()
-        torch.cuda.empty_cache()
-    out["large"] = {"cells": wl.nc, "particles": n, "steps": args.precision_steps,
-                    "checkpoints": [{"step": a["step"], "fp32_vs_fp64": _rel_diff(a, b)}
-                                    for a, b in zip(big["fp32"], big["fp64"])]}
+    out["large"] = {"cells": wl.nc, "particles": n}
+    out["large"].update(precision_protocol(torch, wl, caps, args.precision_steps, args.precision_K,
+                                           P.PIC_INIT_DEVICE | P.PIC_INIT_SORT,
+                                           f" ({wl.nc} cells)"))
     return out
 
 
@@ -469,18 +550,122 @@ def layout_study(torch, args):
     return out
 
 
+def small_configs(torch, args):
+    """The two small configurations, both drawn on the device and replayed
+    from a HIP graph: the periodic Langmuir plasma (512 cells, 51,200
+    electrons, FP64, its 200 steps, no sort) and the bounded magnetised plasma
+    (8,192 cells, 200 particles per cell per species, FP32, B at 45 degrees,
+    pair source, no collisions, sort every 20 steps, 200 steps after 20).
+    Their state fits in the 256 MB last-level cache, so they measure launch
+    and latency, not HBM."""
+    import pic_inputs as pin
+    from paper_2404_10270_amd import pic as P
+    out = {}
+    wl = pin.langmuir()
+    sim = P.PicSim(wl, None, P.PIC_FP64, flags=P.PIC_INIT_DEVICE)
+    d0, _ = sim.diagnostics()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(sim.stream)
+    sim.step_graph(wl.n_steps, 0)
+    e1.record(sim.stream)
+    d1, rc = sim.diagnostics()
+    if rc != 0:
+        raise RuntimeError(f"device status {d1[0].status:#x} in the Langmuir run")
+    ms = e0.elapsed_time(e1)
+    ps = int(d1[0].particle_steps - d0[0].particle_steps)
+    sim.close()
+    out["langmuir_512_cells_fp64"] = {"value": ps / (ms * 1e-3), "unit": "particle-steps/s",
+                                      "particles": wl.n_particles, "steps": wl.n_steps,
+                                      "ms_per_step": round(ms / wl.n_steps, 4)}
+    log(f"langmuir: {ps / (ms * 1e-3):.4e} p-steps/s, {ms / wl.n_steps:.4f} ms/step")
+    wl = pin.bounded()
+    sim = P.PicSim(wl, None, P.PIC_FP32, flags=P.PIC_INIT_DEVICE | P.PIC_INIT_SORT)
+    rate, ms_step, _ = run_form(torch, sim, 200, 20, graph=True)
+    win = time_windows(torch, sim)
+    sim.close()
+    out["bounded_8192_cells_fp32"] = {"value": rate, "unit": "particle-steps/s",
+                                      "particles": wl.n_particles, "steps": 200,
+                                      "ms_per_step": round(ms_step, 4), "windows": win}
+    log(f"bounded 8192 cells: {rate:.4e} p-steps/s, {ms_step:.4f} ms/step")
+    return out
+
+
+def large_run(torch, args):
+    """The largest single-GPU configuration: the collisional bounded plasma on
+    1,000,000 cells with 200 particles per cell per species (4e8 particles),
+    drawn on the device and sorted, sort every 20 steps, as the FP32/fixed-point
+    form and as the FP64 form: whole steps from the HIP graph, five one-period
+    windows, and the mover's algorithmic bandwidth from HIP events."""
+    import pic_inputs as pin
+    from paper_2404_10270_amd import pic as P
+    wl = pin.bounded_mcc(nc=args.large_cells, ppc=200, seed=5, sort_every=SORT_EVERY)
+    n = wl.n_particles
+    caps = [int(0.55 * n) + 1024] * 2
+    out = {"cells": wl.nc, "particles": n, "steps": args.large_steps, "sort_every": SORT_EVERY}
+    for name, prec, bpp in (("fp32", P.PIC_FP32, PUSH_BYTES_FP32), ("fp64", P.PIC_FP64, PUSH_BYTES_FP64)):
+        log(f"large: {wl.nc} cells, {n} particles, {name} form")
+        sim = P.PicSim(wl, None, prec, capacities=caps, flags=P.PIC_INIT_DEVICE | P.PIC_INIT_SORT)
+        rate, ms_step, _ = run_form(torch, sim, args.large_steps, args.warmup, graph=True)
+        win = time_windows(torch, sim)
+        push_ms, per_launch = time_push(torch, sim, 10)
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+        gbs = bpp * per_launch / (push_ms * 1e-3) / 1e9
+        out[name] = {"value": rate, "ms_per_step": round(ms_step, 4), "windows": win,
+                     "mover_us": round(push_ms * 1e3, 1), "mover_GBps": round(gbs, 1),
+                     "mover_frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_particle": bpp}
+        log(f"large {name}: {rate:.4e} p-steps/s, {ms_step:.4f} ms/step, mover {push_ms * 1e3:.1f} us "
+            f"({gbs:.0f} GB/s)")
+    out["fp32_over_fp64"] = round(out["fp32"]["value"] / out["fp64"]["value"], 3)
+    return out
+
+
+def host_info():
+    """CPU model, logical CPUs, the CPUs this process may run on, and the
+    threads the CPU baseline uses (OMP_NUM_THREADS when set, else all)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    omp = os.environ.get("OMP_NUM_THREADS", "")
+    threads = min(int(omp), avail) if omp.isdigit() and int(omp) > 0 else avail
+    return {"cpu_model": model, "nproc": os.cpu_count(), "cpus_available": avail,
+            "threads": threads}
+
+
 def cpu_baseline(args):
-    """The oracle as it stands, single thread, on a bounded sample of the workload."""
+    """The oracle as it stands on the host's cores: `cpu_steps` whole steps of
+    the bench workload from its seeded start, on every available thread (the
+    oracle's independent per-particle loops in parallel, results bit-identical
+    to one thread) and on one thread."""
     import oracle
     import pic_inputs as pin
+    host = host_info()
     wl = workload(args)
     st = pin.initial_state(wl)
     st32 = pin.to_fp32_form(st, wl.nc)
     st_o = [s.as_f64() for s in st32]
-    ps, dt = oracle.time_steps(wl, st_o, args.cpu_steps, caps=pin.capacities(wl, st_o))
-    return {"value": ps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{wl.nc} cells, {sum(s.n for s in st_o)} particles, {args.cpu_steps} whole "
-                      f"steps from the seeded start ({dt:.1f} s)"}
+    del st, st32
+    caps = pin.capacities(wl, st_o)
+    n = sum(s.n for s in st_o)
+    ps, dt = oracle.time_steps(wl, st_o, args.cpu_steps, caps=caps, n_threads=host["threads"])
+    ps1, dt1 = oracle.time_steps(wl, st_o, args.cpu_steps, caps=caps, n_threads=1)
+    return {"value": ps / dt, "unit": "particle-steps/s", "cores": host["threads"], "kind": "oracle",
+            "sample": f"{wl.nc} cells, {n} particles, {args.cpu_steps} whole steps from the seeded "
+                      f"start: {dt:.1f} s on {host['threads']} threads, {dt1:.1f} s on one",
+            "single_thread": {"value": ps1 / dt1, "seconds": round(dt1, 2)},
+            "host": host}
 
 
 def main():
@@ -498,6 +683,10 @@ def main():
     ap.add_argument("--batched-instances", type=int, default=256)
     ap.add_argument("--batched-steps", type=int, default=60)
     ap.add_argument("--no-table1", action="store_true")
+    ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--large-cells", type=int, default=1_000_000)
+    ap.add_argument("--large-steps", type=int, default=20)
+    ap.add_argument("--no-small", action="store_true")
     ap.add_argument("--table1-steps", type=int, default=200)
     ap.add_argument("--layout-study", action="store_true",
                     help="run only the particle-layout study of the mover and print its JSON object")
@@ -506,6 +695,10 @@ def main():
                     help="FP32 form against FP64 form and the oracle (1e6- and 1e4-cell instances); prints its own JSON")
     ap.add_argument("--precision-cells", type=int, default=1_000_000)
     ap.add_argument("--precision-steps", type=int, default=2000)
+    ap.add_argument("--precision-K", type=int, default=8,
+                    help="perturbed FP64 runs in the ensemble of the large instance")
+    ap.add_argument("--precision-skip-small", action="store_true",
+                    help="skip the 10^4-step protocol on the 10,000-cell instance (the GPU test runs it)")
     ap.add_argument("--only-batched", action="store_true",
                     help="run only the batched workload and print its JSON object (profiling)")
     ap.add_argument("--only-table1", action="store_true",
@@ -557,6 +750,8 @@ def main():
     log(f"FP32 form: {args.warmup} warm-up + {args.steps} timed steps")
     rate, ms_step, ps = run_form(torch, sim, args.steps, args.warmup, graph=not args.eager)
     log(f"FP32 form: {rate:.4e} p-steps/s, {ms_step:.4f} ms/step")
+    win = time_windows(torch, sim)
+    log(f"FP32 form: windows median {win['median']:.4e} ({win['min']:.4e} .. {win['max']:.4e})")
     push_ms, per_launch = time_push(torch, sim, args.push_steps)
     log(f"FP32 mover: {push_ms * 1e3:.1f} us/launch, {per_launch:.0f} particles/launch")
     sim.close()
@@ -578,10 +773,13 @@ def main():
         log("FP64 form: init")
         sim64 = make_sim(wl, st, P.PIC_FP64)
         r64, ms64, _ = run_form(torch, sim64, args.steps, args.warmup, graph=not args.eager)
+        win64 = time_windows(torch, sim64)
         p64_ms, per64 = time_push(torch, sim64, args.push_steps)
         log(f"FP64 form: {r64:.4e} p-steps/s, mover {p64_ms * 1e3:.1f} us")
-        fp64 = {"value": r64, "ms_per_step": round(ms64, 4),
-                "mover_GBps": round(PUSH_BYTES_FP64 * per64 / (p64_ms * 1e-3) / 1e9, 1),
+        g64 = PUSH_BYTES_FP64 * per64 / (p64_ms * 1e-3) / 1e9
+        fp64 = {"value": r64, "ms_per_step": round(ms64, 4), "windows": win64,
+                "mover_us": round(p64_ms * 1e3, 2), "mover_GBps": round(g64, 1),
+                "mover_frac": round(g64 / HBM_PEAK_GBS, 4),
                 "fp32_over_fp64": round(rate / r64, 3)}
         sim64.close()
         del sim64
@@ -595,6 +793,16 @@ def main():
     t1 = None
     if not args.no_table1:
         t1 = table1_run(torch, args)
+        torch.cuda.empty_cache()
+
+    small = None
+    if not args.no_small:
+        small = small_configs(torch, args)
+        torch.cuda.empty_cache()
+
+    large = None
+    if not args.no_large:
+        large = large_run(torch, args)
         torch.cuda.empty_cache()
 
     cpu = None
@@ -621,8 +829,11 @@ def main():
                    "cells": wl.nc, "particles": wl.n_particles, "sort_every": SORT_EVERY,
                    "deposit": "int64 fixed point (F=32)", "field_solve": "f64 Thomas",
                    "launch": "eager" if args.eager else "hip graph (pic_step_graph)"},
+        "windows": win,
         "roofline": roof,
         "fp64_form": fp64,
+        "large_1e6_cells": large,
+        "small_configs": small,
         "batched_256": bat,
         "table1": t1,
         "cpu_baseline": cpu,

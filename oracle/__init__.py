@@ -40,7 +40,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fno-fast-math",
-               "-fPIC", "-shared", "-Wall", "-o", tmp, SRC, "-lm"]
+               "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", tmp, SRC, "-lm"]
         subprocess.check_call(cmd)
         os.replace(tmp, LIB)
     return LIB
@@ -143,8 +143,24 @@ def lib():
             f.restype = C.c_int
             if f() != C.sizeof(T):
                 raise RuntimeError(f"oracle struct layout mismatch for {T.__name__}")
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_set_threads.restype = None
+        L.orc_get_threads.argtypes = []
+        L.orc_get_threads.restype = C.c_int
+        L.orc_set_threads(1)  # one thread unless set_threads asks for more
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> int:
+    """Threads for the oracle's independent per-particle loops (results are
+    bit-identical for any count); returns the count in effect."""
+    lib().orc_set_threads(int(n))
+    return int(lib().orc_get_threads())
+
+
+def threads() -> int:
+    return int(lib().orc_get_threads())
 
 
 def _dp(a):
@@ -401,13 +417,18 @@ class OracleSim:
         return o
 
 
-def time_steps(wl: pin.Workload, state, n_steps: int, caps=None):
-    """Wall-clock the oracle as it stands (single thread) for n_steps.
+def time_steps(wl: pin.Workload, state, n_steps: int, caps=None, n_threads: int = 1):
+    """Wall-clock the oracle as it stands for n_steps on n_threads threads.
 
     Returns (particle_steps, seconds)."""
-    o = OracleSim(wl, state, caps=caps)
-    ps0 = int(o.sim.cnt.particle_steps)
-    t0 = time.perf_counter()
-    o.step(n_steps)
-    dt = time.perf_counter() - t0
+    prev = threads()
+    set_threads(n_threads)
+    try:
+        o = OracleSim(wl, state, caps=caps)
+        ps0 = int(o.sim.cnt.particle_steps)
+        t0 = time.perf_counter()
+        o.step(n_steps)
+        dt = time.perf_counter() - t0
+    finally:
+        set_threads(prev)
     return int(o.sim.cnt.particle_steps) - ps0, dt

@@ -29,11 +29,22 @@
  * inputs (SI or plasma units) are converted here, independently of the GPU
  * library.  Everything is FP64; build with -ffp-contract=off so that no
  * multiply-add is fused unless fma() is written out.
+ *
+ * Threads (OpenMP, orc_set_threads; one by default): only loops whose
+ * iterations are independent run in parallel -- the push of each particle,
+ * the periodic wrap, the collision-candidate draw of each particle, and the
+ * deposit into per-thread integer arrays that are then added (integer sums
+ * do not depend on order).  Collisions, walls, source, field and the
+ * floating-point sums of the diagnostics stay serial in particle order, so
+ * every result is bit-identical for any thread count.
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_MAXSP 4
 #define ORC_FRAC_BITS 32            /* fixed-point fraction bits of the deposit */
@@ -191,10 +202,49 @@ static void deposit_add(double x, uint64_t *S)
     S[j + 1] += w1;
 }
 
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}
+
+int orc_get_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 void orc_deposit_species(int64_t n, const double *x, int32_t nc, uint64_t *S)
 {
-    memset(S, 0, sizeof(uint64_t) * (size_t)(nc + 1));
-    for (int64_t p = 0; p < n; ++p) deposit_add(x[p], S);
+    const size_t G = (size_t)nc + 1;
+    memset(S, 0, sizeof(uint64_t) * G);
+    int nt = orc_get_threads();
+    /* each thread deposits its share into an array of its own; the integer
+     * arrays are then added, which gives the same S in any order */
+    uint64_t *T = nt > 1 ? (uint64_t *)calloc((size_t)nt * G, sizeof(uint64_t)) : NULL;
+    if (!T) {
+        for (int64_t p = 0; p < n; ++p) deposit_add(x[p], S);
+        return;
+    }
+#pragma omp parallel num_threads(nt)
+    {
+#ifdef _OPENMP
+        uint64_t *Tt = T + (size_t)omp_get_thread_num() * G;
+#else
+        uint64_t *Tt = T;
+#endif
+#pragma omp for schedule(static)
+        for (int64_t p = 0; p < n; ++p) deposit_add(x[p], Tt);
+    }
+    for (int t = 0; t < nt; ++t)
+        for (size_t j = 0; j < G; ++j) S[j] += T[(size_t)t * G + j];
+    free(T);
 }
 
 /* the same linear weights in plain FP64 (used to bound the fixed-point error) */
@@ -450,6 +500,7 @@ void orc_push_species(const orc_config *c, int k, const double *acc, int64_t n, 
     const double tx = t[0], ty = t[1], sx = sv[0], sy = sv[1];
     const double ms = (double)sub_of(c, k);
     const double hk = 0.5 * ms;
+#pragma omp parallel for schedule(static)
     for (int64_t p = 0; p < n; ++p) {
         double jd = floor(x[p]);
         double f = x[p] - jd;
@@ -479,8 +530,11 @@ void orc_push(orc_sim *s)
         orc_particles *P = &s->sp[k];
         orc_push_species(&s->cfg, k, s->acc[k], P->n, P->x, P->vx, P->vy, P->vz);
         const double ms = (double)sub_of(&s->cfg, k);
+        int cfl = 0;
+#pragma omp parallel for schedule(static) reduction(| : cfl)
         for (int64_t p = 0; p < P->n; ++p)
-            if (fabs(ms * P->vx[p]) >= 1.0) s->cnt.status |= ORC_ST_CFL;
+            if (fabs(ms * P->vx[p]) >= 1.0) cfl = 1;
+        if (cfl) s->cnt.status |= ORC_ST_CFL;
         s->cnt.particle_steps += P->n;
     }
 }
@@ -498,6 +552,7 @@ void orc_walls(orc_sim *s)
         orc_particles *P = &s->sp[k];
         s->cnt.absorbed[k][0] = s->cnt.absorbed[k][1] = 0;
         if (c->bc == ORC_BC_PERIODIC) {
+#pragma omp parallel for schedule(static)
             for (int64_t p = 0; p < P->n; ++p) {
                 double x = P->x[p];
                 if (x < 0.0) x += L;
@@ -729,10 +784,20 @@ int orc_mcc(orc_sim *s)
         /* neutral thermal speed (cells/step) for Maxwellian products */
         const double sig_n = sqrt(c->T_n / M) * (dt / dx);
         const double am = c->m[k] / (c->m[k] + M), bm = M / (c->m[k] + M);
+        /* the candidate test of each particle depends on its own draw only:
+         * it runs in parallel; the candidates then collide in particle order */
+        uint8_t *cand = P->n > 0 ? (uint8_t *)malloc((size_t)P->n) : NULL;
+        if (P->n > 0 && !cand) { free(ev); return -1; }
+#pragma omp parallel for schedule(static)
         for (int64_t p = 0; p < P->n; ++p) {
             uint32_t u[4];
             draw_block(c, P->id[p], step, 0, u);
-            if ((uint64_t)u[0] >= T) continue;
+            cand[p] = (uint64_t)u[0] < T;
+        }
+        for (int64_t p = 0; p < P->n; ++p) {
+            if (!cand[p]) continue;
+            uint32_t u[4];
+            draw_block(c, P->id[p], step, 0, u);
             s->cnt.n_candidates++;
             const double vx = P->vx[p], vy = P->vy[p], vz = P->vz[p];
             const double v2 = (vx * vx + vy * vy) + vz * vz;
@@ -839,6 +904,7 @@ int orc_mcc(orc_sim *s)
                 }
             }
         }
+        free(cand);
     }
 
     /* ids of created particles: events ordered by parent id; event r gives

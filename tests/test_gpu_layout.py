@@ -125,3 +125,53 @@ def test_layouts_agree_over_five_passes():
     # natural sorting hands the particles back grouped by cell
     cells = res["cellpad"][3]["cell"].cpu().numpy()
     assert np.all(np.diff(cells) >= 0)
+
+
+def test_one_pass_of_every_layout_against_the_oracle():
+    """One pass of each layout against the oracle's FP64 push of the same
+    particles on the same grid acceleration (Sec. 6 moveb statements with the
+    Boris rotation): positions within 1e-5 cells and velocities within
+    1e-5 max(|v|, v_th) (FP32 tolerance); the pass's fixed-point deposit of its
+    new positions bit-exact against the oracle's deposit of those positions;
+    the candidate count equal to the oracle Philox draws of the same ids."""
+    import torch
+
+    import oracle
+    from paper_2404_10270_amd import layout as Lb
+    wl, st, acc64, soa = _setup(nc=400, ppc=100, seed=53)
+    flush("layout study: one pass of each layout vs the oracle")
+    ost = [s.as_f64() for s in st]
+    orc = oracle.OracleSim(wl, ost, caps=[ost[0].n + 1])
+    orc.acc[0][:] = acc64
+    orc.push()
+    orc.walls()
+    o = orc.state(0)
+    order = np.argsort(o.id, kind="stable")
+    o_id, o_x = o.id[order], o.x[order]
+    o_v = {f: getattr(o, f)[order] for f in ("vx", "vy", "vz")}
+    vth = wl.vth_hat(wl.species[0])
+    T = int(0.05 * 2 ** 32)
+    key0, key1 = 0x1234, 0x5678
+    n_cand = sum(int(oracle.philox4x32_10([int(i) & 0xFFFFFFFF, int(i) >> 32, 0, 0], [key0, key1])[0]) < T
+                 for i in ost[0].id)
+    acc32 = torch.from_numpy(acc64.astype(np.float32)).cuda()
+    slack = _slack(wl, st)
+    for name, lay in Lb.LAYOUTS.items():
+        S = torch.zeros(wl.nc + 1, dtype=torch.int64, device="cuda")
+        r = Lb.LayoutRun(lay, {k: v.clone() for k, v in soa.items()}, wl.nc, slack)
+        p = _params(wl, acc32, S, T=T)
+        p.slack = slack
+        r.step(p, step=0)
+        out, c = r.store()
+        g = _np(out)
+        assert np.array_equal(g["id"].view(np.uint64), o_id), name
+        xg = g["cell"].astype(np.float64) + g["f"].astype(np.float64)
+        dxw = np.abs(xg - o_x)
+        dxw = np.minimum(dxw, wl.nc - dxw)  # positions on a ring
+        assert np.max(dxw) <= 1e-5, f"{name}: positions {np.max(dxw)}"
+        for f in ("vx", "vy", "vz"):
+            err = np.abs(g[f].astype(np.float64) - o_v[f]) / np.maximum(np.abs(o_v[f]), vth)
+            assert np.max(err) <= 1e-5, f"{name}: {f} {np.max(err)}"
+        S_ref = oracle.deposit_fixed(xg, wl.nc)
+        assert np.array_equal(S.cpu().numpy().view(np.uint64), S_ref), f"{name}: deposit"
+        assert c == n_cand, f"{name}: candidates {c} vs {n_cand}"
