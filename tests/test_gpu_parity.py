@@ -551,3 +551,75 @@ def test_more_segments_than_the_lds_tables_fp64():
                 assert np.max(np.abs(g["x"] - o["x"]), initial=0.0) <= 1e-7
     assert tot > 1000
     sim.close()
+
+
+def test_bounded_8192_cells_full_shape():
+    """The bounded magnetised plasma at its full shape (8,192 cells, 200
+    particles per cell per species, 3.3e6 particles, B at 45 degrees with
+    omega_ce dt = 0.2, pair source, sort every 20 steps).  FP64 form: 25 whole
+    steps (one sort) against the oracle, every particle by id.  FP32 form: the
+    deposit of the whole uploaded state bit-exact, then one push compared with
+    the oracle's push on a sample of 20,000 particles per species."""
+    wl = pin.bounded()
+    assert wl.nc == 8192 and wl.source and wl.mcc is None
+    flush("bounded 8192 cells: FP64, 25 steps")
+    sim, orc, ost = build_pair(wl, FP64)
+    sim.step(25, sort_every=20)
+    orc.step(25)
+    d, rc = sim.diagnostics()
+    d = d[0]
+    od = orc.diagnostics()
+    c = orc.counters
+    assert rc == 0 and d.status == 0 and d.step == 25
+    assert d.n_source == c.n_source and d.next_id == c.next_id and c.n_source > 0
+    for k in range(2):
+        assert d.n_live[k] == od.n[k]
+        assert list(d.absorbed_total[k]) == list(c.absorbed_total[k])
+        g, o = gpu_state(sim, k), oracle_state(orc, k)
+        assert np.array_equal(g["id"], o["id"])
+        assert np.max(np.abs(g["x"] - o["x"])) <= 1e-7
+        assert abs(d.ke[k] / od.ke[k] - 1) <= 1e-9
+    _check_momentum(d, od, wl, 1e-9)
+    sim.close()
+
+    flush("bounded 8192 cells: FP32 deposit and one sampled push")
+    st = pin.initial_state(wl)
+    st32 = pin.to_fp32_form(st, wl.nc)
+    ost = [s.as_f64() for s in st32]
+    caps = pin.capacities(wl, st)
+    sim = P.PicSim(wl, st32, FP32, capacities=caps, flags=P.PIC_INIT_NO_FIELD)
+    sim.deposit()
+    S = sim.grid(P.PIC_R_DEPOSIT)
+    for k in range(2):
+        assert np.array_equal(S[k], oracle.deposit_fixed(ost[k].x, wl.nc))
+    sim.close()
+    sim = P.PicSim(wl, st32, FP32, capacities=caps)
+    sim.push(P.PIC_PUSH_NO_DEPOSIT)
+    full = oracle.OracleSim(wl, ost, caps=caps)
+    full.deposit()
+    full.field()
+    rng = np.random.default_rng(2)
+    empty = pin.SpeciesState(x=np.zeros(0), vx=np.zeros(0), vy=np.zeros(0), vz=np.zeros(0),
+                             id=np.zeros(0, np.uint64))
+    for k, s in enumerate(wl.species):
+        pick = np.sort(rng.choice(ost[k].n, 20000, replace=False))
+        sub = pin.SpeciesState(x=ost[k].x[pick], vx=ost[k].vx[pick], vy=ost[k].vy[pick],
+                               vz=ost[k].vz[pick], id=ost[k].id[pick])
+        o = oracle.OracleSim(wl, [sub if q == k else empty for q in range(2)], caps=[pick.size + 1] * 2)
+        for q in range(2):
+            o.acc[q][:] = full.acc[q]
+        o.push()
+        o.walls()
+        os_ = oracle_state(o, k)
+        g = gpu_state(sim, k)
+        gi = np.searchsorted(g["id"], os_["id"])
+        ok = gi < g["id"].size
+        gi = np.minimum(gi, g["id"].size - 1)
+        ok &= g["id"][gi] == os_["id"]
+        assert ok.mean() > 0.999
+        vth = wl.vth_hat(s)
+        assert np.max(np.abs(g["x"][gi[ok]] - os_["x"][ok])) <= 1e-5
+        for f in ("vx", "vy", "vz"):
+            err = np.abs(g[f][gi[ok]] - os_[f][ok]) / np.maximum(np.abs(os_[f][ok]), vth)
+            assert np.max(err) <= 1e-5
+    sim.close()
