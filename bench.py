@@ -75,6 +75,26 @@ def make_sim(wl, st64, precision):
     return P.PicSim(wl, state, precision, capacities=caps, flags=P.PIC_INIT_SORT)
 
 
+def mover_shapes(sim):
+    """Candidate launch shapes of the mover: 4 chunks per wave in one pass or 2
+    in two passes, on the default grid or on the largest one."""
+    nmax = int(sim.sizes.mover_blocks_max)
+    shapes = [(4, 0), (2, 0)]
+    if nmax > int(sim.sizes.mover_blocks):
+        shapes += [(4, nmax), (2, nmax)]
+    return shapes
+
+
+def tune_mover(sim, trial_steps=40):
+    """Autotune the mover's launch shape at the workload's sort cadence (these
+    trial steps are untimed, like warm-up steps)."""
+    movers = mover_shapes(sim)
+    best, _, rates, _ = sim.autotune(movers, (SORT_EVERY,), trial_steps)
+    return {"chunks": best[0], "blocks": best[1] or int(sim.sizes.mover_blocks),
+            "trials": {f"{m[0]}x{m[1] or int(sim.sizes.mover_blocks)}": round(r, 1)
+                       for m, r in zip(movers, rates)}}
+
+
 def run_form(torch, sim, steps, warmup, graph=False):
     """Time `steps` whole steps after `warmup`; returns (p-steps/s, ms/step, p-steps).
     With `graph` the steps are replayed from a captured HIP graph (pic_step_graph)."""
@@ -244,8 +264,10 @@ def batched(torch, args):
     log(f"batched: {len(wls)} instances, {n} particles, drawn on the device")
     sim = P.PicSim(wls, [None] * len(wls), P.PIC_FP32, flags=P.PIC_INIT_DEVICE | P.PIC_INIT_SORT)
     cands = (5, 10, 20, 40, 80)
-    best, rates = sim.autotune_sort(cands, 80)
-    log(f"batched: autotuned sort cadence {best} ({', '.join(f'{c}: {r:.3e}' for c, r in zip(cands, rates))})")
+    movers = mover_shapes(sim)
+    mover, best, mrates, rates = sim.autotune(movers, cands, 80)
+    log(f"batched: autotuned mover {mover} ({', '.join(f'{m}: {r:.3e}' for m, r in zip(movers, mrates))}), "
+        f"sort cadence {best} ({', '.join(f'{c}: {r:.3e}' for c, r in zip(cands, rates))})")
     d0, _ = sim.diagnostics()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -260,7 +282,10 @@ def batched(torch, args):
     out = {"value": ps / dt, "unit": "particle-steps/s", "instances": len(wls), "particles": n,
            "cells": sum(w.nc for w in wls), "steps": args.batched_steps,
            "ms_per_step": round(1e3 * dt / args.batched_steps, 4), "sort_every": best,
-           "autotune": {str(c): round(r, 1) for c, r in zip(cands, rates)}}
+           "mover": {"chunks": mover[0], "blocks": mover[1] or int(sim.sizes.mover_blocks)},
+           "autotune": {"mover": {f"{m[0]}x{m[1] or int(sim.sizes.mover_blocks)}": round(r, 1)
+                                  for m, r in zip(movers, mrates)},
+                        "sort_every": {str(c): round(r, 1) for c, r in zip(cands, rates)}}}
     log(f"batched: {out['value']:.4e} p-steps/s, {out['ms_per_step']} ms/step")
     return out
 
@@ -606,6 +631,8 @@ def large_run(torch, args):
     for name, prec, bpp in (("fp32", P.PIC_FP32, PUSH_BYTES_FP32), ("fp64", P.PIC_FP64, PUSH_BYTES_FP64)):
         log(f"large: {wl.nc} cells, {n} particles, {name} form")
         sim = P.PicSim(wl, None, prec, capacities=caps, flags=P.PIC_INIT_DEVICE | P.PIC_INIT_SORT)
+        mv = tune_mover(sim)
+        log(f"large {name}: autotuned mover {mv}")
         rate, ms_step, _ = run_form(torch, sim, args.large_steps, args.warmup, graph=True)
         win = time_windows(torch, sim)
         push_ms, per_launch = time_push(torch, sim, 10)
@@ -613,7 +640,7 @@ def large_run(torch, args):
         del sim
         torch.cuda.empty_cache()
         gbs = bpp * per_launch / (push_ms * 1e-3) / 1e9
-        out[name] = {"value": rate, "ms_per_step": round(ms_step, 4), "windows": win,
+        out[name] = {"value": rate, "ms_per_step": round(ms_step, 4), "windows": win, "mover": mv,
                      "mover_us": round(push_ms * 1e3, 1), "mover_GBps": round(gbs, 1),
                      "mover_frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_particle": bpp}
         log(f"large {name}: {rate:.4e} p-steps/s, {ms_step:.4f} ms/step, mover {push_ms * 1e3:.1f} us "
@@ -747,6 +774,8 @@ def main():
 
     log("FP32 form: init")
     sim = make_sim(wl, st, P.PIC_FP32)
+    mover32 = tune_mover(sim)
+    log(f"FP32 form: autotuned mover {mover32}")
     log(f"FP32 form: {args.warmup} warm-up + {args.steps} timed steps")
     rate, ms_step, ps = run_form(torch, sim, args.steps, args.warmup, graph=not args.eager)
     log(f"FP32 form: {rate:.4e} p-steps/s, {ms_step:.4f} ms/step")
@@ -763,7 +792,8 @@ def main():
     log(f"plain copy: {copy_gbs:.0f} GB/s (mover at {achieved / copy_gbs:.2f} of it)")
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile(),
-            "kernel": "push_f32_kernel<true,true> (mover + deposit + candidate list)",
+            "kernel": f"push_f32_kernel<true,true,{mover32['chunks']}> (mover + deposit + candidate list)",
+            "mover": mover32,
             "bytes_per_particle": PUSH_BYTES_FP32,
             "particles_per_launch": int(per_launch), "us_per_launch": round(push_ms * 1e3, 2),
             "copy_GBps": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
@@ -772,6 +802,8 @@ def main():
     if not args.no_fp64:
         log("FP64 form: init")
         sim64 = make_sim(wl, st, P.PIC_FP64)
+        mover64 = tune_mover(sim64)
+        log(f"FP64 form: autotuned mover {mover64}")
         r64, ms64, _ = run_form(torch, sim64, args.steps, args.warmup, graph=not args.eager)
         win64 = time_windows(torch, sim64)
         p64_ms, per64 = time_push(torch, sim64, args.push_steps)
@@ -779,7 +811,7 @@ def main():
         g64 = PUSH_BYTES_FP64 * per64 / (p64_ms * 1e-3) / 1e9
         fp64 = {"value": r64, "ms_per_step": round(ms64, 4), "windows": win64,
                 "mover_us": round(p64_ms * 1e3, 2), "mover_GBps": round(g64, 1),
-                "mover_frac": round(g64 / HBM_PEAK_GBS, 4),
+                "mover_frac": round(g64 / HBM_PEAK_GBS, 4), "mover": mover64,
                 "fp32_over_fp64": round(rate / r64, 3)}
         sim64.close()
         del sim64

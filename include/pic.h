@@ -22,8 +22,8 @@
  *
  * Streams.  pic_init synchronises its stream once, after uploading the
  * tables (the initial draw, sort, deposit and field solve it enqueues after
- * that are not waited for); pic_diagnostics and pic_autotune_sort
- * synchronise too.  Every other phase call enqueues
+ * that are not waited for); pic_diagnostics, pic_autotune_sort and
+ * pic_autotune synchronise too.  Every other phase call enqueues
  * work on the HIP stream given to pic_init and returns without
  * synchronising; pic_query_sizes, pic_region, pic_destroy and pic_strerror
  * do no device work.  A context is not thread-safe; use one context per
@@ -148,6 +148,8 @@ typedef struct {
     uint64_t work_bytes; /* size of the device workspace */
     int64_t x_elem_bytes;/* 4 (PIC_FP32: float offset) or 8 (PIC_FP64: double position) */
     int64_t v_elem_bytes;/* 4 or 8 */
+    int64_t mover_blocks;     /* default persistent grid of the movers (one residency on 256 CUs) */
+    int64_t mover_blocks_max; /* the largest grid pic_set_mover accepts */
 } pic_sizes;
 
 /*
@@ -378,6 +380,32 @@ int pic_autotune_sort(pic_ctx *ctx, const int *cand, int n_cand, int trial_steps
 #define PIC_STATIC_WORK_MAX (64ull << 20)
 int pic_init_static(const pic_config *cfgs, int n_inst, const pic_buffers *bufs, void *stream,
                     unsigned flags, pic_ctx **out);
+
+/*
+ * pic_set_mover -- the launch shape of the mover (Sec. 6 moveb loop; Sec.
+ * 3.1-3.2 tune the matching OpenMP/OpenACC grain and team counts by hand):
+ * chunks = 64-particle chunks a wave loads per pass over its part of a
+ * 1024-particle tile (4: one pass; 2: two passes, fewer registers, more
+ * waves per SIMD), blocks = persistent grid (0: pic_sizes.mover_blocks; at
+ * most pic_sizes.mover_blocks_max).  Results are the same for every shape.
+ * Host only; takes effect from the next step (call it between whole steps)
+ * and drops the graph pic_step_graph captured.  PIC_E_ARG for other values.
+ */
+int pic_set_mover(pic_ctx *ctx, int chunks, int blocks);
+
+/*
+ * pic_autotune -- choose the mover's launch shape and the sort cadence by
+ * measurement.  Each of the n_movers shapes (chunks[i], blocks[i]) runs
+ * trial_steps whole steps at cadences[0] after a fresh sort; the fastest
+ * (particle-steps per second, HIP events) is kept (*best_mover = its index)
+ * and each of the n_cad cadences is then timed with it (*best_cadence = the
+ * fastest value).  rates (may be NULL) receives n_movers + n_cad rates.  The
+ * context is left on the best shape; the trials advance the simulation like
+ * warm-up steps.  Synchronises the stream.
+ */
+int pic_autotune(pic_ctx *ctx, const int *chunks, const int *blocks, int n_movers,
+                 const int *cadences, int n_cad, int trial_steps, int *best_mover,
+                 int *best_cadence, double *rates);
 
 /* pic_region -- byte offset (into pic_buffers.work) and element count of a
  * workspace region; host only. */

@@ -27,6 +27,8 @@ struct pic_ctx {
     bool host_diag_pinned = false;
     std::vector<pic_diag> diag_stage;  // ... or held here (pic_init_static)
     int static_dev = -1;            // device whose static workspace this context holds
+    int chunks = kPer;              // mover chunks per wave and pass (pic_set_mover)
+    int default_blocks = 1;         // the layout's default mover grid
     // pic_step_graph: one sort period captured on a stream of its own
     hipStream_t cap_st = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -242,7 +244,7 @@ double candidate_probability(const pic_config &c, int k)
 
 struct Plan {
     int64_t n_slots = 0, n_tiles = 0, G = 0, n_field_tiles = 0, n_sort_tiles = 0;
-    int n_push_blocks = 1;
+    int n_push_blocks = 1, n_regions = 1;
     std::vector<int64_t> seg_base, seg_tile0, node_base, inst_ftile0;
     Layout L{};
 };
@@ -316,8 +318,11 @@ int plan(const pic_config *cfgs, int n_inst, Plan &p)
     // and 3 waves per SIMD).  A partial second residency leaves the mover's
     // last blocks running alone, and fewer regions make the collide kernel (a
     // block per region) and the event index over the regions cheaper.
-    const int max_blocks = cfgs[0].precision == PIC_FP64 ? 256 * 3 : kMaxPushBlocks;
+    // (pic_set_mover can run the movers on up to twice that grid: the layout
+    // holds regions for it, each sized for the default grid)
+    const int max_blocks = cfgs[0].precision == PIC_FP64 ? 256 * 3 : 256 * 4;
     p.n_push_blocks = (int)std::min<int64_t>(std::max<int64_t>(p.n_tiles, 1), max_blocks);
+    p.n_regions = (int)std::min<int64_t>(std::max<int64_t>(p.n_tiles, 1), 2 * max_blocks);
     L.cand_ovf_cap = cand_capacity(cfgs, n_inst, P);
     L.ev_ovf_cap = L.cand_ovf_cap;
     double expect = 0.0;
@@ -328,20 +333,20 @@ int plan(const pic_config *cfgs, int n_inst, Plan &p)
     L.cand_q = std::max<int64_t>(kCandQMin,
                                  (int64_t)align_up((uint64_t)(1.25 * expect / p.n_push_blocks) + 64, 64));
     L.ev_q = std::max<int64_t>(kEvQMin, L.cand_q / 16);
-    L.cand = take(sizeof(Cand) * ((uint64_t)p.n_push_blocks * L.cand_q + L.cand_ovf_cap));
-    L.cand_n = take(sizeof(uint32_t) * p.n_push_blocks * kWaves);
-    L.ev = take(sizeof(IzEvent) * ((uint64_t)p.n_push_blocks * L.ev_q + L.ev_ovf_cap));
-    L.ev_n = take(sizeof(uint32_t) * p.n_push_blocks);
-    L.ev_rank = take(sizeof(uint32_t) * ((uint64_t)p.n_push_blocks * L.ev_q + L.ev_ovf_cap));
-    L.ev_crank = take(sizeof(uint32_t) * ((uint64_t)p.n_push_blocks * L.ev_q + L.ev_ovf_cap));
-    L.ev_target = take(sizeof(long long) * ((uint64_t)p.n_push_blocks * L.ev_q + L.ev_ovf_cap));
+    L.cand = take(sizeof(Cand) * ((uint64_t)p.n_regions * L.cand_q + L.cand_ovf_cap));
+    L.cand_n = take(sizeof(uint32_t) * p.n_regions * kWaves);
+    L.ev = take(sizeof(IzEvent) * ((uint64_t)p.n_regions * L.ev_q + L.ev_ovf_cap));
+    L.ev_n = take(sizeof(uint32_t) * p.n_regions);
+    L.ev_rank = take(sizeof(uint32_t) * ((uint64_t)p.n_regions * L.ev_q + L.ev_ovf_cap));
+    L.ev_crank = take(sizeof(uint32_t) * ((uint64_t)p.n_regions * L.ev_q + L.ev_ovf_cap));
+    L.ev_target = take(sizeof(long long) * ((uint64_t)p.n_regions * L.ev_q + L.ev_ovf_cap));
     L.nn = take(sizeof(double) * p.G);
-    L.ev_pre = take(sizeof(uint32_t) * ((uint64_t)p.n_push_blocks + 1));
+    L.ev_pre = take(sizeof(uint32_t) * ((uint64_t)p.n_regions + 1));
     L.inst_ev = take(sizeof(uint32_t) * n_inst);
     L.inst_fill = take(sizeof(uint32_t) * n_inst);
     L.inst_start = take(sizeof(uint32_t) * (n_inst + 1));
-    L.rank_bucket = take(sizeof(RankEntry) * ((uint64_t)p.n_push_blocks * L.ev_q + L.ev_ovf_cap));
-    L.cnt_slot = take(sizeof(unsigned long long) * (uint64_t)p.n_push_blocks *
+    L.rank_bucket = take(sizeof(RankEntry) * ((uint64_t)p.n_regions * L.ev_q + L.ev_ovf_cap));
+    L.cnt_slot = take(sizeof(unsigned long long) * (uint64_t)p.n_regions *
                       (n_seg <= kCntSegMax ? n_seg : 0) * kNCnt);
     L.diag_part = take(sizeof(double) * (uint64_t)kDiagBlocks * n_seg * kDiagVals);
     L.diag_out = take(sizeof(pic_diag) * n_inst);
@@ -386,6 +391,8 @@ int pic_query_sizes(const pic_config *cfgs, int n_inst, pic_sizes *out, int64_t 
     out->work_bytes = p.L.total;
     out->x_elem_bytes = cfgs[0].precision == PIC_FP64 ? 8 : 4;
     out->v_elem_bytes = out->x_elem_bytes;
+    out->mover_blocks = p.n_push_blocks;
+    out->mover_blocks_max = p.n_regions;
     if (seg_base)
         for (size_t s = 0; s < p.seg_base.size(); ++s) seg_base[s] = p.seg_base[s];
     return PIC_OK;
@@ -570,6 +577,8 @@ int init_context(const pic_config *cfgs, int n_inst, const pic_buffers *bufs, vo
     d.cand_q = (int32_t)L.cand_q;
     d.ev_q = (int32_t)L.ev_q;
     d.n_push_blocks = p.n_push_blocks;
+    d.n_regions = p.n_regions;
+    c->default_blocks = p.n_push_blocks;
     d.n_field_tiles = p.n_field_tiles;
     d.n_sort_tiles = p.n_sort_tiles;
     d.n_seg = n_seg;
@@ -648,7 +657,8 @@ int pic_push(pic_ctx *c, unsigned flags)
 {
     if (!c) return PIC_E_STATE;
     const bool dep = !(flags & PIC_PUSH_NO_DEPOSIT);
-    return launch_push(c->d, c->st, dep, c->mcc_any, c->sub_any) == hipSuccess ? PIC_OK : PIC_E_DEVICE;
+    return launch_push(c->d, c->st, dep, c->mcc_any, c->sub_any, c->chunks) == hipSuccess ? PIC_OK
+                                                                                         : PIC_E_DEVICE;
 }
 
 int pic_deposit(pic_ctx *c)
@@ -779,6 +789,69 @@ int pic_step_graph(pic_ctx *c, int n_steps, int sort_every)
     return left > 0 ? pic_step(c, left, sort_every) : PIC_OK;
 }
 
+int pic_set_mover(pic_ctx *c, int chunks, int blocks)
+{
+    if (!c) return PIC_E_STATE;
+    if (chunks != kPer && chunks != kPer / 2) return PIC_E_ARG;
+    if (blocks == 0) blocks = c->default_blocks;
+    if (blocks < 1 || blocks > c->d.n_regions) return PIC_E_ARG;
+    if (chunks != c->chunks || blocks != c->d.n_push_blocks) drop_graph(c);
+    c->chunks = chunks;
+    c->d.n_push_blocks = blocks;
+    return PIC_OK;
+}
+
+namespace {
+
+// sort, then trial_steps whole steps at `cadence` as in pic_step_graph, timed
+// with HIP events on the context's stream: particle-steps per second
+int time_trial(pic_ctx *c, int trial_steps, int cadence, hipEvent_t e0, hipEvent_t e1, double *rate)
+{
+    std::vector<InstDyn> before(c->n_inst), after(c->n_inst);
+    int rc = pic_sort(c);  // every trial starts from freshly sorted particles
+    if (rc) return rc;
+    // the graph of this cadence is captured and uploaded before the timing
+    if (trial_steps >= (cadence > 0 ? cadence : 1) && (!c->gexec || c->g_sort != cadence)) {
+        rc = capture_period(c, cadence);
+        if (rc) return rc;
+        if (hipGraphUpload(c->gexec, c->st) != hipSuccess) return PIC_E_DEVICE;
+    }
+    if (hipMemcpyAsync(before.data(), c->d.instd, sizeof(InstDyn) * c->n_inst, hipMemcpyDeviceToHost,
+                       c->st) != hipSuccess ||
+        hipEventRecord(e0, c->st) != hipSuccess)
+        return PIC_E_DEVICE;
+    rc = pic_step_graph(c, trial_steps, cadence);
+    if (rc) return rc;
+    if (hipEventRecord(e1, c->st) != hipSuccess ||
+        hipMemcpyAsync(after.data(), c->d.instd, sizeof(InstDyn) * c->n_inst, hipMemcpyDeviceToHost,
+                       c->st) != hipSuccess ||
+        hipStreamSynchronize(c->st) != hipSuccess)
+        return PIC_E_DEVICE;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess || !(ms > 0.f)) return PIC_E_DEVICE;
+    double ps = 0.0;
+    for (int k = 0; k < c->n_inst; ++k)
+        ps += (double)(after[k].particle_steps - before[k].particle_steps);
+    *rate = ps / (1e-3 * (double)ms);
+    return PIC_OK;
+}
+
+struct EventPair {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    bool ok = false;
+    EventPair()
+    {
+        ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+    }
+    ~EventPair()
+    {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    }
+};
+
+}  // namespace
+
 int pic_autotune_sort(pic_ctx *c, const int *cand, int n_cand, int trial_steps, int *best,
                       double *rates)
 {
@@ -786,52 +859,72 @@ int pic_autotune_sort(pic_ctx *c, const int *cand, int n_cand, int trial_steps, 
     if (!cand || n_cand < 1 || trial_steps < 1 || !best) return PIC_E_ARG;
     for (int i = 0; i < n_cand; ++i)
         if (cand[i] < 0) return PIC_E_ARG;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
-        if (e0) (void)hipEventDestroy(e0);
-        return PIC_E_DEVICE;
-    }
-    std::vector<InstDyn> before(c->n_inst), after(c->n_inst);
-    int rc = PIC_OK, pick = 0;
+    EventPair ev;
+    if (!ev.ok) return PIC_E_DEVICE;
+    int pick = 0;
     double best_rate = -1.0;
-    for (int i = 0; i < n_cand && rc == PIC_OK; ++i) {
-        // every trial starts from freshly sorted particles
-        rc = pic_sort(c);
-        if (rc) break;
-        if (hipMemcpyAsync(before.data(), c->d.instd, sizeof(InstDyn) * c->n_inst,
-                           hipMemcpyDeviceToHost, c->st) != hipSuccess ||
-            hipEventRecord(e0, c->st) != hipSuccess) {
-            rc = PIC_E_DEVICE;
-            break;
-        }
-        rc = pic_step_graph(c, trial_steps, cand[i]);
-        if (rc) break;
-        if (hipEventRecord(e1, c->st) != hipSuccess ||
-            hipMemcpyAsync(after.data(), c->d.instd, sizeof(InstDyn) * c->n_inst,
-                           hipMemcpyDeviceToHost, c->st) != hipSuccess ||
-            hipStreamSynchronize(c->st) != hipSuccess) {
-            rc = PIC_E_DEVICE;
-            break;
-        }
-        float ms = 0.f;
-        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess || !(ms > 0.f)) {
-            rc = PIC_E_DEVICE;
-            break;
-        }
-        double ps = 0.0;
-        for (int k = 0; k < c->n_inst; ++k)
-            ps += (double)(after[k].particle_steps - before[k].particle_steps);
-        const double rate = ps / (1e-3 * (double)ms);
+    for (int i = 0; i < n_cand; ++i) {
+        double rate = 0.0;
+        const int rc = time_trial(c, trial_steps, cand[i], ev.e0, ev.e1, &rate);
+        if (rc) return rc;
         if (rates) rates[i] = rate;
         if (rate > best_rate) {
             best_rate = rate;
             pick = i;
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (rc == PIC_OK) *best = cand[pick];
-    return rc;
+    *best = cand[pick];
+    return PIC_OK;
+}
+
+int pic_autotune(pic_ctx *c, const int *chunks, const int *blocks, int n_movers, const int *cadences,
+                 int n_cad, int trial_steps, int *best_mover, int *best_cadence, double *rates)
+{
+    if (!c) return PIC_E_STATE;
+    if (!chunks || !blocks || n_movers < 1 || !cadences || n_cad < 1 || trial_steps < 1 ||
+        !best_mover || !best_cadence)
+        return PIC_E_ARG;
+    for (int i = 0; i < n_movers; ++i) {
+        const int b = blocks[i] == 0 ? c->default_blocks : blocks[i];
+        if ((chunks[i] != kPer && chunks[i] != kPer / 2) || b < 1 || b > c->d.n_regions)
+            return PIC_E_ARG;
+    }
+    for (int i = 0; i < n_cad; ++i)
+        if (cadences[i] < 0) return PIC_E_ARG;
+    EventPair ev;
+    if (!ev.ok) return PIC_E_DEVICE;
+    // the mover configurations at the first cadence
+    int pick = 0;
+    double best_rate = -1.0;
+    for (int i = 0; i < n_movers; ++i) {
+        int rc = pic_set_mover(c, chunks[i], blocks[i]);
+        double rate = 0.0;
+        if (!rc) rc = time_trial(c, trial_steps, cadences[0], ev.e0, ev.e1, &rate);
+        if (rc) return rc;
+        if (rates) rates[i] = rate;
+        if (rate > best_rate) {
+            best_rate = rate;
+            pick = i;
+        }
+    }
+    *best_mover = pick;
+    int rc = pic_set_mover(c, chunks[pick], blocks[pick]);
+    if (rc) return rc;
+    // then the cadences with that mover
+    int cpick = 0;
+    best_rate = -1.0;
+    for (int j = 0; j < n_cad; ++j) {
+        double rate = 0.0;
+        rc = time_trial(c, trial_steps, cadences[j], ev.e0, ev.e1, &rate);
+        if (rc) return rc;
+        if (rates) rates[n_movers + j] = rate;
+        if (rate > best_rate) {
+            best_rate = rate;
+            cpick = j;
+        }
+    }
+    *best_cadence = cadences[cpick];
+    return PIC_OK;
 }
 
 int pic_diagnostics(pic_ctx *c, pic_diag *out, int n_inst)

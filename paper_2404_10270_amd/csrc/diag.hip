@@ -98,7 +98,7 @@ __global__ __launch_bounds__(kBlock) void diag_final_kernel(Dev d, int n_blocks)
     if (d.n_seg <= kCntSegMax) {
         for (int q = 0; q < kNCnt; ++q) {
             double a = 0.0;  // exact: counts stay far below 2^53
-            for (int b = threadIdx.x; b < d.n_push_blocks; b += kBlock)
+            for (int b = threadIdx.x; b < d.n_regions; b += kBlock)
                 for (int k = 0; k < ic.nsp; ++k)
                     a += (double)d.cnt_slot[((int64_t)b * d.n_seg + ic.seg0 + k) * kNCnt + q];
             pc[q] += (unsigned long long)block_sum(a, s_red);

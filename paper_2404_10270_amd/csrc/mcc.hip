@@ -202,7 +202,7 @@ __device__ void get_event_index(EventIndex &X, const Dev &d)
 __device__ __forceinline__ const IzEvent &event_at(const EventIndex &X, const Dev &d, uint32_t e)
 {
     if (e >= X.in_regions)
-        return d.ev[(int64_t)d.n_push_blocks * d.ev_q + (e - X.in_regions)];
+        return d.ev[(int64_t)d.n_regions * d.ev_q + (e - X.in_regions)];
     int lo = 0, hi = d.n_push_blocks - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -260,7 +260,7 @@ __global__ __launch_bounds__(kBlock) void collide_kernel(Dev d)
             for (int v = 1; v < kWaves; ++v) w += (q >= pre[v]) ? 1 : 0;
             idx = (int64_t)blockIdx.x * d.cand_q + (int64_t)w * qw + (q - pre[w]);
         } else {
-            idx = (int64_t)d.n_push_blocks * d.cand_q + o_lo + (q - nr);
+            idx = (int64_t)d.n_regions * d.cand_q + o_lo + (q - nr);
         }
         const int seg = collide_one<SEGLDS>(d, cur, f64, d.cand[idx], s_sc, s_step, cnt, iz, ev);
         if (iz) {
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(kBlock) void collide_kernel(Dev d)
                 d.ev[(int64_t)blockIdx.x * d.ev_q + e] = ev;
             } else {
                 const uint32_t o = atomicAdd(&d.glob->ev_ovf, 1u);
-                if (o < (uint32_t)d.ev_ovf_cap) d.ev[(int64_t)d.n_push_blocks * d.ev_q + o] = ev;
+                if (o < (uint32_t)d.ev_ovf_cap) d.ev[(int64_t)d.n_regions * d.ev_q + o] = ev;
                 else atomicOr(&d.instd[ev.inst].status, PIC_ST_CANDIDATES);
             }
         }

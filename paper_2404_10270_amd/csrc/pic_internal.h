@@ -23,7 +23,7 @@ constexpr int kSortTile = kBlock * kSortR;
 constexpr int kDiagBlocks = 1024;           // blocks of the diagnostics reduction
 constexpr int kEmitBlocks = 64;             // blocks of the emit/close-of-step kernel
 constexpr int kDiagVals = 6;                // live, sum v2, sum vx, vy, vz, (pad)
-constexpr int kMaxPushBlocks = 256 * 4;     // persistent grid of the particle kernels (at most)
+constexpr int kMaxPushBlocks = 256 * 8;     // candidate regions, and the largest grid of the particle kernels
 constexpr int kCandQMin = 1024;             // least candidate entries per push block region
 constexpr int kEvQMin = 32;                 // least ionisation-event slots per collide block
 constexpr int kCntSegMax = 1024;           // segments counted per block in LDS (no atomics)
@@ -213,10 +213,10 @@ struct Dev {
     AffineStatus *fwd_status, *bwd_status;
     unsigned long long *sort_status;
     double *fe_part;
-    Cand *cand;                 // [n_push_blocks][cand_q] per-block regions, then the overflow list
-    uint32_t *cand_n;           // [n_push_blocks][kWaves] candidates in each wave's part of a region
-    IzEvent *ev;                // [n_push_blocks][ev_q] per-block regions, then the overflow list
-    uint32_t *ev_n;             // [n_push_blocks] events in each region
+    Cand *cand;                 // [n_regions][cand_q] per-block regions, then the overflow list
+    uint32_t *cand_n;           // [n_regions][kWaves] candidates in each wave's part of a region
+    IzEvent *ev;                // [n_regions][ev_q] per-block regions, then the overflow list
+    uint32_t *ev_n;             // [n_regions] events in each region (the first n_push_blocks in use)
     uint32_t *ev_rank;          // [events] rank of each event among its instance's (by parent id)
     uint32_t *ev_crank;         // [events] rank among the events of its instance and cell
     long long *ev_target;       // [events] slot of the atom an event consumes, or -1
@@ -225,18 +225,18 @@ struct Dev {
     // ranks of a batch: events per instance, fill counters, bucket starts, buckets
     uint32_t *inst_ev, *inst_fill, *inst_start;   // [n_inst], [n_inst], [n_inst+1]
     RankEntry *rank_bucket;                        // [events]
-    unsigned long long *cnt_slot;  // [n_push_blocks][n_seg][kNCnt] process counts per block
+    unsigned long long *cnt_slot;  // [n_regions][n_seg][kNCnt] process counts per collide block
     double *diag_part;
     pic_diag *diag_out;
     // sizes
     int64_t n_slots, n_tiles, G, cand_ovf_cap, ev_ovf_cap;
     int64_t n_field_tiles, n_sort_tiles;
     int32_t n_seg, n_inst, nsp, precision;
-    int32_t n_push_blocks;
+    int32_t n_push_blocks;      // grid of the movers and the collide kernel (regions in use)
+    int32_t n_regions;          // candidate / event regions of the layout (>= n_push_blocks)
     int32_t kinetic_any;        // some instance has a kinetic neutral species (with MCC on)
     int32_t cand_q, ev_q;       // entries per block region of the candidate and event lists
     int32_t field_all_off;      // no instance solves the field
-    int32_t _pad;
 };
 
 // ---------------------------------------------------------------------------
@@ -247,7 +247,9 @@ hipError_t launch_init_state(const Dev &d, hipStream_t st, const uint32_t *n_ini
 hipError_t launch_init_device(const Dev &d, hipStream_t st);
 // mcc: test every particle and list the candidates (pic_mcc_collide collides them)
 // subcycled: some species has nstep > 1 (its deposit between pushes is launched too)
-hipError_t launch_push(const Dev &d, hipStream_t st, bool deposit, bool mcc, bool subcycled);
+// chunks: 64-particle chunks a mover wave loads per pass (kPer, or kPer / 2
+// in two passes per tile)
+hipError_t launch_push(const Dev &d, hipStream_t st, bool deposit, bool mcc, bool subcycled, int chunks);
 hipError_t launch_deposit(const Dev &d, hipStream_t st);
 // smooth: the most density-smoother passes of any instance
 hipError_t launch_field(const Dev &d, hipStream_t st, int smooth);

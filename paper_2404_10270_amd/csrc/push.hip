@@ -209,7 +209,7 @@ __device__ __forceinline__ void queue_candidate(const Dev &d, bool cand, uint32_
             atomicOr(&d.instd[inst].status, PIC_ST_CANDIDATES);
             return;
         }
-        idx = (int64_t)d.n_push_blocks * d.cand_q + o;
+        idx = (int64_t)d.n_regions * d.cand_q + o;
     }
     Cand c;
     c.g = g;
@@ -231,7 +231,7 @@ __device__ __forceinline__ void flush_candidates(const Dev &d, uint32_t wn)
 // ---------------------------------------------------------------------------
 // FP32 form: (int32 cell, float f in [0,1), float v), FP32 gather and push
 // ---------------------------------------------------------------------------
-template <bool DEP, bool MCC>
+template <bool DEP, bool MCC, int NP>
 __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
 {
     __shared__ PushLds L;
@@ -284,188 +284,192 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
             cseg = seg;
         }
 
-        // a species with no collision process takes no test (no id read, no
-        // draw); a species on which no field acts takes no gather
-        const bool test = MCC && (flg & kFlgTest);
-        const bool force = (flg & kFlgForce) != 0;
-        // ---- loads of all chunks
-        int32_t j[kPer];
-        float f[kPer], vx[kPer], vy[kPer], vz[kPer];
-        unsigned long long pid[kPer];
-        bool lv[kPer];
-        // the tile's arrays from scalar base pointers; lanes address them with
-        // a 32-bit offset below kTile
-        const int64_t tb = base + t0;
-        const uint32_t rem = (uint32_t)min(count - t0, (int64_t)kTile);
-        float *__restrict__ Xt = X + tb;
-        int32_t *__restrict__ CELLt = CELL + tb;
-        float *__restrict__ VXt = VX + tb;
-        float *__restrict__ VYt = VY + tb;
-        float *__restrict__ VZt = VZ + tb;
-        const unsigned long long *__restrict__ IDt = ID + tb;
-        if (rem == (uint32_t)kTile) {
-            // a full tile: every load unconditional, so none is predicated
-            // and the wave issues all of them before its first wait
-            if (test) {
+        // the tile in kPer / NP passes of NP chunks per wave (NP = kPer: one pass)
+#pragma unroll 1
+        for (int r0 = 0; r0 < kPer; r0 += NP) {
+            // a species with no collision process takes no test (no id read, no
+            // draw); a species on which no field acts takes no gather
+            const bool test = MCC && (flg & kFlgTest);
+            const bool force = (flg & kFlgForce) != 0;
+            // ---- loads of all chunks
+            int32_t j[NP];
+            float f[NP], vx[NP], vy[NP], vz[NP];
+            unsigned long long pid[NP];
+            bool lv[NP];
+            // the tile's arrays from scalar base pointers; lanes address them with
+            // a 32-bit offset below kTile
+            const int64_t tb = base + t0;
+            const uint32_t rem = (uint32_t)min(count - t0, (int64_t)kTile);
+            float *__restrict__ Xt = X + tb;
+            int32_t *__restrict__ CELLt = CELL + tb;
+            float *__restrict__ VXt = VX + tb;
+            float *__restrict__ VYt = VY + tb;
+            float *__restrict__ VZt = VZ + tb;
+            const unsigned long long *__restrict__ IDt = ID + tb;
+            if (rem == (uint32_t)kTile) {
+                // a full tile: every load unconditional, so none is predicated
+                // and the wave issues all of them before its first wait
+                if (test) {
 #pragma unroll
-                for (int k = 0; k < kPer; ++k) {
-                    const uint32_t o = (uint32_t)((wave * kPer + k) * 64 + lane);
-                    j[k] = stream_ld(&CELLt[o]);
-                    f[k] = stream_ld(&Xt[o]);
-                    vx[k] = stream_ld(&VXt[o]);
-                    vy[k] = stream_ld(&VYt[o]);
-                    vz[k] = stream_ld(&VZt[o]);
-                    pid[k] = stream_ld(&IDt[o]);
+                    for (int k = 0; k < NP; ++k) {
+                        const uint32_t o = (uint32_t)((wave * kPer + r0 + k) * 64 + lane);
+                        j[k] = stream_ld(&CELLt[o]);
+                        f[k] = stream_ld(&Xt[o]);
+                        vx[k] = stream_ld(&VXt[o]);
+                        vy[k] = stream_ld(&VYt[o]);
+                        vz[k] = stream_ld(&VZt[o]);
+                        pid[k] = stream_ld(&IDt[o]);
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < NP; ++k) {
+                        const uint32_t o = (uint32_t)((wave * kPer + r0 + k) * 64 + lane);
+                        j[k] = stream_ld(&CELLt[o]);
+                        f[k] = stream_ld(&Xt[o]);
+                        vx[k] = stream_ld(&VXt[o]);
+                        vy[k] = stream_ld(&VYt[o]);
+                        vz[k] = stream_ld(&VZt[o]);
+                        pid[k] = 0;
+                    }
                 }
             } else {
 #pragma unroll
-                for (int k = 0; k < kPer; ++k) {
-                    const uint32_t o = (uint32_t)((wave * kPer + k) * 64 + lane);
-                    j[k] = stream_ld(&CELLt[o]);
-                    f[k] = stream_ld(&Xt[o]);
-                    vx[k] = stream_ld(&VXt[o]);
-                    vy[k] = stream_ld(&VYt[o]);
-                    vz[k] = stream_ld(&VZt[o]);
+                for (int k = 0; k < NP; ++k) {
+                    const uint32_t o = (uint32_t)((wave * kPer + r0 + k) * 64 + lane);
+                    j[k] = kDeadCell;
+                    f[k] = vx[k] = vy[k] = vz[k] = 0.f;
                     pid[k] = 0;
+                    if (o < rem) {
+                        j[k] = stream_ld(&CELLt[o]);
+                        f[k] = stream_ld(&Xt[o]);
+                        vx[k] = stream_ld(&VXt[o]);
+                        vy[k] = stream_ld(&VYt[o]);
+                        vz[k] = stream_ld(&VZt[o]);
+                        if (test) pid[k] = stream_ld(&IDt[o]);
+                    }
                 }
             }
-        } else {
 #pragma unroll
-            for (int k = 0; k < kPer; ++k) {
-                const uint32_t o = (uint32_t)((wave * kPer + k) * 64 + lane);
-                j[k] = kDeadCell;
-                f[k] = vx[k] = vy[k] = vz[k] = 0.f;
-                pid[k] = 0;
-                if (o < rem) {
-                    j[k] = stream_ld(&CELLt[o]);
-                    f[k] = stream_ld(&Xt[o]);
-                    vx[k] = stream_ld(&VXt[o]);
-                    vy[k] = stream_ld(&VYt[o]);
-                    vz[k] = stream_ld(&VZt[o]);
-                    if (test) pid[k] = stream_ld(&IDt[o]);
+            for (int k = 0; k < NP; ++k) lv[k] = j[k] >= 0;
+            // ---- gather
+            // (unpredicated: an empty slot reads node 0 and ignores it, so the
+            // wave issues the four gathers before one wait, not one wait each)
+            float a0[NP], a1[NP];
+            if (force) {
+#pragma unroll
+                for (int k = 0; k < NP; ++k) {
+                    const int jj = j[k] >= 0 ? j[k] : 0;
+                    a0[k] = acc[jj];
+                    a1[k] = acc[jj + 1];
                 }
+            } else {
+#pragma unroll
+                for (int k = 0; k < NP; ++k) a0[k] = a1[k] = 0.f;
             }
-        }
+            // ---- push, walls, candidate test
+            int key[NP];
+            unsigned long long w1[NP];
+            bool cand[NP];
+            bool left = false, right = false, cfl = false, bad = false;
+            int n_left = 0, n_right = 0;
 #pragma unroll
-        for (int k = 0; k < kPer; ++k) lv[k] = j[k] >= 0;
-        // ---- gather
-        // (unpredicated: an empty slot reads node 0 and ignores it, so the
-        // wave issues the four gathers before one wait, not one wait each)
-        float a0[kPer], a1[kPer];
-        if (force) {
-#pragma unroll
-            for (int k = 0; k < kPer; ++k) {
-                const int jj = j[k] >= 0 ? j[k] : 0;
-                a0[k] = acc[jj];
-                a1[k] = acc[jj + 1];
-            }
-        } else {
-#pragma unroll
-            for (int k = 0; k < kPer; ++k) a0[k] = a1[k] = 0.f;
-        }
-        // ---- push, walls, candidate test
-        int key[kPer];
-        unsigned long long w1[kPer];
-        bool cand[kPer];
-        bool left = false, right = false, cfl = false, bad = false;
-        int n_left = 0, n_right = 0;
-#pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            key[k] = -1;
-            w1[k] = 0;
-            cand[k] = false;
-            if (j[k] < 0) continue;
-            const float a = fmaf(f[k], a1[k] - a0[k], a0[k]);
-            const float h = hk * a;
-            const float mx = vx[k] + h, my = vy[k], mz = vz[k];
-            const float px = mx - mz * ty;
-            const float py = my + mz * tx;
-            const float pz = mz + (mx * ty - my * tx);
-            const float qx = mx - pz * sy;
-            const float qy = my + pz * sx;
-            const float qz = mz + (px * sy - py * sx);
-            const float nvx = qx + h, nvy = qy, nvz = qz;
-            // advance in cell-relative coordinates; |fl| is clamped so that a
-            // runaway (flagged) particle still maps to a valid integer cell
-            float fn = f[k] + msf * nvx;
-            const float fl = fminf(fmaxf(floorf(fn), -16777216.0f), 16777216.0f);
-            fn = fn - fl;
-            int32_t jn = j[k] + (int32_t)fl;
-            if (fn >= 1.0f) { fn = 0.0f; jn += 1; }
-            cfl |= !(fabsf(msf * nvx) < 1.0f);
-            const bool bk = !isfinite(nvx) || !isfinite(nvy) || !isfinite(nvz);
-            bad |= bk;
-            if (bk) jn = j[k], fn = f[k];  // keep the slot well-formed; the run is flagged
-            bool l = false, r = false;
-            if (periodic) {
-                if (jn < 0) jn += nc;
-                else if (jn >= nc) jn -= nc;
-                if (jn < 0 || jn >= nc) {
-                    jn %= nc;
+            for (int k = 0; k < NP; ++k) {
+                key[k] = -1;
+                w1[k] = 0;
+                cand[k] = false;
+                if (j[k] < 0) continue;
+                const float a = fmaf(f[k], a1[k] - a0[k], a0[k]);
+                const float h = hk * a;
+                const float mx = vx[k] + h, my = vy[k], mz = vz[k];
+                const float px = mx - mz * ty;
+                const float py = my + mz * tx;
+                const float pz = mz + (mx * ty - my * tx);
+                const float qx = mx - pz * sy;
+                const float qy = my + pz * sx;
+                const float qz = mz + (px * sy - py * sx);
+                const float nvx = qx + h, nvy = qy, nvz = qz;
+                // advance in cell-relative coordinates; |fl| is clamped so that a
+                // runaway (flagged) particle still maps to a valid integer cell
+                float fn = f[k] + msf * nvx;
+                const float fl = fminf(fmaxf(floorf(fn), -16777216.0f), 16777216.0f);
+                fn = fn - fl;
+                int32_t jn = j[k] + (int32_t)fl;
+                if (fn >= 1.0f) { fn = 0.0f; jn += 1; }
+                cfl |= !(fabsf(msf * nvx) < 1.0f);
+                const bool bk = !isfinite(nvx) || !isfinite(nvy) || !isfinite(nvz);
+                bad |= bk;
+                if (bk) jn = j[k], fn = f[k];  // keep the slot well-formed; the run is flagged
+                bool l = false, r = false;
+                if (periodic) {
                     if (jn < 0) jn += nc;
+                    else if (jn >= nc) jn -= nc;
+                    if (jn < 0 || jn >= nc) {
+                        jn %= nc;
+                        if (jn < 0) jn += nc;
+                    }
+                } else if (jn < 0) {
+                    l = true;
+                } else if (jn >= nc) {
+                    r = true;
                 }
-            } else if (jn < 0) {
-                l = true;
-            } else if (jn >= nc) {
-                r = true;
-            }
-            n_left += l;
-            n_right += r;
-            j[k] = (l || r) ? kDeadCell : jn;
-            f[k] = fn;
-            vx[k] = nvx;
-            vy[k] = nvy;
-            vz[k] = nvz;
-            if (j[k] >= 0) {
-                key[k] = j[k];
-                w1[k] = (unsigned long long)rintf(fn * 4294967296.0f);
-                if (test) {
-                    const uint4 u = draw(pid[k], step, 0, key0, key1);
-                    cand[k] = (unsigned long long)u.x < T;
+                n_left += l;
+                n_right += r;
+                j[k] = (l || r) ? kDeadCell : jn;
+                f[k] = fn;
+                vx[k] = nvx;
+                vy[k] = nvy;
+                vz[k] = nvz;
+                if (j[k] >= 0) {
+                    key[k] = j[k];
+                    w1[k] = (unsigned long long)rintf(fn * 4294967296.0f);
+                    if (test) {
+                        const uint4 u = draw(pid[k], step, 0, key0, key1);
+                        cand[k] = (unsigned long long)u.x < T;
+                    }
                 }
             }
-        }
-        // ---- stores (no reads after this point in the tile touch these arrays)
+            // ---- stores (no reads after this point in the tile touch these arrays)
 #pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            const uint32_t o = (uint32_t)((wave * kPer + k) * 64 + lane);
-            if (o < rem && lv[k]) {
-                stream_st(&Xt[o], f[k]);
-                stream_st(&CELLt[o], j[k]);
-                stream_st(&VXt[o], vx[k]);
-                stream_st(&VYt[o], vy[k]);
-                stream_st(&VZt[o], vz[k]);
+            for (int k = 0; k < NP; ++k) {
+                const uint32_t o = (uint32_t)((wave * kPer + r0 + k) * 64 + lane);
+                if (o < rem && lv[k]) {
+                    stream_st(&Xt[o], f[k]);
+                    stream_st(&CELLt[o], j[k]);
+                    stream_st(&VXt[o], vx[k]);
+                    stream_st(&VYt[o], vy[k]);
+                    stream_st(&VZt[o], vz[k]);
+                }
             }
-        }
-        // ---- rare events: wall losses, flags
-        left = n_left > 0;
-        right = n_right > 0;
-        if (ballot(left) | ballot(right) | ballot(cfl) | ballot(bad)) {
-            SegDyn *sd = d.segd + seg;
-            InstDyn *idn = d.instd + inst;
-            const unsigned long long ml = ballot(left), mr = ballot(right);
-            int sl = n_left, sr = n_right;
+            // ---- rare events: wall losses, flags
+            left = n_left > 0;
+            right = n_right > 0;
+            if (ballot(left) | ballot(right) | ballot(cfl) | ballot(bad)) {
+                SegDyn *sd = d.segd + seg;
+                InstDyn *idn = d.instd + inst;
+                const unsigned long long ml = ballot(left), mr = ballot(right);
+                int sl = n_left, sr = n_right;
 #pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                sl += __shfl_xor(sl, o, 64);
-                sr += __shfl_xor(sr, o, 64);
+                for (int o = 32; o > 0; o >>= 1) {
+                    sl += __shfl_xor(sl, o, 64);
+                    sr += __shfl_xor(sr, o, 64);
+                }
+                if (lane == 0) {
+                    if (ml) atomicAdd(&sd->absorbed_step[0], (uint32_t)sl);
+                    if (mr) atomicAdd(&sd->absorbed_step[1], (uint32_t)sr);
+                }
+                wave_or(&idn->status, PIC_ST_CFL, cfl);
+                wave_or(&idn->status, PIC_ST_NONFINITE, bad);
             }
-            if (lane == 0) {
-                if (ml) atomicAdd(&sd->absorbed_step[0], (uint32_t)sl);
-                if (mr) atomicAdd(&sd->absorbed_step[1], (uint32_t)sr);
-            }
-            wave_or(&idn->status, PIC_ST_CFL, cfl);
-            wave_or(&idn->status, PIC_ST_NONFINITE, bad);
-        }
-        // ---- candidates and deposit through LDS
-        if (MCC) {
+            // ---- candidates and deposit through LDS
+            if (MCC) {
 #pragma unroll
-            for (int k = 0; k < kPer; ++k) {
-                const uint32_t o = (uint32_t)((wave * kPer + k) * 64 + lane);
-                queue_candidate(d, cand[k], (uint32_t)(tb + o), seg, inst, vx[k], vy[k], vz[k], pid[k], wn);
+                for (int k = 0; k < NP; ++k) {
+                    const uint32_t o = (uint32_t)((wave * kPer + r0 + k) * 64 + lane);
+                    queue_candidate(d, cand[k], (uint32_t)(tb + o), seg, inst, vx[k], vy[k], vz[k], pid[k], wn);
+                }
             }
+            if (DEP) deposit_tile<NP>(L, S, key, w1);
         }
-        if (DEP) deposit_tile<kPer>(L, S, key, w1);
     }
     if (MCC) flush_candidates(d, wn);
 }
@@ -474,7 +478,7 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
 // FP64 form: double x in cells, double v; the same arithmetic as the FP64
 // reference, operation by operation (no contraction, explicit fma in the gather)
 // ---------------------------------------------------------------------------
-template <bool DEP, bool MCC>
+template <bool DEP, bool MCC, int NP>
 __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
 {
     __shared__ PushLds L;
@@ -524,169 +528,173 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
             if (MCC) step = d.instd[inst].step;
             cseg = seg;
         }
-        const bool test = MCC && (flg & kFlgTest);
-        const bool force = (flg & kFlgForce) != 0;
+        // the tile in kPer / NP passes of NP chunks per wave (NP = kPer: one pass)
+#pragma unroll 1
+        for (int r0 = 0; r0 < kPer; r0 += NP) {
+            const bool test = MCC && (flg & kFlgTest);
+            const bool force = (flg & kFlgForce) != 0;
 
-        double x[kPer], vx[kPer], vy[kPer], vz[kPer];
-        unsigned long long pid[kPer];
-        const int64_t tb = base + t0;
-        const uint32_t rem = (uint32_t)min(count - t0, (int64_t)kTile);
-        double *__restrict__ Xt = X + tb;
-        double *__restrict__ VXt = VX + tb;
-        double *__restrict__ VYt = VY + tb;
-        double *__restrict__ VZt = VZ + tb;
-        const unsigned long long *__restrict__ IDt = ID + tb;
-        if (rem == (uint32_t)kTile) {
-            // a full tile: every load unconditional (see the FP32 form)
-            if (test) {
+            double x[NP], vx[NP], vy[NP], vz[NP];
+            unsigned long long pid[NP];
+            const int64_t tb = base + t0;
+            const uint32_t rem = (uint32_t)min(count - t0, (int64_t)kTile);
+            double *__restrict__ Xt = X + tb;
+            double *__restrict__ VXt = VX + tb;
+            double *__restrict__ VYt = VY + tb;
+            double *__restrict__ VZt = VZ + tb;
+            const unsigned long long *__restrict__ IDt = ID + tb;
+            if (rem == (uint32_t)kTile) {
+                // a full tile: every load unconditional (see the FP32 form)
+                if (test) {
 #pragma unroll
-                for (int k = 0; k < kPer; ++k) {
-                    const uint32_t o = (uint32_t)((wave * kPer + k) * 64 + lane);
-                    x[k] = stream_ld(&Xt[o]);
-                    vx[k] = stream_ld(&VXt[o]);
-                    vy[k] = stream_ld(&VYt[o]);
-                    vz[k] = stream_ld(&VZt[o]);
-                    pid[k] = stream_ld(&IDt[o]);
+                    for (int k = 0; k < NP; ++k) {
+                        const uint32_t o = (uint32_t)((wave * kPer + r0 + k) * 64 + lane);
+                        x[k] = stream_ld(&Xt[o]);
+                        vx[k] = stream_ld(&VXt[o]);
+                        vy[k] = stream_ld(&VYt[o]);
+                        vz[k] = stream_ld(&VZt[o]);
+                        pid[k] = stream_ld(&IDt[o]);
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < NP; ++k) {
+                        const uint32_t o = (uint32_t)((wave * kPer + r0 + k) * 64 + lane);
+                        x[k] = stream_ld(&Xt[o]);
+                        vx[k] = stream_ld(&VXt[o]);
+                        vy[k] = stream_ld(&VYt[o]);
+                        vz[k] = stream_ld(&VZt[o]);
+                        pid[k] = 0;
+                    }
                 }
             } else {
 #pragma unroll
-                for (int k = 0; k < kPer; ++k) {
-                    const uint32_t o = (uint32_t)((wave * kPer + k) * 64 + lane);
-                    x[k] = stream_ld(&Xt[o]);
-                    vx[k] = stream_ld(&VXt[o]);
-                    vy[k] = stream_ld(&VYt[o]);
-                    vz[k] = stream_ld(&VZt[o]);
+                for (int k = 0; k < NP; ++k) {
+                    const uint32_t o = (uint32_t)((wave * kPer + r0 + k) * 64 + lane);
+                    x[k] = kDeadX;
+                    vx[k] = vy[k] = vz[k] = 0.0;
                     pid[k] = 0;
+                    if (o < rem) {
+                        x[k] = stream_ld(&Xt[o]);
+                        vx[k] = stream_ld(&VXt[o]);
+                        vy[k] = stream_ld(&VYt[o]);
+                        vz[k] = stream_ld(&VZt[o]);
+                        if (test) pid[k] = stream_ld(&IDt[o]);
+                    }
                 }
             }
-        } else {
+            // the gather unpredicated (an empty slot reads node 0 and ignores it)
+            double a0[NP], a1[NP], fr[NP];
+            bool live[NP];
+            int32_t jg[NP];
 #pragma unroll
-            for (int k = 0; k < kPer; ++k) {
-                const uint32_t o = (uint32_t)((wave * kPer + k) * 64 + lane);
-                x[k] = kDeadX;
-                vx[k] = vy[k] = vz[k] = 0.0;
-                pid[k] = 0;
-                if (o < rem) {
-                    x[k] = stream_ld(&Xt[o]);
-                    vx[k] = stream_ld(&VXt[o]);
-                    vy[k] = stream_ld(&VYt[o]);
-                    vz[k] = stream_ld(&VZt[o]);
-                    if (test) pid[k] = stream_ld(&IDt[o]);
+            for (int k = 0; k < NP; ++k) {
+                live[k] = x[k] >= 0.0;
+                const double jd = floor(x[k]);
+                jg[k] = live[k] ? (int32_t)jd : 0;
+                fr[k] = live[k] ? x[k] - jd : 0.0;
+            }
+            if (force) {
+#pragma unroll
+                for (int k = 0; k < NP; ++k) {
+                    a0[k] = acc[jg[k]];
+                    a1[k] = acc[jg[k] + 1];
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < NP; ++k) a0[k] = a1[k] = 0.0;
+            }
+            int key[NP];
+            unsigned long long w1[NP];
+            bool cand[NP];
+            bool cfl = false, bad = false;
+            int n_left = 0, n_right = 0;
+#pragma unroll
+            for (int k = 0; k < NP; ++k) {
+                key[k] = -1;
+                w1[k] = 0;
+                cand[k] = false;
+                if (!live[k]) continue;
+                const double a = fma(fr[k], a1[k] - a0[k], a0[k]);
+                const double h = hk * a;
+                const double mx = vx[k] + h, my = vy[k], mz = vz[k];
+                const double px = mx - mz * ty;
+                const double py = my + mz * tx;
+                const double pz = mz + (mx * ty - my * tx);
+                const double qx = mx - pz * sy;
+                const double qy = my + pz * sx;
+                const double qz = mz + (px * sy - py * sx);
+                vx[k] = qx + h;
+                vy[k] = qy;
+                vz[k] = qz;
+                double xn = x[k] + ms * vx[k];
+                cfl |= !(fabs(ms * vx[k]) < 1.0);
+                const bool bk = !isfinite(vx[k]) || !isfinite(vy[k]) || !isfinite(vz[k]);
+                bad |= bk;
+                if (bk) xn = x[k];
+                bool l = false, r = false;
+                if (periodic) {
+                    if (xn < 0.0) xn += L_;
+                    else if (xn >= L_) xn -= L_;
+                    if (xn >= L_) xn -= L_;
+                    if (!(xn >= 0.0 && xn < L_)) {  // displacement beyond one period (flagged)
+                        xn = xn - L_ * floor(xn / L_);
+                        if (!(xn >= 0.0 && xn < L_)) xn = 0.0;
+                    }
+                } else if (xn < 0.0) {
+                    l = true;
+                } else if (xn >= L_) {
+                    r = true;
+                }
+                n_left += l;
+                n_right += r;
+                x[k] = (l || r) ? kDeadX : xn;
+                if (x[k] >= 0.0) {
+                    const double jn = floor(x[k]);
+                    key[k] = (int)jn;
+                    w1[k] = (unsigned long long)rint(ldexp(x[k] - jn, PIC_FRAC_BITS));
+                    if (test) {
+                        const uint4 u = draw(pid[k], step, 0, key0, key1);
+                        cand[k] = (unsigned long long)u.x < T;
+                    }
                 }
             }
-        }
-        // the gather unpredicated (an empty slot reads node 0 and ignores it)
-        double a0[kPer], a1[kPer], fr[kPer];
-        bool live[kPer];
-        int32_t jg[kPer];
 #pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            live[k] = x[k] >= 0.0;
-            const double jd = floor(x[k]);
-            jg[k] = live[k] ? (int32_t)jd : 0;
-            fr[k] = live[k] ? x[k] - jd : 0.0;
-        }
-        if (force) {
-#pragma unroll
-            for (int k = 0; k < kPer; ++k) {
-                a0[k] = acc[jg[k]];
-                a1[k] = acc[jg[k] + 1];
-            }
-        } else {
-#pragma unroll
-            for (int k = 0; k < kPer; ++k) a0[k] = a1[k] = 0.0;
-        }
-        int key[kPer];
-        unsigned long long w1[kPer];
-        bool cand[kPer];
-        bool cfl = false, bad = false;
-        int n_left = 0, n_right = 0;
-#pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            key[k] = -1;
-            w1[k] = 0;
-            cand[k] = false;
-            if (!live[k]) continue;
-            const double a = fma(fr[k], a1[k] - a0[k], a0[k]);
-            const double h = hk * a;
-            const double mx = vx[k] + h, my = vy[k], mz = vz[k];
-            const double px = mx - mz * ty;
-            const double py = my + mz * tx;
-            const double pz = mz + (mx * ty - my * tx);
-            const double qx = mx - pz * sy;
-            const double qy = my + pz * sx;
-            const double qz = mz + (px * sy - py * sx);
-            vx[k] = qx + h;
-            vy[k] = qy;
-            vz[k] = qz;
-            double xn = x[k] + ms * vx[k];
-            cfl |= !(fabs(ms * vx[k]) < 1.0);
-            const bool bk = !isfinite(vx[k]) || !isfinite(vy[k]) || !isfinite(vz[k]);
-            bad |= bk;
-            if (bk) xn = x[k];
-            bool l = false, r = false;
-            if (periodic) {
-                if (xn < 0.0) xn += L_;
-                else if (xn >= L_) xn -= L_;
-                if (xn >= L_) xn -= L_;
-                if (!(xn >= 0.0 && xn < L_)) {  // displacement beyond one period (flagged)
-                    xn = xn - L_ * floor(xn / L_);
-                    if (!(xn >= 0.0 && xn < L_)) xn = 0.0;
-                }
-            } else if (xn < 0.0) {
-                l = true;
-            } else if (xn >= L_) {
-                r = true;
-            }
-            n_left += l;
-            n_right += r;
-            x[k] = (l || r) ? kDeadX : xn;
-            if (x[k] >= 0.0) {
-                const double jn = floor(x[k]);
-                key[k] = (int)jn;
-                w1[k] = (unsigned long long)rint(ldexp(x[k] - jn, PIC_FRAC_BITS));
-                if (test) {
-                    const uint4 u = draw(pid[k], step, 0, key0, key1);
-                    cand[k] = (unsigned long long)u.x < T;
+            for (int k = 0; k < NP; ++k) {
+                const uint32_t o = (uint32_t)((wave * kPer + r0 + k) * 64 + lane);
+                if (o < rem && live[k]) {
+                    stream_st(&Xt[o], x[k]);
+                    stream_st(&VXt[o], vx[k]);
+                    stream_st(&VYt[o], vy[k]);
+                    stream_st(&VZt[o], vz[k]);
                 }
             }
-        }
+            const bool left = n_left > 0, right = n_right > 0;
+            if (ballot(left) | ballot(right) | ballot(cfl) | ballot(bad)) {
+                SegDyn *sd = d.segd + seg;
+                InstDyn *idn = d.instd + inst;
+                const unsigned long long ml = ballot(left), mr = ballot(right);
+                int sl = n_left, sr = n_right;
 #pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            const uint32_t o = (uint32_t)((wave * kPer + k) * 64 + lane);
-            if (o < rem && live[k]) {
-                stream_st(&Xt[o], x[k]);
-                stream_st(&VXt[o], vx[k]);
-                stream_st(&VYt[o], vy[k]);
-                stream_st(&VZt[o], vz[k]);
+                for (int o = 32; o > 0; o >>= 1) {
+                    sl += __shfl_xor(sl, o, 64);
+                    sr += __shfl_xor(sr, o, 64);
+                }
+                if (lane == 0) {
+                    if (ml) atomicAdd(&sd->absorbed_step[0], (uint32_t)sl);
+                    if (mr) atomicAdd(&sd->absorbed_step[1], (uint32_t)sr);
+                }
+                wave_or(&idn->status, PIC_ST_CFL, cfl);
+                wave_or(&idn->status, PIC_ST_NONFINITE, bad);
             }
-        }
-        const bool left = n_left > 0, right = n_right > 0;
-        if (ballot(left) | ballot(right) | ballot(cfl) | ballot(bad)) {
-            SegDyn *sd = d.segd + seg;
-            InstDyn *idn = d.instd + inst;
-            const unsigned long long ml = ballot(left), mr = ballot(right);
-            int sl = n_left, sr = n_right;
+            if (MCC) {
 #pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                sl += __shfl_xor(sl, o, 64);
-                sr += __shfl_xor(sr, o, 64);
+                for (int k = 0; k < NP; ++k) {
+                    const uint32_t o = (uint32_t)((wave * kPer + r0 + k) * 64 + lane);
+                    queue_candidate(d, cand[k], (uint32_t)(tb + o), seg, inst, vx[k], vy[k], vz[k], pid[k], wn);
+                }
             }
-            if (lane == 0) {
-                if (ml) atomicAdd(&sd->absorbed_step[0], (uint32_t)sl);
-                if (mr) atomicAdd(&sd->absorbed_step[1], (uint32_t)sr);
-            }
-            wave_or(&idn->status, PIC_ST_CFL, cfl);
-            wave_or(&idn->status, PIC_ST_NONFINITE, bad);
+            if (DEP) deposit_tile<NP>(L, S, key, w1);
         }
-        if (MCC) {
-#pragma unroll
-            for (int k = 0; k < kPer; ++k) {
-                const uint32_t o = (uint32_t)((wave * kPer + k) * 64 + lane);
-                queue_candidate(d, cand[k], (uint32_t)(tb + o), seg, inst, vx[k], vy[k], vz[k], pid[k], wn);
-            }
-        }
-        if (DEP) deposit_tile<kPer>(L, S, key, w1);
     }
     if (MCC) flush_candidates(d, wn);
 }
@@ -716,24 +724,32 @@ __global__ __launch_bounds__(kBlock) void deposit_kernel(Dev d)
 int push_grid(const Dev &d)
 {
     // persistent-style grid, never more blocks than tiles: one block per
-    // candidate region (the count the layout planned, at most kMaxPushBlocks)
+    // candidate region in use (the default the layout planned, or the grid
+    // pic_set_mover chose, at most the layout's regions)
     return d.n_push_blocks;
 }
 
-template <bool DEP, bool MCC>
-void launch_push_t(const Dev &d, hipStream_t st, dim3 grid)
+template <bool DEP, bool MCC, int NP>
+void launch_push_np(const Dev &d, hipStream_t st, dim3 grid)
 {
-    if (d.precision == PIC_FP64) hipLaunchKernelGGL((push_f64_kernel<DEP, MCC>), grid, dim3(kBlock), 0, st, d);
-    else hipLaunchKernelGGL((push_f32_kernel<DEP, MCC>), grid, dim3(kBlock), 0, st, d);
+    if (d.precision == PIC_FP64) hipLaunchKernelGGL((push_f64_kernel<DEP, MCC, NP>), grid, dim3(kBlock), 0, st, d);
+    else hipLaunchKernelGGL((push_f32_kernel<DEP, MCC, NP>), grid, dim3(kBlock), 0, st, d);
 }
 
-hipError_t launch_push(const Dev &d, hipStream_t st, bool dep, bool mcc, bool subcycled)
+template <bool DEP, bool MCC>
+void launch_push_t(const Dev &d, hipStream_t st, dim3 grid, int chunks)
+{
+    if (chunks == kPer / 2) launch_push_np<DEP, MCC, kPer / 2>(d, st, grid);
+    else launch_push_np<DEP, MCC, kPer>(d, st, grid);
+}
+
+hipError_t launch_push(const Dev &d, hipStream_t st, bool dep, bool mcc, bool subcycled, int chunks)
 {
     const dim3 grid(push_grid(d));
-    if (dep && mcc) launch_push_t<true, true>(d, st, grid);
-    else if (dep) launch_push_t<true, false>(d, st, grid);
-    else if (mcc) launch_push_t<false, true>(d, st, grid);
-    else launch_push_t<false, false>(d, st, grid);
+    if (dep && mcc) launch_push_t<true, true>(d, st, grid, chunks);
+    else if (dep) launch_push_t<true, false>(d, st, grid, chunks);
+    else if (mcc) launch_push_t<false, true>(d, st, grid, chunks);
+    else launch_push_t<false, false>(d, st, grid, chunks);
     if (dep && subcycled) hipLaunchKernelGGL(deposit_kernel<true>, grid, dim3(kBlock), 0, st, d);
     return hipGetLastError();
 }

@@ -49,7 +49,7 @@ PIC_PUSH_NO_DEPOSIT = 0x1
 ABI_SYMBOLS = ("pic_query_sizes", "pic_init", "pic_push", "pic_deposit", "pic_field_solve",
                "pic_mcc_collide", "pic_sort", "pic_diagnostics", "pic_step", "pic_step_graph",
                "pic_autotune_sort", "pic_region", "pic_destroy", "pic_strerror",
-               "pic_init_static")
+               "pic_init_static", "pic_set_mover", "pic_autotune")
 
 
 class pic_species(C.Structure):
@@ -77,7 +77,8 @@ class pic_config(C.Structure):
 class pic_sizes(C.Structure):
     _fields_ = [("n_slots", C.c_int64), ("n_segments", C.c_int64), ("n_nodes", C.c_int64),
                 ("work_bytes", C.c_uint64), ("x_elem_bytes", C.c_int64),
-                ("v_elem_bytes", C.c_int64)]
+                ("v_elem_bytes", C.c_int64), ("mover_blocks", C.c_int64),
+                ("mover_blocks_max", C.c_int64)]
 
 
 class pic_buffers(C.Structure):
@@ -133,6 +134,10 @@ def lib():
         L.pic_step_graph.argtypes = [P, C.c_int, C.c_int]
         L.pic_autotune_sort.argtypes = [P, C.POINTER(C.c_int), C.c_int, C.c_int,
                                         C.POINTER(C.c_int), C.POINTER(C.c_double)]
+        L.pic_set_mover.argtypes = [P, C.c_int, C.c_int]
+        ip = C.POINTER(C.c_int)
+        L.pic_autotune.argtypes = [P, ip, ip, C.c_int, ip, C.c_int, C.c_int, ip, ip,
+                                   C.POINTER(C.c_double)]
         L.pic_diagnostics.argtypes = [P, C.POINTER(pic_diag), C.c_int]
         L.pic_region.argtypes = [P, C.c_int, C.POINTER(C.c_uint64), C.POINTER(C.c_int64)]
         L.pic_strerror.argtypes = [C.c_int]
@@ -228,6 +233,24 @@ def pic_autotune_sort(ctx, candidates: Sequence[int], trial_steps: int):
     _check(lib().pic_autotune_sort(ctx, cand, n, int(trial_steps), C.byref(best), rates),
            "pic_autotune_sort")
     return best.value, list(rates)
+
+
+def pic_set_mover(ctx, chunks: int, blocks: int = 0):
+    return _check(lib().pic_set_mover(ctx, int(chunks), int(blocks)), "pic_set_mover")
+
+
+def pic_autotune(ctx, movers: Sequence, cadences: Sequence[int], trial_steps: int):
+    """((chunks, blocks) of the best mover, best cadence, [rate per mover], [rate per cadence])"""
+    n, m = len(movers), len(cadences)
+    ch = (C.c_int * n)(*[int(a) for a, _ in movers])
+    bl = (C.c_int * n)(*[int(b) for _, b in movers])
+    cad = (C.c_int * m)(*[int(v) for v in cadences])
+    rates = (C.c_double * (n + m))()
+    bm, bc = C.c_int(), C.c_int()
+    _check(lib().pic_autotune(ctx, ch, bl, n, cad, m, int(trial_steps), C.byref(bm), C.byref(bc),
+                              rates), "pic_autotune")
+    r = list(rates)
+    return tuple(movers[bm.value]), bc.value, r[:n], r[n:]
 
 
 def pic_diagnostics(ctx, n_inst: int = 1):
@@ -405,6 +428,12 @@ class PicSim:
 
     def autotune_sort(self, candidates=(5, 10, 20, 40, 80), trial_steps: int = 80):
         return pic_autotune_sort(self.ctx, candidates, trial_steps)
+
+    def set_mover(self, chunks: int, blocks: int = 0):
+        pic_set_mover(self.ctx, chunks, blocks)
+
+    def autotune(self, movers, cadences=(5, 10, 20, 40, 80), trial_steps: int = 80):
+        return pic_autotune(self.ctx, movers, cadences, trial_steps)
 
     def diagnostics(self):
         return pic_diagnostics(self.ctx, self.n_inst)

@@ -150,6 +150,81 @@ def test_autotune_sort_picks_a_candidate_and_leaves_a_valid_state():
     sim.close()
 
 
+COUNTS = ("n_candidates", "n_elastic", "n_ionize", "n_cx", "n_over_cap", "n_source", "particle_steps",
+          "next_id")
+
+
+@pytest.mark.parametrize("prec", [FP32, FP64], ids=["fp32", "fp64"])
+def test_mover_shapes_give_identical_results(prec):
+    """pic_set_mover: the mover in one pass of 4 chunks or two passes of 2, on
+    the default grid or on twice as many blocks, switched between steps,
+    computes exactly what the default computes (every particle by id, every
+    counter) over 30 steps with collisions, pairs, source and sorts."""
+    wl = pin.bounded_mcc(nc=2000, ppc=300, seed=44)
+    wl.mcc.n_n *= 5
+    flush(f"mover shapes prec={prec}")
+    st64 = pin.initial_state(wl)
+    state = pin.to_fp32_form(st64, wl.nc) if prec == FP32 else st64
+    caps = pin.capacities(wl, st64)
+    ref = P.PicSim(wl, state, prec, capacities=caps)
+    nb, nmax = int(ref.sizes.mover_blocks), int(ref.sizes.mover_blocks_max)
+    assert nmax > nb  # the workload has tiles for more than one residency
+    ref.step(30, 10)
+    d0, rc = ref.diagnostics()
+    assert rc == 0
+    want = [gpu_state(ref, k) for k in range(2)]
+    ref.close()
+    plans = [[(2, 0)], [(4, nmax)], [(2, nmax)], [(4, 0), (2, nmax), (4, 0)]]
+    for plan in plans:
+        sim = P.PicSim(wl, state, prec, capacities=caps)
+        for i, (chunks, blocks) in enumerate(plan):
+            sim.set_mover(chunks, blocks)
+            sim.step(30 // len(plan), 10)
+        d, rc = sim.diagnostics()
+        assert rc == 0 and d[0].step == 30, plan
+        for f in COUNTS:
+            assert getattr(d[0], f) == getattr(d0[0], f), (plan, f)
+        for k in range(2):
+            g = gpu_state(sim, k)
+            for f in ("id", "x", "vx", "vy", "vz"):
+                assert np.array_equal(g[f], want[k][f]), (plan, k, f)
+        sim.close()
+
+
+def test_mover_shape_arguments_are_checked():
+    wl = pin.bounded_mcc(nc=300, ppc=20, seed=45)
+    sim, _, _ = build_pair(wl, FP32)
+    for chunks, blocks in ((3, 0), (8, 0), (4, -1), (4, int(sim.sizes.mover_blocks_max) + 1)):
+        with pytest.raises(P.PicError) as e:
+            sim.set_mover(chunks, blocks)
+        assert e.value.code == P.PIC_E_ARG
+    sim.close()
+
+
+def test_autotune_picks_a_mover_and_a_cadence():
+    """pic_autotune over mover shapes, then sort cadences, on a batch of
+    instances: it returns one of the candidates, leaves the context on that
+    shape, and the state stays valid."""
+    wls = pin.batched(n_inst=8, seed=46)
+    flush("autotune mover shape and cadence")
+    sim = P.PicSim(wls, [None] * len(wls), FP32, flags=P.PIC_INIT_DEVICE | P.PIC_INIT_SORT)
+    nmax = int(sim.sizes.mover_blocks_max)
+    movers = [(4, 0), (2, 0), (4, nmax), (2, nmax)]
+    best, cad, mrates, crates = sim.autotune(movers, (10, 20), 20)
+    assert best in movers and cad in (10, 20)
+    assert len(mrates) == 4 and len(crates) == 2 and all(r > 0 for r in mrates + crates)
+    d, rc = sim.diagnostics()
+    assert rc == 0 and all(x.step == 120 for x in d)  # six trials of 20 steps
+    sim.step(7, cad)
+    d, rc = sim.diagnostics()
+    assert rc == 0
+    for i in range(len(wls)):
+        for k in range(2):
+            ids = sim.state(k, inst=i)["id"]
+            assert np.unique(ids).size == ids.size
+    sim.close()
+
+
 def _dump(sim, k, prec):
     """Live particles of species k in the storage form of `prec`."""
     from types import SimpleNamespace
