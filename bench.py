@@ -45,7 +45,12 @@ PUSH_BYTES_FP64 = 4 * 8 + 8 + 4 * 8
 SORT_EVERY = 20
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "push_f32_bounded_mcc_traffic.json")
 PUSH_SOURCES = ["paper_2404_10270_amd/csrc/push.hip", "paper_2404_10270_amd/csrc/device_common.h",
-                "paper_2404_10270_amd/csrc/pic_internal.h", "paper_2404_10270_amd/csrc/mover_common.h"]
+                "paper_2404_10270_amd/csrc/pic_internal.h", "paper_2404_10270_amd/csrc/mover_common.h",
+                "paper_2404_10270_amd/csrc/collide_common.h"]
+# the mover bench.py times for the roofline: pic_push's launch (push, deposit
+# and candidate list; the step's launch also collides the block's own
+# candidates)
+MOVER_KERNEL = "push_f32_kernel<true, true, 4, false>"
 COPY_BYTES = 1 << 30  # calibration copy: 1 GiB read + 1 GiB written per launch
 
 
@@ -137,7 +142,8 @@ def time_windows(torch, sim, n_windows=5, steps=SORT_EVERY, sort_every=SORT_EVER
 
 
 def time_push(torch, sim, n_steps):
-    """Average duration of the fused mover launch, HIP events on its stream."""
+    """Average duration of the mover launch pic_push makes (push, fused deposit
+    and candidate list), HIP events on its stream, between whole steps."""
     from paper_2404_10270_amd import pic as P
     d0, _ = sim.diagnostics()
     evs = []
@@ -146,7 +152,7 @@ def time_push(torch, sim, n_steps):
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(sim.stream)
-        sim.push()  # the launch pic_step makes
+        sim.push()
         e1.record(sim.stream)
         sim.mcc_collide()
         sim.field_solve()
@@ -232,7 +238,7 @@ def pmc_summary(fetch_dir, write_dir, cfetch_dir, cwrite_dir, out):
     """HBM bytes per mover launch: FETCH_SIZE and WRITE_SIZE of the mover,
     each scaled by bytes / counter value of the calibration copy."""
     import statistics
-    mover = "push_f32_kernel"
+    mover = MOVER_KERNEL
     cf = statistics.mean(_pmc_rows(cfetch_dir, "neg_kernel", "FETCH_SIZE"))
     cw = statistics.mean(_pmc_rows(cwrite_dir, "neg_kernel", "WRITE_SIZE"))
     f_fetch, f_write = COPY_BYTES / cf, COPY_BYTES / cw
@@ -792,7 +798,8 @@ def main():
     log(f"plain copy: {copy_gbs:.0f} GB/s (mover at {achieved / copy_gbs:.2f} of it)")
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile(),
-            "kernel": f"push_f32_kernel<true,true,{mover32['chunks']}> (mover + deposit + candidate list)",
+            "kernel": f"{MOVER_KERNEL} (mover + deposit + candidate list, as pic_push launches it; "
+                      f"timed at the autotuned grid of {mover32['blocks']} blocks)",
             "mover": mover32,
             "bytes_per_particle": PUSH_BYTES_FP32,
             "particles_per_launch": int(per_launch), "us_per_launch": round(push_ms * 1e3, 2),

@@ -657,8 +657,9 @@ int pic_push(pic_ctx *c, unsigned flags)
 {
     if (!c) return PIC_E_STATE;
     const bool dep = !(flags & PIC_PUSH_NO_DEPOSIT);
-    return launch_push(c->d, c->st, dep, c->mcc_any, c->sub_any, c->chunks) == hipSuccess ? PIC_OK
-                                                                                         : PIC_E_DEVICE;
+    return launch_push(c->d, c->st, dep, c->mcc_any, c->sub_any, c->chunks, false) == hipSuccess
+               ? PIC_OK
+               : PIC_E_DEVICE;
 }
 
 int pic_deposit(pic_ctx *c)
@@ -676,7 +677,7 @@ int pic_field_solve(pic_ctx *c)
 int pic_mcc_collide(pic_ctx *c)
 {
     if (!c) return PIC_E_STATE;
-    if (c->mcc_any && launch_collide(c->d, c->st) != hipSuccess) return PIC_E_DEVICE;
+    if (c->mcc_any && launch_collide(c->d, c->st, false) != hipSuccess) return PIC_E_DEVICE;
     if (launch_emit(c->d, c->st, c->mcc_any || c->src_any, c->mcc_any) != hipSuccess) return PIC_E_DEVICE;
     c->host_steps += 1;
     return PIC_OK;
@@ -688,13 +689,37 @@ int pic_sort(pic_ctx *c)
     return launch_sort(c->d, c->st) == hipSuccess ? PIC_OK : PIC_E_DEVICE;
 }
 
+}  // extern "C"
+
+namespace {
+
+// pic_push then pic_mcc_collide, with the same results: with collisions on,
+// each mover block collides its own region's candidates right after its push,
+// and the collide kernel takes only the shared overflow list
+int push_and_collide(pic_ctx *c)
+{
+    if (!c->mcc_any) {
+        const int rc = pic_push(c, 0);
+        return rc ? rc : pic_mcc_collide(c);
+    }
+    if (launch_push(c->d, c->st, true, true, c->sub_any, c->chunks, true) != hipSuccess ||
+        launch_collide(c->d, c->st, true) != hipSuccess ||
+        launch_emit(c->d, c->st, true, true) != hipSuccess)
+        return PIC_E_DEVICE;
+    c->host_steps += 1;
+    return PIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int pic_step(pic_ctx *c, int n_steps, int sort_every)
 {
     if (!c) return PIC_E_STATE;
     if (n_steps < 0 || sort_every < 0) return PIC_E_ARG;
     for (int s = 0; s < n_steps; ++s) {
-        int rc = pic_push(c, 0);
-        if (!rc) rc = pic_mcc_collide(c);
+        int rc = push_and_collide(c);
         if (!rc) rc = pic_field_solve(c);
         if (!rc && sort_every > 0 && ((c->cfg[0].step0 + c->host_steps) % sort_every) == 0)
             rc = pic_sort(c);
@@ -709,8 +734,7 @@ namespace {
 int enqueue_period(pic_ctx *c, int n, bool sort)
 {
     for (int s = 0; s < n; ++s) {
-        int rc = pic_push(c, 0);
-        if (!rc) rc = pic_mcc_collide(c);
+        int rc = push_and_collide(c);
         if (!rc) rc = pic_field_solve(c);
         if (rc) return rc;
     }

@@ -24,85 +24,11 @@
 // reads the candidates push block b wrote, writes its ionisation events to its
 // own region and keeps its process counts in its own slot.  Readers of the
 // events index the regions through a prefix sum built in LDS.
-#include "device_common.h"
+#include "collide_common.h"
 
 #pragma clang fp contract(off)
 
 namespace picx {
-
-__device__ __forceinline__ void st_v(void *p, int64_t g, double v, bool f64)
-{
-    if (f64) ((double *)p)[g] = v;
-    else ((float *)p)[g] = (float)v;
-}
-
-// segments whose constants the collide kernel stages in LDS (few segments:
-// a single instance or a small batch)
-constexpr int kCollSegLds = 8;
-
-// collide one listed candidate; returns its segment, fills the counts and
-// the ionisation event, and stores the velocity of a particle that collided.
-// SEGLDS: the segment constants and instance steps come from the block's LDS
-// copies s_sc / s_step (staged at block start, beside the first loads).
-template <bool SEGLDS>
-__device__ __forceinline__ int collide_one(const Dev &d, int cur, bool f64, const Cand &c,
-                                           const SegConst *s_sc, const long long *s_step,
-                                           uint32_t &cnt, bool &iz, IzEvent &ev)
-{
-    const int64_t g = c.g;
-    const int seg = c.seg;  // the mover's segment of the candidate
-    const SegConst &sc = SEGLDS ? s_sc[seg] : d.segc[seg];
-    const long long step = SEGLDS ? s_step[seg] : d.instd[sc.inst].step;
-    double vx = c.vx, vy = c.vy, vz = c.vz;
-    double g2 = 0.0;
-    // with kinetic neutrals: the atom density at the electron (the mover's
-    // linear weights on the node densities of the last field pass)
-    int32_t cell = 0;
-    Rates R;
-    if (sc.kinetic) {
-        double f;
-        if (f64) {
-            const double x = ((const double *)d.x[cur])[g];
-            const double jd = floor(x);
-            cell = (int32_t)jd;
-            f = x - jd;
-        } else {
-            cell = d.cell[cur][g];
-            f = (double)((const float *)d.x[cur])[g];
-        }
-        const double *nn = d.nn + sc.gnode;
-        const double nl = fma(f, nn[cell + 1] - nn[cell], nn[cell]);
-        if (nl > sc.n_bound) atomicOr(&d.instd[sc.inst].status, PIC_ST_NN_CAP);
-        R = local_rates(sc, nl);
-    } else {
-        R = uniform_rates(sc);
-    }
-    collide_vel(sc, R, step, c.pid, vx, vy, vz, cnt, iz, g2);
-    if (cnt & ((1u << kCEl) | (1u << kCIz) | (1u << kCCx) | (1u << kCEx))) {
-        st_v(d.vx[cur], g, vx, f64);
-        st_v(d.vy[cur], g, vy, f64);
-        st_v(d.vz[cur], g, vz, f64);
-    }
-    if (iz) {
-        ev.parent_id = c.pid;
-        ev.slot = (uint32_t)g;
-        ev.seg = seg;
-        ev.inst = sc.inst;
-        ev.cell = cell;
-        ev.g2 = g2;
-    }
-    return seg;
-}
-
-__device__ __forceinline__ void add_counts(InstDyn *idn, uint32_t c)
-{
-    if (c & (1u << kCCand)) atomicAdd(&idn->n_candidates, 1ull);
-    if (c & (1u << kCEl)) atomicAdd(&idn->n_elastic, 1ull);
-    if (c & (1u << kCIz)) atomicAdd(&idn->n_ionize, 1ull);
-    if (c & (1u << kCCx)) atomicAdd(&idn->n_cx, 1ull);
-    if (c & (1u << kCOver)) atomicAdd(&idn->n_over_cap, 1ull);
-    if (c & (1u << kCEx)) atomicAdd(&idn->n_excite, 1ull);
-}
 
 // ---------------------------------------------------------------------------
 // the event list of this step: per-block regions indexed by an LDS prefix sum
@@ -211,87 +137,20 @@ __device__ __forceinline__ const IzEvent &event_at(const EventIndex &X, const De
     return d.ev[(int64_t)lo * d.ev_q + (e - X.pre[lo])];
 }
 
-template <bool SEGLDS>
+// The collisions of the listed candidates: block b takes push block b's
+// region and a share of the overflow list; OVF_ONLY: only the overflow list
+// (after movers that collided their own regions), events to the event
+// overflow list.
+template <bool SEGLDS, bool OVF_ONLY>
 __global__ __launch_bounds__(kBlock) void collide_kernel(Dev d)
 {
     extern __shared__ uint32_t s_cnt[];  // [n_seg][kNCnt] when n_seg <= kCntSegMax
     __shared__ uint32_t s_en;
     __shared__ SegConst s_sc[SEGLDS ? kCollSegLds : 1];
     __shared__ long long s_step[SEGLDS ? kCollSegLds : 1];
-    const bool lds_cnt = d.n_seg <= kCntSegMax;
-    if (lds_cnt)
-        for (int q = threadIdx.x; q < d.n_seg * kNCnt; q += kBlock) s_cnt[q] = 0u;
-    if (threadIdx.x == 0) s_en = 0u;
-    if (SEGLDS) {
-        // the segments' constants word by word, and each segment's step
-        constexpr int kW = (int)(sizeof(SegConst) / 8);
-        static_assert(sizeof(SegConst) % 8 == 0, "segment constants: whole words");
-        const unsigned long long *src = (const unsigned long long *)d.segc;
-        unsigned long long *dst = (unsigned long long *)s_sc;
-        for (int q = threadIdx.x; q < d.n_seg * kW; q += kBlock) dst[q] = src[q];
-        if (threadIdx.x < d.n_seg) s_step[threadIdx.x] = d.instd[d.segc[threadIdx.x].inst].step;
-    }
-    __syncthreads();
-
-    const int cur = d.glob->cur_set;
-    const bool f64 = (d.precision == PIC_FP64);
-    // this block's region of the candidate list (one part per mover wave),
-    // then a share of the overflow list
-    const uint32_t qw = (uint32_t)d.cand_q / kWaves;
-    uint32_t pre[kWaves + 1];
-    pre[0] = 0;
-#pragma unroll
-    for (int w = 0; w < kWaves; ++w) pre[w + 1] = pre[w] + d.cand_n[blockIdx.x * kWaves + w];
-    const uint32_t nr = pre[kWaves];
-    uint32_t novf = d.glob->cand_ovf;
-    if (novf > (uint32_t)d.cand_ovf_cap) novf = (uint32_t)d.cand_ovf_cap;
-    const uint32_t per_block = (novf + gridDim.x - 1) / gridDim.x;
-    const uint32_t o_lo = min(novf, blockIdx.x * per_block);
-    const uint32_t o_hi = min(novf, o_lo + per_block);
-    const uint32_t n_items = nr + (o_hi - o_lo);
-    for (uint32_t q = threadIdx.x; q < n_items; q += kBlock) {
-        uint32_t cnt = 0;  // one bit per process (1 << kC...)
-        bool iz = false;
-        IzEvent ev = {};
-        int64_t idx;
-        if (q < nr) {
-            int w = 0;
-#pragma unroll
-            for (int v = 1; v < kWaves; ++v) w += (q >= pre[v]) ? 1 : 0;
-            idx = (int64_t)blockIdx.x * d.cand_q + (int64_t)w * qw + (q - pre[w]);
-        } else {
-            idx = (int64_t)d.n_regions * d.cand_q + o_lo + (q - nr);
-        }
-        const int seg = collide_one<SEGLDS>(d, cur, f64, d.cand[idx], s_sc, s_step, cnt, iz, ev);
-        if (iz) {
-            // this block's region of the event list; the rare excess goes to the overflow list
-            const uint32_t e = atomicAdd(&s_en, 1u);
-            if (e < (uint32_t)d.ev_q) {
-                d.ev[(int64_t)blockIdx.x * d.ev_q + e] = ev;
-            } else {
-                const uint32_t o = atomicAdd(&d.glob->ev_ovf, 1u);
-                if (o < (uint32_t)d.ev_ovf_cap) d.ev[(int64_t)d.n_regions * d.ev_q + o] = ev;
-                else atomicOr(&d.instd[ev.inst].status, PIC_ST_CANDIDATES);
-            }
-        }
-        if (lds_cnt) {
-#pragma unroll
-            for (int c = 0; c < kNCnt; ++c)
-                if (cnt & (1u << c)) atomicAdd(&s_cnt[seg * kNCnt + c], 1u);
-        } else {
-            add_counts(d.instd + d.segc[seg].inst, cnt);
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) d.ev_n[blockIdx.x] = min(s_en, (uint32_t)d.ev_q);
-    if (lds_cnt) {
-        // this block's own slot: plain read-modify-write, no other block touches it
-        unsigned long long *slot = d.cnt_slot + (int64_t)blockIdx.x * d.n_seg * kNCnt;
-        for (int q = threadIdx.x; q < d.n_seg * kNCnt; q += kBlock) {
-            const uint32_t v = s_cnt[q];
-            if (v) slot[q] += v;
-        }
-    }
+    if (OVF_ONLY && d.glob->cand_ovf == 0u) return;  // uniform: nothing overflowed this step
+    collide_block<SEGLDS>(d, blockIdx.x, !OVF_ONLY, true, nullptr, s_cnt, d.n_seg <= kCntSegMax, s_en,
+                          s_sc, s_step);
 }
 
 // write one created particle into segment `seg`, in-segment index `i`
@@ -895,13 +754,20 @@ __global__ __launch_bounds__(kBlock) void close_step_kernel(Dev d, int with_even
     close_body(d, X, s_m, n_inst, with_events != 0);
 }
 
-hipError_t launch_collide(const Dev &d, hipStream_t st)
+hipError_t launch_collide(const Dev &d, hipStream_t st, bool overflow_only)
 {
     const size_t lds = d.n_seg <= kCntSegMax ? sizeof(uint32_t) * d.n_seg * kNCnt : 0;
-    if (d.n_seg <= kCollSegLds)
-        hipLaunchKernelGGL(collide_kernel<true>, dim3(d.n_push_blocks), dim3(kBlock), lds, st, d);
-    else
-        hipLaunchKernelGGL(collide_kernel<false>, dim3(d.n_push_blocks), dim3(kBlock), lds, st, d);
+    if (overflow_only) {
+        const dim3 grid(kOvfCollideBlocks);
+        if (d.n_seg <= kCollSegLds)
+            hipLaunchKernelGGL((collide_kernel<true, true>), grid, dim3(kBlock), lds, st, d);
+        else
+            hipLaunchKernelGGL((collide_kernel<false, true>), grid, dim3(kBlock), lds, st, d);
+    } else if (d.n_seg <= kCollSegLds) {
+        hipLaunchKernelGGL((collide_kernel<true, false>), dim3(d.n_push_blocks), dim3(kBlock), lds, st, d);
+    } else {
+        hipLaunchKernelGGL((collide_kernel<false, false>), dim3(d.n_push_blocks), dim3(kBlock), lds, st, d);
+    }
     return hipGetLastError();
 }
 

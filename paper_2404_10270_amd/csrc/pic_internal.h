@@ -31,6 +31,7 @@ constexpr int kNCnt = 6;                    // candidates, elastic, ionisation, 
 constexpr int kRankJ = 64;                  // events compared per block pass of the rank kernel
 constexpr int kRankBlocks = 512;            // grid of the rank kernel
 constexpr int kTargetBlocks = 64;           // grid of the neutral-target kernel (a wave per event)
+constexpr int kOvfCollideBlocks = 64;       // grid of the collide kernel for the overflow list only
 constexpr uint32_t kNoIndex = 0xFFFFFFFFu;  // steps since the last sort: no sort yet
 
 constexpr int32_t kDeadCell = -1;           // FP32 form: cell of an absorbed particle
@@ -249,11 +250,16 @@ hipError_t launch_init_device(const Dev &d, hipStream_t st);
 // subcycled: some species has nstep > 1 (its deposit between pushes is launched too)
 // chunks: 64-particle chunks a mover wave loads per pass (kPer, or kPer / 2
 // in two passes per tile)
-hipError_t launch_push(const Dev &d, hipStream_t st, bool deposit, bool mcc, bool subcycled, int chunks);
+// collide (with mcc): each mover block then collides the candidates of its
+// own region (the shared overflow list is left to launch_collide)
+hipError_t launch_push(const Dev &d, hipStream_t st, bool deposit, bool mcc, bool subcycled, int chunks,
+                       bool collide);
 hipError_t launch_deposit(const Dev &d, hipStream_t st);
 // smooth: the most density-smoother passes of any instance
 hipError_t launch_field(const Dev &d, hipStream_t st, int smooth);
-hipError_t launch_collide(const Dev &d, hipStream_t st);
+// overflow_only: after movers that collided their own regions (launch_push
+// with collide), only the shared overflow list is left
+hipError_t launch_collide(const Dev &d, hipStream_t st, bool overflow_only);
 // ionisation and source pairs (when `pairs`), then the close of the step
 // (`events`: collisions ran this step)
 hipError_t launch_emit(const Dev &d, hipStream_t st, bool pairs, bool events);

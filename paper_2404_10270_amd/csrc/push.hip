@@ -26,6 +26,7 @@
 //    the collide kernel reads them contiguously; only a block with more than
 //    its region's cand_q candidates appends the excess to a shared overflow
 //    list.
+#include "collide_common.h"
 #include "mover_common.h"
 
 #pragma clang fp contract(off)
@@ -228,10 +229,33 @@ __device__ __forceinline__ void flush_candidates(const Dev &d, uint32_t wn)
     if (lane_id() == 0) d.cand_n[blockIdx.x * kWaves + (threadIdx.x >> 6)] = min(wn, qw);
 }
 
+// After its push the block collides the candidates of its own region (no
+// other block writes or reads it): once every wave has passed the barrier,
+// its candidate entries and its particles' new velocities are in place.  The
+// process counts take the LDS of the tile tables, which the push no longer
+// needs.  Overflowed candidates are left to the collide kernel.
+__device__ __forceinline__ void collide_own_region(PushLds &L, const Dev &d, uint32_t wn)
+{
+    __shared__ uint32_t s_wn[kWaves];
+    __shared__ uint32_t s_en;
+    __shared__ SegConst s_sc[kCollSegLds];
+    __shared__ long long s_step[kCollSegLds];
+    const uint32_t qw = (uint32_t)d.cand_q / kWaves;
+    if (lane_id() == 0) s_wn[threadIdx.x >> 6] = min(wn, qw);
+    __syncthreads();
+    constexpr size_t kTables = sizeof(L.tile0) + sizeof(L.base) + sizeof(L.count) + sizeof(L.flg);
+    uint32_t *s_cnt = reinterpret_cast<uint32_t *>(&L.tile0[0]);
+    const bool lds_cnt = (size_t)d.n_seg * kNCnt * sizeof(uint32_t) <= kTables;
+    if (d.n_seg <= kCollSegLds)
+        collide_block<true>(d, blockIdx.x, true, false, s_wn, s_cnt, lds_cnt, s_en, s_sc, s_step);
+    else
+        collide_block<false>(d, blockIdx.x, true, false, s_wn, s_cnt, lds_cnt, s_en, s_sc, s_step);
+}
+
 // ---------------------------------------------------------------------------
 // FP32 form: (int32 cell, float f in [0,1), float v), FP32 gather and push
 // ---------------------------------------------------------------------------
-template <bool DEP, bool MCC, int NP>
+template <bool DEP, bool MCC, int NP, bool COLL>
 __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
 {
     __shared__ PushLds L;
@@ -472,13 +496,14 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
         }
     }
     if (MCC) flush_candidates(d, wn);
+    if constexpr (MCC && COLL) collide_own_region(L, d, wn);
 }
 
 // ---------------------------------------------------------------------------
 // FP64 form: double x in cells, double v; the same arithmetic as the FP64
 // reference, operation by operation (no contraction, explicit fma in the gather)
 // ---------------------------------------------------------------------------
-template <bool DEP, bool MCC, int NP>
+template <bool DEP, bool MCC, int NP, bool COLL>
 __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
 {
     __shared__ PushLds L;
@@ -697,6 +722,7 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
         }
     }
     if (MCC) flush_candidates(d, wn);
+    if constexpr (MCC && COLL) collide_own_region(L, d, wn);
 }
 
 // ---------------------------------------------------------------------------
@@ -729,27 +755,32 @@ int push_grid(const Dev &d)
     return d.n_push_blocks;
 }
 
-template <bool DEP, bool MCC, int NP>
+template <bool DEP, bool MCC, int NP, bool COLL>
 void launch_push_np(const Dev &d, hipStream_t st, dim3 grid)
 {
-    if (d.precision == PIC_FP64) hipLaunchKernelGGL((push_f64_kernel<DEP, MCC, NP>), grid, dim3(kBlock), 0, st, d);
-    else hipLaunchKernelGGL((push_f32_kernel<DEP, MCC, NP>), grid, dim3(kBlock), 0, st, d);
+    if (d.precision == PIC_FP64)
+        hipLaunchKernelGGL((push_f64_kernel<DEP, MCC, NP, COLL>), grid, dim3(kBlock), 0, st, d);
+    else
+        hipLaunchKernelGGL((push_f32_kernel<DEP, MCC, NP, COLL>), grid, dim3(kBlock), 0, st, d);
 }
 
-template <bool DEP, bool MCC>
+template <bool DEP, bool MCC, bool COLL>
 void launch_push_t(const Dev &d, hipStream_t st, dim3 grid, int chunks)
 {
-    if (chunks == kPer / 2) launch_push_np<DEP, MCC, kPer / 2>(d, st, grid);
-    else launch_push_np<DEP, MCC, kPer>(d, st, grid);
+    if (chunks == kPer / 2) launch_push_np<DEP, MCC, kPer / 2, COLL>(d, st, grid);
+    else launch_push_np<DEP, MCC, kPer, COLL>(d, st, grid);
 }
 
-hipError_t launch_push(const Dev &d, hipStream_t st, bool dep, bool mcc, bool subcycled, int chunks)
+hipError_t launch_push(const Dev &d, hipStream_t st, bool dep, bool mcc, bool subcycled, int chunks,
+                       bool collide)
 {
     const dim3 grid(push_grid(d));
-    if (dep && mcc) launch_push_t<true, true>(d, st, grid, chunks);
-    else if (dep) launch_push_t<true, false>(d, st, grid, chunks);
-    else if (mcc) launch_push_t<false, true>(d, st, grid, chunks);
-    else launch_push_t<false, false>(d, st, grid, chunks);
+    if (dep && mcc && collide) launch_push_t<true, true, true>(d, st, grid, chunks);
+    else if (dep && mcc) launch_push_t<true, true, false>(d, st, grid, chunks);
+    else if (dep) launch_push_t<true, false, false>(d, st, grid, chunks);
+    else if (mcc && collide) launch_push_t<false, true, true>(d, st, grid, chunks);
+    else if (mcc) launch_push_t<false, true, false>(d, st, grid, chunks);
+    else launch_push_t<false, false, false>(d, st, grid, chunks);
     if (dep && subcycled) hipLaunchKernelGGL(deposit_kernel<true>, grid, dim3(kBlock), 0, st, d);
     return hipGetLastError();
 }

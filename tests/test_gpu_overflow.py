@@ -16,7 +16,9 @@ so these cases force them from the host with the workload's shape:
   times the elastic one, so that a collide block meets about 250 ionisations
   against an event region of 84.
 
-One step on the oracle's field, then counts, ids, positions and velocities
+One step on the oracle's field, by the separate phase calls and by the step
+driver (whose movers collide their own regions and leave only the overflow
+list to the collide kernel), then counts, ids, positions and velocities
 against the oracle (FP64 identical counts and ids; FP32 within the FP32
 tolerance of the one-step test)."""
 import numpy as np
@@ -31,7 +33,10 @@ TILE = 1024                  # particles per mover tile
 GRID = {FP32: 1024, FP64: 768}  # persistent grid of the movers, blocks
 
 
-def _one_step(wl, prec, caps):
+def _one_step(wl, prec, caps, fused):
+    """One step on the oracle's field.  fused: the step driver's path (each
+    mover block collides its own region, the collide kernel only the
+    overflow list); else pic_push then pic_mcc_collide."""
     sim, orc, ost = build_pair(wl, prec, caps=caps, flags=P.PIC_INIT_NO_FIELD)
     orc.deposit()
     orc.field()
@@ -41,8 +46,11 @@ def _one_step(wl, prec, caps):
     orc.mcc()
     orc.source()
     sim.set_acc(acc)
-    sim.push()
-    sim.mcc_collide()
+    if fused:
+        sim.step(1)
+    else:
+        sim.push()
+        sim.mcc_collide()
     d, rc = sim.diagnostics()
     return sim, orc, d[0], rc
 
@@ -75,19 +83,20 @@ def _compare(sim, orc, d, wl, prec):
             assert bad <= (0 if prec == FP64 else 16), (k, f, bad, float(np.max(err)))
 
 
+@pytest.mark.parametrize("fused", [False, True], ids=["phases", "step"])
 @pytest.mark.parametrize("prec", [FP32, FP64], ids=["fp32", "fp64"])
-def test_candidate_overflow_list(prec):
+def test_candidate_overflow_list(prec, fused):
     nc, ppc = 1024, 576
     n = nc * ppc                       # 576 full tiles per species
     wl = pin.bounded_mcc(nc=nc, ppc=ppc, seed=61, source=False)
     wl.mcc.n_n = 1e27
     wl.mcc.sig_iz = 0.0
-    flush(f"candidate overflow prec={prec}")
+    flush(f"candidate overflow prec={prec} fused={fused}")
     # the shape forces the overflow: 1.5 tiles per block, every particle a candidate
     n_tiles = 2 * n // TILE
     grid = min(n_tiles, GRID[prec])
     assert n_tiles == 1152 and n_tiles > grid
-    sim, orc, d, rc = _one_step(wl, prec, [n, n])
+    sim, orc, d, rc = _one_step(wl, prec, [n, n], fused)
     T = [orc.candidate_threshold(k) for k in range(2)]
     expect = n * (T[0] + T[1]) / 2 ** 32
     cand_q = max(1024, -(-(int(1.25 * expect / grid) + 64) // 64) * 64)
@@ -99,16 +108,17 @@ def test_candidate_overflow_list(prec):
     sim.close()
 
 
+@pytest.mark.parametrize("fused", [False, True], ids=["phases", "step"])
 @pytest.mark.parametrize("prec", [FP32, FP64], ids=["fp32", "fp64"])
-def test_ionisation_event_overflow_list(prec):
+def test_ionisation_event_overflow_list(prec, fused):
     nc, ppc = 512, 100
     wl = pin.bounded_mcc(nc=nc, ppc=ppc, seed=62)
     wl.mcc.n_n = 1e27
     wl.mcc.sig_iz = 10 * wl.mcc.sig_el
-    flush(f"ionisation event overflow prec={prec}")
+    flush(f"ionisation event overflow prec={prec} fused={fused}")
     n = nc * ppc
     caps = [3 * n, 3 * n]
-    sim, orc, d, rc = _one_step(wl, prec, caps)
+    sim, orc, d, rc = _one_step(wl, prec, caps, fused)
     n_tiles = 2 * (-(-3 * n // TILE))
     grid = min(n_tiles, GRID[prec])
     T = [orc.candidate_threshold(k) for k in range(2)]
