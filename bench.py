@@ -38,10 +38,11 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per particle and push: read cell, f, vx, vy, vz (4 B each)
-# and the 8 B id; write cell, f, vx, vy, vz
-PUSH_BYTES_FP32 = 5 * 4 + 8 + 5 * 4
-# FP64 form: read x, vx, vy, vz (8 B each) and id; write x, vx, vy, vz
-PUSH_BYTES_FP64 = 4 * 8 + 8 + 4 * 8
+# and the id's low word (4 B: every id of the workloads is below 2^32); write
+# cell, f, vx, vy, vz
+PUSH_BYTES_FP32 = 5 * 4 + 4 + 5 * 4
+# FP64 form: read x, vx, vy, vz (8 B each) and the id's low word; write x, vx, vy, vz
+PUSH_BYTES_FP64 = 4 * 8 + 4 + 4 * 8
 SORT_EVERY = 20
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "push_f32_bounded_mcc_traffic.json")
 PUSH_SOURCES = ["paper_2404_10270_amd/csrc/push.hip", "paper_2404_10270_amd/csrc/device_common.h",
@@ -302,8 +303,8 @@ def table1_run(torch, args):
     particles), 1 m, dt = 4e-14 s, periodic, no field solve; elastic, excitation
     and ionisation against the atoms (stand-in cross sections); FP32 form, drawn
     on the device and sorted, steps from a HIP graph with a sort every 20 steps.
-    The mover moves 48 B per electron (its id is read for the collision test)
-    and 40 B per ion or atom (no process, no id read)."""
+    The mover moves 44 B per electron (its id's low word is read for the
+    collision test) and 40 B per ion or atom (no process, no id read)."""
     import pic_inputs as pin
     from paper_2404_10270_amd import pic as P
     wl = pin.table1()
@@ -317,7 +318,7 @@ def table1_run(torch, args):
     if rc != 0:
         raise RuntimeError(f"device status during the table1 run: {rc}")
     live = [int(d1[0].n_live[k]) for k in range(3)]
-    bytes_launch = PUSH_BYTES_FP32 * live[0] + (PUSH_BYTES_FP32 - 8) * (live[1] + live[2])
+    bytes_launch = PUSH_BYTES_FP32 * live[0] + (PUSH_BYTES_FP32 - 4) * (live[1] + live[2])
     gbs = bytes_launch / (push_ms * 1e-3) / 1e9
     sim.close()
     out = {"value": rate, "unit": "particle-steps/s", "particles": n, "cells": wl.nc,

@@ -162,7 +162,10 @@ typedef struct {
  *   x   PIC_FP32: float in-cell offset f in [0,1); PIC_FP64: double x in cells
  *   cell int32 cell index (PIC_FP32 only; NULL for PIC_FP64)
  *   vx, vy, vz float (PIC_FP32) or double (PIC_FP64), cells per step
- *   id  uint64 particle id (unique, < 2^63)
+ *   id_lo, id_hi  uint32 low and high words of the uint64 particle id
+ *       (unique, < 2^63).  Two arrays so that the mover, whose collision
+ *       test draws from the id, reads 4 bytes per particle while every id
+ *       of an instance is below 2^32 (its high words are then all zero).
  * An absorbed particle keeps its slot until the next sort, marked by
  * cell < 0 (PIC_FP32) or x < 0 (PIC_FP64).
  */
@@ -170,7 +173,7 @@ typedef struct {
     void *x[2];
     int32_t *cell[2];
     void *vx[2], *vy[2], *vz[2];
-    uint64_t *id[2];
+    uint32_t *id_lo[2], *id_hi[2];
     void *work;          /* device workspace of pic_sizes.work_bytes, 256-byte aligned */
 } pic_buffers;
 

@@ -432,7 +432,7 @@ int init_context(const pic_config *cfgs, int n_inst, const pic_buffers *bufs, vo
     const bool f64 = cfgs[0].precision == PIC_FP64;
     for (int b = 0; b < 2; ++b) {
         if (!aligned(bufs->x[b]) || !aligned(bufs->vx[b]) || !aligned(bufs->vy[b]) ||
-            !aligned(bufs->vz[b]) || !aligned(bufs->id[b]))
+            !aligned(bufs->vz[b]) || !aligned(bufs->id_lo[b]) || !aligned(bufs->id_hi[b]))
             return PIC_E_ARG;
         if (!f64 && !aligned(bufs->cell[b])) return PIC_E_ARG;
     }
@@ -512,6 +512,7 @@ int init_context(const pic_config *cfgs, int n_inst, const pic_buffers *bufs, vo
         std::memset(&id, 0, sizeof(id));
         id.step = cf.step0;
         id.next_id = cf.next_id;
+        id.wide_ids = cf.next_id > (1ull << 32) ? 1u : 0u;  // (uploaded ids are checked by the device)
     }
     Globals g;
     std::memset(&g, 0, sizeof(g));
@@ -526,7 +527,8 @@ int init_context(const pic_config *cfgs, int n_inst, const pic_buffers *bufs, vo
         d.vx[b] = bufs->vx[b];
         d.vy[b] = bufs->vy[b];
         d.vz[b] = bufs->vz[b];
-        d.id[b] = (unsigned long long *)bufs->id[b];
+        d.id_lo[b] = bufs->id_lo[b];
+        d.id_hi[b] = bufs->id_hi[b];
     }
     const Layout &L = c->L;
     d.segc = at<SegConst>(W, L.segc);

@@ -162,7 +162,8 @@ hipError_t launch_diag(const Dev &d, hipStream_t st)
 }
 
 // uploaded state: a particle outside [0, nc), with a position offset outside
-// [0, 1) or a non-finite velocity is dropped (marked absorbed) and flagged
+// [0, 1) or a non-finite velocity is dropped (marked absorbed) and flagged;
+// an id at or above 2^32 marks its instance's ids as wide
 __global__ __launch_bounds__(kBlock) void init_check_kernel(Dev d)
 {
     const bool f64 = (d.precision == PIC_FP64);
@@ -198,11 +199,15 @@ __global__ __launch_bounds__(kBlock) void init_check_kernel(Dev d)
                     if (drop) d.cell[0][g] = kDeadCell;
                 }
             }
+            const bool wide = i < count && d.id_hi[0][sc.base + i] != 0u;
             const unsigned long long m = ballot(drop);
             if (m && lane == (__ffsll((long long)m) - 1)) {
                 atomicSub(&d.segd[seg].live, (uint32_t)__popcll(m));
                 atomicOr(&d.instd[sc.inst].status, PIC_ST_BAD_INIT);
             }
+            // an uploaded id at or above 2^32: the movers read both id words
+            const unsigned long long mw = ballot(wide);
+            if (mw && lane == (__ffsll((long long)mw) - 1)) atomicOr(&d.instd[sc.inst].wide_ids, 1u);
         }
     }
 }

@@ -78,7 +78,7 @@ __global__ __launch_bounds__(kBlock) void init_device_kernel(Dev d)
                 ((float *)d.vy[0])[g] = (float)vy;
                 ((float *)d.vz[0])[g] = (float)vz;
             }
-            d.id[0][g] = id;
+            store_id(d, 0, g, id);
         }
     }
 }

@@ -199,7 +199,7 @@ __device__ __forceinline__ void place(const Dev &d, int cur, bool f64, const Pla
     st_v(d.vx[cur], g, vx, f64);
     st_v(d.vy[cur], g, vy, f64);
     st_v(d.vz[cur], g, vz, f64);
-    d.id[cur][g] = id;
+    store_id(d, cur, g, id);
     if ((1ull << PIC_FRAC_BITS) - w1) atomicAdd(S + j, (1ull << PIC_FRAC_BITS) - w1);
     if (w1) atomicAdd(S + j + 1, w1);
 }
@@ -493,7 +493,7 @@ __global__ __launch_bounds__(kBlock) void target_kernel(Dev d)
                             cj = d.cell[cur][g];
                         }
                         if (cj != j) continue;
-                        const unsigned long long id = d.id[cur][g];
+                        const unsigned long long id = load_id(d, cur, g);
                         const uint4 u = draw(id, step, 3, sn.key0, sn.key1);
                         const KeyId k = {((unsigned long long)u.x << 32) | u.y, id, (long long)g};
                         if ((r == 0 || key_less(prev, k)) && key_less(k, best)) best = k;
@@ -717,6 +717,7 @@ __device__ void close_body(const Dev &d, const EventIndex &X, const uint32_t *s_
         }
         idn->particle_steps += pushed;
         idn->next_id += 2ull * (unsigned long long)(m_i + n_src);
+        if (idn->next_id > (1ull << 32)) idn->wide_ids = 1u;  // ids created from now on may need id_hi
         idn->n_source += n_src;
         idn->step += 1;
     }

@@ -112,7 +112,7 @@ struct InstDyn {
     long long step;
     unsigned long long next_id;
     uint32_t status;
-    uint32_t _pad;
+    uint32_t wide_ids;  // some id of the instance may be >= 2^32 (the movers then read id_hi)
     // process counts of batches with more than kCntSegMax segments (otherwise per-block slots)
     unsigned long long n_candidates, n_elastic, n_ionize, n_cx, n_over_cap;
     unsigned long long n_source;
@@ -193,7 +193,7 @@ struct Dev {
     void *x[2];
     int32_t *cell[2];
     void *vx[2], *vy[2], *vz[2];
-    unsigned long long *id[2];
+    uint32_t *id_lo[2], *id_hi[2];   // low and high words of the particle ids
     // tables
     const SegConst *segc;
     const InstConst *instc;
@@ -239,6 +239,18 @@ struct Dev {
     int32_t cand_q, ev_q;       // entries per block region of the candidate and event lists
     int32_t field_all_off;      // no instance solves the field
 };
+
+// a particle's id from its two words
+__device__ __forceinline__ unsigned long long load_id(const Dev &d, int set, int64_t g)
+{
+    return (unsigned long long)d.id_lo[set][g] | ((unsigned long long)d.id_hi[set][g] << 32);
+}
+
+__device__ __forceinline__ void store_id(const Dev &d, int set, int64_t g, unsigned long long id)
+{
+    d.id_lo[set][g] = (uint32_t)id;
+    d.id_hi[set][g] = (uint32_t)(id >> 32);
+}
 
 // ---------------------------------------------------------------------------
 // launchers (each enqueues on `st`; return hipError_t)

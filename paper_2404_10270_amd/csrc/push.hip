@@ -266,7 +266,8 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
     float *__restrict__ VX = (float *)d.vx[cur];
     float *__restrict__ VY = (float *)d.vy[cur];
     float *__restrict__ VZ = (float *)d.vz[cur];
-    const unsigned long long *__restrict__ ID = d.id[cur];
+    const uint32_t *__restrict__ IDL = d.id_lo[cur];
+    const uint32_t *__restrict__ IDH = d.id_hi[cur];
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
     uint32_t wn = 0;  // this wave's candidates so far (uniform)
@@ -284,6 +285,7 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
     uint32_t key0 = 0, key1 = 0;
     unsigned long long T = 0;
     long long step = 0;
+    bool wide = false;  // some id of the segment's instance may be >= 2^32
     for (int64_t t = blockIdx.x; t < d.n_tiles; t += gridDim.x) {
         int64_t tile0, base, count;
         uint32_t flg;
@@ -304,7 +306,10 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
             key0 = sc.key0, key1 = sc.key1;
             T = sc.T;
             inst = sc.inst;
-            if (MCC) step = d.instd[inst].step;
+            if (MCC) {
+                step = d.instd[inst].step;
+                wide = d.instd[inst].wide_ids != 0u;
+            }
             cseg = seg;
         }
 
@@ -329,11 +334,13 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
             float *__restrict__ VXt = VX + tb;
             float *__restrict__ VYt = VY + tb;
             float *__restrict__ VZt = VZ + tb;
-            const unsigned long long *__restrict__ IDt = ID + tb;
+            const uint32_t *__restrict__ IDLt = IDL + tb;
+            const uint32_t *__restrict__ IDHt = IDH + tb;
             if (rem == (uint32_t)kTile) {
                 // a full tile: every load unconditional, so none is predicated
                 // and the wave issues all of them before its first wait
-                if (test) {
+                if (test && !wide) {
+                    // every id below 2^32: the low words are the ids
 #pragma unroll
                     for (int k = 0; k < NP; ++k) {
                         const uint32_t o = (uint32_t)((wave * kPer + r0 + k) * 64 + lane);
@@ -342,7 +349,19 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
                         vx[k] = stream_ld(&VXt[o]);
                         vy[k] = stream_ld(&VYt[o]);
                         vz[k] = stream_ld(&VZt[o]);
-                        pid[k] = stream_ld(&IDt[o]);
+                        pid[k] = stream_ld(&IDLt[o]);
+                    }
+                } else if (test) {
+#pragma unroll
+                    for (int k = 0; k < NP; ++k) {
+                        const uint32_t o = (uint32_t)((wave * kPer + r0 + k) * 64 + lane);
+                        j[k] = stream_ld(&CELLt[o]);
+                        f[k] = stream_ld(&Xt[o]);
+                        vx[k] = stream_ld(&VXt[o]);
+                        vy[k] = stream_ld(&VYt[o]);
+                        vz[k] = stream_ld(&VZt[o]);
+                        pid[k] = (unsigned long long)stream_ld(&IDLt[o]) |
+                                 ((unsigned long long)stream_ld(&IDHt[o]) << 32);
                     }
                 } else {
 #pragma unroll
@@ -369,7 +388,10 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
                         vx[k] = stream_ld(&VXt[o]);
                         vy[k] = stream_ld(&VYt[o]);
                         vz[k] = stream_ld(&VZt[o]);
-                        if (test) pid[k] = stream_ld(&IDt[o]);
+                        if (test) {
+                            pid[k] = stream_ld(&IDLt[o]);
+                            if (wide) pid[k] |= (unsigned long long)stream_ld(&IDHt[o]) << 32;
+                        }
                     }
                 }
             }
@@ -513,7 +535,8 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
     double *__restrict__ VX = (double *)d.vx[cur];
     double *__restrict__ VY = (double *)d.vy[cur];
     double *__restrict__ VZ = (double *)d.vz[cur];
-    const unsigned long long *__restrict__ ID = d.id[cur];
+    const uint32_t *__restrict__ IDL = d.id_lo[cur];
+    const uint32_t *__restrict__ IDH = d.id_hi[cur];
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
     uint32_t wn = 0;  // this wave's candidates so far (uniform)
@@ -530,6 +553,7 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
     unsigned long long T = 0;
     int inst = 0;
     long long step = 0;
+    bool wide = false;  // some id of the segment's instance may be >= 2^32
     for (int64_t t = blockIdx.x; t < d.n_tiles; t += gridDim.x) {
         int64_t tile0, base, count;
         uint32_t flg;
@@ -550,7 +574,10 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
             key0 = sc.key0, key1 = sc.key1;
             T = sc.T;
             inst = sc.inst;
-            if (MCC) step = d.instd[inst].step;
+            if (MCC) {
+                step = d.instd[inst].step;
+                wide = d.instd[inst].wide_ids != 0u;
+            }
             cseg = seg;
         }
         // the tile in kPer / NP passes of NP chunks per wave (NP = kPer: one pass)
@@ -567,10 +594,12 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
             double *__restrict__ VXt = VX + tb;
             double *__restrict__ VYt = VY + tb;
             double *__restrict__ VZt = VZ + tb;
-            const unsigned long long *__restrict__ IDt = ID + tb;
+            const uint32_t *__restrict__ IDLt = IDL + tb;
+            const uint32_t *__restrict__ IDHt = IDH + tb;
             if (rem == (uint32_t)kTile) {
                 // a full tile: every load unconditional (see the FP32 form)
-                if (test) {
+                if (test && !wide) {
+                    // every id below 2^32: the low words are the ids
 #pragma unroll
                     for (int k = 0; k < NP; ++k) {
                         const uint32_t o = (uint32_t)((wave * kPer + r0 + k) * 64 + lane);
@@ -578,7 +607,18 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
                         vx[k] = stream_ld(&VXt[o]);
                         vy[k] = stream_ld(&VYt[o]);
                         vz[k] = stream_ld(&VZt[o]);
-                        pid[k] = stream_ld(&IDt[o]);
+                        pid[k] = stream_ld(&IDLt[o]);
+                    }
+                } else if (test) {
+#pragma unroll
+                    for (int k = 0; k < NP; ++k) {
+                        const uint32_t o = (uint32_t)((wave * kPer + r0 + k) * 64 + lane);
+                        x[k] = stream_ld(&Xt[o]);
+                        vx[k] = stream_ld(&VXt[o]);
+                        vy[k] = stream_ld(&VYt[o]);
+                        vz[k] = stream_ld(&VZt[o]);
+                        pid[k] = (unsigned long long)stream_ld(&IDLt[o]) |
+                                 ((unsigned long long)stream_ld(&IDHt[o]) << 32);
                     }
                 } else {
 #pragma unroll
@@ -603,7 +643,10 @@ __global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
                         vx[k] = stream_ld(&VXt[o]);
                         vy[k] = stream_ld(&VYt[o]);
                         vz[k] = stream_ld(&VZt[o]);
-                        if (test) pid[k] = stream_ld(&IDt[o]);
+                        if (test) {
+                            pid[k] = stream_ld(&IDLt[o]);
+                            if (wide) pid[k] |= (unsigned long long)stream_ld(&IDHt[o]) << 32;
+                        }
                     }
                 }
             }

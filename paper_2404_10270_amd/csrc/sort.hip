@@ -344,7 +344,8 @@ __device__ __forceinline__ void move_fields(const Dev &d, int cur, int nxt, int6
         vy[k] = __builtin_nontemporal_load(&VY[g]);
         vz[k] = __builtin_nontemporal_load(&VZ[g]);
         if (CELL) c[k] = __builtin_nontemporal_load(&d.cell[cur][g]);
-        id[k] = __builtin_nontemporal_load(&d.id[cur][g]);
+        id[k] = (unsigned long long)__builtin_nontemporal_load(&d.id_lo[cur][g]) |
+                ((unsigned long long)__builtin_nontemporal_load(&d.id_hi[cur][g]) << 32);
     };
     if (full) {
         // every slot of a full tile exists: its loads go unpredicated (an
@@ -366,7 +367,7 @@ __device__ __forceinline__ void move_fields(const Dev &d, int cur, int nxt, int6
         VYn[t] = vy[k];
         VZn[t] = vz[k];
         if (CELL) d.cell[nxt][t] = c[k];
-        d.id[nxt][t] = id[k];
+        store_id(d, nxt, t, id[k]);
     }
 }
 

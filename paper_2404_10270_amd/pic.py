@@ -83,8 +83,8 @@ class pic_sizes(C.Structure):
 
 class pic_buffers(C.Structure):
     _fields_ = [("x", C.c_void_p * 2), ("cell", C.c_void_p * 2), ("vx", C.c_void_p * 2),
-                ("vy", C.c_void_p * 2), ("vz", C.c_void_p * 2), ("id", C.c_void_p * 2),
-                ("work", C.c_void_p)]
+                ("vy", C.c_void_p * 2), ("vz", C.c_void_p * 2), ("id_lo", C.c_void_p * 2),
+                ("id_hi", C.c_void_p * 2), ("work", C.c_void_p)]
 
 
 class pic_diag(C.Structure):
@@ -364,7 +364,9 @@ class PicSim:
         self.vx = [torch.zeros(n, dtype=fdt, device=dev) for _ in range(2)]
         self.vy = [torch.zeros(n, dtype=fdt, device=dev) for _ in range(2)]
         self.vz = [torch.zeros(n, dtype=fdt, device=dev) for _ in range(2)]
-        self.id = [torch.zeros(n, dtype=torch.int64, device=dev) for _ in range(2)]
+        # particle ids as two 32-bit words (int32 tensors holding the uint32 bits)
+        self.id_lo = [torch.zeros(n, dtype=torch.int32, device=dev) for _ in range(2)]
+        self.id_hi = [torch.zeros(n, dtype=torch.int32, device=dev) for _ in range(2)]
         # static_work: the context uses libpic's static workspace (pic_init_static)
         self.static_work = static_work
         self.work = None if static_work else torch.zeros(int(sizes.work_bytes), dtype=torch.uint8,
@@ -387,8 +389,10 @@ class PicSim:
                 self.vx[0][b:b + m] = torch.from_numpy(np.ascontiguousarray(s.vx, npdt))
                 self.vy[0][b:b + m] = torch.from_numpy(np.ascontiguousarray(s.vy, npdt))
                 self.vz[0][b:b + m] = torch.from_numpy(np.ascontiguousarray(s.vz, npdt))
-                self.id[0][b:b + m] = torch.from_numpy(
-                    np.ascontiguousarray(s.id, np.uint64).view(np.int64))
+                ids = np.ascontiguousarray(s.id, np.uint64)
+                self.id_lo[0][b:b + m] = torch.from_numpy(
+                    (ids & np.uint64(0xFFFFFFFF)).astype(np.uint32).view(np.int32))
+                self.id_hi[0][b:b + m] = torch.from_numpy((ids >> np.uint64(32)).astype(np.uint32).view(np.int32))
         bufs = pic_buffers()
         for b in range(2):
             bufs.x[b] = self.x[b].data_ptr()
@@ -396,7 +400,8 @@ class PicSim:
             bufs.vx[b] = self.vx[b].data_ptr()
             bufs.vy[b] = self.vy[b].data_ptr()
             bufs.vz[b] = self.vz[b].data_ptr()
-            bufs.id[b] = self.id[b].data_ptr()
+            bufs.id_lo[b] = self.id_lo[b].data_ptr()
+            bufs.id_hi[b] = self.id_hi[b].data_ptr()
         bufs.work = None if static_work else self.work.data_ptr()
         self.bufs = bufs
         self.stream = torch.cuda.current_stream()
@@ -498,6 +503,16 @@ class PicSim:
         off, n = pic_region(self.ctx, PIC_R_NODE_BASE)
         return self.work[off:off + 8 * n].view(torch.int64).cpu().numpy()
 
+    def _ids(self, buf: int, sl=slice(None)):
+        lo = self.id_lo[buf][sl].cpu().numpy().view(np.uint32).astype(np.uint64)
+        hi = self.id_hi[buf][sl].cpu().numpy().view(np.uint32).astype(np.uint64)
+        return lo | (hi << np.uint64(32))
+
+    def ids(self, buf: int, index=None):
+        """Numpy uint64 ids of buffer set `buf`: every slot, or the slots a
+        slice or an index tensor (on the device) selects."""
+        return self._ids(buf, slice(None) if index is None else index)
+
     def state(self, k: int, inst: int = 0, live_only: bool = True):
         """Numpy copy of species k of instance i from the current set: a dict
         with x (float64 position in cells), vx, vy, vz (float64), id (uint64)
@@ -512,7 +527,7 @@ class PicSim:
         vx = self.vx[cur][sl].cpu().numpy().astype(np.float64)
         vy = self.vy[cur][sl].cpu().numpy().astype(np.float64)
         vz = self.vz[cur][sl].cpu().numpy().astype(np.float64)
-        ids = self.id[cur][sl].cpu().numpy().view(np.uint64)
+        ids = self._ids(cur, sl)
         if self.precision == PIC_FP32:
             cell = self.cell[cur][sl].cpu().numpy()
             f = self.x[cur][sl].cpu().numpy()

@@ -131,7 +131,7 @@ def test_init_argument_errors_before_device_work(P):
     # misaligned buffers
     b = P.pic_buffers()
     for i in range(2):
-        b.x[i] = b.vx[i] = b.vy[i] = b.vz[i] = b.id[i] = b.cell[i] = 0x1000 + 8
+        b.x[i] = b.vx[i] = b.vy[i] = b.vz[i] = b.id_lo[i] = b.id_hi[i] = b.cell[i] = 0x1000 + 8
     b.work = 0x2000
     assert L.pic_init(arr, 1, C.byref(b), None, 0, C.byref(ctx)) == P.PIC_E_ARG
     assert ctx.value is None

@@ -370,7 +370,7 @@ def _sampled_slots(sim, k, idx):
     out = {"x": cell.astype(np.float64) + f.astype(np.float64), "cell": cell}
     for name in ("vx", "vy", "vz"):
         out[name] = getattr(sim, name)[0][ii].cpu().numpy().astype(np.float64)
-    out["id"] = sim.id[0][ii].cpu().numpy().view(np.uint64)
+    out["id"] = sim.ids(0, ii)
     return out
 
 
@@ -473,7 +473,7 @@ def test_full_size_batched_256_instances_drawn_sampled():
             x = sim.cell[0][ii].cpu().numpy().astype(np.float64) + sim.x[0][ii].cpu().numpy().astype(np.float64)
             ref = pin.to_fp32_form([o[k]], w.nc)[0]
             assert np.array_equal(x, ref.as_f64().x)
-            assert np.array_equal(sim.id[0][ii].cpu().numpy().view(np.uint64), o[k].id)
+            assert np.array_equal(sim.ids(0, ii), o[k].id)
         S_ref = oracle.init_deposit(w, inst=i, fp32_form=True)
         for k in range(2):
             assert np.array_equal(S[n_i][k], S_ref[k])
@@ -622,4 +622,42 @@ def test_bounded_8192_cells_full_shape():
         for f in ("vx", "vy", "vz"):
             err = np.abs(g[f][gi[ok]] - os_[f][ok]) / np.maximum(np.abs(os_[f][ok]), vth)
             assert np.max(err) <= 1e-5
+    sim.close()
+
+
+@pytest.mark.parametrize("case", ["uploaded", "created"])
+def test_ids_at_or_above_2_32(case):
+    """Particle ids are two 32-bit words; the movers read only the low words
+    while every id of the instance is below 2^32.  Ids of 2^32 and more --
+    uploaded ones (2^36 + i), or created ones once next_id passes 2^32 -- make
+    them read both words: 12 FP64 steps with collisions, pairs, source and
+    sorts give the oracle's counts, ids and positions."""
+    wl = pin.bounded_mcc(nc=256, ppc=40, seed=63)
+    wl.mcc.n_n *= 20
+    st = pin.initial_state(wl)
+    n = int(sum(s.n for s in st))
+    if case == "uploaded":
+        shift = np.uint64(1 << 36)
+        st = [pin.SpeciesState(x=s.x, vx=s.vx, vy=s.vy, vz=s.vz, id=s.id + shift) for s in st]
+        next_id = n + (1 << 36)
+    else:
+        next_id = (1 << 32) - 8
+    flush(f"ids at or above 2^32: {case}")
+    caps = pin.capacities(wl, st)
+    sim = P.PicSim(wl, st, FP64, capacities=caps, next_ids=[next_id])
+    orc = oracle.OracleSim(wl, st, caps=caps)
+    orc.sim.cnt.next_id = next_id
+    sim.step(12, sort_every=5)
+    orc.step(12)
+    d, rc = sim.diagnostics()
+    d = d[0]
+    c = orc.counters
+    assert rc == 0 and d.status == 0
+    assert d.next_id == c.next_id and d.next_id > 2 ** 32
+    assert d.n_candidates == c.n_candidates and d.n_ionize == c.n_ionize and c.n_ionize > 0
+    for k in range(2):
+        g, o = gpu_state(sim, k), oracle_state(orc, k)
+        assert np.array_equal(g["id"], o["id"])
+        assert np.max(np.abs(g["x"] - o["x"])) <= 1e-7
+        assert np.any(g["id"] >= np.uint64(2 ** 32))
     sim.close()
