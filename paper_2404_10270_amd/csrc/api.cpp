@@ -314,13 +314,13 @@ int plan(const pic_config *cfgs, int n_inst, Plan &p)
     // overflow list, whose appends contend on one counter, stays rare), then
     // an overflow list sized for the expected total (mean + 10 sigma).  The
     // persistent grid is one residency of the mover on 256 CUs: 4 blocks per
-    // CU in the FP32 form, 3 in the FP64 form (their register counts allow 4
-    // and 3 waves per SIMD).  A partial second residency leaves the mover's
-    // last blocks running alone, and fewer regions make the collide kernel (a
-    // block per region) and the event index over the regions cheaper.
-    // (pic_set_mover can run the movers on up to twice that grid: the layout
-    // holds regions for it, each sized for the default grid)
-    const int max_blocks = cfgs[0].precision == PIC_FP64 ? 256 * 3 : 256 * 4;
+    // CU (both movers fit 4 waves per SIMD: 128 VGPRs or fewer).  A partial
+    // second residency leaves the mover's last blocks running alone, and
+    // fewer regions make the collide kernel (a block per region) and the
+    // event index over the regions cheaper.  (pic_set_mover can run the
+    // movers on up to twice that grid: the layout holds regions for it, each
+    // sized for the default grid)
+    const int max_blocks = 256 * 4;
     p.n_push_blocks = (int)std::min<int64_t>(std::max<int64_t>(p.n_tiles, 1), max_blocks);
     p.n_regions = (int)std::min<int64_t>(std::max<int64_t>(p.n_tiles, 1), 2 * max_blocks);
     L.cand_ovf_cap = cand_capacity(cfgs, n_inst, P);

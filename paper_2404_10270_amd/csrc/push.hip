@@ -525,8 +525,11 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
 // FP64 form: double x in cells, double v; the same arithmetic as the FP64
 // reference, operation by operation (no contraction, explicit fma in the gather)
 // ---------------------------------------------------------------------------
+// (held to 128 VGPRs, four waves per SIMD, with a 1024-block grid: the
+// compiler spills one to three 4-byte values to scratch; at its free choice
+// of 146 VGPRs the mover ran three waves per SIMD and the step 1.7% slower)
 template <bool DEP, bool MCC, int NP, bool COLL>
-__global__ __launch_bounds__(kBlock) void push_f64_kernel(Dev d)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void push_f64_kernel(Dev d)
 {
     __shared__ PushLds L;
     push_lds_init(L, d, true);

@@ -11,7 +11,7 @@ so these cases force them from the host with the workload's shape:
   for electrons, 0.996 for ions), no ionisation, no source, and exactly as
   many particles as slots, 1.5 tiles per block of the persistent grid: the
   blocks that own two tiles get about 510 candidates per wave against parts
-  of 496 (FP64 form: 768 blocks) or 384 (FP32 form: 1,024 blocks);
+  of 384 (1,024 blocks in both forms);
 * ionisation events: the same dense gas with an ionisation cross section ten
   times the elastic one, so that a collide block meets about 250 ionisations
   against an event region of 84.
@@ -30,7 +30,7 @@ from gpu_common import FP32, FP64, P, build_pair, flush, gpu_state, oracle_state
 pytestmark = pytest.mark.gpu
 
 TILE = 1024                  # particles per mover tile
-GRID = {FP32: 1024, FP64: 768}  # persistent grid of the movers, blocks
+GRID = {FP32: 1024, FP64: 1024}  # persistent grid of the movers, blocks
 
 
 def _one_step(wl, prec, caps, fused):
