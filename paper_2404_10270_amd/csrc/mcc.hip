@@ -540,78 +540,107 @@ __device__ __forceinline__ void consume_atom(const Dev &d, int cur, bool f64, in
     atomicAdd(&d.instd[sn.inst].n_consumed, 1ull);
 }
 
-__global__ __launch_bounds__(kBlock) void emit_kernel(Dev d)
+// the pair of ionisation event e (rank: its rank among its instance's events
+// by parent id): the electron at in-segment index count + rank with id
+// next_id + 2 rank, the ion after it
+__device__ __forceinline__ void emit_ionisation(const Dev &d, int cur, bool f64, uint32_t e, const IzEvent &ev,
+                                                uint32_t rank)
 {
-    __shared__ EventIndex X;
-    get_event_index(X, d);
-    const int cur = d.glob->cur_set;
-    const bool f64 = (d.precision == PIC_FP64);
-    const uint32_t m_all = X.total;
-    const uint32_t stride = gridDim.x * kBlock;
-
-    // ---- ionisation pairs, at in-segment index count + rank and ids next_id + 2 rank
-    for (uint32_t e = blockIdx.x * kBlock + threadIdx.x; e < m_all; e += stride) {
-        const IzEvent ev = event_at(X, d, e);
-        const uint32_t rank = d.ev_rank[e];
-        {
-            const SegConst &se = d.segc[ev.seg];
-            const int seg_i = se.partner;
-            const SegConst &si = d.segc[seg_i];
-            const InstDyn &idn = d.instd[ev.inst];
-            const long long step = idn.step;
-            const unsigned long long nid = idn.next_id + 2ull * rank;
-            // everything the placements read, before their first store
-            const PlaceSeg pe = place_seg(d, ev.seg), pi = place_seg(d, seg_i);
-            const double sig_n = si.sig_n;
-            const int seg_n = d.instc[ev.inst].seg_n;
-            // position of the parent (unchanged by the collision)
-            int32_t cell = 0;
-            float f = 0.f;
-            double x = 0.0;
-            if (f64) x = ((const double *)d.x[cur])[ev.slot];
-            else {
-                cell = d.cell[cur][ev.slot];
-                f = ((const float *)d.x[cur])[ev.slot];
+    const SegConst &se = d.segc[ev.seg];
+    const int seg_i = se.partner;
+    const SegConst &si = d.segc[seg_i];
+    const InstDyn &idn = d.instd[ev.inst];
+    const long long step = idn.step;
+    const unsigned long long nid = idn.next_id + 2ull * rank;
+    // everything the placements read, before their first store
+    const PlaceSeg pe = place_seg(d, ev.seg), pi = place_seg(d, seg_i);
+    const double sig_n = si.sig_n;
+    const int seg_n = d.instc[ev.inst].seg_n;
+    // position of the parent (unchanged by the collision)
+    int32_t cell = 0;
+    float f = 0.f;
+    double x = 0.0;
+    if (f64) x = ((const double *)d.x[cur])[ev.slot];
+    else {
+        cell = d.cell[cur][ev.slot];
+        f = ((const float *)d.x[cur])[ev.slot];
+    }
+    const uint4 u1 = draw(ev.parent_id, step, 1, se.key0, se.key1);
+    const uint4 u2 = draw(ev.parent_id, step, 2, se.key0, se.key1);
+    double d0, d1, d2;
+    iso_dir(u1.z, u1.w, d0, d1, d2);
+    double n0, n1, n2, n3;
+    box_muller(u2.x, u2.y, n0, n1);
+    box_muller(u2.z, u2.w, n2, n3);
+    place(d, cur, f64, pe, (int64_t)pe.count + rank, nid, cell, f, x,
+          ev.g2 * d0, ev.g2 * d1, ev.g2 * d2);
+    // the ion: Maxwellian at the parent, or the consumed atom itself
+    double ivx = sig_n * n0, ivy = sig_n * n1, ivz = sig_n * n2;
+    if (seg_n >= 0) {
+        const long long t = d.ev_target[e];
+        if (t >= 0) {
+            if (f64) {
+                x = ((const double *)d.x[cur])[t];
+                ivx = ((const double *)d.vx[cur])[t];
+                ivy = ((const double *)d.vy[cur])[t];
+                ivz = ((const double *)d.vz[cur])[t];
+            } else {
+                cell = d.cell[cur][t];
+                f = ((const float *)d.x[cur])[t];
+                ivx = (double)((const float *)d.vx[cur])[t];
+                ivy = (double)((const float *)d.vy[cur])[t];
+                ivz = (double)((const float *)d.vz[cur])[t];
             }
-            const uint4 u1 = draw(ev.parent_id, step, 1, se.key0, se.key1);
-            const uint4 u2 = draw(ev.parent_id, step, 2, se.key0, se.key1);
-            double d0, d1, d2;
-            iso_dir(u1.z, u1.w, d0, d1, d2);
-            double n0, n1, n2, n3;
-            box_muller(u2.x, u2.y, n0, n1);
-            box_muller(u2.z, u2.w, n2, n3);
-            place(d, cur, f64, pe, (int64_t)pe.count + rank, nid, cell, f, x,
-                  ev.g2 * d0, ev.g2 * d1, ev.g2 * d2);
-            // the ion: Maxwellian at the parent, or the consumed atom itself
-            double ivx = sig_n * n0, ivy = sig_n * n1, ivz = sig_n * n2;
-            if (seg_n >= 0) {
-                const long long t = d.ev_target[e];
-                if (t >= 0) {
-                    if (f64) {
-                        x = ((const double *)d.x[cur])[t];
-                        ivx = ((const double *)d.vx[cur])[t];
-                        ivy = ((const double *)d.vy[cur])[t];
-                        ivz = ((const double *)d.vz[cur])[t];
-                    } else {
-                        cell = d.cell[cur][t];
-                        f = ((const float *)d.x[cur])[t];
-                        ivx = (double)((const float *)d.vx[cur])[t];
-                        ivy = (double)((const float *)d.vy[cur])[t];
-                        ivz = (double)((const float *)d.vz[cur])[t];
-                    }
-                    consume_atom(d, cur, f64, seg_n, t);
-                } else {
-                    atomicAdd(&d.instd[ev.inst].n_iz_untargeted, 1ull);
-                }
-            }
-            place(d, cur, f64, pi, (int64_t)pi.count + rank, nid + 1ull, cell, f, x, ivx, ivy, ivz);
+            consume_atom(d, cur, f64, seg_n, t);
+        } else {
+            atomicAdd(&d.instd[ev.inst].n_iz_untargeted, 1ull);
         }
     }
+    place(d, cur, f64, pi, (int64_t)pi.count + rank, nid + 1ull, cell, f, x, ivx, ivy, ivz);
+}
 
-    // ---- source pairs: instance i creates as many pairs as ions it lost this step
-    __shared__ uint32_t s_pre[kMaxInstLds + 1];
-    __shared__ uint32_t s_m[kMaxInstLds];
-    const int n_inst = d.n_inst < kMaxInstLds ? d.n_inst : kMaxInstLds;
+// source pair k of instance i (m_i: the instance's ionisation events this
+// step, whose pairs take the ids and slots before the source pairs')
+__device__ __forceinline__ void emit_source_pair(const Dev &d, int cur, bool f64, int i, uint32_t k, uint32_t m_i)
+{
+    const InstConst &ic = d.instc[i];
+    const InstDyn &idn = d.instd[i];
+    const SegConst &se = d.segc[ic.seg_e];
+    const SegConst &si = d.segc[ic.seg_i];
+    const long long step = idn.step;
+    const uint4 b0 = draw_source(k, step, 0, se.key0, se.key1);
+    const uint4 b1 = draw_source(k, step, 1, se.key0, se.key1);
+    const uint4 b2 = draw_source(k, step, 2, se.key0, se.key1);
+    const double x = u01(b0.x) * (double)ic.nc;
+    double e0, e1, e2, e3, i0, i1, i2, i3;
+    box_muller(b0.y, b0.z, e0, e1);
+    box_muller(b1.x, b1.y, e2, e3);
+    box_muller(b1.z, b1.w, i0, i1);
+    box_muller(b2.x, b2.y, i2, i3);
+    int32_t cell = 0;
+    float f = 0.f;
+    if (!f64) split_position(x, ic.nc, cell, f);
+    const unsigned long long nid = idn.next_id + 2ull * (m_i + k);
+    // everything the placements read, before their first store
+    const PlaceSeg pe = place_seg(d, ic.seg_e), pi = place_seg(d, ic.seg_i);
+    const double se_src = se.sig_src, si_src = si.sig_src;
+    place(d, cur, f64, pe, (int64_t)pe.count + m_i + k, nid, cell, f, x, se_src * e0, se_src * e1,
+          se_src * e2);
+    place(d, cur, f64, pi, (int64_t)pi.count + m_i + k, nid + 1ull, cell, f, x, si_src * i0,
+          si_src * i1, si_src * i2);
+}
+
+// the source pairs of every instance (all threads of every block; barriers
+// inside): instance i creates as many pairs as ions it lost this step, from
+// the last blocks down, so that they run beside the ionisation pairs (from
+// the first blocks up), not after them.  MAXI: instances held in LDS.
+template <int MAXI>
+__device__ void emit_sources(const Dev &d, const EventIndex &X, int cur, bool f64)
+{
+    __shared__ uint32_t s_pre[MAXI + 1];
+    __shared__ uint32_t s_m[MAXI];
+    const uint32_t stride = gridDim.x * kBlock;
+    const int n_inst = d.n_inst < MAXI ? d.n_inst : MAXI;
     __syncthreads();
     count_events(X, d, s_m, n_inst);
     {
@@ -652,35 +681,165 @@ __global__ __launch_bounds__(kBlock) void emit_kernel(Dev d)
             const int mid = (lo + hi + 1) >> 1;
             if (s_pre[mid] <= q) lo = mid; else hi = mid - 1;
         }
-        const int i = lo;
-        const uint32_t k = q - s_pre[i];
-        const InstConst &ic = d.instc[i];
-        const InstDyn &idn = d.instd[i];
-        const SegConst &se = d.segc[ic.seg_e];
-        const SegConst &si = d.segc[ic.seg_i];
-        const long long step = idn.step;
-        const uint32_t m_i = s_m[i];
-        const uint4 b0 = draw_source(k, step, 0, se.key0, se.key1);
-        const uint4 b1 = draw_source(k, step, 1, se.key0, se.key1);
-        const uint4 b2 = draw_source(k, step, 2, se.key0, se.key1);
-        const double x = u01(b0.x) * (double)ic.nc;
-        double e0, e1, e2, e3, i0, i1, i2, i3;
-        box_muller(b0.y, b0.z, e0, e1);
-        box_muller(b1.x, b1.y, e2, e3);
-        box_muller(b1.z, b1.w, i0, i1);
-        box_muller(b2.x, b2.y, i2, i3);
-        int32_t cell = 0;
-        float f = 0.f;
-        if (!f64) split_position(x, ic.nc, cell, f);
-        const unsigned long long nid = idn.next_id + 2ull * (m_i + k);
-        // everything the placements read, before their first store
-        const PlaceSeg pe = place_seg(d, ic.seg_e), pi = place_seg(d, ic.seg_i);
-        const double se_src = se.sig_src, si_src = si.sig_src;
-        place(d, cur, f64, pe, (int64_t)pe.count + m_i + k, nid, cell, f, x, se_src * e0, se_src * e1,
-              se_src * e2);
-        place(d, cur, f64, pi, (int64_t)pi.count + m_i + k, nid + 1ull, cell, f, x, si_src * i0,
-              si_src * i1, si_src * i2);
+        emit_source_pair(d, cur, f64, lo, q - s_pre[lo], s_m[lo]);
     }
+}
+
+__global__ __launch_bounds__(kBlock) void emit_kernel(Dev d)
+{
+    __shared__ EventIndex X;
+    get_event_index(X, d);
+    const int cur = d.glob->cur_set;
+    const bool f64 = (d.precision == PIC_FP64);
+    const uint32_t m_all = X.total;
+    const uint32_t stride = gridDim.x * kBlock;
+    // ionisation pairs, ranked by the rank kernels
+    for (uint32_t e = blockIdx.x * kBlock + threadIdx.x; e < m_all; e += stride)
+        emit_ionisation(d, cur, f64, e, event_at(X, d, e), d.ev_rank[e]);
+    emit_sources<kMaxInstLds>(d, X, cur, f64);
+}
+
+// A single instance without kinetic neutrals: the rank of each ionisation
+// event among the step's events by parent id taken here, so that no rank
+// kernel runs.  Block b takes the events of group g = b (+ k grid) of 64:
+// wave 0 first reads and draws everything its 64 pairs need except the rank
+// (those loads then run beside the ranking), every wave compares the group's
+// 64 parent ids (one per lane) against a quarter of all parent ids, staged
+// in LDS in chunks, the four partial ranks are summed in LDS and wave 0
+// places the 64 pairs.
+constexpr int kRankChunk = 4096;  // parent ids per LDS chunk
+
+// what placing an ionisation pair needs besides its rank (no kinetic neutrals)
+struct IzPair {
+    PlaceSeg pe, pi;
+    unsigned long long next_id;
+    int32_t cell;
+    float f;
+    double x;
+    double ev[3], iv[3];  // velocities of the new electron and ion
+};
+
+__device__ __forceinline__ IzPair prepare_pair(const Dev &d, int cur, bool f64, const IzEvent &ev)
+{
+    IzPair q;
+    const SegConst &se = d.segc[ev.seg];
+    const int seg_i = se.partner;
+    const SegConst &si = d.segc[seg_i];
+    const InstDyn &idn = d.instd[ev.inst];
+    const long long step = idn.step;
+    q.next_id = idn.next_id;
+    q.pe = place_seg(d, ev.seg);
+    q.pi = place_seg(d, seg_i);
+    const double sig_n = si.sig_n;
+    q.cell = 0;
+    q.f = 0.f;
+    q.x = 0.0;
+    if (f64) q.x = ((const double *)d.x[cur])[ev.slot];
+    else {
+        q.cell = d.cell[cur][ev.slot];
+        q.f = ((const float *)d.x[cur])[ev.slot];
+    }
+    const uint4 u1 = draw(ev.parent_id, step, 1, se.key0, se.key1);
+    const uint4 u2 = draw(ev.parent_id, step, 2, se.key0, se.key1);
+    double d0, d1, d2;
+    iso_dir(u1.z, u1.w, d0, d1, d2);
+    double n0, n1, n2, n3;
+    box_muller(u2.x, u2.y, n0, n1);
+    box_muller(u2.z, u2.w, n2, n3);
+    q.ev[0] = ev.g2 * d0;
+    q.ev[1] = ev.g2 * d1;
+    q.ev[2] = ev.g2 * d2;
+    q.iv[0] = sig_n * n0;
+    q.iv[1] = sig_n * n1;
+    q.iv[2] = sig_n * n2;
+    return q;
+}
+
+// every parent id of the step into s_pid[0, total) (total <= kRankChunk), by
+// region rather than by event: thread t takes regions t, t + kBlock, ... and
+// loads up to kStageK events of each before its first wait (a region rarely
+// holds more; the rest, and the overflow list, follow in plain loops)
+constexpr int kStageK = 4;
+
+__device__ __forceinline__ void stage_pids(const EventIndex &X, const Dev &d, unsigned long long *s_pid)
+{
+    constexpr int kRegT = (kMaxPushBlocks + kBlock - 1) / kBlock;
+    const int nb = d.n_push_blocks;
+    unsigned long long v[kRegT][kStageK];
+    uint32_t dst[kRegT], n[kRegT];
+#pragma unroll
+    for (int r = 0; r < kRegT; ++r) {
+        const int b = threadIdx.x + r * kBlock;
+        const bool ok = b < nb;
+        dst[r] = ok ? X.pre[b] : 0u;
+        n[r] = ok ? X.pre[b + 1] - X.pre[b] : 0u;
+#pragma unroll
+        for (int k = 0; k < kStageK; ++k)
+            v[r][k] = ((uint32_t)k < n[r]) ? d.ev[(int64_t)b * d.ev_q + k].parent_id : 0ull;
+    }
+#pragma unroll
+    for (int r = 0; r < kRegT; ++r) {
+#pragma unroll
+        for (int k = 0; k < kStageK; ++k)
+            if ((uint32_t)k < n[r]) s_pid[dst[r] + k] = v[r][k];
+        const int b = threadIdx.x + r * kBlock;
+        for (uint32_t k = kStageK; k < n[r]; ++k) s_pid[dst[r] + k] = d.ev[(int64_t)b * d.ev_q + k].parent_id;
+    }
+    for (uint32_t e = X.in_regions + threadIdx.x; e < X.total; e += kBlock)
+        s_pid[e] = d.ev[(int64_t)d.n_regions * d.ev_q + (e - X.in_regions)].parent_id;
+}
+
+__global__ __launch_bounds__(kBlock) void emit_ranked_kernel(Dev d)
+{
+    __shared__ EventIndex X;
+    __shared__ unsigned long long s_pid[kRankChunk];
+    __shared__ uint32_t s_part[kWaves][64];
+    const uint32_t n_src = source_pairs(d, 0);  // read first: in flight beside the index
+    build_event_index(X, d);
+    const int cur = d.glob->cur_set;
+    const bool f64 = (d.precision == PIC_FP64);
+    const uint32_t m = X.total;
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    const uint32_t n_groups = (m + 63u) / 64u;
+    for (uint32_t g = blockIdx.x; g < n_groups; g += gridDim.x) {  // block-uniform
+        const uint32_t e = g * 64u + (uint32_t)lane;
+        const bool mine = e < m;
+        IzEvent ev = {};
+        if (mine) ev = event_at(X, d, e);
+        IzPair q = {};
+        if (wave == 0 && mine) q = prepare_pair(d, cur, f64, ev);
+        uint32_t r = 0;
+        for (uint32_t c0 = 0; c0 < m; c0 += kRankChunk) {
+            const uint32_t cn = min((uint32_t)kRankChunk, m - c0);
+            __syncthreads();  // the previous chunk's readers are done
+            if (m <= (uint32_t)kRankChunk) stage_pids(X, d, s_pid);
+            else
+                for (uint32_t i = threadIdx.x; i < cn; i += kBlock) s_pid[i] = event_at(X, d, c0 + i).parent_id;
+            __syncthreads();
+            const uint32_t q0 = (uint32_t)wave * cn / kWaves, q1 = (uint32_t)(wave + 1) * cn / kWaves;
+            if (mine) {
+                const unsigned long long pid = ev.parent_id;
+#pragma unroll 8
+                for (uint32_t k = q0; k < q1; ++k) r += s_pid[k] < pid ? 1u : 0u;
+            }
+        }
+        s_part[wave][lane] = r;
+        __syncthreads();
+        if (wave == 0 && mine) {
+            uint32_t rank = 0;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) rank += s_part[w][lane];
+            const unsigned long long nid = q.next_id + 2ull * rank;
+            place(d, cur, f64, q.pe, (int64_t)q.pe.count + rank, nid, q.cell, q.f, q.x, q.ev[0], q.ev[1], q.ev[2]);
+            place(d, cur, f64, q.pi, (int64_t)q.pi.count + rank, nid + 1ull, q.cell, q.f, q.x, q.iv[0], q.iv[1],
+                  q.iv[2]);
+        }
+        __syncthreads();  // s_part is free for the next group
+    }
+    // the source pairs, from the last blocks down
+    const uint32_t sb = gridDim.x - 1 - blockIdx.x;
+    for (uint32_t k = sb * kBlock + threadIdx.x; k < n_src; k += gridDim.x * kBlock)
+        emit_source_pair(d, cur, f64, 0, k, m);
 }
 
 // close of the step (one block, all threads): counts, ids, wall-loss
@@ -778,6 +937,14 @@ hipError_t launch_emit(const Dev &d, hipStream_t st, bool pairs, bool events)
         hipLaunchKernelGGL(index_kernel, dim3(1), dim3(kBlock), 0, st, d);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
+    }
+    if (events && d.n_inst == 1 && !d.kinetic_any && pairs) {
+        // ranks inside the emit kernel
+        hipLaunchKernelGGL(emit_ranked_kernel, dim3(kEmitRankedBlocks), dim3(kBlock), 0, st, d);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(close_step_kernel, dim3(1), dim3(kBlock), 0, st, d, 1);
+        return hipGetLastError();
     }
     if (events) {
         hipError_t e;

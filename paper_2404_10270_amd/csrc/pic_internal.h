@@ -22,6 +22,7 @@ constexpr int kSortR = 8;                   // bins per thread in the sort scan
 constexpr int kSortTile = kBlock * kSortR;
 constexpr int kDiagBlocks = 1024;           // blocks of the diagnostics reduction
 constexpr int kEmitBlocks = 64;             // blocks of the emit/close-of-step kernel
+constexpr int kEmitRankedBlocks = 512;      // blocks of the emit kernel that ranks its events (64 per block)
 constexpr int kDiagVals = 6;                // live, sum v2, sum vx, vy, vz, (pad)
 constexpr int kMaxPushBlocks = 256 * 8;     // candidate regions, and the largest grid of the particle kernels
 constexpr int kCandQMin = 1024;             // least candidate entries per push block region
