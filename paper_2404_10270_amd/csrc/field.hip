@@ -12,13 +12,17 @@
 //   backward  phi_u = (u/(u+1)) phi_{u+1} + d'_u,
 // so each sweep is evaluated as a scan over affine maps y -> A y + B: every
 // thread composes kFieldR consecutive maps and the block scans the thread
-// maps.  Tiles chain through three launches, with no atomics and no waiting
-// between blocks:
-//   1. rho, and the composite of each tile's forward maps;
-//   2. the composites of the tiles below give the value entering the tile;
-//      forward sweep (d'), and the composite of the tile's backward maps;
-//   3. the composites of the tiles above give phi entering the tile from the
-//      top; backward sweep (phi), then E, the accelerations, the field energy.
+// maps.  A tile's backward composite depends on the d' entering it from
+// below only linearly (d' = d'(0) + h y, with d'(0) the sweep entering with
+// 0 and h the sweep of 1 with no sources), so both sweeps need a single
+// exchange between tiles and the solve takes two launches, with no atomics
+// and no waiting between blocks:
+//   1. rho; each tile's forward composite and its backward composite as a
+//      function of the d' entering it;
+//   2. every block scans the tiles' composites of its instance: the d'
+//      entering its tile from below and the phi entering it from above; then
+//      the tile's forward sweep (d'), backward sweep (phi), E, the
+//      accelerations and the field energy.
 // Same recurrences as the sequential sweep, regrouped; only the rounding
 // order differs.
 //
@@ -44,6 +48,20 @@ __device__ __forceinline__ Aff compose(Aff second, Aff first)
     Aff r;
     r.A = second.A * first.A;
     r.B = second.A * first.B + second.B;
+    return r;
+}
+
+// a backward map whose constant is B0 + B1 y for the d' y entering the tile
+struct Aff3 {
+    double A, B0, B1;
+};
+
+__device__ __forceinline__ Aff3 compose3(Aff3 second, Aff3 first)
+{
+    Aff3 r;
+    r.A = second.A * first.A;
+    r.B0 = second.A * first.B0 + second.B0;
+    r.B1 = second.A * first.B1 + second.B1;
     return r;
 }
 
@@ -80,38 +98,6 @@ __device__ Aff block_exclusive_scan(Aff m, Aff *agg)
     *agg = total;
     __syncthreads();
     return compose(excl, wpre);
-}
-
-// Composite of n maps taken in application order a = 0..n-1, where map a is
-// agg[idx(a)]: every thread composes a contiguous run, then an ordered tree
-// over the block.  Returns the composite in every thread.
-template <class Idx>
-__device__ Aff compose_ordered(const AffineStatus *agg, int64_t n, Idx idx)
-{
-    __shared__ Aff s_m[kWaves];
-    const int64_t per = (n + kBlock - 1) / kBlock;
-    const int64_t a0 = (int64_t)threadIdx.x * per;
-    Aff m = {1.0, 0.0};
-    for (int64_t a = a0; a < a0 + per && a < n; ++a) {
-        const AffineStatus &s = agg[idx(a)];
-        m = compose(Aff{s.A, s.B}, m);
-    }
-    // the tree's levels inside a wave through shuffles (the same pairs in the
-    // same order as a tree over LDS, without a barrier per level), then the
-    // four wave composites
-    const int lane = lane_id();
-    const int wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int s = 1; s < 64; s <<= 1) {
-        const Aff o = {__shfl_down(m.A, s, 64), __shfl_down(m.B, s, 64)};
-        if ((lane & (2 * s - 1)) == 0) m = compose(o, m);
-    }
-    static_assert(kWaves == 4, "the cross-wave levels below are written for four waves");
-    if (lane == 0) s_m[wave] = m;
-    __syncthreads();
-    const Aff r = compose(compose(s_m[3], s_m[2]), compose(s_m[1], s_m[0]));
-    __syncthreads();
-    return r;
 }
 
 // -g_u = u/(u+1): the multiplier of both sweeps at node u
@@ -186,13 +172,16 @@ __global__ __launch_bounds__(kBlock) void field_rho_kernel(Dev d, int mode)
         return Sj;
     };
     Aff m = {1.0, 0.0};
+    double dv[kFieldR];  // d_j = -rho_j K of the thread's interior nodes
 #pragma unroll
     for (int r = 0; r < kFieldR; ++r) {
         const int64_t j = j0 + r;
+        dv[r] = 0.0;
         if (j > nc) continue;
         if (from_rho) {
             if (j >= 1 && j <= nc - 1) {
                 const double dd = -(d.rho[gnode + j] * K);
+                dv[r] = dd;
                 const double gq = gq_of(j);
                 m = compose(Aff{gq, -(gq * dd)}, m);
             }
@@ -226,6 +215,7 @@ __global__ __launch_bounds__(kBlock) void field_rho_kernel(Dev d, int mode)
         if (mode == kRhoNoSolve) continue;
         if (j >= 1 && j <= nc - 1) {
             const double dd = -(rho * K);
+            dv[r] = dd;
             const double gq = gq_of(j);
             m = compose(Aff{gq, -(gq * dd)}, m);
         }
@@ -247,93 +237,205 @@ __global__ __launch_bounds__(kBlock) void field_rho_kernel(Dev d, int mode)
         return;
     }
     Aff agg;
-    (void)block_exclusive_scan(m, &agg);
+    const Aff excl = block_exclusive_scan(m, &agg);
     if (threadIdx.x == 0) {
         d.fwd_status[vt].A = agg.A;
         d.fwd_status[vt].B = agg.B;
     }
-}
-
-// ---------------------------------------------------------------------------
-// 2. forward sweep (d') and the backward composite of every tile
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void field_fwd_kernel(Dev d)
-{
-    const int64_t vt = blockIdx.x;
-    const int inst = seg_of_tile(d.inst_ftile0, d.n_inst, vt);
-    const InstConst &ic = d.instc[inst];
-    const int64_t lt = vt - ic.ftile0;
-    const int nc = ic.nc;
-
-    // the thread's rho, loaded before the first wait (unpredicated: a node
-    // past nc reads node nc and is not used)
-    const int64_t j0 = lt * kFieldTile + (int64_t)threadIdx.x * kFieldR;
-    double rl[kFieldR];
-#pragma unroll
-    for (int r = 0; r < kFieldR; ++r) rl[r] = d.rho[ic.gnode + min(j0 + r, (int64_t)nc)];
-
-    // d' entering the tile: the composites of the tiles below applied to d'_0 = 0
-    const int64_t first = ic.ftile0;
-    const Aff below = compose_ordered(d.fwd_status, lt, [first](int64_t a) { return first + a; });
-
-    double dv[kFieldR];
-    Aff m = {1.0, 0.0};
+    // the forward sweep inside the tile entering with 0 (d0: the tile's own
+    // sources) and entering with 1 without sources (h): d' = d0 + h y
+    double d0[kFieldR], h[kFieldR];
+    double y0 = excl.B, y1 = excl.A;
 #pragma unroll
     for (int r = 0; r < kFieldR; ++r) {
         const int64_t j = j0 + r;
-        dv[r] = 0.0;
-        if (j >= 1 && j <= nc - 1) {
-            dv[r] = -(rl[r] * ic.K);
-            const double gq = gq_of(j);
-            m = compose(Aff{gq, -(gq * dv[r])}, m);
-        }
-    }
-    Aff agg;
-    const Aff excl = block_exclusive_scan(m, &agg);
-    double y = excl.A * below.B + excl.B;
-    double dp[kFieldR];
-#pragma unroll
-    for (int r = 0; r < kFieldR; ++r) {
-        const int64_t j = j0 + r;
-        dp[r] = 0.0;
+        d0[r] = h[r] = 0.0;
         if (j >= 1 && j <= nc - 1) {
             const double gq = gq_of(j);
-            y = gq * y + (-(gq * dv[r]));
-            d.dprime[ic.gnode + j] = y;
-            dp[r] = y;
+            y0 = gq * y0 + (-(gq * dv[r]));
+            y1 = gq * y1;
+            d0[r] = y0;
+            h[r] = y1;
         }
     }
-    // backward maps phi_u = (u/(u+1)) phi_{u+1} + d'_u of the thread's nodes, top first
-    Aff mb = {1.0, 0.0};
+    // backward maps phi_u = (u/(u+1)) phi_{u+1} + d'_u of the thread's nodes,
+    // top first, with the constant split as d'
+    Aff3 mb = {1.0, 0.0, 0.0};
 #pragma unroll
     for (int r = kFieldR - 1; r >= 0; --r) {
         const int64_t j = j0 + r;
-        if (j >= 1 && j <= nc - 1) mb = compose(Aff{gq_of(j), dp[r]}, mb);
+        if (j >= 1 && j <= nc - 1) mb = compose3(Aff3{gq_of(j), d0[r], h[r]}, mb);
     }
     // the block's composite: threads from the top down, i.e. an ordered tree
     // over i = kBlock - 1 - thread.  Inside a wave index i is lane 63 - l of
-    // group 3 - wave, so each level takes the lane s below (the same pairs in
-    // the same order as the tree over LDS, without a barrier per level).
+    // group 3 - wave, so each level takes the lane s below.
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
 #pragma unroll
     for (int s = 1; s < 64; s <<= 1) {
-        const Aff o = shfl_up_aff(mb, s);
-        if (((63 - lane) & (2 * s - 1)) == 0) mb = compose(o, mb);
+        Aff3 o;
+        o.A = __shfl_up(mb.A, s, 64);
+        o.B0 = __shfl_up(mb.B0, s, 64);
+        o.B1 = __shfl_up(mb.B1, s, 64);
+        if (((63 - lane) & (2 * s - 1)) == 0) mb = compose3(o, mb);
     }
     static_assert(kWaves == 4, "the cross-wave levels below are written for four waves");
-    __shared__ Aff s_b[kWaves];
+    __shared__ Aff3 s_b[kWaves];
     if (lane == 63) s_b[wave] = mb;  // the composite of group 3 - wave
     __syncthreads();
     if (threadIdx.x == 0) {
-        const Aff r = compose(compose(s_b[0], s_b[1]), compose(s_b[2], s_b[3]));
+        const Aff3 r = compose3(compose3(s_b[0], s_b[1]), compose3(s_b[2], s_b[3]));
         d.bwd_status[vt].A = r.A;
-        d.bwd_status[vt].B = r.B;
+        d.bwd_status[vt].B0 = r.B0;
+        d.bwd_status[vt].B1 = r.B1;
     }
 }
 
+// The values entering tile lt of an instance (ntl tiles from tile `first`):
+// y_in, the d' entering it from below; phi_above, the phi entering it from
+// above (the backward composites of the tiles above, top first, applied to
+// phi_nc = 0, each with the d' entering that tile); dp_top, the d' leaving
+// the last tile (at node nc - 1).  Every thread takes a run of consecutive
+// tiles: a block scan of the runs' forward composites gives the d' entering
+// each run, a second one, over the runs from the top, the backward
+// composites above each run.  Runs of up to kRunR tiles (instances of up to
+// kRunR x kBlock tiles) are read into registers before the first wait.  All
+// threads; barriers inside.
+constexpr int kRunR = 4;
+
+template <int R>
+__device__ void tile_level_r(const Dev &d, int64_t first, int64_t ntl, int64_t lt, double &y_in,
+                             double &phi_above, double &dp_top)
+{
+    __shared__ double s_y[kBlock];  // d' entering each run
+    __shared__ double s_out[2];
+    const int64_t per = (ntl + kBlock - 1) / kBlock;
+    const int64_t n_runs = (ntl + per - 1) / per;
+    // thread t: forward run t, backward run n_runs - 1 - t (runs of `per` tiles)
+    const int64_t a0 = (int64_t)threadIdx.x * per;
+    const int64_t a1 = min(a0 + per, ntl);
+    const int64_t q = n_runs - 1 - (int64_t)threadIdx.x;
+    const int64_t b0 = q >= 0 ? q * per : 0;
+    const int64_t b1 = q >= 0 ? min(b0 + per, ntl) : 0;
+    const AffineStatus one = {1.0, 0.0};
+    const BackStatus bone = {1.0, 0.0, 0.0};
+    AffineStatus F[R], FB[R];
+    BackStatus B[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        F[i] = (a0 + i < a1) ? d.fwd_status[first + a0 + i] : one;
+        FB[i] = (b0 + i < b1) ? d.fwd_status[first + b0 + i] : one;
+        B[i] = (b0 + i < b1) ? d.bwd_status[first + b0 + i] : bone;
+    }
+    // forward
+    Aff m = {1.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+        if (a0 + i < a1) m = compose(Aff{F[i].A, F[i].B}, m);
+    Aff agg;
+    const Aff ex = block_exclusive_scan(m, &agg);
+    s_y[threadIdx.x] = ex.B;  // applied to d'_0 = 0
+    if (a0 <= lt && lt < a1) {
+        double y = ex.B;
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+            if (a0 + i < lt) y = F[i].A * y + F[i].B;
+        s_out[0] = y;
+    }
+    __syncthreads();
+    // backward: each tile's map with the d' entering it, from the top down
+    Aff bk[R];
+    {
+        double y = q >= 0 ? s_y[q] : 0.0;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            bk[i] = Aff{B[i].A, B[i].B0 + B[i].B1 * y};
+            y = FB[i].A * y + FB[i].B;
+        }
+    }
+    Aff mb = {1.0, 0.0};
+#pragma unroll
+    for (int i = R - 1; i >= 0; --i)
+        if (b0 + i < b1) mb = compose(bk[i], mb);
+    Aff aggb;
+    const Aff exb = block_exclusive_scan(mb, &aggb);
+    if (q >= 0 && b0 <= lt && lt < b1) {
+        Aff M = exb;
+#pragma unroll
+        for (int i = R - 1; i >= 0; --i)
+            if (b0 + i < b1 && b0 + i > lt) M = compose(bk[i], M);
+        s_out[1] = M.B;
+    }
+    __syncthreads();
+    y_in = s_out[0];
+    phi_above = s_out[1];
+    dp_top = agg.B;
+}
+
+// the same for runs of any length, read tile by tile
+__device__ void tile_level_any(const Dev &d, int64_t first, int64_t ntl, int64_t lt, double &y_in,
+                               double &phi_above, double &dp_top)
+{
+    __shared__ double s_y[kBlock];  // d' entering each run
+    __shared__ double s_out[2];
+    const int64_t per = (ntl + kBlock - 1) / kBlock;
+    const int64_t n_runs = (ntl + per - 1) / per;
+    // d' entering tile t of the run starting at q0 with entering value y
+    auto enter = [&](int64_t q0, int64_t t, double y) {
+        for (int64_t u = q0; u < t; ++u) {
+            const AffineStatus &f = d.fwd_status[first + u];
+            y = f.A * y + f.B;
+        }
+        return y;
+    };
+    const int64_t a0 = (int64_t)threadIdx.x * per;
+    const int64_t a1 = min(a0 + per, ntl);
+    Aff m = {1.0, 0.0};
+    for (int64_t t = a0; t < a1; ++t) {
+        const AffineStatus &f = d.fwd_status[first + t];
+        m = compose(Aff{f.A, f.B}, m);
+    }
+    Aff agg;
+    const Aff ex = block_exclusive_scan(m, &agg);
+    s_y[threadIdx.x] = ex.B;
+    if (a0 <= lt && lt < a1) s_out[0] = enter(a0, lt, ex.B);
+    __syncthreads();
+    const int64_t q = n_runs - 1 - (int64_t)threadIdx.x;
+    int64_t b0 = 0, b1 = 0;
+    Aff mb = {1.0, 0.0};
+    auto back = [&](int64_t t) {
+        const BackStatus &b = d.bwd_status[first + t];
+        return Aff{b.A, b.B0 + b.B1 * enter(b0, t, s_y[q])};
+    };
+    if (q >= 0) {
+        b0 = q * per;
+        b1 = min(b0 + per, ntl);
+        for (int64_t t = b1 - 1; t >= b0; --t) mb = compose(back(t), mb);
+    }
+    Aff aggb;
+    const Aff exb = block_exclusive_scan(mb, &aggb);
+    if (q >= 0 && b0 <= lt && lt < b1) {
+        Aff M = exb;
+        for (int64_t t = b1 - 1; t > lt; --t) M = compose(back(t), M);
+        s_out[1] = M.B;
+    }
+    __syncthreads();
+    y_in = s_out[0];
+    phi_above = s_out[1];
+    dp_top = agg.B;
+}
+
+__device__ __forceinline__ void tile_level(const Dev &d, int64_t first, int64_t ntl, int64_t lt, double &y_in,
+                                           double &phi_above, double &dp_top)
+{
+    if (ntl <= kBlock) tile_level_r<1>(d, first, ntl, lt, y_in, phi_above, dp_top);
+    else if (ntl <= (int64_t)kRunR * kBlock) tile_level_r<kRunR>(d, first, ntl, lt, y_in, phi_above, dp_top);
+    else tile_level_any(d, first, ntl, lt, y_in, phi_above, dp_top);
+}
+
 // ---------------------------------------------------------------------------
-// 3. backward sweep: phi, E, acc, field-energy partials; clears the deposit
+// 2. the values entering the tile, forward sweep (d'), backward sweep (phi),
+//    E, acc, field-energy partials; clears the deposit
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void field_bwd_kernel(Dev d)
 {
@@ -347,22 +449,59 @@ __global__ __launch_bounds__(kBlock) void field_bwd_kernel(Dev d)
     const int64_t G = d.G;
     const int nsp = ic.nsp;
     const double dx = ic.dx;
-
-    // thread t owns the chunk counted from the top of the tile; its d' is
-    // loaded before the first wait (unpredicated: a node past nc reads node
-    // nc and is not used)
     const int64_t lo = lt * kFieldTile;
+
+    // the thread's rho for the forward sweep (thread t: nodes lo + t kFieldR
+    // up), loaded before the first wait (unpredicated: a node past nc reads
+    // node nc and is not used)
+    const int64_t ja = lo + (int64_t)threadIdx.x * kFieldR;
+    double rl[kFieldR];
+#pragma unroll
+    for (int r = 0; r < kFieldR; ++r) rl[r] = d.rho[ic.gnode + min(ja + r, (int64_t)nc)];
+
+    double y_in, phi_above, dp_top;
+    tile_level(d, ic.ftile0, ntl, lt, y_in, phi_above, dp_top);
+
+    // forward sweep of the tile from the d' entering it
+    double dv[kFieldR];
+    Aff mf = {1.0, 0.0};
+#pragma unroll
+    for (int r = 0; r < kFieldR; ++r) {
+        const int64_t j = ja + r;
+        dv[r] = 0.0;
+        if (j >= 1 && j <= nc - 1) {
+            dv[r] = -(rl[r] * ic.K);
+            const double gq = gq_of(j);
+            mf = compose(Aff{gq, -(gq * dv[r])}, mf);
+        }
+    }
+    Aff aggf;
+    const Aff exf = block_exclusive_scan(mf, &aggf);
+    // d' of the thread's nodes, handed through LDS to the backward sweep's
+    // threads, which count their chunks from the top of the tile
+    __shared__ double s_dp[kFieldTile];
+    {
+        double y = exf.A * y_in + exf.B;
+#pragma unroll
+        for (int r = 0; r < kFieldR; ++r) {
+            const int64_t j = ja + r;
+            double v = 0.0;
+            if (j >= 1 && j <= nc - 1) {
+                const double gq = gq_of(j);
+                y = gq * y + (-(gq * dv[r]));
+                v = y;
+            }
+            s_dp[threadIdx.x * kFieldR + r] = v;
+        }
+    }
+    __syncthreads();
+
+    // thread t owns the chunk counted from the top of the tile
     const int64_t c = kBlock - 1 - threadIdx.x;
     const int64_t j0 = lo + c * kFieldR;
     double dl[kFieldR];
 #pragma unroll
-    for (int r = 0; r < kFieldR; ++r) dl[r] = d.dprime[ic.gnode + min(j0 + r, (int64_t)nc)];
-
-    // phi at the first node above the tile: the composites of the tiles
-    // above, top first, applied to phi_nc = 0
-    const int64_t last = ic.ftile0 + ntl - 1;
-    const Aff above = compose_ordered(d.bwd_status, ntl - 1 - lt, [last](int64_t a) { return last - a; });
-    const double phi_above = above.B;
+    for (int r = 0; r < kFieldR; ++r) dl[r] = s_dp[c * kFieldR + r];
 
     double dp[kFieldR];
     Aff m = {1.0, 0.0};
@@ -399,15 +538,15 @@ __global__ __launch_bounds__(kBlock) void field_bwd_kernel(Dev d)
     if (threadIdx.x == 0) {
         const int64_t hi1 = lo + kFieldTile;  // first node above the tile
         s_phi[kFieldTile + 1] = (hi1 <= nc - 1) ? phi_above : 0.0;
-        double below = 0.0;                   // phi at node lo - 1
-        if (lo - 1 >= 1) below = gq_of(lo - 1) * s_phi[1] + d.dprime[ic.gnode + lo - 1];
+        double below = 0.0;                   // phi at node lo - 1 (d' there: the value entering the tile)
+        if (lo - 1 >= 1) below = gq_of(lo - 1) * s_phi[1] + y_in;
         s_phi[0] = below;
     }
     __syncthreads();
 
     double fe = 0.0;
     double phi_nm1 = 0.0;
-    if (periodic && lo == 0 && nc >= 2) phi_nm1 = d.dprime[ic.gnode + nc - 1];  // phi_{nc-1} = d'_{nc-1}
+    if (periodic && lo == 0 && nc >= 2) phi_nm1 = dp_top;  // phi_{nc-1} = d'_{nc-1}
 #pragma unroll
     for (int r = 0; r < kFieldR; ++r) {
         const int64_t j = j0 + r;
@@ -544,9 +683,6 @@ hipError_t launch_field(const Dev &d, hipStream_t st, int smooth)
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(field_fwd_kernel, grid, block, 0, st, d);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(field_bwd_kernel, grid, block, 0, st, d);
     return hipGetLastError();
 }

@@ -168,6 +168,12 @@ struct AffineStatus {
     double A, B;
 };
 
+// a tile's backward composite phi_lo = A phi_above + B0 + B1 y, as a function
+// of the value y of d' entering the tile from below
+struct BackStatus {
+    double A, B0, B1;
+};
+
 // ---------------------------------------------------------------------------
 // workspace layout (byte offsets into pic_buffers.work)
 // ---------------------------------------------------------------------------
@@ -212,7 +218,8 @@ struct Dev {
     float *acc32;               // [nsp][G]
     uint32_t *hist, *cursor, *offsets;  // [nsp][G]
     unsigned long long *seg_start;      // [n_seg] first raw sort position of each segment
-    AffineStatus *fwd_status, *bwd_status;
+    AffineStatus *fwd_status;
+    BackStatus *bwd_status;
     unsigned long long *sort_status;
     double *fe_part;
     Cand *cand;                 // [n_regions][cand_q] per-block regions, then the overflow list

@@ -59,6 +59,35 @@ def test_deposit_bit_exact(name, prec):
 def test_field_solve(name, prec):
     wl = WORKLOADS[name]()
     flush(f"field {name} prec={prec}")
+    _check_field(wl, prec)
+
+
+# Grids of several field tiles (1024 nodes each): the solve's tile-level
+# scans take runs of one tile per thread up to 256 tiles, of up to four in
+# registers up to 1024 tiles, and longer runs read tile by tile beyond.
+# (electrons and ions drawn apart, so that the charge density is not zero)
+def _apart(nc, ppc, seed, **kw):
+    return pin.bounded(nc=nc, ppc=ppc, seed=seed, source=False).replace(pair_start=False, **kw)
+
+
+MANY_TILES = {
+    "bounded_3_tiles": lambda: _apart(3000, 4, 21),
+    "periodic_3_tiles": lambda: pin.langmuir(nc=3000, ppc=4, seed=22),
+    "bounded_293_tiles": lambda: _apart(300_000, 1, 23),
+    "periodic_293_tiles": lambda: pin.langmuir(nc=300_000, ppc=1, seed=24),
+    "bounded_1075_tiles": lambda: _apart(1_100_000, 1, 25),
+    "bounded_smooth2_40_tiles": lambda: _apart(40_000, 2, 26, smooth_passes=2),
+}
+
+
+@pytest.mark.parametrize("name", list(MANY_TILES))
+def test_field_solve_many_tiles(name):
+    wl = MANY_TILES[name]()
+    flush(f"field {name} (nc={wl.nc})")
+    _check_field(wl, FP64)
+
+
+def _check_field(wl, prec):
     sim, orc, ost = build_pair(wl, prec, flags=P.PIC_INIT_NO_FIELD)
     sim.deposit()
     sim.field_solve()
