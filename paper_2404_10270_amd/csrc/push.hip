@@ -40,17 +40,20 @@ struct PushLds {
     int64_t tile0[kSegLds + 1];
     int64_t base[kSegLds];
     uint32_t count[kSegLds];
-    uint8_t flg[kSegLds];   // kFlgTest | kFlgForce of each segment
+    uint8_t flg[kSegLds];   // kFlgTest | kFlgForce | kFlgWide of each segment
 };
 
 // per-segment flags of the movers: a collision process (the candidate test
-// reads ids and draws), a field that acts (the gather)
-constexpr uint32_t kFlgTest = 1u, kFlgForce = 2u;
+// reads ids and draws), a field that acts (the gather), some id of the
+// instance at or above 2^32 (the test reads the ids' high words too; fixed
+// for the length of a launch)
+constexpr uint32_t kFlgTest = 1u, kFlgForce = 2u, kFlgWide = 4u;
 
 __device__ __forceinline__ uint32_t seg_flags(const Dev &d, int s)
 {
     const SegConst &sc = d.segc[s];
-    return (sc.T != 0ull ? kFlgTest : 0u) | (sc.force ? kFlgForce : 0u);
+    return (sc.T != 0ull ? kFlgTest : 0u) | (sc.force ? kFlgForce : 0u) |
+           (d.instd[sc.inst].wide_ids != 0u ? kFlgWide : 0u);
 }
 
 // a subcycled species between its pushes (block-uniform)
@@ -285,7 +288,6 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
     uint32_t key0 = 0, key1 = 0;
     unsigned long long T = 0;
     long long step = 0;
-    bool wide = false;  // some id of the segment's instance may be >= 2^32
     for (int64_t t = blockIdx.x; t < d.n_tiles; t += gridDim.x) {
         int64_t tile0, base, count;
         uint32_t flg;
@@ -295,23 +297,6 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
         // a subcycled species between its pushes keeps its positions (their
         // deposit is a launch of its own, deposit_kernel<true>)
         if (d.n_seg > kSegLds && still(d, seg)) continue;
-        if (seg != cseg) {
-            const SegConst &sc = d.segc[seg];
-            acc = d.acc32 + sc.sp * d.G + sc.gnode;
-            S = d.S + sc.sp * d.G + sc.gnode;
-            nc = sc.nc;
-            periodic = (sc.bc == PIC_BC_PERIODIC);
-            tx = sc.txf, ty = sc.tyf, sx = sc.sxf, sy = sc.syf;
-            msf = sc.msf, hk = 0.5f * sc.msf;
-            key0 = sc.key0, key1 = sc.key1;
-            T = sc.T;
-            inst = sc.inst;
-            if (MCC) {
-                step = d.instd[inst].step;
-                wide = d.instd[inst].wide_ids != 0u;
-            }
-            cseg = seg;
-        }
 
         // the tile in kPer / NP passes of NP chunks per wave (NP = kPer: one pass)
 #pragma unroll 1
@@ -339,7 +324,7 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
             if (rem == (uint32_t)kTile) {
                 // a full tile: every load unconditional, so none is predicated
                 // and the wave issues all of them before its first wait
-                if (test && !wide) {
+                if (test && !(flg & kFlgWide)) {
                     // every id below 2^32: the low words are the ids
 #pragma unroll
                     for (int k = 0; k < NP; ++k) {
@@ -390,13 +375,30 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
                         vz[k] = stream_ld(&VZt[o]);
                         if (test) {
                             pid[k] = stream_ld(&IDLt[o]);
-                            if (wide) pid[k] |= (unsigned long long)stream_ld(&IDHt[o]) << 32;
+                            if (flg & kFlgWide) pid[k] |= (unsigned long long)stream_ld(&IDHt[o]) << 32;
                         }
                     }
                 }
             }
 #pragma unroll
             for (int k = 0; k < NP; ++k) lv[k] = j[k] >= 0;
+            // the segment's constants, read once the tile's loads are issued
+            // (their scalar loads share a counter with the LDS reads that
+            // address the tile: read first, the tile's loads would wait for them)
+            if (r0 == 0 && seg != cseg) {
+                const SegConst &sc = d.segc[seg];
+                acc = d.acc32 + sc.sp * d.G + sc.gnode;
+                S = d.S + sc.sp * d.G + sc.gnode;
+                nc = sc.nc;
+                periodic = (sc.bc == PIC_BC_PERIODIC);
+                tx = sc.txf, ty = sc.tyf, sx = sc.sxf, sy = sc.syf;
+                msf = sc.msf, hk = 0.5f * sc.msf;
+                key0 = sc.key0, key1 = sc.key1;
+                T = sc.T;
+                inst = sc.inst;
+                if (MCC) step = d.instd[inst].step;
+                cseg = seg;
+            }
             // ---- gather
             // (unpredicated: an empty slot reads node 0 and ignores it, so the
             // wave issues the four gathers before one wait, not one wait each)
@@ -556,7 +558,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     unsigned long long T = 0;
     int inst = 0;
     long long step = 0;
-    bool wide = false;  // some id of the segment's instance may be >= 2^32
     for (int64_t t = blockIdx.x; t < d.n_tiles; t += gridDim.x) {
         int64_t tile0, base, count;
         uint32_t flg;
@@ -566,23 +567,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         // a subcycled species between its pushes keeps its positions (their
         // deposit is a launch of its own, deposit_kernel<true>)
         if (d.n_seg > kSegLds && still(d, seg)) continue;
-        if (seg != cseg) {
-            const SegConst &sc = d.segc[seg];
-            acc = d.acc64 + sc.sp * d.G + sc.gnode;
-            S = d.S + sc.sp * d.G + sc.gnode;
-            L_ = (double)sc.nc;
-            periodic = (sc.bc == PIC_BC_PERIODIC);
-            tx = sc.tx, ty = sc.ty, sx = sc.sx, sy = sc.sy;
-            ms = sc.ms, hk = 0.5 * sc.ms;
-            key0 = sc.key0, key1 = sc.key1;
-            T = sc.T;
-            inst = sc.inst;
-            if (MCC) {
-                step = d.instd[inst].step;
-                wide = d.instd[inst].wide_ids != 0u;
-            }
-            cseg = seg;
-        }
         // the tile in kPer / NP passes of NP chunks per wave (NP = kPer: one pass)
 #pragma unroll 1
         for (int r0 = 0; r0 < kPer; r0 += NP) {
@@ -601,7 +585,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             const uint32_t *__restrict__ IDHt = IDH + tb;
             if (rem == (uint32_t)kTile) {
                 // a full tile: every load unconditional (see the FP32 form)
-                if (test && !wide) {
+                if (test && !(flg & kFlgWide)) {
                     // every id below 2^32: the low words are the ids
 #pragma unroll
                     for (int k = 0; k < NP; ++k) {
@@ -648,10 +632,27 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                         vz[k] = stream_ld(&VZt[o]);
                         if (test) {
                             pid[k] = stream_ld(&IDLt[o]);
-                            if (wide) pid[k] |= (unsigned long long)stream_ld(&IDHt[o]) << 32;
+                            if (flg & kFlgWide) pid[k] |= (unsigned long long)stream_ld(&IDHt[o]) << 32;
                         }
                     }
                 }
+            }
+            // the segment's constants, read once the tile's loads are issued
+            // (their scalar loads share a counter with the LDS reads that
+            // address the tile: read first, the tile's loads would wait for them)
+            if (r0 == 0 && seg != cseg) {
+                const SegConst &sc = d.segc[seg];
+                acc = d.acc64 + sc.sp * d.G + sc.gnode;
+                S = d.S + sc.sp * d.G + sc.gnode;
+                L_ = (double)sc.nc;
+                periodic = (sc.bc == PIC_BC_PERIODIC);
+                tx = sc.tx, ty = sc.ty, sx = sc.sx, sy = sc.sy;
+                ms = sc.ms, hk = 0.5 * sc.ms;
+                key0 = sc.key0, key1 = sc.key1;
+                T = sc.T;
+                inst = sc.inst;
+                if (MCC) step = d.instd[inst].step;
+                cseg = seg;
             }
             // the gather unpredicated (an empty slot reads node 0 and ignores it)
             double a0[NP], a1[NP], fr[NP];
