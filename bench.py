@@ -91,9 +91,8 @@ def mover_shapes(sim):
     return shapes
 
 
-def tune_mover(sim, trial_steps=40):
-    """Autotune the mover's launch shape at the workload's sort cadence (these
-    trial steps are untimed, like warm-up steps)."""
+def tune_mover(sim, trial_steps=80):
+    """Autotune the mover's launch shape at the workload's sort cadence."""
     movers = mover_shapes(sim)
     best, _, rates, _ = sim.autotune(movers, (SORT_EVERY,), trial_steps)
     return {"chunks": best[0], "blocks": best[1] or int(sim.sizes.mover_blocks),
@@ -101,11 +100,28 @@ def tune_mover(sim, trial_steps=40):
                        for m, r in zip(movers, rates)}}
 
 
+def tuned_sim(torch, make):
+    """The mover's launch shape chosen on a throwaway copy of the workload
+    (make() builds one), then a fresh copy set to that shape: the trials run
+    hundreds of steps, over which ionisation grows the plasma, so the timed
+    run starts from the workload's own initial state."""
+    sim = make()
+    shape = tune_mover(sim)
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    sim = make()
+    sim.set_mover(shape["chunks"], shape["blocks"])
+    return sim, shape
+
+
 def run_form(torch, sim, steps, warmup, graph=False):
     """Time `steps` whole steps after `warmup`; returns (p-steps/s, ms/step, p-steps).
     With `graph` the steps are replayed from a captured HIP graph (pic_step_graph)."""
     step = sim.step_graph if graph else sim.step
     step(warmup, SORT_EVERY)
+    if graph:
+        sim.step_graph(0, SORT_EVERY)  # the period graph for this phase, captured untimed
     d0, _ = sim.diagnostics()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -269,16 +285,29 @@ def batched(torch, args):
     wls = pin.batched(n_inst=args.batched_instances, seed=4)
     n = sum(w.n_particles for w in wls)
     log(f"batched: {len(wls)} instances, {n} particles, drawn on the device")
-    sim = P.PicSim(wls, [None] * len(wls), P.PIC_FP32, flags=P.PIC_INIT_DEVICE | P.PIC_INIT_SORT)
+    def make():
+        return P.PicSim(wls, [None] * len(wls), P.PIC_FP32, flags=P.PIC_INIT_DEVICE | P.PIC_INIT_SORT)
+    # shape and cadence chosen on a throwaway copy (see tuned_sim)
+    sim = make()
     cands = (5, 10, 20, 40, 80)
     movers = mover_shapes(sim)
     mover, best, mrates, rates = sim.autotune(movers, cands, 80)
     log(f"batched: autotuned mover {mover} ({', '.join(f'{m}: {r:.3e}' for m, r in zip(movers, mrates))}), "
         f"sort cadence {best} ({', '.join(f'{c}: {r:.3e}' for c, r in zip(cands, rates))})")
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    sim = make()
+    sim.set_mover(mover[0], mover[1])
+    # one untimed sort period (the graph is captured in it), then whole periods
+    # (each with its sort), at least --batched-steps steps
+    period = best if best > 0 else 20
+    steps = period * max(1, -(-args.batched_steps // period))
+    sim.step_graph(period, best)
     d0, _ = sim.diagnostics()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sim.step_graph(args.batched_steps, best)
+    sim.step_graph(steps, best)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     d1, rc = sim.diagnostics()
@@ -287,8 +316,8 @@ def batched(torch, args):
     ps = sum(int(d1[i].particle_steps - d0[i].particle_steps) for i in range(len(wls)))
     sim.close()
     out = {"value": ps / dt, "unit": "particle-steps/s", "instances": len(wls), "particles": n,
-           "cells": sum(w.nc for w in wls), "steps": args.batched_steps,
-           "ms_per_step": round(1e3 * dt / args.batched_steps, 4), "sort_every": best,
+           "cells": sum(w.nc for w in wls), "steps": steps,
+           "ms_per_step": round(1e3 * dt / steps, 4), "sort_every": best,
            "mover": {"chunks": mover[0], "blocks": mover[1] or int(sim.sizes.mover_blocks)},
            "autotune": {"mover": {f"{m[0]}x{m[1] or int(sim.sizes.mover_blocks)}": round(r, 1)
                                   for m, r in zip(movers, mrates)},
@@ -595,6 +624,7 @@ def small_configs(torch, args):
     out = {}
     wl = pin.langmuir()
     sim = P.PicSim(wl, None, P.PIC_FP64, flags=P.PIC_INIT_DEVICE)
+    sim.step_graph(0, 0)  # the one-step graph, captured untimed
     d0, _ = sim.diagnostics()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -637,8 +667,8 @@ def large_run(torch, args):
     out = {"cells": wl.nc, "particles": n, "steps": args.large_steps, "sort_every": SORT_EVERY}
     for name, prec, bpp in (("fp32", P.PIC_FP32, PUSH_BYTES_FP32), ("fp64", P.PIC_FP64, PUSH_BYTES_FP64)):
         log(f"large: {wl.nc} cells, {n} particles, {name} form")
-        sim = P.PicSim(wl, None, prec, capacities=caps, flags=P.PIC_INIT_DEVICE | P.PIC_INIT_SORT)
-        mv = tune_mover(sim)
+        sim, mv = tuned_sim(torch, lambda: P.PicSim(wl, None, prec, capacities=caps,
+                                                    flags=P.PIC_INIT_DEVICE | P.PIC_INIT_SORT))
         log(f"large {name}: autotuned mover {mv}")
         rate, ms_step, _ = run_form(torch, sim, args.large_steps, args.warmup, graph=True)
         win = time_windows(torch, sim)
@@ -780,8 +810,7 @@ def main():
     st = pin.initial_state(wl)
 
     log("FP32 form: init")
-    sim = make_sim(wl, st, P.PIC_FP32)
-    mover32 = tune_mover(sim)
+    sim, mover32 = tuned_sim(torch, lambda: make_sim(wl, st, P.PIC_FP32))
     log(f"FP32 form: autotuned mover {mover32}")
     log(f"FP32 form: {args.warmup} warm-up + {args.steps} timed steps")
     rate, ms_step, ps = run_form(torch, sim, args.steps, args.warmup, graph=not args.eager)
@@ -809,8 +838,7 @@ def main():
     fp64 = None
     if not args.no_fp64:
         log("FP64 form: init")
-        sim64 = make_sim(wl, st, P.PIC_FP64)
-        mover64 = tune_mover(sim64)
+        sim64, mover64 = tuned_sim(torch, lambda: make_sim(wl, st, P.PIC_FP64))
         log(f"FP64 form: autotuned mover {mover64}")
         r64, ms64, _ = run_form(torch, sim64, args.steps, args.warmup, graph=not args.eager)
         win64 = time_windows(torch, sim64)

@@ -334,13 +334,17 @@ int pic_step(pic_ctx *ctx, int n_steps, int sort_every);
 
 /*
  * pic_step_graph -- the same n_steps whole steps as pic_step, with the same
- * results, replayed from a HIP graph: one sort period (sort_every steps and
- * the sort, or one step when sort_every is 0) is captured on a stream the
- * context owns, instantiated once (again when sort_every changes) and
- * launched on the context's stream.  Steps before the next sort, and the
- * remainder after the last whole period, run as in pic_step.  The captured
- * work holds no memset and no host synchronisation.  Returns PIC_E_DEVICE
- * when capture or instantiation fails.
+ * results, replayed from a HIP graph: one sort period (sort_every steps with
+ * the sort where pic_step puts it, or one step when sort_every is 0),
+ * starting at the current step's phase of the cadence, is captured on a
+ * stream the context owns, instantiated once (again when sort_every or the
+ * phase changes) and launched on the context's stream once per whole period;
+ * the remainder after the last whole period runs as in pic_step.  With
+ * n_steps = 0 the graph for the current phase is captured and uploaded
+ * without launching anything (so that a later call's first replay carries
+ * no capture).  The captured work holds no memset and no host
+ * synchronisation.  Returns PIC_E_DEVICE when capture or instantiation
+ * fails.
  */
 int pic_step_graph(pic_ctx *ctx, int n_steps, int sort_every);
 
@@ -349,11 +353,13 @@ int pic_step_graph(pic_ctx *ctx, int n_steps, int sort_every);
  * sorting", Sec. 2: how often to restore the order by cell).  For each of
  * the n_cand candidates (a cadence in steps, 0 = never) the particles are
  * sorted, then trial_steps whole steps run as in pic_step_graph and are
- * timed with HIP events; *best receives the candidate with the most
- * particle-steps per second, rates[i] (may be NULL) each candidate's rate.
- * The trials advance the simulation by n_cand * trial_steps steps, like
- * warm-up steps; make trial_steps a multiple of every candidate so that each
- * trial ends with a sort.  Synchronises the stream.
+ * timed with HIP events; every candidate is timed in two interleaved
+ * rounds, after one untimed warm-up trial, and rates[i] (may be NULL)
+ * receives the better of its two rates in particle-steps per second; *best
+ * receives the candidate with the highest.  The trials advance the
+ * simulation by (2 n_cand + 1) trial_steps steps, like warm-up steps; make
+ * trial_steps a multiple of every candidate so that each trial ends with a
+ * sort.  Synchronises the stream.
  */
 int pic_autotune_sort(pic_ctx *ctx, const int *cand, int n_cand, int trial_steps, int *best,
                       double *rates);
@@ -402,9 +408,11 @@ int pic_set_mover(pic_ctx *ctx, int chunks, int blocks);
  * trial_steps whole steps at cadences[0] after a fresh sort; the fastest
  * (particle-steps per second, HIP events) is kept (*best_mover = its index)
  * and each of the n_cad cadences is then timed with it (*best_cadence = the
- * fastest value).  rates (may be NULL) receives n_movers + n_cad rates.  The
- * context is left on the best shape; the trials advance the simulation like
- * warm-up steps.  Synchronises the stream.
+ * fastest value).  As in pic_autotune_sort, each set of candidates is timed
+ * in two interleaved rounds after one untimed warm-up trial, and a
+ * candidate's rate is the better of its two.  rates (may be NULL) receives
+ * n_movers + n_cad rates.  The context is left on the best shape; the trials
+ * advance the simulation like warm-up steps.  Synchronises the stream.
  */
 int pic_autotune(pic_ctx *ctx, const int *chunks, const int *blocks, int n_movers,
                  const int *cadences, int n_cad, int trial_steps, int *best_mover,

@@ -32,7 +32,7 @@ struct pic_ctx {
     // pic_step_graph: one sort period captured on a stream of its own
     hipStream_t cap_st = nullptr;
     hipGraphExec_t gexec = nullptr;
-    int g_period = 0, g_sort = -1;
+    int g_period = 0, g_sort = -1, g_phase = 0;
 };
 
 namespace {
@@ -749,11 +749,19 @@ void drop_graph(pic_ctx *c)
     c->gexec = nullptr;
     c->g_period = 0;
     c->g_sort = -1;
+    c->g_phase = 0;
+}
+
+// steps since the last multiple of the cadence (0 without sorting)
+int cadence_phase(const pic_ctx *c, int sort_every)
+{
+    return sort_every > 0 ? (int)((c->cfg[0].step0 + c->host_steps) % sort_every) : 0;
 }
 
 // capture one period (sort_every steps and the sort, or one step when
-// sort_every is 0) into c->gexec
-int capture_period(pic_ctx *c, int sort_every)
+// sort_every is 0) into c->gexec, starting at `phase` steps into the
+// cadence: sort_every - phase steps, the sort, then the other phase steps
+int capture_period(pic_ctx *c, int sort_every, int phase)
 {
     drop_graph(c);
     if (!c->cap_st && hipStreamCreateWithFlags(&c->cap_st, hipStreamNonBlocking) != hipSuccess) {
@@ -766,7 +774,8 @@ int capture_period(pic_ctx *c, int sort_every)
     if (hipStreamBeginCapture(c->cap_st, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return PIC_E_DEVICE;
     c->st = c->cap_st;
-    const int rc = enqueue_period(c, period, sort_every > 0);
+    int rc = enqueue_period(c, period - phase, sort_every > 0);
+    if (!rc && phase > 0) rc = enqueue_period(c, phase, false);
     c->st = user;
     c->host_steps = steps;  // capture enqueues nothing
     hipGraph_t g = nullptr;
@@ -783,6 +792,7 @@ int capture_period(pic_ctx *c, int sort_every)
     }
     c->g_period = period;
     c->g_sort = sort_every;
+    c->g_phase = phase;
     return PIC_OK;
 }
 
@@ -792,20 +802,17 @@ int pic_step_graph(pic_ctx *c, int n_steps, int sort_every)
 {
     if (!c) return PIC_E_STATE;
     if (n_steps < 0 || sort_every < 0) return PIC_E_ARG;
-    const int64_t step0 = c->cfg[0].step0;
     int left = n_steps;
-    // eager steps up to the next sort, so that every replay starts a period
-    if (sort_every > 0) {
-        while (left > 0 && ((step0 + c->host_steps) % sort_every) != 0) {
-            const int rc = pic_step(c, 1, sort_every);
-            if (rc) return rc;
-            --left;
-        }
-    }
+    // whole periods from the current phase of the cadence replay one graph
+    // (its sort where pic_step would sort); the remainder runs eagerly.
+    // n_steps = 0: capture and upload that graph only, launching nothing
     const int period = sort_every > 0 ? sort_every : 1;
-    if (left >= period && (!c->gexec || c->g_sort != sort_every)) {
-        const int rc = capture_period(c, sort_every);
+    const int phase = cadence_phase(c, sort_every);
+    if ((left >= period || n_steps == 0) &&
+        (!c->gexec || c->g_sort != sort_every || c->g_phase != phase)) {
+        const int rc = capture_period(c, sort_every, phase);
         if (rc) return rc;
+        if (n_steps == 0 && hipGraphUpload(c->gexec, c->st) != hipSuccess) return PIC_E_DEVICE;
     }
     while (left >= period) {
         if (hipGraphLaunch(c->gexec, c->st) != hipSuccess) return PIC_E_DEVICE;
@@ -837,8 +844,10 @@ int time_trial(pic_ctx *c, int trial_steps, int cadence, hipEvent_t e0, hipEvent
     int rc = pic_sort(c);  // every trial starts from freshly sorted particles
     if (rc) return rc;
     // the graph of this cadence is captured and uploaded before the timing
-    if (trial_steps >= (cadence > 0 ? cadence : 1) && (!c->gexec || c->g_sort != cadence)) {
-        rc = capture_period(c, cadence);
+    const int phase = cadence_phase(c, cadence);
+    if (trial_steps >= (cadence > 0 ? cadence : 1) &&
+        (!c->gexec || c->g_sort != cadence || c->g_phase != phase)) {
+        rc = capture_period(c, cadence, phase);
         if (rc) return rc;
         if (hipGraphUpload(c->gexec, c->st) != hipSuccess) return PIC_E_DEVICE;
     }
@@ -876,7 +885,37 @@ struct EventPair {
     }
 };
 
+// Each of n configurations (set(i, &cadence) selects configuration i and
+// its sort cadence) is timed in kTuneRounds interleaved rounds after one
+// untimed warm-up trial of the first; rate[i] = its best round.  (The first
+// trials after a quiet spell ran slower than later ones, which favoured the
+// configurations timed last.)
+constexpr int kTuneRounds = 2;
+
 }  // namespace
+}  // extern "C"
+
+namespace {
+
+template <class Set>
+int best_of_rounds(pic_ctx *c, int n, int trial_steps, EventPair &ev, double *rate, Set set)
+{
+    int cadence = 0;
+    int rc = set(0, &cadence);
+    double r = 0.0;
+    if (!rc) rc = time_trial(c, trial_steps, cadence, ev.e0, ev.e1, &r);
+    for (int round = 0; round < kTuneRounds && !rc; ++round)
+        for (int i = 0; i < n && !rc; ++i) {
+            rc = set(i, &cadence);
+            if (!rc) rc = time_trial(c, trial_steps, cadence, ev.e0, ev.e1, &r);
+            if (!rc && r > rate[i]) rate[i] = r;
+        }
+    return rc;
+}
+
+}  // namespace
+
+extern "C" {
 
 int pic_autotune_sort(pic_ctx *c, const int *cand, int n_cand, int trial_steps, int *best,
                       double *rates)
@@ -887,17 +926,14 @@ int pic_autotune_sort(pic_ctx *c, const int *cand, int n_cand, int trial_steps, 
         if (cand[i] < 0) return PIC_E_ARG;
     EventPair ev;
     if (!ev.ok) return PIC_E_DEVICE;
+    std::vector<double> r(n_cand, -1.0);
+    const int rc = best_of_rounds(c, n_cand, trial_steps, ev, r.data(),
+                                  [&](int i, int *cadence) { *cadence = cand[i]; return PIC_OK; });
+    if (rc) return rc;
     int pick = 0;
-    double best_rate = -1.0;
     for (int i = 0; i < n_cand; ++i) {
-        double rate = 0.0;
-        const int rc = time_trial(c, trial_steps, cand[i], ev.e0, ev.e1, &rate);
-        if (rc) return rc;
-        if (rates) rates[i] = rate;
-        if (rate > best_rate) {
-            best_rate = rate;
-            pick = i;
-        }
+        if (rates) rates[i] = r[i];
+        if (r[i] > r[pick]) pick = i;
     }
     *best = cand[pick];
     return PIC_OK;
@@ -920,34 +956,29 @@ int pic_autotune(pic_ctx *c, const int *chunks, const int *blocks, int n_movers,
     EventPair ev;
     if (!ev.ok) return PIC_E_DEVICE;
     // the mover configurations at the first cadence
+    std::vector<double> rm(n_movers, -1.0);
+    int rc = best_of_rounds(c, n_movers, trial_steps, ev, rm.data(), [&](int i, int *cadence) {
+        *cadence = cadences[0];
+        return pic_set_mover(c, chunks[i], blocks[i]);
+    });
+    if (rc) return rc;
     int pick = 0;
-    double best_rate = -1.0;
     for (int i = 0; i < n_movers; ++i) {
-        int rc = pic_set_mover(c, chunks[i], blocks[i]);
-        double rate = 0.0;
-        if (!rc) rc = time_trial(c, trial_steps, cadences[0], ev.e0, ev.e1, &rate);
-        if (rc) return rc;
-        if (rates) rates[i] = rate;
-        if (rate > best_rate) {
-            best_rate = rate;
-            pick = i;
-        }
+        if (rates) rates[i] = rm[i];
+        if (rm[i] > rm[pick]) pick = i;
     }
     *best_mover = pick;
-    int rc = pic_set_mover(c, chunks[pick], blocks[pick]);
+    rc = pic_set_mover(c, chunks[pick], blocks[pick]);
     if (rc) return rc;
     // then the cadences with that mover
+    std::vector<double> rcad(n_cad, -1.0);
+    rc = best_of_rounds(c, n_cad, trial_steps, ev, rcad.data(),
+                        [&](int j, int *cadence) { *cadence = cadences[j]; return PIC_OK; });
+    if (rc) return rc;
     int cpick = 0;
-    best_rate = -1.0;
     for (int j = 0; j < n_cad; ++j) {
-        double rate = 0.0;
-        rc = time_trial(c, trial_steps, cadences[j], ev.e0, ev.e1, &rate);
-        if (rc) return rc;
-        if (rates) rates[n_movers + j] = rate;
-        if (rate > best_rate) {
-            best_rate = rate;
-            cpick = j;
-        }
+        if (rates) rates[n_movers + j] = rcad[j];
+        if (rcad[j] > rcad[cpick]) cpick = j;
     }
     *best_cadence = cadences[cpick];
     return PIC_OK;

@@ -121,6 +121,17 @@ def test_graph_replays_equal_eager_steps(prec):
         ga, gb = gpu_state(a, k), gpu_state(b, k)
         for f in ("x", "vx", "vy", "vz", "id"):
             assert np.array_equal(ga[f], gb[f]), f
+    # a period that starts 7 steps into the cadence: the graph holds 13 steps,
+    # the sort, then 7 more; two replays and a remainder of 5, eager
+    a.step(45, sort_every=20)
+    b.step_graph(45, 20)
+    da, _ = a.diagnostics()
+    db, rcb = b.diagnostics()
+    assert rcb == 0 and da[0].step == db[0].step == 112
+    for k in range(2):
+        ga, gb = gpu_state(a, k), gpu_state(b, k)
+        for f in ("x", "vx", "vy", "vz", "id"):
+            assert np.array_equal(ga[f], gb[f]), f
     # without sorting: a graph of one step, replayed
     a.step(9, sort_every=0)
     b.step_graph(9, 0)
@@ -140,10 +151,10 @@ def test_autotune_sort_picks_a_candidate_and_leaves_a_valid_state():
     assert best in (5, 10, 20, 0)
     assert len(rates) == 4 and all(r > 0 for r in rates)
     d, rc = sim.diagnostics()
-    assert rc == 0 and d[0].step == 80  # four trials of 20 steps
+    assert rc == 0 and d[0].step == 180  # a warm-up trial, then two rounds of four, 20 steps each
     sim.step(7, best)
     d, rc = sim.diagnostics()
-    assert rc == 0 and d[0].step == 87
+    assert rc == 0 and d[0].step == 187
     for k in range(2):
         ids = gpu_state(sim, k)["id"]
         assert np.unique(ids).size == ids.size
@@ -214,7 +225,8 @@ def test_autotune_picks_a_mover_and_a_cadence():
     assert best in movers and cad in (10, 20)
     assert len(mrates) == 4 and len(crates) == 2 and all(r > 0 for r in mrates + crates)
     d, rc = sim.diagnostics()
-    assert rc == 0 and all(x.step == 120 for x in d)  # six trials of 20 steps
+    # shapes: a warm-up trial and two rounds of four; cadences: a warm-up and two of two (20 steps each)
+    assert rc == 0 and all(x.step == 20 * (1 + 8 + 1 + 4) for x in d)
     sim.step(7, cad)
     d, rc = sim.diagnostics()
     assert rc == 0
