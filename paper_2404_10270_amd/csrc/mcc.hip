@@ -761,8 +761,14 @@ __device__ __forceinline__ IzPair prepare_pair(const Dev &d, int cur, bool f64, 
 // holds more; the rest, and the overflow list, follow in plain loops)
 constexpr int kStageK = 4;
 
-__device__ __forceinline__ void stage_pids(const EventIndex &X, const Dev &d, unsigned long long *s_pid)
+__device__ __forceinline__ void stage_pids(const EventIndex &X, const Dev &d, unsigned long long *s_pid,
+                                           uint32_t *s_pid32)
 {
+    // s_pid32 (not null): the low words only, into s_pid32[0, total)
+    auto put = [&](uint32_t i, unsigned long long v) {
+        if (s_pid32) s_pid32[i] = (uint32_t)v;
+        else s_pid[i] = v;
+    };
     constexpr int kRegT = (kMaxPushBlocks + kBlock - 1) / kBlock;
     const int nb = d.n_push_blocks;
     unsigned long long v[kRegT][kStageK];
@@ -781,18 +787,18 @@ __device__ __forceinline__ void stage_pids(const EventIndex &X, const Dev &d, un
     for (int r = 0; r < kRegT; ++r) {
 #pragma unroll
         for (int k = 0; k < kStageK; ++k)
-            if ((uint32_t)k < n[r]) s_pid[dst[r] + k] = v[r][k];
+            if ((uint32_t)k < n[r]) put(dst[r] + k, v[r][k]);
         const int b = threadIdx.x + r * kBlock;
-        for (uint32_t k = kStageK; k < n[r]; ++k) s_pid[dst[r] + k] = d.ev[(int64_t)b * d.ev_q + k].parent_id;
+        for (uint32_t k = kStageK; k < n[r]; ++k) put(dst[r] + k, d.ev[(int64_t)b * d.ev_q + k].parent_id);
     }
     for (uint32_t e = X.in_regions + threadIdx.x; e < X.total; e += kBlock)
-        s_pid[e] = d.ev[(int64_t)d.n_regions * d.ev_q + (e - X.in_regions)].parent_id;
+        put(e, d.ev[(int64_t)d.n_regions * d.ev_q + (e - X.in_regions)].parent_id);
 }
 
 __global__ __launch_bounds__(kBlock) void emit_ranked_kernel(Dev d)
 {
     __shared__ EventIndex X;
-    __shared__ unsigned long long s_pid[kRankChunk];
+    __shared__ __align__(16) unsigned long long s_pid[kRankChunk];
     __shared__ uint32_t s_part[kWaves][64];
     const uint32_t n_src = source_pairs(d, 0);  // read first: in flight beside the index
     build_event_index(X, d);
@@ -801,6 +807,10 @@ __global__ __launch_bounds__(kBlock) void emit_ranked_kernel(Dev d)
     const uint32_t m = X.total;
     const int lane = lane_id(), wave = threadIdx.x >> 6;
     const uint32_t n_groups = (m + 63u) / 64u;
+    if (blockIdx.x == 0 && threadIdx.x == 0) d.glob->ev_total = m;  // for the close kernel
+    // every id below 2^32: the ranks compare the low words, four per LDS read
+    const bool narrow = d.instd[0].wide_ids == 0u && m <= (uint32_t)kRankChunk;
+    uint32_t *s_pid32 = reinterpret_cast<uint32_t *>(s_pid);
     for (uint32_t g = blockIdx.x; g < n_groups; g += gridDim.x) {  // block-uniform
         const uint32_t e = g * 64u + (uint32_t)lane;
         const bool mine = e < m;
@@ -809,18 +819,38 @@ __global__ __launch_bounds__(kBlock) void emit_ranked_kernel(Dev d)
         IzPair q = {};
         if (wave == 0 && mine) q = prepare_pair(d, cur, f64, ev);
         uint32_t r = 0;
-        for (uint32_t c0 = 0; c0 < m; c0 += kRankChunk) {
-            const uint32_t cn = min((uint32_t)kRankChunk, m - c0);
-            __syncthreads();  // the previous chunk's readers are done
-            if (m <= (uint32_t)kRankChunk) stage_pids(X, d, s_pid);
-            else
-                for (uint32_t i = threadIdx.x; i < cn; i += kBlock) s_pid[i] = event_at(X, d, c0 + i).parent_id;
+        if (narrow) {
+            __syncthreads();  // the previous group's readers are done
+            stage_pids(X, d, s_pid, s_pid32);
+            const uint32_t n4 = (m + 3u) & ~3u;  // padded with ids no parent has below it
+            for (uint32_t i = m + threadIdx.x; i < n4; i += kBlock) s_pid32[i] = 0xFFFFFFFFu;
             __syncthreads();
-            const uint32_t q0 = (uint32_t)wave * cn / kWaves, q1 = (uint32_t)(wave + 1) * cn / kWaves;
+            const uint32_t q0 = ((uint32_t)wave * (n4 / 4u) / kWaves) * 4u;
+            const uint32_t q1 = ((uint32_t)(wave + 1) * (n4 / 4u) / kWaves) * 4u;
             if (mine) {
-                const unsigned long long pid = ev.parent_id;
+                const uint32_t pid = (uint32_t)ev.parent_id;
+#pragma unroll 4
+                for (uint32_t k = q0; k < q1; k += 4) {
+                    const uint4 v = *reinterpret_cast<const uint4 *>(&s_pid32[k]);
+                    r += (v.x < pid ? 1u : 0u) + (v.y < pid ? 1u : 0u) + (v.z < pid ? 1u : 0u) +
+                         (v.w < pid ? 1u : 0u);
+                }
+            }
+        } else {
+            for (uint32_t c0 = 0; c0 < m; c0 += kRankChunk) {
+                const uint32_t cn = min((uint32_t)kRankChunk, m - c0);
+                __syncthreads();  // the previous chunk's readers are done
+                if (m <= (uint32_t)kRankChunk) stage_pids(X, d, s_pid, nullptr);
+                else
+                    for (uint32_t i = threadIdx.x; i < cn; i += kBlock)
+                        s_pid[i] = event_at(X, d, c0 + i).parent_id;
+                __syncthreads();
+                const uint32_t q0 = (uint32_t)wave * cn / kWaves, q1 = (uint32_t)(wave + 1) * cn / kWaves;
+                if (mine) {
+                    const unsigned long long pid = ev.parent_id;
 #pragma unroll 8
-                for (uint32_t k = q0; k < q1; ++k) r += s_pid[k] < pid ? 1u : 0u;
+                    for (uint32_t k = q0; k < q1; ++k) r += s_pid[k] < pid ? 1u : 0u;
+                }
             }
         }
         s_part[wave][lane] = r;
@@ -898,11 +928,23 @@ __device__ void close_body(const Dev &d, const EventIndex &X, const uint32_t *s_
         for (int b = threadIdx.x; b < d.n_push_blocks; b += kBlock) d.ev_n[b] = 0u;
 }
 
+// with_events: 0 no collisions this step; 1 collisions, ranks in the rank
+// array (cleared here); 2 a single instance whose emit kernel ranked its
+// events itself and left their count in glob->ev_total (nothing to clear)
 __global__ __launch_bounds__(kBlock) void close_step_kernel(Dev d, int with_events)
 {
     __shared__ EventIndex X;
     __shared__ uint32_t s_m[kMaxInstLds];
     const int n_inst = d.n_inst < kMaxInstLds ? d.n_inst : kMaxInstLds;
+    if (with_events == 2) {
+        if (threadIdx.x == 0) {
+            X.total = 0u;  // no ranks to clear
+            s_m[0] = d.glob->ev_total;
+        }
+        __syncthreads();
+        close_body(d, X, s_m, n_inst, true);
+        return;
+    }
     if (with_events) {
         get_event_index(X, d);
         count_events(X, d, s_m, n_inst);
@@ -943,7 +985,7 @@ hipError_t launch_emit(const Dev &d, hipStream_t st, bool pairs, bool events)
         hipLaunchKernelGGL(emit_ranked_kernel, dim3(kEmitRankedBlocks), dim3(kBlock), 0, st, d);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(close_step_kernel, dim3(1), dim3(kBlock), 0, st, d, 1);
+        hipLaunchKernelGGL(close_step_kernel, dim3(1), dim3(kBlock), 0, st, d, 2);
         return hipGetLastError();
     }
     if (events) {
