@@ -53,11 +53,14 @@ constexpr int kWaveWin = 64;      // LDS deposit window of one wave, nodes
 // cells are summed across lanes, their two node weights added into the
 // window, and the window flushed with one 64-bit global atomic per touched
 // node.  A run whose nodes fall outside the window adds to S directly.
+// In two halves, so that a mover can issue its next tile's loads between
+// them: deposit_accumulate fills the window (span = 0: nothing to flush),
+// deposit_flush adds it to S and clears it.
 template <int NP>
-__device__ __forceinline__ void deposit_wave(unsigned long long *wdep, unsigned long long *__restrict__ S,
-                                             const int (&key)[NP], const unsigned long long (&w1)[NP])
+__device__ __forceinline__ void deposit_accumulate(unsigned long long *wdep, unsigned long long *__restrict__ S,
+                                                   const int (&key)[NP], const unsigned long long (&w1)[NP],
+                                                   int &lo, int &span)
 {
-    const int lane = lane_id();
     int kmn = 0x7fffffff, kmx = -1;
 #pragma unroll
     for (int k = 0; k < NP; ++k)
@@ -65,8 +68,9 @@ __device__ __forceinline__ void deposit_wave(unsigned long long *wdep, unsigned 
             kmn = min(kmn, key[k]);
             kmx = max(kmx, key[k]);
         }
-    const int lo = __builtin_amdgcn_readfirstlane(wave_min(kmn));
+    lo = __builtin_amdgcn_readfirstlane(wave_min(kmn));
     const int hi = __builtin_amdgcn_readfirstlane(wave_max(kmx));
+    span = 0;
     if (hi < 0) return;  // no live particle in the wave's chunks
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
@@ -88,9 +92,16 @@ __device__ __forceinline__ void deposit_wave(unsigned long long *wdep, unsigned 
             }
         }
     }
+    span = min(hi - lo + 2, kWaveWin);
+}
+
+__device__ __forceinline__ void deposit_flush(unsigned long long *wdep, unsigned long long *__restrict__ S, int lo,
+                                              int span)
+{
+    static_assert(kWaveWin == 64, "one window node per lane");
     wave_lds_sync();
-    const int span = min(hi - lo + 2, kWaveWin);
-    for (int i = lane; i < span; i += 64) {
+    const int i = lane_id();
+    if (i < span) {
         const unsigned long long v = wdep[i];
         if (v) {
             atomicAdd(S + lo + i, v);
@@ -98,6 +109,15 @@ __device__ __forceinline__ void deposit_wave(unsigned long long *wdep, unsigned 
         }
     }
     wave_lds_sync();
+}
+
+template <int NP>
+__device__ __forceinline__ void deposit_wave(unsigned long long *wdep, unsigned long long *__restrict__ S,
+                                             const int (&key)[NP], const unsigned long long (&w1)[NP])
+{
+    int lo, span;
+    deposit_accumulate<NP>(wdep, S, key, w1, lo, span);
+    if (span > 0) deposit_flush(wdep, S, lo, span);
 }
 
 }  // namespace picx

@@ -274,6 +274,11 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
     uint32_t wn = 0;  // this wave's candidates so far (uniform)
+    // the deposit window of the wave's previous pass, flushed once the next
+    // pass's loads are issued (its global atomics would otherwise stand, on
+    // the in-order memory counter, between those loads and their wait)
+    int dlo = 0, dspan = 0;
+    unsigned long long *dS = nullptr;
 
     int hint = 0;  // segment of the previous tile
     // the constants of the segment of the previous tile, kept across tiles
@@ -379,6 +384,10 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
                         }
                     }
                 }
+            }
+            if (DEP && dspan > 0) {
+                deposit_flush(L.wdep[wave], dS, dlo, dspan);
+                dspan = 0;
             }
 #pragma unroll
             for (int k = 0; k < NP; ++k) lv[k] = j[k] >= 0;
@@ -516,9 +525,13 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
                     queue_candidate(d, cand[k], (uint32_t)(tb + o), seg, inst, vx[k], vy[k], vz[k], pid[k], wn);
                 }
             }
-            if (DEP) deposit_tile<NP>(L, S, key, w1);
+            if (DEP) {
+                deposit_accumulate<NP>(L.wdep[wave], S, key, w1, dlo, dspan);
+                dS = S;
+            }
         }
     }
+    if (DEP && dspan > 0) deposit_flush(L.wdep[wave], dS, dlo, dspan);
     if (MCC) flush_candidates(d, wn);
     if constexpr (MCC && COLL) collide_own_region(L, d, wn);
 }
