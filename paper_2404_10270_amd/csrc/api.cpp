@@ -19,6 +19,7 @@ struct pic_ctx {
     bool mcc_any = false, src_any = false;
     int max_smooth = 0;       // most smoother passes of any instance
     bool sub_any = false;     // some species is subcycled (nstep > 1)
+    bool periodic_any = false;  // some instance is periodic (its rho reads the live counts)
     Layout L{};
     Dev d{};
     hipStream_t st = nullptr;
@@ -449,6 +450,7 @@ int init_context(const pic_config *cfgs, int n_inst, const pic_buffers *bufs, vo
     for (int i = 0; i < n_inst; ++i) {
         c->mcc_any = c->mcc_any || cfgs[i].mcc_on;
         c->src_any = c->src_any || cfgs[i].source_on;
+        c->periodic_any = c->periodic_any || cfgs[i].bc == PIC_BC_PERIODIC;
         for (int k = 0; k < cfgs[i].nsp; ++k) c->sub_any = c->sub_any || cfgs[i].sp[k].nstep > 1;
     }
 
@@ -695,19 +697,27 @@ int pic_sort(pic_ctx *c)
 
 namespace {
 
-// pic_push then pic_mcc_collide, with the same results: with collisions on,
-// each mover block collides its own region's candidates right after its push,
-// and the collide kernel takes only the shared overflow list
-int push_and_collide(pic_ctx *c)
+// pic_push, pic_mcc_collide and pic_field_solve, with the same results: with
+// collisions on, each mover block collides its own region's candidates right
+// after its push, and the collide kernel takes only the shared overflow list;
+// with no periodic instance the close of the step runs as one more block of
+// the field's first launch instead of a launch of its own
+int step_once(pic_ctx *c)
 {
+    int close_mode = -1;
+    int *defer = c->periodic_any ? nullptr : &close_mode;
+    bool ok;
     if (!c->mcc_any) {
         const int rc = pic_push(c, 0);
-        return rc ? rc : pic_mcc_collide(c);
+        if (rc) return rc;
+        ok = launch_emit(c->d, c->st, c->src_any, false, defer) == hipSuccess;
+    } else {
+        ok = launch_push(c->d, c->st, true, true, c->sub_any, c->chunks, true) == hipSuccess &&
+             launch_collide(c->d, c->st, true) == hipSuccess &&
+             launch_emit(c->d, c->st, true, true, defer) == hipSuccess;
     }
-    if (launch_push(c->d, c->st, true, true, c->sub_any, c->chunks, true) != hipSuccess ||
-        launch_collide(c->d, c->st, true) != hipSuccess ||
-        launch_emit(c->d, c->st, true, true) != hipSuccess)
-        return PIC_E_DEVICE;
+    ok = ok && launch_field(c->d, c->st, c->max_smooth, close_mode) == hipSuccess;
+    if (!ok) return PIC_E_DEVICE;
     c->host_steps += 1;
     return PIC_OK;
 }
@@ -721,8 +731,7 @@ int pic_step(pic_ctx *c, int n_steps, int sort_every)
     if (!c) return PIC_E_STATE;
     if (n_steps < 0 || sort_every < 0) return PIC_E_ARG;
     for (int s = 0; s < n_steps; ++s) {
-        int rc = push_and_collide(c);
-        if (!rc) rc = pic_field_solve(c);
+        int rc = step_once(c);
         if (!rc && sort_every > 0 && ((c->cfg[0].step0 + c->host_steps) % sort_every) == 0)
             rc = pic_sort(c);
         if (rc) return rc;
@@ -736,8 +745,7 @@ namespace {
 int enqueue_period(pic_ctx *c, int n, bool sort)
 {
     for (int s = 0; s < n; ++s) {
-        int rc = push_and_collide(c);
-        if (!rc) rc = pic_field_solve(c);
+        const int rc = step_once(c);
         if (rc) return rc;
     }
     return sort ? pic_sort(c) : PIC_OK;

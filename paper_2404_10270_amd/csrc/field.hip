@@ -31,8 +31,11 @@
 // which the collisions gather at the electrons.  An instance without a field
 // solve (the paper's Table 1 case) gets E = phi = 0; when no instance solves
 // the field, the first launch alone runs (rho, the neutral density, the
-// deposit cleared).
+// deposit cleared).  Inside a whole step with no periodic instance, the
+// first launch takes one block more, which closes the step (step_close.h):
+// nothing else in the solve reads what the close writes.
 #include "device_common.h"
+#include "step_close.h"
 
 #pragma clang fp contract(off)
 
@@ -115,9 +118,17 @@ enum { kRhoSolve = 0, kRhoFromRho = 1, kRhoNoSolve = 2 };
 // mode kRhoSolve: rho (and the neutral density) from the deposit, and the
 // composites; kRhoFromRho: rho is already in place (smoothed), only the
 // composites; kRhoNoSolve: rho and the neutral density, the deposit cleared,
-// no composites (no instance solves the field)
-__global__ __launch_bounds__(kBlock) void field_rho_kernel(Dev d, int mode)
+// no composites (no instance solves the field).  CLOSE: the last block
+// closes the step instead (close_step, mode close_mode).
+template <bool CLOSE>
+__global__ __launch_bounds__(kBlock) void field_rho_kernel(Dev d, int mode, int close_mode)
 {
+    if constexpr (CLOSE) {
+        if (blockIdx.x == gridDim.x - 1) {  // block-uniform
+            close_step(d, close_mode);
+            return;
+        }
+    }
     const bool from_rho = (mode == kRhoFromRho);
     const int64_t vt = blockIdx.x;
     const int inst = seg_of_tile(d.inst_ftile0, d.n_inst, vt);
@@ -651,16 +662,17 @@ __global__ __launch_bounds__(kBlock) void field_smooth_kernel(Dev d, const doubl
     out[g] = last ? r / vol(jj) : r;
 }
 
-hipError_t launch_field(const Dev &d, hipStream_t st, int smooth)
+hipError_t launch_field(const Dev &d, hipStream_t st, int smooth, int close_mode)
 {
     const dim3 grid((unsigned)d.n_field_tiles), block(kBlock);
-    if (d.field_all_off) {
-        hipLaunchKernelGGL(field_rho_kernel, grid, block, 0, st, d, (int)kRhoNoSolve);
-        return hipGetLastError();
-    }
-    hipLaunchKernelGGL(field_rho_kernel, grid, block, 0, st, d, (int)kRhoSolve);
+    // the first launch, with one block more when it closes the step
+    const int mode0 = d.field_all_off ? (int)kRhoNoSolve : (int)kRhoSolve;
+    if (close_mode >= 0)
+        hipLaunchKernelGGL(field_rho_kernel<true>, dim3(grid.x + 1), block, 0, st, d, mode0, close_mode);
+    else
+        hipLaunchKernelGGL(field_rho_kernel<false>, grid, block, 0, st, d, mode0, -1);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess || d.field_all_off) return e;
     if (smooth > 0) {
         // passes alternate between rho and the d' array (free until the forward sweep)
         const dim3 ng((unsigned)((d.G + kBlock - 1) / kBlock));
@@ -679,7 +691,7 @@ hipError_t launch_field(const Dev &d, hipStream_t st, int smooth)
             e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
-        hipLaunchKernelGGL(field_rho_kernel, grid, block, 0, st, d, (int)kRhoFromRho);
+        hipLaunchKernelGGL(field_rho_kernel<false>, grid, block, 0, st, d, (int)kRhoFromRho, -1);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -275,14 +275,17 @@ hipError_t launch_init_device(const Dev &d, hipStream_t st);
 hipError_t launch_push(const Dev &d, hipStream_t st, bool deposit, bool mcc, bool subcycled, int chunks,
                        bool collide);
 hipError_t launch_deposit(const Dev &d, hipStream_t st);
-// smooth: the most density-smoother passes of any instance
-hipError_t launch_field(const Dev &d, hipStream_t st, int smooth);
+// smooth: the most density-smoother passes of any instance; close_mode >= 0:
+// the first launch also closes the step (close_step's mode; no instance may
+// have a periodic background, whose rho reads the counts the close updates)
+hipError_t launch_field(const Dev &d, hipStream_t st, int smooth, int close_mode = -1);
 // overflow_only: after movers that collided their own regions (launch_push
 // with collide), only the shared overflow list is left
 hipError_t launch_collide(const Dev &d, hipStream_t st, bool overflow_only);
 // ionisation and source pairs (when `pairs`), then the close of the step
-// (`events`: collisions ran this step)
-hipError_t launch_emit(const Dev &d, hipStream_t st, bool pairs, bool events);
+// (`events`: collisions ran this step); with `deferred_close`, the close is
+// not launched and its mode is stored there, for launch_field
+hipError_t launch_emit(const Dev &d, hipStream_t st, bool pairs, bool events, int *deferred_close = nullptr);
 hipError_t launch_sort(const Dev &d, hipStream_t st);
 hipError_t launch_diag(const Dev &d, hipStream_t st);
 
