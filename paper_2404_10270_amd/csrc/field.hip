@@ -452,26 +452,35 @@ __global__ __launch_bounds__(kBlock) void field_bwd_kernel(Dev d)
 {
     const int64_t vt = blockIdx.x;
     const int inst = seg_of_tile(d.inst_ftile0, d.n_inst, vt);
+    // the instance's and its species' constants read once, before any store
+    // (read after the stores below, the compiler would read them again per
+    // node and wait for every store before it)
     const InstConst &ic = d.instc[inst];
-    const int64_t ntl = d.inst_ftile0[inst + 1] - ic.ftile0;
-    const int64_t lt = vt - ic.ftile0;
+    const int64_t ftile0 = ic.ftile0, gnode = ic.gnode;
+    const int64_t ntl = d.inst_ftile0[inst + 1] - ftile0;
+    const int64_t lt = vt - ftile0;
     const int nc = ic.nc;
     const bool periodic = (ic.bc == PIC_BC_PERIODIC);
+    const bool field_off = ic.field_off != 0;
     const int64_t G = d.G;
     const int nsp = ic.nsp;
-    const double dx = ic.dx;
+    const double dx = ic.dx, K = ic.K, eps0 = ic.eps0;
     const int64_t lo = lt * kFieldTile;
+    double accC[PIC_MAX_SPECIES];  // a species past nsp repeats the last one, unused
+#pragma unroll
+    for (int k = 0; k < PIC_MAX_SPECIES; ++k) accC[k] = d.segc[ic.seg0 + min(k, nsp - 1)].accC;
 
     // the thread's rho for the forward sweep (thread t: nodes lo + t kFieldR
     // up), loaded before the first wait (unpredicated: a node past nc reads
-    // node nc and is not used)
+    // node nc and is not used), and rho at the walls
     const int64_t ja = lo + (int64_t)threadIdx.x * kFieldR;
     double rl[kFieldR];
 #pragma unroll
-    for (int r = 0; r < kFieldR; ++r) rl[r] = d.rho[ic.gnode + min(ja + r, (int64_t)nc)];
+    for (int r = 0; r < kFieldR; ++r) rl[r] = d.rho[gnode + min(ja + r, (int64_t)nc)];
+    const double rho_0 = d.rho[gnode], rho_nc = d.rho[gnode + nc];
 
     double y_in, phi_above, dp_top;
-    tile_level(d, ic.ftile0, ntl, lt, y_in, phi_above, dp_top);
+    tile_level(d, ftile0, ntl, lt, y_in, phi_above, dp_top);
 
     // forward sweep of the tile from the d' entering it
     double dv[kFieldR];
@@ -481,7 +490,7 @@ __global__ __launch_bounds__(kBlock) void field_bwd_kernel(Dev d)
         const int64_t j = ja + r;
         dv[r] = 0.0;
         if (j >= 1 && j <= nc - 1) {
-            dv[r] = -(rl[r] * ic.K);
+            dv[r] = -(rl[r] * K);
             const double gq = gq_of(j);
             mf = compose(Aff{gq, -(gq * dv[r])}, mf);
         }
@@ -578,29 +587,33 @@ __global__ __launch_bounds__(kBlock) void field_bwd_kernel(Dev d)
                 V = 0.0;
             }
         } else if (j == 0) {
-            E = -(pr - pc) / dx - d.rho[ic.gnode] * dx / (2.0 * ic.eps0);
+            E = -(pr - pc) / dx - rho_0 * dx / (2.0 * eps0);
             V = 0.5 * dx;
         } else {  // j == nc, absorbing
-            E = -(pc - pl) / dx + d.rho[ic.gnode + nc] * dx / (2.0 * ic.eps0);
+            E = -(pc - pl) / dx + rho_nc * dx / (2.0 * eps0);
             V = 0.5 * dx;
         }
-        if (ic.field_off) E = 0.0;  // no field solve in this instance
-        d.phi[ic.gnode + j] = ic.field_off ? 0.0 : pc;
+        if (field_off) E = 0.0;  // no field solve in this instance
+        d.phi[gnode + j] = field_off ? 0.0 : pc;
         if (!(periodic && j == nc)) {
-            d.E[ic.gnode + j] = E;
+            d.E[gnode + j] = E;
             fe += E * E * V;
-            for (int k = 0; k < nsp; ++k) {
-                const double a = d.segc[ic.seg0 + k].accC * E;
-                d.acc64[k * G + ic.gnode + j] = a;
-                d.acc32[k * G + ic.gnode + j] = (float)a;
+#pragma unroll
+            for (int k = 0; k < PIC_MAX_SPECIES; ++k) {
+                if (k >= nsp) break;
+                const double a = accC[k] * E;
+                d.acc64[k * G + gnode + j] = a;
+                d.acc32[k * G + gnode + j] = (float)a;
                 if (periodic && j == 0) {
-                    d.acc64[k * G + ic.gnode + nc] = a;
-                    d.acc32[k * G + ic.gnode + nc] = (float)a;
+                    d.acc64[k * G + gnode + nc] = a;
+                    d.acc32[k * G + gnode + nc] = (float)a;
                 }
             }
-            if (periodic && j == 0) d.E[ic.gnode + nc] = E;
+            if (periodic && j == 0) d.E[gnode + nc] = E;
         }
-        for (int k = 0; k < nsp; ++k) d.S[k * G + ic.gnode + j] = 0ull;
+#pragma unroll
+        for (int k = 0; k < PIC_MAX_SPECIES; ++k)
+            if (k < nsp) d.S[k * G + gnode + j] = 0ull;
     }
     // field-energy partial of the tile (1/2 eps0 applied by the diagnostics)
     // (a halving tree: the two levels across waves through LDS, the six
@@ -618,7 +631,7 @@ __global__ __launch_bounds__(kBlock) void field_bwd_kernel(Dev d)
             const double o = __shfl_down(v, s, 64);
             if (threadIdx.x < s) v += o;
         }
-        if (threadIdx.x == 0) d.fe_part[ic.ftile0 + lt] = v;
+        if (threadIdx.x == 0) d.fe_part[ftile0 + lt] = v;
     }
 }
 
