@@ -598,15 +598,26 @@ __global__ __launch_bounds__(kBlock) void emit_kernel(Dev d)
 
 // A single instance without kinetic neutrals: the rank of each ionisation
 // event among the step's events by parent id taken here, so that no rank
-// kernel runs.  Block b takes the events of group g = b (+ k grid) of 64:
-// wave 0 first reads and draws everything its 64 pairs need except the rank
-// (those loads then run beside the ranking), every wave compares the group's
-// 64 parent ids (one per lane) against a quarter of all parent ids, staged
-// in LDS in chunks, the four partial ranks are summed in LDS and wave 0
-// places the 64 pairs.
+// kernel runs.  Block b takes the events of group g = b (+ k grid) of 64.
+// Every block stages all parent ids in LDS (their loads issued beside the
+// group's event loads, once when they fit and every id is below 2^32, else
+// per chunk), wave 0 reads and draws everything its 64 pairs need except the
+// rank, every wave compares the group's 64 parent ids (one per lane) against
+// a quarter of the staged ids, the four partial ranks are summed in LDS and
+// wave 0 places the 64 pairs.  The constants of the instance's segments are
+// read into LDS while the event index is built.
 constexpr int kRankChunk = 4096;  // parent ids per LDS chunk
 
-// what placing an ionisation pair needs besides its rank (no kinetic neutrals)
+// the constants a pair of a parent segment needs (no kinetic neutrals)
+struct PairSeg {
+    PlaceSeg pe, pi;  // the electron's and the ion's segment
+    uint32_t key0, key1;
+    double sig_n;     // the ion segment's neutral Maxwellian
+    long long step;
+    unsigned long long next_id;
+};
+
+// what placing an ionisation pair needs besides its rank
 struct IzPair {
     PlaceSeg pe, pi;
     unsigned long long next_id;
@@ -616,18 +627,9 @@ struct IzPair {
     double ev[3], iv[3];  // velocities of the new electron and ion
 };
 
-__device__ __forceinline__ IzPair prepare_pair(const Dev &d, int cur, bool f64, const IzEvent &ev)
+// the parent's position (unchanged by the collision)
+__device__ __forceinline__ void parent_position(const Dev &d, int cur, bool f64, const IzEvent &ev, IzPair &q)
 {
-    IzPair q;
-    const SegConst &se = d.segc[ev.seg];
-    const int seg_i = se.partner;
-    const SegConst &si = d.segc[seg_i];
-    const InstDyn &idn = d.instd[ev.inst];
-    const long long step = idn.step;
-    q.next_id = idn.next_id;
-    q.pe = place_seg(d, ev.seg);
-    q.pi = place_seg(d, seg_i);
-    const double sig_n = si.sig_n;
     q.cell = 0;
     q.f = 0.f;
     q.x = 0.0;
@@ -636,8 +638,16 @@ __device__ __forceinline__ IzPair prepare_pair(const Dev &d, int cur, bool f64, 
         q.cell = d.cell[cur][ev.slot];
         q.f = ((const float *)d.x[cur])[ev.slot];
     }
-    const uint4 u1 = draw(ev.parent_id, step, 1, se.key0, se.key1);
-    const uint4 u2 = draw(ev.parent_id, step, 2, se.key0, se.key1);
+}
+
+// the draws and velocities of event ev's pair, with its segment's constants
+__device__ __forceinline__ void prepare_pair(const PairSeg &P, const IzEvent &ev, IzPair &q)
+{
+    q.next_id = P.next_id;
+    q.pe = P.pe;
+    q.pi = P.pi;
+    const uint4 u1 = draw(ev.parent_id, P.step, 1, P.key0, P.key1);
+    const uint4 u2 = draw(ev.parent_id, P.step, 2, P.key0, P.key1);
     double d0, d1, d2;
     iso_dir(u1.z, u1.w, d0, d1, d2);
     double n0, n1, n2, n3;
@@ -646,50 +656,62 @@ __device__ __forceinline__ IzPair prepare_pair(const Dev &d, int cur, bool f64, 
     q.ev[0] = ev.g2 * d0;
     q.ev[1] = ev.g2 * d1;
     q.ev[2] = ev.g2 * d2;
-    q.iv[0] = sig_n * n0;
-    q.iv[1] = sig_n * n1;
-    q.iv[2] = sig_n * n2;
-    return q;
+    q.iv[0] = P.sig_n * n0;
+    q.iv[1] = P.sig_n * n1;
+    q.iv[2] = P.sig_n * n2;
 }
 
-// every parent id of the step into s_pid[0, total) (total <= kRankChunk), by
-// region rather than by event: thread t takes regions t, t + kBlock, ... and
-// loads up to kStageK events of each before its first wait (a region rarely
-// holds more; the rest, and the overflow list, follow in plain loops)
+// every parent id of the step into LDS, by region rather than by event:
+// thread t takes regions t, t + kBlock, ... and loads up to kStageK events of
+// each before its first wait (a region rarely holds more; the rest, and the
+// overflow list, follow in plain loops).  In two halves, so that a block can
+// issue other loads between them.  T: the id (unsigned long long) or its low
+// word (uint32_t, when every id is below 2^32).
 constexpr int kStageK = 4;
+constexpr int kRegT = (kMaxPushBlocks + kBlock - 1) / kBlock;
 
-__device__ __forceinline__ void stage_pids(const EventIndex &X, const Dev &d, unsigned long long *s_pid,
-                                           uint32_t *s_pid32)
+template <typename T>
+__device__ __forceinline__ T pid_of(const IzEvent &ev)
 {
-    // s_pid32 (not null): the low words only, into s_pid32[0, total)
-    auto put = [&](uint32_t i, unsigned long long v) {
-        if (s_pid32) s_pid32[i] = (uint32_t)v;
-        else s_pid[i] = v;
-    };
-    constexpr int kRegT = (kMaxPushBlocks + kBlock - 1) / kBlock;
-    const int nb = d.n_push_blocks;
-    unsigned long long v[kRegT][kStageK];
+    if constexpr (sizeof(T) == 4) return *reinterpret_cast<const uint32_t *>(&ev.parent_id);  // the low word
+    else return ev.parent_id;
+}
+
+template <typename T>
+struct PidStage {
+    T v[kRegT][kStageK];
     uint32_t dst[kRegT], n[kRegT];
+};
+
+template <typename T>
+__device__ __forceinline__ void stage_pids_load(const EventIndex &X, const Dev &d, PidStage<T> &P)
+{
+    const int nb = d.n_push_blocks;
 #pragma unroll
     for (int r = 0; r < kRegT; ++r) {
         const int b = threadIdx.x + r * kBlock;
         const bool ok = b < nb;
-        dst[r] = ok ? X.pre[b] : 0u;
-        n[r] = ok ? X.pre[b + 1] - X.pre[b] : 0u;
+        P.dst[r] = ok ? X.pre[b] : 0u;
+        P.n[r] = ok ? X.pre[b + 1] - X.pre[b] : 0u;
 #pragma unroll
         for (int k = 0; k < kStageK; ++k)
-            v[r][k] = ((uint32_t)k < n[r]) ? d.ev[(int64_t)b * d.ev_q + k].parent_id : 0ull;
+            P.v[r][k] = ((uint32_t)k < P.n[r]) ? pid_of<T>(d.ev[(int64_t)b * d.ev_q + k]) : T(0);
     }
+}
+
+template <typename T>
+__device__ __forceinline__ void stage_pids_put(const EventIndex &X, const Dev &d, const PidStage<T> &P, T *s)
+{
 #pragma unroll
     for (int r = 0; r < kRegT; ++r) {
 #pragma unroll
         for (int k = 0; k < kStageK; ++k)
-            if ((uint32_t)k < n[r]) put(dst[r] + k, v[r][k]);
+            if ((uint32_t)k < P.n[r]) s[P.dst[r] + k] = P.v[r][k];
         const int b = threadIdx.x + r * kBlock;
-        for (uint32_t k = kStageK; k < n[r]; ++k) put(dst[r] + k, d.ev[(int64_t)b * d.ev_q + k].parent_id);
+        for (uint32_t k = kStageK; k < P.n[r]; ++k) s[P.dst[r] + k] = pid_of<T>(d.ev[(int64_t)b * d.ev_q + k]);
     }
     for (uint32_t e = X.in_regions + threadIdx.x; e < X.total; e += kBlock)
-        put(e, d.ev[(int64_t)d.n_regions * d.ev_q + (e - X.in_regions)].parent_id);
+        s[e] = pid_of<T>(d.ev[(int64_t)d.n_regions * d.ev_q + (e - X.in_regions)]);
 }
 
 __global__ __launch_bounds__(kBlock) void emit_ranked_kernel(Dev d)
@@ -697,31 +719,57 @@ __global__ __launch_bounds__(kBlock) void emit_ranked_kernel(Dev d)
     __shared__ EventIndex X;
     __shared__ __align__(16) unsigned long long s_pid[kRankChunk];
     __shared__ uint32_t s_part[kWaves][64];
+    __shared__ PairSeg s_ps[PIC_MAX_SPECIES];
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
     const uint32_t n_src = source_pairs(d, 0);  // read first: in flight beside the index
+    // the constants of the instance's segments (one thread each; per-lane
+    // loads, which unlike uniform scalar loads do not hold up the index's
+    // LDS operations), into LDS once the index is built
+    const int nsp = d.n_seg;  // a single instance: its segments are 0 .. nsp - 1
+    PairSeg ps = {};
+    const bool ps_mine = wave == 0 && lane < nsp && d.segc[lane].partner >= 0;
     build_event_index(X, d);
+    if (ps_mine) {
+        const SegConst &se = d.segc[lane];
+        const InstDyn &idn = d.instd[se.inst];
+        ps.pe = place_seg(d, lane);
+        ps.pi = place_seg(d, se.partner);
+        ps.key0 = se.key0;
+        ps.key1 = se.key1;
+        ps.sig_n = d.segc[se.partner].sig_n;
+        ps.step = idn.step;
+        ps.next_id = idn.next_id;
+    }
     const int cur = d.glob->cur_set;
     const bool f64 = (d.precision == PIC_FP64);
     const uint32_t m = X.total;
-    const int lane = lane_id(), wave = threadIdx.x >> 6;
     const uint32_t n_groups = (m + 63u) / 64u;
     if (blockIdx.x == 0 && threadIdx.x == 0) d.glob->ev_total = m;  // for the close kernel
     // every id below 2^32: the ranks compare the low words, four per LDS read
     const bool narrow = d.instd[0].wide_ids == 0u && m <= (uint32_t)kRankChunk;
     uint32_t *s_pid32 = reinterpret_cast<uint32_t *>(s_pid);
+    bool staged = false;  // the narrow ids are in LDS (block-uniform)
     for (uint32_t g = blockIdx.x; g < n_groups; g += gridDim.x) {  // block-uniform
         const uint32_t e = g * 64u + (uint32_t)lane;
         const bool mine = e < m;
+        PidStage<uint32_t> P32;
+        if (narrow && !staged) stage_pids_load<uint32_t>(X, d, P32);
         IzEvent ev = {};
         if (mine) ev = event_at(X, d, e);
         IzPair q = {};
-        if (wave == 0 && mine) q = prepare_pair(d, cur, f64, ev);
+        if (wave == 0 && mine) parent_position(d, cur, f64, ev, q);
+        if (ps_mine) s_ps[lane] = ps;
         uint32_t r = 0;
         if (narrow) {
-            __syncthreads();  // the previous group's readers are done
-            stage_pids(X, d, s_pid, s_pid32);
-            const uint32_t n4 = (m + 3u) & ~3u;  // padded with ids no parent has below it
-            for (uint32_t i = m + threadIdx.x; i < n4; i += kBlock) s_pid32[i] = 0xFFFFFFFFu;
+            if (!staged) {
+                stage_pids_put<uint32_t>(X, d, P32, s_pid32);
+                const uint32_t n4 = (m + 3u) & ~3u;  // padded with ids no parent has below it
+                for (uint32_t i = m + threadIdx.x; i < n4; i += kBlock) s_pid32[i] = 0xFFFFFFFFu;
+                staged = true;
+            }
             __syncthreads();
+            if (wave == 0 && mine) prepare_pair(s_ps[ev.seg], ev, q);
+            const uint32_t n4 = (m + 3u) & ~3u;
             const uint32_t q0 = ((uint32_t)wave * (n4 / 4u) / kWaves) * 4u;
             const uint32_t q1 = ((uint32_t)(wave + 1) * (n4 / 4u) / kWaves) * 4u;
             if (mine) {
@@ -736,11 +784,15 @@ __global__ __launch_bounds__(kBlock) void emit_ranked_kernel(Dev d)
         } else {
             for (uint32_t c0 = 0; c0 < m; c0 += kRankChunk) {
                 const uint32_t cn = min((uint32_t)kRankChunk, m - c0);
-                __syncthreads();  // the previous chunk's readers are done
-                if (m <= (uint32_t)kRankChunk) stage_pids(X, d, s_pid, nullptr);
-                else
-                    for (uint32_t i = threadIdx.x; i < cn; i += kBlock)
-                        s_pid[i] = event_at(X, d, c0 + i).parent_id;
+                __syncthreads();  // the previous chunk's readers are done (and s_ps is in place)
+                if (c0 == 0 && wave == 0 && mine) prepare_pair(s_ps[ev.seg], ev, q);
+                if (m <= (uint32_t)kRankChunk) {
+                    PidStage<unsigned long long> P64;
+                    stage_pids_load<unsigned long long>(X, d, P64);
+                    stage_pids_put<unsigned long long>(X, d, P64, s_pid);
+                } else {
+                    for (uint32_t i = threadIdx.x; i < cn; i += kBlock) s_pid[i] = event_at(X, d, c0 + i).parent_id;
+                }
                 __syncthreads();
                 const uint32_t q0 = (uint32_t)wave * cn / kWaves, q1 = (uint32_t)(wave + 1) * cn / kWaves;
                 if (mine) {
