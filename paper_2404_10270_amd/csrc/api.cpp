@@ -308,6 +308,8 @@ int plan(const pic_config *cfgs, int n_inst, Plan &p)
     L.seg_start = take(sizeof(uint64_t) * n_seg);
     L.fwd_status = take(sizeof(AffineStatus) * p.n_field_tiles);
     L.bwd_status = take(sizeof(BackStatus) * p.n_field_tiles);
+    L.sweep = take(sizeof(NodeSweep) * p.n_field_tiles * kFieldTile);
+    L.bpre = take(sizeof(BackStatus) * p.n_field_tiles * kBlock);
     L.sort_status = take(sizeof(uint64_t) * p.n_sort_tiles);
     L.fe_part = take(sizeof(double) * p.n_field_tiles);
     // candidates: one region per push block, sized so that a block holds
@@ -555,6 +557,8 @@ int init_context(const pic_config *cfgs, int n_inst, const pic_buffers *bufs, vo
     d.seg_start = at<unsigned long long>(W, L.seg_start);
     d.fwd_status = at<AffineStatus>(W, L.fwd_status);
     d.bwd_status = at<BackStatus>(W, L.bwd_status);
+    d.sweep = at<NodeSweep>(W, L.sweep);
+    d.bpre = at<BackStatus>(W, L.bpre);
     d.sort_status = at<unsigned long long>(W, L.sort_status);
     d.fe_part = at<double>(W, L.fe_part);
     d.cand = at<Cand>(W, L.cand);

@@ -18,11 +18,12 @@
 // exchange between tiles and the solve takes two launches, with no atomics
 // and no waiting between blocks:
 //   1. rho; each tile's forward composite and its backward composite as a
-//      function of the d' entering it;
+//      function of the d' entering it; each node's d'(0) and h, and each
+//      thread's composite of the backward maps above its nodes in the tile;
 //   2. every block scans the tiles' composites of its instance: the d'
 //      entering its tile from below and the phi entering it from above; then
-//      the tile's forward sweep (d'), backward sweep (phi), E, the
-//      accelerations and the field energy.
+//      each thread's d' = d'(0) + h y and phi with no scan inside the tile,
+//      E, the accelerations and the field energy.
 // Same recurrences as the sequential sweep, regrouped; only the rounding
 // order differs.
 //
@@ -277,25 +278,38 @@ __global__ __launch_bounds__(kBlock) void field_rho_kernel(Dev d, int mode, int 
         const int64_t j = j0 + r;
         if (j >= 1 && j <= nc - 1) mb = compose3(Aff3{gq_of(j), d0[r], h[r]}, mb);
     }
-    // the block's composite: threads from the top down, i.e. an ordered tree
-    // over i = kBlock - 1 - thread.  Inside a wave index i is lane 63 - l of
-    // group 3 - wave, so each level takes the lane s below.
+    // the nodes' forward terms, for the second launch
+    NodeSweep *sw = d.sweep + vt * kFieldTile + (int64_t)threadIdx.x * kFieldR;
+#pragma unroll
+    for (int r = 0; r < kFieldR; ++r) sw[r] = NodeSweep{d0[r], h[r]};
+    // the backward maps of the threads above each thread (a scan from the top
+    // of the tile down), and the tile's composite: inside a wave, lane l
+    // takes the lanes above it, s at a time
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
+    Aff3 inc = mb;  // this lane's map after those of the lanes above it
 #pragma unroll
     for (int s = 1; s < 64; s <<= 1) {
         Aff3 o;
-        o.A = __shfl_up(mb.A, s, 64);
-        o.B0 = __shfl_up(mb.B0, s, 64);
-        o.B1 = __shfl_up(mb.B1, s, 64);
-        if (((63 - lane) & (2 * s - 1)) == 0) mb = compose3(o, mb);
+        o.A = __shfl_down(inc.A, s, 64);
+        o.B0 = __shfl_down(inc.B0, s, 64);
+        o.B1 = __shfl_down(inc.B1, s, 64);
+        if (lane + s < 64) inc = compose3(inc, o);
     }
-    static_assert(kWaves == 4, "the cross-wave levels below are written for four waves");
+    Aff3 ex;  // the lanes above this one
+    ex.A = __shfl_down(inc.A, 1, 64);
+    ex.B0 = __shfl_down(inc.B0, 1, 64);
+    ex.B1 = __shfl_down(inc.B1, 1, 64);
+    if (lane == 63) ex = Aff3{1.0, 0.0, 0.0};
     __shared__ Aff3 s_b[kWaves];
-    if (lane == 63) s_b[wave] = mb;  // the composite of group 3 - wave
+    if (lane == 0) s_b[wave] = inc;  // the wave's composite
     __syncthreads();
+    Aff3 above = {1.0, 0.0, 0.0};  // the waves above this one, top first
+    for (int w = kWaves - 1; w > wave; --w) above = compose3(s_b[w], above);
+    const Aff3 pre = compose3(ex, above);
+    d.bpre[vt * kBlock + threadIdx.x] = BackStatus{pre.A, pre.B0, pre.B1};
     if (threadIdx.x == 0) {
-        const Aff3 r = compose3(compose3(s_b[0], s_b[1]), compose3(s_b[2], s_b[3]));
+        const Aff3 r = compose3(inc, above);
         d.bwd_status[vt].A = r.A;
         d.bwd_status[vt].B0 = r.B0;
         d.bwd_status[vt].B1 = r.B1;
@@ -383,6 +397,84 @@ __device__ void tile_level_r(const Dev &d, int64_t first, int64_t ntl, int64_t l
     dp_top = agg.B;
 }
 
+// the same inside every wave on its own (no LDS, no barrier), for instances
+// of up to 64 R tiles: lane l takes runs of per = ceil(ntl / 64) <= R tiles
+template <int R>
+__device__ void tile_level_w(const Dev &d, int64_t first, int64_t ntl, int64_t lt, double &y_in,
+                             double &phi_above, double &dp_top)
+{
+    const int lane = lane_id();
+    const int64_t per = (ntl + 63) / 64;
+    const int64_t n_runs = (ntl + per - 1) / per;
+    // lane l: forward run l, backward run n_runs - 1 - l
+    const int64_t a0 = (int64_t)lane * per;
+    const int64_t a1 = min(a0 + per, ntl);
+    const int64_t q = n_runs - 1 - (int64_t)lane;
+    const int64_t b0 = q >= 0 ? q * per : 0;
+    const int64_t b1 = q >= 0 ? min(b0 + per, ntl) : 0;
+    const AffineStatus one = {1.0, 0.0};
+    const BackStatus bone = {1.0, 0.0, 0.0};
+    AffineStatus F[R], FB[R];
+    BackStatus B[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        F[i] = (a0 + i < a1) ? d.fwd_status[first + a0 + i] : one;
+        FB[i] = (b0 + i < b1) ? d.fwd_status[first + b0 + i] : one;
+        B[i] = (b0 + i < b1) ? d.bwd_status[first + b0 + i] : bone;
+    }
+    // forward: the runs' composites scanned from the bottom up
+    Aff m = {1.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+        if (a0 + i < a1) m = compose(Aff{F[i].A, F[i].B}, m);
+    Aff inc = m;
+#pragma unroll
+    for (int s = 1; s < 64; s <<= 1) {
+        const Aff o = shfl_up_aff(inc, s);
+        if (lane >= s) inc = compose(inc, o);
+    }
+    Aff ex = shfl_up_aff(inc, 1);
+    if (lane == 0) ex = Aff{1.0, 0.0};
+    const double y_run = ex.B;  // d' entering this lane's run (d'_0 = 0)
+    {
+        double y = y_run;
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+            if (a0 + i < lt) y = F[i].A * y + F[i].B;
+        y_in = __shfl(y, (int)(lt / per), 64);  // from the lane whose run holds tile lt
+    }
+    dp_top = __shfl(inc.B, 63, 64);
+    // backward: each tile's map with the d' entering it, from the top down
+    Aff bk[R];
+    {
+        double y = __shfl(y_run, (int)(q >= 0 ? q : 0), 64);
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            bk[i] = Aff{B[i].A, B[i].B0 + B[i].B1 * y};
+            y = FB[i].A * y + FB[i].B;
+        }
+    }
+    Aff mb = {1.0, 0.0};
+#pragma unroll
+    for (int i = R - 1; i >= 0; --i)
+        if (b0 + i < b1) mb = compose(bk[i], mb);
+    Aff incb = mb;
+#pragma unroll
+    for (int s = 1; s < 64; s <<= 1) {
+        const Aff o = shfl_up_aff(incb, s);
+        if (lane >= s) incb = compose(incb, o);
+    }
+    Aff exb = shfl_up_aff(incb, 1);
+    if (lane == 0) exb = Aff{1.0, 0.0};
+    {
+        Aff M = exb;
+#pragma unroll
+        for (int i = R - 1; i >= 0; --i)
+            if (b0 + i < b1 && b0 + i > lt) M = compose(bk[i], M);
+        phi_above = __shfl(M.B, (int)(n_runs - 1 - lt / per), 64);  // from the lane whose run holds tile lt
+    }
+}
+
 // the same for runs of any length, read tile by tile
 __device__ void tile_level_any(const Dev &d, int64_t first, int64_t ntl, int64_t lt, double &y_in,
                                double &phi_above, double &dp_top)
@@ -439,14 +531,16 @@ __device__ void tile_level_any(const Dev &d, int64_t first, int64_t ntl, int64_t
 __device__ __forceinline__ void tile_level(const Dev &d, int64_t first, int64_t ntl, int64_t lt, double &y_in,
                                            double &phi_above, double &dp_top)
 {
-    if (ntl <= kBlock) tile_level_r<1>(d, first, ntl, lt, y_in, phi_above, dp_top);
+    if (ntl <= 64) tile_level_w<1>(d, first, ntl, lt, y_in, phi_above, dp_top);
+    else if (ntl <= 128) tile_level_w<2>(d, first, ntl, lt, y_in, phi_above, dp_top);
+    else if (ntl <= 256) tile_level_w<4>(d, first, ntl, lt, y_in, phi_above, dp_top);
     else if (ntl <= (int64_t)kRunR * kBlock) tile_level_r<kRunR>(d, first, ntl, lt, y_in, phi_above, dp_top);
     else tile_level_any(d, first, ntl, lt, y_in, phi_above, dp_top);
 }
 
 // ---------------------------------------------------------------------------
-// 2. the values entering the tile, forward sweep (d'), backward sweep (phi),
-//    E, acc, field-energy partials; clears the deposit
+// 2. the values entering the tile, d' and phi of its nodes, E, acc,
+//    field-energy partials; clears the deposit
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void field_bwd_kernel(Dev d)
 {
@@ -464,87 +558,35 @@ __global__ __launch_bounds__(kBlock) void field_bwd_kernel(Dev d)
     const bool field_off = ic.field_off != 0;
     const int64_t G = d.G;
     const int nsp = ic.nsp;
-    const double dx = ic.dx, K = ic.K, eps0 = ic.eps0;
+    const double dx = ic.dx, eps0 = ic.eps0;
     const int64_t lo = lt * kFieldTile;
     double accC[PIC_MAX_SPECIES];  // a species past nsp repeats the last one, unused
 #pragma unroll
     for (int k = 0; k < PIC_MAX_SPECIES; ++k) accC[k] = d.segc[ic.seg0 + min(k, nsp - 1)].accC;
 
-    // the thread's rho for the forward sweep (thread t: nodes lo + t kFieldR
-    // up), loaded before the first wait (unpredicated: a node past nc reads
-    // node nc and is not used), and rho at the walls
-    const int64_t ja = lo + (int64_t)threadIdx.x * kFieldR;
-    double rl[kFieldR];
+    // the thread's nodes (thread t: nodes lo + t kFieldR up): their forward
+    // terms and the backward maps of the threads above them, loaded before
+    // the first wait, and rho at the walls
+    const int64_t c = threadIdx.x;
+    const int64_t j0 = lo + c * kFieldR;
+    NodeSweep sw[kFieldR];
 #pragma unroll
-    for (int r = 0; r < kFieldR; ++r) rl[r] = d.rho[gnode + min(ja + r, (int64_t)nc)];
+    for (int r = 0; r < kFieldR; ++r) sw[r] = d.sweep[vt * kFieldTile + c * kFieldR + r];
+    const BackStatus bp = d.bpre[vt * kBlock + c];
     const double rho_0 = d.rho[gnode], rho_nc = d.rho[gnode + nc];
 
     double y_in, phi_above, dp_top;
     tile_level(d, ftile0, ntl, lt, y_in, phi_above, dp_top);
 
-    // forward sweep of the tile from the d' entering it
-    double dv[kFieldR];
-    Aff mf = {1.0, 0.0};
-#pragma unroll
-    for (int r = 0; r < kFieldR; ++r) {
-        const int64_t j = ja + r;
-        dv[r] = 0.0;
-        if (j >= 1 && j <= nc - 1) {
-            dv[r] = -(rl[r] * K);
-            const double gq = gq_of(j);
-            mf = compose(Aff{gq, -(gq * dv[r])}, mf);
-        }
-    }
-    Aff aggf;
-    const Aff exf = block_exclusive_scan(mf, &aggf);
-    // d' of the thread's nodes, handed through LDS to the backward sweep's
-    // threads, which count their chunks from the top of the tile
-    __shared__ double s_dp[kFieldTile];
-    {
-        double y = exf.A * y_in + exf.B;
-#pragma unroll
-        for (int r = 0; r < kFieldR; ++r) {
-            const int64_t j = ja + r;
-            double v = 0.0;
-            if (j >= 1 && j <= nc - 1) {
-                const double gq = gq_of(j);
-                y = gq * y + (-(gq * dv[r]));
-                v = y;
-            }
-            s_dp[threadIdx.x * kFieldR + r] = v;
-        }
-    }
-    __syncthreads();
-
-    // thread t owns the chunk counted from the top of the tile
-    const int64_t c = kBlock - 1 - threadIdx.x;
-    const int64_t j0 = lo + c * kFieldR;
-    double dl[kFieldR];
-#pragma unroll
-    for (int r = 0; r < kFieldR; ++r) dl[r] = s_dp[c * kFieldR + r];
-
-    double dp[kFieldR];
-    Aff m = {1.0, 0.0};
-#pragma unroll
-    for (int r = kFieldR - 1; r >= 0; --r) {
-        const int64_t j = j0 + r;
-        dp[r] = 0.0;
-        if (j >= 1 && j <= nc - 1) {
-            dp[r] = dl[r];
-            m = compose(Aff{gq_of(j), dp[r]}, m);
-        }
-    }
-    Aff agg;
-    const Aff excl = block_exclusive_scan(m, &agg);
-
-    // phi for the thread's nodes, top down
+    // d' = d0 + h y_in at each node, and phi from the top down, entering the
+    // thread's nodes with the maps of the threads above applied to phi_above
     double ph[kFieldR];
-    double y = excl.A * phi_above + excl.B;
+    double y = bp.A * phi_above + (bp.B0 + bp.B1 * y_in);
 #pragma unroll
     for (int r = kFieldR - 1; r >= 0; --r) {
         const int64_t j = j0 + r;
         if (j >= 1 && j <= nc - 1) {
-            y = gq_of(j) * y + dp[r];
+            y = gq_of(j) * y + (sw[r].d0 + sw[r].h * y_in);
             ph[r] = y;
         } else {
             ph[r] = 0.0;  // nodes 0 and nc (and beyond the grid)

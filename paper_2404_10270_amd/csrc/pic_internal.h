@@ -174,6 +174,12 @@ struct BackStatus {
     double A, B0, B1;
 };
 
+// a field node's forward-sweep terms: d' = d0 + h y for the d' y entering
+// its tile from below
+struct NodeSweep {
+    double d0, h;
+};
+
 // ---------------------------------------------------------------------------
 // workspace layout (byte offsets into pic_buffers.work)
 // ---------------------------------------------------------------------------
@@ -182,7 +188,7 @@ struct Layout {
     uint64_t seg_tile0, seg_base, inst_ftile0, node_base;
     uint64_t S, rho, phi, E, dprime, acc64, acc32;
     uint64_t hist, cursor, offsets, seg_start;
-    uint64_t fwd_status, bwd_status, sort_status;
+    uint64_t fwd_status, bwd_status, sort_status, sweep, bpre;
     uint64_t fe_part;
     uint64_t cand, cand_n, ev, ev_n, ev_rank, cnt_slot;
     uint64_t nn, ev_crank, ev_target, ev_pre;
@@ -220,6 +226,8 @@ struct Dev {
     unsigned long long *seg_start;      // [n_seg] first raw sort position of each segment
     AffineStatus *fwd_status;
     BackStatus *bwd_status;
+    NodeSweep *sweep;   // [n_field_tiles * kFieldTile] per node, tile by tile
+    BackStatus *bpre;   // [n_field_tiles * kBlock] backward maps above each thread's nodes
     unsigned long long *sort_status;
     double *fe_part;
     Cand *cand;                 // [n_regions][cand_q] per-block regions, then the overflow list
