@@ -663,12 +663,15 @@ __device__ __forceinline__ void prepare_pair(const PairSeg &P, const IzEvent &ev
 
 // every parent id of the step into LDS, by region rather than by event:
 // thread t takes regions t, t + kBlock, ... and loads up to kStageK events of
-// each before its first wait (a region rarely holds more; the rest, and the
-// overflow list, follow in plain loops).  In two halves, so that a block can
-// issue other loads between them.  T: the id (unsigned long long) or its low
-// word (uint32_t, when every id is below 2^32).
+// each of its first kStageRows regions before its first wait (a region rarely
+// holds more; the rest, further regions and the overflow list follow in
+// plain loops).  The first regions' loads and stores are separate calls, so
+// that a block can issue other loads between them; staging all of a thread's
+// regions at once would hold twice the registers and halve the kernel's
+// waves per SIMD.  T: the id (unsigned long long) or its low word (uint32_t,
+// when every id is below 2^32).
 constexpr int kStageK = 4;
-constexpr int kRegT = (kMaxPushBlocks + kBlock - 1) / kBlock;
+constexpr int kStageRows = 4;  // regions per thread staged at once (all of them up to 1024 regions)
 
 template <typename T>
 __device__ __forceinline__ T pid_of(const IzEvent &ev)
@@ -679,17 +682,18 @@ __device__ __forceinline__ T pid_of(const IzEvent &ev)
 
 template <typename T>
 struct PidStage {
-    T v[kRegT][kStageK];
-    uint32_t dst[kRegT], n[kRegT];
+    T v[kStageRows][kStageK];
+    uint32_t dst[kStageRows], n[kStageRows];
 };
 
+// the regions threadIdx.x + (r0 + r) kBlock, r < kStageRows
 template <typename T>
-__device__ __forceinline__ void stage_pids_load(const EventIndex &X, const Dev &d, PidStage<T> &P)
+__device__ __forceinline__ void stage_pids_load(const EventIndex &X, const Dev &d, int r0, PidStage<T> &P)
 {
     const int nb = d.n_push_blocks;
 #pragma unroll
-    for (int r = 0; r < kRegT; ++r) {
-        const int b = threadIdx.x + r * kBlock;
+    for (int r = 0; r < kStageRows; ++r) {
+        const int b = threadIdx.x + (r0 + r) * kBlock;
         const bool ok = b < nb;
         P.dst[r] = ok ? X.pre[b] : 0u;
         P.n[r] = ok ? X.pre[b + 1] - X.pre[b] : 0u;
@@ -700,15 +704,27 @@ __device__ __forceinline__ void stage_pids_load(const EventIndex &X, const Dev &
 }
 
 template <typename T>
-__device__ __forceinline__ void stage_pids_put(const EventIndex &X, const Dev &d, const PidStage<T> &P, T *s)
+__device__ __forceinline__ void stage_pids_put(const Dev &d, int r0, const PidStage<T> &P, T *s)
 {
 #pragma unroll
-    for (int r = 0; r < kRegT; ++r) {
+    for (int r = 0; r < kStageRows; ++r) {
 #pragma unroll
         for (int k = 0; k < kStageK; ++k)
             if ((uint32_t)k < P.n[r]) s[P.dst[r] + k] = P.v[r][k];
-        const int b = threadIdx.x + r * kBlock;
+        const int b = threadIdx.x + (r0 + r) * kBlock;
         for (uint32_t k = kStageK; k < P.n[r]; ++k) s[P.dst[r] + k] = pid_of<T>(d.ev[(int64_t)b * d.ev_q + k]);
+    }
+}
+
+// the rest after the first kStageRows rows: the other regions, and the
+// overflow list
+template <typename T>
+__device__ __forceinline__ void stage_pids_rest(const EventIndex &X, const Dev &d, T *s)
+{
+    for (int r0 = kStageRows; r0 * kBlock < d.n_push_blocks; r0 += kStageRows) {  // uniform
+        PidStage<T> P;
+        stage_pids_load<T>(X, d, r0, P);
+        stage_pids_put<T>(d, r0, P, s);
     }
     for (uint32_t e = X.in_regions + threadIdx.x; e < X.total; e += kBlock)
         s[e] = pid_of<T>(d.ev[(int64_t)d.n_regions * d.ev_q + (e - X.in_regions)]);
@@ -753,7 +769,7 @@ __global__ __launch_bounds__(kBlock) void emit_ranked_kernel(Dev d)
         const uint32_t e = g * 64u + (uint32_t)lane;
         const bool mine = e < m;
         PidStage<uint32_t> P32;
-        if (narrow && !staged) stage_pids_load<uint32_t>(X, d, P32);
+        if (narrow && !staged) stage_pids_load<uint32_t>(X, d, 0, P32);
         IzEvent ev = {};
         if (mine) ev = event_at(X, d, e);
         IzPair q = {};
@@ -762,7 +778,8 @@ __global__ __launch_bounds__(kBlock) void emit_ranked_kernel(Dev d)
         uint32_t r = 0;
         if (narrow) {
             if (!staged) {
-                stage_pids_put<uint32_t>(X, d, P32, s_pid32);
+                stage_pids_put<uint32_t>(d, 0, P32, s_pid32);
+                stage_pids_rest<uint32_t>(X, d, s_pid32);
                 const uint32_t n4 = (m + 3u) & ~3u;  // padded with ids no parent has below it
                 for (uint32_t i = m + threadIdx.x; i < n4; i += kBlock) s_pid32[i] = 0xFFFFFFFFu;
                 staged = true;
@@ -788,8 +805,9 @@ __global__ __launch_bounds__(kBlock) void emit_ranked_kernel(Dev d)
                 if (c0 == 0 && wave == 0 && mine) prepare_pair(s_ps[ev.seg], ev, q);
                 if (m <= (uint32_t)kRankChunk) {
                     PidStage<unsigned long long> P64;
-                    stage_pids_load<unsigned long long>(X, d, P64);
-                    stage_pids_put<unsigned long long>(X, d, P64, s_pid);
+                    stage_pids_load<unsigned long long>(X, d, 0, P64);
+                    stage_pids_put<unsigned long long>(d, 0, P64, s_pid);
+                    stage_pids_rest<unsigned long long>(X, d, s_pid);
                 } else {
                     for (uint32_t i = threadIdx.x; i < cn; i += kBlock) s_pid[i] = event_at(X, d, c0 + i).parent_id;
                 }

@@ -254,6 +254,7 @@ struct Dev {
     int32_t kinetic_any;        // some instance has a kinetic neutral species (with MCC on)
     int32_t cand_q, ev_q;       // entries per block region of the candidate and event lists
     int32_t field_all_off;      // no instance solves the field
+    int32_t late_flush;         // the FP32 mover flushes its deposit window after the next pass's loads
 };
 
 // a particle's id from its two words

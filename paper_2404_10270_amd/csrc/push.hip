@@ -275,8 +275,9 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
     const int wave = threadIdx.x >> 6;
     uint32_t wn = 0;  // this wave's candidates so far (uniform)
     // the deposit window of the wave's previous pass, flushed once the next
-    // pass's loads are issued (its global atomics would otherwise stand, on
-    // the in-order memory counter, between those loads and their wait)
+    // pass's loads are issued when d.late_flush (its global atomics would
+    // otherwise stand, on the in-order memory counter, between those loads
+    // and their wait), else at the end of its own pass
     int dlo = 0, dspan = 0;
     unsigned long long *dS = nullptr;
 
@@ -528,6 +529,10 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
             if (DEP) {
                 deposit_accumulate<NP>(L.wdep[wave], S, key, w1, dlo, dspan);
                 dS = S;
+                if (!d.late_flush && dspan > 0) {  // uniform
+                    deposit_flush(L.wdep[wave], S, dlo, dspan);
+                    dspan = 0;
+                }
             }
         }
     }

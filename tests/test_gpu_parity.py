@@ -173,6 +173,28 @@ def test_push_fp32_tolerance(name):
     sim.close()
 
 
+@pytest.mark.parametrize("nc", [300, 300_000], ids=["deposit_in_l2", "deposit_beyond_l2"])
+def test_push_fp32_fused_deposit_matches_the_deposit_kernel(nc):
+    """The FP32 mover's fused deposit flushes its window after the next pass's
+    loads when the deposit array fits in 4 MiB (2 species x 301 nodes) and at
+    the end of each pass otherwise (2 x 300,001 nodes x 8 B = 4.8 MB): either
+    way it equals, node for node, the deposit kernel's of the positions it
+    wrote (that kernel is bit-exact against the oracle in
+    test_deposit_bit_exact)."""
+    wl = pin.bounded(nc=nc, ppc=37.3 if nc < 1000 else 2, seed=31)
+    flush(f"fused deposit fp32 nc={nc}")
+    sim = P.PicSim(wl, None, FP32, flags=P.PIC_INIT_DEVICE)
+    sim.push()
+    S1 = sim.grid(P.PIC_R_DEPOSIT).astype(np.uint64)
+    sim.deposit()  # adds the same positions again
+    S2 = sim.grid(P.PIC_R_DEPOSIT).astype(np.uint64) - S1
+    d, _ = sim.diagnostics()
+    for k in range(2):
+        assert np.array_equal(S1[k], S2[k])
+        assert int(S1[k].sum(dtype=np.uint64)) == int(d[0].n_live[k]) * 2 ** 32
+    sim.close()
+
+
 @pytest.mark.parametrize("prec", [FP32, FP64], ids=["fp32", "fp64"])
 def test_mcc_one_step(prec):
     """Push + collisions + ionisation pairs + source for one step, on the oracle's field."""
