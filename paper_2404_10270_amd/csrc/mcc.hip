@@ -601,11 +601,11 @@ __global__ __launch_bounds__(kBlock) void emit_kernel(Dev d)
 // kernel runs.  Block b takes the events of group g = b (+ k grid) of 64.
 // Every block stages all parent ids in LDS (their loads issued beside the
 // group's event loads, once when they fit and every id is below 2^32, else
-// per chunk), wave 0 reads and draws everything its 64 pairs need except the
-// rank, every wave compares the group's 64 parent ids (one per lane) against
-// a quarter of the staged ids, the four partial ranks are summed in LDS and
-// wave 0 places the 64 pairs.  The constants of the instance's segments are
-// read into LDS while the event index is built.
+// per chunk), wave 0 draws everything its 64 pairs need except the rank while
+// the other waves compare the group's 64 parent ids (one per lane) against a
+// third of the staged ids each, the partial ranks are summed in LDS and wave
+// 0 places the 64 pairs.  The constants of the instance's segments are read
+// into LDS while the event index is built.
 constexpr int kRankChunk = 4096;  // parent ids per LDS chunk
 
 // the constants a pair of a parent segment needs (no kinetic neutrals)
@@ -786,10 +786,12 @@ __global__ __launch_bounds__(kBlock) void emit_ranked_kernel(Dev d)
             }
             __syncthreads();
             if (wave == 0 && mine) prepare_pair(s_ps[ev.seg], ev, q);
+            // waves 1 .. kWaves - 1 compare while wave 0 draws
             const uint32_t n4 = (m + 3u) & ~3u;
-            const uint32_t q0 = ((uint32_t)wave * (n4 / 4u) / kWaves) * 4u;
-            const uint32_t q1 = ((uint32_t)(wave + 1) * (n4 / 4u) / kWaves) * 4u;
-            if (mine) {
+            const uint32_t wc = wave > 0 ? (uint32_t)wave - 1u : 0u;
+            const uint32_t q0 = (wc * (n4 / 4u) / (kWaves - 1)) * 4u;
+            const uint32_t q1 = ((wc + 1u) * (n4 / 4u) / (kWaves - 1)) * 4u;
+            if (mine && wave > 0) {
                 const uint32_t pid = (uint32_t)ev.parent_id;
 #pragma unroll 4
                 for (uint32_t k = q0; k < q1; k += 4) {
@@ -812,8 +814,11 @@ __global__ __launch_bounds__(kBlock) void emit_ranked_kernel(Dev d)
                     for (uint32_t i = threadIdx.x; i < cn; i += kBlock) s_pid[i] = event_at(X, d, c0 + i).parent_id;
                 }
                 __syncthreads();
-                const uint32_t q0 = (uint32_t)wave * cn / kWaves, q1 = (uint32_t)(wave + 1) * cn / kWaves;
-                if (mine) {
+                // the first chunk: waves 1 .. kWaves - 1 compare while wave 0 draws
+                const uint32_t nw = c0 == 0 ? (uint32_t)kWaves - 1u : (uint32_t)kWaves;
+                const uint32_t wc = c0 == 0 ? (wave > 0 ? (uint32_t)wave - 1u : 0u) : (uint32_t)wave;
+                const uint32_t q0 = wc * cn / nw, q1 = (wc + 1u) * cn / nw;
+                if (mine && (c0 > 0 || wave > 0)) {
                     const unsigned long long pid = ev.parent_id;
 #pragma unroll 8
                     for (uint32_t k = q0; k < q1; ++k) r += s_pid[k] < pid ? 1u : 0u;

@@ -121,6 +121,11 @@ struct InstDyn {
     unsigned long long n_consumed, n_iz_untargeted, n_excite;
 };
 
+// the movers' work queues: kUnitCtrs counters (grabs, waves done), one per
+// 128-byte line
+constexpr int kUnitCtrs = 32;
+constexpr int kUnitCtrStride = 32;  // 32-bit words between counters
+
 struct Globals {
     int32_t cur_set;
     uint32_t cand_ovf;       // candidates in the overflow list this step
@@ -133,6 +138,8 @@ struct Globals {
     uint32_t scan_ticket[4];
     uint32_t scan_finish[4];
     unsigned long long scan_gen[4];
+    // the movers' unit counters (zero at set-up; each launch leaves them zero)
+    unsigned int unit_ctr[kUnitCtrs * kUnitCtrStride];
 };
 
 enum ScanId { kScanSort = 2 };

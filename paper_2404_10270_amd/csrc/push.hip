@@ -131,6 +131,66 @@ __device__ __forceinline__ int tile_seg(const PushLds &L, const Dev &d, int64_t 
     return __builtin_amdgcn_readfirstlane(seg);
 }
 
+// The movers take their tiles dynamically, so that a block slowed by where
+// its tiles lie in memory does not hold up the launch.  Block b starts on
+// tile b; the tiles past the grid are handed out by K = min(kUnitCtrs,
+// blocks) counters, interleaved (counter k: tiles blocks + k, blocks + k +
+// K, ...), so that the taken tiles still form one front sweeping the arrays;
+// block b takes from counter b % K.  Wave 0 issues the grab for the block's
+// next tile once the loads of the tile in hand are issued (tile_grab; on
+// one in-order memory counter, a grab issued before them would hold them
+// up), else at the end of the tile, and hands the result to the other waves
+// through LDS at the block's one barrier per tile.  A block whose grab finds
+// the counter exhausted issues no more and adds itself to the counter's done
+// count; the last block of the counter's group sets both back to zero for
+// the next launch (no grab of this launch can follow: every block of the
+// group has made its last).
+struct TileQueue {
+    unsigned int *ctr;   // [0]: grabs, [1]: blocks done
+    uint32_t n_mine;     // tiles of this counter
+    uint32_t n_blocks;   // blocks taking from this counter
+    uint32_t k, K, first;
+    uint32_t pending;    // the last grab (lane 0 of wave 0)
+    bool grabbed;        // a grab was issued since the last tile was taken
+};
+
+__device__ __forceinline__ void tile_queue_init(TileQueue &Q, const Dev &d)
+{
+    const uint32_t nb = gridDim.x;
+    const uint32_t nt = (uint32_t)d.n_tiles;
+    Q.K = nb < (uint32_t)kUnitCtrs ? nb : (uint32_t)kUnitCtrs;
+    Q.k = blockIdx.x % Q.K;
+    Q.first = nb;
+    Q.ctr = d.glob->unit_ctr + Q.k * kUnitCtrStride;
+    const uint32_t rest = nt > nb ? nt - nb : 0u;
+    Q.n_mine = rest > Q.k ? (rest - Q.k + Q.K - 1) / Q.K : 0u;
+    Q.n_blocks = (nb - Q.k + Q.K - 1) / Q.K;
+    Q.pending = 0u;
+    Q.grabbed = false;
+}
+
+__device__ __forceinline__ void tile_grab(TileQueue &Q)
+{
+    Q.pending = lane_id() == 0 ? atomicAdd(Q.ctr, 1u) : 0u;
+    Q.grabbed = true;
+}
+
+// the block's next tile, -1 when its counter is exhausted (wave 0)
+__device__ __forceinline__ int64_t tile_next(TileQueue &Q)
+{
+    if (!Q.grabbed) tile_grab(Q);
+    Q.grabbed = false;
+    const uint32_t i = (uint32_t)__builtin_amdgcn_readfirstlane((int)Q.pending);
+    if (i >= Q.n_mine) {
+        if (lane_id() == 0 && atomicAdd(Q.ctr + 1, 1u) == Q.n_blocks - 1u) {
+            atomicExch(Q.ctr, 0u);
+            atomicExch(Q.ctr + 1, 0u);
+        }
+        return -1;
+    }
+    return (int64_t)Q.first + Q.k + (int64_t)i * Q.K;
+}
+
 // Deposit the kPer chunks of this wave through its own LDS window (no block
 // barrier: the waves of a block run through their tiles independently).
 template <int NP>
@@ -294,19 +354,25 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
     uint32_t key0 = 0, key1 = 0;
     unsigned long long T = 0;
     long long step = 0;
-    for (int64_t t = blockIdx.x; t < d.n_tiles; t += gridDim.x) {
+    TileQueue Q;
+    tile_queue_init(Q, d);
+    __shared__ int64_t s_next[2];  // the block's next tile, by parity of its tiles
+    int par = 0;
+    const int q = wave;  // the wave's part of each tile
+    const bool w0 = __builtin_amdgcn_readfirstlane(wave) == 0;
+    int64_t t = blockIdx.x;  // the grid never has more blocks than tiles
+    if (t < d.n_tiles) do {
         int64_t tile0, base, count;
         uint32_t flg;
         const int seg = tile_seg(L, d, t, tile0, base, count, flg, hint);
         const int64_t t0 = (t - tile0) * (int64_t)kTile;
-        if (t0 >= count) continue;
         // a subcycled species between its pushes keeps its positions (their
         // deposit is a launch of its own, deposit_kernel<true>)
-        if (d.n_seg > kSegLds && still(d, seg)) continue;
+        const bool work = t0 < count && !(d.n_seg > kSegLds && still(d, seg));
 
         // the tile in kPer / NP passes of NP chunks per wave (NP = kPer: one pass)
 #pragma unroll 1
-        for (int r0 = 0; r0 < kPer; r0 += NP) {
+        for (int r0 = 0; work && r0 < kPer; r0 += NP) {
             // a species with no collision process takes no test (no id read, no
             // draw); a species on which no field acts takes no gather
             const bool test = MCC && (flg & kFlgTest);
@@ -334,7 +400,7 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
                     // every id below 2^32: the low words are the ids
 #pragma unroll
                     for (int k = 0; k < NP; ++k) {
-                        const uint32_t o = (uint32_t)((wave * kPer + r0 + k) * 64 + lane);
+                        const uint32_t o = (uint32_t)((q * kPer + r0 + k) * 64 + lane);
                         j[k] = stream_ld(&CELLt[o]);
                         f[k] = stream_ld(&Xt[o]);
                         vx[k] = stream_ld(&VXt[o]);
@@ -345,7 +411,7 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
                 } else if (test) {
 #pragma unroll
                     for (int k = 0; k < NP; ++k) {
-                        const uint32_t o = (uint32_t)((wave * kPer + r0 + k) * 64 + lane);
+                        const uint32_t o = (uint32_t)((q * kPer + r0 + k) * 64 + lane);
                         j[k] = stream_ld(&CELLt[o]);
                         f[k] = stream_ld(&Xt[o]);
                         vx[k] = stream_ld(&VXt[o]);
@@ -357,7 +423,7 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
                 } else {
 #pragma unroll
                     for (int k = 0; k < NP; ++k) {
-                        const uint32_t o = (uint32_t)((wave * kPer + r0 + k) * 64 + lane);
+                        const uint32_t o = (uint32_t)((q * kPer + r0 + k) * 64 + lane);
                         j[k] = stream_ld(&CELLt[o]);
                         f[k] = stream_ld(&Xt[o]);
                         vx[k] = stream_ld(&VXt[o]);
@@ -369,7 +435,7 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
             } else {
 #pragma unroll
                 for (int k = 0; k < NP; ++k) {
-                    const uint32_t o = (uint32_t)((wave * kPer + r0 + k) * 64 + lane);
+                    const uint32_t o = (uint32_t)((q * kPer + r0 + k) * 64 + lane);
                     j[k] = kDeadCell;
                     f[k] = vx[k] = vy[k] = vz[k] = 0.f;
                     pid[k] = 0;
@@ -390,6 +456,7 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
                 deposit_flush(L.wdep[wave], dS, dlo, dspan);
                 dspan = 0;
             }
+            if (w0 && r0 == 0) tile_grab(Q);  // the next tile, behind this one's loads
 #pragma unroll
             for (int k = 0; k < NP; ++k) lv[k] = j[k] >= 0;
             // the segment's constants, read once the tile's loads are issued
@@ -489,7 +556,7 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
             // ---- stores (no reads after this point in the tile touch these arrays)
 #pragma unroll
             for (int k = 0; k < NP; ++k) {
-                const uint32_t o = (uint32_t)((wave * kPer + r0 + k) * 64 + lane);
+                const uint32_t o = (uint32_t)((q * kPer + r0 + k) * 64 + lane);
                 if (o < rem && lv[k]) {
                     stream_st(&Xt[o], f[k]);
                     stream_st(&CELLt[o], j[k]);
@@ -522,7 +589,7 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
             if (MCC) {
 #pragma unroll
                 for (int k = 0; k < NP; ++k) {
-                    const uint32_t o = (uint32_t)((wave * kPer + r0 + k) * 64 + lane);
+                    const uint32_t o = (uint32_t)((q * kPer + r0 + k) * 64 + lane);
                     queue_candidate(d, cand[k], (uint32_t)(tb + o), seg, inst, vx[k], vy[k], vz[k], pid[k], wn);
                 }
             }
@@ -535,7 +602,16 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
                 }
             }
         }
-    }
+        // the block's next tile, from wave 0
+        if (w0) {
+            const int64_t n = tile_next(Q);
+            if (lane_id() == 0) s_next[par] = n;
+        }
+        __syncthreads();
+        t = uniform_i64(s_next[par]);
+        par ^= 1;
+    } while (t >= 0);
+    else if (w0) (void)tile_next(Q);  // (no tile for this block: its counter still counts it done)
     if (DEP && dspan > 0) deposit_flush(L.wdep[wave], dS, dlo, dspan);
     if (MCC) flush_candidates(d, wn);
     if constexpr (MCC && COLL) collide_own_region(L, d, wn);
@@ -576,18 +652,24 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     unsigned long long T = 0;
     int inst = 0;
     long long step = 0;
-    for (int64_t t = blockIdx.x; t < d.n_tiles; t += gridDim.x) {
+    TileQueue Q;
+    tile_queue_init(Q, d);
+    __shared__ int64_t s_next[2];  // the block's next tile, by parity of its tiles
+    int par = 0;
+    const int q = wave;  // the wave's part of each tile
+    const bool w0 = __builtin_amdgcn_readfirstlane(wave) == 0;
+    int64_t t = blockIdx.x;  // the grid never has more blocks than tiles
+    if (t < d.n_tiles) do {
         int64_t tile0, base, count;
         uint32_t flg;
         const int seg = tile_seg(L, d, t, tile0, base, count, flg, hint);
         const int64_t t0 = (t - tile0) * (int64_t)kTile;
-        if (t0 >= count) continue;
         // a subcycled species between its pushes keeps its positions (their
         // deposit is a launch of its own, deposit_kernel<true>)
-        if (d.n_seg > kSegLds && still(d, seg)) continue;
+        const bool work = t0 < count && !(d.n_seg > kSegLds && still(d, seg));
         // the tile in kPer / NP passes of NP chunks per wave (NP = kPer: one pass)
 #pragma unroll 1
-        for (int r0 = 0; r0 < kPer; r0 += NP) {
+        for (int r0 = 0; work && r0 < kPer; r0 += NP) {
             const bool test = MCC && (flg & kFlgTest);
             const bool force = (flg & kFlgForce) != 0;
 
@@ -607,7 +689,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                     // every id below 2^32: the low words are the ids
 #pragma unroll
                     for (int k = 0; k < NP; ++k) {
-                        const uint32_t o = (uint32_t)((wave * kPer + r0 + k) * 64 + lane);
+                        const uint32_t o = (uint32_t)((q * kPer + r0 + k) * 64 + lane);
                         x[k] = stream_ld(&Xt[o]);
                         vx[k] = stream_ld(&VXt[o]);
                         vy[k] = stream_ld(&VYt[o]);
@@ -617,7 +699,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                 } else if (test) {
 #pragma unroll
                     for (int k = 0; k < NP; ++k) {
-                        const uint32_t o = (uint32_t)((wave * kPer + r0 + k) * 64 + lane);
+                        const uint32_t o = (uint32_t)((q * kPer + r0 + k) * 64 + lane);
                         x[k] = stream_ld(&Xt[o]);
                         vx[k] = stream_ld(&VXt[o]);
                         vy[k] = stream_ld(&VYt[o]);
@@ -628,7 +710,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                 } else {
 #pragma unroll
                     for (int k = 0; k < NP; ++k) {
-                        const uint32_t o = (uint32_t)((wave * kPer + r0 + k) * 64 + lane);
+                        const uint32_t o = (uint32_t)((q * kPer + r0 + k) * 64 + lane);
                         x[k] = stream_ld(&Xt[o]);
                         vx[k] = stream_ld(&VXt[o]);
                         vy[k] = stream_ld(&VYt[o]);
@@ -639,7 +721,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             } else {
 #pragma unroll
                 for (int k = 0; k < NP; ++k) {
-                    const uint32_t o = (uint32_t)((wave * kPer + r0 + k) * 64 + lane);
+                    const uint32_t o = (uint32_t)((q * kPer + r0 + k) * 64 + lane);
                     x[k] = kDeadX;
                     vx[k] = vy[k] = vz[k] = 0.0;
                     pid[k] = 0;
@@ -655,6 +737,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                     }
                 }
             }
+            if (w0 && r0 == 0) tile_grab(Q);  // the next tile, behind this one's loads
             // the segment's constants, read once the tile's loads are issued
             // (their scalar loads share a counter with the LDS reads that
             // address the tile: read first, the tile's loads would wait for them)
@@ -750,7 +833,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             }
 #pragma unroll
             for (int k = 0; k < NP; ++k) {
-                const uint32_t o = (uint32_t)((wave * kPer + r0 + k) * 64 + lane);
+                const uint32_t o = (uint32_t)((q * kPer + r0 + k) * 64 + lane);
                 if (o < rem && live[k]) {
                     stream_st(&Xt[o], x[k]);
                     stream_st(&VXt[o], vx[k]);
@@ -779,13 +862,22 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             if (MCC) {
 #pragma unroll
                 for (int k = 0; k < NP; ++k) {
-                    const uint32_t o = (uint32_t)((wave * kPer + r0 + k) * 64 + lane);
+                    const uint32_t o = (uint32_t)((q * kPer + r0 + k) * 64 + lane);
                     queue_candidate(d, cand[k], (uint32_t)(tb + o), seg, inst, vx[k], vy[k], vz[k], pid[k], wn);
                 }
             }
             if (DEP) deposit_tile<NP>(L, S, key, w1);
         }
-    }
+        // the block's next tile, from wave 0
+        if (w0) {
+            const int64_t n = tile_next(Q);
+            if (lane_id() == 0) s_next[par] = n;
+        }
+        __syncthreads();
+        t = uniform_i64(s_next[par]);
+        par ^= 1;
+    } while (t >= 0);
+    else if (w0) (void)tile_next(Q);  // (no tile for this block: its counter still counts it done)
     if (MCC) flush_candidates(d, wn);
     if constexpr (MCC && COLL) collide_own_region(L, d, wn);
 }
