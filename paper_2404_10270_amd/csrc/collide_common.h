@@ -131,20 +131,27 @@ __device__ void collide_block(const Dev &d, int slot, bool region, bool ovf, con
         o_hi = min(novf, o_lo + per_block);
     }
     const uint32_t n_items = nr + (o_hi - o_lo);
-    for (uint32_t q = threadIdx.x; q < n_items; q += kBlock) {
-        uint32_t cnt = 0;  // one bit per process (1 << kC...)
-        bool iz = false;
-        IzEvent ev = {};
-        int64_t idx;
+    // item q's entry: the region's wave parts, then the overflow share
+    auto entry = [&](uint32_t q) -> int64_t {
         if (q < nr) {
             int w = 0;
 #pragma unroll
             for (int v = 1; v < kWaves; ++v) w += (q >= pre[v]) ? 1 : 0;
-            idx = (int64_t)slot * d.cand_q + (int64_t)w * qw + (q - pre[w]);
-        } else {
-            idx = (int64_t)d.n_regions * d.cand_q + o_lo + (q - nr);
+            return (int64_t)slot * d.cand_q + (int64_t)w * qw + (q - pre[w]);
         }
-        const int seg = collide_one<SEGLDS>(d, cur, f64, d.cand[idx], s_sc, s_step, cnt, iz, ev);
+        return (int64_t)d.n_regions * d.cand_q + o_lo + (q - nr);
+    };
+    // each candidate's entry is loaded while the thread's previous one is
+    // collided (the loads would otherwise wait behind its stores)
+    Cand cn{};
+    if (threadIdx.x < n_items) cn = d.cand[entry(threadIdx.x)];
+    for (uint32_t q = threadIdx.x; q < n_items; q += kBlock) {
+        const Cand c = cn;
+        if (q + kBlock < n_items) cn = d.cand[entry(q + kBlock)];
+        uint32_t cnt = 0;  // one bit per process (1 << kC...)
+        bool iz = false;
+        IzEvent ev = {};
+        const int seg = collide_one<SEGLDS>(d, cur, f64, c, s_sc, s_step, cnt, iz, ev);
         if (iz) {
             // this block's region of the event list; the rare excess goes to the overflow list
             const uint32_t e = region ? atomicAdd(&s_en, 1u) : (uint32_t)d.ev_q;
@@ -167,11 +174,12 @@ __device__ void collide_block(const Dev &d, int slot, bool region, bool ovf, con
     __syncthreads();
     if (region && threadIdx.x == 0) d.ev_n[slot] = min(s_en, (uint32_t)d.ev_q);
     if (lds_cnt) {
-        // this block's own slot: plain read-modify-write, no other block touches it
+        // this block's own slot (no other block touches it), by atomics that
+        // return nothing, so that the block does not wait for a read of it
         unsigned long long *cs = d.cnt_slot + (int64_t)slot * d.n_seg * kNCnt;
         for (int q = threadIdx.x; q < d.n_seg * kNCnt; q += kBlock) {
             const uint32_t v = s_cnt[q];
-            if (v) cs[q] += v;
+            if (v) atomicAdd(cs + q, (unsigned long long)v);
         }
     }
 }
