@@ -47,7 +47,7 @@ SORT_EVERY = 20
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "push_f32_bounded_mcc_traffic.json")
 PUSH_SOURCES = ["paper_2404_10270_amd/csrc/push.hip", "paper_2404_10270_amd/csrc/device_common.h",
                 "paper_2404_10270_amd/csrc/pic_internal.h", "paper_2404_10270_amd/csrc/mover_common.h",
-                "paper_2404_10270_amd/csrc/collide_common.h"]
+                "paper_2404_10270_amd/csrc/collide_common.h", "paper_2404_10270_amd/csrc/tile_queue.h"]
 # the mover bench.py times for the roofline: pic_push's launch (push, deposit
 # and candidate list; the step's launch also collides the block's own
 # candidates)

@@ -18,6 +18,7 @@
 // of them can move from the cell the offsets list it in.
 // Segment starts come from the live counts, so absorbed particles need no bin.
 #include "device_common.h"
+#include "tile_queue.h"
 
 namespace picx {
 
@@ -41,6 +42,7 @@ struct SortLds {
     int64_t tile0[kSegLdsS + 1];
     int64_t sbase[kSegLdsS];
     uint32_t count[kSegLdsS];
+    uint32_t live0[kSegLdsS + 1];  // the scatter: live tiles of the segments before each
     int red[2][kWaves];
 };
 
@@ -381,16 +383,40 @@ __global__ __launch_bounds__(kBlock) void sort_scatter_kernel(Dev d)
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
     int hint = 0;  // segment of the previous tile
-    for (int64_t t = blockIdx.x; t < d.n_tiles; t += gridDim.x) {
+    // tiles taken dynamically (tile_queue.h); the next one is handed on at
+    // the barrier after the reservations
+    const uint32_t n_live = d.n_seg <= kSegLdsS ? live_tiles_init<kSegLdsS>(L, d) : (uint32_t)d.n_tiles;
+    TileQueue Q;
+    tile_queue_init(Q, d, n_live);
+    int lhint = 0;  // segment of the previous live tile
+    __shared__ int64_t s_next[2];  // the block's next tile, by parity of its tiles
+    int par = 0;
+    const bool w0 = __builtin_amdgcn_readfirstlane(wave) == 0;
+    auto hand_on = [&]() {
+        if (w0) {
+            const int64_t i = tile_next(Q);
+            const int64_t n = i >= 0 ? live_tile<kSegLdsS>(L, d, (uint32_t)i, lhint) : -1;
+            if (lane == 0) s_next[par] = n;
+        }
+    };
+    int64_t t = blockIdx.x < n_live ? live_tile<kSegLdsS>(L, d, blockIdx.x, lhint) : -1;
+    if (t >= 0) do {
         int64_t tile0, base, count;
         const int seg = sort_tile_seg(L, d, t, tile0, base, count, hint);
         const int64_t t0 = (t - tile0) * (int64_t)kTile;
-        if (t0 >= count) continue;
+        if (t0 >= count) {  // (only without the LDS tables: every tile is handed out)
+            hand_on();
+            __syncthreads();
+            t = tq_uniform_i64(s_next[par]);
+            par ^= 1;
+            continue;
+        }
         const SegConst &sc = d.segc[seg];
         const uint32_t start = (uint32_t)d.seg_start[seg];
         uint32_t *__restrict__ CUR = d.cursor + sc.sp * d.G + sc.gnode;
         int key[kPer];
         tile_keys(d, cur, base, t0, count, f64, key);
+        if (w0) tile_grab(Q);  // the next tile, behind this one's key loads
         int lo, hi;
         tile_window(L, key, lo, hi);
         // rank of every particle among the tile's particles of its cell
@@ -426,7 +452,10 @@ __global__ __launch_bounds__(kBlock) void sort_scatter_kernel(Dev d)
                 }
             }
         }
+        hand_on();
         __syncthreads();
+        const int64_t t_next = tq_uniform_i64(s_next[par]);
+        par ^= 1;
         // destinations; then every field of the tile's particles is loaded
         // before any is stored (a store to the other set could alias a later
         // load in the compiler's view, which would otherwise keep each load
@@ -482,7 +511,9 @@ __global__ __launch_bounds__(kBlock) void sort_scatter_kernel(Dev d)
                 atomicMax(vm, vb);
         }
         // the next tile's window barrier orders the reuse of L.base
-    }
+        t = t_next;
+    } while (t >= 0);
+    else if (w0) (void)tile_next(Q);  // (no tile for this block: its counter still counts it done)
 }
 
 // after the scatter (one block): switch sets and set the counts to the live particles
