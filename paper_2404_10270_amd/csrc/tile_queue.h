@@ -84,20 +84,20 @@ __device__ __forceinline__ int64_t live_tile(const Lds &L, const Dev &d, uint32_
 }
 
 // The movers and the sort's scatter take their tiles dynamically, so that a
-// block slowed by where its tiles lie in memory does not hold up the launch.  Tiles are counted
-// among the live ones (live_tiles_init).  Block b starts on live tile b; the
-// tiles past the grid are handed out by K = min(kUnitCtrs,
-// blocks) counters, interleaved (counter k: tiles blocks + k, blocks + k +
-// K, ...), so that the taken tiles still form one front sweeping the arrays;
-// block b takes from counter b % K.  Wave 0 issues the grab for the block's
-// next tile once the loads of the tile in hand are issued (tile_grab; on
-// one in-order memory counter, a grab issued before them would hold them
-// up), else at the end of the tile, and hands the result to the other waves
-// through LDS at the block's one barrier per tile.  A block whose grab finds
-// the counter exhausted issues no more and adds itself to the counter's done
-// count; the last block of the counter's group sets both back to zero for
-// the next launch (no grab of this launch can follow: every block of the
-// group has made its last).
+// block slowed by where its tiles lie in memory does not hold up the
+// launch.  Tiles are counted among the live ones (live_tiles_init).  Block b
+// starts on live tile b; the tiles past the grid are handed out by
+// K = min(kUnitCtrs, blocks) counters, interleaved (counter k: tiles
+// blocks + k, blocks + k + K, ...), so that the taken tiles still form one
+// front sweeping the arrays; block b takes from counter b % K.  Wave 0
+// issues the grab for the block's next tile once the loads of the tile in
+// hand are issued (tile_grab; on one in-order memory counter, a grab issued
+// before them would hold them up), else at the end of the tile, and hands
+// the result to the other waves through LDS at a block barrier.  A block
+// whose grab finds the counter exhausted issues no more and adds itself to
+// the counter's done count; the last block of the counter's group sets both
+// back to zero for the next launch (no grab of this launch can follow: every
+// block of the group has made its last).
 struct TileQueue {
     unsigned int *ctr;   // [0]: grabs, [1]: blocks done
     uint32_t n_mine;     // tiles of this counter
@@ -127,7 +127,8 @@ __device__ __forceinline__ void tile_grab(TileQueue &Q)
     Q.grabbed = true;
 }
 
-// the block's next tile, -1 when its counter is exhausted (wave 0)
+// the block's next live tile (an index for live_tile), -1 when its counter
+// is exhausted (wave 0)
 __device__ __forceinline__ int64_t tile_next(TileQueue &Q)
 {
     if (!Q.grabbed) tile_grab(Q);
