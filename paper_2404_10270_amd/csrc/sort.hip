@@ -17,6 +17,8 @@
 // atoms keep their velocity until the next sort, so it bounds how far any
 // of them can move from the cell the offsets list it in.
 // Segment starts come from the live counts, so absorbed particles need no bin.
+#include <type_traits>
+
 #include "device_common.h"
 #include "tile_queue.h"
 
@@ -95,48 +97,6 @@ __device__ __forceinline__ int sort_tile_seg(const SortLds &L, const Dev &d, int
     return seg;
 }
 
-// node of a slot, -1 when absorbed
-__device__ __forceinline__ int node_of(const Dev &d, int cur, int64_t g, bool f64)
-{
-    if (f64) {
-        const double x = ((const double *)d.x[cur])[g];
-        return x >= 0.0 ? (int)floor(x) : -1;
-    }
-    return d.cell[cur][g];
-}
-
-// the keys of this wave's kPer chunks of the tile at slot base + t0 (-1 past
-// count or absorbed).  A full tile loads unpredicated, with the precision
-// branch outside the chunk loop, so the wave issues every load before one
-// wait rather than waiting inside each chunk's branch.
-__device__ __forceinline__ void tile_keys(const Dev &d, int cur, int64_t base, int64_t t0, int64_t count,
-                                          bool f64, int (&key)[kPer])
-{
-    const int lane = lane_id();
-    const int wave = threadIdx.x >> 6;
-    if (t0 + kTile <= count) {
-        const int64_t g0 = base + t0 + (int64_t)(wave * kPer) * 64 + lane;
-        if (f64) {
-            const double *X = (const double *)d.x[cur] + g0;
-            double x[kPer];
-#pragma unroll
-            for (int k = 0; k < kPer; ++k) x[k] = __builtin_nontemporal_load(&X[k * 64]);
-#pragma unroll
-            for (int k = 0; k < kPer; ++k) key[k] = x[k] >= 0.0 ? (int)floor(x[k]) : -1;
-        } else {
-            const int32_t *CELL = d.cell[cur] + g0;
-#pragma unroll
-            for (int k = 0; k < kPer; ++k) key[k] = __builtin_nontemporal_load(&CELL[k * 64]);
-        }
-        return;
-    }
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-        const int64_t i = t0 + (int64_t)(wave * kPer + k) * 64 + lane;
-        key[k] = (i < count) ? node_of(d, cur, base + i, f64) : -1;
-    }
-}
-
 // block window [lo, hi] over the keys of this tile (barrier inside)
 __device__ __forceinline__ void tile_window(SortLds &L, const int (&key)[kPer], int &lo, int &hi)
 {
@@ -168,6 +128,63 @@ __device__ __forceinline__ void tile_window(SortLds &L, const int (&key)[kPer], 
     }
 }
 
+// the block's first tile holding particles at or after tile t (its stride:
+// the grid), -1 when none; its segment's values in seg, base, count, t0
+__device__ __forceinline__ int64_t hist_next_tile(const SortLds &L, const Dev &d, int64_t t, int &seg,
+                                                  int64_t &base, int64_t &count, int64_t &t0, int &hint)
+{
+    for (; t < d.n_tiles; t += gridDim.x) {
+        int64_t tile0;
+        seg = sort_tile_seg(L, d, t, tile0, base, count, hint);
+        t0 = (t - tile0) * (int64_t)kTile;
+        if (t0 < count) return t;
+    }
+    return -1;
+}
+
+// The raw keys of a wave's kPer chunks of a tile (in-segment slots
+// t0 + 64 (wave kPer + k) + lane): the cell (FP32 form) or the position
+// (FP64 form).  Slots past the segment's count load the tile's first slot
+// instead (their keys are -1), so that every tile issues the same loads.
+template <bool F64>
+using RawKey = typename std::conditional<F64, double, int32_t>::type;
+
+template <bool F64>
+__device__ __forceinline__ void load_raw_keys(const Dev &d, int cur, int64_t base, int64_t t0, int64_t count,
+                                              RawKey<F64> (&raw)[kPer])
+{
+    const int lane = lane_id();
+    const int wave = threadIdx.x >> 6;
+    const RawKey<F64> *src = F64 ? (const RawKey<F64> *)d.x[cur] : (const RawKey<F64> *)d.cell[cur];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int64_t i = t0 + (int64_t)(wave * kPer + k) * 64 + lane;
+        raw[k] = __builtin_nontemporal_load(&src[base + (i < count ? i : t0)]);
+    }
+}
+
+template <bool F64>
+__device__ __forceinline__ void raw_to_keys(const RawKey<F64> (&raw)[kPer], int64_t t0, int64_t count,
+                                            int (&key)[kPer])
+{
+    const int lane = lane_id();
+    const int wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const bool in = t0 + (int64_t)(wave * kPer + k) * 64 + lane < count;
+        if (F64) key[k] = in && raw[k] >= 0.0 ? (int)floor((double)raw[k]) : -1;
+        else key[k] = in ? (int)raw[k] : -1;
+    }
+}
+
+// Each wave requests its chunks of the block's next tile (and that tile's
+// segment values) before it adds the counts of the tile in hand to the
+// global bins: the loads and the atomics are then in flight together,
+// rather than each tile's loads waiting behind the previous tile's atomics
+// on the in-order memory counter.  Every pass issues the same loads (the
+// last one repeats its own tile's), so the wait for the tile in hand leaves
+// the next tile's loads in flight.
+template <bool F64>
 __global__ __launch_bounds__(kBlock) void sort_hist_kernel(Dev d)
 {
     __shared__ SortLds L;
@@ -175,20 +192,36 @@ __global__ __launch_bounds__(kBlock) void sort_hist_kernel(Dev d)
     for (int i = threadIdx.x; i < kWaves * kHistWaveWin; i += kBlock) (&wcnt[0][0])[i] = 0u;
     sort_lds_init(L, d);
     const int cur = d.glob->cur_set;
-    const bool f64 = (d.precision == PIC_FP64);
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
     uint32_t *W = wcnt[wave];
     int hint = 0;  // segment of the previous tile
-    for (int64_t t = blockIdx.x; t < d.n_tiles; t += gridDim.x) {
-        int64_t tile0, base, count;
-        const int seg = sort_tile_seg(L, d, t, tile0, base, count, hint);
-        const int64_t t0 = (t - tile0) * (int64_t)kTile;
-        if (t0 >= count) continue;
-        const SegConst &sc = d.segc[seg];
-        uint32_t *__restrict__ H = d.hist + sc.sp * d.G + sc.gnode;
+    int seg = 0;
+    int64_t base = 0, count = 0, t0 = 0;
+    int64_t t = hist_next_tile(L, d, blockIdx.x, seg, base, count, t0, hint);
+    if (t < 0) return;
+    // the segment's bins: species and first node, read beside its keys
+    int sp = d.segc[seg].sp;
+    int64_t gnode = d.segc[seg].gnode;
+    RawKey<F64> raw[kPer];
+    load_raw_keys<F64>(d, cur, base, t0, count, raw);
+    while (t >= 0) {
+        int nseg = seg;
+        int64_t nbase = base, ncount = count, nt0 = t0;
+        const int64_t tn = hist_next_tile(L, d, t + gridDim.x, nseg, nbase, ncount, nt0, hint);
+        if (tn < 0) {  // (no next tile: the loads repeat this one's, unused)
+            nseg = seg;
+            nbase = base;
+            ncount = count;
+            nt0 = t0;
+        }
+        const int nsp = d.segc[nseg].sp;
+        const int64_t ngnode = d.segc[nseg].gnode;
+        RawKey<F64> nraw[kPer];
+        load_raw_keys<F64>(d, cur, nbase, nt0, ncount, nraw);
         int key[kPer];
-        tile_keys(d, cur, base, t0, count, f64, key);
+        raw_to_keys<F64>(raw, t0, count, key);
+        uint32_t *__restrict__ H = d.hist + (int64_t)sp * d.G + gnode;
         // this wave's bins: run sums of equal keys into its own LDS window (no
         // block barrier), then one global atomic per touched bin
         int kmn = 0x7fffffff, kmx = -1;
@@ -205,27 +238,38 @@ __global__ __launch_bounds__(kBlock) void sort_hist_kernel(Dev d)
         }
         const int lo = __builtin_amdgcn_readfirstlane(kmn);
         const int hi = __builtin_amdgcn_readfirstlane(kmx);
-        if (hi < 0) continue;  // no live particle in the wave's chunks
+        if (hi >= 0) {  // (else no live particle in the wave's chunks)
 #pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            bool tail;
-            const unsigned long long n = run_sum(key[k], key[k] >= 0 ? 1ull : 0ull, tail);
-            if (tail && key[k] >= 0) {
-                const int rel = key[k] - lo;
-                if (rel < kHistWaveWin) atomicAdd(&W[rel], (uint32_t)n);
-                else atomicAdd(H + key[k], (uint32_t)n);
+            for (int k = 0; k < kPer; ++k) {
+                bool tail;
+                const unsigned long long n = run_sum(key[k], key[k] >= 0 ? 1ull : 0ull, tail);
+                if (tail && key[k] >= 0) {
+                    const int rel = key[k] - lo;
+                    if (rel < kHistWaveWin) atomicAdd(&W[rel], (uint32_t)n);
+                    else atomicAdd(H + key[k], (uint32_t)n);
+                }
             }
-        }
-        hist_wave_sync();
-        const int span = min(hi - lo + 1, kHistWaveWin);
-        for (int i = lane; i < span; i += 64) {
-            const uint32_t v = W[i];
-            if (v) {
-                atomicAdd(H + lo + i, v);
-                W[i] = 0u;
+            hist_wave_sync();
+            static_assert(kHistWaveWin == 64, "one window bin per lane");
+            const int span = min(hi - lo + 1, kHistWaveWin);
+            if (lane < span) {
+                const uint32_t v = W[lane];
+                if (v) {
+                    atomicAdd(H + lo + lane, v);
+                    W[lane] = 0u;
+                }
             }
+            hist_wave_sync();
         }
-        hist_wave_sync();
+        t = tn;
+        seg = nseg;
+        base = nbase;
+        count = ncount;
+        t0 = nt0;
+        sp = nsp;
+        gnode = ngnode;
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) raw[k] = nraw[k];
     }
 }
 
@@ -324,62 +368,115 @@ __global__ __launch_bounds__(kBlock) void sort_scan_kernel(Dev d)
     }
 }
 
-// copy the fields of a wave's kPer chunks (slot g0 + 64 k) to slots to[k]
-// (-1: none) of the other set: all loads, then all stores
-template <typename V, bool CELL>
-__device__ __forceinline__ void move_fields(const Dev &d, int cur, int nxt, int64_t g0,
-                                            const int64_t (&to)[kPer], bool full)
-{
+// The fields of a wave's kPer chunks of a tile (in-segment slots
+// t0 + 64 (wave kPer + k) + lane): the cell (FP32 form) or the position
+// (FP64 form) first, the key being made from it, then the rest.  Slots past
+// the segment's count load the tile's first slot instead (never stored), so
+// that every tile issues the same loads and the waits for them are counted
+// exactly.  The source arrays are streamed once per sort: nontemporal loads
+// keep them from displacing the bins, cursors and the scattered
+// destinations in L2 (the stores stay cached: a tile's particles go to many
+// bins, and L2 merges their partial lines).
+template <bool F64>
+struct TileFields {
+    using V = typename std::conditional<F64, double, float>::type;
     V x[kPer], vx[kPer], vy[kPer], vz[kPer];
     int32_t c[kPer];
-    unsigned long long id[kPer];
+    uint32_t lo[kPer], hi[kPer];
+};
+
+template <bool F64>
+__device__ __forceinline__ void load_fields(const Dev &d, int cur, int64_t base, int64_t t0, int64_t count,
+                                            TileFields<F64> &F, bool (&in)[kPer])
+{
+    using V = typename TileFields<F64>::V;
+    const int lane = lane_id();
+    const int wave = threadIdx.x >> 6;
     const V *X = (const V *)d.x[cur], *VX = (const V *)d.vx[cur], *VY = (const V *)d.vy[cur],
             *VZ = (const V *)d.vz[cur];
-    // the source arrays are streamed once per sort: nontemporal loads keep
-    // them from displacing the bins, cursors and the scattered destinations
-    // in L2 (the stores stay cached: a tile's particles go to many bins, and
-    // L2 merges their partial lines)
-    auto load = [&](int k) {
-        const int64_t g = g0 + (int64_t)k * 64;
-        x[k] = __builtin_nontemporal_load(&X[g]);
-        vx[k] = __builtin_nontemporal_load(&VX[g]);
-        vy[k] = __builtin_nontemporal_load(&VY[g]);
-        vz[k] = __builtin_nontemporal_load(&VZ[g]);
-        if (CELL) c[k] = __builtin_nontemporal_load(&d.cell[cur][g]);
-        id[k] = (unsigned long long)__builtin_nontemporal_load(&d.id_lo[cur][g]) |
-                ((unsigned long long)__builtin_nontemporal_load(&d.id_hi[cur][g]) << 32);
-    };
-    if (full) {
-        // every slot of a full tile exists: its loads go unpredicated (an
-        // absorbed particle's fields are read and not stored)
+    int64_t g[kPer];
 #pragma unroll
-        for (int k = 0; k < kPer; ++k) load(k);
-    } else {
-#pragma unroll
-        for (int k = 0; k < kPer; ++k)
-            if (to[k] >= 0) load(k);
+    for (int k = 0; k < kPer; ++k) {
+        const int64_t i = t0 + (int64_t)(wave * kPer + k) * 64 + lane;
+        in[k] = i < count;
+        g[k] = base + (in[k] ? i : t0);
     }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        if (F64) F.x[k] = __builtin_nontemporal_load(&X[g[k]]);
+        else F.c[k] = __builtin_nontemporal_load(&d.cell[cur][g[k]]);
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        if (!F64) F.x[k] = __builtin_nontemporal_load(&X[g[k]]);
+        F.vx[k] = __builtin_nontemporal_load(&VX[g[k]]);
+        F.vy[k] = __builtin_nontemporal_load(&VY[g[k]]);
+        F.vz[k] = __builtin_nontemporal_load(&VZ[g[k]]);
+        F.lo[k] = __builtin_nontemporal_load(&d.id_lo[cur][g[k]]);
+        F.hi[k] = __builtin_nontemporal_load(&d.id_hi[cur][g[k]]);
+    }
+}
+
+// the stores of the particles with a destination (to[k] >= 0) to the other set
+template <bool F64>
+__device__ __forceinline__ void store_fields(const Dev &d, int nxt, const TileFields<F64> &F,
+                                             const int64_t (&to)[kPer])
+{
+    using V = typename TileFields<F64>::V;
     V *Xn = (V *)d.x[nxt], *VXn = (V *)d.vx[nxt], *VYn = (V *)d.vy[nxt], *VZn = (V *)d.vz[nxt];
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
         if (to[k] < 0) continue;
         const int64_t t = to[k];
-        Xn[t] = x[k];
-        VXn[t] = vx[k];
-        VYn[t] = vy[k];
-        VZn[t] = vz[k];
-        if (CELL) d.cell[nxt][t] = c[k];
-        store_id(d, nxt, t, id[k]);
+        Xn[t] = F.x[k];
+        VXn[t] = F.vx[k];
+        VYn[t] = F.vy[k];
+        VZn[t] = F.vz[k];
+        if (!F64) d.cell[nxt][t] = F.c[k];
+        d.id_lo[nxt][t] = F.lo[k];
+        d.id_hi[nxt][t] = F.hi[k];
     }
 }
 
-__global__ __launch_bounds__(kBlock) void sort_scatter_kernel(Dev d)
+// rank of each of the wave's particles among the tile's particles of its
+// cell: in-window bins count in LDS; a bin outside the tile's window
+// (OUT: some key of the wave is outside) is reserved directly with a global
+// atomic.  Two forms, so that the common one holds no global atomic whose
+// result the compiler would wait for together with the fields in flight.
+template <bool OUT>
+__device__ __forceinline__ void tile_ranks(SortLds &L, uint32_t *__restrict__ CUR, const int (&key)[kPer],
+                                           int lo, const bool (&outside)[kPer], uint32_t (&rank)[kPer])
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        bool tail;
+        const unsigned long long inc = run_sum(key[k], key[k] >= 0 ? 1ull : 0ull, tail);
+        const unsigned long long tails = ballot(tail);
+        uint32_t rb = 0;
+        if (tail && key[k] >= 0) {
+            if (!OUT || !outside[k]) rb = atomicAdd(&L.cnt[key[k] - lo], (uint32_t)inc);
+            else rb = atomicAdd(CUR + key[k], (uint32_t)inc);
+        }
+        const unsigned long long above = tails & ~((1ull << lane) - 1ull);
+        const int tl = __ffsll((long long)above) - 1;
+        rb = __shfl(rb, tl, 64);
+        rank[k] = rb + (uint32_t)inc - 1u;
+    }
+}
+
+// Each tile's fields are all loaded first, and stay in registers while the
+// tile ranks its particles and reserves its bins: the loads are in flight
+// during the ranks, and the wait for the reservations' returns covers them
+// too, rather than the loads starting only once the destinations are known.
+// (held to four waves per SIMD: the grid is one residency of 4 blocks per CU)
+template <bool F64>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void sort_scatter_kernel(Dev d)
 {
     __shared__ SortLds L;
     sort_lds_init(L, d);
     const int cur = d.glob->cur_set;
     const int nxt = cur ^ 1;
-    const bool f64 = (d.precision == PIC_FP64);
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
     int hint = 0;  // segment of the previous tile
@@ -411,35 +508,36 @@ __global__ __launch_bounds__(kBlock) void sort_scatter_kernel(Dev d)
             par ^= 1;
             continue;
         }
+        // the segment's values read before the fields (in the order of the
+        // memory counter, no wait for them then waits for the fields)
         const SegConst &sc = d.segc[seg];
         const uint32_t start = (uint32_t)d.seg_start[seg];
         uint32_t *__restrict__ CUR = d.cursor + sc.sp * d.G + sc.gnode;
+        const uint32_t cap = sc.cap;
+        const int64_t sbase = sc.base;
+        const bool neutral = sc.kind == PIC_KIND_NEUTRAL;
+        TileFields<F64> F;
+        bool in[kPer];
+        load_fields<F64>(d, cur, base, t0, count, F, in);
+        if (w0) tile_grab(Q);  // the next tile, behind this one's loads
         int key[kPer];
-        tile_keys(d, cur, base, t0, count, f64, key);
-        if (w0) tile_grab(Q);  // the next tile, behind this one's key loads
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            if (F64) key[k] = in[k] && F.x[k] >= 0.0 ? (int)floor((double)F.x[k]) : -1;
+            else key[k] = in[k] ? F.c[k] : -1;
+        }
         int lo, hi;
         tile_window(L, key, lo, hi);
         // rank of every particle among the tile's particles of its cell
         uint32_t rank[kPer];
-        bool outside[kPer];
+        bool outside[kPer], any_out = false;
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
-            bool tail;
-            const unsigned long long inc = run_sum(key[k], key[k] >= 0 ? 1ull : 0ull, tail);
-            const unsigned long long tails = ballot(tail);
-            const int rel = key[k] - lo;
-            outside[k] = key[k] >= 0 && rel >= kSortWin;
-            uint32_t rb = 0;
-            if (tail && key[k] >= 0) {
-                // in-window bins: rank within the tile; outside: a direct global reservation
-                if (!outside[k]) rb = atomicAdd(&L.cnt[rel], (uint32_t)inc);
-                else rb = atomicAdd(CUR + key[k], (uint32_t)inc);
-            }
-            const unsigned long long above = tails & ~((1ull << lane) - 1ull);
-            const int tl = __ffsll((long long)above) - 1;
-            rb = __shfl(rb, tl, 64);
-            rank[k] = rb + (uint32_t)inc - 1u;
+            outside[k] = key[k] >= 0 && key[k] - lo >= kSortWin;
+            any_out = any_out || outside[k];
         }
+        if (ballot(any_out)) tile_ranks<true>(L, CUR, key, lo, outside, rank);
+        else tile_ranks<false>(L, CUR, key, lo, outside, rank);
         __syncthreads();
         // one global reservation per touched bin
         if (hi >= 0) {
@@ -456,14 +554,6 @@ __global__ __launch_bounds__(kBlock) void sort_scatter_kernel(Dev d)
         __syncthreads();
         const int64_t t_next = tq_uniform_i64(s_next[par]);
         par ^= 1;
-        // destinations; then every field of the tile's particles is loaded
-        // before any is stored (a store to the other set could alias a later
-        // load in the compiler's view, which would otherwise keep each load
-        // waiting behind the previous store)
-        // (the segment's cap and base read once: the status atomic below would
-        // otherwise make the compiler read them again, with a wait, per chunk)
-        const uint32_t cap = sc.cap;
-        const int64_t sbase = sc.base;
         int64_t to[kPer];
         bool overflow = false;
 #pragma unroll
@@ -479,22 +569,14 @@ __global__ __launch_bounds__(kBlock) void sort_scatter_kernel(Dev d)
             to[k] = sbase + (int64_t)rel;
         }
         if (overflow) atomicOr(&d.instd[sc.inst].status, PIC_ST_INTERNAL);
-        const int64_t g0 = base + t0 + (int64_t)(wave * kPer) * 64 + lane;
-        const bool full = t0 + kTile <= count;
-        if (f64) {
-            move_fields<double, false>(d, cur, nxt, g0, to, full);
-        } else {
-            move_fields<float, true>(d, cur, nxt, g0, to, full);
-        }
-        if (sc.kind == PIC_KIND_NEUTRAL) {
+        store_fields<F64>(d, nxt, F, to);
+        if (neutral) {
             unsigned long long vb = 0ull;
 #pragma unroll
             for (int k = 0; k < kPer; ++k) {
                 if (key[k] < 0) continue;
-                const int64_t g = base + t0 + (int64_t)(wave * kPer + k) * 64 + lane;
-                const double v = f64 ? fabs(((const double *)d.vx[cur])[g])
-                                     : fabs((double)((const float *)d.vx[cur])[g]);
-                const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+                const unsigned long long b =
+                    (unsigned long long)__double_as_longlong(fabs((double)F.vx[k]));
                 vb = b > vb ? b : vb;
             }
 #pragma unroll
@@ -575,7 +657,10 @@ __global__ __launch_bounds__(kBlock) void sort_start_kernel(Dev d)
 hipError_t launch_sort(const Dev &d, hipStream_t st)
 {
     const int grid = push_grid(d);
-    hipLaunchKernelGGL(sort_hist_kernel, dim3(grid), dim3(kBlock), 0, st, d);
+    if (d.precision == PIC_FP64)
+        hipLaunchKernelGGL(sort_hist_kernel<true>, dim3(grid), dim3(kBlock), 0, st, d);
+    else
+        hipLaunchKernelGGL(sort_hist_kernel<false>, dim3(grid), dim3(kBlock), 0, st, d);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(sort_start_kernel, dim3(1), dim3(kBlock), 0, st, d);
@@ -584,7 +669,10 @@ hipError_t launch_sort(const Dev &d, hipStream_t st)
     hipLaunchKernelGGL(sort_scan_kernel, dim3((unsigned)d.n_sort_tiles), dim3(kBlock), 0, st, d);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(sort_scatter_kernel, dim3(grid), dim3(kBlock), 0, st, d);
+    if (d.precision == PIC_FP64)
+        hipLaunchKernelGGL(sort_scatter_kernel<true>, dim3(grid), dim3(kBlock), 0, st, d);
+    else
+        hipLaunchKernelGGL(sort_scatter_kernel<false>, dim3(grid), dim3(kBlock), 0, st, d);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(sort_finish_kernel, dim3(1), dim3(kBlock), 0, st, d);

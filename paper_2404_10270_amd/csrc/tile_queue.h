@@ -121,9 +121,14 @@ __device__ __forceinline__ void tile_queue_init(TileQueue &Q, const Dev &d, uint
     Q.grabbed = false;
 }
 
+// The result is first read by tile_next, so that no wait for it holds up
+// the work on the loads issued ahead of it.  (An increment that wraps at
+// 2^32 - 1, never reached: the compiler aggregates a uniform atomicAdd over
+// the wave and reads its result at once, which would wait for every load in
+// flight.)
 __device__ __forceinline__ void tile_grab(TileQueue &Q)
 {
-    Q.pending = lane_id() == 0 ? atomicAdd(Q.ctr, 1u) : 0u;
+    if (lane_id() == 0) Q.pending = atomicInc(Q.ctr, 0xFFFFFFFFu);
     Q.grabbed = true;
 }
 
