@@ -17,6 +17,7 @@
 // atoms keep their velocity until the next sort, so it bounds how far any
 // of them can move from the cell the offsets list it in.
 // Segment starts come from the live counts, so absorbed particles need no bin.
+#include <climits>
 #include <type_traits>
 
 #include "device_common.h"
@@ -97,6 +98,54 @@ __device__ __forceinline__ int sort_tile_seg(const SortLds &L, const Dev &d, int
     return seg;
 }
 
+// Wave-wide minimum and maximum of a signed key through DPP lane moves (no
+// LDS round trip): within each row of 16 lanes by the xor-1 and xor-2 quad
+// permutes and the half-row and row mirrors, then across rows by the row
+// broadcasts of lanes 15 and 31, which leave the result in lane 63.
+constexpr int kDppQuadXor1 = 0xB1;    // quad_perm [1, 0, 3, 2]
+constexpr int kDppQuadXor2 = 0x4E;    // quad_perm [2, 3, 0, 1]
+constexpr int kDppHalfMirror = 0x141; // row_half_mirror
+constexpr int kDppMirror = 0x140;     // row_mirror
+constexpr int kDppBcast15 = 0x142;    // row_bcast:15 (rows 1 and 3 take lane 15 of the row before)
+constexpr int kDppBcast31 = 0x143;    // row_bcast:31 (rows 2 and 3 take lane 31)
+
+template <bool MAX, int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_step(int v)
+{
+    const int ident = MAX ? INT_MIN : INT_MAX;
+    const int o = __builtin_amdgcn_update_dpp(ident, v, CTRL, ROWS, 0xF, false);
+    return MAX ? max(v, o) : min(v, o);
+}
+
+template <bool MAX>
+__device__ __forceinline__ int wave_reduce_dpp(int v)
+{
+    v = dpp_step<MAX, kDppQuadXor1, 0xF>(v);
+    v = dpp_step<MAX, kDppQuadXor2, 0xF>(v);
+    v = dpp_step<MAX, kDppHalfMirror, 0xF>(v);
+    v = dpp_step<MAX, kDppMirror, 0xF>(v);
+    v = dpp_step<MAX, kDppBcast15, 0xA>(v);
+    v = dpp_step<MAX, kDppBcast31, 0xC>(v);
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
+// Runs of equal keys in lane order (a run: a maximal group of consecutive
+// lanes with one key).  Returns the lane's 1-based position in its run;
+// is_tail marks the run's last lane, whose position is the run's length
+// (the count of particles in one cell, as every lane of a run of live keys
+// counts one).
+__device__ __forceinline__ uint32_t run_position(int key, bool &is_tail)
+{
+    const int lane = lane_id();
+    const int up = __shfl_up(key, 1, 64);
+    const int dn = __shfl_down(key, 1, 64);
+    const bool head = (lane == 0) || (up != key);
+    is_tail = (lane == 63) || (dn != key);
+    const unsigned long long heads = ballot(head);
+    const unsigned long long mask = heads & ((lane == 63) ? ~0ull : ((2ull << lane) - 1ull));
+    return (uint32_t)(lane - (63 - __clzll(mask)) + 1);
+}
+
 // block window [lo, hi] over the keys of this tile (barrier inside)
 __device__ __forceinline__ void tile_window(SortLds &L, const int (&key)[kPer], int &lo, int &hi)
 {
@@ -109,11 +158,8 @@ __device__ __forceinline__ void tile_window(SortLds &L, const int (&key)[kPer], 
             kmn = min(kmn, key[k]);
             kmx = max(kmx, key[k]);
         }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        kmn = min(kmn, __shfl_xor(kmn, o, 64));
-        kmx = max(kmx, __shfl_xor(kmx, o, 64));
-    }
+    kmn = wave_reduce_dpp<false>(kmn);
+    kmx = wave_reduce_dpp<true>(kmx);
     if (lane == 0) {
         L.red[0][wave] = kmn;
         L.red[1][wave] = kmx;
@@ -231,22 +277,17 @@ __global__ __launch_bounds__(kBlock) void sort_hist_kernel(Dev d)
                 kmn = min(kmn, key[k]);
                 kmx = max(kmx, key[k]);
             }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            kmn = min(kmn, __shfl_xor(kmn, o, 64));
-            kmx = max(kmx, __shfl_xor(kmx, o, 64));
-        }
-        const int lo = __builtin_amdgcn_readfirstlane(kmn);
-        const int hi = __builtin_amdgcn_readfirstlane(kmx);
+        const int lo = wave_reduce_dpp<false>(kmn);
+        const int hi = wave_reduce_dpp<true>(kmx);
         if (hi >= 0) {  // (else no live particle in the wave's chunks)
 #pragma unroll
             for (int k = 0; k < kPer; ++k) {
                 bool tail;
-                const unsigned long long n = run_sum(key[k], key[k] >= 0 ? 1ull : 0ull, tail);
+                const uint32_t n = run_position(key[k], tail);
                 if (tail && key[k] >= 0) {
                     const int rel = key[k] - lo;
-                    if (rel < kHistWaveWin) atomicAdd(&W[rel], (uint32_t)n);
-                    else atomicAdd(H + key[k], (uint32_t)n);
+                    if (rel >= 0 && rel < kHistWaveWin) atomicAdd(&W[rel], n);
+                    else atomicAdd(H + key[k], n);
                 }
             }
             hist_wave_sync();
@@ -451,7 +492,7 @@ __device__ __forceinline__ void tile_ranks(SortLds &L, uint32_t *__restrict__ CU
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
         bool tail;
-        const unsigned long long inc = run_sum(key[k], key[k] >= 0 ? 1ull : 0ull, tail);
+        const uint32_t inc = run_position(key[k], tail);
         const unsigned long long tails = ballot(tail);
         uint32_t rb = 0;
         if (tail && key[k] >= 0) {
@@ -533,7 +574,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         bool outside[kPer], any_out = false;
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
-            outside[k] = key[k] >= 0 && key[k] - lo >= kSortWin;
+            outside[k] = key[k] >= 0 && (key[k] < lo || key[k] - lo >= kSortWin);
             any_out = any_out || outside[k];
         }
         if (ballot(any_out)) tile_ranks<true>(L, CUR, key, lo, outside, rank);
