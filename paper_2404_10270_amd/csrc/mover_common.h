@@ -22,20 +22,6 @@ __device__ __forceinline__ void stream_st(T *p, T v)
     __builtin_nontemporal_store(v, p);
 }
 
-__device__ __forceinline__ int wave_min(int v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
-__device__ __forceinline__ int wave_max(int v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
 // Orders this wave's LDS operations before and after the call (a wave's LDS
 // operations complete in issue order; the fences keep the compiler from
 // moving them across).
@@ -55,7 +41,8 @@ constexpr int kWaveWin = 64;      // LDS deposit window of one wave, nodes
 // node.  A run whose nodes fall outside the window adds to S directly.
 // In two halves, so that a mover can issue its next tile's loads between
 // them: deposit_accumulate fills the window (span = 0: nothing to flush),
-// deposit_flush adds it to S and clears it.
+// deposit_flush adds it to S and clears it.  The window's bounds come from
+// DPP lane moves (no LDS round trip).
 template <int NP>
 __device__ __forceinline__ void deposit_accumulate(unsigned long long *wdep, unsigned long long *__restrict__ S,
                                                    const int (&key)[NP], const unsigned long long (&w1)[NP],
@@ -68,8 +55,8 @@ __device__ __forceinline__ void deposit_accumulate(unsigned long long *wdep, uns
             kmn = min(kmn, key[k]);
             kmx = max(kmx, key[k]);
         }
-    lo = __builtin_amdgcn_readfirstlane(wave_min(kmn));
-    const int hi = __builtin_amdgcn_readfirstlane(wave_max(kmx));
+    lo = wave_reduce_dpp<false>(kmn);
+    const int hi = wave_reduce_dpp<true>(kmx);
     span = 0;
     if (hi < 0) return;  // no live particle in the wave's chunks
 #pragma unroll

@@ -17,7 +17,6 @@
 // atoms keep their velocity until the next sort, so it bounds how far any
 // of them can move from the cell the offsets list it in.
 // Segment starts come from the live counts, so absorbed particles need no bin.
-#include <climits>
 #include <type_traits>
 
 #include "device_common.h"
@@ -96,37 +95,6 @@ __device__ __forceinline__ int sort_tile_seg(const SortLds &L, const Dev &d, int
         count = d.segd[seg].count;
     }
     return seg;
-}
-
-// Wave-wide minimum and maximum of a signed key through DPP lane moves (no
-// LDS round trip): within each row of 16 lanes by the xor-1 and xor-2 quad
-// permutes and the half-row and row mirrors, then across rows by the row
-// broadcasts of lanes 15 and 31, which leave the result in lane 63.
-constexpr int kDppQuadXor1 = 0xB1;    // quad_perm [1, 0, 3, 2]
-constexpr int kDppQuadXor2 = 0x4E;    // quad_perm [2, 3, 0, 1]
-constexpr int kDppHalfMirror = 0x141; // row_half_mirror
-constexpr int kDppMirror = 0x140;     // row_mirror
-constexpr int kDppBcast15 = 0x142;    // row_bcast:15 (rows 1 and 3 take lane 15 of the row before)
-constexpr int kDppBcast31 = 0x143;    // row_bcast:31 (rows 2 and 3 take lane 31)
-
-template <bool MAX, int CTRL, int ROWS>
-__device__ __forceinline__ int dpp_step(int v)
-{
-    const int ident = MAX ? INT_MIN : INT_MAX;
-    const int o = __builtin_amdgcn_update_dpp(ident, v, CTRL, ROWS, 0xF, false);
-    return MAX ? max(v, o) : min(v, o);
-}
-
-template <bool MAX>
-__device__ __forceinline__ int wave_reduce_dpp(int v)
-{
-    v = dpp_step<MAX, kDppQuadXor1, 0xF>(v);
-    v = dpp_step<MAX, kDppQuadXor2, 0xF>(v);
-    v = dpp_step<MAX, kDppHalfMirror, 0xF>(v);
-    v = dpp_step<MAX, kDppMirror, 0xF>(v);
-    v = dpp_step<MAX, kDppBcast15, 0xA>(v);
-    v = dpp_step<MAX, kDppBcast31, 0xC>(v);
-    return __builtin_amdgcn_readlane(v, 63);
 }
 
 // Runs of equal keys in lane order (a run: a maximal group of consecutive
