@@ -436,6 +436,11 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
                 for (int k = 0; k < NP; ++k) a0[k] = a1[k] = 0.f;
             }
             // ---- push, walls, candidate test
+            // (every lane runs the arithmetic, an empty slot on whatever its
+            // registers hold, and only live lanes count or keep a result: so
+            // the stored registers are written on every path, and the stores
+            // need no wait for the tile's loads, nor for what was issued
+            // after them)
             int key[NP];
             unsigned long long w1[NP];
             bool cand[NP];
@@ -446,7 +451,7 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
                 key[k] = -1;
                 w1[k] = 0;
                 cand[k] = false;
-                if (j[k] < 0) continue;
+                const bool live = j[k] >= 0;
                 const float a = fmaf(f[k], a1[k] - a0[k], a0[k]);
                 const float h = hk * a;
                 const float mx = vx[k] + h, my = vy[k], mz = vz[k];
@@ -464,8 +469,8 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
                 fn = fn - fl;
                 int32_t jn = j[k] + (int32_t)fl;
                 if (fn >= 1.0f) { fn = 0.0f; jn += 1; }
-                cfl |= !(fabsf(msf * nvx) < 1.0f);
-                const bool bk = !isfinite(nvx) || !isfinite(nvy) || !isfinite(nvz);
+                cfl |= live && !(fabsf(msf * nvx) < 1.0f);
+                const bool bk = live && (!isfinite(nvx) || !isfinite(nvy) || !isfinite(nvz));
                 bad |= bk;
                 if (bk) jn = j[k], fn = f[k];  // keep the slot well-formed; the run is flagged
                 bool l = false, r = false;
@@ -477,13 +482,13 @@ __global__ __launch_bounds__(kBlock) void push_f32_kernel(Dev d)
                         if (jn < 0) jn += nc;
                     }
                 } else if (jn < 0) {
-                    l = true;
+                    l = live;
                 } else if (jn >= nc) {
-                    r = true;
+                    r = live;
                 }
                 n_left += l;
                 n_right += r;
-                j[k] = (l || r) ? kDeadCell : jn;
+                j[k] = (!live || l || r) ? kDeadCell : jn;
                 f[k] = fn;
                 vx[k] = nvx;
                 vy[k] = nvy;
@@ -733,6 +738,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                 key[k] = -1;
                 w1[k] = 0;
                 cand[k] = false;
+                // (dead lanes skip, unlike the FP32 form: with every lane running
+                // the arithmetic the compiler spills two more values here, which
+                // costs more than the waits before the stores that it saves)
                 if (!live[k]) continue;
                 const double a = fma(fr[k], a1[k] - a0[k], a0[k]);
                 const double h = hk * a;
